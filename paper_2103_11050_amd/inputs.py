@@ -1,0 +1,96 @@
+"""Seeded synthetic inputs shared by the HIP path, the oracle, the tests and the benchmark.
+
+This module only produces input data (problem descriptions, permeability fields, initial
+saturations). It holds none of the method's arithmetic: no mobility, no transmissibility,
+no solver. Both the oracle and the HIP path consume what it returns.
+
+Permeability: ln K = sigma * xi, where xi is a stationary zero-mean unit-variance Gaussian
+field with covariance exp(-r^2 / (2 l^2)), sampled at cell centres by circulant embedding
+on a periodic grid padded to twice the domain in each direction, driven by numpy's PCG64
+with the given seed. This stands in for the log-normal fields of the paper's experiments
+(Section 5); the paper's own samples are not available.
+"""
+from __future__ import annotations
+
+import copy
+
+import numpy as np
+
+# boundary kinds per side, sides ordered W, E, S, N
+NOFLOW, PRESSURE, FLUX = 0, 1, 2
+SIDES = ("W", "E", "S", "N")
+
+# Workloads. Sizes follow the configurations of the benchmark; physics follows the paper's
+# model problem (Section 2) with quadratic Corey curves (Section 5).
+_BASE = dict(
+    lx=1.0, ly=1.0, alpha=1.0, eta=0.1, eps_norm="rel", switch_rule="alg1",
+    mu_w=1.0, mu_o=10.0,
+    # water injected on the left (unit inflow per unit length), p = 0 on the right,
+    # no flow on the bottom and top
+    bc_kind=[FLUX, PRESSURE, NOFLOW, NOFLOW], bc_value=[-1.0, 0.0, 0.0, 0.0],
+    s_inj=1.0, cfl=0.5, cn=1, breakthrough_cut=0.01,
+)
+
+CONFIGS = {
+    # plain method, FP64: 32^2 cells, 4x4 subdomains of 8^2, 2 interface elements per side
+    "c1": dict(_BASE, nx=32, ny=32, sub_x=8, sub_y=8, ne_x=2, ne_y=2, mu_o=10.0,
+               sigma2=1.0, corr_len=0.1, seed=1, steps=50),
+    # 256^2 cells, 16x16 subdomains of 16^2, 4 interface elements per side, high contrast
+    "c2": dict(_BASE, nx=256, ny=256, sub_x=16, sub_y=16, ne_x=4, ne_y=4, mu_o=100.0,
+               sigma2=4.0, corr_len=0.05, seed=2, steps=200),
+    # 1024^2 cells, 64x64 subdomains of 16^2, 8 interface elements per side
+    "c3": dict(_BASE, nx=1024, ny=1024, sub_x=16, sub_y=16, ne_x=8, ne_y=8, mu_o=100.0,
+               sigma2=4.0, corr_len=0.05, seed=3, steps=200),
+}
+
+
+def config(name: str, **overrides) -> dict:
+    """Return a deep copy of a named workload with optional overrides."""
+    cfg = copy.deepcopy(CONFIGS[name])
+    cfg.update(overrides)
+    return cfg
+
+
+def gaussian_field(nx: int, ny: int, lx: float, ly: float, corr_len: float, seed: int) -> np.ndarray:
+    """Zero-mean unit-variance Gaussian field on cell centres, shape (ny, nx), float64."""
+    px, py = 2 * nx, 2 * ny
+    hx, hy = lx / nx, ly / ny
+    ix = np.arange(px)
+    iy = np.arange(py)
+    dx = np.minimum(ix, px - ix) * hx
+    dy = np.minimum(iy, py - iy) * hy
+    r2 = dy[:, None] ** 2 + dx[None, :] ** 2
+    c = np.exp(-r2 / (2.0 * corr_len * corr_len))
+    lam = np.fft.fft2(c).real
+    lam = np.maximum(lam, 0.0)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    z = rng.standard_normal((py, px)) + 1j * rng.standard_normal((py, px))
+    f = np.fft.fft2(np.sqrt(lam / (px * py)) * z)
+    return np.ascontiguousarray(f.real[:ny, :nx])
+
+
+def permeability(cfg: dict) -> np.ndarray:
+    """Log-normal permeability K = exp(sqrt(sigma2) * xi), shape (ny, nx)."""
+    xi = gaussian_field(cfg["nx"], cfg["ny"], cfg["lx"], cfg["ly"], cfg["corr_len"], cfg["seed"])
+    return np.exp(np.sqrt(cfg["sigma2"]) * xi)
+
+
+def initial_saturation(cfg: dict) -> np.ndarray:
+    """Reservoir initially filled with oil: s0 = 0 everywhere."""
+    return np.zeros((cfg["ny"], cfg["nx"]))
+
+
+def source(cfg: dict) -> np.ndarray:
+    """No wells: q = 0 everywhere."""
+    return np.zeros((cfg["ny"], cfg["nx"]))
+
+
+def random_problem(seed: int, nx: int, ny: int, sub_x: int, sub_y: int, ne_x: int, ne_y: int,
+                   sigma2: float = 1.0, corr_len: float = 0.2, **overrides) -> tuple[dict, np.ndarray]:
+    """A small seeded problem for parity and property tests: config dict and permeability."""
+    cfg = dict(_BASE, nx=nx, ny=ny, sub_x=sub_x, sub_y=sub_y, ne_x=ne_x, ne_y=ne_y,
+               sigma2=sigma2, corr_len=corr_len, seed=seed, steps=10)
+    cfg["bc_kind"] = list(cfg["bc_kind"])
+    cfg["bc_value"] = list(cfg["bc_value"])
+    cfg.update(overrides)
+    return cfg, permeability(cfg)
