@@ -1,0 +1,170 @@
+/*
+ * mpm2p.h -- C ABI of the MI355X hot path of the Multiscale Perturbation Method for
+ * two-phase flow (MPM-2P) on top of the Multiscale Robin Coupled Method (MRCM),
+ * arXiv 2103.11050.
+ *
+ * The library solves the operator-splitting problem of Section 2 (eq. Darcy for the
+ * pressure, eq. BL2D for the saturation) with the modified splitting of Section 4.2
+ * (Algorithm 1): explicit upwind transport sub-steps, then a velocity update that is
+ * either an MRCM solve with a new set of multiscale basis functions (Section 3) or an
+ * MPM-2P solve that reuses the stored ones (Section 4.1, eq:mpm_tf_3 followed by the
+ * downscaling problems mpm_upd).
+ *
+ * Conventions shared by every call
+ *  - Every call returns mpm_status (int32): 0 on success, a negative code on error. No C++
+ *    exception crosses the boundary.
+ *  - Cell arrays are row-major [ny][nx] doubles. x-face fluxes ux are [ny][nx+1], y-face
+ *    fluxes uy are [ny+1][nx]: normal flux per unit face length, positive along +x / +y.
+ *  - Pointers named dev_* are device (HBM) pointers on the device that is current when
+ *    mpm_create is called; every other pointer is host memory.
+ *  - The caller owns all device memory: it allocates the workspace (size from
+ *    mpm_workspace_size) and keeps it alive until mpm_destroy. The library allocates no
+ *    device memory; it allocates a few bytes of pinned host memory per run.
+ *  - Work is enqueued on the HIP stream given to mpm_create; calls that return data to the
+ *    host (mpm_get_stats) synchronise with that stream.
+ *  - Argument errors return MPM_EINVAL before any device work. Errors found by kernels
+ *    (a non-positive pivot, a singular interface pivot, a non-finite value) set a device
+ *    error word that the next mpm_get_stats or mpm_destroy returns; the run is then
+ *    unusable (MPM_ESTATE).
+ *  - One run per host thread at a time.
+ */
+#ifndef MPM2P_H
+#define MPM2P_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mpm_status;
+
+enum {
+  MPM_OK = 0,
+  MPM_EINVAL = -1,     /* invalid argument or descriptor */
+  MPM_ENOMEM = -2,     /* workspace smaller than mpm_workspace_size, or host allocation failed */
+  MPM_ENOTSPD = -3,    /* a local matrix had a non-positive pivot */
+  MPM_ESINGULAR = -4,  /* the interface system had a zero pivot */
+  MPM_ENONFINITE = -5, /* a non-finite value appeared in the state */
+  MPM_EHIP = -6,       /* a HIP runtime call failed */
+  MPM_ESTATE = -7      /* call not valid in the run's current state */
+};
+
+/* Physical boundary kinds, one per side in the order W, E, S, N (eq. Darcy: p = g on the
+ * pressure boundary, u.n = z on the flux boundary). */
+enum { MPM_BC_NOFLOW = 0, MPM_BC_PRESSURE = 1, MPM_BC_FLUX = 2 };
+
+/* Norm of the switch criterion epsilon = ||kappa^n - kappa^m|| (Section 4.1; Algorithm 1).
+ * REL: L2 over cells divided by ||kappa^m||; ABS: L2(Omega). */
+enum { MPM_EPS_REL_L2 = 0, MPM_EPS_ABS_L2 = 1 };
+
+/* When epsilon is evaluated (Section 4.2). ALG1: the decision at step n uses epsilon of step
+ * n-1, as Algorithm 1 is written. TEXT: the decision uses epsilon of the current saturation,
+ * as the description before the algorithm reads. */
+enum { MPM_SWITCH_ALG1 = 0, MPM_SWITCH_TEXT = 1 };
+
+/* Arithmetic of the local problems. FP64 everywhere, or FP32 local factors with FP64
+ * iterative refinement of every local solve (interface system, residuals, epsilon in FP64). */
+enum { MPM_PREC_FP64 = 0, MPM_PREC_FP32_REFINE = 1 };
+
+/* Branch of a velocity update. */
+enum { MPM_AUTO = -1, MPM_FORCE_MPM = 0, MPM_FORCE_MRCM = 1 };
+
+#define MPM_ABI_VERSION 1
+
+typedef struct mpm_desc {
+  int32_t abi_version;        /* MPM_ABI_VERSION */
+  int32_t nx, ny;             /* fine grid (cells) */
+  double lx, ly;              /* domain [0,lx] x [0,ly] */
+  int32_t sub_x, sub_y;       /* cells per subdomain; nx % sub_x == 0, ny % sub_y == 0 */
+  int32_t ne_x, ne_y;         /* interface elements per subdomain side along x and along y;
+                                 sub_x % ne_x == 0, sub_y % ne_y == 0 (H-bar = H / n_e) */
+  double alpha;               /* Robin parameter > 0; beta = alpha H / kappa (eq:beta) */
+  double eta;                 /* switch threshold; +inf never updates the basis */
+  int32_t eps_norm;           /* MPM_EPS_* */
+  int32_t switch_rule;        /* MPM_SWITCH_* */
+  int32_t precision;          /* MPM_PREC_* */
+  int32_t cn;                 /* transport sub-steps per velocity update (C_n >= 1) */
+  double mu_w, mu_o;          /* viscosities; M = mu_o / mu_w (Corey curves of Section 5) */
+  int32_t bc_kind[4];         /* MPM_BC_* for W, E, S, N */
+  double bc_value[4];         /* g for PRESSURE, outward normal flux z for FLUX (inflow < 0) */
+  double s_inj;               /* injected saturation s-bar on inflow boundary faces */
+  double cfl;                 /* fraction of the monotone upwind time-step bound, (0, 1] */
+  double breakthrough_cut;    /* water cut at the outflow boundary that marks breakthrough */
+} mpm_desc;
+
+typedef struct mpm_stats {
+  int64_t te;                 /* elliptic solves so far (T_e) */
+  int64_t tm;                 /* basis-set computations so far, the initial one included (T_m) */
+  int64_t n_transport;        /* transport sub-steps so far */
+  double eps;                 /* last epsilon */
+  double t;                   /* simulated time */
+  double pvi;                 /* pore volumes injected */
+  double water_cut;           /* water cut after the last transport sub-step */
+  double dt;                  /* current transport sub-step */
+  int32_t breakthrough;       /* 1 once water_cut >= breakthrough_cut */
+  int32_t last_branch;        /* MPM_FORCE_MPM or MPM_FORCE_MRCM of the last update */
+  int32_t error_word;         /* device error bits (0 if none) */
+  int32_t reserved;
+} mpm_stats;
+
+typedef struct mpm_run mpm_run;
+
+/* Exact device workspace of a run in bytes (for admission by footprint). */
+mpm_status mpm_workspace_size(const mpm_desc* desc, size_t* bytes);
+
+/* Creates a run on the current device. dev_workspace: caller-owned device buffer of at least
+ * mpm_workspace_size bytes, 256-byte aligned. hip_stream: a hipStream_t (NULL = default). */
+mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, void* hip_stream,
+                      mpm_run** out);
+
+/* Copies the permeability K (> 0), the source q (may be NULL: q = 0) and the initial
+ * saturation s0 (in [0,1]) into the workspace. Device pointers, row-major [ny][nx]. */
+mpm_status mpm_set_fields(mpm_run* run, const double* dev_K, const double* dev_q, const double* dev_s0);
+
+/* Algorithm 1, first four lines: kappa^0 = lambda(s^0) K, the MRCM velocity, the stored
+ * basis functions, n = 1, epsilon = eta. */
+mpm_status mpm_start(mpm_run* run);
+
+/* Transport sub-steps with the current velocity (Algorithm 1, the inner for loop). */
+mpm_status mpm_transport(mpm_run* run, int32_t nsteps);
+
+/* One velocity update for the current saturation (Algorithm 1, the if/else and the epsilon
+ * update). force: MPM_AUTO, MPM_FORCE_MPM or MPM_FORCE_MRCM. */
+mpm_status mpm_velocity_update(mpm_run* run, int32_t force);
+
+/* One pass of the while loop of Algorithm 1: C_n transport sub-steps, then a velocity update. */
+mpm_status mpm_step(mpm_run* run, int32_t force);
+
+/* Copies the current velocity (device pointers ux [ny][nx+1], uy [ny+1][nx]). */
+mpm_status mpm_get_velocity(mpm_run* run, double* dev_ux, double* dev_uy);
+
+/* Copies the current saturation (device pointer, [ny][nx]). */
+mpm_status mpm_get_saturation(mpm_run* run, double* dev_s);
+
+/* Counters and scalars; synchronises with the run's stream. Returns the device error, if any. */
+mpm_status mpm_get_stats(mpm_run* run, mpm_stats* out);
+
+/* Frees the host-side run. The workspace stays the caller's. */
+mpm_status mpm_destroy(mpm_run* run);
+
+/* Static description of a status code. */
+const char* mpm_status_str(mpm_status status);
+
+/* Sizes of the run's plan: subdomains, interface unknowns, nested-dissection nodes and
+ * levels (host memory; any pointer may be NULL). */
+mpm_status mpm_plan_info(const mpm_run* run, int64_t* n_sub, int64_t* n_iface, int64_t* n_nodes,
+                         int64_t* n_levels);
+
+/* Average duration in milliseconds of each kernel class over the calls since the last reset,
+ * measured with HIP events on the run's stream when profiling is enabled. names/ms/count are
+ * host arrays of length cap; returns the number of classes written in *n. */
+mpm_status mpm_profile(mpm_run* run, int32_t enable, int32_t reset, int32_t cap, const char** names,
+                       double* ms, int64_t* count, int32_t* n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPM2P_H */

@@ -1,0 +1,519 @@
+// C ABI and host runtime: workspace carving, the velocity updates (MRCM and MPM-2P), the
+// transport sub-steps and the modified operator splitting (Section 4.2, Algorithm 1).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "mpm2p.h"
+#include "plan.hpp"
+
+using namespace mpm;
+
+namespace {
+
+// max over [0,1] of f'(s) = 2 M s (1-s) / (M s^2 + (1-s)^2)^2 for the Corey curves: the
+// interior zero of f'' is the root of the cubic
+//   (1 - 2s)(M s^2 + (1-s)^2) - 4 s (1-s)(M s - (1-s)) = 0,
+// bracketed by a coarse scan of f' and then bisected to machine precision.
+double fprime(double s, double M) {
+  const double den = M * s * s + (1.0 - s) * (1.0 - s);
+  return 2.0 * M * s * (1.0 - s) / (den * den);
+}
+double fpp_sign_poly(double s, double M) {
+  return (1.0 - 2.0 * s) * (M * s * s + (1.0 - s) * (1.0 - s)) - 4.0 * s * (1.0 - s) * (M * s - (1.0 - s));
+}
+double max_fprime(double M) {
+  const int n = 4096;
+  int best = 1;
+  double bv = -1.0;
+  for (int i = 1; i < n; ++i) {
+    const double v = fprime(double(i) / n, M);
+    if (v > bv) { bv = v; best = i; }
+  }
+  double a = double(best - 1) / n, b = double(best + 1) / n;
+  double fa = fpp_sign_poly(a, M);
+  for (int it = 0; it < 200 && b - a > 0; ++it) {
+    const double m = 0.5 * (a + b);
+    if (m <= a || m >= b) break;
+    const double fm = fpp_sign_poly(m, M);
+    if ((fm > 0) == (fa > 0)) { a = m; fa = fm; } else { b = m; }
+  }
+  double v = std::max(fprime(a, M), fprime(b, M));
+  return std::max(v, bv);
+}
+
+struct ProfEntry {
+  const char* name = nullptr;   // string literal of the kernel class
+  double ms = 0.0;
+  int64_t count = 0;
+};
+
+}  // namespace
+
+struct mpm_run {
+  Plan P;
+  Geo g;
+  hipStream_t st = nullptr;
+  int device = 0;
+  char* ws = nullptr;
+  double *K, *q, *s, *s2, *kn, *km, *ux, *uy, *uxm, *uym, *fac, *S, *h, *vbnd, *ubnd, *leafK, *leafr;
+  double *front, *fI, *cB, *panel, *y, *red, *scal;
+  int32_t* err;
+  NdArgs nd{};
+  const int32_t* subdofs_d = nullptr;
+  double fmax_deriv = 0.0;
+  double M = 1.0;
+  double area = 1.0;
+  // Algorithm 1 state
+  bool fields = false, started = false, poisoned = false;
+  int64_t te = 0, tm = 0, ntr = 0;
+  double eps_prev = 0.0;       // epsilon after the last update (known on the host)
+  bool eps_pending = false;    // epsilon of the last update still in flight
+  int last_branch = MPM_FORCE_MRCM;
+  double* pinned = nullptr;    // [eps_num, eps_den] copied after the kappa kernel
+  hipEvent_t ev_eps = nullptr;
+  // profiling with HIP events on the run's stream
+  bool prof = false;
+  std::vector<std::pair<const char*, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, ProfEntry> prof_acc;
+  std::string last_error;
+
+  hipEvent_t take_event() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e;
+    hipEventCreate(&e);
+    return e;
+  }
+  void prof_begin(const char* name, hipEvent_t* b) {
+    if (!prof) return;
+    *b = take_event();
+    hipEventRecord(*b, st);
+    (void)name;
+  }
+  void prof_end(const char* name, hipEvent_t b) {
+    if (!prof) return;
+    hipEvent_t e = take_event();
+    hipEventRecord(e, st);
+    pending.push_back({name, {b, e}});
+  }
+  void prof_collect() {
+    for (auto& p : pending) {
+      float ms = 0.f;
+      hipEventSynchronize(p.second.second);
+      hipEventElapsedTime(&ms, p.second.first, p.second.second);
+      auto& a = prof_acc[p.first];
+      a.name = p.first;
+      a.ms += ms;
+      a.count += 1;
+      pool.push_back(p.second.first);
+      pool.push_back(p.second.second);
+    }
+    pending.clear();
+  }
+};
+
+namespace {
+
+struct Scope {
+  mpm_run* r;
+  const char* name;
+  hipEvent_t b = nullptr;
+  Scope(mpm_run* r_, const char* n) : r(r_), name(n) { r->prof_begin(n, &b); }
+  ~Scope() { r->prof_end(name, b); }
+};
+
+Geo make_geo(const Plan& P) {
+  Geo g{};
+  g.nx = P.nx; g.ny = P.ny; g.mx = P.mx; g.my = P.my; g.Sx = P.Sx; g.Sy = P.Sy; g.nsub = P.nsub;
+  g.nc = P.nc; g.band = P.band; g.xfast = P.xfast; g.nb = P.nb; g.ne_x = P.ne_x; g.ne_y = P.ne_y;
+  g.n_vert = P.n_vert; g.ndmax = P.ndmax;
+  g.hx = P.hx; g.hy = P.hy; g.alpha = P.d.alpha; g.mu_w = P.d.mu_w; g.mu_o = P.d.mu_o;
+  for (int k = 0; k < 4; ++k) { g.bc_kind[k] = P.d.bc_kind[k]; g.bc_value[k] = P.d.bc_value[k]; }
+  g.s_inj = P.d.s_inj;
+  return g;
+}
+
+mpm_status hip_check(mpm_run* r, hipError_t e, const char* what) {
+  if (e == hipSuccess) return MPM_OK;
+  if (r) r->last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return MPM_EHIP;
+}
+
+#define HIPCHK(r, call)                                   \
+  do {                                                    \
+    mpm_status s_ = hip_check((r), (call), #call);        \
+    if (s_ != MPM_OK) return s_;                          \
+  } while (0)
+
+double eps_from(const mpm_run* r, double num, double den) {
+  if (r->P.d.eps_norm == MPM_EPS_ABS_L2) return std::sqrt(r->P.hx * r->P.hy * num);
+  return std::sqrt(num) / std::sqrt(den);
+}
+
+// kappa^n = lambda(s) K and the partial sums of epsilon against kappa^m; copies the two sums
+// to pinned host memory and records an event.
+mpm_status kappa_and_eps(mpm_run* r) {
+  {
+    Scope sc(r, "kappa_eps");
+    launch_kappa(r->st, r->P.nx * r->P.ny, r->s, r->K, r->kn, r->km, r->P.d.mu_w, r->P.d.mu_o, r->red, r->scal);
+  }
+  HIPCHK(r, hipMemcpyAsync(r->pinned, r->scal + SC_EPS_NUM, 2 * sizeof(double), hipMemcpyDeviceToHost, r->st));
+  HIPCHK(r, hipEventRecord(r->ev_eps, r->st));
+  return MPM_OK;
+}
+
+void nd_solve(mpm_run* r) {
+  const Plan& P = r->P;
+  const int L = int(P.level_nodes.size()) - 1;
+  {
+    Scope sc(r, "iface_fwd");
+    for (int l = 1; l <= L; ++l) {
+      const int nn = int(P.level_nodes[l].size());
+      if (!nn) continue;
+      launch_nd_level_fwd(r->st, r->nd, P.level_off[l], nn, P.level_nmax[l], P.level_nBmax[l]);
+    }
+  }
+  {
+    Scope sc(r, "iface_bwd");
+    for (int l = L; l >= 1; --l) {
+      const int nn = int(P.level_nodes[l].size());
+      if (!nn) continue;
+      launch_nd_level_bwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l]);
+    }
+  }
+}
+
+void nd_factor(mpm_run* r) {
+  const Plan& P = r->P;
+  const int L = int(P.level_nodes.size()) - 1;
+  Scope sc(r, "iface_factor");
+  for (int l = 1; l <= L; ++l) {
+    const int nn = int(P.level_nodes[l].size());
+    if (!nn) continue;
+    launch_nd_level_factor(r->st, r->nd, P.level_off[l], nn, P.level_nmax[l], P.level_nImax[l]);
+  }
+}
+
+void finish_velocity(mpm_run* r, const double* kap_s, int with_v) {
+  {
+    Scope sc(r, "flux");
+    launch_flux(r->st, r->g, r->km, r->S, r->h, r->vbnd, r->y, r->subdofs_d, r->ubnd, with_v);
+  }
+  {
+    Scope sc(r, "downscale");
+    launch_downscale(r->st, r->g, kap_s, r->q, r->ubnd, r->ux, r->uy, r->red, r->red + r->P.nsub, r->err);
+  }
+  {
+    Scope sc(r, "dt");
+    launch_dt(r->st, r->P.nsub, r->red, r->red + r->P.nsub, r->P.d.cfl, r->fmax_deriv, r->scal);
+  }
+}
+
+// MRCM with a new basis for kappa^n (stored as kappa^m), downscaled with the same kappa.
+mpm_status mrcm_update(mpm_run* r) {
+  HIPCHK(r, hipMemcpyAsync(r->km, r->kn, size_t(r->P.nx) * r->P.ny * 8, hipMemcpyDeviceToDevice, r->st));
+  {
+    Scope sc(r, "basis");
+    launch_basis(r->st, r->g, r->km, r->q, r->fac, r->S, r->h, r->leafK, r->leafr, r->err);
+  }
+  nd_factor(r);
+  nd_solve(r);
+  finish_velocity(r, r->km, 0);
+  const size_t fx = size_t(r->P.ny) * (r->P.nx + 1) * 8, fy = size_t(r->P.ny + 1) * r->P.nx * 8;
+  HIPCHK(r, hipMemcpyAsync(r->uxm, r->ux, fx, hipMemcpyDeviceToDevice, r->st));
+  HIPCHK(r, hipMemcpyAsync(r->uym, r->uy, fy, hipMemcpyDeviceToDevice, r->st));
+  r->tm += 1;
+  return MPM_OK;
+}
+
+// MPM-2P: trivial-Robin solve with the stored kappa^m factors, interface solve with the stored
+// factorisation, reconstruction, downscaling with kappa^n.
+mpm_status mpm_update(mpm_run* r) {
+  {
+    Scope sc(r, "mpm_local");
+    launch_mpm_local(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac, r->h, r->vbnd, r->leafr);
+  }
+  nd_solve(r);
+  finish_velocity(r, r->kn, 1);
+  return MPM_OK;
+}
+
+mpm_status velocity_update(mpm_run* r, int32_t force) {
+  // decision (Algorithm 1: "if epsilon > eta")
+  mpm_status st = kappa_and_eps(r);
+  if (st) return st;
+  double decide;
+  if (r->P.d.switch_rule == MPM_SWITCH_TEXT) {
+    HIPCHK(r, hipEventSynchronize(r->ev_eps));
+    decide = eps_from(r, r->pinned[0], r->pinned[1]);
+  } else {
+    decide = r->eps_prev;
+  }
+  int branch = decide > r->P.d.eta ? MPM_FORCE_MRCM : MPM_FORCE_MPM;
+  if (force == MPM_FORCE_MPM || force == MPM_FORCE_MRCM) branch = force;
+  if (branch == MPM_FORCE_MRCM) {
+    st = mrcm_update(r);
+    r->eps_prev = 0.0;
+    r->eps_pending = false;
+  } else {
+    st = mpm_update(r);
+    r->eps_pending = true;
+  }
+  if (st) return st;
+  r->last_branch = branch;
+  r->te += 1;
+  if (r->eps_pending && r->P.d.switch_rule == MPM_SWITCH_ALG1) {
+    // epsilon of this update is needed by the next decision only; the copy was enqueued
+    // before the solve, so waiting on its event does not drain the stream
+    HIPCHK(r, hipEventSynchronize(r->ev_eps));
+    r->eps_prev = eps_from(r, r->pinned[0], r->pinned[1]);
+    r->eps_pending = false;
+  } else if (r->eps_pending) {
+    r->eps_prev = eps_from(r, r->pinned[0], r->pinned[1]);
+    r->eps_pending = false;
+  }
+  return MPM_OK;
+}
+
+mpm_status transport(mpm_run* r, int32_t nsteps) {
+  for (int k = 0; k < nsteps; ++k) {
+    Scope sc(r, "sat_step");
+    launch_sat_step(r->st, r->g, r->s, r->s2, r->ux, r->uy, r->scal, r->M, r->area);
+    std::swap(r->s, r->s2);
+  }
+  {
+    Scope sc(r, "water_cut");
+    launch_water_cut(r->st, r->g, r->s, r->ux, r->uy, r->scal, r->M);
+  }
+  r->ntr += nsteps;
+  return MPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mpm_status_str(mpm_status s) {
+  switch (s) {
+    case MPM_OK: return "ok";
+    case MPM_EINVAL: return "invalid argument";
+    case MPM_ENOMEM: return "workspace too small or host allocation failed";
+    case MPM_ENOTSPD: return "local matrix not positive definite";
+    case MPM_ESINGULAR: return "interface system singular";
+    case MPM_ENONFINITE: return "non-finite value";
+    case MPM_EHIP: return "HIP runtime error";
+    case MPM_ESTATE: return "call not valid in the current state";
+    default: return "unknown status";
+  }
+}
+
+mpm_status mpm_workspace_size(const mpm_desc* desc, size_t* bytes) {
+  if (!desc || !bytes) return MPM_EINVAL;
+  if (validate(*desc, nullptr) != MPM_OK) return MPM_EINVAL;
+  Plan P;
+  build_plan(*desc, &P);
+  *bytes = P.total_bytes;
+  return MPM_OK;
+}
+
+mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, void* hip_stream, mpm_run** out) {
+  if (!desc || !out) return MPM_EINVAL;
+  *out = nullptr;
+  if (validate(*desc, nullptr) != MPM_OK) return MPM_EINVAL;
+  if (!dev_workspace || (reinterpret_cast<uintptr_t>(dev_workspace) & 255)) return MPM_EINVAL;
+  mpm_run* r = new (std::nothrow) mpm_run();
+  if (!r) return MPM_ENOMEM;
+  build_plan(*desc, &r->P);
+  if (bytes < r->P.total_bytes) { delete r; return MPM_ENOMEM; }
+  const Plan& P = r->P;
+  r->g = make_geo(P);
+  r->st = static_cast<hipStream_t>(hip_stream);
+  hipGetDevice(&r->device);
+  r->ws = static_cast<char*>(dev_workspace);
+  auto D = [&](size_t off) { return reinterpret_cast<double*>(r->ws + off); };
+  r->K = D(P.off_K); r->q = D(P.off_q); r->s = D(P.off_s); r->s2 = D(P.off_s2);
+  r->kn = D(P.off_kn); r->km = D(P.off_km); r->ux = D(P.off_ux); r->uy = D(P.off_uy);
+  r->uxm = D(P.off_uxm); r->uym = D(P.off_uym); r->fac = D(P.off_fac); r->S = D(P.off_S);
+  r->h = D(P.off_h); r->vbnd = D(P.off_vbnd); r->ubnd = D(P.off_ubnd); r->leafK = D(P.off_leafK);
+  r->leafr = D(P.off_leafr); r->front = D(P.off_front); r->fI = D(P.off_fI); r->cB = D(P.off_cB);
+  r->panel = D(P.off_panel); r->y = D(P.off_y); r->red = D(P.off_red); r->scal = D(P.off_scal);
+  r->err = reinterpret_cast<int32_t*>(r->scal + SC_COUNT);
+  r->subdofs_d = reinterpret_cast<const int32_t*>(r->ws + P.off_subdofs);
+  r->nd.nodes = reinterpret_cast<const NodeDev*>(r->ws + P.off_nodes);
+  r->nd.levels = reinterpret_cast<const int32_t*>(r->ws + P.off_levels);
+  r->nd.dof_pool = reinterpret_cast<const int32_t*>(r->ws + P.off_dofpool);
+  r->nd.map_pool = reinterpret_cast<const int32_t*>(r->ws + P.off_mappool);
+  r->nd.front = r->front; r->nd.fI = r->fI; r->nd.cB = r->cB; r->nd.panel = r->panel;
+  r->nd.leafK = r->leafK; r->nd.leafr = r->leafr; r->nd.y = r->y; r->nd.ndmax = P.ndmax;
+  r->nd.piv_b = P.piv_b; r->nd.err = r->err;
+  r->M = P.d.mu_o / P.d.mu_w;
+  r->fmax_deriv = max_fprime(r->M);
+  r->area = P.d.lx * P.d.ly;
+  auto fail = [&](mpm_status s) { if (r->pinned) hipHostFree(r->pinned); delete r; return s; };
+  if (hipHostMalloc(reinterpret_cast<void**>(&r->pinned), 64, hipHostMallocDefault) != hipSuccess) return fail(MPM_ENOMEM);
+  if (hipEventCreateWithFlags(&r->ev_eps, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
+  // upload the plan's index tables
+  auto up = [&](size_t off, const void* src, size_t n) {
+    return n ? hipMemcpyAsync(r->ws + off, src, n, hipMemcpyHostToDevice, r->st) : hipSuccess;
+  };
+  if (up(P.off_nodes, P.nodes.data(), P.nodes.size() * sizeof(NodeDev)) ||
+      up(P.off_levels, P.level_flat.data(), P.level_flat.size() * 4) ||
+      up(P.off_dofpool, P.dof_pool.data(), P.dof_pool.size() * 4) ||
+      up(P.off_mappool, P.map_pool.data(), P.map_pool.size() * 4) ||
+      up(P.off_subdofs, P.sub_dofs.data(), P.sub_dofs.size() * 4) ||
+      up(P.off_subndof, P.sub_ndof.data(), P.sub_ndof.size() * 4) ||
+      hipMemsetAsync(r->scal, 0, SC_COUNT * 8 + 64, r->st) ||
+      hipMemsetAsync(r->y, 0, size_t(std::max(P.n_iface, 1)) * 8, r->st) ||
+      hipStreamSynchronize(r->st))
+    return fail(MPM_EHIP);
+  *out = r;
+  return MPM_OK;
+}
+
+mpm_status mpm_set_fields(mpm_run* r, const double* K, const double* q, const double* s0) {
+  if (!r || !K || !s0) return MPM_EINVAL;
+  const size_t nb = size_t(r->P.nx) * r->P.ny * 8;
+  HIPCHK(r, hipMemcpyAsync(r->K, K, nb, hipMemcpyDeviceToDevice, r->st));
+  if (q) HIPCHK(r, hipMemcpyAsync(r->q, q, nb, hipMemcpyDeviceToDevice, r->st));
+  else HIPCHK(r, hipMemsetAsync(r->q, 0, nb, r->st));
+  HIPCHK(r, hipMemcpyAsync(r->s, s0, nb, hipMemcpyDeviceToDevice, r->st));
+  HIPCHK(r, hipMemsetAsync(r->km, 0, nb, r->st));
+  r->fields = true;
+  r->started = false;
+  return MPM_OK;
+}
+
+mpm_status mpm_start(mpm_run* r) {
+  if (!r) return MPM_EINVAL;
+  if (!r->fields || r->poisoned) return MPM_ESTATE;
+  // Algorithm 1, lines 1-4
+  HIPCHK(r, hipMemsetAsync(r->scal, 0, SC_COUNT * 8, r->st));
+  mpm_status st = kappa_and_eps(r);
+  if (st) return st;
+  r->te = 0; r->tm = 0; r->ntr = 0;
+  st = mrcm_update(r);
+  if (st) return st;
+  r->te = 1;
+  r->eps_prev = r->P.d.eta;
+  r->eps_pending = false;
+  r->last_branch = MPM_FORCE_MRCM;
+  r->started = true;
+  return MPM_OK;
+}
+
+mpm_status mpm_transport(mpm_run* r, int32_t nsteps) {
+  if (!r || nsteps < 0) return MPM_EINVAL;
+  if (!r->started || r->poisoned) return MPM_ESTATE;
+  return transport(r, nsteps);
+}
+
+mpm_status mpm_velocity_update(mpm_run* r, int32_t force) {
+  if (!r || force < -1 || force > 1) return MPM_EINVAL;
+  if (!r->started || r->poisoned) return MPM_ESTATE;
+  return velocity_update(r, force);
+}
+
+mpm_status mpm_step(mpm_run* r, int32_t force) {
+  if (!r || force < -1 || force > 1) return MPM_EINVAL;
+  if (!r->started || r->poisoned) return MPM_ESTATE;
+  mpm_status st = transport(r, r->P.d.cn);
+  if (st) return st;
+  return velocity_update(r, force);
+}
+
+mpm_status mpm_get_velocity(mpm_run* r, double* ux, double* uy) {
+  if (!r || !ux || !uy) return MPM_EINVAL;
+  if (!r->started) return MPM_ESTATE;
+  HIPCHK(r, hipMemcpyAsync(ux, r->ux, size_t(r->P.ny) * (r->P.nx + 1) * 8, hipMemcpyDeviceToDevice, r->st));
+  HIPCHK(r, hipMemcpyAsync(uy, r->uy, size_t(r->P.ny + 1) * r->P.nx * 8, hipMemcpyDeviceToDevice, r->st));
+  return MPM_OK;
+}
+
+mpm_status mpm_get_saturation(mpm_run* r, double* s) {
+  if (!r || !s) return MPM_EINVAL;
+  if (!r->fields) return MPM_ESTATE;
+  HIPCHK(r, hipMemcpyAsync(s, r->s, size_t(r->P.ny) * r->P.nx * 8, hipMemcpyDeviceToDevice, r->st));
+  return MPM_OK;
+}
+
+mpm_status mpm_get_stats(mpm_run* r, mpm_stats* out) {
+  if (!r || !out) return MPM_EINVAL;
+  double sc[SC_COUNT];
+  int32_t errw = 0;
+  HIPCHK(r, hipMemcpyAsync(sc, r->scal, sizeof(sc), hipMemcpyDeviceToHost, r->st));
+  HIPCHK(r, hipMemcpyAsync(&errw, r->err, 4, hipMemcpyDeviceToHost, r->st));
+  HIPCHK(r, hipStreamSynchronize(r->st));
+  if (r->prof) r->prof_collect();
+  std::memset(out, 0, sizeof(*out));
+  out->te = r->te;
+  out->tm = r->tm;
+  out->n_transport = r->ntr;
+  out->eps = r->eps_prev;
+  out->t = sc[SC_T];
+  out->pvi = sc[SC_PVI];
+  out->water_cut = sc[SC_WCUT];
+  out->dt = sc[SC_DT];
+  out->breakthrough = sc[SC_WCUT] >= r->P.d.breakthrough_cut ? 1 : 0;
+  out->last_branch = r->last_branch;
+  out->error_word = errw;
+  if (errw) {
+    r->poisoned = true;
+    if (errw & ERR_NOTSPD) return MPM_ENOTSPD;
+    if (errw & ERR_SINGULAR) return MPM_ESINGULAR;
+    return MPM_ENONFINITE;
+  }
+  return MPM_OK;
+}
+
+mpm_status mpm_destroy(mpm_run* r) {
+  if (!r) return MPM_EINVAL;
+  int32_t errw = 0;
+  hipMemcpyAsync(&errw, r->err, 4, hipMemcpyDeviceToHost, r->st);
+  hipStreamSynchronize(r->st);
+  for (auto& p : r->pending) { hipEventDestroy(p.second.first); hipEventDestroy(p.second.second); }
+  for (auto e : r->pool) hipEventDestroy(e);
+  if (r->ev_eps) hipEventDestroy(r->ev_eps);
+  if (r->pinned) hipHostFree(r->pinned);
+  delete r;
+  if (errw & ERR_NOTSPD) return MPM_ENOTSPD;
+  if (errw & ERR_SINGULAR) return MPM_ESINGULAR;
+  if (errw) return MPM_ENONFINITE;
+  return MPM_OK;
+}
+
+mpm_status mpm_plan_info(const mpm_run* r, int64_t* n_sub, int64_t* n_iface, int64_t* n_nodes, int64_t* n_levels) {
+  if (!r) return MPM_EINVAL;
+  if (n_sub) *n_sub = r->P.nsub;
+  if (n_iface) *n_iface = r->P.n_iface;
+  if (n_nodes) *n_nodes = int64_t(r->P.nodes.size());
+  if (n_levels) *n_levels = int64_t(r->P.level_nodes.size()) - 1;
+  return MPM_OK;
+}
+
+mpm_status mpm_profile(mpm_run* r, int32_t enable, int32_t reset, int32_t cap, const char** names, double* ms,
+                       int64_t* count, int32_t* n) {
+  if (!r) return MPM_EINVAL;
+  HIPCHK(r, hipStreamSynchronize(r->st));
+  r->prof_collect();
+  int k = 0;
+  for (auto& e : r->prof_acc) {
+    if (k >= cap) break;
+    if (names) names[k] = e.second.name;
+    if (ms) ms[k] = e.second.count ? e.second.ms / e.second.count : 0.0;
+    if (count) count[k] = e.second.count;
+    ++k;
+  }
+  if (n) *n = k;
+  if (reset) r->prof_acc.clear();
+  r->prof = enable != 0;
+  return MPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Device-side geometry and helpers shared by the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "plan.hpp"
+
+namespace mpm {
+
+// Everything a kernel needs to know about the grid and the decomposition, passed by value.
+struct Geo {
+  int nx, ny, mx, my, Sx, Sy, nsub;
+  int nc, band, xfast, nb, ne_x, ne_y, n_vert, ndmax;
+  double hx, hy, alpha;
+  double mu_w, mu_o;
+  int bc_kind[4];
+  double bc_value[4];
+  double s_inj;
+};
+
+// Error bits of the device error word.
+enum : int32_t { ERR_NOTSPD = 1, ERR_SINGULAR = 2, ERR_NONFINITE = 4 };
+
+// ---------------------------------------------------------------- local cell ordering
+// Cells of a subdomain are numbered along the shorter side first so that the 5-point
+// matrix has half bandwidth min(mx, my).
+__host__ __device__ inline int loc_index(const Geo& g, int i, int j) {
+  return g.xfast ? j * g.mx + i : i * g.my + j;
+}
+__host__ __device__ inline void loc_ij(const Geo& g, int c, int* i, int* j) {
+  if (g.xfast) { *i = c % g.mx; *j = c / g.mx; }
+  else { *j = c % g.my; *i = c / g.my; }
+}
+
+// ---------------------------------------------------------------- boundary faces
+// Boundary faces of a subdomain: W faces j=0..my-1, E faces, S faces i=0..mx-1, N faces.
+struct BFace {
+  int side;     // 0 W, 1 E, 2 S, 3 N
+  int i, j;     // local cell adjacent to the face
+  int k;        // index along the side
+  int kind;     // FACE_NEU / FACE_DIR / FACE_ROB
+  double flen;  // face length
+  double d;     // cell width normal to the face
+  double H;     // subdomain length normal to the face (Robin coefficient)
+  double sgn;   // n-check . n^i on Gamma: +1 on E and N sides, -1 on W and S sides
+  double value; // physical datum: g (DIR) or outward flux z (NEU)
+};
+
+__host__ __device__ inline BFace bface(const Geo& g, int I, int J, int f) {
+  BFace b;
+  if (f < g.my) { b.side = 0; b.k = f; b.i = 0; b.j = f; }
+  else if (f < 2 * g.my) { b.side = 1; b.k = f - g.my; b.i = g.mx - 1; b.j = b.k; }
+  else if (f < 2 * g.my + g.mx) { b.side = 2; b.k = f - 2 * g.my; b.i = b.k; b.j = 0; }
+  else { b.side = 3; b.k = f - 2 * g.my - g.mx; b.i = b.k; b.j = g.my - 1; }
+  const bool vert = b.side < 2;
+  b.flen = vert ? g.hy : g.hx;
+  b.d = vert ? g.hx : g.hy;
+  b.H = vert ? g.mx * g.hx : g.my * g.hy;
+  b.sgn = (b.side == 1 || b.side == 3) ? 1.0 : -1.0;
+  bool phys = (b.side == 0 && I == 0) || (b.side == 1 && I == g.Sx - 1) ||
+              (b.side == 2 && J == 0) || (b.side == 3 && J == g.Sy - 1);
+  b.value = 0.0;
+  if (!phys) {
+    b.kind = FACE_ROB;
+  } else {
+    const int kind = g.bc_kind[b.side];
+    if (kind == MPM_BC_PRESSURE) { b.kind = FACE_DIR; b.value = g.bc_value[b.side]; }
+    else { b.kind = FACE_NEU; b.value = kind == MPM_BC_FLUX ? g.bc_value[b.side] : 0.0; }
+  }
+  return b;
+}
+
+// Local position of the U unknown of the element of a Gamma face (P is the next one).
+__host__ __device__ inline int bface_dof(const Geo& g, int I, int J, const BFace& b) {
+  const bool hasW = I > 0, hasE = I < g.Sx - 1, hasS = J > 0;
+  const int offW = 0;
+  const int offE = offW + (hasW ? 2 * g.ne_y : 0);
+  const int offS = offE + (hasE ? 2 * g.ne_y : 0);
+  const int offN = offS + (hasS ? 2 * g.ne_x : 0);
+  const int off = b.side == 0 ? offW : b.side == 1 ? offE : b.side == 2 ? offS : offN;
+  const int per = b.side < 2 ? g.my / g.ne_y : g.mx / g.ne_x;
+  return off + 2 * (b.k / per);
+}
+
+// Transmissibility per unit length of a boundary face for conductivity kc of its cell.
+__host__ __device__ inline double bface_trans(const Geo& g, const BFace& b, double kc) {
+  if (b.kind == FACE_DIR) return 2.0 * kc / b.d;
+  if (b.kind == FACE_ROB) return 1.0 / (b.d / (2.0 * kc) + g.alpha * b.H / kc);
+  return 0.0;
+}
+__host__ __device__ inline double robin_beta(const Geo& g, const BFace& b, double kc) {
+  return g.alpha * b.H / kc;
+}
+// Harmonic transmissibility per unit length between two cells at distance d.
+__host__ __device__ inline double harm_trans(double kc, double kd, double d) {
+  return 1.0 / (d / (2.0 * kc) + d / (2.0 * kd));
+}
+
+__device__ inline void set_error(int32_t* err, int32_t bits) { atomicOr(err, bits); }
+
+}  // namespace mpm

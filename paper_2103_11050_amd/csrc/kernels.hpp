@@ -1,0 +1,53 @@
+// Launchers of the HIP kernels (host side), grouped by file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace mpm {
+
+// local.hip
+size_t local_smem_max(const Geo& g);
+void launch_kappa(hipStream_t st, int ncell, const double* s, const double* K, double* kn, const double* km,
+                  double mu_w, double mu_o, double* red, double* scal);
+void launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* fac, double* S,
+                  double* h, double* leafK, double* leafr, int32_t* err);
+void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
+                      const double* uym, const double* q, const double* fac, double* h, double* vbnd,
+                      double* leafr);
+void launch_flux(hipStream_t st, const Geo& g, const double* km, const double* S, const double* h,
+                 const double* vbnd, const double* y, const int32_t* sub_dofs, double* ubnd, int with_v);
+void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
+                      double* ux, double* uy, double* red_rate, double* red_qin, int32_t* err);
+void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double cfl,
+               double fmax_deriv, double* scal);
+
+// nd.hip: nested-dissection factorisation and solve of the interface system
+struct NdArgs {
+  const NodeDev* nodes;
+  const int32_t* levels;      // concatenated node lists per level
+  const int32_t* dof_pool;
+  const int32_t* map_pool;
+  double* front;
+  double* fI;
+  double* cB;
+  double* panel;
+  double* leafK;
+  double* leafr;
+  double* y;
+  int ndmax;
+  int piv_b;
+  int32_t* err;
+};
+void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nmax, int nImax);
+void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nmax, int nBmax);
+void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nImax);
+
+// transport.hip
+void launch_sat_step(hipStream_t st, const Geo& g, const double* s, double* s2, const double* ux,
+                     const double* uy, double* scal, double M, double area);
+void launch_water_cut(hipStream_t st, const Geo& g, const double* s, const double* ux, const double* uy,
+                      double* scal, double M);
+
+}  // namespace mpm

@@ -1,0 +1,232 @@
+// Host plan: validation, decomposition, nested dissection of the interface system, layout.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <unordered_map>
+
+namespace mpm {
+
+namespace {
+
+bool finite(double v) { return std::isfinite(v); }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Rect {
+  int I0, I1, J0, J1;
+};
+
+}  // namespace
+
+mpm_status validate(const mpm_desc& d, std::string* why) {
+  auto bad = [&](const char* m) {
+    if (why) *why = m;
+    return MPM_EINVAL;
+  };
+  if (d.abi_version != MPM_ABI_VERSION) return bad("abi_version mismatch");
+  if (d.nx <= 0 || d.ny <= 0) return bad("nx, ny must be positive");
+  if (d.sub_x <= 0 || d.sub_y <= 0) return bad("sub_x, sub_y must be positive");
+  if (d.nx % d.sub_x || d.ny % d.sub_y) return bad("sub_x, sub_y must divide nx, ny");
+  if (d.ne_x <= 0 || d.ne_y <= 0) return bad("ne_x, ne_y must be positive");
+  if (d.sub_x % d.ne_x || d.sub_y % d.ne_y) return bad("ne_x, ne_y must divide sub_x, sub_y");
+  if (!(d.lx > 0) || !(d.ly > 0) || !finite(d.lx) || !finite(d.ly)) return bad("lx, ly must be positive and finite");
+  if (!(d.alpha > 0) || !finite(d.alpha)) return bad("alpha must be positive and finite");
+  if (std::isnan(d.eta)) return bad("eta must not be NaN");
+  if (d.eps_norm != MPM_EPS_REL_L2 && d.eps_norm != MPM_EPS_ABS_L2) return bad("unknown eps_norm");
+  if (d.switch_rule != MPM_SWITCH_ALG1 && d.switch_rule != MPM_SWITCH_TEXT) return bad("unknown switch_rule");
+  if (d.precision != MPM_PREC_FP64 && d.precision != MPM_PREC_FP32_REFINE) return bad("unknown precision");
+  if (d.cn < 1) return bad("cn must be >= 1");
+  if (!(d.mu_w > 0) || !(d.mu_o > 0) || !finite(d.mu_w) || !finite(d.mu_o)) return bad("viscosities must be positive");
+  bool has_pressure = false;
+  for (int k = 0; k < 4; ++k) {
+    if (d.bc_kind[k] < 0 || d.bc_kind[k] > 2) return bad("unknown bc_kind");
+    if (!finite(d.bc_value[k])) return bad("bc_value must be finite");
+    has_pressure |= d.bc_kind[k] == MPM_BC_PRESSURE;
+  }
+  if (!has_pressure) return bad("at least one side must carry a pressure condition");
+  if (!(d.s_inj >= 0 && d.s_inj <= 1)) return bad("s_inj must lie in [0,1]");
+  if (!(d.cfl > 0 && d.cfl <= 1)) return bad("cfl must lie in (0,1]");
+  if (!(d.breakthrough_cut > 0 && d.breakthrough_cut <= 1)) return bad("breakthrough_cut must lie in (0,1]");
+  const int band = std::min(d.sub_x, d.sub_y);
+  const long nc = long(d.sub_x) * d.sub_y;
+  if (nc * (band + 1) * 8 > 64 * 1024) return bad("subdomain too large for the local factorisation (band storage > 64 KiB)");
+  if (2 * (d.sub_x + d.sub_y) > 64) return bad("subdomain boundary longer than 64 faces");
+  if (2 * (2 * d.ne_x + 2 * d.ne_y) > 128) return bad("more than 128 interface unknowns per subdomain");
+  return MPM_OK;
+}
+
+void build_plan(const mpm_desc& d, Plan* p) {
+  Plan& P = *p;
+  P.d = d;
+  P.nx = d.nx; P.ny = d.ny; P.mx = d.sub_x; P.my = d.sub_y;
+  P.Sx = d.nx / d.sub_x; P.Sy = d.ny / d.sub_y; P.nsub = P.Sx * P.Sy;
+  P.hx = d.lx / d.nx; P.hy = d.ly / d.ny;
+  P.ne_x = d.ne_x; P.ne_y = d.ne_y;
+  P.n_vert = (P.Sx - 1) * P.Sy * P.ne_y;
+  P.n_horiz = P.Sx * (P.Sy - 1) * P.ne_x;
+  P.n_elem = P.n_vert + P.n_horiz;
+  P.n_iface = 2 * P.n_elem;
+  P.nc = P.mx * P.my;
+  P.band = std::min(P.mx, P.my);
+  P.xfast = P.mx <= P.my ? 1 : 0;
+  P.nb = 2 * (P.mx + P.my);
+  P.ndmax = 4 * (P.ne_x + P.ne_y);
+
+  auto vert = [&](int I, int J, int k) { return (J * (P.Sx - 1) + I) * P.ne_y + k; };
+  auto horiz = [&](int I, int J, int k) { return P.n_vert + (J * P.Sx + I) * P.ne_x + k; };
+  auto push_e = [](std::vector<int32_t>& v, int e) { v.push_back(2 * e); v.push_back(2 * e + 1); };
+
+  // boundary unknowns of a rectangle of subdomains, order: left, right, bottom, top
+  auto rect_boundary = [&](const Rect& r) {
+    std::vector<int32_t> v;
+    if (r.I0 > 0)
+      for (int J = r.J0; J < r.J1; ++J)
+        for (int k = 0; k < P.ne_y; ++k) push_e(v, vert(r.I0 - 1, J, k));
+    if (r.I1 < P.Sx)
+      for (int J = r.J0; J < r.J1; ++J)
+        for (int k = 0; k < P.ne_y; ++k) push_e(v, vert(r.I1 - 1, J, k));
+    if (r.J0 > 0)
+      for (int I = r.I0; I < r.I1; ++I)
+        for (int k = 0; k < P.ne_x; ++k) push_e(v, horiz(I, r.J0 - 1, k));
+    if (r.J1 < P.Sy)
+      for (int I = r.I0; I < r.I1; ++I)
+        for (int k = 0; k < P.ne_x; ++k) push_e(v, horiz(I, r.J1 - 1, k));
+    return v;
+  };
+
+  P.sub_ndof.assign(P.nsub, 0);
+  P.sub_dofs.assign(size_t(P.nsub) * P.ndmax, -1);
+  for (int J = 0; J < P.Sy; ++J)
+    for (int I = 0; I < P.Sx; ++I) {
+      auto v = rect_boundary(Rect{I, I + 1, J, J + 1});
+      const int s = J * P.Sx + I;
+      P.sub_ndof[s] = int32_t(v.size());
+      std::copy(v.begin(), v.end(), P.sub_dofs.begin() + size_t(s) * P.ndmax);
+    }
+
+  // nested dissection: recursive bisection of the subdomain grid, post-order node ids
+  P.nodes.clear();
+  P.dof_pool.clear();
+  P.map_pool.clear();
+  std::vector<int> node_level;
+  std::function<std::pair<int, int>(Rect)> build = [&](Rect r) -> std::pair<int, int> {
+    if (r.I1 - r.I0 == 1 && r.J1 - r.J0 == 1) return {-1 - (r.J0 * P.Sx + r.I0), 0};
+    Rect a = r, b = r;
+    std::vector<int32_t> sep;
+    if (r.I1 - r.I0 >= r.J1 - r.J0) {
+      const int Im = (r.I0 + r.I1) / 2;
+      a.I1 = Im; b.I0 = Im;
+      for (int J = r.J0; J < r.J1; ++J)
+        for (int k = 0; k < P.ne_y; ++k) push_e(sep, vert(Im - 1, J, k));
+    } else {
+      const int Jm = (r.J0 + r.J1) / 2;
+      a.J1 = Jm; b.J0 = Jm;
+      for (int I = r.I0; I < r.I1; ++I)
+        for (int k = 0; k < P.ne_x; ++k) push_e(sep, horiz(I, Jm - 1, k));
+    }
+    auto ca = build(a);
+    auto cb = build(b);
+    auto bnd = rect_boundary(r);
+    NodeDev nd{};
+    nd.nI = int32_t(sep.size());
+    nd.nB = int32_t(bnd.size());
+    nd.n = nd.nI + nd.nB;
+    nd.level = 1 + std::max(ca.second, cb.second);
+    nd.child[0] = ca.first;
+    nd.child[1] = cb.first;
+    nd.dof_off = int32_t(P.dof_pool.size());
+    std::unordered_map<int32_t, int32_t> pos;
+    for (size_t i = 0; i < sep.size(); ++i) pos[sep[i]] = int32_t(i);
+    for (size_t i = 0; i < bnd.size(); ++i) pos[bnd[i]] = int32_t(sep.size() + i);
+    P.dof_pool.insert(P.dof_pool.end(), sep.begin(), sep.end());
+    P.dof_pool.insert(P.dof_pool.end(), bnd.begin(), bnd.end());
+    const Rect rc[2] = {a, b};
+    for (int c = 0; c < 2; ++c) {
+      auto cbnd = rect_boundary(rc[c]);
+      nd.map_off[c] = int32_t(P.map_pool.size());
+      nd.nB_child[c] = int32_t(cbnd.size());
+      for (int32_t g : cbnd) P.map_pool.push_back(pos.at(g));
+    }
+    P.nodes.push_back(nd);
+    return {int(P.nodes.size()) - 1, nd.level};
+  };
+  if (P.nsub > 1) {
+    auto r = build(Rect{0, P.Sx, 0, P.Sy});
+    P.root = r.first;
+  } else {
+    P.root = -1;
+  }
+  int maxL = 0;
+  for (auto& n : P.nodes) maxL = std::max(maxL, int(n.level));
+  P.level_nodes.assign(maxL + 1, {});
+  P.level_nmax.assign(maxL + 1, 0);
+  P.level_nImax.assign(maxL + 1, 0);
+  P.level_nBmax.assign(maxL + 1, 0);
+  for (size_t i = 0; i < P.nodes.size(); ++i) {
+    auto& n = P.nodes[i];
+    P.level_nodes[n.level].push_back(int32_t(i));
+    P.level_nmax[n.level] = std::max(P.level_nmax[n.level], n.n);
+    P.level_nImax[n.level] = std::max(P.level_nImax[n.level], n.nI);
+    P.level_nBmax[n.level] = std::max(P.level_nBmax[n.level], n.nB);
+  }
+  // per-node storage
+  int64_t fo = 0, io = 0, co = 0, po = 0;
+  for (auto& n : P.nodes) {
+    n.front_off = fo; fo += int64_t(n.n) * n.n;
+    n.fI_off = io; io += n.nI;
+    n.cB_off = co; co += n.nB;
+    n.panel_off = po; po += int64_t(P.piv_b) * P.piv_b + 2 * int64_t(P.piv_b) * n.n;
+  }
+  P.front_doubles = fo; P.fI_doubles = io; P.cB_doubles = co; P.panel_doubles = po;
+
+  // workspace layout
+  const size_t ncell = size_t(P.nx) * P.ny;
+  const size_t nfx = size_t(P.ny) * (P.nx + 1), nfy = size_t(P.ny + 1) * P.nx;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+  P.off_K = take(ncell * 8);
+  P.off_q = take(ncell * 8);
+  P.off_s = take(ncell * 8);
+  P.off_s2 = take(ncell * 8);
+  P.off_kn = take(ncell * 8);
+  P.off_km = take(ncell * 8);
+  P.off_ux = take(nfx * 8);
+  P.off_uy = take(nfy * 8);
+  P.off_uxm = take(nfx * 8);
+  P.off_uym = take(nfy * 8);
+  P.off_fac = take(size_t(P.nsub) * P.nc * (P.band + 1) * 8);
+  P.off_dinv = take(size_t(P.nsub) * P.nc * 8);
+  P.off_S = take(size_t(P.nsub) * P.nb * P.nb * 8);
+  P.off_h = take(size_t(P.nsub) * P.nb * 8);
+  P.off_vbnd = take(size_t(P.nsub) * P.nb * 8);
+  P.off_ubnd = take(size_t(P.nsub) * P.nb * 8);
+  P.off_leafK = take(size_t(P.nsub) * P.ndmax * P.ndmax * 8);
+  P.off_leafr = take(size_t(P.nsub) * P.ndmax * 8);
+  P.off_front = take(size_t(std::max<int64_t>(fo, 1)) * 8);
+  P.off_fI = take(size_t(std::max<int64_t>(io, 1)) * 8);
+  P.off_cB = take(size_t(std::max<int64_t>(co, 1)) * 8);
+  P.off_panel = take(size_t(std::max<int64_t>(po, 1)) * 8);
+  P.off_y = take(size_t(std::max(P.n_iface, 1)) * 8);
+  P.off_nodes = take(std::max<size_t>(P.nodes.size(), 1) * sizeof(NodeDev));
+  P.off_dofpool = take(std::max<size_t>(P.dof_pool.size(), 1) * 4);
+  P.off_mappool = take(std::max<size_t>(P.map_pool.size(), 1) * 4);
+  P.off_subdofs = take(P.sub_dofs.size() * 4);
+  P.off_subndof = take(P.sub_ndof.size() * 4);
+  P.level_off.assign(P.level_nodes.size() + 1, 0);
+  P.level_flat.clear();
+  for (size_t L = 0; L < P.level_nodes.size(); ++L) {
+    P.level_off[L] = int32_t(P.level_flat.size());
+    P.level_flat.insert(P.level_flat.end(), P.level_nodes[L].begin(), P.level_nodes[L].end());
+  }
+  P.level_off[P.level_nodes.size()] = int32_t(P.level_flat.size());
+  P.off_levels = take(std::max<size_t>(P.level_flat.size(), 1) * 4);
+  const size_t blocks = (ncell + 255) / 256 + size_t(P.nsub) + 64;
+  P.n_red = 4 * blocks;
+  P.off_red = take(P.n_red * 8);
+  P.off_scal = take(SC_COUNT * 8 + 64);
+  P.total_bytes = off;
+}
+
+}  // namespace mpm

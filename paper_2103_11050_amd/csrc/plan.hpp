@@ -1,0 +1,85 @@
+// Host-side plan of a run: decomposition, interface unknowns, nested-dissection tree of the
+// interface system and the layout of every buffer inside the caller's workspace.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mpm2p.h"
+
+namespace mpm {
+
+// Boundary-face kinds of a subdomain's faces (all faces of the subdomain boundary).
+enum FaceKind : int32_t { FACE_NEU = 0, FACE_DIR = 1, FACE_ROB = 2 };
+
+// Device view of one nested-dissection node.
+struct NodeDev {
+  int32_t n, nI, nB;          // front size, eliminated (separator) and boundary unknowns
+  int32_t level;
+  int32_t child[2];           // node ids, or -1-sub for a leaf child (subdomain id)
+  int32_t map_off[2];         // offsets of the children's extend-add maps into map_pool
+  int32_t nB_child[2];        // boundary sizes of the children
+  int32_t dof_off;            // offset of the node's front unknowns (I then B) in dof_pool
+  int32_t pad;
+  int64_t front_off;          // offset (doubles) of the n x n front
+  int64_t fI_off;             // offset (doubles) of the eliminated part of the condensed rhs
+  int64_t cB_off;             // offset (doubles) of the condensed rhs passed to the parent
+  int64_t panel_off;          // offset (doubles) of the pivot-block scratch (b*b + 2*b*n)
+};
+
+struct Plan {
+  mpm_desc d;
+  int nx, ny, mx, my, Sx, Sy, nsub;
+  double hx, hy;
+  int ne_x, ne_y;
+  int n_vert, n_horiz, n_elem, n_iface;
+  int nc;                     // cells per subdomain
+  int band;                   // half bandwidth of the local matrices = min(mx, my)
+  int xfast;                  // 1: local cell order has x fastest (band = mx)
+  int nb;                     // boundary faces per subdomain = 2 (mx + my)
+  int ndmax;                  // max interface unknowns of a subdomain
+  // per subdomain
+  std::vector<int32_t> sub_ndof;      // interface unknowns
+  std::vector<int32_t> sub_dofs;      // nsub * ndmax global unknown ids (local order), -1 pad
+  // nested dissection
+  std::vector<NodeDev> nodes;         // bottom-up; leaves are not nodes
+  std::vector<std::vector<int32_t>> level_nodes;  // level 1.. -> node ids
+  std::vector<int32_t> dof_pool;
+  std::vector<int32_t> map_pool;
+  int root = -1;
+  int piv_b = 32;                     // pivot block of the blocked sweep
+  std::vector<int32_t> level_nmax, level_nImax, level_nBmax;
+  // workspace layout (byte offsets)
+  size_t off_K, off_q, off_s, off_s2, off_kn, off_km, off_ux, off_uy, off_uxm, off_uym;
+  size_t off_fac, off_dinv, off_S, off_h, off_vbnd, off_ubnd, off_leafK, off_leafr;
+  size_t off_front, off_fI, off_cB, off_panel, off_y;
+  size_t off_nodes, off_dofpool, off_mappool, off_subdofs, off_subndof, off_levels;
+  std::vector<int32_t> level_off;     // offsets of each level's node list in the uploaded level array
+  std::vector<int32_t> level_flat;
+  size_t off_red, off_scal;
+  size_t n_red;               // doubles in the reduction scratch
+  size_t total_bytes;
+  int64_t front_doubles = 0, panel_doubles = 0, fI_doubles = 0, cB_doubles = 0;
+};
+
+// Validates the descriptor; returns MPM_OK or MPM_EINVAL with a message.
+mpm_status validate(const mpm_desc& d, std::string* why);
+// Builds the plan (decomposition, tree, layout). Assumes validate() passed.
+void build_plan(const mpm_desc& d, Plan* p);
+
+// Scalars kept on the device (indices into the scalar block of the workspace).
+enum Scalar : int {
+  SC_EPS_NUM = 0,   // sum (kappa^n - kappa^m)^2
+  SC_EPS_DEN,       // sum (kappa^m)^2
+  SC_DT,            // transport sub-step
+  SC_QIN,           // boundary inflow
+  SC_T,             // simulated time
+  SC_PVI,
+  SC_WCUT,
+  SC_MAXRATE,
+  SC_COUNT = 16
+};
+
+}  // namespace mpm

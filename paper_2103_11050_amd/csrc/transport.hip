@@ -1,0 +1,93 @@
+// Saturation transport (eq. BL2D): explicit Euler in time with first-order upwind fluxes and
+// the velocity frozen over the sub-steps (Section 4). HBM-bound stencil: each thread updates
+// one cell from its four face fluxes and the upwind saturations.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace mpm {
+
+namespace {
+
+__device__ inline double fracflow(double s, double M) {
+  const double a = M * s * s;
+  const double o = 1.0 - s;
+  return a / (a + o * o);
+}
+
+}  // namespace
+
+// s2 = s - dt/|c| sum_f |f| u_f f(s_upwind); the injected saturation on inflow boundary faces.
+__global__ void __launch_bounds__(256)
+k_sat_step(Geo g, const double* __restrict__ s, double* __restrict__ s2, const double* __restrict__ ux,
+           const double* __restrict__ uy, double* __restrict__ scal, double M, double area) {
+  const int gi = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int gj = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const double dt = scal[SC_DT];
+  if (gi < g.nx && gj < g.ny) {
+    const int c = gj * g.nx + gi;
+    const double sc = s[c];
+    const double uW = ux[gj * (g.nx + 1) + gi];
+    const double uE = ux[gj * (g.nx + 1) + gi + 1];
+    const double uS = uy[gj * g.nx + gi];
+    const double uN = uy[(gj + 1) * g.nx + gi];
+    const double sW = gi > 0 ? s[c - 1] : g.s_inj;
+    const double sE = gi < g.nx - 1 ? s[c + 1] : g.s_inj;
+    const double sS = gj > 0 ? s[c - g.nx] : g.s_inj;
+    const double sN = gj < g.ny - 1 ? s[c + g.nx] : g.s_inj;
+    const double FW = g.hy * uW * fracflow(uW > 0.0 ? sW : sc, M);
+    const double FE = g.hy * uE * fracflow(uE > 0.0 ? sc : sE, M);
+    const double FS = g.hx * uS * fracflow(uS > 0.0 ? sS : sc, M);
+    const double FN = g.hx * uN * fracflow(uN > 0.0 ? sc : sN, M);
+    s2[c] = sc - dt / (g.hx * g.hy) * ((FE - FW) + (FN - FS));
+  }
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    scal[SC_T] += dt;
+    scal[SC_PVI] += dt * scal[SC_QIN] / area;
+  }
+}
+
+// Water cut over boundary faces with outflow: sum |f| u f(s_c) / sum |f| u (fixed order).
+__global__ void __launch_bounds__(256)
+k_water_cut(Geo g, const double* __restrict__ s, const double* __restrict__ ux, const double* __restrict__ uy,
+            double* __restrict__ scal, double M) {
+  __shared__ double sq[256], sw[256];
+  double q = 0.0, w = 0.0;
+  const int nW = g.ny, nS = g.nx;
+  const int tot = 2 * nW + 2 * nS;
+  for (int e = threadIdx.x; e < tot; e += 256) {
+    double u, sc, fl;
+    if (e < nW) { const int j = e; u = -ux[j * (g.nx + 1)]; sc = s[j * g.nx]; fl = g.hy; }
+    else if (e < 2 * nW) { const int j = e - nW; u = ux[j * (g.nx + 1) + g.nx]; sc = s[j * g.nx + g.nx - 1]; fl = g.hy; }
+    else if (e < 2 * nW + nS) { const int i = e - 2 * nW; u = -uy[i]; sc = s[i]; fl = g.hx; }
+    else { const int i = e - 2 * nW - nS; u = uy[g.ny * g.nx + i]; sc = s[(g.ny - 1) * g.nx + i]; fl = g.hx; }
+    const double out = fl * fmax(u, 0.0);
+    q += out;
+    w += out * fracflow(sc, M);
+  }
+  sq[threadIdx.x] = q;
+  sw[threadIdx.x] = w;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      sq[threadIdx.x] += sq[threadIdx.x + o];
+      sw[threadIdx.x] += sw[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) scal[SC_WCUT] = sq[0] > 0.0 ? sw[0] / sq[0] : 0.0;
+}
+
+void launch_sat_step(hipStream_t st, const Geo& g, const double* s, double* s2, const double* ux,
+                     const double* uy, double* scal, double M, double area) {
+  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4);
+  hipLaunchKernelGGL(k_sat_step, grid, dim3(256), 0, st, g, s, s2, ux, uy, scal, M, area);
+}
+
+void launch_water_cut(hipStream_t st, const Geo& g, const double* s, const double* ux, const double* uy,
+                      double* scal, double M) {
+  hipLaunchKernelGGL(k_water_cut, dim3(1), dim3(256), 0, st, g, s, ux, uy, scal, M);
+}
+
+}  // namespace mpm

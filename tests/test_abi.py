@@ -1,0 +1,91 @@
+"""The C-ABI library loads and exports every symbol of include/mpm2p.h; descriptor
+validation and argument errors are caught on the host before any device work (CPU only)."""
+import ctypes
+import math
+import os
+
+import pytest
+
+from paper_2103_11050_amd import binding, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpm2p.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2103_11050_amd import build
+        build.build(verbose=False)
+    return binding.load()
+
+
+def test_exports_every_header_symbol(lib):
+    names = binding.header_symbols(HEADER)
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(binding._SIGS), set(names) ^ set(binding._SIGS)
+
+
+def test_status_strings(lib):
+    for code in range(0, -8, -1):
+        s = lib.mpm_status_str(code).decode()
+        assert s and s != "unknown status"
+    assert lib.mpm_status_str(-99).decode() == "unknown status"
+
+
+def _size(cfg, **kw):
+    d = binding.make_desc(cfg)
+    for k, v in kw.items():
+        setattr(d, k, v)
+    n = ctypes.c_size_t()
+    return binding.load().mpm_workspace_size(ctypes.byref(d), ctypes.byref(n)), n.value
+
+
+def test_workspace_size_valid(lib):
+    st, n = _size(inputs.config("c1"))
+    assert st == 0 and n > 0
+    st3, n3 = _size(inputs.config("c3"))
+    assert st3 == 0 and n3 > n
+
+
+@pytest.mark.parametrize("field,value", [
+    ("abi_version", 2), ("nx", 0), ("sub_x", 5), ("ne_x", 3), ("alpha", 0.0), ("alpha", float("nan")),
+    ("eta", float("nan")), ("cn", 0), ("mu_w", -1.0), ("cfl", 1.5), ("s_inj", 2.0), ("eps_norm", 7),
+    ("switch_rule", 3), ("precision", 9), ("breakthrough_cut", 0.0), ("lx", -1.0),
+])
+def test_invalid_descriptor(lib, field, value):
+    st, _ = _size(inputs.config("c1"), **{field: value})
+    assert st == binding.MPM_EINVAL
+
+
+def test_no_pressure_boundary_rejected(lib):
+    cfg = inputs.config("c1", bc_kind=[2, 0, 0, 0])
+    st, _ = _size(cfg)
+    assert st == binding.MPM_EINVAL
+
+
+def test_oversized_subdomain_rejected(lib):
+    cfg = inputs.config("c1", nx=64, ny=64, sub_x=32, sub_y=32, ne_x=4, ne_y=4)
+    st, _ = _size(cfg)
+    assert st == binding.MPM_EINVAL
+
+
+def test_eta_infinity_accepted(lib):
+    st, _ = _size(inputs.config("c1", eta=math.inf))
+    assert st == 0
+
+
+def test_null_and_misaligned_arguments(lib):
+    d = binding.make_desc(inputs.config("c1"))
+    h = ctypes.c_void_p()
+    assert lib.mpm_create(ctypes.byref(d), None, 0, None, ctypes.byref(h)) == binding.MPM_EINVAL
+    assert lib.mpm_create(ctypes.byref(d), ctypes.c_void_p(0x1001), 1 << 20, None, ctypes.byref(h)) == binding.MPM_EINVAL
+    assert lib.mpm_create(None, None, 0, None, ctypes.byref(h)) == binding.MPM_EINVAL
+    assert lib.mpm_workspace_size(None, None) == binding.MPM_EINVAL
+    for fn in ("mpm_start", "mpm_destroy"):
+        assert getattr(lib, fn)(None) == binding.MPM_EINVAL
+    assert lib.mpm_step(None, -1) == binding.MPM_EINVAL
+    assert lib.mpm_transport(None, 1) == binding.MPM_EINVAL
+    assert lib.mpm_get_stats(None, None) == binding.MPM_EINVAL

@@ -1,0 +1,153 @@
+"""Parity of the HIP path with the FP64 oracle on the same seeded inputs (GPU only).
+
+Velocity: relative L2 error in the RT0-trapezoidal norm <= 1e-10 (FP64 path).
+Saturation: relative L1 error <= 1e-9. Branch decisions must agree step by step.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import downscale as odown
+from oracle import fine, mpm as ompm, mrcm as omrcm, physics, splitting
+from paper_2103_11050_amd import inputs
+
+from .gpu_common import FP64_SAT_TOL, FP64_VEL_TOL, sat_rel_err, to_np, vel_rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def binding():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_11050_amd import binding as b
+    b.load()
+    return b
+
+
+def _gpu_run(binding, cfg, K, s0=None):
+    dev = torch.device("cuda:0")
+    Kt = torch.from_numpy(np.ascontiguousarray(K)).to(dev)
+    s0 = np.zeros_like(K) if s0 is None else s0
+    st = torch.from_numpy(np.ascontiguousarray(s0)).to(dev)
+    r = binding.Run(cfg, Kt, st)
+    return r
+
+
+SHAPES = [
+    # nx, ny, sub_x, sub_y, ne_x, ne_y
+    (32, 32, 8, 8, 2, 2),
+    (12, 8, 4, 4, 2, 1),
+    (24, 16, 8, 4, 4, 2),
+    (20, 10, 20, 10, 1, 1),     # one subdomain, no interface
+    (48, 8, 8, 8, 1, 4),        # one row of subdomains
+    (12, 12, 4, 4, 4, 4),       # one fine face per interface element
+    (30, 20, 10, 10, 5, 2),     # 3 x 2 subdomains, ragged tree
+    (40, 24, 8, 8, 2, 2),       # 5 x 3 subdomains
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_mrcm_velocity_matches_oracle(binding, shape):
+    nx, ny, mx, my, nex, ney = shape
+    print(f"[gpu] mrcm shape={shape}", flush=True)
+    cfg, K = inputs.random_problem(31 + nx + ny, nx, ny, mx, my, nex, ney, sigma2=2.0, corr_len=0.2)
+    s0 = np.random.default_rng(3).uniform(0, 1, K.shape)
+    kap = physics.conductivity(s0, K, cfg["mu_w"], cfg["mu_o"])
+    rx, ry, _, _ = ompm.mrcm_velocity(cfg, kap)
+    r = _gpu_run(binding, cfg, K, s0)
+    r.start()
+    ux, uy = r.velocity()
+    st = r.stats()
+    assert st["error_word"] == 0
+    err = vel_rel_err(cfg, to_np(ux), to_np(uy), rx, ry)
+    print(f"    rel L2 velocity error {err:.3e}", flush=True)
+    assert err <= FP64_VEL_TOL
+    r.close()
+
+
+def test_one_face_elements_reproduce_fine_solve(binding):
+    """MRCM with one fine face per element equals the undecomposed fine solve (Section 5.4)."""
+    cfg, K = inputs.random_problem(77, 48, 32, 8, 8, 8, 8, sigma2=3.0, corr_len=0.1)
+    kap = physics.conductivity(np.zeros_like(K), K, cfg["mu_w"], cfg["mu_o"])
+    _, fx, fy = fine.fine_solve(cfg, kap)
+    r = _gpu_run(binding, cfg, K)
+    r.start()
+    ux, uy = r.velocity()
+    assert vel_rel_err(cfg, to_np(ux), to_np(uy), fx, fy) <= FP64_VEL_TOL
+
+
+def _compare_runs(binding, cfg, K, nsteps, label, forced=None, vel_tol=FP64_VEL_TOL, sat_tol=FP64_SAT_TOL):
+    print(f"[gpu] run {label} steps={nsteps}", flush=True)
+    s0 = inputs.initial_saturation(cfg)
+    orun = splitting.start(cfg, K, s0)
+    r = _gpu_run(binding, cfg, K, s0)
+    r.start()
+    ux, uy = r.velocity()
+    errs = [vel_rel_err(cfg, to_np(ux), to_np(uy), orun.ux, orun.uy)]
+    assert errs[0] <= vel_tol, errs
+    worst_s = 0.0
+    for n in range(1, nsteps + 1):
+        f = None if forced is None else forced[n]
+        branch = splitting.step(orun, f)
+        force = binding.AUTO if f is None else (binding.FORCE_MRCM if f == "mrcm" else binding.FORCE_MPM)
+        # replay the oracle's decision where epsilon sits on the threshold (rounding tie)
+        decide = orun.history[-1]["decide"]
+        if f is None and abs(decide - cfg["eta"]) <= 1e-9 * max(abs(cfg["eta"]), 1e-300):
+            force = binding.FORCE_MRCM if branch == "mrcm" else binding.FORCE_MPM
+        r.step(force)
+        st = r.stats()
+        assert st["error_word"] == 0
+        gb = "mrcm" if st["last_branch"] == binding.FORCE_MRCM else "mpm"
+        assert gb == branch, (n, gb, branch)
+        ux, uy = r.velocity()
+        e = vel_rel_err(cfg, to_np(ux), to_np(uy), orun.ux, orun.uy)
+        es = sat_rel_err(to_np(r.saturation()), orun.s)
+        errs.append(e)
+        worst_s = max(worst_s, es)
+        assert e <= vel_tol, (n, e)
+        assert es <= sat_tol, (n, es)
+        assert math.isclose(st["eps"], orun.eps, rel_tol=1e-8, abs_tol=1e-14), (n, st["eps"], orun.eps)
+        assert math.isclose(st["pvi"], orun.pvi, rel_tol=1e-10), (n, st["pvi"], orun.pvi)
+        assert math.isclose(st["water_cut"], orun.wcut, rel_tol=1e-8, abs_tol=1e-14)
+        assert st["te"] == orun.n and st["tm"] == orun.ell + 1
+    print(f"    max rel velocity error {max(errs):.3e}, max rel saturation error {worst_s:.3e}", flush=True)
+    r.close()
+    return orun
+
+
+def test_c1_full_run(binding):
+    """Workload 1 (32^2, 4x4 subdomains of 8^2, 2 elements per side): all 51 elliptic solves."""
+    cfg = inputs.config("c1")
+    K = inputs.permeability(cfg)
+    _compare_runs(binding, cfg, K, cfg["steps"], "c1")
+
+
+def test_mpm_and_mrcm_mixed(binding):
+    """A small high-contrast case with a low threshold so both branches occur."""
+    cfg, K = inputs.random_problem(5, 32, 24, 8, 8, 2, 4, sigma2=4.0, corr_len=0.15, eta=0.002, mu_o=40.0)
+    orun = _compare_runs(binding, cfg, K, 25, "mixed")
+    branches = [h["branch"] for h in orun.history]
+    assert "mpm" in branches[1:] and "mrcm" in branches[1:]
+
+
+def test_text_switch_rule_and_abs_norm(binding):
+    cfg, K = inputs.random_problem(9, 24, 24, 8, 8, 2, 2, sigma2=2.0, corr_len=0.2, eta=1e-3,
+                                   switch_rule="text", eps_norm="abs")
+    _compare_runs(binding, cfg, K, 12, "text-abs")
+
+
+def test_c2_window(binding):
+    """Workload 2 (256^2, 16x16 subdomains of 16^2, 4 elements per side, log-variance 4)."""
+    cfg = inputs.config("c2")
+    K = inputs.permeability(cfg)
+    _compare_runs(binding, cfg, K, 4, "c2")
+
+
+def test_c2_forced_update(binding):
+    cfg = inputs.config("c2")
+    K = inputs.permeability(cfg)
+    _compare_runs(binding, cfg, K, 3, "c2-forced", forced=[None, "mpm", "mrcm", "mpm"])
