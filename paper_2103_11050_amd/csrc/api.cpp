@@ -135,7 +135,9 @@ Geo make_geo(const Plan& P) {
   g.nc = P.nc; g.band = P.band; g.xfast = P.xfast; g.nb = P.nb; g.ne_x = P.ne_x; g.ne_y = P.ne_y;
   g.n_vert = P.n_vert; g.ndmax = P.ndmax;
   g.hx = P.hx; g.hy = P.hy; g.alpha = P.d.alpha; g.mu_w = P.d.mu_w; g.mu_o = P.d.mu_o;
-  for (int k = 0; k < 4; ++k) { g.bc_kind[k] = P.d.bc_kind[k]; g.bc_value[k] = P.d.bc_value[k]; }
+  g.bc_pack = 0;
+  for (int k = 0; k < 4; ++k) g.bc_pack |= (P.d.bc_kind[k] & 3) << (2 * k);
+  g.bc_v0 = P.d.bc_value[0]; g.bc_v1 = P.d.bc_value[1]; g.bc_v2 = P.d.bc_value[2]; g.bc_v3 = P.d.bc_value[3];
   g.s_inj = P.d.s_inj;
   return g;
 }
@@ -221,7 +223,11 @@ mpm_status mrcm_update(mpm_run* r) {
   HIPCHK(r, hipMemcpyAsync(r->km, r->kn, size_t(r->P.nx) * r->P.ny * 8, hipMemcpyDeviceToDevice, r->st));
   {
     Scope sc(r, "basis");
-    launch_basis(r->st, r->g, r->km, r->q, r->fac, r->S, r->h, r->leafK, r->leafr, r->err);
+    launch_basis(r->st, r->g, r->km, r->q, r->S, r->h, r->leafK, r->leafr, r->err);
+  }
+  {
+    Scope sc(r, "line_factor");
+    launch_line_factor(r->st, r->g, r->km, r->fac, r->err);
   }
   nd_factor(r);
   nd_solve(r);

@@ -14,10 +14,19 @@ struct Geo {
   int nc, band, xfast, nb, ne_x, ne_y, n_vert, ndmax;
   double hx, hy, alpha;
   double mu_w, mu_o;
-  int bc_kind[4];
-  double bc_value[4];
+  int bc_pack;          // MPM_BC_* of side s in bits 2s..2s+1 (sides W, E, S, N)
+  double bc_v0, bc_v1, bc_v2, bc_v3;
   double s_inj;
 };
+
+// Physical boundary data of a side without a run-time index into the struct (which would
+// force the by-value kernel argument into scratch memory).
+__host__ __device__ __forceinline__ int bc_kind_of(const Geo& g, int side) { return (g.bc_pack >> (2 * side)) & 3; }
+__host__ __device__ __forceinline__ double bc_value_of(const Geo& g, int side) {
+  const double a = (side & 1) ? g.bc_v1 : g.bc_v0;
+  const double b = (side & 1) ? g.bc_v3 : g.bc_v2;
+  return (side & 2) ? b : a;
+}
 
 // Error bits of the device error word.
 enum : int32_t { ERR_NOTSPD = 1, ERR_SINGULAR = 2, ERR_NONFINITE = 4 };
@@ -25,12 +34,16 @@ enum : int32_t { ERR_NOTSPD = 1, ERR_SINGULAR = 2, ERR_NONFINITE = 4 };
 // ---------------------------------------------------------------- local cell ordering
 // Cells of a subdomain are numbered along the shorter side first so that the 5-point
 // matrix has half bandwidth min(mx, my).
-__host__ __device__ inline int loc_index(const Geo& g, int i, int j) {
+__host__ __device__ __forceinline__ int loc_index(const Geo& g, int i, int j) {
   return g.xfast ? j * g.mx + i : i * g.my + j;
 }
-__host__ __device__ inline void loc_ij(const Geo& g, int c, int* i, int* j) {
-  if (g.xfast) { *i = c % g.mx; *j = c / g.mx; }
-  else { *j = c % g.my; *i = c / g.my; }
+__host__ __device__ __forceinline__ void loc_ij(const Geo& g, int c, int* i, int* j) {
+  // values first, then unconditional stores (a conditional store target would be turned into
+  // an address select and force the locals into scratch)
+  const int len = g.xfast ? g.mx : g.my;
+  const int a = c % len, b = c / len;
+  *i = g.xfast ? a : b;
+  *j = g.xfast ? b : a;
 }
 
 // ---------------------------------------------------------------- boundary faces
@@ -47,7 +60,7 @@ struct BFace {
   double value; // physical datum: g (DIR) or outward flux z (NEU)
 };
 
-__host__ __device__ inline BFace bface(const Geo& g, int I, int J, int f) {
+__host__ __device__ __forceinline__ BFace bface(const Geo& g, int I, int J, int f) {
   BFace b;
   if (f < g.my) { b.side = 0; b.k = f; b.i = 0; b.j = f; }
   else if (f < 2 * g.my) { b.side = 1; b.k = f - g.my; b.i = g.mx - 1; b.j = b.k; }
@@ -64,15 +77,16 @@ __host__ __device__ inline BFace bface(const Geo& g, int I, int J, int f) {
   if (!phys) {
     b.kind = FACE_ROB;
   } else {
-    const int kind = g.bc_kind[b.side];
-    if (kind == MPM_BC_PRESSURE) { b.kind = FACE_DIR; b.value = g.bc_value[b.side]; }
-    else { b.kind = FACE_NEU; b.value = kind == MPM_BC_FLUX ? g.bc_value[b.side] : 0.0; }
+    const int kind = bc_kind_of(g, b.side);
+    const double val = bc_value_of(g, b.side);
+    if (kind == MPM_BC_PRESSURE) { b.kind = FACE_DIR; b.value = val; }
+    else { b.kind = FACE_NEU; b.value = kind == MPM_BC_FLUX ? val : 0.0; }
   }
   return b;
 }
 
 // Local position of the U unknown of the element of a Gamma face (P is the next one).
-__host__ __device__ inline int bface_dof(const Geo& g, int I, int J, const BFace& b) {
+__host__ __device__ __forceinline__ int bface_dof(const Geo& g, int I, int J, const BFace& b) {
   const bool hasW = I > 0, hasE = I < g.Sx - 1, hasS = J > 0;
   const int offW = 0;
   const int offE = offW + (hasW ? 2 * g.ne_y : 0);
@@ -83,20 +97,42 @@ __host__ __device__ inline int bface_dof(const Geo& g, int I, int J, const BFace
   return off + 2 * (b.k / per);
 }
 
+// First boundary face and face count of the element carrying local interface unknown a
+// (local order: sides W, E, S, N present on Gamma, elements along each side, U then P).
+__host__ __device__ __forceinline__ void dof_faces(const Geo& g, int I, int J, int a, int* f0, int* cnt) {
+  const bool hasW = I > 0, hasE = I < g.Sx - 1, hasS = J > 0, hasN = J < g.Sy - 1;
+  const int nW = hasW ? 2 * g.ne_y : 0, nE = hasE ? 2 * g.ne_y : 0, nS = hasS ? 2 * g.ne_x : 0;
+  const int nN = hasN ? 2 * g.ne_x : 0;
+  const int perY = g.my / g.ne_y, perX = g.mx / g.ne_x;
+  if (a < nW) { *f0 = (a / 2) * perY; *cnt = perY; return; }
+  a -= nW;
+  if (a < nE) { *f0 = g.my + (a / 2) * perY; *cnt = perY; return; }
+  a -= nE;
+  if (a < nS) { *f0 = 2 * g.my + (a / 2) * perX; *cnt = perX; return; }
+  a -= nS;
+  if (a < nN) { *f0 = 2 * g.my + g.mx + (a / 2) * perX; *cnt = perX; return; }
+  *f0 = 0;
+  *cnt = 0;
+}
+
+__host__ __device__ __forceinline__ int sub_ndof(const Geo& g, int I, int J) {
+  return 2 * ((I > 0) + (I < g.Sx - 1)) * g.ne_y + 2 * ((J > 0) + (J < g.Sy - 1)) * g.ne_x;
+}
+
 // Transmissibility per unit length of a boundary face for conductivity kc of its cell.
-__host__ __device__ inline double bface_trans(const Geo& g, const BFace& b, double kc) {
+__host__ __device__ __forceinline__ double bface_trans(const Geo& g, const BFace& b, double kc) {
   if (b.kind == FACE_DIR) return 2.0 * kc / b.d;
   if (b.kind == FACE_ROB) return 1.0 / (b.d / (2.0 * kc) + g.alpha * b.H / kc);
   return 0.0;
 }
-__host__ __device__ inline double robin_beta(const Geo& g, const BFace& b, double kc) {
+__host__ __device__ __forceinline__ double robin_beta(const Geo& g, const BFace& b, double kc) {
   return g.alpha * b.H / kc;
 }
 // Harmonic transmissibility per unit length between two cells at distance d.
-__host__ __device__ inline double harm_trans(double kc, double kd, double d) {
+__host__ __device__ __forceinline__ double harm_trans(double kc, double kd, double d) {
   return 1.0 / (d / (2.0 * kc) + d / (2.0 * kd));
 }
 
-__device__ inline void set_error(int32_t* err, int32_t bits) { atomicOr(err, bits); }
+__device__ __forceinline__ void set_error(int32_t* err, int32_t bits) { atomicOr(err, bits); }
 
 }  // namespace mpm

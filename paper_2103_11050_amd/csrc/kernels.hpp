@@ -11,8 +11,11 @@ namespace mpm {
 size_t local_smem_max(const Geo& g);
 void launch_kappa(hipStream_t st, int ncell, const double* s, const double* K, double* kn, const double* km,
                   double mu_w, double mu_o, double* red, double* scal);
-void launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* fac, double* S,
-                  double* h, double* leafK, double* leafr, int32_t* err);
+void launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
+                  double* leafK, double* leafr, int32_t* err);
+// lines.hip
+void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double* fac, int32_t* err);
+size_t line_factor_doubles(int nsub, int nc, int band);
 void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                       const double* uym, const double* q, const double* fac, double* h, double* vbnd,
                       double* leafr);

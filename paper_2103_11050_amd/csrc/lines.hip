@@ -1,0 +1,331 @@
+// Line-block kernels: factorisation of the kappa^m local Robin matrices (kept for MPM-2P),
+// the MPM-2P trivial-Robin solve and the all-Neumann downscaling, each one wavefront per
+// subdomain with the block inverses in registers.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "kernels.hpp"
+#include "lines.hpp"
+
+namespace mpm {
+
+namespace {
+
+constexpr int MSMAX = 16;   // lines per subdomain held in registers
+
+__device__ __forceinline__ int gcell2(const Geo& g, int I, int J, int i, int j) { return (J * g.my + j) * g.nx + I * g.mx + i; }
+
+__device__ __forceinline__ void load_tile2(const Geo& g, int I, int J, const double* src, double* dst) {
+  for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
+    int i, j;
+    loc_ij(g, c, &i, &j);
+    dst[c] = src[gcell2(g, I, J, i, j)];
+  }
+}
+
+// factor offsets: E[sub][line][t][lane]
+template <int MF>
+__device__ __forceinline__ size_t efac_off(const Geo& g, int sub, int ln, int t) {
+  constexpr int EPL = LB<MF>::EPL;
+  const int nl = g.nc / g.band;
+  return ((size_t(sub) * nl + ln) * EPL + t) * 64;
+}
+
+// Block elimination over all lines; the inverses D_ln^-1 go to Es[(ln*EPL + t)*64 + lane]
+// (LDS or global).
+template <int MF>
+__device__ __forceinline__ void lb_factor(const Geo& g, int I, int J, const double* kl, int mode, const LB<MF>& L,
+                                          double* Es, bool& ok) {
+  constexpr int EPL = LB<MF>::EPL;
+  const int nl = g.nc / g.band;
+  double prev[EPL], cur[EPL];
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) prev[t] = 0.0;
+#pragma unroll 1
+  for (int ln = 0; ln < nl; ++ln) {
+    lb_block<MF>(g, I, J, kl, ln, mode, L, prev, cur);
+    lb_inverse<MF>(L, cur, ok);
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) {
+      Es[(size_t(ln) * EPL + t) * 64 + L.lane] = cur[t];
+      prev[t] = cur[t];
+    }
+  }
+}
+
+// x (LDS, local order) holds the right-hand side on entry and the solution on exit; w is LDS
+// scratch of nl*MF doubles; Es holds the block inverses as written by lb_factor.
+template <int MF>
+__device__ __forceinline__ void lb_solve(const Geo& g, const double* kl, int mode, const LB<MF>& L,
+                                         const double* Es, double* x, double* w) {
+  constexpr int EPL = LB<MF>::EPL;
+  const int nl = g.nc / g.band;
+  const int len = g.band;
+  const bool rin = L.row < len;
+  double wprev = 0.0;
+#pragma unroll 1
+  for (int ln = 0; ln < nl; ++ln) {
+    double e[EPL];
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) e[t] = Es[(size_t(ln) * EPL + t) * 64 + L.lane];
+    double z = rin ? x[ln * len + L.row] : 0.0;
+    if (ln > 0 && rin) z += line_y(g, kl, ln - 1, L.row, mode) * wprev;
+    wprev = lb_matvec<MF>(L, e, z);
+    if (L.cg == 0) w[ln * MF + L.row] = wprev;
+  }
+  double xnext = wprev;
+  if (rin && L.cg == 0) x[(nl - 1) * len + L.row] = xnext;
+#pragma unroll 1
+  for (int ln = nl - 2; ln >= 0; --ln) {
+    double e[EPL];
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) e[t] = Es[(size_t(ln) * EPL + t) * 64 + L.lane];
+    const double v = rin ? line_y(g, kl, ln, L.row, mode) * xnext : 0.0;
+    xnext = w[ln * MF + L.row] + lb_matvec<MF>(L, e, v);
+    if (rin && L.cg == 0) x[ln * len + L.row] = xnext;
+  }
+  __syncthreads();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// Factor of the local Robin matrix of kappa^m (eq:mrc1 with zero data), stored for MPM-2P.
+template <int MF>
+__global__ void __launch_bounds__(64) k_line_factor(Geo g, const double* __restrict__ kap, double* __restrict__ fac,
+                                                    int32_t* err) {
+  __shared__ double kl[256];
+  constexpr int EPL = LB<MF>::EPL;
+  const int sub = blockIdx.x;
+  const int I = sub % g.Sx, J = sub / g.Sx;
+  LB<MF> L;
+  load_tile2(g, I, J, kap, kl);
+  __syncthreads();
+  bool ok = true;
+  lb_factor<MF>(g, I, J, kl, 0, L, fac + efac_off<MF>(g, sub, 0, 0), ok);
+  if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
+}
+
+// ---------------------------------------------------------------------------------------------
+// MPM-2P trivial-Robin local solve (eq:mpm_tf_3 with the kappa^m basis): right-hand side
+// |c| q - sum_{non-Neumann faces} |f| v_f - sum_{Neumann faces} |f| z with
+// v_f = (t^n_f / t^m_f) u~^m_f; zero Dirichlet and Robin data. Outputs the boundary fluxes
+// h = W T delta p on Robin/Dirichlet faces, the boundary values of v and the interface
+// right-hand side B^T h.
+template <int MF>
+__global__ void __launch_bounds__(64)
+k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict__ kap_m,
+               const double* __restrict__ uxm, const double* __restrict__ uym, const double* __restrict__ q,
+               const double* __restrict__ fac, double* __restrict__ hg, double* __restrict__ vbnd,
+               double* __restrict__ leafr) {
+  __shared__ double kl[256], x[256], hsh[64], wsh[256];
+  const int sub = blockIdx.x;
+  const int I = sub % g.Sx, J = sub / g.Sx;
+  const int n = g.nc, nb = g.nb;
+  LB<MF> L;
+  load_tile2(g, I, J, kap_m, kl);
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    int i, j;
+    loc_ij(g, c, &i, &j);
+    const int gi = I * g.mx + i, gj = J * g.my + j;
+    const int gc = gj * g.nx + gi;
+    const double kn = kap_n[gc], km = kap_m[gc];
+    double r = g.hx * g.hy * q[gc];
+    {
+      const double u = uxm[gj * (g.nx + 1) + gi];
+      if (gi > 0) {
+        const double ratio = harm_trans(kn, kap_n[gc - 1], g.hx) / harm_trans(km, kap_m[gc - 1], g.hx);
+        r -= g.hy * (-ratio * u);
+      } else {
+        BFace f = bface(g, I, J, j);
+        r -= f.kind == FACE_NEU ? f.flen * f.value : g.hy * (-(kn / km) * u);
+      }
+    }
+    {
+      const double u = uxm[gj * (g.nx + 1) + gi + 1];
+      if (gi < g.nx - 1) {
+        const double ratio = harm_trans(kn, kap_n[gc + 1], g.hx) / harm_trans(km, kap_m[gc + 1], g.hx);
+        r -= g.hy * (ratio * u);
+      } else {
+        BFace f = bface(g, I, J, g.my + j);
+        r -= f.kind == FACE_NEU ? f.flen * f.value : g.hy * ((kn / km) * u);
+      }
+    }
+    {
+      const double u = uym[gj * g.nx + gi];
+      if (gj > 0) {
+        const double ratio = harm_trans(kn, kap_n[gc - g.nx], g.hy) / harm_trans(km, kap_m[gc - g.nx], g.hy);
+        r -= g.hx * (-ratio * u);
+      } else {
+        BFace f = bface(g, I, J, 2 * g.my + i);
+        r -= f.kind == FACE_NEU ? f.flen * f.value : g.hx * (-(kn / km) * u);
+      }
+    }
+    {
+      const double u = uym[(gj + 1) * g.nx + gi];
+      if (gj < g.ny - 1) {
+        const double ratio = harm_trans(kn, kap_n[gc + g.nx], g.hy) / harm_trans(km, kap_m[gc + g.nx], g.hy);
+        r -= g.hx * (ratio * u);
+      } else {
+        BFace f = bface(g, I, J, 2 * g.my + g.mx + i);
+        r -= f.kind == FACE_NEU ? f.flen * f.value : g.hx * ((kn / km) * u);
+      }
+    }
+    x[c] = r;
+  }
+  __syncthreads();
+  lb_solve<MF>(g, kl, 0, L, fac + efac_off<MF>(g, sub, 0, 0), x, wsh);
+  for (int f = threadIdx.x; f < nb; f += blockDim.x) {
+    BFace bf = bface(g, I, J, f);
+    const int gi = I * g.mx + bf.i, gj = J * g.my + bf.j;
+    const int gc = gj * g.nx + gi;
+    const double km = kap_m[gc], kn = kap_n[gc];
+    const double w = bf.flen * bface_trans(g, bf, km);
+    const double h = bf.kind == FACE_NEU ? 0.0 : w * x[loc_index(g, bf.i, bf.j)];
+    hsh[f] = h;
+    hg[size_t(sub) * nb + f] = h;
+    double v = 0.0;
+    if (bf.kind != FACE_NEU) {
+      double u, dd;
+      int nbr;
+      if (bf.side == 0) { u = -uxm[gj * (g.nx + 1) + gi]; nbr = gi > 0 ? gc - 1 : -1; dd = g.hx; }
+      else if (bf.side == 1) { u = uxm[gj * (g.nx + 1) + gi + 1]; nbr = gi < g.nx - 1 ? gc + 1 : -1; dd = g.hx; }
+      else if (bf.side == 2) { u = -uym[gj * g.nx + gi]; nbr = gj > 0 ? gc - g.nx : -1; dd = g.hy; }
+      else { u = uym[(gj + 1) * g.nx + gi]; nbr = gj < g.ny - 1 ? gc + g.nx : -1; dd = g.hy; }
+      const double ratio = nbr >= 0 ? harm_trans(kn, kap_n[nbr], dd) / harm_trans(km, kap_m[nbr], dd) : kn / km;
+      v = ratio * u;
+    }
+    vbnd[size_t(sub) * nb + f] = v;
+  }
+  __syncthreads();
+  // interface right-hand side B^T h: U unknown -sgn beta_f, P unknown 1 on the element's faces
+  const int nd = sub_ndof(g, I, J);
+  for (int a = threadIdx.x; a < nd; a += blockDim.x) {
+    int f0, cnt;
+    dof_faces(g, I, J, a, &f0, &cnt);
+    double v = 0.0;
+    for (int xx = f0; xx < f0 + cnt; ++xx) {
+      BFace ff = bface(g, I, J, xx);
+      const double wgt = (a & 1) ? 1.0 : -ff.sgn * robin_beta(g, ff, kl[loc_index(g, ff.i, ff.j)]);
+      v += wgt * hsh[xx];
+    }
+    leafr[size_t(sub) * g.ndmax + a] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Downscaling (eq. mpm_upd): all-Neumann problem with conductivity kap_s per subdomain, the
+// mean of both sides' boundary fluxes on Gamma, the own flux on the physical boundary, the
+// first cell pinned. Writes the velocity on the faces the subdomain owns, the largest outflow
+// rate per cell volume and the inflow through the physical boundary.
+template <int MF>
+__global__ void __launch_bounds__(64)
+k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict__ q,
+               const double* __restrict__ ubnd, double* __restrict__ ux, double* __restrict__ uy,
+               double* __restrict__ red_rate, double* __restrict__ red_qin, int32_t* err) {
+  __shared__ double kl[256], x[256], w[64], scratch[128], wsh[256];
+  __shared__ double Es[MSMAX * MF * MF];
+  const int sub = blockIdx.x;
+  const int I = sub % g.Sx, J = sub / g.Sx;
+  const int n = g.nc, nb = g.nb;
+  LB<MF> L;
+  load_tile2(g, I, J, kap_s, kl);
+  for (int f = threadIdx.x; f < nb; f += blockDim.x) {
+    BFace bf = bface(g, I, J, f);
+    double u = ubnd[size_t(sub) * nb + f];
+    if (bf.kind == FACE_ROB) {
+      int ns, nf;
+      if (bf.side == 0) { ns = sub - 1; nf = g.my + bf.k; }
+      else if (bf.side == 1) { ns = sub + 1; nf = bf.k; }
+      else if (bf.side == 2) { ns = sub - g.Sx; nf = 2 * g.my + g.mx + bf.k; }
+      else { ns = sub + g.Sx; nf = 2 * g.my + bf.k; }
+      u = 0.5 * (u - ubnd[size_t(ns) * nb + nf]);
+    }
+    w[f] = u;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    int i, j;
+    loc_ij(g, c, &i, &j);
+    double r = g.hx * g.hy * q[gcell2(g, I, J, i, j)];
+    if (i == 0) r -= g.hy * w[j];
+    if (i == g.mx - 1) r -= g.hy * w[g.my + j];
+    if (j == 0) r -= g.hx * w[2 * g.my + i];
+    if (j == g.my - 1) r -= g.hx * w[2 * g.my + g.mx + i];
+    x[c] = c == 0 ? 0.0 : r;
+  }
+  __syncthreads();
+  bool ok = true;
+  lb_factor<MF>(g, I, J, kl, 1, L, Es, ok);
+  if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
+  lb_solve<MF>(g, kl, 1, L, Es, x, wsh);
+  double rate = 0.0;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    int i, j;
+    loc_ij(g, c, &i, &j);
+    const int gi = I * g.mx + i, gj = J * g.my + j;
+    const double pc = x[c];
+    double uW, uE, uS, uN;
+    if (i > 0) uW = harm_trans(kl[loc_index(g, i - 1, j)], kl[c], g.hx) * (x[loc_index(g, i - 1, j)] - pc);
+    else uW = -w[j];
+    if (i < g.mx - 1) uE = harm_trans(kl[c], kl[loc_index(g, i + 1, j)], g.hx) * (pc - x[loc_index(g, i + 1, j)]);
+    else uE = w[g.my + j];
+    if (j > 0) uS = harm_trans(kl[loc_index(g, i, j - 1)], kl[c], g.hy) * (x[loc_index(g, i, j - 1)] - pc);
+    else uS = -w[2 * g.my + i];
+    if (j < g.my - 1) uN = harm_trans(kl[c], kl[loc_index(g, i, j + 1)], g.hy) * (pc - x[loc_index(g, i, j + 1)]);
+    else uN = w[2 * g.my + g.mx + i];
+    ux[gj * (g.nx + 1) + gi] = uW;
+    uy[gj * g.nx + gi] = uS;
+    if (gi == g.nx - 1) ux[gj * (g.nx + 1) + gi + 1] = uE;
+    if (gj == g.ny - 1) uy[(gj + 1) * g.nx + gi] = uN;
+    const double out = g.hy * (fmax(uE, 0.0) + fmax(-uW, 0.0)) + g.hx * (fmax(uN, 0.0) + fmax(-uS, 0.0));
+    rate = fmax(rate, out / (g.hx * g.hy));
+  }
+  double qin = 0.0;
+  for (int f = threadIdx.x; f < nb; f += blockDim.x) {
+    BFace bf = bface(g, I, J, f);
+    if (bf.kind != FACE_ROB) qin += bf.flen * fmax(-w[f], 0.0);
+  }
+  scratch[threadIdx.x] = rate;
+  scratch[64 + threadIdx.x] = qin;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0, s = 0.0;
+    for (int t = 0; t < 64; ++t) { m = fmax(m, scratch[t]); s += scratch[64 + t]; }
+    red_rate[sub] = m;
+    red_qin[sub] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+
+static int line_mf(const Geo& g) { return g.band <= 8 ? 8 : 16; }
+
+void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double* fac, int32_t* err) {
+  if (line_mf(g) == 8) hipLaunchKernelGGL(k_line_factor<8>, dim3(g.nsub), dim3(64), 0, st, g, kap, fac, err);
+  else hipLaunchKernelGGL(k_line_factor<16>, dim3(g.nsub), dim3(64), 0, st, g, kap, fac, err);
+}
+
+void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
+                      const double* uym, const double* q, const double* fac, double* h, double* vbnd,
+                      double* leafr) {
+  if (line_mf(g) == 8)
+    hipLaunchKernelGGL(k_mpm_local_lb<8>, dim3(g.nsub), dim3(64), 0, st, g, kn, km, uxm, uym, q, fac, h, vbnd, leafr);
+  else
+    hipLaunchKernelGGL(k_mpm_local_lb<16>, dim3(g.nsub), dim3(64), 0, st, g, kn, km, uxm, uym, q, fac, h, vbnd, leafr);
+}
+
+void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
+                      double* ux, double* uy, double* red_rate, double* red_qin, int32_t* err) {
+  if (line_mf(g) == 8)
+    hipLaunchKernelGGL(k_downscale_lb<8>, dim3(g.nsub), dim3(64), 0, st, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, err);
+  else
+    hipLaunchKernelGGL(k_downscale_lb<16>, dim3(g.nsub), dim3(64), 0, st, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, err);
+}
+
+size_t line_factor_doubles(int nsub, int nc, int band) {
+  const int mf = band <= 8 ? 8 : 16;
+  return size_t(nsub) * (nc / band) * mf * mf;
+}
+
+}  // namespace mpm

@@ -1,0 +1,172 @@
+// Register-resident line-block factorisation of a subdomain's two-point flux matrix.
+//
+// With cells numbered line by line (a line runs along the shorter side of the subdomain), the
+// 5-point matrix is block tridiagonal: diagonal blocks T_j are tridiagonal (couplings inside
+// line j) and the off-diagonal blocks are -Y_j with Y_j diagonal (couplings between lines j
+// and j+1). Block elimination gives
+//   D_0 = T_0,   D_j = T_j - Y_{j-1} D_{j-1}^-1 Y_{j-1},
+// and the solve
+//   z_0 = r_0,  w_j = D_j^-1 z_j,  z_{j+1} = r_{j+1} + Y_j w_j,
+//   x_last = w_last,  x_j = w_j + D_j^-1 (Y_j x_{j+1}).
+// One wavefront owns one subdomain. Each D_j^-1 (MF x MF, lines padded with identity rows to
+// MF in {8, 16}) is spread over the 64 lanes, EPL entries per lane: lane -> (row, column
+// group). Inversion is a Gauss-Jordan sweep with the pivot row and column broadcast by lane
+// shuffles; the SPD pivots need no pivoting.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace mpm {
+
+template <int MF>
+struct LB {
+  static constexpr int EPL = MF * MF / 64;   // entries per lane
+  static constexpr int LPR = MF / EPL;       // lanes per row
+  int lane, row, cg;
+  __device__ LB() {
+    lane = threadIdx.x & 63;
+    row = lane / LPR;
+    cg = lane % LPR;
+  }
+  __device__ int col(int t) const { return cg * EPL + t; }
+};
+
+// In-place inverse of the SPD block held as a[t] = D[row][col(t)]. Clears ok on a
+// non-positive pivot. The pivot loop runs in groups of EPL so that the register holding
+// column k is known at compile time.
+template <int MF>
+__device__ __forceinline__ void lb_inverse(const LB<MF>& L, double (&a)[LB<MF>::EPL], bool& ok) {
+  constexpr int EPL = LB<MF>::EPL, LPR = LB<MF>::LPR;
+#pragma unroll 1
+  for (int k0 = 0; k0 < MF; k0 += EPL) {
+#pragma unroll
+    for (int kk = 0; kk < EPL; ++kk) {
+      const int k = k0 + kk;
+      double rk[EPL];
+#pragma unroll
+      for (int t = 0; t < EPL; ++t) rk[t] = __shfl(a[t], k * LPR + L.cg);
+      const double ck = __shfl(a[kk], L.row * LPR + k0 / EPL);
+      const double d = __shfl(a[kk], k * LPR + k0 / EPL);
+      ok = ok && (d > 0.0);
+      const double rd = 1.0 / d;
+#pragma unroll
+      for (int t = 0; t < EPL; ++t) {
+        const int j = L.col(t);
+        double v;
+        if (L.row == k) v = (j == k) ? -rd : rk[t] * rd;
+        else if (j == k) v = ck * rd;
+        else v = a[t] - ck * rk[t] * rd;
+        a[t] = v;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) a[t] = -a[t];
+}
+
+// y = D v for vectors replicated over a row's lanes (lane holds v[row]); result replicated.
+template <int MF>
+__device__ __forceinline__ double lb_matvec(const LB<MF>& L, const double (&a)[LB<MF>::EPL], double v) {
+  constexpr int EPL = LB<MF>::EPL, LPR = LB<MF>::LPR;
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) acc += a[t] * __shfl(v, L.col(t) * LPR);
+#pragma unroll
+  for (int o = 1; o < LPR; o <<= 1) acc += __shfl_xor(acc, o);
+  return acc;
+}
+
+// Geometry of the line decomposition of a subdomain.
+struct LineGeo {
+  int len;      // cells per line (band of the banded ordering)
+  int nlines;   // number of lines
+};
+
+__device__ __forceinline__ LineGeo line_geo(const Geo& g) {
+  LineGeo lg;
+  lg.len = g.band;
+  lg.nlines = g.nc / g.band;
+  return lg;
+}
+
+// (i, j) of the cell at position pos of line ln (matches loc_index: c = ln * len + pos).
+__device__ __forceinline__ void line_cell(const Geo& g, int ln, int pos, int* i, int* j) {
+  *i = g.xfast ? pos : ln;
+  *j = g.xfast ? ln : pos;
+}
+
+// Entries of the subdomain matrix in line form, from the conductivity tile kl (LDS, local
+// order). mode 0: boundary faces with Dirichlet/Robin transmissibility (eq:mrc1); mode 1:
+// all-Neumann with cell 0 pinned.
+//   diag(ln,pos), off(ln,pos) = weight of the coupling pos <-> pos+1 inside the line,
+//   yc(ln,pos) = weight of the coupling to line ln+1.
+__device__ __forceinline__ double cell_diag(const Geo& g, int I, int J, const double* kl, int ln, int pos, int mode) {
+  int i, j;
+  line_cell(g, ln, pos, &i, &j);
+  const int c = ln * g.band + pos;
+  if (mode == 1 && c == 0) return 1.0;
+  const double kc = kl[c];
+  double d = 0.0;
+  if (i > 0) d += g.hy * harm_trans(kc, kl[loc_index(g, i - 1, j)], g.hx);
+  if (i < g.mx - 1) d += g.hy * harm_trans(kc, kl[loc_index(g, i + 1, j)], g.hx);
+  if (j > 0) d += g.hx * harm_trans(kc, kl[loc_index(g, i, j - 1)], g.hy);
+  if (j < g.my - 1) d += g.hx * harm_trans(kc, kl[loc_index(g, i, j + 1)], g.hy);
+  if (mode == 0) {
+    if (i == 0) { BFace f = bface(g, I, J, j); d += f.flen * bface_trans(g, f, kc); }
+    if (i == g.mx - 1) { BFace f = bface(g, I, J, g.my + j); d += f.flen * bface_trans(g, f, kc); }
+    if (j == 0) { BFace f = bface(g, I, J, 2 * g.my + i); d += f.flen * bface_trans(g, f, kc); }
+    if (j == g.my - 1) { BFace f = bface(g, I, J, 2 * g.my + g.mx + i); d += f.flen * bface_trans(g, f, kc); }
+  }
+  return d;
+}
+
+// Weight of the coupling between position pos and pos+1 of line ln (0 if pinned).
+__device__ __forceinline__ double line_off(const Geo& g, const double* kl, int ln, int pos, int mode) {
+  const int c = ln * g.band + pos;
+  if (mode == 1 && c == 0) return 0.0;
+  // pos -> pos+1 moves along the fast axis
+  if (g.xfast) return g.hy * harm_trans(kl[c], kl[c + 1], g.hx);
+  return g.hx * harm_trans(kl[c], kl[c + 1], g.hy);
+}
+
+// Weight of the coupling between (ln, pos) and (ln+1, pos).
+__device__ __forceinline__ double line_y(const Geo& g, const double* kl, int ln, int pos, int mode) {
+  const int c = ln * g.band + pos;
+  if (mode == 1 && c == 0) return 0.0;
+  const int d = c + g.band;
+  if (g.xfast) return g.hx * harm_trans(kl[c], kl[d], g.hy);
+  return g.hy * harm_trans(kl[c], kl[d], g.hx);
+}
+
+// Builds D_j for line ln in registers: T_ln - Y_{ln-1} Eprev Y_{ln-1}.
+template <int MF>
+__device__ __forceinline__ void lb_block(const Geo& g, int I, int J, const double* kl, int ln, int mode, const LB<MF>& L,
+                                const double (&Eprev)[LB<MF>::EPL], double (&a)[LB<MF>::EPL]) {
+  constexpr int EPL = LB<MF>::EPL;
+  const int len = g.band;
+  const int r = L.row;
+  const bool rin = r < len;
+  const double drow = rin ? cell_diag(g, I, J, kl, ln, r, mode) : 1.0;
+  const double offR = (rin && r + 1 < len) ? line_off(g, kl, ln, r, mode) : 0.0;
+  const double offL = (rin && r > 0) ? line_off(g, kl, ln, r - 1, mode) : 0.0;
+  const double yr = (ln > 0 && rin) ? line_y(g, kl, ln - 1, r, mode) : 0.0;
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) {
+    const int c = L.col(t);
+    double v;
+    if (c == r) v = drow;
+    else if (c == r + 1) v = -offR;
+    else if (c == r - 1) v = -offL;
+    else v = 0.0;
+    if (ln > 0 && rin && c < len) {
+      const double yc = line_y(g, kl, ln - 1, c, mode);
+      v -= yr * Eprev[t] * yc;
+    }
+    if (!rin || c >= len) v = (c == r) ? 1.0 : 0.0;
+    a[t] = v;
+  }
+}
+
+}  // namespace mpm

@@ -19,12 +19,12 @@ constexpr int LOCAL_THREADS = 128;
 // ------------------------------------------------------------------ band helpers
 // Band storage: A(i, j), i-b <= j <= i, at A[i*(b+1) + (j - i + b)]; diagonal at offset b.
 
-__device__ inline double& bandref(double* A, int b, int i, int j) { return A[i * (b + 1) + (j - i + b)]; }
+__device__ __forceinline__ double& bandref(double* A, int b, int i, int j) { return A[i * (b + 1) + (j - i + b)]; }
 
 // Two-point flux matrix of a subdomain with conductivity kap (LDS, local order).
 // neumann = false: boundary faces carry their Dirichlet/Robin transmissibility (eq:mrc1).
 // neumann = true : all boundary faces are flux faces and cell 0 is pinned (p = 0).
-__device__ void assemble_band(const Geo& g, int I, int J, const double* kap, double* A, bool neumann) {
+__device__ __forceinline__ void assemble_band(const Geo& g, int I, int J, const double* kap, double* A, bool neumann) {
   const int b = g.band, n = g.nc;
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     for (int o = 0; o <= b; ++o) A[c * (b + 1) + o] = 0.0;
@@ -64,7 +64,7 @@ __device__ void assemble_band(const Geo& g, int I, int J, const double* kap, dou
 
 // In-place L D L^T of the band. On exit the strict lower band holds L and the diagonal slot
 // holds 1/d. Returns false (and sets the error word) on a non-positive pivot.
-__device__ void band_ldlt(const Geo& g, double* A, int32_t* err) {
+__device__ __forceinline__ void band_ldlt(const Geo& g, double* A, int32_t* err) {
   const int b = g.band, n = g.nc;
   const int P = b * (b + 1) / 2;
   bool ok = true;
@@ -96,32 +96,11 @@ __device__ void band_ldlt(const Geo& g, double* A, int32_t* err) {
   if (!ok && threadIdx.x == 0) set_error(err, ERR_NOTSPD);
 }
 
-// Solves L D L^T x = x in place (x in LDS).
-__device__ void band_solve(const Geo& g, const double* A, double* x) {
-  const int b = g.band, n = g.nc;
-  for (int k = 0; k < n; ++k) {
-    const double xk = x[k];
-    const int o = threadIdx.x + 1;
-    if (o <= b && k + o < n) x[k + o] -= A[(k + o) * (b + 1) + (b - o)] * xk;
-    __syncthreads();
-  }
-  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] *= A[i * (b + 1) + b];
-  __syncthreads();
-  for (int k = n - 1; k >= 0; --k) {
-    const double xk = x[k];
-    const int o = threadIdx.x + 1;
-    if (o <= b && k - o >= 0) x[k - o] -= A[k * (b + 1) + (b - o)] * xk;
-    __syncthreads();
-  }
-}
-
-__device__ inline int gcell(const Geo& g, int I, int J, int i, int j) {
+__device__ __forceinline__ int gcell(const Geo& g, int I, int J, int i, int j) {
   return (J * g.my + j) * g.nx + I * g.mx + i;
 }
-__device__ inline int gfx(const Geo& g, int gi, int gj) { return gj * (g.nx + 1) + gi; }  // x-face left of cell gi
-__device__ inline int gfy(const Geo& g, int gi, int gj) { return gj * g.nx + gi; }        // y-face below cell gj
 
-__device__ void load_tile(const Geo& g, int I, int J, const double* src, double* dst) {
+__device__ __forceinline__ void load_tile(const Geo& g, int I, int J, const double* src, double* dst) {
   for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
     int i, j;
     loc_ij(g, c, &i, &j);
@@ -129,35 +108,9 @@ __device__ void load_tile(const Geo& g, int I, int J, const double* src, double*
   }
 }
 
-// Element-face table of a subdomain's local interface unknowns: first face and count.
-__device__ void dof_faces(const Geo& g, int I, int J, int a, int* f0, int* cnt) {
-  // walk the sides in local order W, E, S, N
-  int off = 0;
-  const bool has[4] = {I > 0, I < g.Sx - 1, J > 0, J < g.Sy - 1};
-  const int start[4] = {0, g.my, 2 * g.my, 2 * g.my + g.mx};
-  for (int s = 0; s < 4; ++s) {
-    if (!has[s]) continue;
-    const int ne = s < 2 ? g.ne_y : g.ne_x;
-    const int per = s < 2 ? g.my / g.ne_y : g.mx / g.ne_x;
-    if (a < off + 2 * ne) {
-      const int k = (a - off) / 2;
-      *f0 = start[s] + k * per;
-      *cnt = per;
-      return;
-    }
-    off += 2 * ne;
-  }
-  *f0 = 0;
-  *cnt = 0;
-}
-
-__device__ inline int sub_ndof(const Geo& g, int I, int J) {
-  return 2 * ((I > 0) + (I < g.Sx - 1)) * g.ne_y + 2 * ((J > 0) + (J < g.Sy - 1)) * g.ne_x;
-}
-
 // Restriction B^T of boundary-face quantities to local interface unknowns:
 // U unknown: -sgn beta_f on the element's faces; P unknown: 1.
-__device__ inline double bweight(const Geo& g, const BFace& f, bool is_p, double kc) {
+__device__ __forceinline__ double bweight(const Geo& g, const BFace& f, bool is_p, double kc) {
   return is_p ? 1.0 : -f.sgn * robin_beta(g, f, kc);
 }
 
@@ -232,8 +185,7 @@ __global__ void k_reduce_eps(int nblocks, const double* __restrict__ red, double
 //  * the subdomain's block of the interface system (eq:mrc2 with the Robin rows negated):
 //    K_i = B^T S B - D_i and its right-hand side B^T h.
 __global__ void __launch_bounds__(LOCAL_THREADS)
-k_basis(Geo g, const double* __restrict__ kap, const double* __restrict__ q, double* __restrict__ fac,
-        double* __restrict__ Sg, double* __restrict__ hg, double* __restrict__ leafK,
+k_basis(Geo g, const double* __restrict__ kap, const double* __restrict__ q, double* __restrict__ Sg, double* __restrict__ hg, double* __restrict__ leafK,
         double* __restrict__ leafr, int32_t* err) {
   extern __shared__ double smem[];
   const int sub = blockIdx.x;
@@ -251,8 +203,6 @@ k_basis(Geo g, const double* __restrict__ kap, const double* __restrict__ q, dou
   __syncthreads();
   assemble_band(g, I, J, kl, A, false);
   band_ldlt(g, A, err);
-  double* fac_s = fac + size_t(sub) * bandsz;
-  for (int e = threadIdx.x; e < bandsz; e += blockDim.x) fac_s[e] = A[e];
 
   // non-homogeneous right-hand side: |c| q + sum_DIR |f| t g - sum_NEU |f| z (Robin datum 0)
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
@@ -373,119 +323,6 @@ k_basis(Geo g, const double* __restrict__ kap, const double* __restrict__ q, dou
   }
 }
 
-// ====================================================================== A5: MPM-2P local solve
-// The non-homogeneous local problem of eq:mpm_tf_3 with the stored kappa^m factor:
-// v_f = (t^n_f / t^m_f) u~^m_f is the discrete -kappa^n grad p^m; the right-hand side is
-// |c| q - sum_{non-Neumann faces} |f| v_f - sum_{Neumann faces} |f| z; Dirichlet and Robin
-// data are zero. Outputs the boundary fluxes h = W T delta p on Robin/Dirichlet faces, the
-// boundary values of v, and the interface right-hand side B^T h.
-__global__ void __launch_bounds__(64)
-k_mpm_local(Geo g, const double* __restrict__ kap_n, const double* __restrict__ kap_m,
-            const double* __restrict__ uxm, const double* __restrict__ uym, const double* __restrict__ q,
-            const double* __restrict__ fac, double* __restrict__ hg, double* __restrict__ vbnd,
-            double* __restrict__ leafr) {
-  extern __shared__ double smem[];
-  const int sub = blockIdx.x;
-  const int I = sub % g.Sx, J = sub / g.Sx;
-  const int b = g.band, n = g.nc, nb = g.nb;
-  const int bandsz = n * (b + 1);
-  double* A = smem;
-  double* x = A + bandsz;
-  double* hsh = x + n;
-  const double* fac_s = fac + size_t(sub) * bandsz;
-  for (int e = threadIdx.x; e < bandsz; e += blockDim.x) A[e] = fac_s[e];
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    int i, j;
-    loc_ij(g, c, &i, &j);
-    const int gi = I * g.mx + i, gj = J * g.my + j;
-    const int gc = gj * g.nx + gi;
-    const double kn = kap_n[gc], km = kap_m[gc];
-    double r = g.hx * g.hy * q[gc];
-    // four faces: outward v = sign * (ratio * u~m)
-    // W
-    {
-      const double u = uxm[gfx(g, gi, gj)];
-      if (gi > 0) {
-        const double ratio = harm_trans(kn, kap_n[gc - 1], g.hx) / harm_trans(km, kap_m[gc - 1], g.hx);
-        r -= g.hy * (-ratio * u);
-      } else {
-        BFace f = bface(g, I, J, j);
-        r -= f.kind == FACE_NEU ? f.flen * f.value : g.hy * (-(kn / km) * u);
-      }
-    }
-    {
-      const double u = uxm[gfx(g, gi + 1, gj)];
-      if (gi < g.nx - 1) {
-        const double ratio = harm_trans(kn, kap_n[gc + 1], g.hx) / harm_trans(km, kap_m[gc + 1], g.hx);
-        r -= g.hy * (ratio * u);
-      } else {
-        BFace f = bface(g, I, J, g.my + j);
-        r -= f.kind == FACE_NEU ? f.flen * f.value : g.hy * ((kn / km) * u);
-      }
-    }
-    {
-      const double u = uym[gfy(g, gi, gj)];
-      if (gj > 0) {
-        const double ratio = harm_trans(kn, kap_n[gc - g.nx], g.hy) / harm_trans(km, kap_m[gc - g.nx], g.hy);
-        r -= g.hx * (-ratio * u);
-      } else {
-        BFace f = bface(g, I, J, 2 * g.my + i);
-        r -= f.kind == FACE_NEU ? f.flen * f.value : g.hx * (-(kn / km) * u);
-      }
-    }
-    {
-      const double u = uym[gfy(g, gi, gj + 1)];
-      if (gj < g.ny - 1) {
-        const double ratio = harm_trans(kn, kap_n[gc + g.nx], g.hy) / harm_trans(km, kap_m[gc + g.nx], g.hy);
-        r -= g.hx * (ratio * u);
-      } else {
-        BFace f = bface(g, I, J, 2 * g.my + g.mx + i);
-        r -= f.kind == FACE_NEU ? f.flen * f.value : g.hx * ((kn / km) * u);
-      }
-    }
-    x[c] = r;
-  }
-  __syncthreads();
-  band_solve(g, A, x);
-  for (int f = threadIdx.x; f < nb; f += blockDim.x) {
-    BFace bf = bface(g, I, J, f);
-    const int gi = I * g.mx + bf.i, gj = J * g.my + bf.j;
-    const int gc = gj * g.nx + gi;
-    const double km = kap_m[gc], kn = kap_n[gc];
-    const double w = bf.flen * bface_trans(g, bf, km);
-    const double h = bf.kind == FACE_NEU ? 0.0 : w * x[loc_index(g, bf.i, bf.j)];
-    hsh[f] = h;
-    hg[size_t(sub) * nb + f] = h;
-    // outward v on this face
-    double v = 0.0;
-    if (bf.kind != FACE_NEU) {
-      double u, ratio;
-      int nbr = -1;
-      double dd;
-      if (bf.side == 0) { u = -uxm[gfx(g, gi, gj)]; nbr = gi > 0 ? gc - 1 : -1; dd = g.hx; }
-      else if (bf.side == 1) { u = uxm[gfx(g, gi + 1, gj)]; nbr = gi < g.nx - 1 ? gc + 1 : -1; dd = g.hx; }
-      else if (bf.side == 2) { u = -uym[gfy(g, gi, gj)]; nbr = gj > 0 ? gc - g.nx : -1; dd = g.hy; }
-      else { u = uym[gfy(g, gi, gj + 1)]; nbr = gj < g.ny - 1 ? gc + g.nx : -1; dd = g.hy; }
-      ratio = nbr >= 0 ? harm_trans(kn, kap_n[nbr], dd) / harm_trans(km, kap_m[nbr], dd) : kn / km;
-      v = ratio * u;
-    }
-    vbnd[size_t(sub) * nb + f] = v;
-  }
-  __syncthreads();
-  const int nd = sub_ndof(g, I, J);
-  for (int a = threadIdx.x; a < nd; a += blockDim.x) {
-    int fa, na;
-    dof_faces(g, I, J, a, &fa, &na);
-    double v = 0.0;
-    for (int xx = fa; xx < fa + na; ++xx) {
-      BFace ff = bface(g, I, J, xx);
-      const int gc = (J * g.my + ff.j) * g.nx + I * g.mx + ff.i;
-      v += bweight(g, ff, a & 1, kap_m[gc]) * hsh[xx];
-    }
-    leafr[size_t(sub) * g.ndmax + a] = v;
-  }
-}
-
 // ====================================================================== A7: boundary fluxes
 // Reconstruction on every boundary face of every subdomain from the interface solution:
 // W u = h - S r with the Robin data r_f = -sgn beta_f U_l + P_l on Gamma faces (zero on
@@ -529,94 +366,6 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
   }
 }
 
-// ====================================================================== A8: downscaling
-// eq. mpm_upd: per subdomain an all-Neumann problem with conductivity kap_s, boundary flux
-// = mean of the two sides' fluxes on Gamma (the subdomain's own flux on the physical
-// boundary), source q, first cell pinned to p = 0. Writes the conservative velocity on the
-// faces the subdomain owns (interior faces, W and S faces, and E/N faces on the domain
-// boundary), the maximum outflow rate per unit cell volume and the boundary inflow.
-__global__ void __launch_bounds__(64)
-k_downscale(Geo g, const double* __restrict__ kap_s, const double* __restrict__ q,
-            const double* __restrict__ ubnd, double* __restrict__ ux, double* __restrict__ uy,
-            double* __restrict__ red_rate, double* __restrict__ red_qin, int32_t* err) {
-  extern __shared__ double smem[];
-  const int sub = blockIdx.x;
-  const int I = sub % g.Sx, J = sub / g.Sx;
-  const int b = g.band, n = g.nc, nb = g.nb;
-  double* A = smem;
-  double* x = A + n * (b + 1);
-  double* kl = x + n;
-  double* w = kl + n;
-  double* scratch = w + nb;
-  load_tile(g, I, J, kap_s, kl);
-  for (int f = threadIdx.x; f < nb; f += blockDim.x) {
-    BFace bf = bface(g, I, J, f);
-    double u = ubnd[size_t(sub) * nb + f];
-    if (bf.kind == FACE_ROB) {
-      int ns, nf;
-      if (bf.side == 0) { ns = sub - 1; nf = g.my + bf.k; }
-      else if (bf.side == 1) { ns = sub + 1; nf = bf.k; }
-      else if (bf.side == 2) { ns = sub - g.Sx; nf = 2 * g.my + g.mx + bf.k; }
-      else { ns = sub + g.Sx; nf = 2 * g.my + bf.k; }
-      u = 0.5 * (u - ubnd[size_t(ns) * nb + nf]);
-    }
-    w[f] = u;
-  }
-  __syncthreads();
-  assemble_band(g, I, J, kl, A, true);
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    int i, j;
-    loc_ij(g, c, &i, &j);
-    double r = g.hx * g.hy * q[gcell(g, I, J, i, j)];
-    if (i == 0) r -= g.hy * w[j];
-    if (i == g.mx - 1) r -= g.hy * w[g.my + j];
-    if (j == 0) r -= g.hx * w[2 * g.my + i];
-    if (j == g.my - 1) r -= g.hx * w[2 * g.my + g.mx + i];
-    x[c] = c == 0 ? 0.0 : r;
-  }
-  __syncthreads();
-  band_ldlt(g, A, err);
-  band_solve(g, A, x);
-  // fluxes
-  double rate = 0.0;
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    int i, j;
-    loc_ij(g, c, &i, &j);
-    const int gi = I * g.mx + i, gj = J * g.my + j;
-    const double pc = x[c];
-    double uW, uE, uS, uN;  // +x / +y oriented
-    if (i > 0) uW = harm_trans(kl[loc_index(g, i - 1, j)], kl[c], g.hx) * (x[loc_index(g, i - 1, j)] - pc);
-    else uW = -w[j];
-    if (i < g.mx - 1) uE = harm_trans(kl[c], kl[loc_index(g, i + 1, j)], g.hx) * (pc - x[loc_index(g, i + 1, j)]);
-    else uE = w[g.my + j];
-    if (j > 0) uS = harm_trans(kl[loc_index(g, i, j - 1)], kl[c], g.hy) * (x[loc_index(g, i, j - 1)] - pc);
-    else uS = -w[2 * g.my + i];
-    if (j < g.my - 1) uN = harm_trans(kl[c], kl[loc_index(g, i, j + 1)], g.hy) * (pc - x[loc_index(g, i, j + 1)]);
-    else uN = w[2 * g.my + g.mx + i];
-    ux[gfx(g, gi, gj)] = uW;
-    uy[gfy(g, gi, gj)] = uS;
-    if (gi == g.nx - 1) ux[gfx(g, gi + 1, gj)] = uE;
-    if (gj == g.ny - 1) uy[gfy(g, gi, gj + 1)] = uN;
-    const double out = g.hy * (fmax(uE, 0.0) + fmax(-uW, 0.0)) + g.hx * (fmax(uN, 0.0) + fmax(-uS, 0.0));
-    rate = fmax(rate, out / (g.hx * g.hy));
-  }
-  scratch[threadIdx.x] = rate;
-  // boundary inflow through the physical boundary
-  double qin = 0.0;
-  for (int f = threadIdx.x; f < nb; f += blockDim.x) {
-    BFace bf = bface(g, I, J, f);
-    if (bf.kind != FACE_ROB) qin += bf.flen * fmax(-w[f], 0.0);
-  }
-  scratch[64 + threadIdx.x] = qin;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = 0.0, s = 0.0;
-    for (int t = 0; t < blockDim.x; ++t) { m = fmax(m, scratch[t]); s += scratch[64 + t]; }
-    red_rate[sub] = m;
-    red_qin[sub] = s;
-  }
-}
-
 // Transport sub-step from the maximum outflow rate; boundary inflow (fixed-order sums).
 __global__ void k_dt(int nsub, const double* __restrict__ red_rate, const double* __restrict__ red_qin,
                      double cfl, double fmax_deriv, double* __restrict__ scal) {
@@ -649,12 +398,7 @@ static size_t basis_smem(const Geo& g) {
   const int b = g.band, n = g.nc, nb = g.nb;
   return size_t(max(n * (b + 1), nb * nb) + 2 * n + (b + 1) * (nb + 1) + 2 * nb) * 8;
 }
-static size_t mpm_local_smem(const Geo& g) { return size_t(g.nc * (g.band + 1) + g.nc + g.nb) * 8; }
-static size_t downscale_smem(const Geo& g) { return size_t(g.nc * (g.band + 1) + 2 * g.nc + g.nb + 128) * 8; }
-
-size_t local_smem_max(const Geo& g) {
-  return std::max(basis_smem(g), std::max(mpm_local_smem(g), downscale_smem(g)));
-}
+size_t local_smem_max(const Geo& g) { return basis_smem(g); }
 
 void launch_kappa(hipStream_t st, int ncell, const double* s, const double* K, double* kn, const double* km,
                   double mu_w, double mu_o, double* red, double* scal) {
@@ -663,28 +407,15 @@ void launch_kappa(hipStream_t st, int ncell, const double* s, const double* K, d
   hipLaunchKernelGGL(k_reduce_eps, dim3(1), dim3(256), 0, st, nblk, red, scal);
 }
 
-void launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* fac, double* S,
-                  double* h, double* leafK, double* leafr, int32_t* err) {
-  hipLaunchKernelGGL(k_basis, dim3(g.nsub), dim3(LOCAL_THREADS), basis_smem(g), st, g, kap, q, fac, S, h, leafK,
-                     leafr, err);
-}
-
-void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
-                      const double* uym, const double* q, const double* fac, double* h, double* vbnd,
-                      double* leafr) {
-  hipLaunchKernelGGL(k_mpm_local, dim3(g.nsub), dim3(64), mpm_local_smem(g), st, g, kn, km, uxm, uym, q, fac, h,
-                     vbnd, leafr);
+void launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
+                  double* leafK, double* leafr, int32_t* err) {
+  hipLaunchKernelGGL(k_basis, dim3(g.nsub), dim3(LOCAL_THREADS), basis_smem(g), st, g, kap, q, S, h, leafK, leafr,
+                     err);
 }
 
 void launch_flux(hipStream_t st, const Geo& g, const double* km, const double* S, const double* h,
                  const double* vbnd, const double* y, const int32_t* sub_dofs, double* ubnd, int with_v) {
   hipLaunchKernelGGL(k_flux, dim3(g.nsub), dim3(64), 0, st, g, km, S, h, vbnd, y, sub_dofs, ubnd, with_v);
-}
-
-void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
-                      double* ux, double* uy, double* red_rate, double* red_qin, int32_t* err) {
-  hipLaunchKernelGGL(k_downscale, dim3(g.nsub), dim3(64), downscale_smem(g), st, g, kap_s, q, ubnd, ux, uy,
-                     red_rate, red_qin, err);
 }
 
 void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double cfl,

@@ -23,7 +23,7 @@ namespace {
 
 constexpr int TILE = 64;
 
-__device__ inline const double* child_S(const NdArgs& a, const NodeDev& nd, int c, int* stride, int* off) {
+__device__ __forceinline__ const double* child_S(const NdArgs& a, const NodeDev& nd, int c, int* stride, int* off) {
   const int ch = nd.child[c];
   if (ch < 0) {
     const int sub = -1 - ch;
@@ -37,7 +37,7 @@ __device__ inline const double* child_S(const NdArgs& a, const NodeDev& nd, int 
   return a.front + cn.front_off;
 }
 
-__device__ inline const double* child_c(const NdArgs& a, const NodeDev& nd, int c) {
+__device__ __forceinline__ const double* child_c(const NdArgs& a, const NodeDev& nd, int c) {
   const int ch = nd.child[c];
   if (ch < 0) return a.leafr + size_t(-1 - ch) * a.ndmax;
   return a.cB + a.nodes[ch].cB_off;

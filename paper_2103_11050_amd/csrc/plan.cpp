@@ -52,7 +52,7 @@ mpm_status validate(const mpm_desc& d, std::string* why) {
   const int band = std::min(d.sub_x, d.sub_y);
   const long nc = long(d.sub_x) * d.sub_y;
   if (nc * (band + 1) * 8 > 64 * 1024) return bad("subdomain too large for the local factorisation (band storage > 64 KiB)");
-  if (2 * (d.sub_x + d.sub_y) > 64) return bad("subdomain boundary longer than 64 faces");
+  if (d.sub_x > 16 || d.sub_y > 16) return bad("subdomain sides longer than 16 cells are not supported");
   if (2 * (2 * d.ne_x + 2 * d.ne_y) > 128) return bad("more than 128 interface unknowns per subdomain");
   return MPM_OK;
 }
@@ -196,7 +196,10 @@ void build_plan(const mpm_desc& d, Plan* p) {
   P.off_uy = take(nfy * 8);
   P.off_uxm = take(nfx * 8);
   P.off_uym = take(nfy * 8);
-  P.off_fac = take(size_t(P.nsub) * P.nc * (P.band + 1) * 8);
+  {
+    const int mf = P.band <= 8 ? 8 : 16;
+    P.off_fac = take(size_t(P.nsub) * (P.nc / P.band) * mf * mf * 8);
+  }
   P.off_dinv = take(size_t(P.nsub) * P.nc * 8);
   P.off_S = take(size_t(P.nsub) * P.nb * P.nb * 8);
   P.off_h = take(size_t(P.nsub) * P.nb * 8);

@@ -10,7 +10,7 @@ namespace mpm {
 
 namespace {
 
-__device__ inline double fracflow(double s, double M) {
+__device__ __forceinline__ double fracflow(double s, double M) {
   const double a = M * s * s;
   const double o = 1.0 - s;
   return a / (a + o * o);

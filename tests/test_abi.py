@@ -67,7 +67,7 @@ def test_no_pressure_boundary_rejected(lib):
 
 
 def test_oversized_subdomain_rejected(lib):
-    cfg = inputs.config("c1", nx=64, ny=64, sub_x=32, sub_y=32, ne_x=4, ne_y=4)
+    cfg = inputs.config("c1", nx=40, ny=40, sub_x=20, sub_y=10, ne_x=4, ne_y=2)
     st, _ = _size(cfg)
     assert st == binding.MPM_EINVAL
 

@@ -42,7 +42,7 @@ SHAPES = [
     (32, 32, 8, 8, 2, 2),
     (12, 8, 4, 4, 2, 1),
     (24, 16, 8, 4, 4, 2),
-    (20, 10, 20, 10, 1, 1),     # one subdomain, no interface
+    (16, 10, 16, 10, 1, 1),     # one subdomain, no interface, padded lines
     (48, 8, 8, 8, 1, 4),        # one row of subdomains
     (12, 12, 4, 4, 4, 4),       # one fine face per interface element
     (30, 20, 10, 10, 5, 2),     # 3 x 2 subdomains, ragged tree
