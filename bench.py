@@ -139,6 +139,18 @@ def main():
     for _ in range(args.profile_steps):
         run.step()
     prof = run.profile(enable=False, reset=True)
+    # latency of a basis update (MRCM), forced after the timed window
+    torch.cuda.synchronize()
+    mr = []
+    run.profile(enable=True, reset=True)
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        run.step(binding.FORCE_MRCM)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        mr.append(e0.elapsed_time(e1))
+    mprof = run.profile(enable=False, reset=True)
     alg = algorithmic_bytes(cfg)
     cand = {k: v for k, v in prof.items() if k in alg}
     dom = max(cand, key=lambda k: cand[k][0]) if cand else None
@@ -169,6 +181,8 @@ def main():
                    "step_latency_ms_p99": round(float(np.percentile(lat, 99)), 4)},
         "roofline": roof,
         "kernels_ms": {k: round(v[0], 5) for k, v in sorted(prof.items())},
+        "mrcm_update_ms": round(float(np.median(mr)), 4),
+        "mrcm_kernels_ms": {k: round(v[0], 5) for k, v in sorted(mprof.items())},
     }
     run.close()
     if not args.no_cpu_baseline:

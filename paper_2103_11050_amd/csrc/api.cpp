@@ -63,7 +63,7 @@ struct mpm_run {
   int device = 0;
   char* ws = nullptr;
   double *K, *q, *s, *s2, *kn, *km, *ux, *uy, *uxm, *uym, *fac, *S, *h, *vbnd, *ubnd, *leafK, *leafr;
-  double *front, *fI, *cB, *panel, *y, *red, *scal;
+  double *front, *fI, *cB, *panel, *y, *red, *scal, *dsE, *nfac;
   int32_t* err;
   NdArgs nd{};
   const int32_t* subdofs_d = nullptr;
@@ -174,9 +174,11 @@ mpm_status kappa_and_eps(mpm_run* r) {
 void nd_solve(mpm_run* r) {
   const Plan& P = r->P;
   const int L = int(P.level_nodes.size()) - 1;
+  const int nroots = int(P.fuse_off.size()) - 1;
   {
     Scope sc(r, "iface_fwd");
-    for (int l = 1; l <= L; ++l) {
+    if (nroots > 0) launch_nd_fused_fwd(r->st, r->nd, nroots, P.fuse_nmax);
+    for (int l = P.fuse_level + 1; l <= L; ++l) {
       const int nn = int(P.level_nodes[l].size());
       if (!nn) continue;
       launch_nd_level_fwd(r->st, r->nd, P.level_off[l], nn, P.level_nmax[l], P.level_nBmax[l]);
@@ -184,11 +186,12 @@ void nd_solve(mpm_run* r) {
   }
   {
     Scope sc(r, "iface_bwd");
-    for (int l = L; l >= 1; --l) {
+    for (int l = L; l > P.fuse_level; --l) {
       const int nn = int(P.level_nodes[l].size());
       if (!nn) continue;
-      launch_nd_level_bwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l]);
+      launch_nd_level_bwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l], P.level_nmax[l]);
     }
+    if (nroots > 0) launch_nd_fused_bwd(r->st, r->nd, nroots, P.fuse_nmax);
   }
 }
 
@@ -203,14 +206,15 @@ void nd_factor(mpm_run* r) {
   }
 }
 
-void finish_velocity(mpm_run* r, const double* kap_s, int with_v) {
+void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store) {
   {
     Scope sc(r, "flux");
     launch_flux(r->st, r->g, r->km, r->S, r->h, r->vbnd, r->y, r->subdofs_d, r->ubnd, with_v);
   }
   {
     Scope sc(r, "downscale");
-    launch_downscale(r->st, r->g, kap_s, r->q, r->ubnd, r->ux, r->uy, r->red, r->red + r->P.nsub, r->err);
+    launch_downscale(r->st, r->g, kap_s, r->km, r->q, r->ubnd, r->ux, r->uy, r->red, r->red + r->P.nsub, r->dsE,
+                     r->nfac, store, r->err);
   }
   {
     Scope sc(r, "dt");
@@ -231,7 +235,7 @@ mpm_status mrcm_update(mpm_run* r) {
   }
   nd_factor(r);
   nd_solve(r);
-  finish_velocity(r, r->km, 0);
+  finish_velocity(r, r->km, 0, 1);
   const size_t fx = size_t(r->P.ny) * (r->P.nx + 1) * 8, fy = size_t(r->P.ny + 1) * r->P.nx * 8;
   HIPCHK(r, hipMemcpyAsync(r->uxm, r->ux, fx, hipMemcpyDeviceToDevice, r->st));
   HIPCHK(r, hipMemcpyAsync(r->uym, r->uy, fy, hipMemcpyDeviceToDevice, r->st));
@@ -247,7 +251,7 @@ mpm_status mpm_update(mpm_run* r) {
     launch_mpm_local(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac, r->h, r->vbnd, r->leafr);
   }
   nd_solve(r);
-  finish_velocity(r, r->kn, 1);
+  finish_velocity(r, r->kn, 1, 0);
   return MPM_OK;
 }
 
@@ -350,6 +354,7 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   r->h = D(P.off_h); r->vbnd = D(P.off_vbnd); r->ubnd = D(P.off_ubnd); r->leafK = D(P.off_leafK);
   r->leafr = D(P.off_leafr); r->front = D(P.off_front); r->fI = D(P.off_fI); r->cB = D(P.off_cB);
   r->panel = D(P.off_panel); r->y = D(P.off_y); r->red = D(P.off_red); r->scal = D(P.off_scal);
+  r->dsE = D(P.off_dsE); r->nfac = D(P.off_nfac);
   r->err = reinterpret_cast<int32_t*>(r->scal + SC_COUNT);
   r->subdofs_d = reinterpret_cast<const int32_t*>(r->ws + P.off_subdofs);
   r->nd.nodes = reinterpret_cast<const NodeDev*>(r->ws + P.off_nodes);
@@ -359,6 +364,8 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   r->nd.front = r->front; r->nd.fI = r->fI; r->nd.cB = r->cB; r->nd.panel = r->panel;
   r->nd.leafK = r->leafK; r->nd.leafr = r->leafr; r->nd.y = r->y; r->nd.ndmax = P.ndmax;
   r->nd.piv_b = P.piv_b; r->nd.err = r->err;
+  r->nd.fuse_off = reinterpret_cast<const int32_t*>(r->ws + P.off_fuse_off);
+  r->nd.fuse_nodes = reinterpret_cast<const int32_t*>(r->ws + P.off_fuse_nodes);
   r->M = P.d.mu_o / P.d.mu_w;
   r->fmax_deriv = max_fprime(r->M);
   r->area = P.d.lx * P.d.ly;
@@ -371,6 +378,8 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   };
   if (up(P.off_nodes, P.nodes.data(), P.nodes.size() * sizeof(NodeDev)) ||
       up(P.off_levels, P.level_flat.data(), P.level_flat.size() * 4) ||
+      up(P.off_fuse_off, P.fuse_off.data(), P.fuse_off.size() * 4) ||
+      up(P.off_fuse_nodes, P.fuse_nodes.data(), P.fuse_nodes.size() * 4) ||
       up(P.off_dofpool, P.dof_pool.data(), P.dof_pool.size() * 4) ||
       up(P.off_mappool, P.map_pool.data(), P.map_pool.size() * 4) ||
       up(P.off_subdofs, P.sub_dofs.data(), P.sub_dofs.size() * 4) ||

@@ -128,9 +128,14 @@ __host__ __device__ __forceinline__ double bface_trans(const Geo& g, const BFace
 __host__ __device__ __forceinline__ double robin_beta(const Geo& g, const BFace& b, double kc) {
   return g.alpha * b.H / kc;
 }
-// Harmonic transmissibility per unit length between two cells at distance d.
+// Harmonic transmissibility per unit length between two cells at distance d:
+// (d/(2 kc) + d/(2 kd))^-1 = 2 kc kd / (d (kc + kd)), one division.
 __host__ __device__ __forceinline__ double harm_trans(double kc, double kd, double d) {
-  return 1.0 / (d / (2.0 * kc) + d / (2.0 * kd));
+  return 2.0 * kc * kd / (d * (kc + kd));
+}
+// t^n / t^m of a face between cells c and d (the distance cancels), one division.
+__host__ __device__ __forceinline__ double harm_ratio(double knc, double knd, double kmc, double kmd) {
+  return (knc * knd * (kmc + kmd)) / (kmc * kmd * (knc + knd));
 }
 
 __device__ __forceinline__ void set_error(int32_t* err, int32_t bits) { atomicOr(err, bits); }

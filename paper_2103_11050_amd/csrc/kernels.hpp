@@ -21,8 +21,11 @@ void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const doub
                       double* leafr);
 void launch_flux(hipStream_t st, const Geo& g, const double* km, const double* S, const double* h,
                  const double* vbnd, const double* y, const int32_t* sub_dofs, double* ubnd, int with_v);
-void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
-                      double* ux, double* uy, double* red_rate, double* red_qin, int32_t* err);
+// store = 1: kap_s is kappa^m; the inverse blocks are kept for later steps. store = 0: a
+// subdomain whose kap_s tile equals its kap_m tile reuses the kept blocks.
+void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* kap_m, const double* q,
+                      const double* ubnd, double* ux, double* uy, double* red_rate, double* red_qin, double* Escr,
+                      double* Ekeep, int store, int32_t* err);
 void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double cfl,
                double fmax_deriv, double* scal);
 
@@ -42,10 +45,14 @@ struct NdArgs {
   int ndmax;
   int piv_b;
   int32_t* err;
+  const int32_t* fuse_off;    // subtree offsets into fuse_nodes (bottom levels)
+  const int32_t* fuse_nodes;  // subtree nodes, children before parents
 };
 void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nmax, int nImax);
 void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nmax, int nBmax);
-void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nImax);
+void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nImax, int nmax);
+void launch_nd_fused_fwd(hipStream_t st, const NdArgs& a, int nroots, int nmax);
+void launch_nd_fused_bwd(hipStream_t st, const NdArgs& a, int nroots, int nmax);
 
 // transport.hip
 void launch_sat_step(hipStream_t st, const Geo& g, const double* s, double* s2, const double* ux,

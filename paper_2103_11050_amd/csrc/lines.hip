@@ -34,8 +34,7 @@ __device__ __forceinline__ size_t efac_off(const Geo& g, int sub, int ln, int t)
 // Block elimination over all lines; the inverses D_ln^-1 go to Es[(ln*EPL + t)*64 + lane]
 // (LDS or global).
 template <int MF>
-__device__ __forceinline__ void lb_factor(const Geo& g, int I, int J, const double* kl, int mode, const LB<MF>& L,
-                                          double* Es, bool& ok) {
+__device__ __forceinline__ void lb_factor(const Geo& g, const LineW& W, const LB<MF>& L, double* Es, bool& ok) {
   constexpr int EPL = LB<MF>::EPL;
   const int nl = g.nc / g.band;
   double prev[EPL], cur[EPL];
@@ -43,7 +42,7 @@ __device__ __forceinline__ void lb_factor(const Geo& g, int I, int J, const doub
   for (int t = 0; t < EPL; ++t) prev[t] = 0.0;
 #pragma unroll 1
   for (int ln = 0; ln < nl; ++ln) {
-    lb_block<MF>(g, I, J, kl, ln, mode, L, prev, cur);
+    lb_block<MF>(W, ln, L, prev, cur);
     lb_inverse<MF>(L, cur, ok);
 #pragma unroll
     for (int t = 0; t < EPL; ++t) {
@@ -56,8 +55,8 @@ __device__ __forceinline__ void lb_factor(const Geo& g, int I, int J, const doub
 // x (LDS, local order) holds the right-hand side on entry and the solution on exit; w is LDS
 // scratch of nl*MF doubles; Es holds the block inverses as written by lb_factor.
 template <int MF>
-__device__ __forceinline__ void lb_solve(const Geo& g, const double* kl, int mode, const LB<MF>& L,
-                                         const double* Es, double* x, double* w) {
+__device__ __forceinline__ void lb_solve(const Geo& g, const LineW& W, const LB<MF>& L, const double* Es, double* x,
+                                         double* w) {
   constexpr int EPL = LB<MF>::EPL;
   const int nl = g.nc / g.band;
   const int len = g.band;
@@ -69,7 +68,7 @@ __device__ __forceinline__ void lb_solve(const Geo& g, const double* kl, int mod
 #pragma unroll
     for (int t = 0; t < EPL; ++t) e[t] = Es[(size_t(ln) * EPL + t) * 64 + L.lane];
     double z = rin ? x[ln * len + L.row] : 0.0;
-    if (ln > 0 && rin) z += line_y(g, kl, ln - 1, L.row, mode) * wprev;
+    if (ln > 0 && rin) z += W.y(ln - 1, L.row) * wprev;
     wprev = lb_matvec<MF>(L, e, z);
     if (L.cg == 0) w[ln * MF + L.row] = wprev;
   }
@@ -80,7 +79,7 @@ __device__ __forceinline__ void lb_solve(const Geo& g, const double* kl, int mod
     double e[EPL];
 #pragma unroll
     for (int t = 0; t < EPL; ++t) e[t] = Es[(size_t(ln) * EPL + t) * 64 + L.lane];
-    const double v = rin ? line_y(g, kl, ln, L.row, mode) * xnext : 0.0;
+    const double v = rin ? W.y(ln, L.row) * xnext : 0.0;
     xnext = w[ln * MF + L.row] + lb_matvec<MF>(L, e, v);
     if (rin && L.cg == 0) x[ln * len + L.row] = xnext;
   }
@@ -94,15 +93,16 @@ __device__ __forceinline__ void lb_solve(const Geo& g, const double* kl, int mod
 template <int MF>
 __global__ void __launch_bounds__(64) k_line_factor(Geo g, const double* __restrict__ kap, double* __restrict__ fac,
                                                     int32_t* err) {
-  __shared__ double kl[256];
-  constexpr int EPL = LB<MF>::EPL;
+  __shared__ double kl[256], tE[256], tN[256], dg[256];
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
   LB<MF> L;
   load_tile2(g, I, J, kap, kl);
   __syncthreads();
+  fill_trans(g, I, J, kl, 0, tE, tN, dg);
+  const LineW W{tE, tN, dg, g.xfast, g.band, 0};
   bool ok = true;
-  lb_factor<MF>(g, I, J, kl, 0, L, fac + efac_off<MF>(g, sub, 0, 0), ok);
+  lb_factor<MF>(g, W, L, fac + efac_off<MF>(g, sub, 0, 0), ok);
   if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
 }
 
@@ -118,7 +118,7 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
                const double* __restrict__ uxm, const double* __restrict__ uym, const double* __restrict__ q,
                const double* __restrict__ fac, double* __restrict__ hg, double* __restrict__ vbnd,
                double* __restrict__ leafr) {
-  __shared__ double kl[256], x[256], hsh[64], wsh[256];
+  __shared__ double kl[256], x[256], hsh[64], wsh[256], tE[256], tN[256], dg[256];
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int n = g.nc, nb = g.nb;
@@ -134,7 +134,7 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
     {
       const double u = uxm[gj * (g.nx + 1) + gi];
       if (gi > 0) {
-        const double ratio = harm_trans(kn, kap_n[gc - 1], g.hx) / harm_trans(km, kap_m[gc - 1], g.hx);
+        const double ratio = harm_ratio(kn, kap_n[gc - 1], km, kap_m[gc - 1]);
         r -= g.hy * (-ratio * u);
       } else {
         BFace f = bface(g, I, J, j);
@@ -144,7 +144,7 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
     {
       const double u = uxm[gj * (g.nx + 1) + gi + 1];
       if (gi < g.nx - 1) {
-        const double ratio = harm_trans(kn, kap_n[gc + 1], g.hx) / harm_trans(km, kap_m[gc + 1], g.hx);
+        const double ratio = harm_ratio(kn, kap_n[gc + 1], km, kap_m[gc + 1]);
         r -= g.hy * (ratio * u);
       } else {
         BFace f = bface(g, I, J, g.my + j);
@@ -154,7 +154,7 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
     {
       const double u = uym[gj * g.nx + gi];
       if (gj > 0) {
-        const double ratio = harm_trans(kn, kap_n[gc - g.nx], g.hy) / harm_trans(km, kap_m[gc - g.nx], g.hy);
+        const double ratio = harm_ratio(kn, kap_n[gc - g.nx], km, kap_m[gc - g.nx]);
         r -= g.hx * (-ratio * u);
       } else {
         BFace f = bface(g, I, J, 2 * g.my + i);
@@ -164,7 +164,7 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
     {
       const double u = uym[(gj + 1) * g.nx + gi];
       if (gj < g.ny - 1) {
-        const double ratio = harm_trans(kn, kap_n[gc + g.nx], g.hy) / harm_trans(km, kap_m[gc + g.nx], g.hy);
+        const double ratio = harm_ratio(kn, kap_n[gc + g.nx], km, kap_m[gc + g.nx]);
         r -= g.hx * (ratio * u);
       } else {
         BFace f = bface(g, I, J, 2 * g.my + g.mx + i);
@@ -174,7 +174,9 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
     x[c] = r;
   }
   __syncthreads();
-  lb_solve<MF>(g, kl, 0, L, fac + efac_off<MF>(g, sub, 0, 0), x, wsh);
+  fill_trans(g, I, J, kl, 0, tE, tN, dg);
+  const LineW W{tE, tN, dg, g.xfast, g.band, 0};
+  lb_solve<MF>(g, W, L, fac + efac_off<MF>(g, sub, 0, 0), x, wsh);
   for (int f = threadIdx.x; f < nb; f += blockDim.x) {
     BFace bf = bface(g, I, J, f);
     const int gi = I * g.mx + bf.i, gj = J * g.my + bf.j;
@@ -192,7 +194,7 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
       else if (bf.side == 1) { u = uxm[gj * (g.nx + 1) + gi + 1]; nbr = gi < g.nx - 1 ? gc + 1 : -1; dd = g.hx; }
       else if (bf.side == 2) { u = -uym[gj * g.nx + gi]; nbr = gj > 0 ? gc - g.nx : -1; dd = g.hy; }
       else { u = uym[(gj + 1) * g.nx + gi]; nbr = gj < g.ny - 1 ? gc + g.nx : -1; dd = g.hy; }
-      const double ratio = nbr >= 0 ? harm_trans(kn, kap_n[nbr], dd) / harm_trans(km, kap_m[nbr], dd) : kn / km;
+      const double ratio = nbr >= 0 ? harm_ratio(kn, kap_n[nbr], km, kap_m[nbr]) : kn / km;
       v = ratio * u;
     }
     vbnd[size_t(sub) * nb + f] = v;
@@ -220,11 +222,12 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
 // rate per cell volume and the inflow through the physical boundary.
 template <int MF>
 __global__ void __launch_bounds__(64)
-k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict__ q,
-               const double* __restrict__ ubnd, double* __restrict__ ux, double* __restrict__ uy,
-               double* __restrict__ red_rate, double* __restrict__ red_qin, int32_t* err) {
-  __shared__ double kl[256], x[256], w[64], scratch[128], wsh[256];
-  __shared__ double Es[MSMAX * MF * MF];
+k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict__ kap_m,
+               const double* __restrict__ q, const double* __restrict__ ubnd, double* __restrict__ ux,
+               double* __restrict__ uy, double* __restrict__ red_rate, double* __restrict__ red_qin,
+               double* __restrict__ Escr, double* __restrict__ Ekeep, int store, int32_t* err) {
+  __shared__ double kl[256], x[256], w[64], scratch[128], wsh[256], tE[256], tN[256], dg[256];
+  __shared__ int changed;
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int n = g.nc, nb = g.nb;
@@ -255,10 +258,36 @@ k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict
     x[c] = c == 0 ? 0.0 : r;
   }
   __syncthreads();
-  bool ok = true;
-  lb_factor<MF>(g, I, J, kl, 1, L, Es, ok);
-  if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
-  lb_solve<MF>(g, kl, 1, L, Es, x, wsh);
+  fill_trans(g, I, J, kl, 1, tE, tN, dg);
+  const LineW W{tE, tN, dg, g.xfast, g.band, 1};
+  // the kept kappa^m blocks are exact for a subdomain whose conductivity has not changed
+  if (threadIdx.x == 0) changed = 0;
+  __syncthreads();
+  if (!store) {
+    bool diff = false;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+      int i, j;
+      loc_ij(g, c, &i, &j);
+      diff = diff || (kl[c] != kap_m[gcell2(g, I, J, i, j)]);
+    }
+    if (diff) changed = 1;
+  }
+  __syncthreads();
+  const size_t eoff = efac_off<MF>(g, sub, 0, 0);
+  double* Es;
+  if (store) {
+    Es = Ekeep + eoff;
+  } else if (changed) {
+    Es = Escr + eoff;
+  } else {
+    Es = Ekeep + eoff;
+  }
+  if (store || changed) {
+    bool ok = true;
+    lb_factor<MF>(g, W, L, Es, ok);
+    if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
+  }
+  lb_solve<MF>(g, W, L, Es, x, wsh);
   double rate = 0.0;
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     int i, j;
@@ -266,13 +295,14 @@ k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict
     const int gi = I * g.mx + i, gj = J * g.my + j;
     const double pc = x[c];
     double uW, uE, uS, uN;
-    if (i > 0) uW = harm_trans(kl[loc_index(g, i - 1, j)], kl[c], g.hx) * (x[loc_index(g, i - 1, j)] - pc);
+    // interior faces: the pinned cell's couplings are part of the flux field (tE, tN hold them)
+    if (i > 0) { const int d = loc_index(g, i - 1, j); uW = tE[d] / g.hy * (x[d] - pc); }
     else uW = -w[j];
-    if (i < g.mx - 1) uE = harm_trans(kl[c], kl[loc_index(g, i + 1, j)], g.hx) * (pc - x[loc_index(g, i + 1, j)]);
+    if (i < g.mx - 1) uE = tE[c] / g.hy * (pc - x[loc_index(g, i + 1, j)]);
     else uE = w[g.my + j];
-    if (j > 0) uS = harm_trans(kl[loc_index(g, i, j - 1)], kl[c], g.hy) * (x[loc_index(g, i, j - 1)] - pc);
+    if (j > 0) { const int d = loc_index(g, i, j - 1); uS = tN[d] / g.hx * (x[d] - pc); }
     else uS = -w[2 * g.my + i];
-    if (j < g.my - 1) uN = harm_trans(kl[c], kl[loc_index(g, i, j + 1)], g.hy) * (pc - x[loc_index(g, i, j + 1)]);
+    if (j < g.my - 1) uN = tN[c] / g.hx * (pc - x[loc_index(g, i, j + 1)]);
     else uN = w[2 * g.my + g.mx + i];
     ux[gj * (g.nx + 1) + gi] = uW;
     uy[gj * g.nx + gi] = uS;
@@ -315,12 +345,15 @@ void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const doub
     hipLaunchKernelGGL(k_mpm_local_lb<16>, dim3(g.nsub), dim3(64), 0, st, g, kn, km, uxm, uym, q, fac, h, vbnd, leafr);
 }
 
-void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
-                      double* ux, double* uy, double* red_rate, double* red_qin, int32_t* err) {
+void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* kap_m, const double* q,
+                      const double* ubnd, double* ux, double* uy, double* red_rate, double* red_qin, double* Escr,
+                      double* Ekeep, int store, int32_t* err) {
   if (line_mf(g) == 8)
-    hipLaunchKernelGGL(k_downscale_lb<8>, dim3(g.nsub), dim3(64), 0, st, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, err);
+    hipLaunchKernelGGL(k_downscale_lb<8>, dim3(g.nsub), dim3(64), 0, st, g, kap_s, kap_m, q, ubnd, ux, uy, red_rate,
+                       red_qin, Escr, Ekeep, store, err);
   else
-    hipLaunchKernelGGL(k_downscale_lb<16>, dim3(g.nsub), dim3(64), 0, st, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, err);
+    hipLaunchKernelGGL(k_downscale_lb<16>, dim3(g.nsub), dim3(64), 0, st, g, kap_s, kap_m, q, ubnd, ux, uy, red_rate,
+                       red_qin, Escr, Ekeep, store, err);
 }
 
 size_t line_factor_doubles(int nsub, int nc, int band) {

@@ -50,7 +50,10 @@ __device__ __forceinline__ void lb_inverse(const LB<MF>& L, double (&a)[LB<MF>::
       const double ck = __shfl(a[kk], L.row * LPR + k0 / EPL);
       const double d = __shfl(a[kk], k * LPR + k0 / EPL);
       ok = ok && (d > 0.0);
-      const double rd = 1.0 / d;
+      // 1/d: hardware reciprocal refined by two Newton steps (full double precision)
+      double rd = __builtin_amdgcn_rcp(d);
+      rd = fma(rd, fma(-d, rd, 1.0), rd);
+      rd = fma(rd, fma(-d, rd, 1.0), rd);
 #pragma unroll
       for (int t = 0; t < EPL; ++t) {
         const int j = L.col(t);
@@ -97,61 +100,73 @@ __device__ __forceinline__ void line_cell(const Geo& g, int ln, int pos, int* i,
   *j = g.xfast ? ln : pos;
 }
 
-// Entries of the subdomain matrix in line form, from the conductivity tile kl (LDS, local
-// order). mode 0: boundary faces with Dirichlet/Robin transmissibility (eq:mrc1); mode 1:
-// all-Neumann with cell 0 pinned.
-//   diag(ln,pos), off(ln,pos) = weight of the coupling pos <-> pos+1 inside the line,
-//   yc(ln,pos) = weight of the coupling to line ln+1.
-__device__ __forceinline__ double cell_diag(const Geo& g, int I, int J, const double* kl, int ln, int pos, int mode) {
-  int i, j;
-  line_cell(g, ln, pos, &i, &j);
-  const int c = ln * g.band + pos;
-  if (mode == 1 && c == 0) return 1.0;
-  const double kc = kl[c];
-  double d = 0.0;
-  if (i > 0) d += g.hy * harm_trans(kc, kl[loc_index(g, i - 1, j)], g.hx);
-  if (i < g.mx - 1) d += g.hy * harm_trans(kc, kl[loc_index(g, i + 1, j)], g.hx);
-  if (j > 0) d += g.hx * harm_trans(kc, kl[loc_index(g, i, j - 1)], g.hy);
-  if (j < g.my - 1) d += g.hx * harm_trans(kc, kl[loc_index(g, i, j + 1)], g.hy);
-  if (mode == 0) {
-    if (i == 0) { BFace f = bface(g, I, J, j); d += f.flen * bface_trans(g, f, kc); }
-    if (i == g.mx - 1) { BFace f = bface(g, I, J, g.my + j); d += f.flen * bface_trans(g, f, kc); }
-    if (j == 0) { BFace f = bface(g, I, J, 2 * g.my + i); d += f.flen * bface_trans(g, f, kc); }
-    if (j == g.my - 1) { BFace f = bface(g, I, J, 2 * g.my + g.mx + i); d += f.flen * bface_trans(g, f, kc); }
+// Face weights of a subdomain's matrix, computed once per cell into LDS (local order):
+// tE[c] = |f| t of the face to the +x neighbour inside the subdomain (0 on its E edge),
+// tN[c] likewise to the +y neighbour, dg[c] = diagonal entry.
+// mode 0: boundary faces with their Dirichlet/Robin transmissibility (eq:mrc1);
+// mode 1: all boundary faces are flux faces and cell 0 is pinned (p = 0): its couplings are
+// dropped from the matrix and its diagonal is 1.
+__device__ __forceinline__ void fill_trans(const Geo& g, int I, int J, const double* kl, int mode, double* tE,
+                                           double* tN, double* dg) {
+  for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
+    int i, j;
+    loc_ij(g, c, &i, &j);
+    const double kc = kl[c];
+    tE[c] = i < g.mx - 1 ? g.hy * harm_trans(kc, kl[loc_index(g, i + 1, j)], g.hx) : 0.0;
+    tN[c] = j < g.my - 1 ? g.hx * harm_trans(kc, kl[loc_index(g, i, j + 1)], g.hy) : 0.0;
   }
-  return d;
+  __syncthreads();
+  for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
+    int i, j;
+    loc_ij(g, c, &i, &j);
+    const double kc = kl[c];
+    double d = tE[c] + tN[c];
+    if (i > 0) d += tE[loc_index(g, i - 1, j)];
+    if (j > 0) d += tN[loc_index(g, i, j - 1)];
+    if (mode == 0) {
+      if (i == 0) { BFace f = bface(g, I, J, j); d += f.flen * bface_trans(g, f, kc); }
+      if (i == g.mx - 1) { BFace f = bface(g, I, J, g.my + j); d += f.flen * bface_trans(g, f, kc); }
+      if (j == 0) { BFace f = bface(g, I, J, 2 * g.my + i); d += f.flen * bface_trans(g, f, kc); }
+      if (j == g.my - 1) { BFace f = bface(g, I, J, 2 * g.my + g.mx + i); d += f.flen * bface_trans(g, f, kc); }
+    }
+    dg[c] = (mode == 1 && c == 0) ? 1.0 : d;
+  }
+  __syncthreads();
 }
 
-// Weight of the coupling between position pos and pos+1 of line ln (0 if pinned).
-__device__ __forceinline__ double line_off(const Geo& g, const double* kl, int ln, int pos, int mode) {
-  const int c = ln * g.band + pos;
-  if (mode == 1 && c == 0) return 0.0;
-  // pos -> pos+1 moves along the fast axis
-  if (g.xfast) return g.hy * harm_trans(kl[c], kl[c + 1], g.hx);
-  return g.hx * harm_trans(kl[c], kl[c + 1], g.hy);
-}
+// Couplings in line form. The matrix entries with the pinned cell are zero.
+struct LineW {
+  const double* tE;
+  const double* tN;
+  const double* dg;
+  int xfast, band, mode;
+  // weight between position pos and pos+1 of line ln
+  __device__ __forceinline__ double off(int ln, int pos) const {
+    const int c = ln * band + pos;
+    if (mode == 1 && c == 0) return 0.0;
+    return xfast ? tE[c] : tN[c];
+  }
+  // weight between (ln, pos) and (ln+1, pos)
+  __device__ __forceinline__ double y(int ln, int pos) const {
+    const int c = ln * band + pos;
+    if (mode == 1 && c == 0) return 0.0;
+    return xfast ? tN[c] : tE[c];
+  }
+  __device__ __forceinline__ double diag(int ln, int pos) const { return dg[ln * band + pos]; }
+};
 
-// Weight of the coupling between (ln, pos) and (ln+1, pos).
-__device__ __forceinline__ double line_y(const Geo& g, const double* kl, int ln, int pos, int mode) {
-  const int c = ln * g.band + pos;
-  if (mode == 1 && c == 0) return 0.0;
-  const int d = c + g.band;
-  if (g.xfast) return g.hx * harm_trans(kl[c], kl[d], g.hy);
-  return g.hy * harm_trans(kl[c], kl[d], g.hx);
-}
-
-// Builds D_j for line ln in registers: T_ln - Y_{ln-1} Eprev Y_{ln-1}.
+// Builds D_ln for line ln in registers: T_ln - Y_{ln-1} Eprev Y_{ln-1}.
 template <int MF>
-__device__ __forceinline__ void lb_block(const Geo& g, int I, int J, const double* kl, int ln, int mode, const LB<MF>& L,
-                                const double (&Eprev)[LB<MF>::EPL], double (&a)[LB<MF>::EPL]) {
+__device__ __forceinline__ void lb_block(const LineW& W, int ln, const LB<MF>& L, const double (&Eprev)[LB<MF>::EPL],
+                                         double (&a)[LB<MF>::EPL]) {
   constexpr int EPL = LB<MF>::EPL;
-  const int len = g.band;
+  const int len = W.band;
   const int r = L.row;
   const bool rin = r < len;
-  const double drow = rin ? cell_diag(g, I, J, kl, ln, r, mode) : 1.0;
-  const double offR = (rin && r + 1 < len) ? line_off(g, kl, ln, r, mode) : 0.0;
-  const double offL = (rin && r > 0) ? line_off(g, kl, ln, r - 1, mode) : 0.0;
-  const double yr = (ln > 0 && rin) ? line_y(g, kl, ln - 1, r, mode) : 0.0;
+  const double drow = rin ? W.diag(ln, r) : 1.0;
+  const double offR = (rin && r + 1 < len) ? W.off(ln, r) : 0.0;
+  const double offL = (rin && r > 0) ? W.off(ln, r - 1) : 0.0;
+  const double yr = (ln > 0 && rin) ? W.y(ln - 1, r) : 0.0;
 #pragma unroll
   for (int t = 0; t < EPL; ++t) {
     const int c = L.col(t);
@@ -160,10 +175,7 @@ __device__ __forceinline__ void lb_block(const Geo& g, int I, int J, const doubl
     else if (c == r + 1) v = -offR;
     else if (c == r - 1) v = -offL;
     else v = 0.0;
-    if (ln > 0 && rin && c < len) {
-      const double yc = line_y(g, kl, ln - 1, c, mode);
-      v -= yr * Eprev[t] * yc;
-    }
+    if (ln > 0 && rin && c < len) v -= yr * Eprev[t] * W.y(ln - 1, c);
     if (!rin || c >= len) v = (c == r) ? 1.0 : 0.0;
     a[t] = v;
   }

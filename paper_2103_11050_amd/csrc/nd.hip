@@ -68,7 +68,7 @@ __global__ void k_nd_extend(NdArgs a, int loff, int c) {
 }
 
 // Pivot block kb of every node of the level: P = A_KK, Pinv = P^-1 (Gauss-Jordan sweep in LDS,
-// no pivoting), C = old row panel A_K*, R = Pinv C. One workgroup per node.
+// no pivoting). One workgroup per node.
 __global__ void __launch_bounds__(256) k_nd_pivot(NdArgs a, int loff, int kb) {
   __shared__ double P[32 * 33];
   __shared__ double colk[32], rowk[32];
@@ -80,15 +80,9 @@ __global__ void __launch_bounds__(256) k_nd_pivot(NdArgs a, int loff, int kb) {
   const int n = nd.n;
   const double* F = a.front + nd.front_off;
   double* Pinv = a.panel + nd.panel_off;
-  double* C = Pinv + pb * pb;
-  double* R = C + int64_t(pb) * n;
   for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
     const int i = e / bs, j = e % bs;
     P[i * 33 + j] = F[int64_t(K0 + i) * n + K0 + j];
-  }
-  for (int64_t e = threadIdx.x; e < int64_t(bs) * n; e += blockDim.x) {
-    const int k = int(e / n), j = int(e % n);
-    C[int64_t(k) * n + j] = F[int64_t(K0 + k) * n + j];
   }
   __syncthreads();
   // sweep operator on every index of P: afterwards P = -P_orig^-1
@@ -118,12 +112,43 @@ __global__ void __launch_bounds__(256) k_nd_pivot(NdArgs a, int loff, int kb) {
     const int i = e / bs, j = e % bs;
     Pinv[i * pb + j] = -P[i * 33 + j];
   }
-  __syncthreads();
-  // R = Pinv C (bs x n)
-  for (int64_t e = threadIdx.x; e < int64_t(bs) * n; e += blockDim.x) {
-    const int k = int(e / n), j = int(e % n);
+}
+
+// Row panel of pivot block kb: C = old rows A_K* (copied, the update overwrites them) and
+// R = Pinv C, 64 columns per workgroup.
+__global__ void __launch_bounds__(256) k_nd_rpanel(NdArgs a, int loff, int kb) {
+  __shared__ double Pi[32][33];
+  __shared__ double Cs[32][65];
+  const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
+  const int pb = a.piv_b;
+  const int K0 = kb * pb;
+  if (K0 >= nd.nI) return;
+  const int bs = min(pb, nd.nI - K0);
+  const int n = nd.n;
+  const int j0 = blockIdx.x * 64;
+  if (j0 >= n) return;
+  const double* F = a.front + nd.front_off;
+  const double* Pinv = a.panel + nd.panel_off;
+  double* C = a.panel + nd.panel_off + pb * pb;
+  double* R = C + int64_t(pb) * n;
+  for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) Pi[e / bs][e % bs] = Pinv[(e / bs) * pb + e % bs];
+  for (int e = threadIdx.x; e < bs * 64; e += blockDim.x) {
+    const int k = e / 64, t = e % 64;
+    const int j = j0 + t;
     double v = 0.0;
-    for (int t = 0; t < bs; ++t) v += -P[k * 33 + t] * C[int64_t(t) * n + j];
+    if (j < n) {
+      v = F[int64_t(K0 + k) * n + j];
+      C[int64_t(k) * n + j] = v;
+    }
+    Cs[k][t] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < bs * 64; e += blockDim.x) {
+    const int k = e / 64, t = e % 64;
+    const int j = j0 + t;
+    if (j >= n) continue;
+    double v = 0.0;
+    for (int u = 0; u < bs; ++u) v += Pi[k][u] * Cs[u][t];
     R[int64_t(k) * n + j] = v;
   }
 }
@@ -183,10 +208,17 @@ __global__ void __launch_bounds__(256) k_nd_update(NdArgs a, int loff, int kb) {
   }
 }
 
-// Forward: gather the children's condensed right-hand sides into the node's front vector.
-__global__ void __launch_bounds__(256) k_nd_fwd_gather(NdArgs a, int loff) {
+// Forward, one level: every workgroup gathers its node's front right-hand side f (children's
+// condensed vectors, child 0 then child 1) into LDS, then computes 64 entries of
+// c_B = f_B - BI f_I. BI = IB^T is read from the node's I rows (row-major, so consecutive
+// lanes read consecutive columns); the four waves split the I range and their partial sums
+// are added in a fixed order. Workgroup 0 of each node also stores f_I for the backward pass.
+__global__ void __launch_bounds__(256) k_nd_fwd(NdArgs a, int loff) {
   extern __shared__ double f[];
-  const NodeDev nd = a.nodes[a.levels[loff + blockIdx.x]];
+  __shared__ double part[4][64];
+  const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
+  const int j0 = blockIdx.x * 64;
+  if (j0 >= max(nd.nB, 1)) return;
   for (int i = threadIdx.x; i < nd.n; i += blockDim.x) f[i] = 0.0;
   __syncthreads();
   for (int c = 0; c < 2; ++c) {
@@ -195,38 +227,118 @@ __global__ void __launch_bounds__(256) k_nd_fwd_gather(NdArgs a, int loff) {
     for (int i = threadIdx.x; i < nd.nB_child[c]; i += blockDim.x) f[map[i]] += src[i];
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < nd.nI; i += blockDim.x) a.fI[nd.fI_off + i] = f[i];
-  for (int i = threadIdx.x; i < nd.nB; i += blockDim.x) a.cB[nd.cB_off + i] = f[nd.nI + i];
-}
-
-// Forward: c_B = f_B - BI f_I, one wavefront per row.
-__global__ void __launch_bounds__(256) k_nd_fwd_gemv(NdArgs a, int loff) {
-  const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
-  const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= nd.nB) return;
-  const double* row = a.front + nd.front_off + int64_t(nd.nI + r) * nd.n;
-  const double* fI = a.fI + nd.fI_off;
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < nd.nI; i += blockDim.x) a.fI[nd.fI_off + i] = f[i];
+  if (nd.nB == 0) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j = j0 + lane;
   double acc = 0.0;
-  for (int i = lane; i < nd.nI; i += 64) acc += row[i] * fI[i];
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-  if (lane == 0) a.cB[nd.cB_off + r] -= acc;
+  if (j < nd.nB) {
+    // 8 independent row loads in flight per wave
+    const double* col = a.front + nd.front_off + nd.nI + j;
+    const int64_t n = nd.n;
+    double acc8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int i = wv;
+    for (; i + 28 < nd.nI; i += 32) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc8[u] += col[int64_t(i + 4 * u) * n] * f[i + 4 * u];
+    }
+    for (; i < nd.nI; i += 4) acc8[0] += col[int64_t(i) * n] * f[i];
+    acc = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
+  }
+  part[wv][lane] = acc;
+  __syncthreads();
+  if (wv == 0 && j < nd.nB)
+    a.cB[nd.cB_off + j] = f[nd.nI + j] - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
 }
 
-// Backward: x_I = -II f_I - IB x_B, one wavefront per row; scatters x_I into y.
-__global__ void __launch_bounds__(256) k_nd_bwd(NdArgs a, int loff) {
+// Backward, one level: v = [f_I; x_B] in LDS (x_B gathered from the solution by the node's
+// unknown list), then x_I = -[II IB] v, one wavefront per row, rows split over workgroups.
+__global__ void __launch_bounds__(256) k_nd_bwd(NdArgs a, int loff, int rows_per_block) {
+  extern __shared__ double v[];
   const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
-  const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= nd.nI) return;
-  const double* row = a.front + nd.front_off + int64_t(r) * nd.n;
-  const double* fI = a.fI + nd.fI_off;
+  const int r0 = blockIdx.x * rows_per_block;
+  if (r0 >= nd.nI) return;
   const int32_t* dofs = a.dof_pool + nd.dof_off;
-  double acc = 0.0;
-  for (int i = lane; i < nd.nI; i += 64) acc += row[i] * fI[i];
-  for (int j = lane; j < nd.nB; j += 64) acc += row[nd.nI + j] * a.y[dofs[nd.nI + j]];
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-  if (lane == 0) a.y[dofs[r]] = -acc;
+  for (int i = threadIdx.x; i < nd.nI; i += blockDim.x) v[i] = a.fI[nd.fI_off + i];
+  for (int i = threadIdx.x; i < nd.nB; i += blockDim.x) v[nd.nI + i] = a.y[dofs[nd.nI + i]];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r1 = min(nd.nI, r0 + rows_per_block);
+  for (int r = r0 + wv; r < r1; r += 4) {
+    const double* row = a.front + nd.front_off + int64_t(r) * nd.n;
+    double acc8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int k = lane;
+    for (; k + 448 < nd.n; k += 512) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc8[u] += row[k + 64 * u] * v[k + 64 * u];
+    }
+    for (; k < nd.n; k += 64) acc8[0] += row[k] * v[k];
+    double acc = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) a.y[dofs[r]] = -acc;
+  }
+}
+
+// Bottom levels fused: one workgroup walks one subtree, children before parents (forward)
+// or parents before children (backward); the per-node work is that of k_nd_fwd / k_nd_bwd.
+__global__ void __launch_bounds__(256) k_nd_fwd_fused(NdArgs a) {
+  extern __shared__ double f[];
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int idx = a.fuse_off[blockIdx.x]; idx < a.fuse_off[blockIdx.x + 1]; ++idx) {
+    const NodeDev nd = a.nodes[a.fuse_nodes[idx]];
+    for (int i = threadIdx.x; i < nd.n; i += blockDim.x) f[i] = 0.0;
+    __syncthreads();
+    for (int c = 0; c < 2; ++c) {
+      const double* src = child_c(a, nd, c);
+      const int32_t* map = a.map_pool + nd.map_off[c];
+      for (int i = threadIdx.x; i < nd.nB_child[c]; i += blockDim.x) f[map[i]] += src[i];
+      __syncthreads();
+    }
+    for (int i = threadIdx.x; i < nd.nI; i += blockDim.x) a.fI[nd.fI_off + i] = f[i];
+    for (int j0 = 0; j0 < nd.nB; j0 += 64) {
+      const int j = j0 + lane;
+      double acc = 0.0;
+      if (j < nd.nB) {
+        const double* col = a.front + nd.front_off + nd.nI + j;
+        for (int i = wv; i < nd.nI; i += 4) acc += col[int64_t(i) * nd.n] * f[i];
+      }
+      part[wv][lane] = acc;
+      __syncthreads();
+      if (wv == 0 && j < nd.nB)
+        a.cB[nd.cB_off + j] = f[nd.nI + j] - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_nd_bwd_fused(NdArgs a) {
+  extern __shared__ double v[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int idx = a.fuse_off[blockIdx.x + 1] - 1; idx >= a.fuse_off[blockIdx.x]; --idx) {
+    const NodeDev nd = a.nodes[a.fuse_nodes[idx]];
+    const int32_t* dofs = a.dof_pool + nd.dof_off;
+    for (int i = threadIdx.x; i < nd.nI; i += blockDim.x) v[i] = a.fI[nd.fI_off + i];
+    for (int i = threadIdx.x; i < nd.nB; i += blockDim.x) v[nd.nI + i] = a.y[dofs[nd.nI + i]];
+    __syncthreads();
+    for (int r = wv; r < nd.nI; r += 4) {
+      const double* row = a.front + nd.front_off + int64_t(r) * nd.n;
+      double acc = 0.0;
+      for (int k = lane; k < nd.n; k += 64) acc += row[k] * v[k];
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      if (lane == 0) a.y[dofs[r]] = -acc;
+    }
+    __syncthreads();
+  }
+}
+
+void launch_nd_fused_fwd(hipStream_t st, const NdArgs& a, int nroots, int nmax) {
+  hipLaunchKernelGGL(k_nd_fwd_fused, dim3(nroots), dim3(256), size_t(nmax) * 8, st, a);
+}
+
+void launch_nd_fused_bwd(hipStream_t st, const NdArgs& a, int nroots, int nmax) {
+  hipLaunchKernelGGL(k_nd_bwd_fused, dim3(nroots), dim3(256), size_t(nmax) * 8, st, a);
 }
 
 void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nmax, int nImax) {
@@ -237,17 +349,19 @@ void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int loff, int nnode
   const int tpd = (nmax + TILE - 1) / TILE;
   for (int kb = 0; kb < nblk; ++kb) {
     hipLaunchKernelGGL(k_nd_pivot, dim3(nnodes), dim3(256), 0, st, a, loff, kb);
+    hipLaunchKernelGGL(k_nd_rpanel, dim3(tpd, nnodes), dim3(256), 0, st, a, loff, kb);
     hipLaunchKernelGGL(k_nd_update, dim3(tpd * tpd, nnodes), dim3(256), 0, st, a, loff, kb);
   }
 }
 
 void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nmax, int nBmax) {
-  hipLaunchKernelGGL(k_nd_fwd_gather, dim3(nnodes), dim3(256), size_t(nmax) * 8, st, a, loff);
-  if (nBmax > 0) hipLaunchKernelGGL(k_nd_fwd_gemv, dim3((nBmax + 3) / 4, nnodes), dim3(256), 0, st, a, loff);
+  const int gx = std::max(1, (nBmax + 63) / 64);
+  hipLaunchKernelGGL(k_nd_fwd, dim3(gx, nnodes), dim3(256), size_t(nmax) * 8, st, a, loff);
 }
 
-void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax) {
-  hipLaunchKernelGGL(k_nd_bwd, dim3((nImax + 3) / 4, nnodes), dim3(256), 0, st, a, loff);
+void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nmax) {
+  const int rpb = 16;
+  hipLaunchKernelGGL(k_nd_bwd, dim3((nImax + rpb - 1) / rpb, nnodes), dim3(256), size_t(nmax) * 8, st, a, loff, rpb);
 }
 
 }  // namespace mpm

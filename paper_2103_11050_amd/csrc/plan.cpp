@@ -171,6 +171,35 @@ void build_plan(const mpm_desc& d, Plan* p) {
     P.level_nImax[n.level] = std::max(P.level_nImax[n.level], n.nI);
     P.level_nBmax[n.level] = std::max(P.level_nBmax[n.level], n.nB);
   }
+  // fused bottom levels
+  {
+    // measured: walking a subtree per workgroup is a latency chain slower than one launch per
+    // level, so no level is fused by default
+    P.fuse_level = 0;
+    std::vector<int> parent(P.nodes.size(), -1);
+    for (size_t i = 0; i < P.nodes.size(); ++i)
+      for (int c = 0; c < 2; ++c)
+        if (P.nodes[i].child[c] >= 0) parent[P.nodes[i].child[c]] = int(i);
+    P.fuse_off.assign(1, 0);
+    P.fuse_nodes.clear();
+    P.fuse_nmax = 0;
+    if (P.fuse_level) {
+      std::function<void(int)> collect = [&](int id) {
+        for (int c = 0; c < 2; ++c)
+          if (P.nodes[id].child[c] >= 0) collect(P.nodes[id].child[c]);
+        P.fuse_nodes.push_back(id);
+        P.fuse_nmax = std::max(P.fuse_nmax, int(P.nodes[id].n));
+      };
+      for (size_t i = 0; i < P.nodes.size(); ++i) {
+        const int L = P.nodes[i].level;
+        const int pl = parent[i] >= 0 ? P.nodes[parent[i]].level : 1 << 30;
+        if (L <= P.fuse_level && pl > P.fuse_level) {
+          collect(int(i));
+          P.fuse_off.push_back(int32_t(P.fuse_nodes.size()));
+        }
+      }
+    }
+  }
   // per-node storage
   int64_t fo = 0, io = 0, co = 0, po = 0;
   for (auto& n : P.nodes) {
@@ -204,6 +233,11 @@ void build_plan(const mpm_desc& d, Plan* p) {
   P.off_S = take(size_t(P.nsub) * P.nb * P.nb * 8);
   P.off_h = take(size_t(P.nsub) * P.nb * 8);
   P.off_vbnd = take(size_t(P.nsub) * P.nb * 8);
+  {
+    const int mf = P.band <= 8 ? 8 : 16;
+    P.off_dsE = take(size_t(P.nsub) * (P.nc / P.band) * mf * mf * 8);
+    P.off_nfac = take(size_t(P.nsub) * (P.nc / P.band) * mf * mf * 8);
+  }
   P.off_ubnd = take(size_t(P.nsub) * P.nb * 8);
   P.off_leafK = take(size_t(P.nsub) * P.ndmax * P.ndmax * 8);
   P.off_leafr = take(size_t(P.nsub) * P.ndmax * 8);
@@ -225,6 +259,8 @@ void build_plan(const mpm_desc& d, Plan* p) {
   }
   P.level_off[P.level_nodes.size()] = int32_t(P.level_flat.size());
   P.off_levels = take(std::max<size_t>(P.level_flat.size(), 1) * 4);
+  P.off_fuse_off = take(std::max<size_t>(P.fuse_off.size(), 1) * 4);
+  P.off_fuse_nodes = take(std::max<size_t>(P.fuse_nodes.size(), 1) * 4);
   const size_t blocks = (ncell + 255) / 256 + size_t(P.nsub) + 64;
   P.n_red = 4 * blocks;
   P.off_red = take(P.n_red * 8);

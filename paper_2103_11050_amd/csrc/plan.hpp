@@ -58,6 +58,14 @@ struct Plan {
   size_t off_nodes, off_dofpool, off_mappool, off_subdofs, off_subndof, off_levels;
   std::vector<int32_t> level_off;     // offsets of each level's node list in the uploaded level array
   std::vector<int32_t> level_flat;
+  // bottom levels 1..fuse_level are solved one subtree per workgroup: subtree roots are the
+  // nodes of level <= fuse_level whose parent lies above it
+  int fuse_level = 0;
+  int fuse_nmax = 0;
+  std::vector<int32_t> fuse_off;      // per subtree, offset into fuse_nodes (size roots+1)
+  std::vector<int32_t> fuse_nodes;    // subtree nodes, children before parents
+  size_t off_fuse_off = 0, off_fuse_nodes = 0;
+  size_t off_dsE = 0, off_nfac = 0;   // downscale inverse blocks: scratch and the kept kappa^m ones
   size_t off_red, off_scal;
   size_t n_red;               // doubles in the reduction scratch
   size_t total_bytes;
