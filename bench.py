@@ -8,11 +8,15 @@ log-normal permeability with log-variance 4 (seeded, synthetic), viscosity ratio
 The initial MRCM (Algorithm 1, first lines) and the warm-up steps are outside the timed
 region; inputs are resident in HBM before it starts.
 
-Prints one JSON line.
+Prints one JSON line. Extra modes: --copy-probe-mib (a plain device copy, to calibrate the
+HBM counters) and --make-traffic (builds the traffic record from rocprofv3 counter output).
 """
 from __future__ import annotations
 
 import argparse
+import collections
+import csv
+import hashlib
 import json
 import os
 import platform
@@ -26,36 +30,103 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_1024.json")
+# sources of the kernels each traffic record covers (the record is void once they change)
+KERNEL_SOURCES = {
+    "mpm_local": ["lines.hip", "lines.hpp", "device.hpp"],
+    "downscale": ["lines.hip", "lines.hpp", "device.hpp"],
+    "flux": ["local.hip", "device.hpp"],
+    "kappa_eps": ["local.hip"],
+    "sat_step": ["transport.hip", "device.hpp"],
+}
+# rocprofv3 kernel names -> kernel classes of the library's event profiler
+TRAFFIC_NAMES = {"k_mpm_local_lb": "mpm_local", "k_downscale_lb": "downscale", "k_flux": "flux",
+                 "k_kappa": "kappa_eps", "k_sat_step": "sat_step"}
 
 
 def algorithmic_bytes(cfg: dict) -> dict:
     """Bytes each kernel class must move per launch at this workload (FP64 path).
 
-    Cell fields are 8 B per cell, face fields 8 B per face. Per subdomain: the stored local
-    factor nc (b+1) doubles, the Robin-to-flux map nb^2 doubles, boundary vectors nb doubles.
+    Cell fields are 8 B per cell, face fields 8 B per face. Per subdomain: the kept line-block
+    inverses (lines x 16^2 doubles, lines padded to 8 or 16 cells), the Robin-to-flux map
+    nb^2 doubles, boundary vectors nb doubles (nb = 2 (mx + my)).
     """
     nx, ny, mx, my = cfg["nx"], cfg["ny"], cfg["sub_x"], cfg["sub_y"]
     nc = nx * ny
     nfaces = ny * (nx + 1) + (ny + 1) * nx
     nsub = (nx // mx) * (ny // my)
-    b = min(mx, my)
+    band = min(mx, my)
+    mf = 8 if band <= 8 else 16
+    blocks = 8.0 * nsub * (mx * my // band) * mf * mf
     nb = 2 * (mx + my)
     ndof = 4 * (cfg["ne_x"] + cfg["ne_y"])
     return {
         # s, K, kappa^m read; kappa^n written
         "kappa_eps": 32.0 * nc,
-        # s read, four face fluxes per cell (each face shared: ~2 faces per cell), s written
+        # s read, four face fluxes per cell (each face shared), s written
         "sat_step": 8.0 * nc + 8.0 * nfaces + 8.0 * nc,
-        # factor read; kappa^n, kappa^m, q read; u~^m read; h, v written; interface rhs written
-        "mpm_local": 8.0 * nsub * mx * my * (b + 1) + 24.0 * nc + 8.0 * nfaces + 16.0 * nsub * nb + 8.0 * nsub * ndof,
+        # kept blocks; kappa^n, kappa^m, q; u~^m; h and v written; interface rhs written
+        "mpm_local": blocks + 24.0 * nc + 8.0 * nfaces + 16.0 * nsub * nb + 8.0 * nsub * ndof,
         # Robin-to-flux map, h, v read; boundary fluxes written
         "flux": 8.0 * nsub * nb * nb + 24.0 * nsub * nb,
-        # kappa, q read; boundary fluxes read (own + neighbour); velocity written
-        "downscale": 16.0 * nc + 16.0 * nsub * nb + 8.0 * nfaces,
+        # kept blocks; kappa, q; boundary fluxes (own + neighbour); velocity written
+        "downscale": blocks + 16.0 * nc + 16.0 * nsub * nb + 8.0 * nfaces,
     }
 
 
-def roc_info():
+def source_hash(kernel: str) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kernel, []):
+        with open(os.path.join(ROOT, "paper_2103_11050_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter record, if it was taken on
+    the current source of that kernel; None otherwise."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or k.get("source_hash") != source_hash(kernel):
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
+
+
+def _per_kernel(path):
+    d = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"].split("(")[0].split("<")[0].replace("void ", "").replace("mpm::", "")
+        d[name].append(float(r["Counter_Value"]))
+    return d
+
+
+def make_traffic(fetch, write, cfetch, cwrite):
+    """Writes the traffic record from two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE) and the same counters on a plain device copy (--copy-probe-mib 256), which
+    calibrates KiB-per-dispatch to bytes."""
+    f, w = _per_kernel(fetch), _per_kernel(write)
+    cf, cw = _per_kernel(cfetch), _per_kernel(cwrite)
+    copy_bytes = 256 * (1 << 20)
+    kf = copy_bytes / (1024.0 * max(cf["__amd_rocclr_copyBuffer"]))
+    kw = copy_bytes / (1024.0 * max(cw["__amd_rocclr_copyBuffer"]))
+    out = {"calibration": {"copy_bytes": copy_bytes, "fetch_scale": kf, "write_scale": kw,
+                           "note": "bytes = counter KiB * 1024 * scale; scale from a plain copy"},
+           "kernels": {}}
+    for raw, name in TRAFFIC_NAMES.items():
+        if raw not in f:
+            continue
+        fv, wv = f[raw], w.get(raw, [0.0])
+        out["kernels"][name] = {
+            "fetch_bytes": sum(fv) / len(fv) * 1024 * kf, "write_bytes": sum(wv) / len(wv) * 1024 * kw,
+            "dispatches": len(fv), "source_hash": source_hash(name)}
+    json.dump(out, open(TRAFFIC_FILE, "w"), indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def host_cpu():
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
         model = [l.split(":", 1)[1].strip() for l in out.splitlines() if l.startswith("Model name")]
@@ -86,7 +157,7 @@ def cpu_baseline(cfg: dict, K: np.ndarray, steps: int = 3) -> dict:
     return {"value": rate_window * scale, "unit": "velocity updates/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle MPM-2P steps on the {w}x{w} corner window of the 1024^2 field "
                       f"({steps} steps after one MRCM update, {dt:.1f} s, 1 thread), rate scaled by the "
-                      f"cell ratio {scale:.4f}; host: {roc_info()}, {os.cpu_count()} logical CPUs"}
+                      f"cell ratio {scale:.4f}; host: {host_cpu()}, {os.cpu_count()} logical CPUs"}
 
 
 def main():
@@ -97,13 +168,30 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--make-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="build the traffic record from rocprofv3 --pmc outputs and exit")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.make_traffic:
+        make_traffic(*args.make_traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
               f"sharding is described in DESIGN.md but not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 8 * n, "launches": 5}))
+        return
 
     from paper_2103_11050_amd import binding, inputs
 
@@ -159,7 +247,7 @@ def main():
         ms = cand[dom][0]
         achieved = alg[dom] / (ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
                 "avg_ms": round(ms, 5), "algorithmic_bytes": alg[dom]}
     out = {
         "metric": "velocity updates/s (MRCM + MPM-2P) at 1024^2 cells; p50/p99 run latency; %roofline",

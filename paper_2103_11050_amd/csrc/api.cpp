@@ -65,7 +65,10 @@ struct mpm_run {
   double *K, *q, *s, *s2, *kn, *km, *ux, *uy, *uxm, *uym, *fac, *S, *h, *vbnd, *ubnd, *leafK, *leafr;
   double *front, *fI, *cB, *panel, *y, *red, *scal, *dsE, *nfac;
   int32_t* err;
+  int32_t* dsflag = nullptr;
   NdArgs nd{};
+  hipStream_t st2 = nullptr;           // second stream: factorisations overlapped with the solves
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   const int32_t* subdofs_d = nullptr;
   double fmax_deriv = 0.0;
   double M = 1.0;
@@ -181,7 +184,7 @@ void nd_solve(mpm_run* r) {
     for (int l = P.fuse_level + 1; l <= L; ++l) {
       const int nn = int(P.level_nodes[l].size());
       if (!nn) continue;
-      launch_nd_level_fwd(r->st, r->nd, P.level_off[l], nn, P.level_nmax[l], P.level_nBmax[l]);
+      launch_nd_level_fwd(r->st, r->nd, P.level_off[l], nn, P.level_nmax[l], P.level_nImax[l], P.level_nBmax[l]);
     }
   }
   {
@@ -213,8 +216,8 @@ void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store) {
   }
   {
     Scope sc(r, "downscale");
-    launch_downscale(r->st, r->g, kap_s, r->km, r->q, r->ubnd, r->ux, r->uy, r->red, r->red + r->P.nsub, r->dsE,
-                     r->nfac, store, r->err);
+    launch_downscale(r->st, r->g, kap_s, r->q, r->ubnd, r->ux, r->uy, r->red, r->red + r->P.nsub, r->dsE, r->nfac,
+                     r->dsflag, store, r->err);
   }
   {
     Scope sc(r, "dt");
@@ -246,11 +249,17 @@ mpm_status mrcm_update(mpm_run* r) {
 // MPM-2P: trivial-Robin solve with the stored kappa^m factors, interface solve with the stored
 // factorisation, reconstruction, downscaling with kappa^n.
 mpm_status mpm_update(mpm_run* r) {
+  // kappa^n Neumann factors of the changed subdomains on the second stream
+  HIPCHK(r, hipEventRecord(r->ev_fork, r->st));
+  HIPCHK(r, hipStreamWaitEvent(r->st2, r->ev_fork, 0));
+  launch_ds_factor(r->st2, r->g, r->kn, r->km, r->dsE, r->dsflag, r->err);
+  HIPCHK(r, hipEventRecord(r->ev_join, r->st2));
   {
     Scope sc(r, "mpm_local");
     launch_mpm_local(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac, r->h, r->vbnd, r->leafr);
   }
   nd_solve(r);
+  HIPCHK(r, hipStreamWaitEvent(r->st, r->ev_join, 0));
   finish_velocity(r, r->kn, 1, 0);
   return MPM_OK;
 }
@@ -355,6 +364,7 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   r->leafr = D(P.off_leafr); r->front = D(P.off_front); r->fI = D(P.off_fI); r->cB = D(P.off_cB);
   r->panel = D(P.off_panel); r->y = D(P.off_y); r->red = D(P.off_red); r->scal = D(P.off_scal);
   r->dsE = D(P.off_dsE); r->nfac = D(P.off_nfac);
+  r->dsflag = reinterpret_cast<int32_t*>(r->ws + P.off_dsflag);
   r->err = reinterpret_cast<int32_t*>(r->scal + SC_COUNT);
   r->subdofs_d = reinterpret_cast<const int32_t*>(r->ws + P.off_subdofs);
   r->nd.nodes = reinterpret_cast<const NodeDev*>(r->ws + P.off_nodes);
@@ -369,9 +379,21 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   r->M = P.d.mu_o / P.d.mu_w;
   r->fmax_deriv = max_fprime(r->M);
   r->area = P.d.lx * P.d.ly;
-  auto fail = [&](mpm_status s) { if (r->pinned) hipHostFree(r->pinned); delete r; return s; };
+  auto fail = [&](mpm_status s) {
+    if (r->pinned) hipHostFree(r->pinned);
+    if (r->ev_eps) hipEventDestroy(r->ev_eps);
+    if (r->ev_fork) hipEventDestroy(r->ev_fork);
+    if (r->ev_join) hipEventDestroy(r->ev_join);
+    if (r->st2) hipStreamDestroy(r->st2);
+    delete r;
+    return s;
+  };
   if (hipHostMalloc(reinterpret_cast<void**>(&r->pinned), 64, hipHostMallocDefault) != hipSuccess) return fail(MPM_ENOMEM);
   if (hipEventCreateWithFlags(&r->ev_eps, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
+  if (hipEventCreateWithFlags(&r->ev_fork, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
+  if (hipEventCreateWithFlags(&r->ev_join, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
+  // default priority (the same as the caller's stream)
+  if (hipStreamCreateWithFlags(&r->st2, hipStreamNonBlocking) != hipSuccess) return fail(MPM_EHIP);
   // upload the plan's index tables
   auto up = [&](size_t off, const void* src, size_t n) {
     return n ? hipMemcpyAsync(r->ws + off, src, n, hipMemcpyHostToDevice, r->st) : hipSuccess;
@@ -495,6 +517,9 @@ mpm_status mpm_destroy(mpm_run* r) {
   for (auto& p : r->pending) { hipEventDestroy(p.second.first); hipEventDestroy(p.second.second); }
   for (auto e : r->pool) hipEventDestroy(e);
   if (r->ev_eps) hipEventDestroy(r->ev_eps);
+  if (r->ev_fork) hipEventDestroy(r->ev_fork);
+  if (r->ev_join) hipEventDestroy(r->ev_join);
+  if (r->st2) { hipStreamSynchronize(r->st2); hipStreamDestroy(r->st2); }
   if (r->pinned) hipHostFree(r->pinned);
   delete r;
   if (errw & ERR_NOTSPD) return MPM_ENOTSPD;

@@ -21,11 +21,15 @@ void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const doub
                       double* leafr);
 void launch_flux(hipStream_t st, const Geo& g, const double* km, const double* S, const double* h,
                  const double* vbnd, const double* y, const int32_t* sub_dofs, double* ubnd, int with_v);
-// store = 1: kap_s is kappa^m; the inverse blocks are kept for later steps. store = 0: a
-// subdomain whose kap_s tile equals its kap_m tile reuses the kept blocks.
-void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* kap_m, const double* q,
-                      const double* ubnd, double* ux, double* uy, double* red_rate, double* red_qin, double* Escr,
-                      double* Ekeep, int store, int32_t* err);
+// Neumann inverse blocks of kappa^n for the subdomains whose conductivity tile differs from
+// kappa^m (into Escr, flag[sub] = 1), flag[sub] = 0 elsewhere.
+void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, const double* kap_m, double* Escr,
+                      int32_t* flag, int32_t* err);
+// store = 1: kap_s is kappa^m, its inverse blocks are formed here and kept (Ekeep).
+// store = 0: the blocks come from Escr where flag[sub] is set, else from Ekeep.
+void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
+                      double* ux, double* uy, double* red_rate, double* red_qin, double* Escr, double* Ekeep,
+                      const int32_t* flag, int store, int32_t* err);
 void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double cfl,
                double fmax_deriv, double* scal);
 
@@ -49,7 +53,7 @@ struct NdArgs {
   const int32_t* fuse_nodes;  // subtree nodes, children before parents
 };
 void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nmax, int nImax);
-void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nmax, int nBmax);
+void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nmax, int nImax, int nBmax);
 void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nImax, int nmax);
 void launch_nd_fused_fwd(hipStream_t st, const NdArgs& a, int nroots, int nmax);
 void launch_nd_fused_bwd(hipStream_t st, const NdArgs& a, int nroots, int nmax);

@@ -11,7 +11,6 @@ namespace mpm {
 
 namespace {
 
-constexpr int MSMAX = 16;   // lines per subdomain held in registers
 
 __device__ __forceinline__ int gcell2(const Geo& g, int I, int J, int i, int j) { return (J * g.my + j) * g.nx + I * g.mx + i; }
 
@@ -61,29 +60,79 @@ __device__ __forceinline__ void lb_solve(const Geo& g, const LineW& W, const LB<
   const int nl = g.nc / g.band;
   const int len = g.band;
   const bool rin = L.row < len;
+  // the next line's block is loaded while the current one is applied
+  double e[EPL], en[EPL];
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) e[t] = Es[size_t(t) * 64 + L.lane];
   double wprev = 0.0;
 #pragma unroll 1
   for (int ln = 0; ln < nl; ++ln) {
-    double e[EPL];
+    const int lnn = ln + 1 < nl ? ln + 1 : ln;
 #pragma unroll
-    for (int t = 0; t < EPL; ++t) e[t] = Es[(size_t(ln) * EPL + t) * 64 + L.lane];
+    for (int t = 0; t < EPL; ++t) en[t] = Es[(size_t(lnn) * EPL + t) * 64 + L.lane];
     double z = rin ? x[ln * len + L.row] : 0.0;
     if (ln > 0 && rin) z += W.y(ln - 1, L.row) * wprev;
     wprev = lb_matvec<MF>(L, e, z);
     if (L.cg == 0) w[ln * MF + L.row] = wprev;
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) e[t] = en[t];
   }
   double xnext = wprev;
   if (rin && L.cg == 0) x[(nl - 1) * len + L.row] = xnext;
+  if (nl >= 2) {
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) e[t] = Es[(size_t(nl - 2) * EPL + t) * 64 + L.lane];
+  }
 #pragma unroll 1
   for (int ln = nl - 2; ln >= 0; --ln) {
-    double e[EPL];
+    const int lnn = ln > 0 ? ln - 1 : 0;
 #pragma unroll
-    for (int t = 0; t < EPL; ++t) e[t] = Es[(size_t(ln) * EPL + t) * 64 + L.lane];
+    for (int t = 0; t < EPL; ++t) en[t] = Es[(size_t(lnn) * EPL + t) * 64 + L.lane];
     const double v = rin ? W.y(ln, L.row) * xnext : 0.0;
     xnext = w[ln * MF + L.row] + lb_matvec<MF>(L, e, v);
     if (rin && L.cg == 0) x[ln * len + L.row] = xnext;
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) e[t] = en[t];
   }
   __syncthreads();
+}
+
+// Same solve with a compile-time line count: all inverse blocks are loaded into registers at
+// once (every load in flight together) and serve both sweeps, so they are read from memory
+// once.
+template <int MF, int NL>
+__device__ __forceinline__ void lb_solve_reg(const LineW& W, const LB<MF>& L, const double* Es, double* x) {
+  constexpr int EPL = LB<MF>::EPL;
+  const int len = W.band;
+  const bool rin = L.row < len;
+  double E[NL][EPL];
+#pragma unroll
+  for (int ln = 0; ln < NL; ++ln)
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) E[ln][t] = Es[(size_t(ln) * EPL + t) * 64 + L.lane];
+  double w[NL];
+#pragma unroll
+  for (int ln = 0; ln < NL; ++ln) {
+    double z = rin ? x[ln * len + L.row] : 0.0;
+    if (ln > 0 && rin) z += W.y(ln - 1, L.row) * w[ln - 1];
+    w[ln] = lb_matvec<MF>(L, E[ln], z);
+  }
+  double xnext = w[NL - 1];
+  if (rin && L.cg == 0) x[(NL - 1) * len + L.row] = xnext;
+#pragma unroll
+  for (int ln = NL - 2; ln >= 0; --ln) {
+    const double v = rin ? W.y(ln, L.row) * xnext : 0.0;
+    xnext = w[ln] + lb_matvec<MF>(L, E[ln], v);
+    if (rin && L.cg == 0) x[ln * len + L.row] = xnext;
+  }
+  __syncthreads();
+}
+
+template <int MF, int NL>
+__device__ __forceinline__ void lb_solve_any(const Geo& g, const LineW& W, const LB<MF>& L, const double* Es,
+                                             double* x, double* w) {
+  if constexpr (NL > 0) lb_solve_reg<MF, NL>(W, L, Es, x);
+  else lb_solve<MF>(g, W, L, Es, x, w);
 }
 
 }  // namespace
@@ -112,7 +161,7 @@ __global__ void __launch_bounds__(64) k_line_factor(Geo g, const double* __restr
 // v_f = (t^n_f / t^m_f) u~^m_f; zero Dirichlet and Robin data. Outputs the boundary fluxes
 // h = W T delta p on Robin/Dirichlet faces, the boundary values of v and the interface
 // right-hand side B^T h.
-template <int MF>
+template <int MF, int NL>
 __global__ void __launch_bounds__(64)
 k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict__ kap_m,
                const double* __restrict__ uxm, const double* __restrict__ uym, const double* __restrict__ q,
@@ -176,7 +225,7 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
   __syncthreads();
   fill_trans(g, I, J, kl, 0, tE, tN, dg);
   const LineW W{tE, tN, dg, g.xfast, g.band, 0};
-  lb_solve<MF>(g, W, L, fac + efac_off<MF>(g, sub, 0, 0), x, wsh);
+  lb_solve_any<MF, NL>(g, W, L, fac + efac_off<MF>(g, sub, 0, 0), x, wsh);
   for (int f = threadIdx.x; f < nb; f += blockDim.x) {
     BFace bf = bface(g, I, J, f);
     const int gi = I * g.mx + bf.i, gj = J * g.my + bf.j;
@@ -188,12 +237,12 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
     hg[size_t(sub) * nb + f] = h;
     double v = 0.0;
     if (bf.kind != FACE_NEU) {
-      double u, dd;
+      double u;
       int nbr;
-      if (bf.side == 0) { u = -uxm[gj * (g.nx + 1) + gi]; nbr = gi > 0 ? gc - 1 : -1; dd = g.hx; }
-      else if (bf.side == 1) { u = uxm[gj * (g.nx + 1) + gi + 1]; nbr = gi < g.nx - 1 ? gc + 1 : -1; dd = g.hx; }
-      else if (bf.side == 2) { u = -uym[gj * g.nx + gi]; nbr = gj > 0 ? gc - g.nx : -1; dd = g.hy; }
-      else { u = uym[(gj + 1) * g.nx + gi]; nbr = gj < g.ny - 1 ? gc + g.nx : -1; dd = g.hy; }
+      if (bf.side == 0) { u = -uxm[gj * (g.nx + 1) + gi]; nbr = gi > 0 ? gc - 1 : -1; }
+      else if (bf.side == 1) { u = uxm[gj * (g.nx + 1) + gi + 1]; nbr = gi < g.nx - 1 ? gc + 1 : -1; }
+      else if (bf.side == 2) { u = -uym[gj * g.nx + gi]; nbr = gj > 0 ? gc - g.nx : -1; }
+      else { u = uym[(gj + 1) * g.nx + gi]; nbr = gj < g.ny - 1 ? gc + g.nx : -1; }
       const double ratio = nbr >= 0 ? harm_ratio(kn, kap_n[nbr], km, kap_m[nbr]) : kn / km;
       v = ratio * u;
     }
@@ -220,14 +269,13 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
 // mean of both sides' boundary fluxes on Gamma, the own flux on the physical boundary, the
 // first cell pinned. Writes the velocity on the faces the subdomain owns, the largest outflow
 // rate per cell volume and the inflow through the physical boundary.
-template <int MF>
+template <int MF, int NL>
 __global__ void __launch_bounds__(64)
-k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict__ kap_m,
-               const double* __restrict__ q, const double* __restrict__ ubnd, double* __restrict__ ux,
-               double* __restrict__ uy, double* __restrict__ red_rate, double* __restrict__ red_qin,
-               double* __restrict__ Escr, double* __restrict__ Ekeep, int store, int32_t* err) {
+k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict__ q,
+               const double* __restrict__ ubnd, double* __restrict__ ux, double* __restrict__ uy,
+               double* __restrict__ red_rate, double* __restrict__ red_qin, double* __restrict__ Escr,
+               double* __restrict__ Ekeep, const int32_t* __restrict__ flag, int store, int32_t* err) {
   __shared__ double kl[256], x[256], w[64], scratch[128], wsh[256], tE[256], tN[256], dg[256];
-  __shared__ int changed;
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int n = g.nc, nb = g.nb;
@@ -260,34 +308,14 @@ k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict
   __syncthreads();
   fill_trans(g, I, J, kl, 1, tE, tN, dg);
   const LineW W{tE, tN, dg, g.xfast, g.band, 1};
-  // the kept kappa^m blocks are exact for a subdomain whose conductivity has not changed
-  if (threadIdx.x == 0) changed = 0;
-  __syncthreads();
-  if (!store) {
-    bool diff = false;
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-      int i, j;
-      loc_ij(g, c, &i, &j);
-      diff = diff || (kl[c] != kap_m[gcell2(g, I, J, i, j)]);
-    }
-    if (diff) changed = 1;
-  }
-  __syncthreads();
   const size_t eoff = efac_off<MF>(g, sub, 0, 0);
-  double* Es;
+  double* Es = (!store && flag[sub]) ? Escr + eoff : Ekeep + eoff;
   if (store) {
-    Es = Ekeep + eoff;
-  } else if (changed) {
-    Es = Escr + eoff;
-  } else {
-    Es = Ekeep + eoff;
-  }
-  if (store || changed) {
     bool ok = true;
     lb_factor<MF>(g, W, L, Es, ok);
     if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
   }
-  lb_solve<MF>(g, W, L, Es, x, wsh);
+  lb_solve_any<MF, NL>(g, W, L, Es, x, wsh);
   double rate = 0.0;
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     int i, j;
@@ -328,6 +356,41 @@ k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict
 }
 
 // ---------------------------------------------------------------------------------------------
+// Neumann inverse blocks of kappa^n where the subdomain's conductivity tile changed since the
+// last MRCM update (elsewhere the kept kappa^m blocks are exact). Runs on a second stream,
+// overlapped with the MPM-2P local and interface solves.
+template <int MF>
+__global__ void __launch_bounds__(64)
+k_ds_factor(Geo g, const double* __restrict__ kap_n, const double* __restrict__ kap_m, double* __restrict__ Escr,
+            int32_t* __restrict__ flag, int32_t* err) {
+  __shared__ double kl[256], tE[256], tN[256], dg[256];
+  __shared__ int changed;
+  const int sub = blockIdx.x;
+  const int I = sub % g.Sx, J = sub / g.Sx;
+  LB<MF> L;
+  if (threadIdx.x == 0) changed = 0;
+  __syncthreads();
+  bool diff = false;
+  for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
+    int i, j;
+    loc_ij(g, c, &i, &j);
+    const int gc = gcell2(g, I, J, i, j);
+    const double kn = kap_n[gc];
+    kl[c] = kn;
+    diff = diff || (kn != kap_m[gc]);
+  }
+  if (diff) changed = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) flag[sub] = changed;
+  if (!changed) return;
+  fill_trans(g, I, J, kl, 1, tE, tN, dg);
+  const LineW W{tE, tN, dg, g.xfast, g.band, 1};
+  bool ok = true;
+  lb_factor<MF>(g, W, L, Escr + efac_off<MF>(g, sub, 0, 0), ok);
+  if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
+}
+
+// ---------------------------------------------------------------------------------------------
 
 static int line_mf(const Geo& g) { return g.band <= 8 ? 8 : 16; }
 
@@ -336,24 +399,36 @@ void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double*
   else hipLaunchKernelGGL(k_line_factor<16>, dim3(g.nsub), dim3(64), 0, st, g, kap, fac, err);
 }
 
+// line length padded to MF in {8, 16}; the solve keeps the blocks in registers for the
+// common line counts 8 and 16
+#define MPM_LB_DISPATCH(KERNEL, ...)                                                             \
+  do {                                                                                           \
+    const int nl_ = g.nc / g.band;                                                               \
+    if (line_mf(g) == 8) {                                                                       \
+      if (nl_ == 8) hipLaunchKernelGGL((KERNEL<8, 8>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__);   \
+      else hipLaunchKernelGGL((KERNEL<8, 0>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__);            \
+    } else {                                                                                     \
+      if (nl_ == 16) hipLaunchKernelGGL((KERNEL<16, 16>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__); \
+      else hipLaunchKernelGGL((KERNEL<16, 0>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__);           \
+    }                                                                                            \
+  } while (0)
+
 void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                       const double* uym, const double* q, const double* fac, double* h, double* vbnd,
                       double* leafr) {
-  if (line_mf(g) == 8)
-    hipLaunchKernelGGL(k_mpm_local_lb<8>, dim3(g.nsub), dim3(64), 0, st, g, kn, km, uxm, uym, q, fac, h, vbnd, leafr);
-  else
-    hipLaunchKernelGGL(k_mpm_local_lb<16>, dim3(g.nsub), dim3(64), 0, st, g, kn, km, uxm, uym, q, fac, h, vbnd, leafr);
+  MPM_LB_DISPATCH(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, leafr);
 }
 
-void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* kap_m, const double* q,
-                      const double* ubnd, double* ux, double* uy, double* red_rate, double* red_qin, double* Escr,
-                      double* Ekeep, int store, int32_t* err) {
-  if (line_mf(g) == 8)
-    hipLaunchKernelGGL(k_downscale_lb<8>, dim3(g.nsub), dim3(64), 0, st, g, kap_s, kap_m, q, ubnd, ux, uy, red_rate,
-                       red_qin, Escr, Ekeep, store, err);
-  else
-    hipLaunchKernelGGL(k_downscale_lb<16>, dim3(g.nsub), dim3(64), 0, st, g, kap_s, kap_m, q, ubnd, ux, uy, red_rate,
-                       red_qin, Escr, Ekeep, store, err);
+void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, const double* kap_m, double* Escr,
+                      int32_t* flag, int32_t* err) {
+  if (line_mf(g) == 8) hipLaunchKernelGGL(k_ds_factor<8>, dim3(g.nsub), dim3(64), 0, st, g, kap_n, kap_m, Escr, flag, err);
+  else hipLaunchKernelGGL(k_ds_factor<16>, dim3(g.nsub), dim3(64), 0, st, g, kap_n, kap_m, Escr, flag, err);
+}
+
+void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
+                      double* ux, double* uy, double* red_rate, double* red_qin, double* Escr, double* Ekeep,
+                      const int32_t* flag, int store, int32_t* err) {
+  MPM_LB_DISPATCH(k_downscale_lb, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, Escr, Ekeep, flag, store, err);
 }
 
 size_t line_factor_doubles(int nsub, int nc, int band) {

@@ -208,17 +208,15 @@ __global__ void __launch_bounds__(256) k_nd_update(NdArgs a, int loff, int kb) {
   }
 }
 
-// Forward, one level: every workgroup gathers its node's front right-hand side f (children's
-// condensed vectors, child 0 then child 1) into LDS, then computes 64 entries of
-// c_B = f_B - BI f_I. BI = IB^T is read from the node's I rows (row-major, so consecutive
-// lanes read consecutive columns); the four waves split the I range and their partial sums
-// are added in a fixed order. Workgroup 0 of each node also stores f_I for the backward pass.
-__global__ void __launch_bounds__(256) k_nd_fwd(NdArgs a, int loff) {
+// Forward, one level. Every workgroup gathers its node's front right-hand side f (children's
+// condensed vectors, child 0 then child 1) into LDS; workgroup 0 stores f_I for the backward
+// pass; then groups of G lanes form c_B[j] = f_B[j] - (BI f_I)[j] for rows j of the stored BI
+// block (row-major, so each group reads one contiguous row).
+__global__ void __launch_bounds__(256) k_nd_fwd(NdArgs a, int loff, int G, int rows_per_block) {
   extern __shared__ double f[];
-  __shared__ double part[4][64];
   const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
-  const int j0 = blockIdx.x * 64;
-  if (j0 >= max(nd.nB, 1)) return;
+  const int r0 = blockIdx.x * rows_per_block;
+  if (r0 >= max(nd.nB, 1)) return;
   for (int i = threadIdx.x; i < nd.n; i += blockDim.x) f[i] = 0.0;
   __syncthreads();
   for (int c = 0; c < 2; ++c) {
@@ -229,32 +227,26 @@ __global__ void __launch_bounds__(256) k_nd_fwd(NdArgs a, int loff) {
   }
   if (blockIdx.x == 0)
     for (int i = threadIdx.x; i < nd.nI; i += blockDim.x) a.fI[nd.fI_off + i] = f[i];
-  if (nd.nB == 0) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int j = j0 + lane;
-  double acc = 0.0;
-  if (j < nd.nB) {
-    // 8 independent row loads in flight per wave
-    const double* col = a.front + nd.front_off + nd.nI + j;
-    const int64_t n = nd.n;
-    double acc8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int i = wv;
-    for (; i + 28 < nd.nI; i += 32) {
+  const int gl = threadIdx.x % G, grp = threadIdx.x / G;
+  const int r1 = min(nd.nB, r0 + rows_per_block);
+  for (int j = r0 + grp; j < r1; j += 256 / G) {
+    const double* row = a.front + nd.front_off + int64_t(nd.nI + j) * nd.n;
+    double acc4[4] = {0, 0, 0, 0};
+    int k = gl;
+    for (; k + 3 * G < nd.nI; k += 4 * G) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc8[u] += col[int64_t(i + 4 * u) * n] * f[i + 4 * u];
+      for (int u = 0; u < 4; ++u) acc4[u] += row[k + u * G] * f[k + u * G];
     }
-    for (; i < nd.nI; i += 4) acc8[0] += col[int64_t(i) * n] * f[i];
-    acc = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
+    for (; k < nd.nI; k += G) acc4[0] += row[k] * f[k];
+    double acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (gl == 0) a.cB[nd.cB_off + j] = f[nd.nI + j] - acc;
   }
-  part[wv][lane] = acc;
-  __syncthreads();
-  if (wv == 0 && j < nd.nB)
-    a.cB[nd.cB_off + j] = f[nd.nI + j] - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
 }
 
 // Backward, one level: v = [f_I; x_B] in LDS (x_B gathered from the solution by the node's
-// unknown list), then x_I = -[II IB] v, one wavefront per row, rows split over workgroups.
-__global__ void __launch_bounds__(256) k_nd_bwd(NdArgs a, int loff, int rows_per_block) {
+// unknown list), then x_I = -[II IB] v, one group of G lanes per row.
+__global__ void __launch_bounds__(256) k_nd_bwd(NdArgs a, int loff, int G, int rows_per_block) {
   extern __shared__ double v[];
   const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
   const int r0 = blockIdx.x * rows_per_block;
@@ -263,20 +255,20 @@ __global__ void __launch_bounds__(256) k_nd_bwd(NdArgs a, int loff, int rows_per
   for (int i = threadIdx.x; i < nd.nI; i += blockDim.x) v[i] = a.fI[nd.fI_off + i];
   for (int i = threadIdx.x; i < nd.nB; i += blockDim.x) v[nd.nI + i] = a.y[dofs[nd.nI + i]];
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int gl = threadIdx.x % G, grp = threadIdx.x / G;
   const int r1 = min(nd.nI, r0 + rows_per_block);
-  for (int r = r0 + wv; r < r1; r += 4) {
+  for (int r = r0 + grp; r < r1; r += 256 / G) {
     const double* row = a.front + nd.front_off + int64_t(r) * nd.n;
-    double acc8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int k = lane;
-    for (; k + 448 < nd.n; k += 512) {
+    double acc4[4] = {0, 0, 0, 0};
+    int k = gl;
+    for (; k + 3 * G < nd.n; k += 4 * G) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc8[u] += row[k + 64 * u] * v[k + 64 * u];
+      for (int u = 0; u < 4; ++u) acc4[u] += row[k + u * G] * v[k + u * G];
     }
-    for (; k < nd.n; k += 64) acc8[0] += row[k] * v[k];
-    double acc = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) + ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (lane == 0) a.y[dofs[r]] = -acc;
+    for (; k < nd.n; k += G) acc4[0] += row[k] * v[k];
+    double acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (gl == 0) a.y[dofs[r]] = -acc;
   }
 }
 
@@ -354,14 +346,27 @@ void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int loff, int nnode
   }
 }
 
-void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nmax, int nBmax) {
-  const int gx = std::max(1, (nBmax + 63) / 64);
-  hipLaunchKernelGGL(k_nd_fwd, dim3(gx, nnodes), dim3(256), size_t(nmax) * 8, st, a, loff);
+static int group_for(int len) { return len <= 48 ? 16 : (len <= 96 ? 32 : 64); }
+
+// Rows per workgroup: a multiple of the rows one pass covers, sized for ~2048 workgroups.
+static int rows_per_block(int nrows, int nnodes, int G) {
+  const int per_pass = 256 / G;
+  const int wg_per_node = std::max(1, std::min((nrows + per_pass - 1) / per_pass, (2048 + nnodes - 1) / nnodes));
+  const int rpb = (nrows + wg_per_node - 1) / wg_per_node;
+  return std::max(per_pass, (rpb + per_pass - 1) / per_pass * per_pass);
+}
+
+void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nmax, int nImax, int nBmax) {
+  const int G = group_for(nImax);
+  const int rpb = rows_per_block(std::max(nBmax, 1), nnodes, G);
+  const int gx = std::max(1, (nBmax + rpb - 1) / rpb);
+  hipLaunchKernelGGL(k_nd_fwd, dim3(gx, nnodes), dim3(256), size_t(nmax) * 8, st, a, loff, G, rpb);
 }
 
 void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nmax) {
-  const int rpb = 16;
-  hipLaunchKernelGGL(k_nd_bwd, dim3((nImax + rpb - 1) / rpb, nnodes), dim3(256), size_t(nmax) * 8, st, a, loff, rpb);
+  const int G = group_for(nmax);
+  const int rpb = rows_per_block(nImax, nnodes, G);
+  hipLaunchKernelGGL(k_nd_bwd, dim3((nImax + rpb - 1) / rpb, nnodes), dim3(256), size_t(nmax) * 8, st, a, loff, G, rpb);
 }
 
 }  // namespace mpm

@@ -237,6 +237,7 @@ void build_plan(const mpm_desc& d, Plan* p) {
     const int mf = P.band <= 8 ? 8 : 16;
     P.off_dsE = take(size_t(P.nsub) * (P.nc / P.band) * mf * mf * 8);
     P.off_nfac = take(size_t(P.nsub) * (P.nc / P.band) * mf * mf * 8);
+    P.off_dsflag = take(size_t(P.nsub) * 4);
   }
   P.off_ubnd = take(size_t(P.nsub) * P.nb * 8);
   P.off_leafK = take(size_t(P.nsub) * P.ndmax * P.ndmax * 8);

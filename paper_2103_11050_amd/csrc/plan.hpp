@@ -66,6 +66,7 @@ struct Plan {
   std::vector<int32_t> fuse_nodes;    // subtree nodes, children before parents
   size_t off_fuse_off = 0, off_fuse_nodes = 0;
   size_t off_dsE = 0, off_nfac = 0;   // downscale inverse blocks: scratch and the kept kappa^m ones
+  size_t off_dsflag = 0;              // per subdomain: conductivity changed since the last update
   size_t off_red, off_scal;
   size_t n_red;               // doubles in the reduction scratch
   size_t total_bytes;
