@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -59,7 +60,15 @@ struct ProfEntry {
 struct mpm_run {
   Plan P;
   Geo g;
-  hipStream_t st = nullptr;
+  hipStream_t st = nullptr;            // the library's stream (all work)
+  hipStream_t ust = nullptr;           // the caller's stream (ordering only)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // the MPM-2P step replayed as two graphs: transport sub-steps + kappa/epsilon (one per
+  // parity of the saturation double buffer), and the MPM-2P velocity update
+  bool use_graphs = true;
+  hipGraphExec_t g_trans[2] = {nullptr, nullptr};
+  hipGraphExec_t g_mpm = nullptr;
+  double* s_base = nullptr;
   int device = 0;
   char* ws = nullptr;
   double *K, *q, *s, *s2, *kn, *km, *ux, *uy, *uxm, *uym, *fac, *S, *h, *vbnd, *ubnd, *leafK, *leafr;
@@ -162,16 +171,59 @@ double eps_from(const mpm_run* r, double num, double den) {
   return std::sqrt(num) / std::sqrt(den);
 }
 
-// kappa^n = lambda(s) K and the partial sums of epsilon against kappa^m; copies the two sums
-// to pinned host memory and records an event.
-mpm_status kappa_and_eps(mpm_run* r) {
+// kappa^n = lambda(s) K and the partial sums of epsilon against kappa^m, copied to pinned host
+// memory (the caller records ev_eps after it).
+mpm_status kappa_and_eps_nodes(mpm_run* r) {
   {
     Scope sc(r, "kappa_eps");
     launch_kappa(r->st, r->P.nx * r->P.ny, r->s, r->K, r->kn, r->km, r->P.d.mu_w, r->P.d.mu_o, r->red, r->scal);
   }
   HIPCHK(r, hipMemcpyAsync(r->pinned, r->scal + SC_EPS_NUM, 2 * sizeof(double), hipMemcpyDeviceToHost, r->st));
+  return MPM_OK;
+}
+
+mpm_status kappa_and_eps(mpm_run* r) {
+  mpm_status st = kappa_and_eps_nodes(r);
+  if (st) return st;
   HIPCHK(r, hipEventRecord(r->ev_eps, r->st));
   return MPM_OK;
+}
+
+// Work of the caller's stream before a call is ordered before the library's, and the library's
+// before the caller's later work.
+mpm_status enter(mpm_run* r) {
+  if (r->st == r->ust) return MPM_OK;
+  HIPCHK(r, hipEventRecord(r->ev_in, r->ust));
+  HIPCHK(r, hipStreamWaitEvent(r->st, r->ev_in, 0));
+  return MPM_OK;
+}
+mpm_status leave(mpm_run* r, mpm_status st) {
+  if (r->st == r->ust) return st;
+  if (hipEventRecord(r->ev_out, r->st) != hipSuccess || hipStreamWaitEvent(r->ust, r->ev_out, 0) != hipSuccess)
+    return st ? st : MPM_EHIP;
+  return st;
+}
+
+// Captures what body() enqueues on the library's stream into an executable graph, then
+// launches it once. Returns nullptr (and enqueues nothing) if capture is not available.
+template <class F>
+hipGraphExec_t capture_and_launch(mpm_run* r, F&& body) {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (hipStreamBeginCapture(r->st, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+  const mpm_status st = body();
+  const hipError_t e = hipStreamEndCapture(r->st, &graph);
+  if (st != MPM_OK || e != hipSuccess || !graph) {
+    if (graph) hipGraphDestroy(graph);
+    return nullptr;
+  }
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
+  hipGraphDestroy(graph);
+  if (exec && hipGraphLaunch(exec, r->st) != hipSuccess) {
+    hipGraphExecDestroy(exec);
+    exec = nullptr;
+  }
+  return exec;
 }
 
 void nd_solve(mpm_run* r) {
@@ -248,7 +300,7 @@ mpm_status mrcm_update(mpm_run* r) {
 
 // MPM-2P: trivial-Robin solve with the stored kappa^m factors, interface solve with the stored
 // factorisation, reconstruction, downscaling with kappa^n.
-mpm_status mpm_update(mpm_run* r) {
+mpm_status mpm_update_body(mpm_run* r) {
   // kappa^n Neumann factors of the changed subdomains on the second stream
   HIPCHK(r, hipEventRecord(r->ev_fork, r->st));
   HIPCHK(r, hipStreamWaitEvent(r->st2, r->ev_fork, 0));
@@ -264,9 +316,23 @@ mpm_status mpm_update(mpm_run* r) {
   return MPM_OK;
 }
 
-mpm_status velocity_update(mpm_run* r, int32_t force) {
+mpm_status mpm_update(mpm_run* r) {
+  if (r->use_graphs && !r->prof) {
+    if (r->g_mpm) {
+      HIPCHK(r, hipGraphLaunch(r->g_mpm, r->st));
+      return MPM_OK;
+    }
+    r->g_mpm = capture_and_launch(r, [&] { return mpm_update_body(r); });
+    if (r->g_mpm) return MPM_OK;
+    r->use_graphs = false;   // capture unavailable: stay eager
+  }
+  return mpm_update_body(r);
+}
+
+mpm_status velocity_update(mpm_run* r, int32_t force, bool kappa_done = false) {
   // decision (Algorithm 1: "if epsilon > eta")
-  mpm_status st = kappa_and_eps(r);
+  mpm_status st = MPM_OK;
+  if (!kappa_done) st = kappa_and_eps(r);
   if (st) return st;
   double decide;
   if (r->P.d.switch_rule == MPM_SWITCH_TEXT) {
@@ -301,7 +367,7 @@ mpm_status velocity_update(mpm_run* r, int32_t force) {
   return MPM_OK;
 }
 
-mpm_status transport(mpm_run* r, int32_t nsteps) {
+mpm_status transport_body(mpm_run* r, int32_t nsteps) {
   for (int k = 0; k < nsteps; ++k) {
     Scope sc(r, "sat_step");
     launch_sat_step(r->st, r->g, r->s, r->s2, r->ux, r->uy, r->scal, r->M, r->area);
@@ -311,8 +377,48 @@ mpm_status transport(mpm_run* r, int32_t nsteps) {
     Scope sc(r, "water_cut");
     launch_water_cut(r->st, r->g, r->s, r->ux, r->uy, r->scal, r->M);
   }
-  r->ntr += nsteps;
   return MPM_OK;
+}
+
+mpm_status transport(mpm_run* r, int32_t nsteps) {
+  mpm_status st = transport_body(r, nsteps);
+  r->ntr += nsteps;
+  return st;
+}
+
+// One pass of Algorithm 1's while loop. With graphs, the C_n transport sub-steps and kappa^n
+// are one graph (per parity of the saturation buffers) and the MPM-2P update another.
+mpm_status step(mpm_run* r, int32_t force) {
+  if (!(r->use_graphs && !r->prof)) {
+    mpm_status st = transport(r, r->P.d.cn);
+    if (st) return st;
+    return velocity_update(r, force);
+  }
+  const int par = r->s == r->s_base ? 0 : 1;
+  const int cn = r->P.d.cn;
+  if (r->g_trans[par]) {
+    HIPCHK(r, hipGraphLaunch(r->g_trans[par], r->st));
+    for (int k = 0; k < cn; ++k) std::swap(r->s, r->s2);
+  } else {
+    double* s0 = r->s;
+    double* s1 = r->s2;
+    r->g_trans[par] = capture_and_launch(r, [&] {
+      mpm_status st = transport_body(r, cn);
+      if (st) return st;
+      return kappa_and_eps_nodes(r);
+    });
+    if (!r->g_trans[par]) {
+      r->s = s0;
+      r->s2 = s1;
+      r->use_graphs = false;
+      mpm_status st = transport(r, cn);
+      if (st) return st;
+      return velocity_update(r, force);
+    }
+  }
+  r->ntr += cn;
+  HIPCHK(r, hipEventRecord(r->ev_eps, r->st));
+  return velocity_update(r, force, true);
 }
 
 }  // namespace
@@ -353,7 +459,7 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   if (bytes < r->P.total_bytes) { delete r; return MPM_ENOMEM; }
   const Plan& P = r->P;
   r->g = make_geo(P);
-  r->st = static_cast<hipStream_t>(hip_stream);
+  r->ust = static_cast<hipStream_t>(hip_stream);
   hipGetDevice(&r->device);
   r->ws = static_cast<char*>(dev_workspace);
   auto D = [&](size_t off) { return reinterpret_cast<double*>(r->ws + off); };
@@ -364,6 +470,7 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   r->leafr = D(P.off_leafr); r->front = D(P.off_front); r->fI = D(P.off_fI); r->cB = D(P.off_cB);
   r->panel = D(P.off_panel); r->y = D(P.off_y); r->red = D(P.off_red); r->scal = D(P.off_scal);
   r->dsE = D(P.off_dsE); r->nfac = D(P.off_nfac);
+  r->s_base = r->s;
   r->dsflag = reinterpret_cast<int32_t*>(r->ws + P.off_dsflag);
   r->err = reinterpret_cast<int32_t*>(r->scal + SC_COUNT);
   r->subdofs_d = reinterpret_cast<const int32_t*>(r->ws + P.off_subdofs);
@@ -384,7 +491,10 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
     if (r->ev_eps) hipEventDestroy(r->ev_eps);
     if (r->ev_fork) hipEventDestroy(r->ev_fork);
     if (r->ev_join) hipEventDestroy(r->ev_join);
+    if (r->ev_in) hipEventDestroy(r->ev_in);
+    if (r->ev_out) hipEventDestroy(r->ev_out);
     if (r->st2) hipStreamDestroy(r->st2);
+    if (r->st && r->st != r->ust) hipStreamDestroy(r->st);
     delete r;
     return s;
   };
@@ -392,8 +502,23 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   if (hipEventCreateWithFlags(&r->ev_eps, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
   if (hipEventCreateWithFlags(&r->ev_fork, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
   if (hipEventCreateWithFlags(&r->ev_join, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
-  // default priority (the same as the caller's stream)
+  if (hipEventCreateWithFlags(&r->ev_in, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
+  if (hipEventCreateWithFlags(&r->ev_out, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
+  // Graph replay is opt-in: on gfx950 it measured slower than eager launches for this step.
+  // With graphs the work runs on a stream of the library's own (capture needs one), ordered
+  // against the caller's stream by events; without, it runs on the caller's stream.
+  {
+    const char* e = std::getenv("MPM2P_GRAPHS");
+    r->use_graphs = e && e[0] && e[0] != '0';
+  }
+  // the library's streams, default priority
+  if (r->use_graphs) {
+    if (hipStreamCreateWithFlags(&r->st, hipStreamNonBlocking) != hipSuccess) return fail(MPM_EHIP);
+  } else {
+    r->st = r->ust;
+  }
   if (hipStreamCreateWithFlags(&r->st2, hipStreamNonBlocking) != hipSuccess) return fail(MPM_EHIP);
+  if (hipStreamSynchronize(r->ust) != hipSuccess) return fail(MPM_EHIP);
   // upload the plan's index tables
   auto up = [&](size_t off, const void* src, size_t n) {
     return n ? hipMemcpyAsync(r->ws + off, src, n, hipMemcpyHostToDevice, r->st) : hipSuccess;
@@ -416,12 +541,19 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
 
 mpm_status mpm_set_fields(mpm_run* r, const double* K, const double* q, const double* s0) {
   if (!r || !K || !s0) return MPM_EINVAL;
+  mpm_status st = enter(r);
+  if (st) return st;
   const size_t nb = size_t(r->P.nx) * r->P.ny * 8;
-  HIPCHK(r, hipMemcpyAsync(r->K, K, nb, hipMemcpyDeviceToDevice, r->st));
-  if (q) HIPCHK(r, hipMemcpyAsync(r->q, q, nb, hipMemcpyDeviceToDevice, r->st));
-  else HIPCHK(r, hipMemsetAsync(r->q, 0, nb, r->st));
-  HIPCHK(r, hipMemcpyAsync(r->s, s0, nb, hipMemcpyDeviceToDevice, r->st));
-  HIPCHK(r, hipMemsetAsync(r->km, 0, nb, r->st));
+  auto body = [&]() -> mpm_status {
+    HIPCHK(r, hipMemcpyAsync(r->K, K, nb, hipMemcpyDeviceToDevice, r->st));
+    if (q) HIPCHK(r, hipMemcpyAsync(r->q, q, nb, hipMemcpyDeviceToDevice, r->st));
+    else HIPCHK(r, hipMemsetAsync(r->q, 0, nb, r->st));
+    HIPCHK(r, hipMemcpyAsync(r->s, s0, nb, hipMemcpyDeviceToDevice, r->st));
+    HIPCHK(r, hipMemsetAsync(r->km, 0, nb, r->st));
+    return MPM_OK;
+  };
+  st = leave(r, body());
+  if (st) return st;
   r->fields = true;
   r->started = false;
   return MPM_OK;
@@ -430,12 +562,17 @@ mpm_status mpm_set_fields(mpm_run* r, const double* K, const double* q, const do
 mpm_status mpm_start(mpm_run* r) {
   if (!r) return MPM_EINVAL;
   if (!r->fields || r->poisoned) return MPM_ESTATE;
-  // Algorithm 1, lines 1-4
-  HIPCHK(r, hipMemsetAsync(r->scal, 0, SC_COUNT * 8, r->st));
-  mpm_status st = kappa_and_eps(r);
+  mpm_status st = enter(r);
   if (st) return st;
-  r->te = 0; r->tm = 0; r->ntr = 0;
-  st = mrcm_update(r);
+  // Algorithm 1, lines 1-4
+  auto body = [&]() -> mpm_status {
+    HIPCHK(r, hipMemsetAsync(r->scal, 0, SC_COUNT * 8, r->st));
+    mpm_status s2 = kappa_and_eps(r);
+    if (s2) return s2;
+    r->te = 0; r->tm = 0; r->ntr = 0;
+    return mrcm_update(r);
+  };
+  st = leave(r, body());
   if (st) return st;
   r->te = 1;
   r->eps_prev = r->P.d.eta;
@@ -448,36 +585,50 @@ mpm_status mpm_start(mpm_run* r) {
 mpm_status mpm_transport(mpm_run* r, int32_t nsteps) {
   if (!r || nsteps < 0) return MPM_EINVAL;
   if (!r->started || r->poisoned) return MPM_ESTATE;
-  return transport(r, nsteps);
+  mpm_status st = enter(r);
+  if (st) return st;
+  return leave(r, transport(r, nsteps));
 }
 
 mpm_status mpm_velocity_update(mpm_run* r, int32_t force) {
   if (!r || force < -1 || force > 1) return MPM_EINVAL;
   if (!r->started || r->poisoned) return MPM_ESTATE;
-  return velocity_update(r, force);
+  mpm_status st = enter(r);
+  if (st) return st;
+  return leave(r, velocity_update(r, force));
 }
 
 mpm_status mpm_step(mpm_run* r, int32_t force) {
   if (!r || force < -1 || force > 1) return MPM_EINVAL;
   if (!r->started || r->poisoned) return MPM_ESTATE;
-  mpm_status st = transport(r, r->P.d.cn);
+  mpm_status st = enter(r);
   if (st) return st;
-  return velocity_update(r, force);
+  return leave(r, step(r, force));
 }
 
 mpm_status mpm_get_velocity(mpm_run* r, double* ux, double* uy) {
   if (!r || !ux || !uy) return MPM_EINVAL;
   if (!r->started) return MPM_ESTATE;
-  HIPCHK(r, hipMemcpyAsync(ux, r->ux, size_t(r->P.ny) * (r->P.nx + 1) * 8, hipMemcpyDeviceToDevice, r->st));
-  HIPCHK(r, hipMemcpyAsync(uy, r->uy, size_t(r->P.ny + 1) * r->P.nx * 8, hipMemcpyDeviceToDevice, r->st));
-  return MPM_OK;
+  mpm_status st = enter(r);
+  if (st) return st;
+  auto body = [&]() -> mpm_status {
+    HIPCHK(r, hipMemcpyAsync(ux, r->ux, size_t(r->P.ny) * (r->P.nx + 1) * 8, hipMemcpyDeviceToDevice, r->st));
+    HIPCHK(r, hipMemcpyAsync(uy, r->uy, size_t(r->P.ny + 1) * r->P.nx * 8, hipMemcpyDeviceToDevice, r->st));
+    return MPM_OK;
+  };
+  return leave(r, body());
 }
 
 mpm_status mpm_get_saturation(mpm_run* r, double* s) {
   if (!r || !s) return MPM_EINVAL;
   if (!r->fields) return MPM_ESTATE;
-  HIPCHK(r, hipMemcpyAsync(s, r->s, size_t(r->P.ny) * r->P.nx * 8, hipMemcpyDeviceToDevice, r->st));
-  return MPM_OK;
+  mpm_status st = enter(r);
+  if (st) return st;
+  auto body = [&]() -> mpm_status {
+    HIPCHK(r, hipMemcpyAsync(s, r->s, size_t(r->P.ny) * r->P.nx * 8, hipMemcpyDeviceToDevice, r->st));
+    return MPM_OK;
+  };
+  return leave(r, body());
 }
 
 mpm_status mpm_get_stats(mpm_run* r, mpm_stats* out) {
@@ -516,10 +667,16 @@ mpm_status mpm_destroy(mpm_run* r) {
   hipStreamSynchronize(r->st);
   for (auto& p : r->pending) { hipEventDestroy(p.second.first); hipEventDestroy(p.second.second); }
   for (auto e : r->pool) hipEventDestroy(e);
+  for (auto& gx : r->g_trans)
+    if (gx) hipGraphExecDestroy(gx);
+  if (r->g_mpm) hipGraphExecDestroy(r->g_mpm);
+  if (r->ev_in) hipEventDestroy(r->ev_in);
+  if (r->ev_out) hipEventDestroy(r->ev_out);
   if (r->ev_eps) hipEventDestroy(r->ev_eps);
   if (r->ev_fork) hipEventDestroy(r->ev_fork);
   if (r->ev_join) hipEventDestroy(r->ev_join);
   if (r->st2) { hipStreamSynchronize(r->st2); hipStreamDestroy(r->st2); }
+  if (r->st && r->st != r->ust) hipStreamDestroy(r->st);
   if (r->pinned) hipHostFree(r->pinned);
   delete r;
   if (errw & ERR_NOTSPD) return MPM_ENOTSPD;

@@ -140,4 +140,30 @@ __host__ __device__ __forceinline__ double harm_ratio(double knc, double knd, do
 
 __device__ __forceinline__ void set_error(int32_t* err, int32_t bits) { atomicOr(err, bits); }
 
+// Transport sub-step from the maximum outflow rate and the boundary inflow, reduced in a fixed
+// order from per-subdomain partials (run by one workgroup of 256 threads).
+__device__ __forceinline__ void reduce_dt(int nsub, const double* red_rate, const double* red_qin, double cfl,
+                                          double fmax_deriv, double* scal, double* sm, double* ss) {
+  double m = 0.0, s = 0.0;
+  for (int i = threadIdx.x; i < nsub; i += blockDim.x) {
+    m = fmax(m, red_rate[i]);
+    s += red_qin[i];
+  }
+  sm[threadIdx.x] = m;
+  ss[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+      ss[threadIdx.x] += ss[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    scal[SC_MAXRATE] = sm[0];
+    scal[SC_QIN] = ss[0];
+    scal[SC_DT] = cfl / (fmax_deriv * sm[0]);
+  }
+}
+
 }  // namespace mpm

@@ -11,6 +11,8 @@ namespace mpm {
 size_t local_smem_max(const Geo& g);
 void launch_kappa(hipStream_t st, int ncell, const double* s, const double* K, double* kn, const double* km,
                   double mu_w, double mu_o, double* red, double* scal);
+void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double cfl,
+               double fmax_deriv, double* scal);
 void launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
                   double* leafK, double* leafr, int32_t* err);
 // lines.hip
@@ -30,8 +32,6 @@ void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, const d
 void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
                       double* ux, double* uy, double* red_rate, double* red_qin, double* Escr, double* Ekeep,
                       const int32_t* flag, int store, int32_t* err);
-void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double cfl,
-               double fmax_deriv, double* scal);
 
 // nd.hip: nested-dissection factorisation and solve of the interface system
 struct NdArgs {

@@ -118,9 +118,9 @@ __device__ __forceinline__ double bweight(const Geo& g, const BFace& f, bool is_
 
 // ====================================================================== A1: kappa, epsilon
 
-__global__ void k_kappa(int ncell, const double* __restrict__ s, const double* __restrict__ K,
-                        double* __restrict__ kap_n, const double* __restrict__ kap_m, double mu_w, double mu_o,
-                        double* __restrict__ red) {
+__global__ void __launch_bounds__(256)
+k_kappa(int ncell, const double* __restrict__ s, const double* __restrict__ K, double* __restrict__ kap_n,
+        const double* __restrict__ kap_m, double mu_w, double mu_o, double* __restrict__ red) {
   __shared__ double sa[256], sb[256];
   const int c = blockIdx.x * 256 + threadIdx.x;
   double a = 0.0, bb = 0.0;
@@ -151,7 +151,8 @@ __global__ void k_kappa(int ncell, const double* __restrict__ s, const double* _
 }
 
 // Fixed-order reduction of the epsilon partial sums into the scalar block.
-__global__ void k_reduce_eps(int nblocks, const double* __restrict__ red, double* __restrict__ scal) {
+__global__ void __launch_bounds__(256) k_reduce_eps(int nblocks, const double* __restrict__ red,
+                                                    double* __restrict__ scal) {
   __shared__ double sa[256], sb[256];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < nblocks; i += 256) {
@@ -172,6 +173,14 @@ __global__ void k_reduce_eps(int nblocks, const double* __restrict__ red, double
     scal[SC_EPS_NUM] = sa[0];
     scal[SC_EPS_DEN] = sb[0];
   }
+}
+
+// Transport sub-step from the maximum outflow rate and the boundary inflow (fixed order).
+__global__ void __launch_bounds__(256) k_dt(int nsub, const double* __restrict__ red_rate,
+                                            const double* __restrict__ red_qin, double cfl, double fmax_deriv,
+                                            double* __restrict__ scal) {
+  __shared__ double sm[256], ss[256];
+  reduce_dt(nsub, red_rate, red_qin, cfl, fmax_deriv, scal, sm, ss);
 }
 
 // ====================================================================== A2+A3: MRCM basis
@@ -366,32 +375,6 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
   }
 }
 
-// Transport sub-step from the maximum outflow rate; boundary inflow (fixed-order sums).
-__global__ void k_dt(int nsub, const double* __restrict__ red_rate, const double* __restrict__ red_qin,
-                     double cfl, double fmax_deriv, double* __restrict__ scal) {
-  __shared__ double sm[256], ss[256];
-  double m = 0.0, s = 0.0;
-  for (int i = threadIdx.x; i < nsub; i += 256) {
-    m = fmax(m, red_rate[i]);
-    s += red_qin[i];
-  }
-  sm[threadIdx.x] = m;
-  ss[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
-      ss[threadIdx.x] += ss[threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    scal[SC_MAXRATE] = sm[0];
-    scal[SC_QIN] = ss[0];
-    scal[SC_DT] = cfl / (fmax_deriv * sm[0]);
-  }
-}
-
 // ---------------------------------------------------------------------- launchers
 
 static size_t basis_smem(const Geo& g) {
@@ -407,6 +390,11 @@ void launch_kappa(hipStream_t st, int ncell, const double* s, const double* K, d
   hipLaunchKernelGGL(k_reduce_eps, dim3(1), dim3(256), 0, st, nblk, red, scal);
 }
 
+void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double cfl,
+               double fmax_deriv, double* scal) {
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, st, nsub, red_rate, red_qin, cfl, fmax_deriv, scal);
+}
+
 void launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
                   double* leafK, double* leafr, int32_t* err) {
   hipLaunchKernelGGL(k_basis, dim3(g.nsub), dim3(LOCAL_THREADS), basis_smem(g), st, g, kap, q, S, h, leafK, leafr,
@@ -416,11 +404,6 @@ void launch_basis(hipStream_t st, const Geo& g, const double* kap, const double*
 void launch_flux(hipStream_t st, const Geo& g, const double* km, const double* S, const double* h,
                  const double* vbnd, const double* y, const int32_t* sub_dofs, double* ubnd, int with_v) {
   hipLaunchKernelGGL(k_flux, dim3(g.nsub), dim3(64), 0, st, g, km, S, h, vbnd, y, sub_dofs, ubnd, with_v);
-}
-
-void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double cfl,
-               double fmax_deriv, double* scal) {
-  hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, st, nsub, red_rate, red_qin, cfl, fmax_deriv, scal);
 }
 
 }  // namespace mpm

@@ -151,3 +151,35 @@ def test_c2_forced_update(binding):
     cfg = inputs.config("c2")
     K = inputs.permeability(cfg)
     _compare_runs(binding, cfg, K, 3, "c2-forced", forced=[None, "mpm", "mrcm", "mpm"])
+
+
+def test_graph_replays_match_eager(binding, monkeypatch):
+    """The MPM-2P step replayed from captured graphs gives bitwise the same state as eager
+    launches, step after step, with eager MRCM updates and host synchronisations between
+    replays."""
+    cfg, K = inputs.random_problem(21, 48, 32, 8, 8, 2, 2, sigma2=3.0, corr_len=0.15, mu_o=40.0)
+    forces = [binding.AUTO, binding.AUTO, binding.FORCE_MRCM, binding.AUTO, binding.AUTO, binding.AUTO,
+              binding.FORCE_MRCM, binding.AUTO, binding.AUTO]
+
+    def trajectory(graphs):
+        if graphs:
+            monkeypatch.setenv("MPM2P_GRAPHS", "1")
+        else:
+            monkeypatch.delenv("MPM2P_GRAPHS", raising=False)
+        r = _gpu_run(binding, cfg, K)
+        r.start()
+        out = []
+        for f in forces:
+            r.step(f)
+            st = r.stats()
+            ux, uy = r.velocity()
+            out.append((to_np(ux), to_np(uy), to_np(r.saturation()), st["eps"], st["last_branch"]))
+        r.close()
+        return out
+
+    eager = trajectory(False)
+    graph = trajectory(True)
+    for n, (a, b) in enumerate(zip(eager, graph)):
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), n
+        assert np.array_equal(a[2], b[2]), n
+        assert a[3] == b[3] and a[4] == b[4], n
