@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmpm2p.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["plan.cpp", "local.hip", "lines.hip", "nd.hip", "transport.hip", "api.cpp"]
+SOURCES = ["plan.cpp", "local.hip", "basis.hip", "lines.hip", "nd.hip", "transport.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

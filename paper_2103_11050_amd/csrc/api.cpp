@@ -280,11 +280,12 @@ void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store) {
 // MRCM with a new basis for kappa^n (stored as kappa^m), downscaled with the same kappa.
 mpm_status mrcm_update(mpm_run* r) {
   HIPCHK(r, hipMemcpyAsync(r->km, r->kn, size_t(r->P.nx) * r->P.ny * 8, hipMemcpyDeviceToDevice, r->st));
+  bool have_fac;
   {
     Scope sc(r, "basis");
-    launch_basis(r->st, r->g, r->km, r->q, r->S, r->h, r->leafK, r->leafr, r->err);
+    have_fac = launch_basis(r->st, r->g, r->km, r->q, r->S, r->h, r->leafK, r->leafr, r->fac, r->err);
   }
-  {
+  if (!have_fac) {
     Scope sc(r, "line_factor");
     launch_line_factor(r->st, r->g, r->km, r->fac, r->err);
   }

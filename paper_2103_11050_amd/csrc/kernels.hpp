@@ -8,13 +8,14 @@
 namespace mpm {
 
 // local.hip
-size_t local_smem_max(const Geo& g);
 void launch_kappa(hipStream_t st, int ncell, const double* s, const double* K, double* kn, const double* km,
                   double mu_w, double mu_o, double* red, double* scal);
 void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double cfl,
                double fmax_deriv, double* scal);
-void launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
-                  double* leafK, double* leafr, int32_t* err);
+
+// basis.hip: returns whether the kappa^m line-block inverses were written as well
+bool launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
+                  double* leafK, double* leafr, double* fac, int32_t* err);
 // lines.hip
 void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double* fac, int32_t* err);
 size_t line_factor_doubles(int nsub, int nc, int band);

@@ -20,7 +20,10 @@
 
 namespace mpm {
 
-template <int MF>
+// IL = false: lane (row, cg) holds columns cg*EPL + t (contiguous groups);
+// IL = true : lane (row, cg) holds columns cg + LPR*t (interleaved), the layout whose entry t
+//             is the matrix-core operand of the t-th K-chunk.
+template <int MF, bool IL = false>
 struct LB {
   static constexpr int EPL = MF * MF / 64;   // entries per lane
   static constexpr int LPR = MF / EPL;       // lanes per row
@@ -30,7 +33,7 @@ struct LB {
     row = lane / LPR;
     cg = lane % LPR;
   }
-  __device__ int col(int t) const { return cg * EPL + t; }
+  __device__ int col(int t) const { return IL ? cg + LPR * t : cg * EPL + t; }
 };
 
 // In-place inverse of the SPD block held as a[t] = D[row][col(t)]. Clears ok on a
@@ -69,9 +72,42 @@ __device__ __forceinline__ void lb_inverse(const LB<MF>& L, double (&a)[LB<MF>::
   for (int t = 0; t < EPL; ++t) a[t] = -a[t];
 }
 
-// y = D v for vectors replicated over a row's lanes (lane holds v[row]); result replicated.
+// The same inverse for the interleaved layout: pivot k = ck + LPR*tk lives in entry tk.
 template <int MF>
-__device__ __forceinline__ double lb_matvec(const LB<MF>& L, const double (&a)[LB<MF>::EPL], double v) {
+__device__ __forceinline__ void lb_inverse_il(const LB<MF, true>& L, double (&a)[LB<MF>::EPL], bool& ok) {
+  constexpr int EPL = LB<MF>::EPL, LPR = LB<MF>::LPR;
+#pragma unroll
+  for (int tk = 0; tk < EPL; ++tk) {
+#pragma unroll 1
+    for (int ck = 0; ck < LPR; ++ck) {
+      const int k = ck + LPR * tk;
+      double rk[EPL];
+#pragma unroll
+      for (int t = 0; t < EPL; ++t) rk[t] = __shfl(a[t], k * LPR + L.cg);
+      const double cv = __shfl(a[tk], L.row * LPR + ck);
+      const double d = __shfl(a[tk], k * LPR + ck);
+      ok = ok && (d > 0.0);
+      double rd = __builtin_amdgcn_rcp(d);
+      rd = fma(rd, fma(-d, rd, 1.0), rd);
+      rd = fma(rd, fma(-d, rd, 1.0), rd);
+#pragma unroll
+      for (int t = 0; t < EPL; ++t) {
+        const int j = L.col(t);
+        double v;
+        if (L.row == k) v = (j == k) ? -rd : rk[t] * rd;
+        else if (j == k) v = cv * rd;
+        else v = a[t] - cv * rk[t] * rd;
+        a[t] = v;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) a[t] = -a[t];
+}
+
+// y = D v for vectors replicated over a row's lanes (lane holds v[row]); result replicated.
+template <int MF, bool IL>
+__device__ __forceinline__ double lb_matvec(const LB<MF, IL>& L, const double (&a)[LB<MF>::EPL], double v) {
   constexpr int EPL = LB<MF>::EPL, LPR = LB<MF>::LPR;
   double acc = 0.0;
 #pragma unroll
@@ -156,9 +192,9 @@ struct LineW {
 };
 
 // Builds D_ln for line ln in registers: T_ln - Y_{ln-1} Eprev Y_{ln-1}.
-template <int MF>
-__device__ __forceinline__ void lb_block(const LineW& W, int ln, const LB<MF>& L, const double (&Eprev)[LB<MF>::EPL],
-                                         double (&a)[LB<MF>::EPL]) {
+template <int MF, bool IL>
+__device__ __forceinline__ void lb_block(const LineW& W, int ln, const LB<MF, IL>& L,
+                                         const double (&Eprev)[LB<MF>::EPL], double (&a)[LB<MF>::EPL]) {
   constexpr int EPL = LB<MF>::EPL;
   const int len = W.band;
   const int r = L.row;
