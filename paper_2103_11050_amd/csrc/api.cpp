@@ -75,6 +75,8 @@ struct mpm_run {
   double *front, *fI, *cB, *panel, *y, *red, *scal, *dsE, *nfac;
   int32_t* err;
   int32_t* dsflag = nullptr;
+  int32_t* dslist = nullptr;
+  int32_t* dscount = nullptr;          // number of entries of dslist (device)
   NdArgs nd{};
   hipStream_t st2 = nullptr;           // second stream: factorisations overlapped with the solves
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -176,7 +178,7 @@ double eps_from(const mpm_run* r, double num, double den) {
 mpm_status kappa_and_eps_nodes(mpm_run* r) {
   {
     Scope sc(r, "kappa_eps");
-    launch_kappa(r->st, r->P.nx * r->P.ny, r->s, r->K, r->kn, r->km, r->P.d.mu_w, r->P.d.mu_o, r->red, r->scal);
+    launch_kappa(r->st, r->g, r->s, r->K, r->kn, r->km, r->red, r->scal, r->dsflag, r->dslist, r->dscount);
   }
   HIPCHK(r, hipMemcpyAsync(r->pinned, r->scal + SC_EPS_NUM, 2 * sizeof(double), hipMemcpyDeviceToHost, r->st));
   return MPM_OK;
@@ -273,7 +275,7 @@ void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store) {
   }
   {
     Scope sc(r, "dt");
-    launch_dt(r->st, r->P.nsub, r->red, r->red + r->P.nsub, r->P.d.cfl, r->fmax_deriv, r->scal);
+    launch_dt(r->st, r->P.nsub, r->red, r->red + r->P.nsub, r->P.d.cfl, r->fmax_deriv, r->scal, r->dscount);
   }
 }
 
@@ -302,15 +304,16 @@ mpm_status mrcm_update(mpm_run* r) {
 // MPM-2P: trivial-Robin solve with the stored kappa^m factors, interface solve with the stored
 // factorisation, reconstruction, downscaling with kappa^n.
 mpm_status mpm_update_body(mpm_run* r) {
-  // kappa^n Neumann factors of the changed subdomains on the second stream
-  HIPCHK(r, hipEventRecord(r->ev_fork, r->st));
-  HIPCHK(r, hipStreamWaitEvent(r->st2, r->ev_fork, 0));
-  launch_ds_factor(r->st2, r->g, r->kn, r->km, r->dsE, r->dsflag, r->err);
-  HIPCHK(r, hipEventRecord(r->ev_join, r->st2));
   {
     Scope sc(r, "mpm_local");
     launch_mpm_local(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac, r->h, r->vbnd, r->leafr);
   }
+  // kappa^n Neumann factors of the changed subdomains on the second stream, overlapped with
+  // the interface solve (whose level kernels leave most of the chip idle)
+  HIPCHK(r, hipEventRecord(r->ev_fork, r->st));
+  HIPCHK(r, hipStreamWaitEvent(r->st2, r->ev_fork, 0));
+  launch_ds_factor(r->st2, r->g, r->kn, r->dsE, r->dslist, r->dscount, r->err);
+  HIPCHK(r, hipEventRecord(r->ev_join, r->st2));
   nd_solve(r);
   HIPCHK(r, hipStreamWaitEvent(r->st, r->ev_join, 0));
   finish_velocity(r, r->kn, 1, 0);
@@ -473,12 +476,15 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   r->dsE = D(P.off_dsE); r->nfac = D(P.off_nfac);
   r->s_base = r->s;
   r->dsflag = reinterpret_cast<int32_t*>(r->ws + P.off_dsflag);
+  r->dslist = reinterpret_cast<int32_t*>(r->ws + P.off_dslist);
   r->err = reinterpret_cast<int32_t*>(r->scal + SC_COUNT);
+  r->dscount = r->err + 1;
   r->subdofs_d = reinterpret_cast<const int32_t*>(r->ws + P.off_subdofs);
   r->nd.nodes = reinterpret_cast<const NodeDev*>(r->ws + P.off_nodes);
   r->nd.levels = reinterpret_cast<const int32_t*>(r->ws + P.off_levels);
   r->nd.dof_pool = reinterpret_cast<const int32_t*>(r->ws + P.off_dofpool);
   r->nd.map_pool = reinterpret_cast<const int32_t*>(r->ws + P.off_mappool);
+  r->nd.inv_pool = reinterpret_cast<const int32_t*>(r->ws + P.off_invpool);
   r->nd.front = r->front; r->nd.fI = r->fI; r->nd.cB = r->cB; r->nd.panel = r->panel;
   r->nd.leafK = r->leafK; r->nd.leafr = r->leafr; r->nd.y = r->y; r->nd.ndmax = P.ndmax;
   r->nd.piv_b = P.piv_b; r->nd.err = r->err;
@@ -499,6 +505,25 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
     delete r;
     return s;
   };
+  // every device pointer the kernels take must lie inside the caller's workspace
+  {
+    const char* lo = r->ws;
+    const char* hi = r->ws + P.total_bytes;
+    auto in = [&](const void* p, size_t n) {
+      const char* c = static_cast<const char*>(p);
+      return c != nullptr && c >= lo && c + n <= hi;
+    };
+    const size_t cb = size_t(P.nx) * P.ny * 8, ns = size_t(P.nsub);
+    const size_t fx = size_t(P.ny) * (P.nx + 1) * 8, fy = size_t(P.ny + 1) * P.nx * 8;
+    const bool ok = in(r->K, cb) && in(r->q, cb) && in(r->s, cb) && in(r->s2, cb) && in(r->kn, cb) &&
+                    in(r->km, cb) && in(r->ux, fx) && in(r->uy, fy) && in(r->uxm, fx) && in(r->uym, fy) &&
+                    in(r->S, ns * P.nb * P.nb * 8) && in(r->h, ns * P.nb * 8) && in(r->vbnd, ns * P.nb * 8) &&
+                    in(r->ubnd, ns * P.nb * 8) && in(r->leafK, ns * P.ndmax * P.ndmax * 8) &&
+                    in(r->leafr, ns * P.ndmax * 8) && in(r->red, P.n_red * 8) && in(r->scal, SC_COUNT * 8) &&
+                    in(r->err, 4) && in(r->dscount, 4) && in(r->dsflag, ns * 4) && in(r->dslist, ns * 4) &&
+                    in(r->y, size_t(std::max(P.n_iface, 1)) * 8) && in(r->subdofs_d, ns * P.ndmax * 4);
+    if (!ok) return fail(MPM_EINVAL);
+  }
   if (hipHostMalloc(reinterpret_cast<void**>(&r->pinned), 64, hipHostMallocDefault) != hipSuccess) return fail(MPM_ENOMEM);
   if (hipEventCreateWithFlags(&r->ev_eps, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
   if (hipEventCreateWithFlags(&r->ev_fork, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
@@ -530,6 +555,7 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
       up(P.off_fuse_nodes, P.fuse_nodes.data(), P.fuse_nodes.size() * 4) ||
       up(P.off_dofpool, P.dof_pool.data(), P.dof_pool.size() * 4) ||
       up(P.off_mappool, P.map_pool.data(), P.map_pool.size() * 4) ||
+      up(P.off_invpool, P.inv_pool.data(), P.inv_pool.size() * 4) ||
       up(P.off_subdofs, P.sub_dofs.data(), P.sub_dofs.size() * 4) ||
       up(P.off_subndof, P.sub_ndof.data(), P.sub_ndof.size() * 4) ||
       hipMemsetAsync(r->scal, 0, SC_COUNT * 8 + 64, r->st) ||

@@ -8,10 +8,10 @@
 namespace mpm {
 
 // local.hip
-void launch_kappa(hipStream_t st, int ncell, const double* s, const double* K, double* kn, const double* km,
-                  double mu_w, double mu_o, double* red, double* scal);
+void launch_kappa(hipStream_t st, const Geo& g, const double* s, const double* K, double* kn, const double* km,
+                  double* red, double* scal, int32_t* flag, int32_t* list, int32_t* count);
 void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double cfl,
-               double fmax_deriv, double* scal);
+               double fmax_deriv, double* scal, int32_t* count);
 
 // basis.hip: returns whether the kappa^m line-block inverses were written as well
 bool launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
@@ -26,8 +26,8 @@ void launch_flux(hipStream_t st, const Geo& g, const double* km, const double* S
                  const double* vbnd, const double* y, const int32_t* sub_dofs, double* ubnd, int with_v);
 // Neumann inverse blocks of kappa^n for the subdomains whose conductivity tile differs from
 // kappa^m (into Escr, flag[sub] = 1), flag[sub] = 0 elsewhere.
-void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, const double* kap_m, double* Escr,
-                      int32_t* flag, int32_t* err);
+void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, double* Escr, const int32_t* list,
+                      const int32_t* count, int32_t* err);
 // store = 1: kap_s is kappa^m, its inverse blocks are formed here and kept (Ekeep).
 // store = 0: the blocks come from Escr where flag[sub] is set, else from Ekeep.
 void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
@@ -40,6 +40,7 @@ struct NdArgs {
   const int32_t* levels;      // concatenated node lists per level
   const int32_t* dof_pool;
   const int32_t* map_pool;
+  const int32_t* inv_pool;
   double* front;
   double* fI;
   double* cB;

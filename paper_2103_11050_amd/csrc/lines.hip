@@ -3,6 +3,8 @@
 // subdomain with the block inverses in registers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.hpp"
 #include "kernels.hpp"
 #include "lines.hpp"
@@ -101,15 +103,45 @@ __device__ __forceinline__ void lb_solve(const Geo& g, const LineW& W, const LB<
 // once (every load in flight together) and serve both sweeps, so they are read from memory
 // once.
 template <int MF, int NL>
+__device__ __forceinline__ void lb_load_reg(const LB<MF>& L, const double* Es, double (&E)[NL][LB<MF>::EPL]) {
+  constexpr int EPL = LB<MF>::EPL;
+#pragma unroll
+  for (int ln = 0; ln < NL; ++ln)
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) E[ln][t] = Es[(size_t(ln) * EPL + t) * 64 + L.lane];
+}
+
+// The two sweeps with the blocks already in registers.
+template <int MF, int NL>
+__device__ __forceinline__ void lb_solve_regs(const LineW& W, const LB<MF>& L, const double (&E)[NL][LB<MF>::EPL],
+                                              double* x) {
+  const int len = W.band;
+  const bool rin = L.row < len;
+  double w[NL];
+#pragma unroll
+  for (int ln = 0; ln < NL; ++ln) {
+    double z = rin ? x[ln * len + L.row] : 0.0;
+    if (ln > 0 && rin) z += W.y(ln - 1, L.row) * w[ln - 1];
+    w[ln] = lb_matvec<MF>(L, E[ln], z);
+  }
+  double xnext = w[NL - 1];
+  if (rin && L.cg == 0) x[(NL - 1) * len + L.row] = xnext;
+#pragma unroll
+  for (int ln = NL - 2; ln >= 0; --ln) {
+    const double v = rin ? W.y(ln, L.row) * xnext : 0.0;
+    xnext = w[ln] + lb_matvec<MF>(L, E[ln], v);
+    if (rin && L.cg == 0) x[ln * len + L.row] = xnext;
+  }
+  __syncthreads();
+}
+
+template <int MF, int NL>
 __device__ __forceinline__ void lb_solve_reg(const LineW& W, const LB<MF>& L, const double* Es, double* x) {
   constexpr int EPL = LB<MF>::EPL;
   const int len = W.band;
   const bool rin = L.row < len;
   double E[NL][EPL];
-#pragma unroll
-  for (int ln = 0; ln < NL; ++ln)
-#pragma unroll
-    for (int t = 0; t < EPL; ++t) E[ln][t] = Es[(size_t(ln) * EPL + t) * 64 + L.lane];
+  lb_load_reg<MF, NL>(L, Es, E);
   double w[NL];
 #pragma unroll
   for (int ln = 0; ln < NL; ++ln) {
@@ -156,34 +188,107 @@ __global__ void __launch_bounds__(64) k_line_factor(Geo g, const double* __restr
 }
 
 // ---------------------------------------------------------------------------------------------
+// Tiles of one subdomain with a one-cell halo (corners excluded), loaded with every global
+// read issued before the first use: conductivities kappa^n and kappa^m at
+// T[(j + 1) * (mx + 2) + i + 1], the previous velocity on the subdomain's faces and q.
+struct HaloTiles {
+  double* kn;
+  double* km;
+  double* ux;   // [my][mx + 1]
+  double* uy;   // [my + 1][mx]
+  double* q;    // local order
+};
+
+__device__ __forceinline__ void load_halo_tiles(const Geo& g, int I, int J, const double* __restrict__ kap_n,
+                                                const double* __restrict__ kap_m, const double* __restrict__ uxm,
+                                                const double* __restrict__ uym, const double* __restrict__ q,
+                                                const HaloTiles& T) {
+  constexpr int NH = (18 * 18 + 63) / 64, NF = (16 * 17 + 63) / 64, NC = 256 / 64;
+  const int TW = g.mx + 2, nh = TW * (g.my + 2);
+  const int nfx = g.my * (g.mx + 1), nfy = (g.my + 1) * g.mx;
+  double a[NH], b[NH], fx[NF], fy[NF], qc[NC];
+#pragma unroll
+  for (int s = 0; s < NH; ++s) {
+    const int e = threadIdx.x + 64 * s;
+    const int ti = e % TW - 1, tj = e / TW - 1;
+    const int gi = I * g.mx + ti, gj = J * g.my + tj;
+    const bool edge_i = ti < 0 || ti >= g.mx, edge_j = tj < 0 || tj >= g.my;
+    const bool ok = e < nh && !(edge_i && edge_j) && gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
+    const int gc = ok ? gj * g.nx + gi : 0;
+    a[s] = kap_n[gc];
+    b[s] = kap_m[gc];
+  }
+#pragma unroll
+  for (int s = 0; s < NF; ++s) {
+    const int e = threadIdx.x + 64 * s;
+    const int ex = e < nfx ? e : 0, ey = e < nfy ? e : 0;
+    fx[s] = uxm[(J * g.my + ex / (g.mx + 1)) * (g.nx + 1) + I * g.mx + ex % (g.mx + 1)];
+    fy[s] = uym[(J * g.my + ey / g.mx) * g.nx + I * g.mx + ey % g.mx];
+  }
+#pragma unroll
+  for (int s = 0; s < NC; ++s) {
+    const int c = threadIdx.x + 64 * s;
+    int i, j;
+    loc_ij(g, c < g.nc ? c : 0, &i, &j);
+    qc[s] = q[(J * g.my + j) * g.nx + I * g.mx + i];
+  }
+#pragma unroll
+  for (int s = 0; s < NH; ++s) {
+    const int e = threadIdx.x + 64 * s;
+    if (e < nh) {
+      T.kn[e] = a[s];
+      T.km[e] = b[s];
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NF; ++s) {
+    const int e = threadIdx.x + 64 * s;
+    if (e < nfx) T.ux[e] = fx[s];
+    if (e < nfy) T.uy[e] = fy[s];
+  }
+#pragma unroll
+  for (int s = 0; s < NC; ++s) {
+    const int c = threadIdx.x + 64 * s;
+    if (c < g.nc) T.q[c] = qc[s];
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------------
 // MPM-2P trivial-Robin local solve (eq:mpm_tf_3 with the kappa^m basis): right-hand side
 // |c| q - sum_{non-Neumann faces} |f| v_f - sum_{Neumann faces} |f| z with
 // v_f = (t^n_f / t^m_f) u~^m_f; zero Dirichlet and Robin data. Outputs the boundary fluxes
 // h = W T delta p on Robin/Dirichlet faces, the boundary values of v and the interface
-// right-hand side B^T h.
+// right-hand side B^T h. The kept inverse blocks and all tiles are requested at entry.
 template <int MF, int NL>
 __global__ void __launch_bounds__(64)
 k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict__ kap_m,
                const double* __restrict__ uxm, const double* __restrict__ uym, const double* __restrict__ q,
                const double* __restrict__ fac, double* __restrict__ hg, double* __restrict__ vbnd,
                double* __restrict__ leafr) {
+  __shared__ double knt[18 * 18], kmt[18 * 18], uxs[16 * 17], uys[17 * 16], qs[256];
   __shared__ double kl[256], x[256], hsh[64], wsh[256], tE[256], tN[256], dg[256];
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int n = g.nc, nb = g.nb;
+  const int TW = g.mx + 2;
   LB<MF> L;
-  load_tile2(g, I, J, kap_m, kl);
+  constexpr int NLR = NL > 0 ? NL : 1;
+  double E[NLR][LB<MF>::EPL];
+  if constexpr (NL > 0) lb_load_reg<MF, NL>(L, fac + efac_off<MF>(g, sub, 0, 0), E);
+  load_halo_tiles(g, I, J, kap_n, kap_m, uxm, uym, q, HaloTiles{knt, kmt, uxs, uys, qs});
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     int i, j;
     loc_ij(g, c, &i, &j);
     const int gi = I * g.mx + i, gj = J * g.my + j;
-    const int gc = gj * g.nx + gi;
-    const double kn = kap_n[gc], km = kap_m[gc];
-    double r = g.hx * g.hy * q[gc];
+    const int e = (j + 1) * TW + i + 1;
+    const double kn = knt[e], km = kmt[e];
+    kl[c] = km;
+    double r = g.hx * g.hy * qs[c];
     {
-      const double u = uxm[gj * (g.nx + 1) + gi];
+      const double u = uxs[j * (g.mx + 1) + i];
       if (gi > 0) {
-        const double ratio = harm_ratio(kn, kap_n[gc - 1], km, kap_m[gc - 1]);
+        const double ratio = harm_ratio(kn, knt[e - 1], km, kmt[e - 1]);
         r -= g.hy * (-ratio * u);
       } else {
         BFace f = bface(g, I, J, j);
@@ -191,9 +296,9 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
       }
     }
     {
-      const double u = uxm[gj * (g.nx + 1) + gi + 1];
+      const double u = uxs[j * (g.mx + 1) + i + 1];
       if (gi < g.nx - 1) {
-        const double ratio = harm_ratio(kn, kap_n[gc + 1], km, kap_m[gc + 1]);
+        const double ratio = harm_ratio(kn, knt[e + 1], km, kmt[e + 1]);
         r -= g.hy * (ratio * u);
       } else {
         BFace f = bface(g, I, J, g.my + j);
@@ -201,9 +306,9 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
       }
     }
     {
-      const double u = uym[gj * g.nx + gi];
+      const double u = uys[j * g.mx + i];
       if (gj > 0) {
-        const double ratio = harm_ratio(kn, kap_n[gc - g.nx], km, kap_m[gc - g.nx]);
+        const double ratio = harm_ratio(kn, knt[e - TW], km, kmt[e - TW]);
         r -= g.hx * (-ratio * u);
       } else {
         BFace f = bface(g, I, J, 2 * g.my + i);
@@ -211,9 +316,9 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
       }
     }
     {
-      const double u = uym[(gj + 1) * g.nx + gi];
+      const double u = uys[(j + 1) * g.mx + i];
       if (gj < g.ny - 1) {
-        const double ratio = harm_ratio(kn, kap_n[gc + g.nx], km, kap_m[gc + g.nx]);
+        const double ratio = harm_ratio(kn, knt[e + TW], km, kmt[e + TW]);
         r -= g.hx * (ratio * u);
       } else {
         BFace f = bface(g, I, J, 2 * g.my + g.mx + i);
@@ -225,12 +330,13 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
   __syncthreads();
   fill_trans(g, I, J, kl, 0, tE, tN, dg);
   const LineW W{tE, tN, dg, g.xfast, g.band, 0};
-  lb_solve_any<MF, NL>(g, W, L, fac + efac_off<MF>(g, sub, 0, 0), x, wsh);
+  if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
+  else lb_solve<MF>(g, W, L, fac + efac_off<MF>(g, sub, 0, 0), x, wsh);
   for (int f = threadIdx.x; f < nb; f += blockDim.x) {
     BFace bf = bface(g, I, J, f);
     const int gi = I * g.mx + bf.i, gj = J * g.my + bf.j;
-    const int gc = gj * g.nx + gi;
-    const double km = kap_m[gc], kn = kap_n[gc];
+    const int e = (bf.j + 1) * TW + bf.i + 1;
+    const double km = kmt[e], kn = knt[e];
     const double w = bf.flen * bface_trans(g, bf, km);
     const double h = bf.kind == FACE_NEU ? 0.0 : w * x[loc_index(g, bf.i, bf.j)];
     hsh[f] = h;
@@ -239,11 +345,11 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
     if (bf.kind != FACE_NEU) {
       double u;
       int nbr;
-      if (bf.side == 0) { u = -uxm[gj * (g.nx + 1) + gi]; nbr = gi > 0 ? gc - 1 : -1; }
-      else if (bf.side == 1) { u = uxm[gj * (g.nx + 1) + gi + 1]; nbr = gi < g.nx - 1 ? gc + 1 : -1; }
-      else if (bf.side == 2) { u = -uym[gj * g.nx + gi]; nbr = gj > 0 ? gc - g.nx : -1; }
-      else { u = uym[(gj + 1) * g.nx + gi]; nbr = gj < g.ny - 1 ? gc + g.nx : -1; }
-      const double ratio = nbr >= 0 ? harm_ratio(kn, kap_n[nbr], km, kap_m[nbr]) : kn / km;
+      if (bf.side == 0) { u = -uxs[bf.j * (g.mx + 1) + bf.i]; nbr = gi > 0 ? e - 1 : -1; }
+      else if (bf.side == 1) { u = uxs[bf.j * (g.mx + 1) + bf.i + 1]; nbr = gi < g.nx - 1 ? e + 1 : -1; }
+      else if (bf.side == 2) { u = -uys[bf.j * g.mx + bf.i]; nbr = gj > 0 ? e - TW : -1; }
+      else { u = uys[(bf.j + 1) * g.mx + bf.i]; nbr = gj < g.ny - 1 ? e + TW : -1; }
+      const double ratio = nbr >= 0 ? harm_ratio(kn, knt[nbr], km, kmt[nbr]) : kn / km;
       v = ratio * u;
     }
     vbnd[size_t(sub) * nb + f] = v;
@@ -356,38 +462,31 @@ k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict
 }
 
 // ---------------------------------------------------------------------------------------------
-// Neumann inverse blocks of kappa^n where the subdomain's conductivity tile changed since the
-// last MRCM update (elsewhere the kept kappa^m blocks are exact). Runs on a second stream,
-// overlapped with the MPM-2P local and interface solves.
+// Neumann inverse blocks of kappa^n for the subdomains whose conductivity tile changed since the
+// last MRCM update (listed by the conductivity kernel; elsewhere the kept kappa^m blocks are
+// exact). A fixed grid walks the list. Runs on a second stream, overlapped with the interface
+// solve.
 template <int MF>
 __global__ void __launch_bounds__(64)
-k_ds_factor(Geo g, const double* __restrict__ kap_n, const double* __restrict__ kap_m, double* __restrict__ Escr,
-            int32_t* __restrict__ flag, int32_t* err) {
+k_ds_factor(Geo g, const double* __restrict__ kap_n, double* __restrict__ Escr, const int32_t* __restrict__ list,
+            const int32_t* __restrict__ count, int32_t* err) {
   __shared__ double kl[256], tE[256], tN[256], dg[256];
-  __shared__ int changed;
-  const int sub = blockIdx.x;
-  const int I = sub % g.Sx, J = sub / g.Sx;
   LB<MF> L;
-  if (threadIdx.x == 0) changed = 0;
-  __syncthreads();
-  bool diff = false;
-  for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
-    int i, j;
-    loc_ij(g, c, &i, &j);
-    const int gc = gcell2(g, I, J, i, j);
-    const double kn = kap_n[gc];
-    kl[c] = kn;
-    diff = diff || (kn != kap_m[gc]);
+  const int n = min(*count, g.nsub);
+#pragma unroll 1
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int sub = list[it];
+    if (sub < 0 || sub >= g.nsub) continue;
+    const int I = sub % g.Sx, J = sub / g.Sx;
+    load_tile2(g, I, J, kap_n, kl);
+    __syncthreads();
+    fill_trans(g, I, J, kl, 1, tE, tN, dg);
+    const LineW W{tE, tN, dg, g.xfast, g.band, 1};
+    bool ok = true;
+    lb_factor<MF>(g, W, L, Escr + efac_off<MF>(g, sub, 0, 0), ok);
+    if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
+    __syncthreads();
   }
-  if (diff) changed = 1;
-  __syncthreads();
-  if (threadIdx.x == 0) flag[sub] = changed;
-  if (!changed) return;
-  fill_trans(g, I, J, kl, 1, tE, tN, dg);
-  const LineW W{tE, tN, dg, g.xfast, g.band, 1};
-  bool ok = true;
-  lb_factor<MF>(g, W, L, Escr + efac_off<MF>(g, sub, 0, 0), ok);
-  if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -419,10 +518,12 @@ void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const doub
   MPM_LB_DISPATCH(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, leafr);
 }
 
-void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, const double* kap_m, double* Escr,
-                      int32_t* flag, int32_t* err) {
-  if (line_mf(g) == 8) hipLaunchKernelGGL(k_ds_factor<8>, dim3(g.nsub), dim3(64), 0, st, g, kap_n, kap_m, Escr, flag, err);
-  else hipLaunchKernelGGL(k_ds_factor<16>, dim3(g.nsub), dim3(64), 0, st, g, kap_n, kap_m, Escr, flag, err);
+void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, double* Escr, const int32_t* list,
+                      const int32_t* count, int32_t* err) {
+  const int grid = std::min(g.nsub, 1024);
+  if (line_mf(g) == 8)
+    hipLaunchKernelGGL(k_ds_factor<8>, dim3(grid), dim3(64), 0, st, g, kap_n, Escr, list, count, err);
+  else hipLaunchKernelGGL(k_ds_factor<16>, dim3(grid), dim3(64), 0, st, g, kap_n, Escr, list, count, err);
 }
 
 void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,

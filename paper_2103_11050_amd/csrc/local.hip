@@ -9,25 +9,34 @@ namespace mpm {
 
 // ====================================================================== A1: kappa, epsilon
 
+// One workgroup per subdomain tile: kappa^n = lambda(s) K, the tile's partial sums of
+// (kappa^n - kappa^m)^2 and (kappa^m)^2, and whether any conductivity of the tile changed
+// since the last MRCM update (flag, and the subdomain appended to the list of changed ones).
 __global__ void __launch_bounds__(256)
-k_kappa(int ncell, const double* __restrict__ s, const double* __restrict__ K, double* __restrict__ kap_n,
-        const double* __restrict__ kap_m, double mu_w, double mu_o, double* __restrict__ red) {
+k_kappa(Geo g, const double* __restrict__ s, const double* __restrict__ K, double* __restrict__ kap_n,
+        const double* __restrict__ kap_m, double* __restrict__ red, int32_t* __restrict__ flag,
+        int32_t* __restrict__ list, int32_t* __restrict__ count) {
   __shared__ double sa[256], sb[256];
-  const int c = blockIdx.x * 256 + threadIdx.x;
+  const int sub = blockIdx.x;
+  const int I = sub % g.Sx, J = sub / g.Sx;
+  const int c = threadIdx.x;
   double a = 0.0, bb = 0.0;
-  if (c < ncell) {
-    const double sv = s[c];
-    const double lam = sv * sv / mu_w + (1.0 - sv) * (1.0 - sv) / mu_o;
-    const double kn = lam * K[c];
-    kap_n[c] = kn;
-    const double km = kap_m[c];
+  int diff = 0;
+  if (c < g.nc) {
+    const int gc = (J * g.my + c / g.mx) * g.nx + I * g.mx + c % g.mx;
+    const double sv = s[gc];
+    const double lam = sv * sv / g.mu_w + (1.0 - sv) * (1.0 - sv) / g.mu_o;
+    const double kn = lam * K[gc];
+    kap_n[gc] = kn;
+    const double km = kap_m[gc];
     const double dd = kn - km;
     a = dd * dd;
     bb = km * km;
+    diff = kn != km;
   }
   sa[threadIdx.x] = a;
   sb[threadIdx.x] = bb;
-  __syncthreads();
+  const int changed = __syncthreads_or(diff);
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
       sa[threadIdx.x] += sa[threadIdx.x + w];
@@ -36,8 +45,13 @@ k_kappa(int ncell, const double* __restrict__ s, const double* __restrict__ K, d
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    red[2 * blockIdx.x] = sa[0];
-    red[2 * blockIdx.x + 1] = sb[0];
+    red[2 * sub] = sa[0];
+    red[2 * sub + 1] = sb[0];
+    flag[sub] = changed;
+    if (changed) {
+      const int at = atomicAdd(count, 1);
+      if (at < g.nsub) list[at] = sub;
+    }
   }
 }
 
@@ -67,11 +81,13 @@ __global__ void __launch_bounds__(256) k_reduce_eps(int nblocks, const double* _
 }
 
 // Transport sub-step from the maximum outflow rate and the boundary inflow (fixed order).
+// Also empties the list of changed subdomains for the next velocity update.
 __global__ void __launch_bounds__(256) k_dt(int nsub, const double* __restrict__ red_rate,
                                             const double* __restrict__ red_qin, double cfl, double fmax_deriv,
-                                            double* __restrict__ scal) {
+                                            double* __restrict__ scal, int32_t* __restrict__ count) {
   __shared__ double sm[256], ss[256];
   reduce_dt(nsub, red_rate, red_qin, cfl, fmax_deriv, scal, sm, ss);
+  if (threadIdx.x == 0) *count = 0;
 }
 
 // ====================================================================== A7: boundary fluxes
@@ -119,16 +135,15 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
 
 // ---------------------------------------------------------------------- launchers
 
-void launch_kappa(hipStream_t st, int ncell, const double* s, const double* K, double* kn, const double* km,
-                  double mu_w, double mu_o, double* red, double* scal) {
-  const int nblk = (ncell + 255) / 256;
-  hipLaunchKernelGGL(k_kappa, dim3(nblk), dim3(256), 0, st, ncell, s, K, kn, km, mu_w, mu_o, red);
-  hipLaunchKernelGGL(k_reduce_eps, dim3(1), dim3(256), 0, st, nblk, red, scal);
+void launch_kappa(hipStream_t st, const Geo& g, const double* s, const double* K, double* kn, const double* km,
+                  double* red, double* scal, int32_t* flag, int32_t* list, int32_t* count) {
+  hipLaunchKernelGGL(k_kappa, dim3(g.nsub), dim3(256), 0, st, g, s, K, kn, km, red, flag, list, count);
+  hipLaunchKernelGGL(k_reduce_eps, dim3(1), dim3(256), 0, st, g.nsub, red, scal);
 }
 
 void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double cfl,
-               double fmax_deriv, double* scal) {
-  hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, st, nsub, red_rate, red_qin, cfl, fmax_deriv, scal);
+               double fmax_deriv, double* scal, int32_t* count) {
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, st, nsub, red_rate, red_qin, cfl, fmax_deriv, scal, count);
 }
 
 void launch_flux(hipStream_t st, const Geo& g, const double* km, const double* S, const double* h,

@@ -272,6 +272,132 @@ __global__ void __launch_bounds__(256) k_nd_bwd(NdArgs a, int loff, int G, int r
   }
 }
 
+// Register-batched forms of the two sweeps. A workgroup takes RP x (256/G) rows of one node,
+// G lanes per row, U columns per lane, and issues every load of its block (and of the vector
+// it multiplies) before the first use, so that one level costs about two memory round trips
+// (indices, then everything else) rather than one per row. Loads are unconditional at clamped
+// (valid) addresses and masked afterwards, so the compiler keeps them all in flight. No LDS and
+// no barriers: the forward right-hand side is gathered per lane through the inverse
+// extend-add maps.
+template <int G, int U, int RP>
+__global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a, int loff) {
+  constexpr int RPP = 256 / G, RPB = RP * RPP;
+  const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
+  const int r0 = blockIdx.x * RPB;
+  if (r0 >= max(nd.nB, 1)) return;
+  const int gl = threadIdx.x % G, grp = threadIdx.x / G;
+  const double* __restrict__ F = a.front + nd.front_off;
+  const int32_t* __restrict__ inv0 = a.inv_pool + nd.inv_off;
+  const int32_t* __restrict__ inv1 = inv0 + nd.n;
+  const double* __restrict__ src0 = child_c(a, nd, 0);
+  const double* __restrict__ src1 = child_c(a, nd, 1);
+  const int nI1 = max(nd.nI, 1) - 1, nB1 = max(nd.nB, 1) - 1;
+  // indices of f at this lane's columns (k < nI) and rows (nI + j)
+  int ik0[U], ik1[U], ib0[RP], ib1[RP];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = min(gl + u * G, nI1);
+    ik0[u] = inv0[k];
+    ik1[u] = inv1[k];
+  }
+  double m[RP][U];
+  if (nd.nB > 0) {
+#pragma unroll
+    for (int p = 0; p < RP; ++p) {
+      const int j = min(r0 + p * RPP + grp, nB1);
+      ib0[p] = inv0[nd.nI + j];
+      ib1[p] = inv1[nd.nI + j];
+    }
+#pragma unroll
+    for (int p = 0; p < RP; ++p) {
+      const int j = min(r0 + p * RPP + grp, nB1);
+#pragma unroll
+      for (int u = 0; u < U; ++u) m[p][u] = F[int64_t(nd.nI + j) * nd.n + min(gl + u * G, nI1)];
+    }
+  } else {
+    // the root: no boundary rows, only f_I is stored
+#pragma unroll
+    for (int p = 0; p < RP; ++p) {
+      ib0[p] = -1;
+      ib1[p] = -1;
+#pragma unroll
+      for (int u = 0; u < U; ++u) m[p][u] = 0.0;
+    }
+  }
+  double fk[U], fb[RP];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const double x0 = src0[max(ik0[u], 0)], x1 = src1[max(ik1[u], 0)];
+    fk[u] = (ik0[u] >= 0 ? x0 : 0.0) + (ik1[u] >= 0 ? x1 : 0.0);
+  }
+#pragma unroll
+  for (int p = 0; p < RP; ++p) {
+    const double x0 = src0[max(ib0[p], 0)], x1 = src1[max(ib1[p], 0)];
+    fb[p] = (ib0[p] >= 0 ? x0 : 0.0) + (ib1[p] >= 0 ? x1 : 0.0);
+  }
+  if (blockIdx.x == 0 && grp == 0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = gl + u * G;
+      if (k < nd.nI) a.fI[nd.fI_off + k] = fk[u];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < RP; ++p) {
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += (gl + u * G < nd.nI) ? m[p][u] * fk[u] : 0.0;
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    const int j = r0 + p * RPP + grp;
+    if (gl == 0 && j < nd.nB) a.cB[nd.cB_off + j] = fb[p] - acc;
+  }
+}
+
+template <int G, int U, int RP>
+__global__ void __launch_bounds__(256) k_nd_bwd_rb(NdArgs a, int loff) {
+  constexpr int RPP = 256 / G, RPB = RP * RPP;
+  const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
+  const int r0 = blockIdx.x * RPB;
+  if (r0 >= nd.nI) return;
+  const int gl = threadIdx.x % G, grp = threadIdx.x / G;
+  const double* __restrict__ F = a.front + nd.front_off;
+  const int32_t* __restrict__ dofs = a.dof_pool + nd.dof_off;
+  const int n1 = nd.n - 1, nI1 = nd.nI - 1;
+  // v = [f_I; x_B]: unknown ids of this lane's columns first
+  int dk[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) dk[u] = dofs[min(gl + u * G, n1)];
+  int dr[RP];
+#pragma unroll
+  for (int p = 0; p < RP; ++p) dr[p] = dofs[min(r0 + p * RPP + grp, nI1)];
+  double m[RP][U];
+#pragma unroll
+  for (int p = 0; p < RP; ++p) {
+    const int r = min(r0 + p * RPP + grp, nI1);
+#pragma unroll
+    for (int u = 0; u < U; ++u) m[p][u] = F[int64_t(r) * nd.n + min(gl + u * G, n1)];
+  }
+  double v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = gl + u * G;
+    const double xi = a.fI[nd.fI_off + min(k, nI1)];
+    const double xb = a.y[dk[u]];
+    v[u] = k < nd.nI ? xi : (k < nd.n ? xb : 0.0);
+  }
+#pragma unroll
+  for (int p = 0; p < RP; ++p) {
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += m[p][u] * v[u];
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    const int r = r0 + p * RPP + grp;
+    if (gl == 0 && r < nd.nI) a.y[dr[p]] = -acc;
+  }
+}
+
 // Bottom levels fused: one workgroup walks one subtree, children before parents (forward)
 // or parents before children (backward); the per-node work is that of k_nd_fwd / k_nd_bwd.
 __global__ void __launch_bounds__(256) k_nd_fwd_fused(NdArgs a) {
@@ -356,7 +482,46 @@ static int rows_per_block(int nrows, int nnodes, int G) {
   return std::max(per_pass, (rpb + per_pass - 1) / per_pass * per_pass);
 }
 
+// Register-batched shape for a row length: lanes per row, columns per lane, rows per lane
+// group (about eight loads of the block per lane). Returns false past the largest shape.
+struct RbShape {
+  int G, U, RP;
+};
+static bool rb_shape(int len, RbShape* sh) {
+  if (len <= 16) *sh = {16, 1, 8};
+  else if (len <= 32) *sh = {32, 1, 8};
+  else if (len <= 64) *sh = {64, 1, 8};
+  else if (len <= 128) *sh = {64, 2, 4};
+  else if (len <= 256) *sh = {64, 4, 2};
+  else if (len <= 512) *sh = {64, 8, 1};
+  else if (len <= 1024) *sh = {64, 16, 1};
+  else if (len <= 1536) *sh = {64, 24, 1};
+  else if (len <= 2048) *sh = {64, 32, 1};
+  else return false;
+  return true;
+}
+
+#define ND_RB_LAUNCH(KER, sh, rows, nnodes, st, a, loff)                                              \
+  do {                                                                                              \
+    const int rpb_ = (sh).RP * (256 / (sh).G);                                                      \
+    const dim3 grid_(std::max(1, ((rows) + rpb_ - 1) / rpb_), (nnodes));                          \
+    if ((sh).G == 16) hipLaunchKernelGGL((KER<16, 1, 8>), grid_, dim3(256), 0, st, a, loff);        \
+    else if ((sh).G == 32) hipLaunchKernelGGL((KER<32, 1, 8>), grid_, dim3(256), 0, st, a, loff);   \
+    else if ((sh).U == 1) hipLaunchKernelGGL((KER<64, 1, 8>), grid_, dim3(256), 0, st, a, loff);    \
+    else if ((sh).U == 2) hipLaunchKernelGGL((KER<64, 2, 4>), grid_, dim3(256), 0, st, a, loff);    \
+    else if ((sh).U == 4) hipLaunchKernelGGL((KER<64, 4, 2>), grid_, dim3(256), 0, st, a, loff);    \
+    else if ((sh).U == 8) hipLaunchKernelGGL((KER<64, 8, 1>), grid_, dim3(256), 0, st, a, loff);    \
+    else if ((sh).U == 16) hipLaunchKernelGGL((KER<64, 16, 1>), grid_, dim3(256), 0, st, a, loff);  \
+    else if ((sh).U == 24) hipLaunchKernelGGL((KER<64, 24, 1>), grid_, dim3(256), 0, st, a, loff);  \
+    else hipLaunchKernelGGL((KER<64, 32, 1>), grid_, dim3(256), 0, st, a, loff);                    \
+  } while (0)
+
 void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nmax, int nImax, int nBmax) {
+  RbShape sh;
+  if (rb_shape(nImax, &sh)) {
+    ND_RB_LAUNCH(k_nd_fwd_rb, sh, std::max(nBmax, 1), nnodes, st, a, loff);
+    return;
+  }
   const int G = group_for(nImax);
   const int rpb = rows_per_block(std::max(nBmax, 1), nnodes, G);
   const int gx = std::max(1, (nBmax + rpb - 1) / rpb);
@@ -364,6 +529,11 @@ void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, 
 }
 
 void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nmax) {
+  RbShape sh;
+  if (rb_shape(nmax, &sh)) {
+    ND_RB_LAUNCH(k_nd_bwd_rb, sh, nImax, nnodes, st, a, loff);
+    return;
+  }
   const int G = group_for(nmax);
   const int rpb = rows_per_block(nImax, nnodes, G);
   hipLaunchKernelGGL(k_nd_bwd, dim3((nImax + rpb - 1) / rpb, nnodes), dim3(256), size_t(nmax) * 8, st, a, loff, G, rpb);

@@ -110,6 +110,7 @@ void build_plan(const mpm_desc& d, Plan* p) {
   P.nodes.clear();
   P.dof_pool.clear();
   P.map_pool.clear();
+  P.inv_pool.clear();
   std::vector<int> node_level;
   std::function<std::pair<int, int>(Rect)> build = [&](Rect r) -> std::pair<int, int> {
     if (r.I1 - r.I0 == 1 && r.J1 - r.J0 == 1) return {-1 - (r.J0 * P.Sx + r.I0), 0};
@@ -149,6 +150,11 @@ void build_plan(const mpm_desc& d, Plan* p) {
       nd.nB_child[c] = int32_t(cbnd.size());
       for (int32_t g : cbnd) P.map_pool.push_back(pos.at(g));
     }
+    nd.inv_off = int32_t(P.inv_pool.size());
+    P.inv_pool.resize(P.inv_pool.size() + 2 * size_t(nd.n), -1);
+    for (int c = 0; c < 2; ++c)
+      for (int i = 0; i < nd.nB_child[c]; ++i)
+        P.inv_pool[nd.inv_off + size_t(c) * nd.n + P.map_pool[nd.map_off[c] + i]] = i;
     P.nodes.push_back(nd);
     return {int(P.nodes.size()) - 1, nd.level};
   };
@@ -238,6 +244,7 @@ void build_plan(const mpm_desc& d, Plan* p) {
     P.off_dsE = take(size_t(P.nsub) * (P.nc / P.band) * mf * mf * 8);
     P.off_nfac = take(size_t(P.nsub) * (P.nc / P.band) * mf * mf * 8);
     P.off_dsflag = take(size_t(P.nsub) * 4);
+    P.off_dslist = take(size_t(P.nsub) * 4);
   }
   P.off_ubnd = take(size_t(P.nsub) * P.nb * 8);
   P.off_leafK = take(size_t(P.nsub) * P.ndmax * P.ndmax * 8);
@@ -250,6 +257,7 @@ void build_plan(const mpm_desc& d, Plan* p) {
   P.off_nodes = take(std::max<size_t>(P.nodes.size(), 1) * sizeof(NodeDev));
   P.off_dofpool = take(std::max<size_t>(P.dof_pool.size(), 1) * 4);
   P.off_mappool = take(std::max<size_t>(P.map_pool.size(), 1) * 4);
+  P.off_invpool = take(std::max<size_t>(P.inv_pool.size(), 1) * 4);
   P.off_subdofs = take(P.sub_dofs.size() * 4);
   P.off_subndof = take(P.sub_ndof.size() * 4);
   P.level_off.assign(P.level_nodes.size() + 1, 0);

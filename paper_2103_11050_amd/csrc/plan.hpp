@@ -22,7 +22,8 @@ struct NodeDev {
   int32_t map_off[2];         // offsets of the children's extend-add maps into map_pool
   int32_t nB_child[2];        // boundary sizes of the children
   int32_t dof_off;            // offset of the node's front unknowns (I then B) in dof_pool
-  int32_t pad;
+  int32_t inv_off;            // offset of the inverse extend-add maps in inv_pool: for child c and
+                              // front index k, inv_pool[inv_off + c*n + k] = the child's index, or -1
   int64_t front_off;          // offset (doubles) of the n x n front
   int64_t fI_off;             // offset (doubles) of the eliminated part of the condensed rhs
   int64_t cB_off;             // offset (doubles) of the condensed rhs passed to the parent
@@ -48,6 +49,7 @@ struct Plan {
   std::vector<std::vector<int32_t>> level_nodes;  // level 1.. -> node ids
   std::vector<int32_t> dof_pool;
   std::vector<int32_t> map_pool;
+  std::vector<int32_t> inv_pool;
   int root = -1;
   int piv_b = 32;                     // pivot block of the blocked sweep
   std::vector<int32_t> level_nmax, level_nImax, level_nBmax;
@@ -55,6 +57,7 @@ struct Plan {
   size_t off_K, off_q, off_s, off_s2, off_kn, off_km, off_ux, off_uy, off_uxm, off_uym;
   size_t off_fac, off_dinv, off_S, off_h, off_vbnd, off_ubnd, off_leafK, off_leafr;
   size_t off_front, off_fI, off_cB, off_panel, off_y;
+  size_t off_invpool = 0;
   size_t off_nodes, off_dofpool, off_mappool, off_subdofs, off_subndof, off_levels;
   std::vector<int32_t> level_off;     // offsets of each level's node list in the uploaded level array
   std::vector<int32_t> level_flat;
@@ -67,6 +70,7 @@ struct Plan {
   size_t off_fuse_off = 0, off_fuse_nodes = 0;
   size_t off_dsE = 0, off_nfac = 0;   // downscale inverse blocks: scratch and the kept kappa^m ones
   size_t off_dsflag = 0;              // per subdomain: conductivity changed since the last update
+  size_t off_dslist = 0;              // the changed subdomains (count in the integer word after the error word)
   size_t off_red, off_scal;
   size_t n_red;               // doubles in the reduction scratch
   size_t total_bytes;
