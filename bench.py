@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_1024.json")
 # sources of the kernels each traffic record covers (the record is void once they change)
 KERNEL_SOURCES = {
-    "mpm_local": ["lines.hip", "lines.hpp", "device.hpp"],
+    "mpm_local": ["lines.hip", "lines.hpp", "device.hpp", "kernels.hpp"],
     "downscale": ["lines.hip", "lines.hpp", "device.hpp"],
     "flux": ["local.hip", "device.hpp"],
     "kappa_eps": ["local.hip"],
@@ -72,6 +72,23 @@ def algorithmic_bytes(cfg: dict) -> dict:
         # kept blocks; kappa, q; boundary fluxes (own + neighbour); velocity written
         "downscale": blocks + 16.0 * nc + 16.0 * nsub * nb + 8.0 * nfaces,
     }
+
+
+def phase_rooflines(alg: dict, sb: dict, prof: dict, cfg: dict, ms_step: float) -> dict:
+    """HBM rooflines of the interface sweeps (many level kernels each, so not a single-kernel
+    figure) and of the whole MPM-2P step (sum of the algorithmic bytes of its kernels; the
+    Neumann refactorisation of changed subdomains and the scalar reductions left out)."""
+    out = {}
+    for name, key in (("iface_fwd", "fwd"), ("iface_bwd", "bwd")):
+        if name in prof and prof[name][0] > 0:
+            gbs = sb[key] / (prof[name][0] * 1e-3) / 1e9
+            out[name] = {"bytes": sb[key], "ms": round(prof[name][0], 5), "achieved": round(gbs, 1),
+                         "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    step_bytes = sum(alg[k] * (cfg["cn"] if k == "sat_step" else 1) for k in alg) + sb["fwd"] + sb["bwd"]
+    gbs = step_bytes / (ms_step * 1e-3) / 1e9
+    out["step"] = {"bytes": step_bytes, "ms": round(ms_step, 4), "achieved": round(gbs, 1),
+                   "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def source_hash(kernel: str) -> str:
@@ -118,9 +135,11 @@ def make_traffic(fetch, write, cfetch, cwrite):
     for raw, name in TRAFFIC_NAMES.items():
         if raw not in f:
             continue
+        # median over the dispatches: the MPM-2P steps outnumber the MRCM updates in the
+        # profiled run (the downscaling of an MRCM update also writes the kept factors)
         fv, wv = f[raw], w.get(raw, [0.0])
         out["kernels"][name] = {
-            "fetch_bytes": sum(fv) / len(fv) * 1024 * kf, "write_bytes": sum(wv) / len(wv) * 1024 * kw,
+            "fetch_bytes": float(np.median(fv)) * 1024 * kf, "write_bytes": float(np.median(wv)) * 1024 * kw,
             "dispatches": len(fv), "source_hash": source_hash(name)}
     json.dump(out, open(TRAFFIC_FILE, "w"), indent=1)
     print(json.dumps(out, indent=1))
@@ -240,6 +259,7 @@ def main():
         mr.append(e0.elapsed_time(e1))
     mprof = run.profile(enable=False, reset=True)
     alg = algorithmic_bytes(cfg)
+    sb = run.solve_bytes()
     cand = {k: v for k, v in prof.items() if k in alg}
     dom = max(cand, key=lambda k: cand[k][0]) if cand else None
     roof = None
@@ -268,6 +288,7 @@ def main():
                    "step_latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
                    "step_latency_ms_p99": round(float(np.percentile(lat, 99)), 4)},
         "roofline": roof,
+        "phases": phase_rooflines(alg, sb, prof, cfg, 1e3 * elapsed / args.steps),
         "kernels_ms": {k: round(v[0], 5) for k, v in sorted(prof.items())},
         "mrcm_update_ms": round(float(np.median(mr)), 4),
         "mrcm_kernels_ms": {k: round(v[0], 5) for k, v in sorted(mprof.items())},

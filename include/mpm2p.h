@@ -157,6 +157,12 @@ const char* mpm_status_str(mpm_status status);
 mpm_status mpm_plan_info(const mpm_run* run, int64_t* n_sub, int64_t* n_iface, int64_t* n_nodes,
                          int64_t* n_levels);
 
+/* Bytes of the interface factorisation (Section 5.3, eq:mrc2) that one solve reads: the forward
+ * sweep's BI blocks and the backward sweep's [II IB] rows, summed over the nested-dissection
+ * nodes, and the size of all fronts (host memory; any pointer may be NULL). */
+mpm_status mpm_plan_solve_bytes(const mpm_run* run, int64_t* fwd_bytes, int64_t* bwd_bytes,
+                                int64_t* front_bytes);
+
 /* Average duration in milliseconds of each kernel class over the calls since the last reset,
  * measured with HIP events on the run's stream when profiling is enabled. names/ms/count are
  * host arrays of length cap; returns the number of classes written in *n. */

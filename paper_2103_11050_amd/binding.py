@@ -64,6 +64,7 @@ _SIGS = {
     "mpm_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
     "mpm_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
     "mpm_plan_info": (ctypes.c_int32, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 4),
+    "mpm_plan_solve_bytes": (ctypes.c_int32, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 3),
     "mpm_profile": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
@@ -198,6 +199,11 @@ class Run:
         v = [ctypes.c_int64() for _ in range(4)]
         _check(load().mpm_plan_info(self.h, *[ctypes.byref(x) for x in v]), "mpm_plan_info")
         return dict(n_sub=v[0].value, n_iface=v[1].value, n_nodes=v[2].value, n_levels=v[3].value)
+
+    def solve_bytes(self) -> dict:
+        v = [ctypes.c_int64() for _ in range(3)]
+        _check(load().mpm_plan_solve_bytes(self.h, *[ctypes.byref(x) for x in v]), "mpm_plan_solve_bytes")
+        return dict(fwd=v[0].value, bwd=v[1].value, front=v[2].value)
 
     def profile(self, enable: bool = True, reset: bool = True) -> dict:
         cap = 64

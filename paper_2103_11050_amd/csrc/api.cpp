@@ -71,9 +71,10 @@ struct mpm_run {
   double* s_base = nullptr;
   int device = 0;
   char* ws = nullptr;
-  double *K, *q, *s, *s2, *kn, *km, *ux, *uy, *uxm, *uym, *fac, *S, *h, *vbnd, *ubnd, *leafK, *leafr;
-  double *front, *fI, *cB, *panel, *y, *red, *scal, *dsE, *nfac;
+  double *K, *q, *s, *s2, *kn, *km, *ux, *uy, *uxm, *uym, *fac, *S, *h, *vbnd, *ubnd, *leafK;
+  double *front, *fI, *slots, *panel, *y, *red, *scal, *dsE, *nfac;
   int32_t* err;
+  const LeafUp* leafup = nullptr;
   int32_t* dsflag = nullptr;
   int32_t* dslist = nullptr;
   int32_t* dscount = nullptr;          // number of entries of dslist (device)
@@ -90,7 +91,9 @@ struct mpm_run {
   double eps_prev = 0.0;       // epsilon after the last update (known on the host)
   bool eps_pending = false;    // epsilon of the last update still in flight
   int last_branch = MPM_FORCE_MRCM;
-  double* pinned = nullptr;    // [eps_num, eps_den] copied after the kappa kernel
+  double* pinned = nullptr;    // [eps_num, eps_den], written by the eps reduction kernel
+  double* pinned_dev = nullptr;  // the same memory as the device sees it
+  int64_t eps_seq = 0;           // sequence number of the latest kappa launch
   hipEvent_t ev_eps = nullptr;
   // profiling with HIP events on the run's stream
   bool prof = false;
@@ -173,14 +176,31 @@ double eps_from(const mpm_run* r, double num, double den) {
   return std::sqrt(num) / std::sqrt(den);
 }
 
-// kappa^n = lambda(s) K and the partial sums of epsilon against kappa^m, copied to pinned host
-// memory (the caller records ev_eps after it).
+// kappa^n = lambda(s) K and the sums of epsilon against kappa^m, also written by the reduction
+// kernel into pinned host memory (the caller records ev_eps after it).
 mpm_status kappa_and_eps_nodes(mpm_run* r) {
   {
     Scope sc(r, "kappa_eps");
-    launch_kappa(r->st, r->g, r->s, r->K, r->kn, r->km, r->red, r->scal, r->dsflag, r->dslist, r->dscount);
+    launch_kappa(r->st, r->g, r->s, r->K, r->kn, r->km, r->red, r->scal, r->dsflag, r->dslist, r->dscount,
+                 r->dscount + 1, r->pinned_dev);
   }
-  HIPCHK(r, hipMemcpyAsync(r->pinned, r->scal + SC_EPS_NUM, 2 * sizeof(double), hipMemcpyDeviceToHost, r->st));
+  r->eps_seq += 1;
+  return MPM_OK;
+}
+
+// Host copy of the epsilon sums of the latest kappa launch. The reduction kernel writes them
+// to pinned host memory with its sequence number; after the event, a number other than the
+// expected one means the data has not reached the host yet: drain the stream and look again.
+mpm_status wait_eps(mpm_run* r) {
+  HIPCHK(r, hipEventSynchronize(r->ev_eps));
+  volatile double* p = r->pinned;
+  if (p[2] != double(r->eps_seq)) {
+    HIPCHK(r, hipStreamSynchronize(r->st));
+    if (p[2] != double(r->eps_seq)) {
+      r->last_error = "epsilon sums did not reach host memory";
+      return MPM_EHIP;
+    }
+  }
   return MPM_OK;
 }
 
@@ -228,27 +248,26 @@ hipGraphExec_t capture_and_launch(mpm_run* r, F&& body) {
   return exec;
 }
 
+LeafOut leaf_dest(const mpm_run* r) { return LeafOut{r->slots, r->leafup, r->nd.map_pool}; }
+
 void nd_solve(mpm_run* r) {
   const Plan& P = r->P;
   const int L = int(P.level_nodes.size()) - 1;
-  const int nroots = int(P.fuse_off.size()) - 1;
   {
     Scope sc(r, "iface_fwd");
-    if (nroots > 0) launch_nd_fused_fwd(r->st, r->nd, nroots, P.fuse_nmax);
-    for (int l = P.fuse_level + 1; l <= L; ++l) {
+    for (int l = 1; l < L; ++l) {
       const int nn = int(P.level_nodes[l].size());
       if (!nn) continue;
-      launch_nd_level_fwd(r->st, r->nd, P.level_off[l], nn, P.level_nmax[l], P.level_nImax[l], P.level_nBmax[l]);
+      launch_nd_level_fwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l], P.level_nBmax[l]);
     }
   }
   {
     Scope sc(r, "iface_bwd");
-    for (int l = L; l > P.fuse_level; --l) {
+    for (int l = L; l >= 1; --l) {
       const int nn = int(P.level_nodes[l].size());
       if (!nn) continue;
-      launch_nd_level_bwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l], P.level_nmax[l]);
+      launch_nd_level_bwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l], P.level_nmax[l], l == L ? 1 : 0);
     }
-    if (nroots > 0) launch_nd_fused_bwd(r->st, r->nd, nroots, P.fuse_nmax);
   }
 }
 
@@ -285,7 +304,7 @@ mpm_status mrcm_update(mpm_run* r) {
   bool have_fac;
   {
     Scope sc(r, "basis");
-    have_fac = launch_basis(r->st, r->g, r->km, r->q, r->S, r->h, r->leafK, r->leafr, r->fac, r->err);
+    have_fac = launch_basis(r->st, r->g, r->km, r->q, r->S, r->h, r->leafK, leaf_dest(r), r->fac, r->err);
   }
   if (!have_fac) {
     Scope sc(r, "line_factor");
@@ -303,17 +322,23 @@ mpm_status mrcm_update(mpm_run* r) {
 
 // MPM-2P: trivial-Robin solve with the stored kappa^m factors, interface solve with the stored
 // factorisation, reconstruction, downscaling with kappa^n.
-mpm_status mpm_update_body(mpm_run* r) {
-  {
-    Scope sc(r, "mpm_local");
-    launch_mpm_local(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac, r->h, r->vbnd, r->leafr);
-  }
+mpm_status mpm_update_body(mpm_run* r, bool capturing) {
   // kappa^n Neumann factors of the changed subdomains on the second stream, overlapped with
-  // the interface solve (whose level kernels leave most of the chip idle)
-  HIPCHK(r, hipEventRecord(r->ev_fork, r->st));
-  HIPCHK(r, hipStreamWaitEvent(r->st2, r->ev_fork, 0));
+  // the local and interface solves. It forks at the epsilon event, recorded right after the
+  // conductivity and its changed-subdomain list (one marker on the main stream, not two).
+  // (Under graph capture the fork must be recorded inside the capture: a marker of its own.)
+  if (capturing) {
+    HIPCHK(r, hipEventRecord(r->ev_fork, r->st));
+    HIPCHK(r, hipStreamWaitEvent(r->st2, r->ev_fork, 0));
+  } else {
+    HIPCHK(r, hipStreamWaitEvent(r->st2, r->ev_eps, 0));
+  }
   launch_ds_factor(r->st2, r->g, r->kn, r->dsE, r->dslist, r->dscount, r->err);
   HIPCHK(r, hipEventRecord(r->ev_join, r->st2));
+  {
+    Scope sc(r, "mpm_local");
+    launch_mpm_local(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac, r->h, r->vbnd, leaf_dest(r));
+  }
   nd_solve(r);
   HIPCHK(r, hipStreamWaitEvent(r->st, r->ev_join, 0));
   finish_velocity(r, r->kn, 1, 0);
@@ -326,11 +351,11 @@ mpm_status mpm_update(mpm_run* r) {
       HIPCHK(r, hipGraphLaunch(r->g_mpm, r->st));
       return MPM_OK;
     }
-    r->g_mpm = capture_and_launch(r, [&] { return mpm_update_body(r); });
+    r->g_mpm = capture_and_launch(r, [&] { return mpm_update_body(r, true); });
     if (r->g_mpm) return MPM_OK;
     r->use_graphs = false;   // capture unavailable: stay eager
   }
-  return mpm_update_body(r);
+  return mpm_update_body(r, false);
 }
 
 mpm_status velocity_update(mpm_run* r, int32_t force, bool kappa_done = false) {
@@ -340,7 +365,8 @@ mpm_status velocity_update(mpm_run* r, int32_t force, bool kappa_done = false) {
   if (st) return st;
   double decide;
   if (r->P.d.switch_rule == MPM_SWITCH_TEXT) {
-    HIPCHK(r, hipEventSynchronize(r->ev_eps));
+    st = wait_eps(r);
+    if (st) return st;
     decide = eps_from(r, r->pinned[0], r->pinned[1]);
   } else {
     decide = r->eps_prev;
@@ -359,9 +385,10 @@ mpm_status velocity_update(mpm_run* r, int32_t force, bool kappa_done = false) {
   r->last_branch = branch;
   r->te += 1;
   if (r->eps_pending && r->P.d.switch_rule == MPM_SWITCH_ALG1) {
-    // epsilon of this update is needed by the next decision only; the copy was enqueued
-    // before the solve, so waiting on its event does not drain the stream
-    HIPCHK(r, hipEventSynchronize(r->ev_eps));
+    // epsilon of this update is needed by the next decision only; it was reduced before the
+    // solve, so waiting for it does not drain the stream
+    st = wait_eps(r);
+    if (st) return st;
     r->eps_prev = eps_from(r, r->pinned[0], r->pinned[1]);
     r->eps_pending = false;
   } else if (r->eps_pending) {
@@ -402,6 +429,7 @@ mpm_status step(mpm_run* r, int32_t force) {
   const int cn = r->P.d.cn;
   if (r->g_trans[par]) {
     HIPCHK(r, hipGraphLaunch(r->g_trans[par], r->st));
+    r->eps_seq += 1;
     for (int k = 0; k < cn; ++k) std::swap(r->s, r->s2);
   } else {
     double* s0 = r->s;
@@ -471,7 +499,7 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   r->kn = D(P.off_kn); r->km = D(P.off_km); r->ux = D(P.off_ux); r->uy = D(P.off_uy);
   r->uxm = D(P.off_uxm); r->uym = D(P.off_uym); r->fac = D(P.off_fac); r->S = D(P.off_S);
   r->h = D(P.off_h); r->vbnd = D(P.off_vbnd); r->ubnd = D(P.off_ubnd); r->leafK = D(P.off_leafK);
-  r->leafr = D(P.off_leafr); r->front = D(P.off_front); r->fI = D(P.off_fI); r->cB = D(P.off_cB);
+  r->front = D(P.off_front); r->fI = D(P.off_fI); r->slots = D(P.off_slot);
   r->panel = D(P.off_panel); r->y = D(P.off_y); r->red = D(P.off_red); r->scal = D(P.off_scal);
   r->dsE = D(P.off_dsE); r->nfac = D(P.off_nfac);
   r->s_base = r->s;
@@ -485,11 +513,11 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   r->nd.dof_pool = reinterpret_cast<const int32_t*>(r->ws + P.off_dofpool);
   r->nd.map_pool = reinterpret_cast<const int32_t*>(r->ws + P.off_mappool);
   r->nd.inv_pool = reinterpret_cast<const int32_t*>(r->ws + P.off_invpool);
-  r->nd.front = r->front; r->nd.fI = r->fI; r->nd.cB = r->cB; r->nd.panel = r->panel;
-  r->nd.leafK = r->leafK; r->nd.leafr = r->leafr; r->nd.y = r->y; r->nd.ndmax = P.ndmax;
+  r->nd.front = r->front; r->nd.fI = r->fI; r->nd.slots = r->slots; r->nd.panel = r->panel;
+  r->nd.leafK = r->leafK; r->nd.y = r->y; r->nd.ndmax = P.ndmax;
   r->nd.piv_b = P.piv_b; r->nd.err = r->err;
-  r->nd.fuse_off = reinterpret_cast<const int32_t*>(r->ws + P.off_fuse_off);
-  r->nd.fuse_nodes = reinterpret_cast<const int32_t*>(r->ws + P.off_fuse_nodes);
+  r->nd.lnodes = reinterpret_cast<const NodeDev*>(r->ws + P.off_lnodes);
+  r->leafup = reinterpret_cast<const LeafUp*>(r->ws + P.off_leafup);
   r->M = P.d.mu_o / P.d.mu_w;
   r->fmax_deriv = max_fprime(r->M);
   r->area = P.d.lx * P.d.ly;
@@ -519,15 +547,25 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
                     in(r->km, cb) && in(r->ux, fx) && in(r->uy, fy) && in(r->uxm, fx) && in(r->uym, fy) &&
                     in(r->S, ns * P.nb * P.nb * 8) && in(r->h, ns * P.nb * 8) && in(r->vbnd, ns * P.nb * 8) &&
                     in(r->ubnd, ns * P.nb * 8) && in(r->leafK, ns * P.ndmax * P.ndmax * 8) &&
-                    in(r->leafr, ns * P.ndmax * 8) && in(r->red, P.n_red * 8) && in(r->scal, SC_COUNT * 8) &&
-                    in(r->err, 4) && in(r->dscount, 4) && in(r->dsflag, ns * 4) && in(r->dslist, ns * 4) &&
-                    in(r->y, size_t(std::max(P.n_iface, 1)) * 8) && in(r->subdofs_d, ns * P.ndmax * 4);
+                    in(r->red, P.n_red * 8) && in(r->scal, SC_COUNT * 8) &&
+                    in(r->err, 12) && in(r->dscount, 8) && in(r->dsflag, ns * 4) && in(r->dslist, ns * 4) &&
+                    in(r->y, size_t(std::max(P.n_iface, 1)) * 8) && in(r->subdofs_d, ns * P.ndmax * 4) &&
+                    in(r->slots, size_t(std::max<int64_t>(P.slot_doubles, 1)) * 8) &&
+                    in(r->leafup, ns * sizeof(LeafUp)) &&
+                    in(r->nd.lnodes, std::max<size_t>(P.lnodes.size(), 1) * sizeof(NodeDev));
     if (!ok) return fail(MPM_EINVAL);
   }
   if (hipHostMalloc(reinterpret_cast<void**>(&r->pinned), 64, hipHostMallocDefault) != hipSuccess) return fail(MPM_ENOMEM);
-  if (hipEventCreateWithFlags(&r->ev_eps, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
-  if (hipEventCreateWithFlags(&r->ev_fork, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
-  if (hipEventCreateWithFlags(&r->ev_join, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
+  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&r->pinned_dev), r->pinned, 0) != hipSuccess ||
+      !r->pinned_dev)
+    return fail(MPM_EHIP);
+  r->pinned[0] = r->pinned[1] = r->pinned[2] = 0.0;
+  // events that only order work on the device (and the epsilon event, whose host-side data
+  // is checked by sequence number): device-scope release, no cache writeback to system scope
+  const unsigned ev_flags = hipEventDisableTiming | hipEventReleaseToDevice;
+  if (hipEventCreateWithFlags(&r->ev_eps, ev_flags) != hipSuccess) return fail(MPM_EHIP);
+  if (hipEventCreateWithFlags(&r->ev_fork, ev_flags) != hipSuccess) return fail(MPM_EHIP);
+  if (hipEventCreateWithFlags(&r->ev_join, ev_flags) != hipSuccess) return fail(MPM_EHIP);
   if (hipEventCreateWithFlags(&r->ev_in, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
   if (hipEventCreateWithFlags(&r->ev_out, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
   // Graph replay is opt-in: on gfx950 it measured slower than eager launches for this step.
@@ -551,8 +589,9 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   };
   if (up(P.off_nodes, P.nodes.data(), P.nodes.size() * sizeof(NodeDev)) ||
       up(P.off_levels, P.level_flat.data(), P.level_flat.size() * 4) ||
-      up(P.off_fuse_off, P.fuse_off.data(), P.fuse_off.size() * 4) ||
-      up(P.off_fuse_nodes, P.fuse_nodes.data(), P.fuse_nodes.size() * 4) ||
+      up(P.off_lnodes, P.lnodes.data(), P.lnodes.size() * sizeof(NodeDev)) ||
+      up(P.off_leafup, P.leafup.data(), P.leafup.size() * sizeof(LeafUp)) ||
+      hipMemsetAsync(r->slots, 0, size_t(std::max<int64_t>(P.slot_doubles, 1)) * 8, r->st) ||
       up(P.off_dofpool, P.dof_pool.data(), P.dof_pool.size() * 4) ||
       up(P.off_mappool, P.map_pool.data(), P.map_pool.size() * 4) ||
       up(P.off_invpool, P.inv_pool.data(), P.inv_pool.size() * 4) ||
@@ -709,6 +748,19 @@ mpm_status mpm_destroy(mpm_run* r) {
   if (errw & ERR_NOTSPD) return MPM_ENOTSPD;
   if (errw & ERR_SINGULAR) return MPM_ESINGULAR;
   if (errw) return MPM_ENONFINITE;
+  return MPM_OK;
+}
+
+mpm_status mpm_plan_solve_bytes(const mpm_run* r, int64_t* fwd, int64_t* bwd, int64_t* front) {
+  if (!r) return MPM_EINVAL;
+  int64_t f = 0, b = 0;
+  for (const NodeDev& n : r->P.nodes) {
+    f += int64_t(n.nB) * n.nI * 8;
+    b += int64_t(n.nI) * n.n * 8;
+  }
+  if (fwd) *fwd = f;
+  if (bwd) *bwd = b;
+  if (front) *front = r->P.front_doubles * 8;
   return MPM_OK;
 }
 

@@ -82,12 +82,13 @@ __device__ __forceinline__ double bweight(const Geo& g, const BFace& f, bool is_
 
 // One wavefront per subdomain. Writes S (nb x nb, row-major per subdomain), h, the interface
 // block K_i = B^T S B - D_i with its right-hand side B^T h (eq:mrc2 with the Robin rows
-// negated), and, with store_fac, the line-block inverses D_j^-1 in the layout the MPM-2P solve
-// reads (E[sub][line][t][lane], contiguous line-block layout, lines padded to 16).
+// negated; the right-hand side goes into the parent's slot of the interface solve), and, with
+// store_fac, the line-block inverses D_j^-1 in the layout the MPM-2P solve reads
+// (E[sub][line][t][lane], contiguous line-block layout, lines padded to 16).
 __global__ void __launch_bounds__(64)
 k_basis_mfma(Geo g, const double* __restrict__ kap, const double* __restrict__ q, double* __restrict__ Sg,
-             double* __restrict__ hg, double* __restrict__ leafK, double* __restrict__ leafr,
-             double* __restrict__ fac, int store_fac, int32_t* err) {
+             double* __restrict__ hg, double* __restrict__ leafK, LeafOut lo, double* __restrict__ fac,
+             int store_fac, int32_t* err) {
   __shared__ double kl[256], tE[256], tN[256], dg[256], rhs0[256], wsh[64], hsh[64];
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
@@ -283,7 +284,7 @@ k_basis_mfma(Geo g, const double* __restrict__ kap, const double* __restrict__ q
       const BFace ff = bface(g, I, J, x);
       v += bweight(g, ff, a & 1, kl[loc_index(g, ff.i, ff.j)]) * hsh[x];
     }
-    leafr[size_t(sub) * g.ndmax + a] = v;
+    leaf_out(lo, sub, a, v);
   }
 }
 
@@ -291,9 +292,9 @@ k_basis_mfma(Geo g, const double* __restrict__ kap, const double* __restrict__ q
 
 // Returns whether the kappa^m line-block inverses were written (lines of 9..16 cells).
 bool launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
-                  double* leafK, double* leafr, double* fac, int32_t* err) {
+                  double* leafK, LeafOut lo, double* fac, int32_t* err) {
   const int store = g.band > 8 ? 1 : 0;
-  hipLaunchKernelGGL(k_basis_mfma, dim3(g.nsub), dim3(64), 0, st, g, kap, q, S, h, leafK, leafr, fac, store, err);
+  hipLaunchKernelGGL(k_basis_mfma, dim3(g.nsub), dim3(64), 0, st, g, kap, q, S, h, leafK, lo, fac, store, err);
   return store != 0;
 }
 

@@ -141,18 +141,33 @@ __host__ __device__ __forceinline__ double harm_ratio(double knc, double knd, do
 __device__ __forceinline__ void set_error(int32_t* err, int32_t bits) { atomicOr(err, bits); }
 
 // Transport sub-step from the maximum outflow rate and the boundary inflow, reduced in a fixed
-// order from per-subdomain partials (run by one workgroup of 256 threads).
+// order from per-subdomain partials (run by one workgroup of 256 threads; each thread issues
+// its loads in batches of 16 before adding them).
 __device__ __forceinline__ void reduce_dt(int nsub, const double* red_rate, const double* red_qin, double cfl,
                                           double fmax_deriv, double* scal, double* sm, double* ss) {
+  constexpr int B = 16;
   double m = 0.0, s = 0.0;
-  for (int i = threadIdx.x; i < nsub; i += blockDim.x) {
-    m = fmax(m, red_rate[i]);
-    s += red_qin[i];
+  for (int base = 0; base < nsub; base += 256 * B) {
+    double vr[B], vq[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int i = base + threadIdx.x + 256 * u;
+      const int ic = i < nsub ? i : 0;
+      vr[u] = red_rate[ic];
+      vq[u] = red_qin[ic];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      if (base + int(threadIdx.x) + 256 * u < nsub) {
+        m = fmax(m, vr[u]);
+        s += vq[u];
+      }
+    }
   }
   sm[threadIdx.x] = m;
   ss[threadIdx.x] = s;
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+  for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
       sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
       ss[threadIdx.x] += ss[threadIdx.x + w];

@@ -264,8 +264,7 @@ template <int MF, int NL>
 __global__ void __launch_bounds__(64)
 k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict__ kap_m,
                const double* __restrict__ uxm, const double* __restrict__ uym, const double* __restrict__ q,
-               const double* __restrict__ fac, double* __restrict__ hg, double* __restrict__ vbnd,
-               double* __restrict__ leafr) {
+               const double* __restrict__ fac, double* __restrict__ hg, double* __restrict__ vbnd, LeafOut lo) {
   __shared__ double knt[18 * 18], kmt[18 * 18], uxs[16 * 17], uys[17 * 16], qs[256];
   __shared__ double kl[256], x[256], hsh[64], wsh[256], tE[256], tN[256], dg[256];
   const int sub = blockIdx.x;
@@ -366,7 +365,7 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
       const double wgt = (a & 1) ? 1.0 : -ff.sgn * robin_beta(g, ff, kl[loc_index(g, ff.i, ff.j)]);
       v += wgt * hsh[xx];
     }
-    leafr[size_t(sub) * g.ndmax + a] = v;
+    leaf_out(lo, sub, a, v);
   }
 }
 
@@ -514,8 +513,8 @@ void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double*
 
 void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                       const double* uym, const double* q, const double* fac, double* h, double* vbnd,
-                      double* leafr) {
-  MPM_LB_DISPATCH(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, leafr);
+                      LeafOut lo) {
+  MPM_LB_DISPATCH(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, lo);
 }
 
 void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, double* Escr, const int32_t* list,

@@ -55,14 +55,30 @@ k_kappa(Geo g, const double* __restrict__ s, const double* __restrict__ K, doubl
   }
 }
 
-// Fixed-order reduction of the epsilon partial sums into the scalar block.
+// Fixed-order reduction of the epsilon partial sums into the scalar block; the two sums are
+// also written to host memory for the switch decision.
 __global__ void __launch_bounds__(256) k_reduce_eps(int nblocks, const double* __restrict__ red,
-                                                    double* __restrict__ scal) {
+                                                    double* __restrict__ scal, int32_t* __restrict__ seq,
+                                                    double* __restrict__ host) {
+  constexpr int B = 16;
   __shared__ double sa[256], sb[256];
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nblocks; i += 256) {
-    a += red[2 * i];
-    b += red[2 * i + 1];
+  for (int base = 0; base < nblocks; base += 256 * B) {
+    double va[B], vb[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int i = base + threadIdx.x + 256 * u;
+      const int ic = i < nblocks ? i : 0;
+      va[u] = red[2 * ic];
+      vb[u] = red[2 * ic + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      if (base + int(threadIdx.x) + 256 * u < nblocks) {
+        a += va[u];
+        b += vb[u];
+      }
+    }
   }
   sa[threadIdx.x] = a;
   sb[threadIdx.x] = b;
@@ -77,6 +93,11 @@ __global__ void __launch_bounds__(256) k_reduce_eps(int nblocks, const double* _
   if (threadIdx.x == 0) {
     scal[SC_EPS_NUM] = sa[0];
     scal[SC_EPS_DEN] = sb[0];
+    const int32_t q = *seq + 1;
+    *seq = q;
+    host[0] = sa[0];
+    host[1] = sb[0];
+    host[2] = double(q);
   }
 }
 
@@ -123,9 +144,11 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
     if (bf.kind == FACE_NEU) {
       u = bf.value;
     } else {
-      const double* Srow = Sg + (size_t(sub) * nb + f) * nb;
+      // S is symmetric: column f is read, coalesced over the lanes
+      const double* Ss = Sg + size_t(sub) * nb * nb + f;
       double acc = hg[size_t(sub) * nb + f];
-      for (int t = 0; t < nb; ++t) acc -= Srow[t] * r[t];
+#pragma unroll 16
+      for (int t = 0; t < nb; ++t) acc -= Ss[size_t(t) * nb] * r[t];
       u = acc / bf.flen;
       if (with_v) u += vbnd[size_t(sub) * nb + f];
     }
@@ -136,9 +159,10 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
 // ---------------------------------------------------------------------- launchers
 
 void launch_kappa(hipStream_t st, const Geo& g, const double* s, const double* K, double* kn, const double* km,
-                  double* red, double* scal, int32_t* flag, int32_t* list, int32_t* count) {
+                  double* red, double* scal, int32_t* flag, int32_t* list, int32_t* count, int32_t* seq,
+                  double* host) {
   hipLaunchKernelGGL(k_kappa, dim3(g.nsub), dim3(256), 0, st, g, s, K, kn, km, red, flag, list, count);
-  hipLaunchKernelGGL(k_reduce_eps, dim3(1), dim3(256), 0, st, g.nsub, red, scal);
+  hipLaunchKernelGGL(k_reduce_eps, dim3(1), dim3(256), 0, st, g.nsub, red, scal, seq, host);
 }
 
 void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double cfl,

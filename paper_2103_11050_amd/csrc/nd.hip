@@ -7,11 +7,14 @@
 //
 // Recursive bisection of the subdomain grid gives a tree; a node's front holds the unknowns
 // of its separator (I) and of its outer boundary (B). Factorisation, level by level from the
-// leaves: extend-add the children's Schur complements into the front, then sweep the I
+// leaves: assemble the front from the children's Schur complements, then sweep the I
 // unknowns in blocks of piv_b. After the sweep the front holds
 //   II = -F_II^-1,  IB = F_II^-1 F_IB,  BI = F_BI F_II^-1,  BB = F_BB - F_BI F_II^-1 F_IB.
 // Solve: forward (leaves to root) c_B = f_B - BI f_I; backward (root to leaves)
 //   x_I = -II f_I - IB x_B.
+// In the forward sweep vectors travel between levels through slots (see NodeDev): a node's f
+// is the sum of its two child slots, so every load of a forward level kernel is independent of
+// the others. The backward sweep gathers x_B from the solution vector.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -37,33 +40,34 @@ __device__ __forceinline__ const double* child_S(const NdArgs& a, const NodeDev&
   return a.front + cn.front_off;
 }
 
-__device__ __forceinline__ const double* child_c(const NdArgs& a, const NodeDev& nd, int c) {
-  const int ch = nd.child[c];
-  if (ch < 0) return a.leafr + size_t(-1 - ch) * a.ndmax;
-  return a.cB + a.nodes[ch].cB_off;
-}
-
 }  // namespace
 
-__global__ void k_nd_zero(NdArgs a, int loff) {
+// Front assembly (extend-add of both children's Schur complements, zero elsewhere), written
+// row by row and gathered through the inverse maps: entry (k, l) is
+// S0[inv0 k][inv0 l] + S1[inv1 k][inv1 l] with absent terms left out (child 0 first, the same
+// sum as adding the children one after the other into a zeroed front).
+constexpr int ASM_ROWS = 8;
+__global__ void __launch_bounds__(256) k_nd_assemble(NdArgs a, int loff) {
   const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
-  const int64_t n2 = int64_t(nd.n) * nd.n;
+  const int n = nd.n;
+  const int k0 = blockIdx.x * ASM_ROWS;
+  if (k0 >= n) return;
+  int st0, of0, st1, of1;
+  const double* S0 = child_S(a, nd, 0, &st0, &of0);
+  const double* S1 = child_S(a, nd, 1, &st1, &of1);
+  const int32_t* inv0 = a.inv_pool + nd.inv_off;
+  const int32_t* inv1 = inv0 + n;
   double* F = a.front + nd.front_off;
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n2; e += int64_t(gridDim.x) * blockDim.x) F[e] = 0.0;
-}
-
-// Adds child c's Schur complement into the parent front (one child per launch: deterministic).
-__global__ void k_nd_extend(NdArgs a, int loff, int c) {
-  const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
-  const int nBc = nd.nB_child[c];
-  int stride, off;
-  const double* S = child_S(a, nd, c, &stride, &off);
-  const int32_t* map = a.map_pool + nd.map_off[c];
-  double* F = a.front + nd.front_off;
-  const int64_t tot = int64_t(nBc) * nBc;
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < tot; e += int64_t(gridDim.x) * blockDim.x) {
-    const int i = int(e / nBc), j = int(e % nBc);
-    F[int64_t(map[i]) * nd.n + map[j]] += S[int64_t(off + i) * stride + off + j];
+  const int k1 = min(n, k0 + ASM_ROWS);
+  for (int l = threadIdx.x; l < n; l += 256) {
+    const int b0 = inv0[l], b1 = inv1[l];
+    for (int k = k0; k < k1; ++k) {
+      const int a0 = inv0[k], a1 = inv1[k];
+      double v = 0.0;
+      if (a0 >= 0 && b0 >= 0) v = S0[int64_t(of0 + a0) * st0 + of0 + b0];
+      if (a1 >= 0 && b1 >= 0) v += S1[int64_t(of1 + a1) * st1 + of1 + b1];
+      F[int64_t(k) * n + l] = v;
+    }
   }
 }
 
@@ -208,261 +212,141 @@ __global__ void __launch_bounds__(256) k_nd_update(NdArgs a, int loff, int kb) {
   }
 }
 
-// Forward, one level. Every workgroup gathers its node's front right-hand side f (children's
-// condensed vectors, child 0 then child 1) into LDS; workgroup 0 stores f_I for the backward
-// pass; then groups of G lanes form c_B[j] = f_B[j] - (BI f_I)[j] for rows j of the stored BI
-// block (row-major, so each group reads one contiguous row).
-__global__ void __launch_bounds__(256) k_nd_fwd(NdArgs a, int loff, int G, int rows_per_block) {
-  extern __shared__ double f[];
-  const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
-  const int r0 = blockIdx.x * rows_per_block;
-  if (r0 >= max(nd.nB, 1)) return;
-  for (int i = threadIdx.x; i < nd.n; i += blockDim.x) f[i] = 0.0;
-  __syncthreads();
-  for (int c = 0; c < 2; ++c) {
-    const double* src = child_c(a, nd, c);
-    const int32_t* map = a.map_pool + nd.map_off[c];
-    for (int i = threadIdx.x; i < nd.nB_child[c]; i += blockDim.x) f[map[i]] += src[i];
-    __syncthreads();
-  }
-  if (blockIdx.x == 0)
-    for (int i = threadIdx.x; i < nd.nI; i += blockDim.x) a.fI[nd.fI_off + i] = f[i];
-  const int gl = threadIdx.x % G, grp = threadIdx.x / G;
-  const int r1 = min(nd.nB, r0 + rows_per_block);
-  for (int j = r0 + grp; j < r1; j += 256 / G) {
-    const double* row = a.front + nd.front_off + int64_t(nd.nI + j) * nd.n;
-    double acc4[4] = {0, 0, 0, 0};
-    int k = gl;
-    for (; k + 3 * G < nd.nI; k += 4 * G) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc4[u] += row[k + u * G] * f[k + u * G];
-    }
-    for (; k < nd.nI; k += G) acc4[0] += row[k] * f[k];
-    double acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
-    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (gl == 0) a.cB[nd.cB_off + j] = f[nd.nI + j] - acc;
-  }
+// Load at a 32-bit element offset from a base that is uniform over the wavefront (the byte
+// offset stays 32-bit, so the base can live in scalar registers).
+__device__ __forceinline__ double ld32(const double* base, uint32_t elem) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + (elem << 3));
 }
 
-// Backward, one level: v = [f_I; x_B] in LDS (x_B gathered from the solution by the node's
-// unknown list), then x_I = -[II IB] v, one group of G lanes per row.
-__global__ void __launch_bounds__(256) k_nd_bwd(NdArgs a, int loff, int G, int rows_per_block) {
-  extern __shared__ double v[];
-  const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
-  const int r0 = blockIdx.x * rows_per_block;
-  if (r0 >= nd.nI) return;
-  const int32_t* dofs = a.dof_pool + nd.dof_off;
-  for (int i = threadIdx.x; i < nd.nI; i += blockDim.x) v[i] = a.fI[nd.fI_off + i];
-  for (int i = threadIdx.x; i < nd.nB; i += blockDim.x) v[nd.nI + i] = a.y[dofs[nd.nI + i]];
-  __syncthreads();
-  const int gl = threadIdx.x % G, grp = threadIdx.x / G;
-  const int r1 = min(nd.nI, r0 + rows_per_block);
-  for (int r = r0 + grp; r < r1; r += 256 / G) {
-    const double* row = a.front + nd.front_off + int64_t(r) * nd.n;
-    double acc4[4] = {0, 0, 0, 0};
-    int k = gl;
-    for (; k + 3 * G < nd.n; k += 4 * G) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc4[u] += row[k + u * G] * v[k + u * G];
-    }
-    for (; k < nd.n; k += G) acc4[0] += row[k] * v[k];
-    double acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
-    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (gl == 0) a.y[dofs[r]] = -acc;
-  }
-}
+// Forward and backward sweeps, one launch per level. A workgroup takes RP x (256/G) rows of
+// one node, G lanes per row, U columns per lane (longer rows in chunks of G*U), and issues
+// every load of its block and of the vector it multiplies before the first use: one memory
+// round trip per level. Loads are unconditional at clamped (valid) addresses and masked
+// afterwards so that the compiler keeps them all in flight; no LDS and no barriers.
 
-// Register-batched forms of the two sweeps. A workgroup takes RP x (256/G) rows of one node,
-// G lanes per row, U columns per lane, and issues every load of its block (and of the vector
-// it multiplies) before the first use, so that one level costs about two memory round trips
-// (indices, then everything else) rather than one per row. Loads are unconditional at clamped
-// (valid) addresses and masked afterwards, so the compiler keeps them all in flight. No LDS and
-// no barriers: the forward right-hand side is gathered per lane through the inverse
-// extend-add maps.
-template <int G, int U, int RP>
+// c_B = f_B - BI f_I with f = slot0 + slot1, written into the parent's slot for this node;
+// workgroup 0 of the node also stores f_I for the backward sweep. The root is not launched.
+// Rows longer than G*U (only with CH) are taken in chunks.
+template <int G, int U, int RP, bool CH>
 __global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a, int loff) {
   constexpr int RPP = 256 / G, RPB = RP * RPP;
-  const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
+  const NodeDev nd = a.lnodes[loff + blockIdx.y];
   const int r0 = blockIdx.x * RPB;
-  if (r0 >= max(nd.nB, 1)) return;
+  if (r0 >= nd.nB) return;
   const int gl = threadIdx.x % G, grp = threadIdx.x / G;
   const double* __restrict__ F = a.front + nd.front_off;
-  const int32_t* __restrict__ inv0 = a.inv_pool + nd.inv_off;
-  const int32_t* __restrict__ inv1 = inv0 + nd.n;
-  const double* __restrict__ src0 = child_c(a, nd, 0);
-  const double* __restrict__ src1 = child_c(a, nd, 1);
-  const int nI1 = max(nd.nI, 1) - 1, nB1 = max(nd.nB, 1) - 1;
-  // indices of f at this lane's columns (k < nI) and rows (nI + j)
-  int ik0[U], ik1[U], ib0[RP], ib1[RP];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int k = min(gl + u * G, nI1);
-    ik0[u] = inv0[k];
-    ik1[u] = inv1[k];
-  }
-  double m[RP][U];
-  if (nd.nB > 0) {
-#pragma unroll
-    for (int p = 0; p < RP; ++p) {
-      const int j = min(r0 + p * RPP + grp, nB1);
-      ib0[p] = inv0[nd.nI + j];
-      ib1[p] = inv1[nd.nI + j];
-    }
-#pragma unroll
-    for (int p = 0; p < RP; ++p) {
-      const int j = min(r0 + p * RPP + grp, nB1);
-#pragma unroll
-      for (int u = 0; u < U; ++u) m[p][u] = F[int64_t(nd.nI + j) * nd.n + min(gl + u * G, nI1)];
-    }
-  } else {
-    // the root: no boundary rows, only f_I is stored
-#pragma unroll
-    for (int p = 0; p < RP; ++p) {
-      ib0[p] = -1;
-      ib1[p] = -1;
-#pragma unroll
-      for (int u = 0; u < U; ++u) m[p][u] = 0.0;
-    }
-  }
-  double fk[U], fb[RP];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const double x0 = src0[max(ik0[u], 0)], x1 = src1[max(ik1[u], 0)];
-    fk[u] = (ik0[u] >= 0 ? x0 : 0.0) + (ik1[u] >= 0 ? x1 : 0.0);
-  }
+  const double* __restrict__ s0 = a.slots + nd.slot_off;
+  const int32_t* __restrict__ up = a.map_pool + nd.up_map_off;
+  const int n = nd.n, nI = nd.nI, nI1 = nd.nI - 1, nB1 = nd.nB - 1;
+  uint32_t rowoff[RP];
+  double fb[RP], acc[RP];
+  int32_t to[RP];
 #pragma unroll
   for (int p = 0; p < RP; ++p) {
-    const double x0 = src0[max(ib0[p], 0)], x1 = src1[max(ib1[p], 0)];
-    fb[p] = (ib0[p] >= 0 ? x0 : 0.0) + (ib1[p] >= 0 ? x1 : 0.0);
+    const int j = min(r0 + p * RPP + grp, nB1);
+    rowoff[p] = uint32_t(nI + j) * uint32_t(n);
+    fb[p] = s0[nI + j] + s0[n + nI + j];
+    to[p] = up[j];
+    acc[p] = 0.0;
   }
-  if (blockIdx.x == 0 && grp == 0) {
+  for (int k0 = 0; k0 < (CH ? nI : 1); k0 += G * U) {
+    double m[RP][U], fk[U];
+#pragma unroll
+    for (int p = 0; p < RP; ++p)
+#pragma unroll
+      for (int u = 0; u < U; ++u) m[p][u] = ld32(F, rowoff[p] + uint32_t(min(k0 + gl + u * G, nI1)));
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int k = gl + u * G;
-      if (k < nd.nI) a.fI[nd.fI_off + k] = fk[u];
+      const int k = min(k0 + gl + u * G, nI1);
+      fk[u] = ld32(s0, k) + ld32(s0, n + k);
     }
+    if (blockIdx.x == 0 && grp == 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + gl + u * G;
+        if (k < nI) a.fI[nd.fI_off + k] = fk[u];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < RP; ++p)
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[p] += (k0 + gl + u * G < nI) ? m[p][u] * fk[u] : 0.0;
   }
 #pragma unroll
   for (int p = 0; p < RP; ++p) {
-    double acc = 0.0;
+    double v = acc[p];
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc += (gl + u * G < nd.nI) ? m[p][u] * fk[u] : 0.0;
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
     const int j = r0 + p * RPP + grp;
-    if (gl == 0 && j < nd.nB) a.cB[nd.cB_off + j] = fb[p] - acc;
+    if (gl == 0 && j < nd.nB) a.slots[nd.up_slot_off + to[p]] = fb[p] - v;
   }
 }
 
-template <int G, int U, int RP>
-__global__ void __launch_bounds__(256) k_nd_bwd_rb(NdArgs a, int loff) {
+// x_I = -II f_I - IB x_B, with f_I stored by the forward sweep (at the root: the sum of its two
+// slots) and x_B gathered from the solution vector through the node's unknown ids (issued
+// first, the block loads behind them); x_I goes to the solution vector.
+template <int G, int U, int RP, bool CH, bool ROOT>
+__device__ __forceinline__ void k_nd_bwd_body(const NdArgs& a, int loff) {
   constexpr int RPP = 256 / G, RPB = RP * RPP;
-  const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
+  const NodeDev nd = a.lnodes[loff + blockIdx.y];
   const int r0 = blockIdx.x * RPB;
   if (r0 >= nd.nI) return;
   const int gl = threadIdx.x % G, grp = threadIdx.x / G;
   const double* __restrict__ F = a.front + nd.front_off;
+  const double* __restrict__ s0 = a.slots + nd.slot_off;
+  const double* __restrict__ fI = a.fI + nd.fI_off;
   const int32_t* __restrict__ dofs = a.dof_pool + nd.dof_off;
-  const int n1 = nd.n - 1, nI1 = nd.nI - 1;
-  // v = [f_I; x_B]: unknown ids of this lane's columns first
-  int dk[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) dk[u] = dofs[min(gl + u * G, n1)];
-  int dr[RP];
-#pragma unroll
-  for (int p = 0; p < RP; ++p) dr[p] = dofs[min(r0 + p * RPP + grp, nI1)];
-  double m[RP][U];
+  const int n = nd.n, nI = nd.nI, n1 = nd.n - 1, nI1 = nd.nI - 1;
+  uint32_t rowoff[RP];
+  int32_t dr[RP];
+  double acc[RP];
 #pragma unroll
   for (int p = 0; p < RP; ++p) {
     const int r = min(r0 + p * RPP + grp, nI1);
-#pragma unroll
-    for (int u = 0; u < U; ++u) m[p][u] = F[int64_t(r) * nd.n + min(gl + u * G, n1)];
+    rowoff[p] = uint32_t(r) * uint32_t(n);
+    dr[p] = dofs[r];
+    acc[p] = 0.0;
   }
-  double v[U];
+  for (int k0 = 0; k0 < (CH ? n : 1); k0 += G * U) {
+    int32_t dk[U];
+    if constexpr (!ROOT) {
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int k = gl + u * G;
-    const double xi = a.fI[nd.fI_off + min(k, nI1)];
-    const double xb = a.y[dk[u]];
-    v[u] = k < nd.nI ? xi : (k < nd.n ? xb : 0.0);
+      for (int u = 0; u < U; ++u) dk[u] = dofs[min(max(k0 + gl + u * G, nI), n1)];
+    }
+    double m[RP][U], v[U];
+#pragma unroll
+    for (int p = 0; p < RP; ++p)
+#pragma unroll
+      for (int u = 0; u < U; ++u) m[p][u] = ld32(F, rowoff[p] + uint32_t(min(k0 + gl + u * G, n1)));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + gl + u * G;
+      const int ki = min(k, nI1);
+      if constexpr (ROOT) {
+        v[u] = k < nI ? ld32(s0, ki) + ld32(s0, n + ki) : 0.0;
+      } else {
+        const double xi = ld32(fI, ki);
+        const double xb = a.y[dk[u]];
+        v[u] = k < nI ? xi : (k < n ? xb : 0.0);
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < RP; ++p)
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[p] += m[p][u] * v[u];
   }
 #pragma unroll
   for (int p = 0; p < RP; ++p) {
-    double acc = 0.0;
+    double x = acc[p];
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc += m[p][u] * v[u];
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);
     const int r = r0 + p * RPP + grp;
-    if (gl == 0 && r < nd.nI) a.y[dr[p]] = -acc;
+    if (gl == 0 && r < nI) a.y[dr[p]] = -x;
   }
-}
-
-// Bottom levels fused: one workgroup walks one subtree, children before parents (forward)
-// or parents before children (backward); the per-node work is that of k_nd_fwd / k_nd_bwd.
-__global__ void __launch_bounds__(256) k_nd_fwd_fused(NdArgs a) {
-  extern __shared__ double f[];
-  __shared__ double part[4][64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int idx = a.fuse_off[blockIdx.x]; idx < a.fuse_off[blockIdx.x + 1]; ++idx) {
-    const NodeDev nd = a.nodes[a.fuse_nodes[idx]];
-    for (int i = threadIdx.x; i < nd.n; i += blockDim.x) f[i] = 0.0;
-    __syncthreads();
-    for (int c = 0; c < 2; ++c) {
-      const double* src = child_c(a, nd, c);
-      const int32_t* map = a.map_pool + nd.map_off[c];
-      for (int i = threadIdx.x; i < nd.nB_child[c]; i += blockDim.x) f[map[i]] += src[i];
-      __syncthreads();
-    }
-    for (int i = threadIdx.x; i < nd.nI; i += blockDim.x) a.fI[nd.fI_off + i] = f[i];
-    for (int j0 = 0; j0 < nd.nB; j0 += 64) {
-      const int j = j0 + lane;
-      double acc = 0.0;
-      if (j < nd.nB) {
-        const double* col = a.front + nd.front_off + nd.nI + j;
-        for (int i = wv; i < nd.nI; i += 4) acc += col[int64_t(i) * nd.n] * f[i];
-      }
-      part[wv][lane] = acc;
-      __syncthreads();
-      if (wv == 0 && j < nd.nB)
-        a.cB[nd.cB_off + j] = f[nd.nI + j] - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
-      __syncthreads();
-    }
-  }
-}
-
-__global__ void __launch_bounds__(256) k_nd_bwd_fused(NdArgs a) {
-  extern __shared__ double v[];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int idx = a.fuse_off[blockIdx.x + 1] - 1; idx >= a.fuse_off[blockIdx.x]; --idx) {
-    const NodeDev nd = a.nodes[a.fuse_nodes[idx]];
-    const int32_t* dofs = a.dof_pool + nd.dof_off;
-    for (int i = threadIdx.x; i < nd.nI; i += blockDim.x) v[i] = a.fI[nd.fI_off + i];
-    for (int i = threadIdx.x; i < nd.nB; i += blockDim.x) v[nd.nI + i] = a.y[dofs[nd.nI + i]];
-    __syncthreads();
-    for (int r = wv; r < nd.nI; r += 4) {
-      const double* row = a.front + nd.front_off + int64_t(r) * nd.n;
-      double acc = 0.0;
-      for (int k = lane; k < nd.n; k += 64) acc += row[k] * v[k];
-      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-      if (lane == 0) a.y[dofs[r]] = -acc;
-    }
-    __syncthreads();
-  }
-}
-
-void launch_nd_fused_fwd(hipStream_t st, const NdArgs& a, int nroots, int nmax) {
-  hipLaunchKernelGGL(k_nd_fwd_fused, dim3(nroots), dim3(256), size_t(nmax) * 8, st, a);
-}
-
-void launch_nd_fused_bwd(hipStream_t st, const NdArgs& a, int nroots, int nmax) {
-  hipLaunchKernelGGL(k_nd_bwd_fused, dim3(nroots), dim3(256), size_t(nmax) * 8, st, a);
 }
 
 void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nmax, int nImax) {
-  const int zb = std::min<int64_t>((int64_t(nmax) * nmax + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_nd_zero, dim3(zb, nnodes), dim3(256), 0, st, a, loff);
-  for (int c = 0; c < 2; ++c) hipLaunchKernelGGL(k_nd_extend, dim3(zb, nnodes), dim3(256), 0, st, a, loff, c);
+  hipLaunchKernelGGL(k_nd_assemble, dim3((nmax + ASM_ROWS - 1) / ASM_ROWS, nnodes), dim3(256), 0, st, a, loff);
   const int nblk = (nImax + a.piv_b - 1) / a.piv_b;
   const int tpd = (nmax + TILE - 1) / TILE;
   for (int kb = 0; kb < nblk; ++kb) {
@@ -472,71 +356,56 @@ void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int loff, int nnode
   }
 }
 
-static int group_for(int len) { return len <= 48 ? 16 : (len <= 96 ? 32 : 64); }
-
-// Rows per workgroup: a multiple of the rows one pass covers, sized for ~2048 workgroups.
-static int rows_per_block(int nrows, int nnodes, int G) {
-  const int per_pass = 256 / G;
-  const int wg_per_node = std::max(1, std::min((nrows + per_pass - 1) / per_pass, (2048 + nnodes - 1) / nnodes));
-  const int rpb = (nrows + wg_per_node - 1) / wg_per_node;
-  return std::max(per_pass, (rpb + per_pass - 1) / per_pass * per_pass);
-}
-
-// Register-batched shape for a row length: lanes per row, columns per lane, rows per lane
-// group (about eight loads of the block per lane). Returns false past the largest shape.
+// Shape for a row length: lanes per row, columns per lane, rows per lane group (about eight
+// loads of the block per lane); rows longer than 1536 are taken in chunks of 1024.
 struct RbShape {
   int G, U, RP;
 };
-static bool rb_shape(int len, RbShape* sh) {
-  if (len <= 16) *sh = {16, 1, 8};
-  else if (len <= 32) *sh = {32, 1, 8};
-  else if (len <= 64) *sh = {64, 1, 8};
-  else if (len <= 128) *sh = {64, 2, 4};
-  else if (len <= 256) *sh = {64, 4, 2};
-  else if (len <= 512) *sh = {64, 8, 1};
-  else if (len <= 1024) *sh = {64, 16, 1};
-  else if (len <= 1536) *sh = {64, 24, 1};
-  else if (len <= 2048) *sh = {64, 32, 1};
-  else return false;
-  return true;
+static RbShape rb_shape(int len) {
+  if (len <= 16) return {16, 1, 8};
+  if (len <= 32) return {32, 1, 8};
+  if (len <= 64) return {64, 1, 8};
+  if (len <= 128) return {64, 2, 4};
+  if (len <= 256) return {64, 4, 2};
+  if (len <= 512) return {64, 8, 1};
+  if (len <= 1024) return {64, 16, 1};
+  if (len <= 1536) return {64, 24, 1};
+  return {64, 0, 1};   // longer rows: chunks of 1024
 }
 
-#define ND_RB_LAUNCH(KER, sh, rows, nnodes, st, a, loff)                                              \
+#define ND_RB_LAUNCH(KER, sh, rows, nnodes, st, ...)                                                  \
   do {                                                                                              \
     const int rpb_ = (sh).RP * (256 / (sh).G);                                                      \
     const dim3 grid_(std::max(1, ((rows) + rpb_ - 1) / rpb_), (nnodes));                          \
-    if ((sh).G == 16) hipLaunchKernelGGL((KER<16, 1, 8>), grid_, dim3(256), 0, st, a, loff);        \
-    else if ((sh).G == 32) hipLaunchKernelGGL((KER<32, 1, 8>), grid_, dim3(256), 0, st, a, loff);   \
-    else if ((sh).U == 1) hipLaunchKernelGGL((KER<64, 1, 8>), grid_, dim3(256), 0, st, a, loff);    \
-    else if ((sh).U == 2) hipLaunchKernelGGL((KER<64, 2, 4>), grid_, dim3(256), 0, st, a, loff);    \
-    else if ((sh).U == 4) hipLaunchKernelGGL((KER<64, 4, 2>), grid_, dim3(256), 0, st, a, loff);    \
-    else if ((sh).U == 8) hipLaunchKernelGGL((KER<64, 8, 1>), grid_, dim3(256), 0, st, a, loff);    \
-    else if ((sh).U == 16) hipLaunchKernelGGL((KER<64, 16, 1>), grid_, dim3(256), 0, st, a, loff);  \
-    else if ((sh).U == 24) hipLaunchKernelGGL((KER<64, 24, 1>), grid_, dim3(256), 0, st, a, loff);  \
-    else hipLaunchKernelGGL((KER<64, 32, 1>), grid_, dim3(256), 0, st, a, loff);                    \
+    if ((sh).G == 16) hipLaunchKernelGGL((KER<16, 1, 8, false>), grid_, dim3(256), 0, st, __VA_ARGS__);        \
+    else if ((sh).G == 32) hipLaunchKernelGGL((KER<32, 1, 8, false>), grid_, dim3(256), 0, st, __VA_ARGS__);   \
+    else if ((sh).U == 1) hipLaunchKernelGGL((KER<64, 1, 8, false>), grid_, dim3(256), 0, st, __VA_ARGS__);    \
+    else if ((sh).U == 2) hipLaunchKernelGGL((KER<64, 2, 4, false>), grid_, dim3(256), 0, st, __VA_ARGS__);    \
+    else if ((sh).U == 4) hipLaunchKernelGGL((KER<64, 4, 2, false>), grid_, dim3(256), 0, st, __VA_ARGS__);    \
+    else if ((sh).U == 8) hipLaunchKernelGGL((KER<64, 8, 1, false>), grid_, dim3(256), 0, st, __VA_ARGS__);    \
+    else if ((sh).U == 16) hipLaunchKernelGGL((KER<64, 16, 1, false>), grid_, dim3(256), 0, st, __VA_ARGS__);  \
+    else if ((sh).U == 24) hipLaunchKernelGGL((KER<64, 24, 1, false>), grid_, dim3(256), 0, st, __VA_ARGS__);  \
+    else hipLaunchKernelGGL((KER<64, 16, 1, true>), grid_, dim3(256), 0, st, __VA_ARGS__);                     \
   } while (0)
 
-void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nmax, int nImax, int nBmax) {
-  RbShape sh;
-  if (rb_shape(nImax, &sh)) {
-    ND_RB_LAUNCH(k_nd_fwd_rb, sh, std::max(nBmax, 1), nnodes, st, a, loff);
-    return;
-  }
-  const int G = group_for(nImax);
-  const int rpb = rows_per_block(std::max(nBmax, 1), nnodes, G);
-  const int gx = std::max(1, (nBmax + rpb - 1) / rpb);
-  hipLaunchKernelGGL(k_nd_fwd, dim3(gx, nnodes), dim3(256), size_t(nmax) * 8, st, a, loff, G, rpb);
+void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nBmax) {
+  const RbShape sh = rb_shape(nImax);
+  ND_RB_LAUNCH(k_nd_fwd_rb, sh, nBmax, nnodes, st, a, loff);
 }
 
-void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nmax) {
-  RbShape sh;
-  if (rb_shape(nmax, &sh)) {
-    ND_RB_LAUNCH(k_nd_bwd_rb, sh, nImax, nnodes, st, a, loff);
-    return;
-  }
-  const int G = group_for(nmax);
-  const int rpb = rows_per_block(nImax, nnodes, G);
-  hipLaunchKernelGGL(k_nd_bwd, dim3((nImax + rpb - 1) / rpb, nnodes), dim3(256), size_t(nmax) * 8, st, a, loff, G, rpb);
+template <int G, int U, int RP, bool CH>
+__global__ void __launch_bounds__(256) k_nd_bwd_inner(NdArgs a, int loff) {
+  k_nd_bwd_body<G, U, RP, CH, false>(a, loff);
+}
+template <int G, int U, int RP, bool CH>
+__global__ void __launch_bounds__(256) k_nd_bwd_root(NdArgs a, int loff) {
+  k_nd_bwd_body<G, U, RP, CH, true>(a, loff);
+}
+
+void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nmax, int root) {
+  const RbShape sh = rb_shape(nmax);
+  if (root) ND_RB_LAUNCH(k_nd_bwd_root, sh, nImax, nnodes, st, a, loff);
+  else ND_RB_LAUNCH(k_nd_bwd_inner, sh, nImax, nnodes, st, a, loff);
 }
 
 }  // namespace mpm

@@ -177,44 +177,31 @@ void build_plan(const mpm_desc& d, Plan* p) {
     P.level_nImax[n.level] = std::max(P.level_nImax[n.level], n.nI);
     P.level_nBmax[n.level] = std::max(P.level_nBmax[n.level], n.nB);
   }
-  // fused bottom levels
-  {
-    // measured: walking a subtree per workgroup is a latency chain slower than one launch per
-    // level, so no level is fused by default
-    P.fuse_level = 0;
-    std::vector<int> parent(P.nodes.size(), -1);
-    for (size_t i = 0; i < P.nodes.size(); ++i)
-      for (int c = 0; c < 2; ++c)
-        if (P.nodes[i].child[c] >= 0) parent[P.nodes[i].child[c]] = int(i);
-    P.fuse_off.assign(1, 0);
-    P.fuse_nodes.clear();
-    P.fuse_nmax = 0;
-    if (P.fuse_level) {
-      std::function<void(int)> collect = [&](int id) {
-        for (int c = 0; c < 2; ++c)
-          if (P.nodes[id].child[c] >= 0) collect(P.nodes[id].child[c]);
-        P.fuse_nodes.push_back(id);
-        P.fuse_nmax = std::max(P.fuse_nmax, int(P.nodes[id].n));
-      };
-      for (size_t i = 0; i < P.nodes.size(); ++i) {
-        const int L = P.nodes[i].level;
-        const int pl = parent[i] >= 0 ? P.nodes[parent[i]].level : 1 << 30;
-        if (L <= P.fuse_level && pl > P.fuse_level) {
-          collect(int(i));
-          P.fuse_off.push_back(int32_t(P.fuse_nodes.size()));
-        }
-      }
-    }
-  }
-  // per-node storage
-  int64_t fo = 0, io = 0, co = 0, po = 0;
+  // per-node storage and the forward-solve slots
+  int64_t fo = 0, io = 0, po = 0, so = 0;
   for (auto& n : P.nodes) {
     n.front_off = fo; fo += int64_t(n.n) * n.n;
     n.fI_off = io; io += n.nI;
-    n.cB_off = co; co += n.nB;
     n.panel_off = po; po += int64_t(P.piv_b) * P.piv_b + 2 * int64_t(P.piv_b) * n.n;
+    n.slot_off = so; so += 2 * int64_t(n.n);
+    n.up_slot_off = -1;
+    n.up_map_off = -1;
+    n.pad = 0;
   }
-  P.front_doubles = fo; P.fI_doubles = io; P.cB_doubles = co; P.panel_doubles = po;
+  P.leafup.assign(P.nsub, LeafUp{-1, -1, 0});
+  for (auto& n : P.nodes) {
+    for (int c = 0; c < 2; ++c) {
+      const int ch = n.child[c];
+      const int64_t slot = n.slot_off + int64_t(c) * n.n;
+      if (ch < 0) {
+        P.leafup[-1 - ch] = LeafUp{slot, n.map_off[c], 0};
+      } else {
+        P.nodes[ch].up_slot_off = slot;
+        P.nodes[ch].up_map_off = n.map_off[c];
+      }
+    }
+  }
+  P.front_doubles = fo; P.fI_doubles = io; P.panel_doubles = po; P.slot_doubles = so;
 
   // workspace layout
   const size_t ncell = size_t(P.nx) * P.ny;
@@ -248,10 +235,9 @@ void build_plan(const mpm_desc& d, Plan* p) {
   }
   P.off_ubnd = take(size_t(P.nsub) * P.nb * 8);
   P.off_leafK = take(size_t(P.nsub) * P.ndmax * P.ndmax * 8);
-  P.off_leafr = take(size_t(P.nsub) * P.ndmax * 8);
   P.off_front = take(size_t(std::max<int64_t>(fo, 1)) * 8);
   P.off_fI = take(size_t(std::max<int64_t>(io, 1)) * 8);
-  P.off_cB = take(size_t(std::max<int64_t>(co, 1)) * 8);
+  P.off_slot = take(size_t(std::max<int64_t>(so, 1)) * 8);
   P.off_panel = take(size_t(std::max<int64_t>(po, 1)) * 8);
   P.off_y = take(size_t(std::max(P.n_iface, 1)) * 8);
   P.off_nodes = take(std::max<size_t>(P.nodes.size(), 1) * sizeof(NodeDev));
@@ -268,8 +254,10 @@ void build_plan(const mpm_desc& d, Plan* p) {
   }
   P.level_off[P.level_nodes.size()] = int32_t(P.level_flat.size());
   P.off_levels = take(std::max<size_t>(P.level_flat.size(), 1) * 4);
-  P.off_fuse_off = take(std::max<size_t>(P.fuse_off.size(), 1) * 4);
-  P.off_fuse_nodes = take(std::max<size_t>(P.fuse_nodes.size(), 1) * 4);
+  P.lnodes.clear();
+  for (int32_t id : P.level_flat) P.lnodes.push_back(P.nodes[id]);
+  P.off_lnodes = take(std::max<size_t>(P.lnodes.size(), 1) * sizeof(NodeDev));
+  P.off_leafup = take(std::max<size_t>(P.leafup.size(), 1) * sizeof(LeafUp));
   const size_t blocks = (ncell + 255) / 256 + size_t(P.nsub) + 64;
   P.n_red = 4 * blocks;
   P.off_red = take(P.n_red * 8);

@@ -15,6 +15,10 @@ namespace mpm {
 enum FaceKind : int32_t { FACE_NEU = 0, FACE_DIR = 1, FACE_ROB = 2 };
 
 // Device view of one nested-dissection node.
+//
+// The forward solve passes vectors between levels through slots rather than by gathering: a
+// node writes its condensed right-hand side into its parent's slot for it (front order, two
+// slots per node, one per child; entries the child does not reach stay zero).
 struct NodeDev {
   int32_t n, nI, nB;          // front size, eliminated (separator) and boundary unknowns
   int32_t level;
@@ -24,10 +28,21 @@ struct NodeDev {
   int32_t dof_off;            // offset of the node's front unknowns (I then B) in dof_pool
   int32_t inv_off;            // offset of the inverse extend-add maps in inv_pool: for child c and
                               // front index k, inv_pool[inv_off + c*n + k] = the child's index, or -1
+  int32_t up_map_off;         // offset in map_pool of this node's B entries in its parent's front
+  int32_t pad;
   int64_t front_off;          // offset (doubles) of the n x n front
   int64_t fI_off;             // offset (doubles) of the eliminated part of the condensed rhs
-  int64_t cB_off;             // offset (doubles) of the condensed rhs passed to the parent
   int64_t panel_off;          // offset (doubles) of the pivot-block scratch (b*b + 2*b*n)
+  int64_t slot_off;           // offset (doubles) of the node's two child slots (2 x n)
+  int64_t up_slot_off;        // offset of the parent's slot this node writes into (-1: root)
+};
+
+// Where a subdomain's interface right-hand side goes: the slot of its parent node and the map
+// of its unknowns into the parent's front (slot -1: no tree).
+struct LeafUp {
+  int64_t slot_off;
+  int32_t map_off;
+  int32_t pad;
 };
 
 struct Plan {
@@ -55,26 +70,22 @@ struct Plan {
   std::vector<int32_t> level_nmax, level_nImax, level_nBmax;
   // workspace layout (byte offsets)
   size_t off_K, off_q, off_s, off_s2, off_kn, off_km, off_ux, off_uy, off_uxm, off_uym;
-  size_t off_fac, off_dinv, off_S, off_h, off_vbnd, off_ubnd, off_leafK, off_leafr;
-  size_t off_front, off_fI, off_cB, off_panel, off_y;
+  size_t off_fac, off_dinv, off_S, off_h, off_vbnd, off_ubnd, off_leafK;
+  size_t off_front, off_fI, off_panel, off_y;
   size_t off_invpool = 0;
   size_t off_nodes, off_dofpool, off_mappool, off_subdofs, off_subndof, off_levels;
   std::vector<int32_t> level_off;     // offsets of each level's node list in the uploaded level array
   std::vector<int32_t> level_flat;
-  // bottom levels 1..fuse_level are solved one subtree per workgroup: subtree roots are the
-  // nodes of level <= fuse_level whose parent lies above it
-  int fuse_level = 0;
-  int fuse_nmax = 0;
-  std::vector<int32_t> fuse_off;      // per subtree, offset into fuse_nodes (size roots+1)
-  std::vector<int32_t> fuse_nodes;    // subtree nodes, children before parents
-  size_t off_fuse_off = 0, off_fuse_nodes = 0;
+  std::vector<NodeDev> lnodes;        // the nodes again, level by level (level_flat order)
+  std::vector<LeafUp> leafup;         // per subdomain
+  size_t off_lnodes = 0, off_leafup = 0, off_slot = 0;
   size_t off_dsE = 0, off_nfac = 0;   // downscale inverse blocks: scratch and the kept kappa^m ones
   size_t off_dsflag = 0;              // per subdomain: conductivity changed since the last update
   size_t off_dslist = 0;              // the changed subdomains (count in the integer word after the error word)
   size_t off_red, off_scal;
   size_t n_red;               // doubles in the reduction scratch
   size_t total_bytes;
-  int64_t front_doubles = 0, panel_doubles = 0, fI_doubles = 0, cB_doubles = 0;
+  int64_t front_doubles = 0, panel_doubles = 0, fI_doubles = 0, slot_doubles = 0;
 };
 
 // Validates the descriptor; returns MPM_OK or MPM_EINVAL with a message.

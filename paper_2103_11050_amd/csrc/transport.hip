@@ -48,23 +48,42 @@ k_sat_step(Geo g, const double* __restrict__ s, double* __restrict__ s2, const d
   }
 }
 
-// Water cut over boundary faces with outflow: sum |f| u f(s_c) / sum |f| u (fixed order).
+// Water cut over boundary faces with outflow: sum |f| u f(s_c) / sum |f| u (fixed order; loads
+// issued in batches of 16 per thread).
 __global__ void __launch_bounds__(256)
 k_water_cut(Geo g, const double* __restrict__ s, const double* __restrict__ ux, const double* __restrict__ uy,
             double* __restrict__ scal, double M) {
+  constexpr int B = 16;
   __shared__ double sq[256], sw[256];
   double q = 0.0, w = 0.0;
   const int nW = g.ny, nS = g.nx;
   const int tot = 2 * nW + 2 * nS;
-  for (int e = threadIdx.x; e < tot; e += 256) {
-    double u, sc, fl;
-    if (e < nW) { const int j = e; u = -ux[j * (g.nx + 1)]; sc = s[j * g.nx]; fl = g.hy; }
-    else if (e < 2 * nW) { const int j = e - nW; u = ux[j * (g.nx + 1) + g.nx]; sc = s[j * g.nx + g.nx - 1]; fl = g.hy; }
-    else if (e < 2 * nW + nS) { const int i = e - 2 * nW; u = -uy[i]; sc = s[i]; fl = g.hx; }
-    else { const int i = e - 2 * nW - nS; u = uy[g.ny * g.nx + i]; sc = s[(g.ny - 1) * g.nx + i]; fl = g.hx; }
-    const double out = fl * fmax(u, 0.0);
-    q += out;
-    w += out * fracflow(sc, M);
+  for (int base = 0; base < tot; base += 256 * B) {
+    double vu[B], vs[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int e0 = base + threadIdx.x + 256 * u;
+      const int e = e0 < tot ? e0 : 0;
+      const bool vert = e < 2 * nW;
+      const int k = vert ? (e < nW ? e : e - nW) : (e < 2 * nW + nS ? e - 2 * nW : e - 2 * nW - nS);
+      const bool hi = vert ? e >= nW : e >= 2 * nW + nS;
+      const double* up = vert ? ux : uy;
+      const int ui = vert ? k * (g.nx + 1) + (hi ? g.nx : 0) : (hi ? g.ny * g.nx : 0) + k;
+      const int si = vert ? k * g.nx + (hi ? g.nx - 1 : 0) : (hi ? (g.ny - 1) * g.nx : 0) + k;
+      const double uv = up[ui];
+      vu[u] = hi ? uv : -uv;
+      vs[u] = s[si];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int e = base + threadIdx.x + 256 * u;
+      if (e < tot) {
+        const double fl = e < 2 * nW ? g.hy : g.hx;
+        const double out = fl * fmax(vu[u], 0.0);
+        q += out;
+        w += out * fracflow(vs[u], M);
+      }
+    }
   }
   sq[threadIdx.x] = q;
   sw[threadIdx.x] = w;
