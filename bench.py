@@ -179,13 +179,52 @@ def cpu_baseline(cfg: dict, K: np.ndarray, steps: int = 3) -> dict:
                       f"cell ratio {scale:.4f}; host: {host_cpu()}, {os.cpu_count()} logical CPUs"}
 
 
+def precision_form(binding, cfg, Kt, st, steps: int, warmup: int) -> dict:
+    """The precision form (FP32 inverse blocks in the MPM-2P local solves and downscaling, FP64
+    refinement, FP64 interface solve and switch criterion) beside the FP64 path on the same
+    workload: its rate over `steps` steps and its velocity difference from the FP64 path after
+    the same steps from the same start."""
+    import torch
+
+    runs = {}
+    for name, prec in (("fp64", binding.PREC_FP64), ("fp32", binding.PREC_FP32_REFINE)):
+        r = binding.Run(cfg, Kt, st, precision=prec)
+        r.start()
+        for _ in range(warmup):
+            r.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r.step()
+        torch.cuda.synchronize()
+        runs[name] = (r, steps / (time.perf_counter() - t0))
+    (r64, v64), (r32, v32) = runs["fp64"], runs["fp32"]
+    ux64, uy64 = (t.cpu().numpy() for t in r64.velocity())
+    ux32, uy32 = (t.cpu().numpy() for t in r32.velocity())
+    def rt0(ux, uy):   # velocity norm of the lowest-order mixed space with the trapezoidal rule
+        return np.sum(ux[:, :-1] ** 2) + np.sum(ux[:, 1:] ** 2) + np.sum(uy[:-1, :] ** 2) + np.sum(uy[1:, :] ** 2)
+
+    num = rt0(ux32 - ux64, uy32 - uy64)
+    den = rt0(ux64, uy64)
+    b64, b32 = r64.stats()["last_branch"], r32.stats()["last_branch"]
+    r64.close()
+    r32.close()
+    return {"value": round(v32, 2), "fp64_value_same_window": round(v64, 2), "steps": steps,
+            "vel_rel_l2_vs_fp64": float(np.sqrt(num / den)), "same_branches": bool(b64 == b32),
+            "note": "FP32 blocks applied in FP32, FP64 iterative refinement of every local solve"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c3")
+    ap.add_argument("--precision", choices=["fp64", "fp32-refine"], default="fp64",
+                    help="local solves with FP64 blocks, or FP32 blocks with FP64 refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-form", action="store_true",
+                    help="skip the side-by-side run of the FP32-block precision form")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--make-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="build the traffic record from rocprofv3 --pmc outputs and exit")
@@ -220,26 +259,33 @@ def main():
     dev = torch.device("cuda:0")
     Kt = torch.from_numpy(K).to(dev)
     st = torch.from_numpy(s0).to(dev)
-    run = binding.Run(cfg, Kt, st)
+    prec = binding.PREC_FP64 if args.precision == "fp64" else binding.PREC_FP32_REFINE
+    run = binding.Run(cfg, Kt, st, precision=prec)
     run.start()
     for _ in range(args.warmup):
         run.step()
     torch.cuda.synchronize()
     s_before = run.stats()
     stream = run.stream
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    # throughput window: nothing but the steps between the two synchronisations
     t0 = time.perf_counter()
-    evs[0].record(stream)
     for k in range(args.steps):
         run.step()
-        evs[k + 1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     s_after = run.stats()
     elapsed = t1 - t0
-    lat = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
     n_mrcm = s_after["tm"] - s_before["tm"]
     value = args.steps / elapsed
+    # per-step latency window (an event per step, which itself costs a few microseconds)
+    nlat = min(args.steps, 100)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nlat + 1)]
+    evs[0].record(stream)
+    for k in range(nlat):
+        run.step()
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    lat = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(nlat)])
 
     # kernel timing with HIP events on the run's stream (separate short window)
     run.profile(enable=True, reset=True)
@@ -280,7 +326,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32 blocks + f64 refinement (interface, residuals, epsilon f64)",
         "data": "synthetic",
         "config": {"workload": "1024^2 cells, 64x64 subdomains of 16^2, 8 interface elements per side, "
                                "log-normal K (log-variance 4, correlation length 0.05, seed 3), M=100, eta=0.1, C_n=1",
@@ -294,6 +340,8 @@ def main():
         "mrcm_kernels_ms": {k: round(v[0], 5) for k, v in sorted(mprof.items())},
     }
     run.close()
+    if args.precision == "fp64" and not args.no_precision_form:
+        out["precision_form"] = precision_form(binding, cfg, Kt, st, min(args.steps, 100), args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, K)
     print(json.dumps(out))

@@ -74,6 +74,8 @@ struct mpm_run {
   double *K, *q, *s, *s2, *kn, *km, *ux, *uy, *uxm, *uym, *fac, *S, *h, *vbnd, *ubnd, *leafK;
   double *front, *fI, *slots, *panel, *y, *red, *scal, *dsE, *nfac;
   int32_t* err;
+  float *fac32 = nullptr, *nfac32 = nullptr, *dsE32 = nullptr;   // precision form
+  bool f32 = false;
   const LeafUp* leafup = nullptr;
   int32_t* dsflag = nullptr;
   int32_t* dslist = nullptr;
@@ -289,8 +291,16 @@ void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store) {
   }
   {
     Scope sc(r, "downscale");
-    launch_downscale(r->st, r->g, kap_s, r->q, r->ubnd, r->ux, r->uy, r->red, r->red + r->P.nsub, r->dsE, r->nfac,
-                     r->dsflag, store, r->err);
+    if (r->f32 && !store)
+      launch_downscale_f32(r->st, r->g, kap_s, r->q, r->ubnd, r->ux, r->uy, r->red, r->red + r->P.nsub, r->dsE32,
+                           r->nfac32, r->dsflag, r->err);
+    else
+      launch_downscale(r->st, r->g, kap_s, r->q, r->ubnd, r->ux, r->uy, r->red, r->red + r->P.nsub, r->dsE,
+                       r->nfac, r->dsflag, store, r->err);
+  }
+  if (r->f32 && store) {
+    Scope sc(r, "to_f32");
+    launch_to_f32(r->st, r->P.n_blocks, r->nfac, r->nfac32);
   }
   {
     Scope sc(r, "dt");
@@ -309,6 +319,10 @@ mpm_status mrcm_update(mpm_run* r) {
   if (!have_fac) {
     Scope sc(r, "line_factor");
     launch_line_factor(r->st, r->g, r->km, r->fac, r->err);
+  }
+  if (r->f32) {
+    Scope sc(r, "to_f32");
+    launch_to_f32(r->st, r->P.n_blocks, r->fac, r->fac32);
   }
   nd_factor(r);
   nd_solve(r);
@@ -333,11 +347,15 @@ mpm_status mpm_update_body(mpm_run* r, bool capturing) {
   } else {
     HIPCHK(r, hipStreamWaitEvent(r->st2, r->ev_eps, 0));
   }
-  launch_ds_factor(r->st2, r->g, r->kn, r->dsE, r->dslist, r->dscount, r->err);
+  if (r->f32) launch_ds_factor_f32(r->st2, r->g, r->kn, r->dsE32, r->dslist, r->dscount, r->err);
+  else launch_ds_factor(r->st2, r->g, r->kn, r->dsE, r->dslist, r->dscount, r->err);
   HIPCHK(r, hipEventRecord(r->ev_join, r->st2));
   {
     Scope sc(r, "mpm_local");
-    launch_mpm_local(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac, r->h, r->vbnd, leaf_dest(r));
+    if (r->f32)
+      launch_mpm_local_f32(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac32, r->h, r->vbnd, leaf_dest(r));
+    else
+      launch_mpm_local(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac, r->h, r->vbnd, leaf_dest(r));
   }
   nd_solve(r);
   HIPCHK(r, hipStreamWaitEvent(r->st, r->ev_join, 0));
@@ -502,6 +520,12 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   r->front = D(P.off_front); r->fI = D(P.off_fI); r->slots = D(P.off_slot);
   r->panel = D(P.off_panel); r->y = D(P.off_y); r->red = D(P.off_red); r->scal = D(P.off_scal);
   r->dsE = D(P.off_dsE); r->nfac = D(P.off_nfac);
+  r->f32 = P.d.precision == MPM_PREC_FP32_REFINE;
+  if (r->f32) {
+    r->fac32 = reinterpret_cast<float*>(r->ws + P.off_fac32);
+    r->nfac32 = reinterpret_cast<float*>(r->ws + P.off_nfac32);
+    r->dsE32 = reinterpret_cast<float*>(r->ws + P.off_dsE32);
+  }
   r->s_base = r->s;
   r->dsflag = reinterpret_cast<int32_t*>(r->ws + P.off_dsflag);
   r->dslist = reinterpret_cast<int32_t*>(r->ws + P.off_dslist);
@@ -552,6 +576,8 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
                     in(r->y, size_t(std::max(P.n_iface, 1)) * 8) && in(r->subdofs_d, ns * P.ndmax * 4) &&
                     in(r->slots, size_t(std::max<int64_t>(P.slot_doubles, 1)) * 8) &&
                     in(r->leafup, ns * sizeof(LeafUp)) &&
+                    (!r->f32 || (in(r->fac32, P.n_blocks * 4) && in(r->nfac32, P.n_blocks * 4) &&
+                                 in(r->dsE32, P.n_blocks * 4))) &&
                     in(r->nd.lnodes, std::max<size_t>(P.lnodes.size(), 1) * sizeof(NodeDev));
     if (!ok) return fail(MPM_EINVAL);
   }

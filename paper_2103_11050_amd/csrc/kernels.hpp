@@ -43,6 +43,17 @@ void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, double*
                       const int32_t* count, int32_t* err);
 // store = 1: kap_s is kappa^m, its inverse blocks are formed here and kept (Ekeep).
 // store = 0: the blocks come from Escr where flag[sub] is set, else from Ekeep.
+// precision form: FP32 inverse blocks, FP64 refinement (MPM-2P steps), and the conversion of
+// FP64 blocks kept by an MRCM update
+void launch_ds_factor_f32(hipStream_t st, const Geo& g, const double* kap_n, float* Escr, const int32_t* list,
+                          const int32_t* count, int32_t* err);
+void launch_mpm_local_f32(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
+                          const double* uym, const double* q, const float* fac, double* h, double* vbnd,
+                          LeafOut lo);
+void launch_downscale_f32(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
+                          double* ux, double* uy, double* red_rate, double* red_qin, float* Escr, float* Ekeep,
+                          const int32_t* flag, int32_t* err);
+void launch_to_f32(hipStream_t st, size_t n, const double* src, float* dst);
 void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
                       double* ux, double* uy, double* red_rate, double* red_qin, double* Escr, double* Ekeep,
                       const int32_t* flag, int store, int32_t* err);

@@ -34,8 +34,8 @@ __device__ __forceinline__ size_t efac_off(const Geo& g, int sub, int ln, int t)
 
 // Block elimination over all lines; the inverses D_ln^-1 go to Es[(ln*EPL + t)*64 + lane]
 // (LDS or global).
-template <int MF>
-__device__ __forceinline__ void lb_factor(const Geo& g, const LineW& W, const LB<MF>& L, double* Es, bool& ok) {
+template <int MF, typename T>
+__device__ __forceinline__ void lb_factor(const Geo& g, const LineW& W, const LB<MF>& L, T* Es, bool& ok) {
   constexpr int EPL = LB<MF>::EPL;
   const int nl = g.nc / g.band;
   double prev[EPL], cur[EPL];
@@ -47,7 +47,7 @@ __device__ __forceinline__ void lb_factor(const Geo& g, const LineW& W, const LB
     lb_inverse<MF>(L, cur, ok);
 #pragma unroll
     for (int t = 0; t < EPL; ++t) {
-      Es[(size_t(ln) * EPL + t) * 64 + L.lane] = cur[t];
+      Es[(size_t(ln) * EPL + t) * 64 + L.lane] = T(cur[t]);
       prev[t] = cur[t];
     }
   }
@@ -167,6 +167,118 @@ __device__ __forceinline__ void lb_solve_any(const Geo& g, const LineW& W, const
   else lb_solve<MF>(g, W, L, Es, x, w);
 }
 
+// ------------------------------------------------------------------ FP32 blocks, FP64 refinement
+// Precision form: the inverse blocks are stored in FP32 and applied in FP32; each solve is
+// recovered by FP64 iterative refinement against the FP64 line form of the same matrix.
+
+template <int MF>
+__device__ __forceinline__ float lb_matvec_f(const LB<MF>& L, const float (&a)[LB<MF>::EPL], float v) {
+  constexpr int EPL = LB<MF>::EPL, LPR = LB<MF>::LPR;
+  float acc = 0.0f;
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) acc += a[t] * __shfl(v, L.col(t) * LPR);
+#pragma unroll
+  for (int o = 1; o < LPR; o <<= 1) acc += __shfl_xor(acc, o);
+  return acc;
+}
+
+// Up to 16 lines of FP32 blocks into registers (nl lines at run time).
+template <int MF>
+__device__ __forceinline__ void lb_load_f32(const LB<MF>& L, const float* Es, int nl, float (&E)[16][LB<MF>::EPL]) {
+  constexpr int EPL = LB<MF>::EPL;
+#pragma unroll
+  for (int ln = 0; ln < 16; ++ln)
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) E[ln][t] = ln < nl ? Es[(size_t(ln) * EPL + t) * 64 + L.lane] : 0.0f;
+}
+
+// d = M^-1 r with the FP32 blocks (both sweeps in FP32); r and d in LDS, local order, FP64.
+template <int MF>
+__device__ __forceinline__ void lb_apply_f32(const LineW& W, const LB<MF>& L, int nl,
+                                             const float (&E)[16][LB<MF>::EPL], const double* r, double* d) {
+  const int len = W.band;
+  const bool rin = L.row < len;
+  float w[16];
+#pragma unroll
+  for (int ln = 0; ln < 16; ++ln) {
+    w[ln] = 0.0f;
+    if (ln < nl) {
+      float z = rin ? float(r[ln * len + L.row]) : 0.0f;
+      if (ln > 0 && rin) z += float(W.y(ln - 1, L.row)) * w[ln - 1];
+      w[ln] = lb_matvec_f<MF>(L, E[ln], z);
+    }
+  }
+  float xn = 0.0f;
+#pragma unroll
+  for (int ln = 15; ln >= 0; --ln) {
+    if (ln < nl) {
+      float xv = w[ln];
+      if (ln < nl - 1) {
+        const float v = rin ? float(W.y(ln, L.row)) * xn : 0.0f;
+        xv += lb_matvec_f<MF>(L, E[ln], v);
+      }
+      xn = xv;
+      if (rin && L.cg == 0) d[ln * len + L.row] = double(xv);
+    }
+  }
+  __syncthreads();
+}
+
+// r = b - A x in FP64 with A the line form of the matrix (the one the blocks invert).
+__device__ __forceinline__ void line_residual(const Geo& g, const LineW& W, int nl, const double* b,
+                                              const double* x, double* r) {
+  const int len = W.band;
+  for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
+    const int ln = c / len, pos = c % len;
+    double ax = W.diag(ln, pos) * x[c];
+    if (pos + 1 < len) ax -= W.off(ln, pos) * x[c + 1];
+    if (pos > 0) ax -= W.off(ln, pos - 1) * x[c - 1];
+    if (ln + 1 < nl) ax -= W.y(ln, pos) * x[c + len];
+    if (ln > 0) ax -= W.y(ln - 1, pos) * x[c - len];
+    r[c] = b[c] - ax;
+  }
+  __syncthreads();
+}
+
+// Refinement budget of the precision form: corrections stop once the largest one is below
+// REFINE_RTOL times the largest solution entry (four orders below the 1e-6 bound of the
+// precision form), at most REFINE_MAXIT of them.
+constexpr double REFINE_RTOL = 1e-10;
+constexpr int REFINE_MAXIT = 8;
+
+// x holds the right-hand side on entry and the solution on exit (LDS, local order); ws is LDS
+// scratch of 3 * nc doubles. One wavefront.
+template <int MF>
+__device__ __forceinline__ void lb_solve_refined(const Geo& g, const LineW& W, const LB<MF>& L,
+                                                 const float (&E)[16][LB<MF>::EPL], double* x, double* ws) {
+  const int nl = g.nc / g.band;
+  double* b = ws;
+  double* r = ws + g.nc;
+  double* d = ws + 2 * g.nc;
+  for (int c = threadIdx.x; c < g.nc; c += blockDim.x) b[c] = x[c];
+  __syncthreads();
+  lb_apply_f32<MF>(W, L, nl, E, b, x);
+#pragma unroll 1
+  for (int it = 0; it < REFINE_MAXIT; ++it) {
+    line_residual(g, W, nl, b, x, r);
+    lb_apply_f32<MF>(W, L, nl, E, r, d);
+    double dm = 0.0, xm = 0.0;
+    for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
+      const double xv = x[c] + d[c];
+      x[c] = xv;
+      dm = fmax(dm, fabs(d[c]));
+      xm = fmax(xm, fabs(xv));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      dm = fmax(dm, __shfl_xor(dm, o));
+      xm = fmax(xm, __shfl_xor(xm, o));
+    }
+    __syncthreads();
+    if (dm <= REFINE_RTOL * xm) break;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------
@@ -260,21 +372,26 @@ __device__ __forceinline__ void load_halo_tiles(const Geo& g, int I, int J, cons
 // v_f = (t^n_f / t^m_f) u~^m_f; zero Dirichlet and Robin data. Outputs the boundary fluxes
 // h = W T delta p on Robin/Dirichlet faces, the boundary values of v and the interface
 // right-hand side B^T h. The kept inverse blocks and all tiles are requested at entry.
-template <int MF, int NL>
+// With T = float the kept blocks are FP32 (all lines in registers, up to 16) and the solve is
+// refined in FP64.
+template <int MF, int NL, typename T>
 __global__ void __launch_bounds__(64)
 k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict__ kap_m,
                const double* __restrict__ uxm, const double* __restrict__ uym, const double* __restrict__ q,
-               const double* __restrict__ fac, double* __restrict__ hg, double* __restrict__ vbnd, LeafOut lo) {
+               const T* __restrict__ fac, double* __restrict__ hg, double* __restrict__ vbnd, LeafOut lo) {
+  constexpr bool F32 = sizeof(T) == 4;
   __shared__ double knt[18 * 18], kmt[18 * 18], uxs[16 * 17], uys[17 * 16], qs[256];
-  __shared__ double kl[256], x[256], hsh[64], wsh[256], tE[256], tN[256], dg[256];
+  __shared__ double kl[256], x[256], hsh[64], wsh[F32 ? 768 : 256], tE[256], tN[256], dg[256];
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int n = g.nc, nb = g.nb;
   const int TW = g.mx + 2;
   LB<MF> L;
   constexpr int NLR = NL > 0 ? NL : 1;
-  double E[NLR][LB<MF>::EPL];
-  if constexpr (NL > 0) lb_load_reg<MF, NL>(L, fac + efac_off<MF>(g, sub, 0, 0), E);
+  double E[F32 ? 1 : NLR][LB<MF>::EPL];
+  float Ef[F32 ? 16 : 1][LB<MF>::EPL];
+  if constexpr (F32) lb_load_f32<MF>(L, fac + efac_off<MF>(g, sub, 0, 0), g.nc / g.band, Ef);
+  else if constexpr (NL > 0) lb_load_reg<MF, NL>(L, fac + efac_off<MF>(g, sub, 0, 0), E);
   load_halo_tiles(g, I, J, kap_n, kap_m, uxm, uym, q, HaloTiles{knt, kmt, uxs, uys, qs});
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     int i, j;
@@ -329,7 +446,8 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
   __syncthreads();
   fill_trans(g, I, J, kl, 0, tE, tN, dg);
   const LineW W{tE, tN, dg, g.xfast, g.band, 0};
-  if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
+  if constexpr (F32) lb_solve_refined<MF>(g, W, L, Ef, x, wsh);
+  else if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
   else lb_solve<MF>(g, W, L, fac + efac_off<MF>(g, sub, 0, 0), x, wsh);
   for (int f = threadIdx.x; f < nb; f += blockDim.x) {
     BFace bf = bface(g, I, J, f);
@@ -374,17 +492,29 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
 // mean of both sides' boundary fluxes on Gamma, the own flux on the physical boundary, the
 // first cell pinned. Writes the velocity on the faces the subdomain owns, the largest outflow
 // rate per cell volume and the inflow through the physical boundary.
-template <int MF, int NL>
+// With T = float (MPM-2P steps of the precision form; store = 0) the blocks are FP32 and the
+// solve is refined in FP64. The blocks are requested at entry.
+template <int MF, int NL, typename T>
 __global__ void __launch_bounds__(64)
 k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict__ q,
                const double* __restrict__ ubnd, double* __restrict__ ux, double* __restrict__ uy,
-               double* __restrict__ red_rate, double* __restrict__ red_qin, double* __restrict__ Escr,
-               double* __restrict__ Ekeep, const int32_t* __restrict__ flag, int store, int32_t* err) {
-  __shared__ double kl[256], x[256], w[64], scratch[128], wsh[256], tE[256], tN[256], dg[256];
+               double* __restrict__ red_rate, double* __restrict__ red_qin, T* __restrict__ Escr,
+               T* __restrict__ Ekeep, const int32_t* __restrict__ flag, int store, int32_t* err) {
+  constexpr bool F32 = sizeof(T) == 4;
+  __shared__ double kl[256], x[256], w[64], scratch[128], wsh[F32 ? 768 : 256], tE[256], tN[256], dg[256];
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int n = g.nc, nb = g.nb;
   LB<MF> L;
+  const size_t eoff = efac_off<MF>(g, sub, 0, 0);
+  T* Es = (!store && flag[sub]) ? Escr + eoff : Ekeep + eoff;
+  constexpr int NLR = NL > 0 ? NL : 1;
+  double E[F32 ? 1 : NLR][LB<MF>::EPL];
+  float Ef[F32 ? 16 : 1][LB<MF>::EPL];
+  if constexpr (F32) lb_load_f32<MF>(L, Es, g.nc / g.band, Ef);
+  else if constexpr (NL > 0) {
+    if (!store) lb_load_reg<MF, NL>(L, Es, E);
+  }
   load_tile2(g, I, J, kap_s, kl);
   for (int f = threadIdx.x; f < nb; f += blockDim.x) {
     BFace bf = bface(g, I, J, f);
@@ -413,14 +543,18 @@ k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict
   __syncthreads();
   fill_trans(g, I, J, kl, 1, tE, tN, dg);
   const LineW W{tE, tN, dg, g.xfast, g.band, 1};
-  const size_t eoff = efac_off<MF>(g, sub, 0, 0);
-  double* Es = (!store && flag[sub]) ? Escr + eoff : Ekeep + eoff;
-  if (store) {
-    bool ok = true;
-    lb_factor<MF>(g, W, L, Es, ok);
-    if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
+  if constexpr (F32) {
+    lb_solve_refined<MF>(g, W, L, Ef, x, wsh);
+  } else {
+    if (store) {
+      bool ok = true;
+      lb_factor<MF>(g, W, L, Es, ok);
+      if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
+      if constexpr (NL > 0) lb_load_reg<MF, NL>(L, Es, E);
+    }
+    if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
+    else lb_solve<MF>(g, W, L, Es, x, wsh);
   }
-  lb_solve_any<MF, NL>(g, W, L, Es, x, wsh);
   double rate = 0.0;
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     int i, j;
@@ -465,9 +599,9 @@ k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict
 // last MRCM update (listed by the conductivity kernel; elsewhere the kept kappa^m blocks are
 // exact). A fixed grid walks the list. Runs on a second stream, overlapped with the interface
 // solve.
-template <int MF>
+template <int MF, typename T>
 __global__ void __launch_bounds__(64)
-k_ds_factor(Geo g, const double* __restrict__ kap_n, double* __restrict__ Escr, const int32_t* __restrict__ list,
+k_ds_factor(Geo g, const double* __restrict__ kap_n, T* __restrict__ Escr, const int32_t* __restrict__ list,
             const int32_t* __restrict__ count, int32_t* err) {
   __shared__ double kl[256], tE[256], tN[256], dg[256];
   LB<MF> L;
@@ -499,16 +633,23 @@ void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double*
 
 // line length padded to MF in {8, 16}; the solve keeps the blocks in registers for the
 // common line counts 8 and 16
-#define MPM_LB_DISPATCH(KERNEL, ...)                                                             \
-  do {                                                                                           \
-    const int nl_ = g.nc / g.band;                                                               \
-    if (line_mf(g) == 8) {                                                                       \
-      if (nl_ == 8) hipLaunchKernelGGL((KERNEL<8, 8>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__);   \
-      else hipLaunchKernelGGL((KERNEL<8, 0>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__);            \
-    } else {                                                                                     \
-      if (nl_ == 16) hipLaunchKernelGGL((KERNEL<16, 16>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__); \
-      else hipLaunchKernelGGL((KERNEL<16, 0>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__);           \
-    }                                                                                            \
+#define MPM_LB_DISPATCH(KERNEL, ...)                                                                     \
+  do {                                                                                                   \
+    const int nl_ = g.nc / g.band;                                                                       \
+    if (line_mf(g) == 8) {                                                                               \
+      if (nl_ == 8) hipLaunchKernelGGL((KERNEL<8, 8, double>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__);  \
+      else hipLaunchKernelGGL((KERNEL<8, 0, double>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__);           \
+    } else {                                                                                             \
+      if (nl_ == 16) hipLaunchKernelGGL((KERNEL<16, 16, double>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__); \
+      else hipLaunchKernelGGL((KERNEL<16, 0, double>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__);          \
+    }                                                                                                    \
+  } while (0)
+
+// precision form: FP32 blocks, any line count up to 16
+#define MPM_LB_DISPATCH_F32(KERNEL, ...)                                                                 \
+  do {                                                                                                   \
+    if (line_mf(g) == 8) hipLaunchKernelGGL((KERNEL<8, 16, float>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__); \
+    else hipLaunchKernelGGL((KERNEL<16, 16, float>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__);        \
   } while (0)
 
 void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
@@ -517,12 +658,45 @@ void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const doub
   MPM_LB_DISPATCH(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, lo);
 }
 
-void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, double* Escr, const int32_t* list,
-                      const int32_t* count, int32_t* err) {
+template <typename T>
+static void ds_factor_any(hipStream_t st, const Geo& g, const double* kap_n, T* Escr, const int32_t* list,
+                          const int32_t* count, int32_t* err) {
   const int grid = std::min(g.nsub, 1024);
   if (line_mf(g) == 8)
-    hipLaunchKernelGGL(k_ds_factor<8>, dim3(grid), dim3(64), 0, st, g, kap_n, Escr, list, count, err);
-  else hipLaunchKernelGGL(k_ds_factor<16>, dim3(grid), dim3(64), 0, st, g, kap_n, Escr, list, count, err);
+    hipLaunchKernelGGL((k_ds_factor<8, T>), dim3(grid), dim3(64), 0, st, g, kap_n, Escr, list, count, err);
+  else hipLaunchKernelGGL((k_ds_factor<16, T>), dim3(grid), dim3(64), 0, st, g, kap_n, Escr, list, count, err);
+}
+
+void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, double* Escr, const int32_t* list,
+                      const int32_t* count, int32_t* err) {
+  ds_factor_any<double>(st, g, kap_n, Escr, list, count, err);
+}
+
+void launch_ds_factor_f32(hipStream_t st, const Geo& g, const double* kap_n, float* Escr, const int32_t* list,
+                          const int32_t* count, int32_t* err) {
+  ds_factor_any<float>(st, g, kap_n, Escr, list, count, err);
+}
+
+void launch_mpm_local_f32(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
+                          const double* uym, const double* q, const float* fac, double* h, double* vbnd,
+                          LeafOut lo) {
+  MPM_LB_DISPATCH_F32(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, lo);
+}
+
+void launch_downscale_f32(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
+                          double* ux, double* uy, double* red_rate, double* red_qin, float* Escr, float* Ekeep,
+                          const int32_t* flag, int32_t* err) {
+  MPM_LB_DISPATCH_F32(k_downscale_lb, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, Escr, Ekeep, flag, 0, err);
+}
+
+__global__ void __launch_bounds__(256) k_to_f32(size_t n, const double* __restrict__ src, float* __restrict__ dst) {
+  const size_t i = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) dst[i] = float(src[i]);
+}
+
+void launch_to_f32(hipStream_t st, size_t n, const double* src, float* dst) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_to_f32, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, n, src, dst);
 }
 
 void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,

@@ -230,6 +230,12 @@ void build_plan(const mpm_desc& d, Plan* p) {
     const int mf = P.band <= 8 ? 8 : 16;
     P.off_dsE = take(size_t(P.nsub) * (P.nc / P.band) * mf * mf * 8);
     P.off_nfac = take(size_t(P.nsub) * (P.nc / P.band) * mf * mf * 8);
+    // precision form: FP32 copies of the three block sets
+    P.n_blocks = size_t(P.nsub) * (P.nc / P.band) * mf * mf;
+    const bool f32 = d.precision == MPM_PREC_FP32_REFINE;
+    P.off_fac32 = take(f32 ? P.n_blocks * 4 : 0);
+    P.off_nfac32 = take(f32 ? P.n_blocks * 4 : 0);
+    P.off_dsE32 = take(f32 ? P.n_blocks * 4 : 0);
     P.off_dsflag = take(size_t(P.nsub) * 4);
     P.off_dslist = take(size_t(P.nsub) * 4);
   }

@@ -80,6 +80,8 @@ struct Plan {
   std::vector<LeafUp> leafup;         // per subdomain
   size_t off_lnodes = 0, off_leafup = 0, off_slot = 0;
   size_t off_dsE = 0, off_nfac = 0;   // downscale inverse blocks: scratch and the kept kappa^m ones
+  size_t n_blocks = 0;                // entries of one block set (kept kappa^m Robin, Neumann, scratch)
+  size_t off_fac32 = 0, off_nfac32 = 0, off_dsE32 = 0;   // their FP32 copies (precision form only)
   size_t off_dsflag = 0;              // per subdomain: conductivity changed since the last update
   size_t off_dslist = 0;              // the changed subdomains (count in the integer word after the error word)
   size_t off_red, off_scal;

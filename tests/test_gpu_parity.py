@@ -28,12 +28,12 @@ def binding():
     return b
 
 
-def _gpu_run(binding, cfg, K, s0=None):
+def _gpu_run(binding, cfg, K, s0=None, precision=0):
     dev = torch.device("cuda:0")
     Kt = torch.from_numpy(np.ascontiguousarray(K)).to(dev)
     s0 = np.zeros_like(K) if s0 is None else s0
     st = torch.from_numpy(np.ascontiguousarray(s0)).to(dev)
-    r = binding.Run(cfg, Kt, st)
+    r = binding.Run(cfg, Kt, st, precision=precision)
     return r
 
 
@@ -80,11 +80,12 @@ def test_one_face_elements_reproduce_fine_solve(binding):
     assert vel_rel_err(cfg, to_np(ux), to_np(uy), fx, fy) <= FP64_VEL_TOL
 
 
-def _compare_runs(binding, cfg, K, nsteps, label, forced=None, vel_tol=FP64_VEL_TOL, sat_tol=FP64_SAT_TOL):
-    print(f"[gpu] run {label} steps={nsteps}", flush=True)
+def _compare_runs(binding, cfg, K, nsteps, label, forced=None, vel_tol=FP64_VEL_TOL, sat_tol=FP64_SAT_TOL,
+                  precision=0):
+    print(f"[gpu] run {label} steps={nsteps} precision={precision}", flush=True)
     s0 = inputs.initial_saturation(cfg)
     orun = splitting.start(cfg, K, s0)
-    r = _gpu_run(binding, cfg, K, s0)
+    r = _gpu_run(binding, cfg, K, s0, precision)
     r.start()
     ux, uy = r.velocity()
     errs = [vel_rel_err(cfg, to_np(ux), to_np(uy), orun.ux, orun.uy)]
@@ -183,3 +184,35 @@ def test_graph_replays_match_eager(binding, monkeypatch):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), n
         assert np.array_equal(a[2], b[2]), n
         assert a[3] == b[3] and a[4] == b[4], n
+
+
+# ---------------------------------------------------------------- precision form
+# FP32 inverse blocks in the MPM-2P local solves and downscaling, FP64 iterative refinement,
+# FP64 interface solve and switch criterion. Bound of the mixed path: relative L2 velocity
+# error <= 1e-6 against the FP64 oracle (saturation likewise, relative L1).
+MIXED_VEL_TOL = 1e-6
+MIXED_SAT_TOL = 1e-6
+
+
+def test_precision_form_c1_full_run(binding):
+    cfg = inputs.config("c1")
+    K = inputs.permeability(cfg)
+    _compare_runs(binding, cfg, K, cfg["steps"], "c1-mixed", vel_tol=MIXED_VEL_TOL, sat_tol=MIXED_SAT_TOL,
+                  precision=binding.PREC_FP32_REFINE)
+
+
+@pytest.mark.parametrize("shape", [(24, 16, 8, 4, 4, 2), (30, 20, 10, 10, 5, 2), (16, 10, 16, 10, 1, 1),
+                                   (40, 24, 8, 8, 2, 2)])
+def test_precision_form_mpm_steps(binding, shape):
+    """MPM-2P steps (forced) through the FP32-block kernels on padded, odd and short line counts."""
+    nx, ny, mx, my, nex, ney = shape
+    cfg, K = inputs.random_problem(61 + nx, nx, ny, mx, my, nex, ney, sigma2=3.0, corr_len=0.2, mu_o=40.0)
+    _compare_runs(binding, cfg, K, 6, f"mixed-{shape}", forced=[None] + ["mpm"] * 6, vel_tol=MIXED_VEL_TOL,
+                  sat_tol=MIXED_SAT_TOL, precision=binding.PREC_FP32_REFINE)
+
+
+def test_precision_form_c2_window(binding):
+    cfg = inputs.config("c2")
+    K = inputs.permeability(cfg)
+    _compare_runs(binding, cfg, K, 3, "c2-mixed", forced=[None, "mpm", "mrcm", "mpm"], vel_tol=MIXED_VEL_TOL,
+                  sat_tol=MIXED_SAT_TOL, precision=binding.PREC_FP32_REFINE)
