@@ -137,6 +137,35 @@ mpm_status mpm_velocity_update(mpm_run* run, int32_t force);
 /* One pass of the while loop of Algorithm 1: C_n transport sub-steps, then a velocity update. */
 mpm_status mpm_step(mpm_run* run, int32_t force);
 
+/* Up to max_updates passes of Algorithm 1's while loop (automatic switch), stopping after the
+ * first one whose water cut reaches breakthrough_cut when stop_at_breakthrough is nonzero
+ * (Section 4.2; the stopping rule of the workloads). *done (host, may be NULL) receives the
+ * number of passes made. Errors as mpm_step. */
+mpm_status mpm_advance(mpm_run* run, int32_t max_updates, int32_t stop_at_breakthrough, int32_t* done);
+
+/* Text of the last HIP error the run met (host buffer of len bytes, NUL-terminated). */
+mpm_status mpm_last_error(const mpm_run* run, char* buf, size_t len);
+
+/* Batch of runs stepped together: the batched and serving forms of the workloads (many
+ * independent runs of Algorithm 1, Section 4.2, of any sizes). A batch holds `capacity` slots;
+ * a slot takes a started run and can be emptied and refilled at any time (continuous batching).
+ * The batch owns no device memory; the runs keep their workspaces and streams, and runs on
+ * distinct streams overlap on the device. Host-side object; one host thread at a time. */
+typedef struct mpm_batch mpm_batch;
+mpm_status mpm_batch_create(int32_t capacity, mpm_batch** out);
+/* MPM_ESTATE if the slot is taken, the run is in another slot of this batch, not started or
+ * poisoned; MPM_EINVAL on a bad slot or NULL. */
+mpm_status mpm_batch_attach(mpm_batch* batch, int32_t slot, mpm_run* run);
+mpm_status mpm_batch_detach(mpm_batch* batch, int32_t slot);
+/* One pass of Algorithm 1's while loop (automatic switch) for every filled slot with
+ * active[slot] != 0 (active NULL: all filled slots). Every run's work is issued before any
+ * wait. breakthrough (host, capacity entries, may be NULL) receives 1 for the stepped runs
+ * whose water cut reached breakthrough_cut. Returns the first error met; a run that failed is
+ * poisoned, the others are stepped. */
+mpm_status mpm_batch_step(mpm_batch* batch, const uint8_t* active, uint8_t* breakthrough);
+/* Frees the batch object only (the runs stay the caller's). */
+mpm_status mpm_batch_destroy(mpm_batch* batch);
+
 /* Copies the current velocity (device pointers ux [ny][nx+1], uy [ny+1][nx]). */
 mpm_status mpm_get_velocity(mpm_run* run, double* dev_ux, double* dev_uy);
 

@@ -65,6 +65,13 @@ _SIGS = {
     "mpm_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
     "mpm_plan_info": (ctypes.c_int32, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 4),
     "mpm_plan_solve_bytes": (ctypes.c_int32, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 3),
+    "mpm_advance": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "mpm_last_error": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t]),
+    "mpm_batch_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "mpm_batch_attach": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "mpm_batch_detach": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "mpm_batch_step": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "mpm_batch_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
     "mpm_profile": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
@@ -169,6 +176,16 @@ class Run:
     def step(self, force: int = AUTO):
         _check(load().mpm_step(self.h, force), "mpm_step")
 
+    def advance(self, max_updates: int, stop_at_breakthrough: bool = True) -> int:
+        done = ctypes.c_int32()
+        _check(load().mpm_advance(self.h, max_updates, int(stop_at_breakthrough), ctypes.byref(done)), "mpm_advance")
+        return done.value
+
+    def last_error(self) -> str:
+        buf = ctypes.create_string_buffer(512)
+        _check(load().mpm_last_error(self.h, buf, 512), "mpm_last_error")
+        return buf.value.decode()
+
     def transport(self, nsteps: int):
         _check(load().mpm_transport(self.h, nsteps), "mpm_transport")
 
@@ -236,3 +253,37 @@ def header_symbols(header_path: str) -> list[str]:
     txt = open(header_path).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:mpm_status|const char\s*\*)\s*(mpm_[a-z_]+)\s*\(", txt, flags=re.M)))
+
+
+class Batch:
+    """Slots of started runs stepped together (thin wrapper of mpm_batch). Give each run its own
+    stream so that their work overlaps on the device."""
+
+    def __init__(self, capacity: int):
+        h = ctypes.c_void_p()
+        _check(load().mpm_batch_create(capacity, ctypes.byref(h)), "mpm_batch_create")
+        self.h = h
+        self.capacity = capacity
+        self.runs = [None] * capacity
+
+    def attach(self, slot: int, run: "Run"):
+        _check(load().mpm_batch_attach(self.h, slot, run.h), "mpm_batch_attach")
+        self.runs[slot] = run
+
+    def detach(self, slot: int):
+        _check(load().mpm_batch_detach(self.h, slot), "mpm_batch_detach")
+        self.runs[slot] = None
+
+    def step(self, active=None):
+        """One pass for every filled (and active) slot; returns the per-slot breakthrough flags."""
+        bt = (ctypes.c_uint8 * self.capacity)()
+        act = None
+        if active is not None:
+            act = (ctypes.c_uint8 * self.capacity)(*[1 if a else 0 for a in active])
+        _check(load().mpm_batch_step(self.h, act, bt), "mpm_batch_step")
+        return [bool(x) for x in bt]
+
+    def close(self):
+        if self.h:
+            load().mpm_batch_destroy(self.h)
+            self.h = None

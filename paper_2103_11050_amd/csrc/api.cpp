@@ -93,7 +93,7 @@ struct mpm_run {
   double eps_prev = 0.0;       // epsilon after the last update (known on the host)
   bool eps_pending = false;    // epsilon of the last update still in flight
   int last_branch = MPM_FORCE_MRCM;
-  double* pinned = nullptr;    // [eps_num, eps_den], written by the eps reduction kernel
+  double* pinned = nullptr;    // [eps_num, eps_den, sequence, water cut], written by kernels
   double* pinned_dev = nullptr;  // the same memory as the device sees it
   int64_t eps_seq = 0;           // sequence number of the latest kappa launch
   hipEvent_t ev_eps = nullptr;
@@ -376,21 +376,11 @@ mpm_status mpm_update(mpm_run* r) {
   return mpm_update_body(r, false);
 }
 
-mpm_status velocity_update(mpm_run* r, int32_t force, bool kappa_done = false) {
-  // decision (Algorithm 1: "if epsilon > eta")
-  mpm_status st = MPM_OK;
-  if (!kappa_done) st = kappa_and_eps(r);
-  if (st) return st;
-  double decide;
-  if (r->P.d.switch_rule == MPM_SWITCH_TEXT) {
-    st = wait_eps(r);
-    if (st) return st;
-    decide = eps_from(r, r->pinned[0], r->pinned[1]);
-  } else {
-    decide = r->eps_prev;
-  }
+// The update for a decision value (Algorithm 1: "if epsilon > eta"; force overrides it).
+mpm_status vu_update(mpm_run* r, int32_t force, double decide) {
   int branch = decide > r->P.d.eta ? MPM_FORCE_MRCM : MPM_FORCE_MPM;
   if (force == MPM_FORCE_MPM || force == MPM_FORCE_MRCM) branch = force;
+  mpm_status st;
   if (branch == MPM_FORCE_MRCM) {
     st = mrcm_update(r);
     r->eps_prev = 0.0;
@@ -402,18 +392,46 @@ mpm_status velocity_update(mpm_run* r, int32_t force, bool kappa_done = false) {
   if (st) return st;
   r->last_branch = branch;
   r->te += 1;
-  if (r->eps_pending && r->P.d.switch_rule == MPM_SWITCH_ALG1) {
-    // epsilon of this update is needed by the next decision only; it was reduced before the
-    // solve, so waiting for it does not drain the stream
-    st = wait_eps(r);
-    if (st) return st;
-    r->eps_prev = eps_from(r, r->pinned[0], r->pinned[1]);
-    r->eps_pending = false;
-  } else if (r->eps_pending) {
+  return MPM_OK;
+}
+
+// After the update is enqueued: epsilon of this update for the next decision. With the lagged
+// rule it was reduced before the solve, so waiting for it does not drain the stream.
+mpm_status vu_finish(mpm_run* r) {
+  if (r->eps_pending) {
+    if (r->P.d.switch_rule == MPM_SWITCH_ALG1) {
+      mpm_status st = wait_eps(r);
+      if (st) return st;
+    }
     r->eps_prev = eps_from(r, r->pinned[0], r->pinned[1]);
     r->eps_pending = false;
   }
   return MPM_OK;
+}
+
+// The decision value: epsilon of the current saturation (text rule; waits for it) or of the
+// previous update (Algorithm 1 as written).
+mpm_status vu_decision(mpm_run* r, double* decide) {
+  if (r->P.d.switch_rule == MPM_SWITCH_TEXT) {
+    mpm_status st = wait_eps(r);
+    if (st) return st;
+    *decide = eps_from(r, r->pinned[0], r->pinned[1]);
+  } else {
+    *decide = r->eps_prev;
+  }
+  return MPM_OK;
+}
+
+mpm_status velocity_update(mpm_run* r, int32_t force, bool kappa_done = false) {
+  mpm_status st = MPM_OK;
+  if (!kappa_done) st = kappa_and_eps(r);
+  if (st) return st;
+  double decide;
+  st = vu_decision(r, &decide);
+  if (st) return st;
+  st = vu_update(r, force, decide);
+  if (st) return st;
+  return vu_finish(r);
 }
 
 mpm_status transport_body(mpm_run* r, int32_t nsteps) {
@@ -585,7 +603,7 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   if (hipHostGetDevicePointer(reinterpret_cast<void**>(&r->pinned_dev), r->pinned, 0) != hipSuccess ||
       !r->pinned_dev)
     return fail(MPM_EHIP);
-  r->pinned[0] = r->pinned[1] = r->pinned[2] = 0.0;
+  r->pinned[0] = r->pinned[1] = r->pinned[2] = r->pinned[3] = 0.0;
   // events that only order work on the device (and the epsilon event, whose host-side data
   // is checked by sequence number): device-scope release, no cache writeback to system scope
   const unsigned ev_flags = hipEventDisableTiming | hipEventReleaseToDevice;
@@ -696,6 +714,110 @@ mpm_status mpm_step(mpm_run* r, int32_t force) {
   mpm_status st = enter(r);
   if (st) return st;
   return leave(r, step(r, force));
+}
+
+mpm_status mpm_advance(mpm_run* r, int32_t max_updates, int32_t stop_at_breakthrough, int32_t* done) {
+  if (!r || max_updates < 0) return MPM_EINVAL;
+  if (!r->started || r->poisoned) return MPM_ESTATE;
+  mpm_status st = enter(r);
+  if (st) return st;
+  int32_t n = 0;
+  while (n < max_updates) {
+    st = step(r, MPM_AUTO);
+    if (st) break;
+    ++n;
+    // the water cut reaches host memory with the epsilon sums of the same step
+    if (stop_at_breakthrough && r->pinned[3] >= r->P.d.breakthrough_cut) break;
+  }
+  if (done) *done = n;
+  return leave(r, st);
+}
+
+mpm_status mpm_last_error(const mpm_run* r, char* buf, size_t len) {
+  if (!r || !buf || !len) return MPM_EINVAL;
+  const size_t n = std::min(len - 1, r->last_error.size());
+  std::memcpy(buf, r->last_error.data(), n);
+  buf[n] = 0;
+  return MPM_OK;
+}
+
+// ------------------------------------------------------------------ batch of runs
+struct mpm_batch {
+  std::vector<mpm_run*> slot;
+};
+
+mpm_status mpm_batch_create(int32_t capacity, mpm_batch** out) {
+  if (capacity <= 0 || !out) return MPM_EINVAL;
+  mpm_batch* b = new (std::nothrow) mpm_batch();
+  if (!b) return MPM_ENOMEM;
+  b->slot.assign(size_t(capacity), nullptr);
+  *out = b;
+  return MPM_OK;
+}
+
+mpm_status mpm_batch_attach(mpm_batch* b, int32_t slot, mpm_run* r) {
+  if (!b || !r || slot < 0 || slot >= int32_t(b->slot.size())) return MPM_EINVAL;
+  if (b->slot[slot]) return MPM_ESTATE;
+  for (mpm_run* x : b->slot)
+    if (x == r) return MPM_ESTATE;
+  if (!r->started || r->poisoned) return MPM_ESTATE;
+  b->slot[slot] = r;
+  return MPM_OK;
+}
+
+mpm_status mpm_batch_detach(mpm_batch* b, int32_t slot) {
+  if (!b || slot < 0 || slot >= int32_t(b->slot.size())) return MPM_EINVAL;
+  b->slot[slot] = nullptr;
+  return MPM_OK;
+}
+
+mpm_status mpm_batch_step(mpm_batch* b, const uint8_t* active, uint8_t* breakthrough) {
+  if (!b) return MPM_EINVAL;
+  const size_t n = b->slot.size();
+  std::vector<mpm_run*> run;
+  for (size_t i = 0; i < n; ++i) {
+    mpm_run* r = b->slot[i];
+    if (!r || (active && !active[i])) continue;
+    if (r->poisoned) return MPM_ESTATE;
+    run.push_back(r);
+  }
+  // every run's transport and conductivity first, then (lagged rule) its update, before any
+  // wait; each run is on its own stream, so their kernels overlap on the device
+  mpm_status first = MPM_OK;
+  auto note = [&](mpm_run* r, mpm_status st) {
+    if (st && !first) first = st;
+    if (st) r->poisoned = true;
+  };
+  for (mpm_run* r : run) {
+    mpm_status st = enter(r);
+    if (!st) st = transport(r, r->P.d.cn);
+    if (!st) st = kappa_and_eps(r);
+    if (!st && r->P.d.switch_rule == MPM_SWITCH_ALG1) st = vu_update(r, MPM_AUTO, r->eps_prev);
+    note(r, st);
+  }
+  for (mpm_run* r : run) {
+    if (r->poisoned || r->P.d.switch_rule != MPM_SWITCH_TEXT) continue;
+    double decide;
+    mpm_status st = vu_decision(r, &decide);
+    if (!st) st = vu_update(r, MPM_AUTO, decide);
+    note(r, st);
+  }
+  for (mpm_run* r : run) {
+    if (r->poisoned) continue;
+    note(r, leave(r, vu_finish(r)));
+  }
+  if (breakthrough)
+    for (size_t i = 0; i < n; ++i) {
+      mpm_run* r = b->slot[i];
+      breakthrough[i] = (r && (!active || active[i]) && r->pinned[3] >= r->P.d.breakthrough_cut) ? 1 : 0;
+    }
+  return first;
+}
+
+mpm_status mpm_batch_destroy(mpm_batch* b) {
+  if (!b) return MPM_EINVAL;
+  delete b;
+  return MPM_OK;
 }
 
 mpm_status mpm_get_velocity(mpm_run* r, double* ux, double* uy) {

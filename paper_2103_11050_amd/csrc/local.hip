@@ -55,8 +55,9 @@ k_kappa(Geo g, const double* __restrict__ s, const double* __restrict__ K, doubl
   }
 }
 
-// Fixed-order reduction of the epsilon partial sums into the scalar block; the two sums are
-// also written to host memory for the switch decision.
+// Fixed-order reduction of the epsilon partial sums into the scalar block; the two sums (and
+// the water cut of the preceding transport) are also written to host memory, with a sequence
+// number, for the switch decision and breakthrough checks.
 __global__ void __launch_bounds__(256) k_reduce_eps(int nblocks, const double* __restrict__ red,
                                                     double* __restrict__ scal, int32_t* __restrict__ seq,
                                                     double* __restrict__ host) {
@@ -97,6 +98,7 @@ __global__ void __launch_bounds__(256) k_reduce_eps(int nblocks, const double* _
     *seq = q;
     host[0] = sa[0];
     host[1] = sb[0];
+    host[3] = scal[SC_WCUT];
     host[2] = double(q);
   }
 }

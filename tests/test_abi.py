@@ -89,3 +89,28 @@ def test_null_and_misaligned_arguments(lib):
     assert lib.mpm_step(None, -1) == binding.MPM_EINVAL
     assert lib.mpm_transport(None, 1) == binding.MPM_EINVAL
     assert lib.mpm_get_stats(None, None) == binding.MPM_EINVAL
+
+
+def test_batch_host_side_errors(lib):
+    """The batch object is host-only: argument and state errors need no device."""
+    h = ctypes.c_void_p()
+    assert lib.mpm_batch_create(0, ctypes.byref(h)) == binding.MPM_EINVAL
+    assert lib.mpm_batch_create(4, None) == binding.MPM_EINVAL
+    assert lib.mpm_batch_create(4, ctypes.byref(h)) == binding.MPM_OK
+    assert lib.mpm_batch_attach(h, 0, None) == binding.MPM_EINVAL
+    assert lib.mpm_batch_attach(h, 4, ctypes.c_void_p(1)) == binding.MPM_EINVAL
+    assert lib.mpm_batch_attach(h, -1, ctypes.c_void_p(1)) == binding.MPM_EINVAL
+    assert lib.mpm_batch_detach(h, 7) == binding.MPM_EINVAL
+    assert lib.mpm_batch_detach(h, 2) == binding.MPM_OK
+    bt = (ctypes.c_uint8 * 4)(9, 9, 9, 9)
+    assert lib.mpm_batch_step(h, None, bt) == binding.MPM_OK      # empty batch: nothing to do
+    assert list(bt) == [0, 0, 0, 0]
+    assert lib.mpm_batch_step(None, None, None) == binding.MPM_EINVAL
+    assert lib.mpm_batch_destroy(h) == binding.MPM_OK
+    assert lib.mpm_batch_destroy(None) == binding.MPM_EINVAL
+
+
+def test_advance_and_last_error_arguments(lib):
+    assert lib.mpm_advance(None, 1, 1, None) == binding.MPM_EINVAL
+    buf = ctypes.create_string_buffer(8)
+    assert lib.mpm_last_error(None, buf, 8) == binding.MPM_EINVAL

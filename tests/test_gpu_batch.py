@@ -1,0 +1,154 @@
+"""Batched and served forms (GPU only): runs of different sizes stepped together in one batch,
+each on its own stream, give bitwise the results of the same runs stepped alone; slots can be
+emptied and refilled between steps; breakthrough stops a run."""
+import numpy as np
+import pytest
+
+from paper_2103_11050_amd import inputs
+
+from .gpu_common import to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def binding():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_11050_amd import binding as b
+    b.load()
+    return b
+
+
+PROBLEMS = [
+    # seed, nx, ny, sub, ne, overrides
+    (101, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=20.0, eta=0.01)),
+    (102, 64, 48, 16, 4, dict(sigma2=3.0, corr_len=0.1, mu_o=50.0, eta=0.05)),
+    (103, 48, 48, 8, 4, dict(sigma2=1.0, corr_len=0.2, mu_o=10.0, eta=0.02, switch_rule="text")),
+    (104, 64, 64, 16, 8, dict(sigma2=4.0, corr_len=0.1, mu_o=100.0, eta=0.1)),
+]
+
+
+def _make(binding, p, stream=None):
+    seed, nx, ny, sub, ne, kw = p
+    cfg, K = inputs.random_problem(seed, nx, ny, sub, sub, ne, ne, **kw)
+    dev = torch.device("cuda:0")
+    Kt = torch.from_numpy(np.ascontiguousarray(K)).to(dev)
+    st = torch.from_numpy(np.ascontiguousarray(inputs.initial_saturation(cfg))).to(dev)
+    torch.cuda.synchronize()
+    r = binding.Run(cfg, Kt, st, stream=stream)
+    r.start()
+    return r
+
+
+def _state(r):
+    torch.cuda.synchronize()
+    ux, uy = r.velocity()
+    s = r.saturation()
+    st = r.stats()
+    torch.cuda.synchronize()
+    return to_np(ux), to_np(uy), to_np(s), st
+
+
+def _same(a, b):
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    for k in ("te", "tm", "eps", "pvi", "water_cut", "last_branch"):
+        assert a[3][k] == b[3][k], (k, a[3][k], b[3][k])
+
+
+def test_batch_equals_solo(binding):
+    nsteps = 12
+    print("[gpu] batch of", len(PROBLEMS), "runs,", nsteps, "steps", flush=True)
+    solo = []
+    for p in PROBLEMS:
+        r = _make(binding, p)
+        for _ in range(nsteps):
+            r.step()
+        solo.append(_state(r))
+        r.close()
+    streams = [torch.cuda.Stream() for _ in PROBLEMS]
+    runs = [_make(binding, p, s) for p, s in zip(PROBLEMS, streams)]
+    b = binding.Batch(len(runs) + 1)          # one slot left empty
+    for i, r in enumerate(runs):
+        b.attach(i, r)
+    for _ in range(nsteps):
+        b.step()
+    for r, ref in zip(runs, solo):
+        _same(_state(r), ref)
+    assert any(ref[3]["tm"] > 1 for ref in solo), "no basis update exercised"
+    b.close()
+    for r in runs:
+        r.close()
+
+
+def test_slots_refilled_between_steps(binding):
+    """Continuous batching: a run leaves its slot for some steps (its state is untouched), a new
+    run takes another slot mid-way, and every run ends equal to its solo run with the same
+    number of steps."""
+    p0, p1, p2 = PROBLEMS[0], PROBLEMS[1], PROBLEMS[3]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    r0, r1 = _make(binding, p0, streams[0]), _make(binding, p1, streams[1])
+    b = binding.Batch(2)
+    b.attach(0, r0)
+    b.attach(1, r1)
+    n0 = n1 = n2 = 0
+    for _ in range(3):
+        b.step()
+        n0 += 1
+        n1 += 1
+    b.detach(0)                       # r0 waits
+    for _ in range(2):
+        b.step()
+        n1 += 1
+    r2 = _make(binding, p2, streams[2])
+    b.attach(0, r2)                   # a new request takes the freed slot
+    for _ in range(4):
+        b.step()
+        n1 += 1
+        n2 += 1
+    b.step([False, True])             # only slot 1
+    n1 += 1
+    b.detach(1)
+    b.attach(1, r0)                   # r0 comes back
+    for _ in range(2):
+        b.step()
+        n0 += 1
+        n2 += 1
+    got = {0: _state(r0), 1: _state(r1), 2: _state(r2)}
+    for key, p, n in ((0, p0, n0), (1, p1, n1), (2, p2, n2)):
+        r = _make(binding, p)
+        for _ in range(n):
+            r.step()
+        _same(got[key], _state(r))
+        r.close()
+    b.close()
+    for r in (r0, r1, r2):
+        r.close()
+
+
+def test_advance_stops_at_breakthrough(binding):
+    cfg, K = inputs.random_problem(7, 32, 16, 8, 8, 2, 2, sigma2=1.0, corr_len=0.3, mu_o=5.0, eta=0.05)
+    dev = torch.device("cuda:0")
+    Kt = torch.from_numpy(np.ascontiguousarray(K)).to(dev)
+    st = torch.from_numpy(np.zeros_like(K)).to(dev)
+    r = binding.Run(cfg, Kt, st)
+    r.start()
+    done = r.advance(5000, True)
+    s = r.stats()
+    assert s["breakthrough"] == 1 and s["water_cut"] >= cfg["breakthrough_cut"]
+    assert s["te"] == done + 1
+    # stepping one by one gives the same first breakthrough step
+    r2 = binding.Run(cfg, Kt, st)
+    r2.start()
+    n = 0
+    while True:
+        r2.step()
+        n += 1
+        if r2.stats()["breakthrough"]:
+            break
+    assert n == done
+    _same(_state(r), _state(r2))
+    r.close()
+    r2.close()
