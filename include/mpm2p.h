@@ -143,7 +143,8 @@ mpm_status mpm_step(mpm_run* run, int32_t force);
  * number of passes made. Errors as mpm_step. */
 mpm_status mpm_advance(mpm_run* run, int32_t max_updates, int32_t stop_at_breakthrough, int32_t* done);
 
-/* Text of the last HIP error the run met (host buffer of len bytes, NUL-terminated). */
+/* Text of the last HIP error the run met (host buffer of len bytes, NUL-terminated); with run
+ * NULL, why the last mpm_create of the calling thread failed. */
 mpm_status mpm_last_error(const mpm_run* run, char* buf, size_t len);
 
 /* Batch of runs stepped together: the batched and serving forms of the workloads (many

@@ -87,6 +87,9 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library {path} is missing: build it with `python -m paper_2103_11050_amd.build`")
+    # PyTorch brings its own HIP runtime; load it first so that the library binds to the same
+    # runtime instance as the tensors and streams it is given (one runtime per process)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
@@ -163,10 +166,18 @@ class Run:
         aligned = (base + 255) & ~255
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        _check(lib.mpm_create(ctypes.byref(self.desc), ctypes.c_void_p(aligned), ctypes.c_size_t(self.ws_bytes),
-                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), "mpm_create")
+        st = lib.mpm_create(ctypes.byref(self.desc), ctypes.c_void_p(aligned), ctypes.c_size_t(self.ws_bytes),
+                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != MPM_OK:
+            buf = ctypes.create_string_buffer(512)
+            lib.mpm_last_error(None, buf, 512)
+            _check(st, "mpm_create (" + buf.value.decode() + ")")
         self.h = h
         self._keep = (K, s0, q)
+        # the inputs were written on the caller's current stream
+        cur = torch.cuda.current_stream(self.device)
+        if self.stream != cur:
+            self.stream.wait_stream(cur)
         _check(lib.mpm_set_fields(self.h, ctypes.c_void_p(_ptr(K)), ctypes.c_void_p(_ptr(q)),
                                   ctypes.c_void_p(_ptr(s0))), "mpm_set_fields")
 
@@ -199,12 +210,23 @@ class Run:
         uy = torch.empty((ny + 1, nx), dtype=torch.float64, device=self.device)
         _check(load().mpm_get_velocity(self.h, ctypes.c_void_p(ux.data_ptr()), ctypes.c_void_p(uy.data_ptr())),
                "mpm_get_velocity")
+        self._hand_over(ux, uy)
         return ux, uy
+
+    def _hand_over(self, *ts):
+        """Outputs written on the run's stream become usable on the caller's current stream."""
+        import torch
+        cur = torch.cuda.current_stream(self.device)
+        if self.stream != cur:
+            for t in ts:
+                t.record_stream(self.stream)
+            cur.wait_stream(self.stream)
 
     def saturation(self):
         import torch
         s = torch.empty((self.cfg["ny"], self.cfg["nx"]), dtype=torch.float64, device=self.device)
         _check(load().mpm_get_saturation(self.h, ctypes.c_void_p(s.data_ptr())), "mpm_get_saturation")
+        self._hand_over(s)
         return s
 
     def stats(self) -> dict:

@@ -18,6 +18,9 @@ using namespace mpm;
 
 namespace {
 
+// Why the last mpm_create of this thread failed (for mpm_last_error with no run).
+thread_local std::string g_create_error;
+
 // max over [0,1] of f'(s) = 2 M s (1-s) / (M s^2 + (1-s)^2)^2 for the Corey curves: the
 // interior zero of f'' is the root of the cubic
 //   (1 - 2s)(M s^2 + (1-s)^2) - 4 s (1-s)(M s - (1-s)) = 0,
@@ -563,6 +566,14 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   r->M = P.d.mu_o / P.d.mu_w;
   r->fmax_deriv = max_fprime(r->M);
   r->area = P.d.lx * P.d.ly;
+#define CREATE_CHK(call)                                                           \
+  do {                                                                             \
+    const hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess) {                                                        \
+      g_create_error = std::string(#call) + ": " + hipGetErrorString(e_);          \
+      return fail(MPM_EHIP);                                                       \
+    }                                                                              \
+  } while (0)
   auto fail = [&](mpm_status s) {
     if (r->pinned) hipHostFree(r->pinned);
     if (r->ev_eps) hipEventDestroy(r->ev_eps);
@@ -599,19 +610,18 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
                     in(r->nd.lnodes, std::max<size_t>(P.lnodes.size(), 1) * sizeof(NodeDev));
     if (!ok) return fail(MPM_EINVAL);
   }
-  if (hipHostMalloc(reinterpret_cast<void**>(&r->pinned), 64, hipHostMallocDefault) != hipSuccess) return fail(MPM_ENOMEM);
-  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&r->pinned_dev), r->pinned, 0) != hipSuccess ||
-      !r->pinned_dev)
-    return fail(MPM_EHIP);
+  CREATE_CHK(hipHostMalloc(reinterpret_cast<void**>(&r->pinned), 64, hipHostMallocDefault));
+  CREATE_CHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&r->pinned_dev), r->pinned, 0));
+  if (!r->pinned_dev) return fail(MPM_EHIP);
   r->pinned[0] = r->pinned[1] = r->pinned[2] = r->pinned[3] = 0.0;
   // events that only order work on the device (and the epsilon event, whose host-side data
   // is checked by sequence number): device-scope release, no cache writeback to system scope
   const unsigned ev_flags = hipEventDisableTiming | hipEventReleaseToDevice;
-  if (hipEventCreateWithFlags(&r->ev_eps, ev_flags) != hipSuccess) return fail(MPM_EHIP);
-  if (hipEventCreateWithFlags(&r->ev_fork, ev_flags) != hipSuccess) return fail(MPM_EHIP);
-  if (hipEventCreateWithFlags(&r->ev_join, ev_flags) != hipSuccess) return fail(MPM_EHIP);
-  if (hipEventCreateWithFlags(&r->ev_in, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
-  if (hipEventCreateWithFlags(&r->ev_out, hipEventDisableTiming) != hipSuccess) return fail(MPM_EHIP);
+  CREATE_CHK(hipEventCreateWithFlags(&r->ev_eps, ev_flags));
+  CREATE_CHK(hipEventCreateWithFlags(&r->ev_fork, ev_flags));
+  CREATE_CHK(hipEventCreateWithFlags(&r->ev_join, ev_flags));
+  CREATE_CHK(hipEventCreateWithFlags(&r->ev_in, hipEventDisableTiming));
+  CREATE_CHK(hipEventCreateWithFlags(&r->ev_out, hipEventDisableTiming));
   // Graph replay is opt-in: on gfx950 it measured slower than eager launches for this step.
   // With graphs the work runs on a stream of the library's own (capture needs one), ordered
   // against the caller's stream by events; without, it runs on the caller's stream.
@@ -621,12 +631,12 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   }
   // the library's streams, default priority
   if (r->use_graphs) {
-    if (hipStreamCreateWithFlags(&r->st, hipStreamNonBlocking) != hipSuccess) return fail(MPM_EHIP);
+    CREATE_CHK(hipStreamCreateWithFlags(&r->st, hipStreamNonBlocking));
   } else {
     r->st = r->ust;
   }
-  if (hipStreamCreateWithFlags(&r->st2, hipStreamNonBlocking) != hipSuccess) return fail(MPM_EHIP);
-  if (hipStreamSynchronize(r->ust) != hipSuccess) return fail(MPM_EHIP);
+  CREATE_CHK(hipStreamCreateWithFlags(&r->st2, hipStreamNonBlocking));
+  CREATE_CHK(hipStreamSynchronize(r->ust));
   // upload the plan's index tables
   auto up = [&](size_t off, const void* src, size_t n) {
     return n ? hipMemcpyAsync(r->ws + off, src, n, hipMemcpyHostToDevice, r->st) : hipSuccess;
@@ -734,9 +744,10 @@ mpm_status mpm_advance(mpm_run* r, int32_t max_updates, int32_t stop_at_breakthr
 }
 
 mpm_status mpm_last_error(const mpm_run* r, char* buf, size_t len) {
-  if (!r || !buf || !len) return MPM_EINVAL;
-  const size_t n = std::min(len - 1, r->last_error.size());
-  std::memcpy(buf, r->last_error.data(), n);
+  if (!buf || !len) return MPM_EINVAL;
+  const std::string& e = r ? r->last_error : g_create_error;
+  const size_t n = std::min(len - 1, e.size());
+  std::memcpy(buf, e.data(), n);
   buf[n] = 0;
   return MPM_OK;
 }

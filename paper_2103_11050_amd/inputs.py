@@ -94,3 +94,37 @@ def random_problem(seed: int, nx: int, ny: int, sub_x: int, sub_y: int, ne_x: in
     cfg["bc_value"] = list(cfg["bc_value"])
     cfg.update(overrides)
     return cfg, permeability(cfg)
+
+
+def batch_workload(n: int = 256) -> list[dict]:
+    """Batched form: n realisations of uneven sizes, class r mod 3 -> 64^2 cells in 8^2
+    subdomains, 128^2 in 16^2, 256^2 in 16^2 (subdomain sides are limited to 16 cells here);
+    4 interface elements per side, log-variance 4, correlation length 0.05, seed 1000 + r,
+    viscosity ratio 100, eta = 0.1."""
+    out = []
+    for r in range(n):
+        nx, sub = ((64, 8), (128, 16), (256, 16))[r % 3]
+        cfg = dict(_BASE, nx=nx, ny=nx, sub_x=sub, sub_y=sub, ne_x=4, ne_y=4, mu_o=100.0, eta=0.1,
+                   sigma2=4.0, corr_len=0.05, seed=1000 + r, steps=0)
+        cfg["bc_kind"] = list(cfg["bc_kind"])
+        cfg["bc_value"] = list(cfg["bc_value"])
+        out.append(cfg)
+    return out
+
+
+def serve_requests(n: int = 256, grids=(128, 256, 512), seed: int = 7) -> list[dict]:
+    """Serving form: n forward-run requests; grid drawn uniformly from `grids` (16^2
+    subdomains, 4 interface elements per side), log-variance uniform in [1, 4], correlation
+    length 0.05, viscosity ratio uniform in [10, 100], permeability seed 5000 + r. The draws
+    use numpy's PCG64 with `seed`."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for r in range(n):
+        nx = int(grids[rng.integers(len(grids))])
+        cfg = dict(_BASE, nx=nx, ny=nx, sub_x=16, sub_y=16, ne_x=4, ne_y=4,
+                   mu_o=float(rng.uniform(10.0, 100.0)), eta=0.1, sigma2=float(rng.uniform(1.0, 4.0)),
+                   corr_len=0.05, seed=5000 + r, steps=0)
+        cfg["bc_kind"] = list(cfg["bc_kind"])
+        cfg["bc_value"] = list(cfg["bc_value"])
+        out.append(cfg)
+    return out

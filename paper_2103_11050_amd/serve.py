@@ -1,0 +1,204 @@
+"""Batched and served forms of the MPM-2P workload on one GPU.
+
+Serving: forward-run requests (Algorithm 1 of Section 4.2, each run to water breakthrough)
+arrive over time. A request is admitted into a free slot of one `Batch` when its exact device
+footprint (`mpm_workspace_size`) fits the remaining HBM budget; it then keeps its basis,
+interface factorisation and saturation resident in its workspace and steps together with the
+others (each run on its own stream, every run's work issued before any wait). A finished run
+leaves its slot and frees its footprint for the next request (continuous batching).
+
+Batched: many realisations of uneven sizes stepped together for a fixed number of passes.
+
+Both report velocity updates per second over the whole batch; serving also reports runs/s and
+the p50/p99 request latency (arrival to breakthrough).
+
+    python -m paper_2103_11050_amd.serve serve --requests 32
+    python -m paper_2103_11050_amd.serve batch --runs 256 --steps 20
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import binding, inputs
+
+
+class Server:
+    """Slots of one batch, admission by device footprint, one stream per slot."""
+
+    def __init__(self, capacity: int, budget_bytes: int, max_updates: int = 100000, keep_results: bool = False):
+        import torch
+        self.torch = torch
+        self.capacity = capacity
+        self.budget = budget_bytes
+        self.max_updates = max_updates
+        self.keep = keep_results
+        self.batch = binding.Batch(capacity)
+        self.streams = [torch.cuda.Stream() for _ in range(capacity)]
+        self.dev = torch.device("cuda:0")
+
+    def _open(self, cfg: dict, slot: int):
+        torch = self.torch
+        K = inputs.permeability(cfg)
+        Kt = torch.from_numpy(K).to(self.dev)
+        st = torch.from_numpy(inputs.initial_saturation(cfg)).to(self.dev)
+        torch.cuda.synchronize()
+        run = binding.Run(cfg, Kt, st, stream=self.streams[slot])
+        run.start()
+        return run
+
+    def serve(self, requests: list[dict], arrivals: list[float]) -> dict:
+        """Runs every request to breakthrough (or max_updates passes); arrivals in seconds from
+        the start. Returns the summary and the per-request records."""
+        order = sorted(range(len(requests)), key=lambda i: arrivals[i])
+        pending = collections.deque(order)
+        free = list(range(self.capacity))
+        active = {}          # slot -> [request id, run, footprint, passes]
+        used = 0
+        recs = {}
+        t0 = time.perf_counter()
+        steps_total = 0
+        batch_steps = 0
+        while pending or active:
+            now = time.perf_counter() - t0
+            while pending and free and arrivals[pending[0]] <= now:
+                i = pending[0]
+                need = binding.workspace_size(requests[i])
+                if used + need > self.budget:
+                    break
+                pending.popleft()
+                slot = free.pop()
+                run = self._open(requests[i], slot)
+                self.batch.attach(slot, run)
+                active[slot] = [i, run, need, 0]
+                used += need
+                recs[i] = {"id": i, "nx": requests[i]["nx"], "arrival": arrivals[i],
+                           "admit": time.perf_counter() - t0}
+            if not active:
+                if pending:
+                    time.sleep(max(0.0, min(0.01, arrivals[pending[0]] - (time.perf_counter() - t0))))
+                continue
+            bt = self.batch.step()
+            steps_total += len(active)
+            batch_steps += 1
+            for slot in list(active):
+                i, run, need, n = active[slot]
+                n += 1
+                active[slot][3] = n
+                if bt[slot] or n >= self.max_updates:
+                    self.batch.detach(slot)
+                    s = run.stats()
+                    rec = recs[i]
+                    rec.update(finish=time.perf_counter() - t0, te=s["te"], tm=s["tm"], pvi=s["pvi"],
+                               breakthrough=bool(s["breakthrough"]), passes=n)
+                    rec["latency"] = rec["finish"] - rec["arrival"]
+                    if self.keep:
+                        ux, uy = run.velocity()
+                        rec["state"] = (ux.cpu().numpy(), uy.cpu().numpy(), run.saturation().cpu().numpy())
+                    run.close()
+                    del active[slot]
+                    free.append(slot)
+                    used -= need
+        makespan = time.perf_counter() - t0
+        lat = np.array([r["latency"] for r in recs.values()])
+        te = sum(r["te"] for r in recs.values())
+        summary = {"requests": len(recs), "makespan_s": round(makespan, 3),
+                   "runs_per_s": round(len(recs) / makespan, 3),
+                   "velocity_updates_per_s": round(te / makespan, 1),
+                   "latency_p50_s": round(float(np.percentile(lat, 50)), 3),
+                   "latency_p99_s": round(float(np.percentile(lat, 99)), 3),
+                   "all_broke_through": all(r["breakthrough"] for r in recs.values()),
+                   "mean_runs_per_batch_step": round(steps_total / max(1, batch_steps), 2)}
+        return {"summary": summary, "records": [recs[i] for i in sorted(recs)]}
+
+    def close(self):
+        self.batch.close()
+
+
+def poisson_arrivals(n: int, rate: float, seed: int = 7) -> list[float]:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return list(np.cumsum(rng.exponential(1.0 / rate, n)))
+
+
+def batch_rate(cfgs: list[dict], steps: int) -> dict:
+    """The batched form: every realisation started, then `steps` passes of the whole batch."""
+    import torch
+    dev = torch.device("cuda:0")
+    b = binding.Batch(len(cfgs))
+    runs = []
+    for i, cfg in enumerate(cfgs):
+        Kt = torch.from_numpy(inputs.permeability(cfg)).to(dev)
+        st = torch.from_numpy(inputs.initial_saturation(cfg)).to(dev)
+        torch.cuda.synchronize()
+        r = binding.Run(cfg, Kt, st, stream=torch.cuda.Stream())
+        r.start()
+        b.attach(i, r)
+        runs.append(r)
+    torch.cuda.synchronize()
+    b.step()                      # warm-up pass
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # the same realisations one after the other on one stream, for comparison
+    t1 = time.perf_counter()
+    for r in runs:
+        r.step()
+    torch.cuda.synchronize()
+    one = time.perf_counter() - t1
+    mrcm = sum(r.stats()["tm"] for r in runs)
+    for r in runs:
+        r.close()
+    b.close()
+    cells = sum(c["nx"] * c["ny"] for c in cfgs)
+    return {"runs": len(cfgs), "steps": steps, "velocity_updates_per_s": round(len(cfgs) * steps / dt, 1),
+            "cell_updates_per_s": round(cells * steps / dt, 1), "ms_per_batch_step": round(1e3 * dt / steps, 3),
+            "ms_one_pass_each_run_in_turn": round(1e3 * one, 3), "basis_sets_total": int(mrcm)}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    s = sub.add_parser("serve")
+    s.add_argument("--requests", type=int, default=32)
+    s.add_argument("--grids", type=int, nargs="+", default=[128, 256, 512])
+    s.add_argument("--capacity", type=int, default=16)
+    s.add_argument("--budget-gib", type=float, default=200.0)
+    s.add_argument("--rate", type=float, default=0.0,
+                   help="arrivals per second; 0: 70%% of the capacity measured with all requests at t = 0")
+    s.add_argument("--max-updates", type=int, default=100000)
+    b = sub.add_parser("batch")
+    b.add_argument("--runs", type=int, default=256)
+    b.add_argument("--steps", type=int, default=20)
+    args = ap.parse_args(argv)
+    binding.load()
+    if args.mode == "batch":
+        out = batch_rate(inputs.batch_workload(args.runs), args.steps)
+        print(json.dumps({"form": "batched", **out}))
+        return
+    reqs = inputs.serve_requests(args.requests, tuple(args.grids))
+    budget = int(args.budget_gib * (1 << 30))
+    rate = args.rate
+    out = {"form": "serving", "grids": args.grids, "capacity": args.capacity}
+    if rate <= 0:
+        srv = Server(args.capacity, budget, args.max_updates)
+        cal = srv.serve(reqs, [0.0] * len(reqs))["summary"]
+        srv.close()
+        rate = 0.7 * cal["runs_per_s"]
+        out["capacity_measured"] = cal
+    srv = Server(args.capacity, budget, args.max_updates)
+    res = srv.serve(reqs, poisson_arrivals(len(reqs), rate))
+    srv.close()
+    out.update(rate_per_s=round(rate, 4), **res["summary"])
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    sys.exit(main())

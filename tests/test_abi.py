@@ -113,4 +113,6 @@ def test_batch_host_side_errors(lib):
 def test_advance_and_last_error_arguments(lib):
     assert lib.mpm_advance(None, 1, 1, None) == binding.MPM_EINVAL
     buf = ctypes.create_string_buffer(8)
-    assert lib.mpm_last_error(None, buf, 8) == binding.MPM_EINVAL
+    assert lib.mpm_last_error(None, None, 8) == binding.MPM_EINVAL
+    assert lib.mpm_last_error(None, buf, 0) == binding.MPM_EINVAL
+    assert lib.mpm_last_error(None, buf, 8) == binding.MPM_OK      # no run: the last create failure

@@ -152,3 +152,32 @@ def test_advance_stops_at_breakthrough(binding):
     _same(_state(r), _state(r2))
     r.close()
     r2.close()
+
+
+def test_served_equals_alone(binding):
+    """Requests admitted over time into the batch (fewer slots than requests, so some wait)
+    finish with bitwise the results of the same runs advanced alone to breakthrough."""
+    from paper_2103_11050_amd import serve
+    reqs = inputs.serve_requests(5, grids=(32, 64))
+    for c in reqs:
+        c.update(sub_x=8, sub_y=8, ne_x=2, ne_y=2)
+    arrivals = [0.0, 0.0, 0.01, 0.02, 0.02]
+    print("[gpu] serve", len(reqs), "requests", flush=True)
+    srv = serve.Server(capacity=3, budget_bytes=1 << 34, max_updates=4000, keep_results=True)
+    res = srv.serve(reqs, arrivals)
+    srv.close()
+    assert res["summary"]["requests"] == 5 and res["summary"]["all_broke_through"]
+    for rec, cfg in zip(res["records"], reqs):
+        dev = torch.device("cuda:0")
+        Kt = torch.from_numpy(inputs.permeability(cfg)).to(dev)
+        st = torch.from_numpy(inputs.initial_saturation(cfg)).to(dev)
+        r = binding.Run(cfg, Kt, st)
+        r.start()
+        n = r.advance(4000, True)
+        assert n == rec["passes"]
+        ux, uy = r.velocity()
+        s = r.saturation()
+        assert np.array_equal(to_np(ux), rec["state"][0]) and np.array_equal(to_np(uy), rec["state"][1])
+        assert np.array_equal(to_np(s), rec["state"][2])
+        assert r.stats()["te"] == rec["te"]
+        r.close()
