@@ -456,21 +456,20 @@ mpm_status transport(mpm_run* r, int32_t nsteps) {
   return st;
 }
 
-// One pass of Algorithm 1's while loop. With graphs, the C_n transport sub-steps and kappa^n
-// are one graph (per parity of the saturation buffers) and the MPM-2P update another.
-mpm_status step(mpm_run* r, int32_t force) {
-  if (!(r->use_graphs && !r->prof)) {
-    mpm_status st = transport(r, r->P.d.cn);
-    if (st) return st;
-    return velocity_update(r, force);
-  }
-  const int par = r->s == r->s_base ? 0 : 1;
+// C_n transport sub-steps and kappa^n with its epsilon sums (event ev_eps recorded after them).
+// With graphs they are one graph per parity of the saturation buffers.
+mpm_status transport_and_kappa(mpm_run* r) {
   const int cn = r->P.d.cn;
-  if (r->g_trans[par]) {
-    HIPCHK(r, hipGraphLaunch(r->g_trans[par], r->st));
-    r->eps_seq += 1;
-    for (int k = 0; k < cn; ++k) std::swap(r->s, r->s2);
-  } else {
+  if (r->use_graphs && !r->prof) {
+    const int par = r->s == r->s_base ? 0 : 1;
+    if (r->g_trans[par]) {
+      HIPCHK(r, hipGraphLaunch(r->g_trans[par], r->st));
+      r->eps_seq += 1;
+      for (int k = 0; k < cn; ++k) std::swap(r->s, r->s2);
+      r->ntr += cn;
+      HIPCHK(r, hipEventRecord(r->ev_eps, r->st));
+      return MPM_OK;
+    }
     double* s0 = r->s;
     double* s1 = r->s2;
     r->g_trans[par] = capture_and_launch(r, [&] {
@@ -478,17 +477,25 @@ mpm_status step(mpm_run* r, int32_t force) {
       if (st) return st;
       return kappa_and_eps_nodes(r);
     });
-    if (!r->g_trans[par]) {
-      r->s = s0;
-      r->s2 = s1;
-      r->use_graphs = false;
-      mpm_status st = transport(r, cn);
-      if (st) return st;
-      return velocity_update(r, force);
+    if (r->g_trans[par]) {
+      r->ntr += cn;
+      HIPCHK(r, hipEventRecord(r->ev_eps, r->st));
+      return MPM_OK;
     }
+    // capture unavailable: stay eager
+    r->s = s0;
+    r->s2 = s1;
+    r->use_graphs = false;
   }
-  r->ntr += cn;
-  HIPCHK(r, hipEventRecord(r->ev_eps, r->st));
+  mpm_status st = transport(r, cn);
+  if (st) return st;
+  return kappa_and_eps(r);
+}
+
+// One pass of Algorithm 1's while loop.
+mpm_status step(mpm_run* r, int32_t force) {
+  mpm_status st = transport_and_kappa(r);
+  if (st) return st;
   return velocity_update(r, force, true);
 }
 
@@ -801,8 +808,7 @@ mpm_status mpm_batch_step(mpm_batch* b, const uint8_t* active, uint8_t* breakthr
   };
   for (mpm_run* r : run) {
     mpm_status st = enter(r);
-    if (!st) st = transport(r, r->P.d.cn);
-    if (!st) st = kappa_and_eps(r);
+    if (!st) st = transport_and_kappa(r);
     if (!st && r->P.d.switch_rule == MPM_SWITCH_ALG1) st = vu_update(r, MPM_AUTO, r->eps_prev);
     note(r, st);
   }
