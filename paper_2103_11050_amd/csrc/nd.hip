@@ -380,6 +380,9 @@ static RbShape rb_shape(int len) {
     if ((sh).G == 16) hipLaunchKernelGGL((KER<16, 1, 8, false>), grid_, dim3(256), 0, st, __VA_ARGS__);        \
     else if ((sh).G == 32) hipLaunchKernelGGL((KER<32, 1, 8, false>), grid_, dim3(256), 0, st, __VA_ARGS__);   \
     else if ((sh).U == 1) hipLaunchKernelGGL((KER<64, 1, 8, false>), grid_, dim3(256), 0, st, __VA_ARGS__);    \
+    else if ((sh).U == 2 && (sh).RP == 8) hipLaunchKernelGGL((KER<64, 2, 8, false>), grid_, dim3(256), 0, st, __VA_ARGS__); \
+    else if ((sh).U == 4 && (sh).RP == 4) hipLaunchKernelGGL((KER<64, 4, 4, false>), grid_, dim3(256), 0, st, __VA_ARGS__); \
+    else if ((sh).U == 8 && (sh).RP == 2) hipLaunchKernelGGL((KER<64, 8, 2, false>), grid_, dim3(256), 0, st, __VA_ARGS__); \
     else if ((sh).U == 2) hipLaunchKernelGGL((KER<64, 2, 4, false>), grid_, dim3(256), 0, st, __VA_ARGS__);    \
     else if ((sh).U == 4) hipLaunchKernelGGL((KER<64, 4, 2, false>), grid_, dim3(256), 0, st, __VA_ARGS__);    \
     else if ((sh).U == 8) hipLaunchKernelGGL((KER<64, 8, 1, false>), grid_, dim3(256), 0, st, __VA_ARGS__);    \
@@ -402,8 +405,16 @@ __global__ void __launch_bounds__(256) k_nd_bwd_root(NdArgs a, int loff) {
   k_nd_bwd_body<G, U, RP, CH, true>(a, loff);
 }
 
+// The backward sweep takes twice the rows per lane group for rows of 65..512 entries (fewer,
+// longer-lived workgroups per level; measured slightly faster).
+static RbShape rb_shape_bwd(int len) {
+  RbShape sh = rb_shape(len);
+  if (sh.G == 64 && sh.U >= 2 && sh.U <= 8) sh.RP *= 2;
+  return sh;
+}
+
 void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nmax, int root) {
-  const RbShape sh = rb_shape(nmax);
+  const RbShape sh = rb_shape_bwd(nmax);
   if (root) ND_RB_LAUNCH(k_nd_bwd_root, sh, nImax, nnodes, st, a, loff);
   else ND_RB_LAUNCH(k_nd_bwd_inner, sh, nImax, nnodes, st, a, loff);
 }
