@@ -69,10 +69,48 @@ def gaussian_field(nx: int, ny: int, lx: float, ly: float, corr_len: float, seed
     return np.ascontiguousarray(f.real[:ny, :nx])
 
 
+def self_similar_field(nx: int, ny: int, lx: float, ly: float, seed: int, beta: float = 0.5) -> np.ndarray:
+    """Zero-mean Gaussian field with the self-similar covariance |x - y|^-beta (Section 5.1
+    uses beta = 1/2), shape (ny, nx): spectral synthesis with power spectrum |k|^(beta - 2)
+    (the 2-D Fourier transform of the covariance) on a periodic grid padded to twice the
+    domain, the constant mode removed, driven by numpy's PCG64 with `seed`. The covariance is
+    singular at zero distance, so the sample has no intrinsic scale: it is returned with unit
+    range (max - min = 1) over the domain; callers scale it."""
+    px, py = 2 * nx, 2 * ny
+    kx = np.fft.fftfreq(px, d=lx / nx)
+    ky = np.fft.fftfreq(py, d=ly / ny)
+    k = np.sqrt(ky[:, None] ** 2 + kx[None, :] ** 2)
+    amp = np.zeros_like(k)
+    amp[k > 0] = k[k > 0] ** ((beta - 2.0) / 2.0)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    z = rng.standard_normal((py, px)) + 1j * rng.standard_normal((py, px))
+    f = np.fft.ifft2(amp * z).real[:ny, :nx]
+    f = f - f.mean()
+    return np.ascontiguousarray(f / (f.max() - f.min()))
+
+
 def permeability(cfg: dict) -> np.ndarray:
-    """Log-normal permeability K = exp(sqrt(sigma2) * xi), shape (ny, nx)."""
+    """Permeability of a workload, shape (ny, nx): log-normal K = exp(sqrt(sigma2) xi) with
+    Gaussian covariance, or (field = "self_similar") K = k0 exp(delta xi) with xi the
+    self-similar field scaled to the range ln(contrast) / delta."""
+    if cfg.get("field") == "self_similar":
+        xi = self_similar_field(cfg["nx"], cfg["ny"], cfg["lx"], cfg["ly"], cfg["seed"])
+        return cfg["k0"] * np.exp(np.log(cfg["contrast"]) * xi)
     xi = gaussian_field(cfg["nx"], cfg["ny"], cfg["lx"], cfg["ly"], cfg["corr_len"], cfg["seed"])
     return np.exp(np.sqrt(cfg["sigma2"]) * xi)
+
+
+def x1_config(contrast: float = 1e3, ne: int = 1, cn: int = 1, eta: float = 1e-2, seed: int = 11) -> dict:
+    """The Gaussian-field experiment of Section 5.1: [0,1]^2 with 64^2 cells, 4x4 subdomains of
+    16^2, p = 1 on the left and p = 0 on the right, no flow on the bottom and top, no sources,
+    M = 40, alpha = 1, eta = 1e-2; K = 0.8 exp(delta xi) with the self-similar field xi and
+    Kmax/Kmin = contrast (1e3 for delta = 2.5, 1e6 for delta = 4.5); ne interface elements per
+    side (H-bar = H / ne); C_n transport sub-steps per elliptic step."""
+    cfg = dict(_BASE, nx=64, ny=64, sub_x=16, sub_y=16, ne_x=ne, ne_y=ne, mu_o=40.0, eta=eta, cn=cn,
+               field="self_similar", k0=0.8, contrast=contrast, seed=seed, steps=0)
+    cfg["bc_kind"] = [PRESSURE, PRESSURE, NOFLOW, NOFLOW]
+    cfg["bc_value"] = [1.0, 0.0, 0.0, 0.0]
+    return cfg
 
 
 def initial_saturation(cfg: dict) -> np.ndarray:

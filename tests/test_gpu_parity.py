@@ -216,3 +216,12 @@ def test_precision_form_c2_window(binding):
     K = inputs.permeability(cfg)
     _compare_runs(binding, cfg, K, 3, "c2-mixed", forced=[None, "mpm", "mrcm", "mpm"], vel_tol=MIXED_VEL_TOL,
                   sat_tol=MIXED_SAT_TOL, precision=binding.PREC_FP32_REFINE)
+
+
+@pytest.mark.parametrize("ne,contrast,cn,steps", [(1, 1e3, 1, 8), (2, 1e6, 1, 8), (2, 1e3, 20, 3)])
+def test_x1_gaussian_experiment_config(binding, ne, contrast, cn, steps):
+    """The Section 5.1 experiment's set-up (self-similar field, p = 1 / 0 on the left / right,
+    M = 40, eta = 1e-2) with H-bar = H and H / 2 and C_n = 1 and 20."""
+    cfg = inputs.x1_config(contrast, ne=ne, cn=cn)
+    K = inputs.permeability(cfg)
+    _compare_runs(binding, cfg, K, steps, f"x1-ne{ne}-c{contrast:g}-cn{cn}")
