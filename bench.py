@@ -113,9 +113,14 @@ def measured_traffic(kernel: str):
 
 
 def _per_kernel(path):
+    """Counter values per kernel (FP64 instances only: the FP32-block instances of the
+    precision form are left out)."""
     d = collections.defaultdict(list)
     for r in csv.DictReader(open(path)):
-        name = r["Kernel_Name"].split("(")[0].split("<")[0].replace("void ", "").replace("mpm::", "")
+        full = r["Kernel_Name"].split("(")[0]
+        if "float" in full:
+            continue
+        name = full.split("<")[0].replace("void ", "").replace("mpm::", "")
         d[name].append(float(r["Counter_Value"]))
     return d
 
