@@ -302,23 +302,17 @@ __global__ void __launch_bounds__(64) k_line_factor(Geo g, const double* __restr
 // ---------------------------------------------------------------------------------------------
 // Tiles of one subdomain with a one-cell halo (corners excluded), loaded with every global
 // read issued before the first use: conductivities kappa^n and kappa^m at
-// T[(j + 1) * (mx + 2) + i + 1], the previous velocity on the subdomain's faces and q.
-struct HaloTiles {
-  double* kn;
-  double* km;
-  double* ux;   // [my][mx + 1]
-  double* uy;   // [my + 1][mx]
-  double* q;    // local order
-};
-
+// T[(j + 1) * (mx + 2) + i + 1] and the previous velocity on the subdomain's faces go to LDS
+// (ux [my][mx + 1], uy [my + 1][mx]); q stays in registers, qc[s] for local cell
+// threadIdx.x + 64 s.
 __device__ __forceinline__ void load_halo_tiles(const Geo& g, int I, int J, const double* __restrict__ kap_n,
                                                 const double* __restrict__ kap_m, const double* __restrict__ uxm,
                                                 const double* __restrict__ uym, const double* __restrict__ q,
-                                                const HaloTiles& T) {
-  constexpr int NH = (18 * 18 + 63) / 64, NF = (16 * 17 + 63) / 64, NC = 256 / 64;
+                                                double* kn, double* km, double* ux, double* uy, double (&qc)[4]) {
+  constexpr int NH = (18 * 18 + 63) / 64, NF = (16 * 17 + 63) / 64;
   const int TW = g.mx + 2, nh = TW * (g.my + 2);
   const int nfx = g.my * (g.mx + 1), nfy = (g.my + 1) * g.mx;
-  double a[NH], b[NH], fx[NF], fy[NF], qc[NC];
+  double a[NH], b[NH], fx[NF], fy[NF];
 #pragma unroll
   for (int s = 0; s < NH; ++s) {
     const int e = threadIdx.x + 64 * s;
@@ -338,7 +332,7 @@ __device__ __forceinline__ void load_halo_tiles(const Geo& g, int I, int J, cons
     fy[s] = uym[(J * g.my + ey / g.mx) * g.nx + I * g.mx + ey % g.mx];
   }
 #pragma unroll
-  for (int s = 0; s < NC; ++s) {
+  for (int s = 0; s < 4; ++s) {
     const int c = threadIdx.x + 64 * s;
     int i, j;
     loc_ij(g, c < g.nc ? c : 0, &i, &j);
@@ -348,22 +342,84 @@ __device__ __forceinline__ void load_halo_tiles(const Geo& g, int I, int J, cons
   for (int s = 0; s < NH; ++s) {
     const int e = threadIdx.x + 64 * s;
     if (e < nh) {
-      T.kn[e] = a[s];
-      T.km[e] = b[s];
+      kn[e] = a[s];
+      km[e] = b[s];
     }
   }
 #pragma unroll
   for (int s = 0; s < NF; ++s) {
     const int e = threadIdx.x + 64 * s;
-    if (e < nfx) T.ux[e] = fx[s];
-    if (e < nfy) T.uy[e] = fy[s];
-  }
-#pragma unroll
-  for (int s = 0; s < NC; ++s) {
-    const int c = threadIdx.x + 64 * s;
-    if (c < g.nc) T.q[c] = qc[s];
+    if (e < nfx) ux[e] = fx[s];
+    if (e < nfy) uy[e] = fy[s];
   }
   __syncthreads();
+}
+
+// Right-hand side of the trivial-Robin problem at local cell (i, j): |c| q minus the outflow
+// of v = (t^n / t^m) u~^m through the cell's faces, z on Neumann faces (halo tiles as above).
+__device__ __forceinline__ double mpm_rhs_cell(const Geo& g, int I, int J, int i, int j, double qv,
+                                               const double* knt, const double* kmt, const double* uxs,
+                                               const double* uys) {
+  const int TW = g.mx + 2;
+  const int gi = I * g.mx + i, gj = J * g.my + j;
+  const int e = (j + 1) * TW + i + 1;
+  const double kn = knt[e], km = kmt[e];
+  double r = g.hx * g.hy * qv;
+  {
+    const double u = uxs[j * (g.mx + 1) + i];
+    if (gi > 0) {
+      r -= g.hy * (-harm_ratio(kn, knt[e - 1], km, kmt[e - 1]) * u);
+    } else {
+      BFace f = bface(g, I, J, j);
+      r -= f.kind == FACE_NEU ? f.flen * f.value : g.hy * (-(kn / km) * u);
+    }
+  }
+  {
+    const double u = uxs[j * (g.mx + 1) + i + 1];
+    if (gi < g.nx - 1) {
+      r -= g.hy * (harm_ratio(kn, knt[e + 1], km, kmt[e + 1]) * u);
+    } else {
+      BFace f = bface(g, I, J, g.my + j);
+      r -= f.kind == FACE_NEU ? f.flen * f.value : g.hy * ((kn / km) * u);
+    }
+  }
+  {
+    const double u = uys[j * g.mx + i];
+    if (gj > 0) {
+      r -= g.hx * (-harm_ratio(kn, knt[e - TW], km, kmt[e - TW]) * u);
+    } else {
+      BFace f = bface(g, I, J, 2 * g.my + i);
+      r -= f.kind == FACE_NEU ? f.flen * f.value : g.hx * (-(kn / km) * u);
+    }
+  }
+  {
+    const double u = uys[(j + 1) * g.mx + i];
+    if (gj < g.ny - 1) {
+      r -= g.hx * (harm_ratio(kn, knt[e + TW], km, kmt[e + TW]) * u);
+    } else {
+      BFace f = bface(g, I, J, 2 * g.my + g.mx + i);
+      r -= f.kind == FACE_NEU ? f.flen * f.value : g.hx * ((kn / km) * u);
+    }
+  }
+  return r;
+}
+
+// Outward v = (t^n / t^m) u~^m on boundary face bf of the subdomain (0 on Neumann faces).
+__device__ __forceinline__ double mpm_vbnd_face(const Geo& g, int I, int J, const BFace& bf, const double* knt,
+                                                const double* kmt, const double* uxs, const double* uys) {
+  if (bf.kind == FACE_NEU) return 0.0;
+  const int TW = g.mx + 2;
+  const int gi = I * g.mx + bf.i, gj = J * g.my + bf.j;
+  const int e = (bf.j + 1) * TW + bf.i + 1;
+  const double km = kmt[e], kn = knt[e];
+  double u;
+  int nbr;
+  if (bf.side == 0) { u = -uxs[bf.j * (g.mx + 1) + bf.i]; nbr = gi > 0 ? e - 1 : -1; }
+  else if (bf.side == 1) { u = uxs[bf.j * (g.mx + 1) + bf.i + 1]; nbr = gi < g.nx - 1 ? e + 1 : -1; }
+  else if (bf.side == 2) { u = -uys[bf.j * g.mx + bf.i]; nbr = gj > 0 ? e - TW : -1; }
+  else { u = uys[(bf.j + 1) * g.mx + bf.i]; nbr = gj < g.ny - 1 ? e + TW : -1; }
+  const double ratio = nbr >= 0 ? harm_ratio(kn, knt[nbr], km, kmt[nbr]) : kn / km;
+  return ratio * u;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -372,16 +428,18 @@ __device__ __forceinline__ void load_halo_tiles(const Geo& g, int I, int J, cons
 // v_f = (t^n_f / t^m_f) u~^m_f; zero Dirichlet and Robin data. Outputs the boundary fluxes
 // h = W T delta p on Robin/Dirichlet faces, the boundary values of v and the interface
 // right-hand side B^T h. The kept inverse blocks and all tiles are requested at entry.
+// LDS is reused as the steps retire (kappa^n halo -> line couplings, x-faces -> solution,
+// y-faces -> h), about 9.5 KB per subdomain: registers, not LDS, bound the subdomains per CU.
 // With T = float the kept blocks are FP32 (all lines in registers, up to 16) and the solve is
-// refined in FP64.
+// refined in FP64 against the full line form of the matrix.
 template <int MF, int NL, typename T>
 __global__ void __launch_bounds__(64)
 k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict__ kap_m,
                const double* __restrict__ uxm, const double* __restrict__ uym, const double* __restrict__ q,
                const T* __restrict__ fac, double* __restrict__ hg, double* __restrict__ vbnd, LeafOut lo) {
   constexpr bool F32 = sizeof(T) == 4;
-  __shared__ double knt[18 * 18], kmt[18 * 18], uxs[16 * 17], uys[17 * 16], qs[256];
-  __shared__ double kl[256], x[256], hsh[64], wsh[F32 ? 768 : 256], tE[256], tN[256], dg[256];
+  __shared__ double knt[18 * 18], kmt[18 * 18], uxs[16 * 17], uys[17 * 16];
+  __shared__ double xtra[F32 ? 3 * 256 + 768 : 1];   // precision form: tE, tN, dg, refinement scratch
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int n = g.nc, nb = g.nb;
@@ -390,97 +448,67 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
   constexpr int NLR = NL > 0 ? NL : 1;
   double E[F32 ? 1 : NLR][LB<MF>::EPL];
   float Ef[F32 ? 16 : 1][LB<MF>::EPL];
-  if constexpr (F32) lb_load_f32<MF>(L, fac + efac_off<MF>(g, sub, 0, 0), g.nc / g.band, Ef);
-  else if constexpr (NL > 0) lb_load_reg<MF, NL>(L, fac + efac_off<MF>(g, sub, 0, 0), E);
-  load_halo_tiles(g, I, J, kap_n, kap_m, uxm, uym, q, HaloTiles{knt, kmt, uxs, uys, qs});
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    int i, j;
-    loc_ij(g, c, &i, &j);
-    const int gi = I * g.mx + i, gj = J * g.my + j;
-    const int e = (j + 1) * TW + i + 1;
-    const double kn = knt[e], km = kmt[e];
-    kl[c] = km;
-    double r = g.hx * g.hy * qs[c];
-    {
-      const double u = uxs[j * (g.mx + 1) + i];
-      if (gi > 0) {
-        const double ratio = harm_ratio(kn, knt[e - 1], km, kmt[e - 1]);
-        r -= g.hy * (-ratio * u);
-      } else {
-        BFace f = bface(g, I, J, j);
-        r -= f.kind == FACE_NEU ? f.flen * f.value : g.hy * (-(kn / km) * u);
-      }
+  const T* Es = fac + efac_off<MF>(g, sub, 0, 0);
+  if constexpr (F32) lb_load_f32<MF>(L, Es, g.nc / g.band, Ef);
+  else if constexpr (NL > 0) lb_load_reg<MF, NL>(L, Es, E);
+  double qc[4];
+  load_halo_tiles(g, I, J, kap_n, kap_m, uxm, uym, q, knt, kmt, uxs, uys, qc);
+  double rhs[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int c = threadIdx.x + 64 * s;
+    rhs[s] = 0.0;
+    if (c < n) {
+      int i, j;
+      loc_ij(g, c, &i, &j);
+      rhs[s] = mpm_rhs_cell(g, I, J, i, j, qc[s], knt, kmt, uxs, uys);
     }
-    {
-      const double u = uxs[j * (g.mx + 1) + i + 1];
-      if (gi < g.nx - 1) {
-        const double ratio = harm_ratio(kn, knt[e + 1], km, kmt[e + 1]);
-        r -= g.hy * (ratio * u);
-      } else {
-        BFace f = bface(g, I, J, g.my + j);
-        r -= f.kind == FACE_NEU ? f.flen * f.value : g.hy * ((kn / km) * u);
-      }
-    }
-    {
-      const double u = uys[j * g.mx + i];
-      if (gj > 0) {
-        const double ratio = harm_ratio(kn, knt[e - TW], km, kmt[e - TW]);
-        r -= g.hx * (-ratio * u);
-      } else {
-        BFace f = bface(g, I, J, 2 * g.my + i);
-        r -= f.kind == FACE_NEU ? f.flen * f.value : g.hx * (-(kn / km) * u);
-      }
-    }
-    {
-      const double u = uys[(j + 1) * g.mx + i];
-      if (gj < g.ny - 1) {
-        const double ratio = harm_ratio(kn, knt[e + TW], km, kmt[e + TW]);
-        r -= g.hx * (ratio * u);
-      } else {
-        BFace f = bface(g, I, J, 2 * g.my + g.mx + i);
-        r -= f.kind == FACE_NEU ? f.flen * f.value : g.hx * ((kn / km) * u);
-      }
-    }
-    x[c] = r;
   }
-  __syncthreads();
-  fill_trans(g, I, J, kl, 0, tE, tN, dg);
-  const LineW W{tE, tN, dg, g.xfast, g.band, 0};
-  if constexpr (F32) lb_solve_refined<MF>(g, W, L, Ef, x, wsh);
-  else if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
-  else lb_solve<MF>(g, W, L, fac + efac_off<MF>(g, sub, 0, 0), x, wsh);
-  for (int f = threadIdx.x; f < nb; f += blockDim.x) {
+  for (int f = threadIdx.x; f < nb; f += 64)
+    vbnd[size_t(sub) * nb + f] = mpm_vbnd_face(g, I, J, bface(g, I, J, f), knt, kmt, uxs, uys);
+  __syncthreads();   // the kappa^n halo and the face tiles are dead from here on
+  double* x = uxs;
+  double* ty = knt;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int c = threadIdx.x + 64 * s;
+    if (c < n) x[c] = rhs[s];
+  }
+  auto kmf = [&](int i, int j) { return kmt[(j + 1) * TW + i + 1]; };
+  double* tE = xtra;
+  double* tN = xtra + 256;
+  double* dg = xtra + 512;
+  if constexpr (F32) fill_trans_k(g, I, J, kmf, 0, tE, tN, dg);
+  else {
+    fill_ycoup_k(g, kmf, ty);
+    __syncthreads();
+  }
+  if constexpr (F32) {
+    const LineW W{tE, tN, dg, g.xfast, g.band, 0};
+    lb_solve_refined<MF>(g, W, L, Ef, x, xtra + 768);
+  } else {
+    const LineW W{ty, ty, nullptr, g.xfast, g.band, 0};
+    if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
+    else lb_solve<MF>(g, W, L, Es, x, uys);
+  }
+  double* hsh = uys;
+  for (int f = threadIdx.x; f < nb; f += 64) {
     BFace bf = bface(g, I, J, f);
-    const int gi = I * g.mx + bf.i, gj = J * g.my + bf.j;
-    const int e = (bf.j + 1) * TW + bf.i + 1;
-    const double km = kmt[e], kn = knt[e];
-    const double w = bf.flen * bface_trans(g, bf, km);
-    const double h = bf.kind == FACE_NEU ? 0.0 : w * x[loc_index(g, bf.i, bf.j)];
+    const double km = kmt[(bf.j + 1) * TW + bf.i + 1];
+    const double h = bf.kind == FACE_NEU ? 0.0 : bf.flen * bface_trans(g, bf, km) * x[loc_index(g, bf.i, bf.j)];
     hsh[f] = h;
     hg[size_t(sub) * nb + f] = h;
-    double v = 0.0;
-    if (bf.kind != FACE_NEU) {
-      double u;
-      int nbr;
-      if (bf.side == 0) { u = -uxs[bf.j * (g.mx + 1) + bf.i]; nbr = gi > 0 ? e - 1 : -1; }
-      else if (bf.side == 1) { u = uxs[bf.j * (g.mx + 1) + bf.i + 1]; nbr = gi < g.nx - 1 ? e + 1 : -1; }
-      else if (bf.side == 2) { u = -uys[bf.j * g.mx + bf.i]; nbr = gj > 0 ? e - TW : -1; }
-      else { u = uys[(bf.j + 1) * g.mx + bf.i]; nbr = gj < g.ny - 1 ? e + TW : -1; }
-      const double ratio = nbr >= 0 ? harm_ratio(kn, knt[nbr], km, kmt[nbr]) : kn / km;
-      v = ratio * u;
-    }
-    vbnd[size_t(sub) * nb + f] = v;
   }
   __syncthreads();
   // interface right-hand side B^T h: U unknown -sgn beta_f, P unknown 1 on the element's faces
   const int nd = sub_ndof(g, I, J);
-  for (int a = threadIdx.x; a < nd; a += blockDim.x) {
+  for (int a = threadIdx.x; a < nd; a += 64) {
     int f0, cnt;
     dof_faces(g, I, J, a, &f0, &cnt);
     double v = 0.0;
     for (int xx = f0; xx < f0 + cnt; ++xx) {
       BFace ff = bface(g, I, J, xx);
-      const double wgt = (a & 1) ? 1.0 : -ff.sgn * robin_beta(g, ff, kl[loc_index(g, ff.i, ff.j)]);
+      const double wgt = (a & 1) ? 1.0 : -ff.sgn * robin_beta(g, ff, kmt[(ff.j + 1) * TW + ff.i + 1]);
       v += wgt * hsh[xx];
     }
     leaf_out(lo, sub, a, v);
@@ -501,7 +529,10 @@ k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict
                double* __restrict__ red_rate, double* __restrict__ red_qin, T* __restrict__ Escr,
                T* __restrict__ Ekeep, const int32_t* __restrict__ flag, int store, int32_t* err) {
   constexpr bool F32 = sizeof(T) == 4;
-  __shared__ double kl[256], x[256], w[64], scratch[128], wsh[F32 ? 768 : 256], tE[256], tN[256], dg[256];
+  // the conductivity tile is dead once the weights are built and then holds the solution
+  __shared__ double kl[256], w[64], tE[256], tN[256], dg[256];
+  __shared__ double wsh[F32 ? 768 : (NL > 0 ? 1 : 256)];
+  double* x = kl;
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int n = g.nc, nb = g.nb;
@@ -529,11 +560,23 @@ k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict
     }
     w[f] = u;
   }
+  double qc[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int c = threadIdx.x + 64 * s;
+    int i, j;
+    loc_ij(g, c < n ? c : 0, &i, &j);
+    qc[s] = q[gcell2(g, I, J, i, j)];
+  }
   __syncthreads();
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+  fill_trans(g, I, J, kl, 1, tE, tN, dg);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int c = threadIdx.x + 64 * s;
+    if (c >= n) continue;
     int i, j;
     loc_ij(g, c, &i, &j);
-    double r = g.hx * g.hy * q[gcell2(g, I, J, i, j)];
+    double r = g.hx * g.hy * qc[s];
     if (i == 0) r -= g.hy * w[j];
     if (i == g.mx - 1) r -= g.hy * w[g.my + j];
     if (j == 0) r -= g.hx * w[2 * g.my + i];
@@ -541,7 +584,6 @@ k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict
     x[c] = c == 0 ? 0.0 : r;
   }
   __syncthreads();
-  fill_trans(g, I, J, kl, 1, tE, tN, dg);
   const LineW W{tE, tN, dg, g.xfast, g.band, 1};
   if constexpr (F32) {
     lb_solve_refined<MF>(g, W, L, Ef, x, wsh);
@@ -583,14 +625,15 @@ k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict
     BFace bf = bface(g, I, J, f);
     if (bf.kind != FACE_ROB) qin += bf.flen * fmax(-w[f], 0.0);
   }
-  scratch[threadIdx.x] = rate;
-  scratch[64 + threadIdx.x] = qin;
-  __syncthreads();
+  // one wavefront: butterfly reductions
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    rate = fmax(rate, __shfl_xor(rate, o));
+    qin += __shfl_xor(qin, o);
+  }
   if (threadIdx.x == 0) {
-    double m = 0.0, s = 0.0;
-    for (int t = 0; t < 64; ++t) { m = fmax(m, scratch[t]); s += scratch[64 + t]; }
-    red_rate[sub] = m;
-    red_qin[sub] = s;
+    red_rate[sub] = rate;
+    red_qin[sub] = qin;
   }
 }
 

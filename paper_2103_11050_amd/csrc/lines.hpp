@@ -138,24 +138,26 @@ __device__ __forceinline__ void line_cell(const Geo& g, int ln, int pos, int* i,
 
 // Face weights of a subdomain's matrix, computed once per cell into LDS (local order):
 // tE[c] = |f| t of the face to the +x neighbour inside the subdomain (0 on its E edge),
-// tN[c] likewise to the +y neighbour, dg[c] = diagonal entry.
+// tN[c] likewise to the +y neighbour, dg[c] = diagonal entry. kf(i, j) gives the cell's
+// conductivity.
 // mode 0: boundary faces with their Dirichlet/Robin transmissibility (eq:mrc1);
 // mode 1: all boundary faces are flux faces and cell 0 is pinned (p = 0): its couplings are
 // dropped from the matrix and its diagonal is 1.
-__device__ __forceinline__ void fill_trans(const Geo& g, int I, int J, const double* kl, int mode, double* tE,
-                                           double* tN, double* dg) {
+template <class KF>
+__device__ __forceinline__ void fill_trans_k(const Geo& g, int I, int J, KF kf, int mode, double* tE, double* tN,
+                                             double* dg) {
   for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
     int i, j;
     loc_ij(g, c, &i, &j);
-    const double kc = kl[c];
-    tE[c] = i < g.mx - 1 ? g.hy * harm_trans(kc, kl[loc_index(g, i + 1, j)], g.hx) : 0.0;
-    tN[c] = j < g.my - 1 ? g.hx * harm_trans(kc, kl[loc_index(g, i, j + 1)], g.hy) : 0.0;
+    const double kc = kf(i, j);
+    tE[c] = i < g.mx - 1 ? g.hy * harm_trans(kc, kf(i + 1, j), g.hx) : 0.0;
+    tN[c] = j < g.my - 1 ? g.hx * harm_trans(kc, kf(i, j + 1), g.hy) : 0.0;
   }
   __syncthreads();
   for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
     int i, j;
     loc_ij(g, c, &i, &j);
-    const double kc = kl[c];
+    const double kc = kf(i, j);
     double d = tE[c] + tN[c];
     if (i > 0) d += tE[loc_index(g, i - 1, j)];
     if (j > 0) d += tN[loc_index(g, i, j - 1)];
@@ -168,6 +170,27 @@ __device__ __forceinline__ void fill_trans(const Geo& g, int I, int J, const dou
     dg[c] = (mode == 1 && c == 0) ? 1.0 : d;
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ void fill_trans(const Geo& g, int I, int J, const double* kl, int mode, double* tE,
+                                           double* tN, double* dg) {
+  fill_trans_k(g, I, J, [&](int i, int j) { return kl[loc_index(g, i, j)]; }, mode, tE, tN, dg);
+}
+
+// Only the couplings between neighbouring lines (what a solve with kept inverse blocks needs):
+// ty[c] = |f| t of the face from cell c to its neighbour on the next line (0 on the last line).
+// No barrier.
+template <class KF>
+__device__ __forceinline__ void fill_ycoup_k(const Geo& g, KF kf, double* ty) {
+  for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
+    int i, j;
+    loc_ij(g, c, &i, &j);
+    const double kc = kf(i, j);
+    double t;
+    if (g.xfast) t = j < g.my - 1 ? g.hx * harm_trans(kc, kf(i, j + 1), g.hy) : 0.0;
+    else t = i < g.mx - 1 ? g.hy * harm_trans(kc, kf(i + 1, j), g.hx) : 0.0;
+    ty[c] = t;
+  }
 }
 
 // Couplings in line form. The matrix entries with the pinned cell are zero.
