@@ -150,12 +150,19 @@ mpm_status mpm_last_error(const mpm_run* run, char* buf, size_t len);
 /* Batch of runs stepped together: the batched and serving forms of the workloads (many
  * independent runs of Algorithm 1, Section 4.2, of any sizes). A batch holds `capacity` slots;
  * a slot takes a started run and can be emptied and refilled at any time (continuous batching).
- * The batch owns no device memory; the runs keep their workspaces and streams, and runs on
- * distinct streams overlap on the device. Host-side object; one host thread at a time. */
+ * Runs with equal descriptors form groups (at most 128 runs per launch): each phase of a step
+ * (transport, conductivity and epsilon, local solves, interface solve, reconstruction,
+ * downscaling) is one kernel launch for the whole group, on streams the batch owns; a run in
+ * a group whose switch takes the MRCM branch is updated on its own within the step. Other runs
+ * step alone on their own streams. The batch owns no device memory; the runs keep their
+ * workspaces. While a run is attached, its work is ordered by the batch: work on its stream is
+ * ordered before the batch's at attach time and after it at detach time (and around every
+ * call on the run itself). A run can be in one batch at a time; mpm_destroy detaches it.
+ * Host-side object; one host thread at a time. */
 typedef struct mpm_batch mpm_batch;
 mpm_status mpm_batch_create(int32_t capacity, mpm_batch** out);
-/* MPM_ESTATE if the slot is taken, the run is in another slot of this batch, not started or
- * poisoned; MPM_EINVAL on a bad slot or NULL. */
+/* MPM_ESTATE if the slot is taken, the run is already in a batch, not started or poisoned;
+ * MPM_EINVAL on a bad slot or NULL. */
 mpm_status mpm_batch_attach(mpm_batch* batch, int32_t slot, mpm_run* run);
 mpm_status mpm_batch_detach(mpm_batch* batch, int32_t slot);
 /* One pass of Algorithm 1's while loop (automatic switch) for every filled slot with
@@ -164,7 +171,7 @@ mpm_status mpm_batch_detach(mpm_batch* batch, int32_t slot);
  * whose water cut reached breakthrough_cut. Returns the first error met; a run that failed is
  * poisoned, the others are stepped. */
 mpm_status mpm_batch_step(mpm_batch* batch, const uint8_t* active, uint8_t* breakthrough);
-/* Frees the batch object only (the runs stay the caller's). */
+/* Detaches every run and frees the batch and its streams (the runs stay the caller's). */
 mpm_status mpm_batch_destroy(mpm_batch* batch);
 
 /* Copies the current velocity (device pointers ux [ny][nx+1], uy [ny+1][nx]). */

@@ -106,6 +106,11 @@ struct mpm_run {
   std::vector<hipEvent_t> pool;
   std::map<std::string, ProfEntry> prof_acc;
   std::string last_error;
+  // batch membership: while the run steps in a group of a batch, st is the group's stream and
+  // home the stream it had before
+  mpm_batch* owner = nullptr;
+  int32_t owner_slot = -1;
+  hipStream_t home = nullptr;
 
   hipEvent_t take_event() {
     if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
@@ -255,7 +260,7 @@ hipGraphExec_t capture_and_launch(mpm_run* r, F&& body) {
 
 LeafOut leaf_dest(const mpm_run* r) { return LeafOut{r->slots, r->leafup, r->nd.map_pool}; }
 
-void nd_solve(mpm_run* r) {
+void nd_solve(mpm_run* r, const RunTab& rt = one_run()) {
   const Plan& P = r->P;
   const int L = int(P.level_nodes.size()) - 1;
   {
@@ -263,7 +268,7 @@ void nd_solve(mpm_run* r) {
     for (int l = 1; l < L; ++l) {
       const int nn = int(P.level_nodes[l].size());
       if (!nn) continue;
-      launch_nd_level_fwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l], P.level_nBmax[l]);
+      launch_nd_level_fwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l], P.level_nBmax[l], rt);
     }
   }
   {
@@ -271,7 +276,7 @@ void nd_solve(mpm_run* r) {
     for (int l = L; l >= 1; --l) {
       const int nn = int(P.level_nodes[l].size());
       if (!nn) continue;
-      launch_nd_level_bwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l], P.level_nmax[l], l == L ? 1 : 0);
+      launch_nd_level_bwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l], P.level_nmax[l], l == L ? 1 : 0, rt);
     }
   }
 }
@@ -287,19 +292,19 @@ void nd_factor(mpm_run* r) {
   }
 }
 
-void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store) {
+void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store, const RunTab& rt = one_run()) {
   {
     Scope sc(r, "flux");
-    launch_flux(r->st, r->g, r->km, r->S, r->h, r->vbnd, r->y, r->subdofs_d, r->ubnd, with_v);
+    launch_flux(r->st, r->g, r->km, r->S, r->h, r->vbnd, r->y, r->subdofs_d, r->ubnd, with_v, rt);
   }
   {
     Scope sc(r, "downscale");
     if (r->f32 && !store)
       launch_downscale_f32(r->st, r->g, kap_s, r->q, r->ubnd, r->ux, r->uy, r->red, r->red + r->P.nsub, r->dsE32,
-                           r->nfac32, r->dsflag, r->err);
+                           r->nfac32, r->dsflag, r->err, rt);
     else
       launch_downscale(r->st, r->g, kap_s, r->q, r->ubnd, r->ux, r->uy, r->red, r->red + r->P.nsub, r->dsE,
-                       r->nfac, r->dsflag, store, r->err);
+                       r->nfac, r->dsflag, store, r->err, rt);
   }
   if (r->f32 && store) {
     Scope sc(r, "to_f32");
@@ -307,7 +312,7 @@ void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store) {
   }
   {
     Scope sc(r, "dt");
-    launch_dt(r->st, r->P.nsub, r->red, r->red + r->P.nsub, r->P.d.cfl, r->fmax_deriv, r->scal, r->dscount);
+    launch_dt(r->st, r->P.nsub, r->red, r->red + r->P.nsub, r->P.d.cfl, r->fmax_deriv, r->scal, r->dscount, rt);
   }
 }
 
@@ -339,7 +344,7 @@ mpm_status mrcm_update(mpm_run* r) {
 
 // MPM-2P: trivial-Robin solve with the stored kappa^m factors, interface solve with the stored
 // factorisation, reconstruction, downscaling with kappa^n.
-mpm_status mpm_update_body(mpm_run* r, bool capturing) {
+mpm_status mpm_update_body(mpm_run* r, bool capturing, const RunTab& rt = one_run()) {
   // kappa^n Neumann factors of the changed subdomains on the second stream, overlapped with
   // the local and interface solves. It forks at the epsilon event, recorded right after the
   // conductivity and its changed-subdomain list (one marker on the main stream, not two).
@@ -350,19 +355,20 @@ mpm_status mpm_update_body(mpm_run* r, bool capturing) {
   } else {
     HIPCHK(r, hipStreamWaitEvent(r->st2, r->ev_eps, 0));
   }
-  if (r->f32) launch_ds_factor_f32(r->st2, r->g, r->kn, r->dsE32, r->dslist, r->dscount, r->err);
-  else launch_ds_factor(r->st2, r->g, r->kn, r->dsE, r->dslist, r->dscount, r->err);
+  if (r->f32) launch_ds_factor_f32(r->st2, r->g, r->kn, r->dsE32, r->dslist, r->dscount, r->err, rt);
+  else launch_ds_factor(r->st2, r->g, r->kn, r->dsE, r->dslist, r->dscount, r->err, rt);
   HIPCHK(r, hipEventRecord(r->ev_join, r->st2));
   {
     Scope sc(r, "mpm_local");
     if (r->f32)
-      launch_mpm_local_f32(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac32, r->h, r->vbnd, leaf_dest(r));
+      launch_mpm_local_f32(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac32, r->h, r->vbnd, leaf_dest(r),
+                           rt);
     else
-      launch_mpm_local(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac, r->h, r->vbnd, leaf_dest(r));
+      launch_mpm_local(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac, r->h, r->vbnd, leaf_dest(r), rt);
   }
-  nd_solve(r);
+  nd_solve(r, rt);
   HIPCHK(r, hipStreamWaitEvent(r->st, r->ev_join, 0));
-  finish_velocity(r, r->kn, 1, 0);
+  finish_velocity(r, r->kn, 1, 0, rt);
   return MPM_OK;
 }
 
@@ -759,10 +765,189 @@ mpm_status mpm_last_error(const mpm_run* r, char* buf, size_t len) {
   return MPM_OK;
 }
 
+}  // extern "C"
+
 // ------------------------------------------------------------------ batch of runs
+// Runs whose descriptors are equal (and whose saturation buffers have the same parity) form a
+// group: each phase of a step is one launch for the whole group (grid z over the runs, a table
+// of workspace offsets as a kernel argument), on streams the batch owns. Other runs step alone
+// on their own streams. Every run's work is issued before any wait.
+struct GroupStreams {
+  hipStream_t st = nullptr, st2 = nullptr;
+  hipEvent_t ev_eps = nullptr, ev_move = nullptr;
+};
+
 struct mpm_batch {
   std::vector<mpm_run*> slot;
+  std::vector<GroupStreams> gs;
+  std::map<std::string, int> gs_of;   // group key -> index into gs
 };
+
+namespace {
+
+// Descriptor fields one by one (no padding bytes) and the saturation parity.
+std::string group_key(const mpm_run* r) {
+  const mpm_desc& d = r->P.d;
+  std::string k;
+  auto put = [&](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
+  put(&d.abi_version, 4); put(&d.nx, 4); put(&d.ny, 4); put(&d.lx, 8); put(&d.ly, 8);
+  put(&d.sub_x, 4); put(&d.sub_y, 4); put(&d.ne_x, 4); put(&d.ne_y, 4); put(&d.alpha, 8); put(&d.eta, 8);
+  put(&d.eps_norm, 4); put(&d.switch_rule, 4); put(&d.precision, 4); put(&d.cn, 4); put(&d.mu_w, 8);
+  put(&d.mu_o, 8); put(d.bc_kind, 16); put(d.bc_value, 32); put(&d.s_inj, 8); put(&d.cfl, 8);
+  put(&d.breakthrough_cut, 8);
+  k.push_back(r->s == r->s_base ? 0 : 1);
+  return k;
+}
+
+// Index into b->gs of the streams of a group (created on first use; the vector may grow, so
+// callers keep the index, not a pointer).
+mpm_status group_streams(mpm_batch* b, const std::string& key, int* out) {
+  auto it = b->gs_of.find(key);
+  if (it != b->gs_of.end()) { *out = it->second; return MPM_OK; }
+  constexpr size_t kMaxPairs = 16;   // further groups share stream pairs (serialised, still correct)
+  if (b->gs.size() >= kMaxPairs) {
+    const int i = int(b->gs_of.size() % kMaxPairs);
+    b->gs_of[key] = i;
+    *out = i;
+    return MPM_OK;
+  }
+  GroupStreams g;
+  const unsigned ev_flags = hipEventDisableTiming | hipEventReleaseToDevice;
+  if (hipStreamCreateWithFlags(&g.st, hipStreamNonBlocking) != hipSuccess) return MPM_EHIP;
+  if (hipStreamCreateWithFlags(&g.st2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&g.ev_eps, ev_flags) != hipSuccess ||
+      hipEventCreateWithFlags(&g.ev_move, hipEventDisableTiming) != hipSuccess) {
+    if (g.st2) hipStreamDestroy(g.st2);
+    if (g.ev_eps) hipEventDestroy(g.ev_eps);
+    hipStreamDestroy(g.st);
+    return MPM_EHIP;
+  }
+  b->gs.push_back(g);
+  b->gs_of[key] = int(b->gs.size()) - 1;
+  *out = int(b->gs.size()) - 1;
+  return MPM_OK;
+}
+
+// The run's work moves to stream st (ordered after everything issued for it so far, including
+// the caller's stream), or back home with st = nullptr.
+mpm_status move_run(mpm_run* r, hipStream_t st) {
+  hipStream_t to = st ? st : r->home;
+  if (!to || r->st == to) return MPM_OK;
+  if (!r->home) {
+    mpm_status e = enter(r);
+    if (e) return e;
+  }
+  HIPCHK(r, hipEventRecord(r->ev_out, r->st));
+  HIPCHK(r, hipStreamWaitEvent(to, r->ev_out, 0));
+  if (!r->home) r->home = r->st;
+  r->st = to;
+  if (to == r->home) r->home = nullptr;
+  return MPM_OK;
+}
+
+RunTab make_tab(const std::vector<mpm_run*>& g) {
+  RunTab t{};
+  t.n = int32_t(g.size());
+  for (size_t i = 0; i < g.size(); ++i) {
+    t.ws[i] = int64_t(g[i]->ws - g[0]->ws);
+    t.host[i] = int64_t(reinterpret_cast<char*>(g[i]->pinned_dev) - reinterpret_cast<char*>(g[0]->pinned_dev));
+  }
+  return t;
+}
+
+// Epsilon sums of the group's latest conductivity launch on the host (one event for the group,
+// then each run's sequence number).
+mpm_status group_wait_eps(const std::vector<mpm_run*>& g, GroupStreams& gs) {
+  if (hipEventSynchronize(gs.ev_eps) != hipSuccess) return MPM_EHIP;
+  for (mpm_run* r : g) {
+    volatile double* p = r->pinned;
+    if (p[2] != double(r->eps_seq)) {
+      HIPCHK(r, hipStreamSynchronize(r->st));
+      if (p[2] != double(r->eps_seq)) {
+        r->last_error = "epsilon sums did not reach host memory";
+        return MPM_EHIP;
+      }
+    }
+  }
+  return MPM_OK;
+}
+
+// One pass of Algorithm 1's while loop for a group of at least two runs on its streams, up to
+// the wait for the epsilon of the updated runs (group_finish).
+mpm_status group_issue(std::vector<mpm_run*>& g, GroupStreams& gs, std::vector<mpm_run*>* updated) {
+  for (mpm_run* r : g) {
+    mpm_status e = move_run(r, gs.st);
+    if (e) return e;
+  }
+  mpm_run* L = g[0];
+  const RunTab rt = make_tab(g);
+  const int cn = L->P.d.cn;
+  // transport sub-steps, water cut, conductivity and epsilon sums of every run
+  for (int k = 0; k < cn; ++k) {
+    launch_sat_step(gs.st, L->g, L->s, L->s2, L->ux, L->uy, L->scal, L->M, L->area, rt);
+    for (mpm_run* r : g) std::swap(r->s, r->s2);
+  }
+  launch_water_cut(gs.st, L->g, L->s, L->ux, L->uy, L->scal, L->M, rt);
+  launch_kappa(gs.st, L->g, L->s, L->K, L->kn, L->km, L->red, L->scal, L->dsflag, L->dslist, L->dscount,
+               L->dscount + 1, L->pinned_dev, rt);
+  for (mpm_run* r : g) {
+    r->eps_seq += 1;
+    r->ntr += cn;
+  }
+  HIPCHK(L, hipGetLastError());
+  HIPCHK(L, hipEventRecord(gs.ev_eps, gs.st));
+  // decisions (Algorithm 1: epsilon of the previous update; text rule: of this saturation)
+  const bool waited = L->P.d.switch_rule == MPM_SWITCH_TEXT;
+  if (waited) {
+    mpm_status e = group_wait_eps(g, gs);
+    if (e) return e;
+  }
+  std::vector<mpm_run*> mpm, mrcm;
+  for (mpm_run* r : g) {
+    const double decide = waited ? eps_from(r, r->pinned[0], r->pinned[1]) : r->eps_prev;
+    (decide > r->P.d.eta ? mrcm : mpm).push_back(r);
+  }
+  if (!mpm.empty()) {
+    mpm_run* M = mpm[0];
+    const RunTab rm = make_tab(mpm);
+    // the ds_factor fork of the first run's update waits for the group's conductivity
+    HIPCHK(M, hipEventRecord(M->ev_eps, gs.st));
+    mpm_status e = mpm_update_body(M, false, rm);
+    if (e) return e;
+    HIPCHK(M, hipGetLastError());
+    for (mpm_run* r : mpm) {
+      r->eps_pending = true;
+      r->last_branch = MPM_FORCE_MPM;
+      r->te += 1;
+    }
+  }
+  for (mpm_run* r : mrcm) {
+    mpm_status e = mrcm_update(r);
+    if (e) return e;
+    r->eps_prev = 0.0;
+    r->eps_pending = false;
+    r->last_branch = MPM_FORCE_MRCM;
+    r->te += 1;
+  }
+  *updated = std::move(mpm);
+  return MPM_OK;
+}
+
+// Epsilon of this step for the runs that took the MPM-2P branch (the next decision's value).
+mpm_status group_finish(const std::vector<mpm_run*>& mpm, GroupStreams& gs) {
+  if (mpm.empty()) return MPM_OK;
+  mpm_status e = group_wait_eps(mpm, gs);
+  if (e) return e;
+  for (mpm_run* r : mpm) {
+    r->eps_prev = eps_from(r, r->pinned[0], r->pinned[1]);
+    r->eps_pending = false;
+  }
+  return MPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 mpm_status mpm_batch_create(int32_t capacity, mpm_batch** out) {
   if (capacity <= 0 || !out) return MPM_EINVAL;
@@ -775,18 +960,23 @@ mpm_status mpm_batch_create(int32_t capacity, mpm_batch** out) {
 
 mpm_status mpm_batch_attach(mpm_batch* b, int32_t slot, mpm_run* r) {
   if (!b || !r || slot < 0 || slot >= int32_t(b->slot.size())) return MPM_EINVAL;
-  if (b->slot[slot]) return MPM_ESTATE;
-  for (mpm_run* x : b->slot)
-    if (x == r) return MPM_ESTATE;
+  if (b->slot[slot] || r->owner) return MPM_ESTATE;
   if (!r->started || r->poisoned) return MPM_ESTATE;
   b->slot[slot] = r;
+  r->owner = b;
+  r->owner_slot = slot;
   return MPM_OK;
 }
 
 mpm_status mpm_batch_detach(mpm_batch* b, int32_t slot) {
   if (!b || slot < 0 || slot >= int32_t(b->slot.size())) return MPM_EINVAL;
+  mpm_run* r = b->slot[slot];
   b->slot[slot] = nullptr;
-  return MPM_OK;
+  if (!r) return MPM_OK;
+  r->owner = nullptr;
+  r->owner_slot = -1;
+  mpm_status e = move_run(r, nullptr);
+  return e ? e : leave(r, MPM_OK);
 }
 
 mpm_status mpm_batch_step(mpm_batch* b, const uint8_t* active, uint8_t* breakthrough) {
@@ -799,27 +989,71 @@ mpm_status mpm_batch_step(mpm_batch* b, const uint8_t* active, uint8_t* breakthr
     if (r->poisoned) return MPM_ESTATE;
     run.push_back(r);
   }
-  // every run's transport and conductivity first, then (lagged rule) its update, before any
-  // wait; each run is on its own stream, so their kernels overlap on the device
   mpm_status first = MPM_OK;
   auto note = [&](mpm_run* r, mpm_status st) {
     if (st && !first) first = st;
     if (st) r->poisoned = true;
   };
+  // groups in slot order, split into launches of at most MPM_GROUP_MAX runs
+  std::vector<std::string> order;
+  std::map<std::string, std::vector<mpm_run*>> groups;
   for (mpm_run* r : run) {
-    mpm_status st = enter(r);
+    std::string k = group_key(r);
+    auto& v = groups[k];
+    if (v.empty()) order.push_back(k);
+    v.push_back(r);
+  }
+  struct Issued {
+    std::vector<mpm_run*> runs, updated;
+    int gs;
+  };
+  std::vector<Issued> issued;
+  std::vector<mpm_run*> alone;
+  for (const std::string& k : order) {
+    std::vector<mpm_run*>& v = groups[k];
+    if (v.size() < 2) {
+      alone.push_back(v[0]);
+      continue;
+    }
+    int gs = -1;
+    mpm_status st = group_streams(b, k, &gs);
+    if (st) {
+      for (mpm_run* r : v) note(r, st);
+      continue;
+    }
+    for (size_t a = 0; a < v.size(); a += MPM_GROUP_MAX) {
+      std::vector<mpm_run*> chunk(v.begin() + a, v.begin() + std::min(v.size(), a + MPM_GROUP_MAX));
+      if (chunk.size() == 1) {
+        alone.push_back(chunk[0]);
+        continue;
+      }
+      Issued is{chunk, {}, gs};
+      mpm_status e = group_issue(chunk, b->gs[gs], &is.updated);
+      if (e) for (mpm_run* r : chunk) note(r, e);
+      else issued.push_back(std::move(is));
+    }
+  }
+  // runs stepping alone: every run's transport and conductivity first, then (lagged rule) its
+  // update, before any wait; each on its own stream
+  for (mpm_run* r : alone) {
+    mpm_status st = move_run(r, nullptr);
+    if (!st) st = enter(r);
     if (!st) st = transport_and_kappa(r);
     if (!st && r->P.d.switch_rule == MPM_SWITCH_ALG1) st = vu_update(r, MPM_AUTO, r->eps_prev);
     note(r, st);
   }
-  for (mpm_run* r : run) {
+  for (mpm_run* r : alone) {
     if (r->poisoned || r->P.d.switch_rule != MPM_SWITCH_TEXT) continue;
     double decide;
     mpm_status st = vu_decision(r, &decide);
     if (!st) st = vu_update(r, MPM_AUTO, decide);
     note(r, st);
   }
-  for (mpm_run* r : run) {
+  for (Issued& is : issued) {
+    mpm_status e = group_finish(is.updated, b->gs[is.gs]);
+    if (e) for (mpm_run* r : is.runs) note(r, e);
+  }
+  for (mpm_run* r : alone) {
     if (r->poisoned) continue;
     note(r, leave(r, vu_finish(r)));
   }
@@ -833,6 +1067,16 @@ mpm_status mpm_batch_step(mpm_batch* b, const uint8_t* active, uint8_t* breakthr
 
 mpm_status mpm_batch_destroy(mpm_batch* b) {
   if (!b) return MPM_EINVAL;
+  for (size_t i = 0; i < b->slot.size(); ++i)
+    if (b->slot[i]) mpm_batch_detach(b, int32_t(i));
+  for (GroupStreams& g : b->gs) {
+    hipStreamSynchronize(g.st);
+    hipStreamSynchronize(g.st2);
+    hipEventDestroy(g.ev_eps);
+    hipEventDestroy(g.ev_move);
+    hipStreamDestroy(g.st2);
+    hipStreamDestroy(g.st);
+  }
   delete b;
   return MPM_OK;
 }
@@ -893,6 +1137,7 @@ mpm_status mpm_get_stats(mpm_run* r, mpm_stats* out) {
 
 mpm_status mpm_destroy(mpm_run* r) {
   if (!r) return MPM_EINVAL;
+  if (r->owner) mpm_batch_detach(r->owner, r->owner_slot);
   int32_t errw = 0;
   hipMemcpyAsync(&errw, r->err, 4, hipMemcpyDeviceToHost, r->st);
   hipStreamSynchronize(r->st);

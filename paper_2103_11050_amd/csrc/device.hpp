@@ -19,6 +19,22 @@ struct Geo {
   double s_inj;
 };
 
+// Runs of one batch that share their decomposition and parameters step through one launch per
+// phase: blockIdx.z selects the run, whose workspace (and pinned host block) sits at a byte
+// offset from the first run's; the launch carries the first run's pointers. n = 0: one run,
+// no offsets. Passed by value (kernel argument) and indexed only in kernel bodies.
+constexpr int MPM_GROUP_MAX = 128;
+struct RunTab {
+  int32_t n;
+  int64_t ws[MPM_GROUP_MAX];
+  int64_t host[MPM_GROUP_MAX];
+};
+
+template <class T>
+__host__ __device__ __forceinline__ T* at_off(T* p, int64_t o) {
+  return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + uintptr_t(o));
+}
+
 // Physical boundary data of a side without a run-time index into the struct (which would
 // force the by-value kernel argument into scratch memory).
 __host__ __device__ __forceinline__ int bc_kind_of(const Geo& g, int side) { return (g.bc_pack >> (2 * side)) & 3; }

@@ -436,8 +436,21 @@ template <int MF, int NL, typename T>
 __global__ void __launch_bounds__(64)
 k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict__ kap_m,
                const double* __restrict__ uxm, const double* __restrict__ uym, const double* __restrict__ q,
-               const T* __restrict__ fac, double* __restrict__ hg, double* __restrict__ vbnd, LeafOut lo) {
+               const T* __restrict__ fac, double* __restrict__ hg, double* __restrict__ vbnd, LeafOut lo,
+               RunTab rt) {
   constexpr bool F32 = sizeof(T) == 4;
+  {
+    const int64_t wo = ws_off(rt);
+    kap_n = at_off(kap_n, wo);
+    kap_m = at_off(kap_m, wo);
+    uxm = at_off(uxm, wo);
+    uym = at_off(uym, wo);
+    q = at_off(q, wo);
+    fac = at_off(fac, wo);
+    hg = at_off(hg, wo);
+    vbnd = at_off(vbnd, wo);
+    lo = leaf_at(lo, wo);
+  }
   __shared__ double knt[18 * 18], kmt[18 * 18], uxs[16 * 17], uys[17 * 16];
   __shared__ double xtra[F32 ? 3 * 256 + 768 : 1];   // precision form: tE, tN, dg, refinement scratch
   const int sub = blockIdx.x;
@@ -527,8 +540,22 @@ __global__ void __launch_bounds__(64)
 k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict__ q,
                const double* __restrict__ ubnd, double* __restrict__ ux, double* __restrict__ uy,
                double* __restrict__ red_rate, double* __restrict__ red_qin, T* __restrict__ Escr,
-               T* __restrict__ Ekeep, const int32_t* __restrict__ flag, int store, int32_t* err) {
+               T* __restrict__ Ekeep, const int32_t* __restrict__ flag, int store, int32_t* err, RunTab rt) {
   constexpr bool F32 = sizeof(T) == 4;
+  {
+    const int64_t wo = ws_off(rt);
+    kap_s = at_off(kap_s, wo);
+    q = at_off(q, wo);
+    ubnd = at_off(ubnd, wo);
+    ux = at_off(ux, wo);
+    uy = at_off(uy, wo);
+    red_rate = at_off(red_rate, wo);
+    red_qin = at_off(red_qin, wo);
+    Escr = at_off(Escr, wo);
+    Ekeep = at_off(Ekeep, wo);
+    flag = at_off(flag, wo);
+    err = at_off(err, wo);
+  }
   // the conductivity tile is dead once the weights are built and then holds the solution
   __shared__ double kl[256], w[64], tE[256], tN[256], dg[256];
   __shared__ double wsh[F32 ? 768 : (NL > 0 ? 1 : 256)];
@@ -645,8 +672,16 @@ k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict
 template <int MF, typename T>
 __global__ void __launch_bounds__(64)
 k_ds_factor(Geo g, const double* __restrict__ kap_n, T* __restrict__ Escr, const int32_t* __restrict__ list,
-            const int32_t* __restrict__ count, int32_t* err) {
+            const int32_t* __restrict__ count, int32_t* err, RunTab rt) {
   __shared__ double kl[256], tE[256], tN[256], dg[256];
+  {
+    const int64_t wo = ws_off(rt);
+    kap_n = at_off(kap_n, wo);
+    Escr = at_off(Escr, wo);
+    list = at_off(list, wo);
+    count = at_off(count, wo);
+    err = at_off(err, wo);
+  }
   LB<MF> L;
   const int n = min(*count, g.nsub);
 #pragma unroll 1
@@ -680,56 +715,56 @@ void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double*
   do {                                                                                                   \
     const int nl_ = g.nc / g.band;                                                                       \
     if (line_mf(g) == 8) {                                                                               \
-      if (nl_ == 8) hipLaunchKernelGGL((KERNEL<8, 8, double>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__);  \
-      else hipLaunchKernelGGL((KERNEL<8, 0, double>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__);           \
+      if (nl_ == 8) hipLaunchKernelGGL((KERNEL<8, 8, double>), dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, __VA_ARGS__);  \
+      else hipLaunchKernelGGL((KERNEL<8, 0, double>), dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, __VA_ARGS__);           \
     } else {                                                                                             \
-      if (nl_ == 16) hipLaunchKernelGGL((KERNEL<16, 16, double>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__); \
-      else hipLaunchKernelGGL((KERNEL<16, 0, double>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__);          \
+      if (nl_ == 16) hipLaunchKernelGGL((KERNEL<16, 16, double>), dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, __VA_ARGS__); \
+      else hipLaunchKernelGGL((KERNEL<16, 0, double>), dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, __VA_ARGS__);          \
     }                                                                                                    \
   } while (0)
 
 // precision form: FP32 blocks, any line count up to 16
 #define MPM_LB_DISPATCH_F32(KERNEL, ...)                                                                 \
   do {                                                                                                   \
-    if (line_mf(g) == 8) hipLaunchKernelGGL((KERNEL<8, 16, float>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__); \
-    else hipLaunchKernelGGL((KERNEL<16, 16, float>), dim3(g.nsub), dim3(64), 0, st, __VA_ARGS__);        \
+    if (line_mf(g) == 8) hipLaunchKernelGGL((KERNEL<8, 16, float>), dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, __VA_ARGS__); \
+    else hipLaunchKernelGGL((KERNEL<16, 16, float>), dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, __VA_ARGS__);        \
   } while (0)
 
 void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                       const double* uym, const double* q, const double* fac, double* h, double* vbnd,
-                      LeafOut lo) {
-  MPM_LB_DISPATCH(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, lo);
+                      LeafOut lo, const RunTab& rt) {
+  MPM_LB_DISPATCH(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, lo, rt);
 }
 
 template <typename T>
 static void ds_factor_any(hipStream_t st, const Geo& g, const double* kap_n, T* Escr, const int32_t* list,
-                          const int32_t* count, int32_t* err) {
-  const int grid = std::min(g.nsub, 1024);
+                          const int32_t* count, int32_t* err, const RunTab& rt) {
+  const dim3 grid(std::min(g.nsub, 1024), 1, runs_of(rt));
   if (line_mf(g) == 8)
-    hipLaunchKernelGGL((k_ds_factor<8, T>), dim3(grid), dim3(64), 0, st, g, kap_n, Escr, list, count, err);
-  else hipLaunchKernelGGL((k_ds_factor<16, T>), dim3(grid), dim3(64), 0, st, g, kap_n, Escr, list, count, err);
+    hipLaunchKernelGGL((k_ds_factor<8, T>), grid, dim3(64), 0, st, g, kap_n, Escr, list, count, err, rt);
+  else hipLaunchKernelGGL((k_ds_factor<16, T>), grid, dim3(64), 0, st, g, kap_n, Escr, list, count, err, rt);
 }
 
 void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, double* Escr, const int32_t* list,
-                      const int32_t* count, int32_t* err) {
-  ds_factor_any<double>(st, g, kap_n, Escr, list, count, err);
+                      const int32_t* count, int32_t* err, const RunTab& rt) {
+  ds_factor_any<double>(st, g, kap_n, Escr, list, count, err, rt);
 }
 
 void launch_ds_factor_f32(hipStream_t st, const Geo& g, const double* kap_n, float* Escr, const int32_t* list,
-                          const int32_t* count, int32_t* err) {
-  ds_factor_any<float>(st, g, kap_n, Escr, list, count, err);
+                          const int32_t* count, int32_t* err, const RunTab& rt) {
+  ds_factor_any<float>(st, g, kap_n, Escr, list, count, err, rt);
 }
 
 void launch_mpm_local_f32(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                           const double* uym, const double* q, const float* fac, double* h, double* vbnd,
-                          LeafOut lo) {
-  MPM_LB_DISPATCH_F32(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, lo);
+                          LeafOut lo, const RunTab& rt) {
+  MPM_LB_DISPATCH_F32(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, lo, rt);
 }
 
 void launch_downscale_f32(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
                           double* ux, double* uy, double* red_rate, double* red_qin, float* Escr, float* Ekeep,
-                          const int32_t* flag, int32_t* err) {
-  MPM_LB_DISPATCH_F32(k_downscale_lb, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, Escr, Ekeep, flag, 0, err);
+                          const int32_t* flag, int32_t* err, const RunTab& rt) {
+  MPM_LB_DISPATCH_F32(k_downscale_lb, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, Escr, Ekeep, flag, 0, err, rt);
 }
 
 __global__ void __launch_bounds__(256) k_to_f32(size_t n, const double* __restrict__ src, float* __restrict__ dst) {
@@ -744,8 +779,8 @@ void launch_to_f32(hipStream_t st, size_t n, const double* src, float* dst) {
 
 void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
                       double* ux, double* uy, double* red_rate, double* red_qin, double* Escr, double* Ekeep,
-                      const int32_t* flag, int store, int32_t* err) {
-  MPM_LB_DISPATCH(k_downscale_lb, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, Escr, Ekeep, flag, store, err);
+                      const int32_t* flag, int store, int32_t* err, const RunTab& rt) {
+  MPM_LB_DISPATCH(k_downscale_lb, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, Escr, Ekeep, flag, store, err, rt);
 }
 
 size_t line_factor_doubles(int nsub, int nc, int band) {

@@ -228,7 +228,8 @@ __device__ __forceinline__ double ld32(const double* base, uint32_t elem) {
 // workgroup 0 of the node also stores f_I for the backward sweep. The root is not launched.
 // Rows longer than G*U (only with CH) are taken in chunks.
 template <int G, int U, int RP, bool CH>
-__global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a, int loff) {
+__global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a0, int loff, RunTab rt) {
+  const NdArgs a = nd_at(a0, ws_off(rt));
   constexpr int RPP = 256 / G, RPB = RP * RPP;
   const NodeDev nd = a.lnodes[loff + blockIdx.y];
   const int r0 = blockIdx.x * RPB;
@@ -373,10 +374,10 @@ static RbShape rb_shape(int len) {
   return {64, 0, 1};   // longer rows: chunks of 1024
 }
 
-#define ND_RB_LAUNCH(KER, sh, rows, nnodes, st, ...)                                                  \
+#define ND_RB_LAUNCH(KER, sh, rows, nnodes, nruns, st, ...)                                           \
   do {                                                                                              \
     const int rpb_ = (sh).RP * (256 / (sh).G);                                                      \
-    const dim3 grid_(std::max(1, ((rows) + rpb_ - 1) / rpb_), (nnodes));                          \
+    const dim3 grid_(std::max(1, ((rows) + rpb_ - 1) / rpb_), (nnodes), (nruns));                 \
     if ((sh).G == 16) hipLaunchKernelGGL((KER<16, 1, 8, false>), grid_, dim3(256), 0, st, __VA_ARGS__);        \
     else if ((sh).G == 32) hipLaunchKernelGGL((KER<32, 1, 8, false>), grid_, dim3(256), 0, st, __VA_ARGS__);   \
     else if ((sh).U == 1) hipLaunchKernelGGL((KER<64, 1, 8, false>), grid_, dim3(256), 0, st, __VA_ARGS__);    \
@@ -391,18 +392,19 @@ static RbShape rb_shape(int len) {
     else hipLaunchKernelGGL((KER<64, 16, 1, true>), grid_, dim3(256), 0, st, __VA_ARGS__);                     \
   } while (0)
 
-void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nBmax) {
+void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nBmax,
+                         const RunTab& rt) {
   const RbShape sh = rb_shape(nImax);
-  ND_RB_LAUNCH(k_nd_fwd_rb, sh, nBmax, nnodes, st, a, loff);
+  ND_RB_LAUNCH(k_nd_fwd_rb, sh, nBmax, nnodes, runs_of(rt), st, a, loff, rt);
 }
 
 template <int G, int U, int RP, bool CH>
-__global__ void __launch_bounds__(256) k_nd_bwd_inner(NdArgs a, int loff) {
-  k_nd_bwd_body<G, U, RP, CH, false>(a, loff);
+__global__ void __launch_bounds__(256) k_nd_bwd_inner(NdArgs a, int loff, RunTab rt) {
+  k_nd_bwd_body<G, U, RP, CH, false>(nd_at(a, ws_off(rt)), loff);
 }
 template <int G, int U, int RP, bool CH>
-__global__ void __launch_bounds__(256) k_nd_bwd_root(NdArgs a, int loff) {
-  k_nd_bwd_body<G, U, RP, CH, true>(a, loff);
+__global__ void __launch_bounds__(256) k_nd_bwd_root(NdArgs a, int loff, RunTab rt) {
+  k_nd_bwd_body<G, U, RP, CH, true>(nd_at(a, ws_off(rt)), loff);
 }
 
 // The backward sweep takes twice the rows per lane group for rows of 65..512 entries (fewer,
@@ -413,10 +415,11 @@ static RbShape rb_shape_bwd(int len) {
   return sh;
 }
 
-void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nmax, int root) {
+void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nmax, int root,
+                         const RunTab& rt) {
   const RbShape sh = rb_shape_bwd(nmax);
-  if (root) ND_RB_LAUNCH(k_nd_bwd_root, sh, nImax, nnodes, st, a, loff);
-  else ND_RB_LAUNCH(k_nd_bwd_inner, sh, nImax, nnodes, st, a, loff);
+  if (root) ND_RB_LAUNCH(k_nd_bwd_root, sh, nImax, nnodes, runs_of(rt), st, a, loff, rt);
+  else ND_RB_LAUNCH(k_nd_bwd_inner, sh, nImax, nnodes, runs_of(rt), st, a, loff, rt);
 }
 
 }  // namespace mpm

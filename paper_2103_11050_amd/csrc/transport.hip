@@ -21,7 +21,15 @@ __device__ __forceinline__ double fracflow(double s, double M) {
 // s2 = s - dt/|c| sum_f |f| u_f f(s_upwind); the injected saturation on inflow boundary faces.
 __global__ void __launch_bounds__(256)
 k_sat_step(Geo g, const double* __restrict__ s, double* __restrict__ s2, const double* __restrict__ ux,
-           const double* __restrict__ uy, double* __restrict__ scal, double M, double area) {
+           const double* __restrict__ uy, double* __restrict__ scal, double M, double area, RunTab rt) {
+  {
+    const int64_t wo = ws_off(rt);
+    s = at_off(s, wo);
+    s2 = at_off(s2, wo);
+    ux = at_off(ux, wo);
+    uy = at_off(uy, wo);
+    scal = at_off(scal, wo);
+  }
   const int gi = blockIdx.x * 64 + (threadIdx.x & 63);
   const int gj = blockIdx.y * 4 + (threadIdx.x >> 6);
   const double dt = scal[SC_DT];
@@ -52,7 +60,14 @@ k_sat_step(Geo g, const double* __restrict__ s, double* __restrict__ s2, const d
 // issued in batches of 16 per thread).
 __global__ void __launch_bounds__(256)
 k_water_cut(Geo g, const double* __restrict__ s, const double* __restrict__ ux, const double* __restrict__ uy,
-            double* __restrict__ scal, double M) {
+            double* __restrict__ scal, double M, RunTab rt) {
+  {
+    const int64_t wo = ws_off(rt);
+    s = at_off(s, wo);
+    ux = at_off(ux, wo);
+    uy = at_off(uy, wo);
+    scal = at_off(scal, wo);
+  }
   constexpr int B = 16;
   __shared__ double sq[256], sw[256];
   double q = 0.0, w = 0.0;
@@ -99,14 +114,14 @@ k_water_cut(Geo g, const double* __restrict__ s, const double* __restrict__ ux, 
 }
 
 void launch_sat_step(hipStream_t st, const Geo& g, const double* s, double* s2, const double* ux,
-                     const double* uy, double* scal, double M, double area) {
-  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4);
-  hipLaunchKernelGGL(k_sat_step, grid, dim3(256), 0, st, g, s, s2, ux, uy, scal, M, area);
+                     const double* uy, double* scal, double M, double area, const RunTab& rt) {
+  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, runs_of(rt));
+  hipLaunchKernelGGL(k_sat_step, grid, dim3(256), 0, st, g, s, s2, ux, uy, scal, M, area, rt);
 }
 
 void launch_water_cut(hipStream_t st, const Geo& g, const double* s, const double* ux, const double* uy,
-                      double* scal, double M) {
-  hipLaunchKernelGGL(k_water_cut, dim3(1), dim3(256), 0, st, g, s, ux, uy, scal, M);
+                      double* scal, double M, const RunTab& rt) {
+  hipLaunchKernelGGL(k_water_cut, dim3(1, 1, runs_of(rt)), dim3(256), 0, st, g, s, ux, uy, scal, M, rt);
 }
 
 }  // namespace mpm

@@ -4,8 +4,9 @@ Serving: forward-run requests (Algorithm 1 of Section 4.2, each run to water bre
 arrive over time. A request is admitted into a free slot of one `Batch` when its exact device
 footprint (`mpm_workspace_size`) fits the remaining HBM budget; it then keeps its basis,
 interface factorisation and saturation resident in its workspace and steps together with the
-others (each run on its own stream, every run's work issued before any wait). A finished run
-leaves its slot and frees its footprint for the next request (continuous batching).
+others (runs with equal descriptors as one launch per phase, the rest each on its own stream;
+every run's work issued before any wait). A finished run leaves its slot and frees its
+footprint for the next request (continuous batching).
 
 Batched: many realisations of uneven sizes stepped together for a fixed number of passes.
 

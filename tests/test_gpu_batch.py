@@ -181,3 +181,100 @@ def test_served_equals_alone(binding):
         assert np.array_equal(to_np(s), rec["state"][2])
         assert r.stats()["te"] == rec["te"]
         r.close()
+
+
+# Runs with equal descriptors (only the permeability differs) step as one group: one launch per
+# phase for all of them. Group A mixes MRCM and MPM-2P updates in the same step (small eta),
+# group B uses the text switch rule, group C the precision form; one run steps alone.
+GROUPED = [
+    # (seed, nx, ny, sub, ne, overrides, precision)
+    (201, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=20.0, eta=0.01), 0),
+    (202, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=20.0, eta=0.01), 0),
+    (203, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=20.0, eta=0.01), 0),
+    (204, 64, 48, 16, 4, dict(sigma2=3.0, corr_len=0.1, mu_o=50.0, eta=0.05, switch_rule="text"), 0),
+    (205, 64, 48, 16, 4, dict(sigma2=3.0, corr_len=0.1, mu_o=50.0, eta=0.05, switch_rule="text"), 0),
+    (206, 48, 32, 16, 4, dict(sigma2=2.0, corr_len=0.2, mu_o=30.0, eta=0.03), 1),
+    (207, 48, 32, 16, 4, dict(sigma2=2.0, corr_len=0.2, mu_o=30.0, eta=0.03), 1),
+    (208, 64, 64, 16, 8, dict(sigma2=4.0, corr_len=0.1, mu_o=100.0, eta=0.1), 0),
+]
+
+
+def _make_g(binding, p, stream=None):
+    seed, nx, ny, sub, ne, kw, prec = p
+    cfg, K = inputs.random_problem(seed, nx, ny, sub, sub, ne, ne, **kw)
+    dev = torch.device("cuda:0")
+    Kt = torch.from_numpy(np.ascontiguousarray(K)).to(dev)
+    st = torch.from_numpy(np.ascontiguousarray(inputs.initial_saturation(cfg))).to(dev)
+    torch.cuda.synchronize()
+    r = binding.Run(cfg, Kt, st, precision=prec, stream=stream)
+    r.start()
+    return r
+
+
+def _solo(binding, p, n):
+    r = _make_g(binding, p)
+    hist = []
+    for _ in range(n):
+        r.step()
+        hist.append(r.stats()["last_branch"])
+    out = _state(r)
+    r.close()
+    return out, hist
+
+
+def test_grouped_batch_equals_solo(binding):
+    nsteps = 12
+    print("[gpu] grouped batch of", len(GROUPED), "runs,", nsteps, "steps", flush=True)
+    solo = [_solo(binding, p, nsteps) for p in GROUPED]
+    streams = [torch.cuda.Stream() for _ in GROUPED]
+    runs = [_make_g(binding, p, s) for p, s in zip(GROUPED, streams)]
+    b = binding.Batch(len(runs))
+    for i, r in enumerate(runs):
+        b.attach(i, r)
+    for _ in range(nsteps):
+        b.step()
+    for r, (ref, _) in zip(runs, solo):
+        _same(_state(r), ref)
+    # group A took both branches within one step at least once
+    hists = [h for _, h in solo[:3]]
+    assert any(len({h[k] for h in hists}) == 2 for k in range(nsteps)), hists
+    b.close()
+    for r in runs:
+        r.close()
+
+
+def test_grouped_batch_parity_and_refill(binding):
+    """Runs of one descriptor leave and rejoin the batch, so that their saturation buffers
+    differ in parity (separate groups) and groups shrink and grow between steps; each run ends
+    equal to its solo run with the same number of steps."""
+    ps = GROUPED[:3]
+    streams = [torch.cuda.Stream() for _ in ps]
+    runs = [_make_g(binding, p, s) for p, s in zip(ps, streams)]
+    n = [0, 0, 0]
+    b = binding.Batch(3)
+    for i, r in enumerate(runs):
+        b.attach(i, r)
+    for _ in range(3):
+        b.step()
+        n = [k + 1 for k in n]
+    b.detach(0)
+    b.step()                          # group of two
+    n[1] += 1
+    n[2] += 1
+    b.attach(0, runs[0])              # back, one step behind: a group of its own parity
+    for _ in range(2):
+        b.step()
+        n = [k + 1 for k in n]
+    b.step([True, False, True])       # runs 0 and 2 (different parity)
+    n[0] += 1
+    n[2] += 1
+    b.step([True, True, False])       # runs 0 and 1 (same parity again)
+    n[0] += 1
+    n[1] += 1
+    got = [_state(r) for r in runs]
+    b.close()
+    for p, k, g in zip(ps, n, got):
+        ref, _ = _solo(binding, p, k)
+        _same(g, ref)
+    for r in runs:
+        r.close()
