@@ -88,6 +88,7 @@ struct mpm_run {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   const int32_t* subdofs_d = nullptr;
   double fmax_deriv = 0.0;
+  double params[SC_FMAX - SC_MUW + 1] = {};   // the run's physics for the scalar block
   double M = 1.0;
   double area = 1.0;
   // Algorithm 1 state
@@ -111,6 +112,10 @@ struct mpm_run {
   mpm_batch* owner = nullptr;
   int32_t owner_slot = -1;
   hipStream_t home = nullptr;
+  // the run tables last written to this run's workspace (when it leads a batch group): all
+  // runs of the group, and those of them taking the MPM-2P branch
+  RunTab tab_host[2] = {};
+  unsigned tab_n[2] = {0, 0};
 
   hipEvent_t take_event() {
     if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
@@ -161,7 +166,7 @@ Geo make_geo(const Plan& P) {
   g.nx = P.nx; g.ny = P.ny; g.mx = P.mx; g.my = P.my; g.Sx = P.Sx; g.Sy = P.Sy; g.nsub = P.nsub;
   g.nc = P.nc; g.band = P.band; g.xfast = P.xfast; g.nb = P.nb; g.ne_x = P.ne_x; g.ne_y = P.ne_y;
   g.n_vert = P.n_vert; g.ndmax = P.ndmax;
-  g.hx = P.hx; g.hy = P.hy; g.alpha = P.d.alpha; g.mu_w = P.d.mu_w; g.mu_o = P.d.mu_o;
+  g.hx = P.hx; g.hy = P.hy; g.alpha = P.d.alpha;
   g.bc_pack = 0;
   for (int k = 0; k < 4; ++k) g.bc_pack |= (P.d.bc_kind[k] & 3) << (2 * k);
   g.bc_v0 = P.d.bc_value[0]; g.bc_v1 = P.d.bc_value[1]; g.bc_v2 = P.d.bc_value[2]; g.bc_v3 = P.d.bc_value[3];
@@ -260,7 +265,7 @@ hipGraphExec_t capture_and_launch(mpm_run* r, F&& body) {
 
 LeafOut leaf_dest(const mpm_run* r) { return LeafOut{r->slots, r->leafup, r->nd.map_pool}; }
 
-void nd_solve(mpm_run* r, const RunTab& rt = one_run()) {
+void nd_solve(mpm_run* r, Runs rt = one_run()) {
   const Plan& P = r->P;
   const int L = int(P.level_nodes.size()) - 1;
   {
@@ -292,7 +297,7 @@ void nd_factor(mpm_run* r) {
   }
 }
 
-void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store, const RunTab& rt = one_run()) {
+void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store, Runs rt = one_run()) {
   {
     Scope sc(r, "flux");
     launch_flux(r->st, r->g, r->km, r->S, r->h, r->vbnd, r->y, r->subdofs_d, r->ubnd, with_v, rt);
@@ -312,7 +317,7 @@ void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store, con
   }
   {
     Scope sc(r, "dt");
-    launch_dt(r->st, r->P.nsub, r->red, r->red + r->P.nsub, r->P.d.cfl, r->fmax_deriv, r->scal, r->dscount, rt);
+    launch_dt(r->st, r->P.nsub, r->red, r->red + r->P.nsub, r->scal, r->dscount, rt);
   }
 }
 
@@ -344,7 +349,7 @@ mpm_status mrcm_update(mpm_run* r) {
 
 // MPM-2P: trivial-Robin solve with the stored kappa^m factors, interface solve with the stored
 // factorisation, reconstruction, downscaling with kappa^n.
-mpm_status mpm_update_body(mpm_run* r, bool capturing, const RunTab& rt = one_run()) {
+mpm_status mpm_update_body(mpm_run* r, bool capturing, Runs rt = one_run()) {
   // kappa^n Neumann factors of the changed subdomains on the second stream, overlapped with
   // the local and interface solves. It forks at the epsilon event, recorded right after the
   // conductivity and its changed-subdomain list (one marker on the main stream, not two).
@@ -446,12 +451,12 @@ mpm_status velocity_update(mpm_run* r, int32_t force, bool kappa_done = false) {
 mpm_status transport_body(mpm_run* r, int32_t nsteps) {
   for (int k = 0; k < nsteps; ++k) {
     Scope sc(r, "sat_step");
-    launch_sat_step(r->st, r->g, r->s, r->s2, r->ux, r->uy, r->scal, r->M, r->area);
+    launch_sat_step(r->st, r->g, r->s, r->s2, r->ux, r->uy, r->scal, r->area);
     std::swap(r->s, r->s2);
   }
   {
     Scope sc(r, "water_cut");
-    launch_water_cut(r->st, r->g, r->s, r->ux, r->uy, r->scal, r->M);
+    launch_water_cut(r->st, r->g, r->s, r->ux, r->uy, r->scal);
   }
   return MPM_OK;
 }
@@ -578,6 +583,11 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   r->leafup = reinterpret_cast<const LeafUp*>(r->ws + P.off_leafup);
   r->M = P.d.mu_o / P.d.mu_w;
   r->fmax_deriv = max_fprime(r->M);
+  r->params[SC_MUW - SC_MUW] = P.d.mu_w;
+  r->params[SC_MUO - SC_MUW] = P.d.mu_o;
+  r->params[SC_MRATIO - SC_MUW] = r->M;
+  r->params[SC_CFL - SC_MUW] = P.d.cfl;
+  r->params[SC_FMAX - SC_MUW] = r->fmax_deriv;
   r->area = P.d.lx * P.d.ly;
 #define CREATE_CHK(call)                                                           \
   do {                                                                             \
@@ -700,6 +710,7 @@ mpm_status mpm_start(mpm_run* r) {
   // Algorithm 1, lines 1-4
   auto body = [&]() -> mpm_status {
     HIPCHK(r, hipMemsetAsync(r->scal, 0, SC_COUNT * 8, r->st));
+    HIPCHK(r, hipMemcpyAsync(r->scal + SC_MUW, r->params, sizeof(r->params), hipMemcpyHostToDevice, r->st));
     mpm_status s2 = kappa_and_eps(r);
     if (s2) return s2;
     r->te = 0; r->tm = 0; r->ntr = 0;
@@ -785,16 +796,18 @@ struct mpm_batch {
 
 namespace {
 
-// Descriptor fields one by one (no padding bytes) and the saturation parity.
+// The descriptor fields that shape the launches, one by one (no padding bytes), and the
+// saturation parity. The viscosities and cfl (read by the kernels from each run's scalar
+// block) and eta, the epsilon norm and the breakthrough cut (host-side, per run) may differ
+// inside a group.
 std::string group_key(const mpm_run* r) {
   const mpm_desc& d = r->P.d;
   std::string k;
   auto put = [&](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
   put(&d.abi_version, 4); put(&d.nx, 4); put(&d.ny, 4); put(&d.lx, 8); put(&d.ly, 8);
-  put(&d.sub_x, 4); put(&d.sub_y, 4); put(&d.ne_x, 4); put(&d.ne_y, 4); put(&d.alpha, 8); put(&d.eta, 8);
-  put(&d.eps_norm, 4); put(&d.switch_rule, 4); put(&d.precision, 4); put(&d.cn, 4); put(&d.mu_w, 8);
-  put(&d.mu_o, 8); put(d.bc_kind, 16); put(d.bc_value, 32); put(&d.s_inj, 8); put(&d.cfl, 8);
-  put(&d.breakthrough_cut, 8);
+  put(&d.sub_x, 4); put(&d.sub_y, 4); put(&d.ne_x, 4); put(&d.ne_y, 4); put(&d.alpha, 8);
+  put(&d.switch_rule, 4); put(&d.precision, 4); put(&d.cn, 4); put(d.bc_kind, 16); put(d.bc_value, 32);
+  put(&d.s_inj, 8);
   k.push_back(r->s == r->s_base ? 0 : 1);
   return k;
 }
@@ -845,14 +858,27 @@ mpm_status move_run(mpm_run* r, hipStream_t st) {
   return MPM_OK;
 }
 
-RunTab make_tab(const std::vector<mpm_run*>& g) {
-  RunTab t{};
-  t.n = int32_t(g.size());
-  for (size_t i = 0; i < g.size(); ++i) {
-    t.ws[i] = int64_t(g[i]->ws - g[0]->ws);
-    t.host[i] = int64_t(reinterpret_cast<char*>(g[i]->pinned_dev) - reinterpret_cast<char*>(g[0]->pinned_dev));
+// Table `which` of the group g led by g[0], written into the leader's workspace on stream st
+// when it differs from the one already there.
+mpm_status group_tab(const std::vector<mpm_run*>& g, int which, hipStream_t st, Runs* out) {
+  mpm_run* L = g[0];
+  RunTab& t = L->tab_host[which];
+  const unsigned n = unsigned(g.size());
+  bool same = L->tab_n[which] == n;
+  for (unsigned i = 0; i < n; ++i) {
+    const int64_t w = int64_t(g[i]->ws - L->ws);
+    const int64_t h = int64_t(reinterpret_cast<char*>(g[i]->pinned_dev) - reinterpret_cast<char*>(L->pinned_dev));
+    same = same && t.ws[i] == w && t.host[i] == h;
+    t.ws[i] = w;
+    t.host[i] = h;
   }
-  return t;
+  RunTab* dev = reinterpret_cast<RunTab*>(L->ws + L->P.off_rtab) + which;
+  if (!same) {
+    HIPCHK(L, hipMemcpyAsync(dev, &t, sizeof(RunTab), hipMemcpyHostToDevice, st));
+    L->tab_n[which] = n;
+  }
+  *out = Runs{dev, n};
+  return MPM_OK;
 }
 
 // Epsilon sums of the group's latest conductivity launch on the host (one event for the group,
@@ -880,14 +906,18 @@ mpm_status group_issue(std::vector<mpm_run*>& g, GroupStreams& gs, std::vector<m
     if (e) return e;
   }
   mpm_run* L = g[0];
-  const RunTab rt = make_tab(g);
+  Runs rt;
+  {
+    mpm_status e = group_tab(g, 0, gs.st, &rt);
+    if (e) return e;
+  }
   const int cn = L->P.d.cn;
   // transport sub-steps, water cut, conductivity and epsilon sums of every run
   for (int k = 0; k < cn; ++k) {
-    launch_sat_step(gs.st, L->g, L->s, L->s2, L->ux, L->uy, L->scal, L->M, L->area, rt);
+    launch_sat_step(gs.st, L->g, L->s, L->s2, L->ux, L->uy, L->scal, L->area, rt);
     for (mpm_run* r : g) std::swap(r->s, r->s2);
   }
-  launch_water_cut(gs.st, L->g, L->s, L->ux, L->uy, L->scal, L->M, rt);
+  launch_water_cut(gs.st, L->g, L->s, L->ux, L->uy, L->scal, rt);
   launch_kappa(gs.st, L->g, L->s, L->K, L->kn, L->km, L->red, L->scal, L->dsflag, L->dslist, L->dscount,
                L->dscount + 1, L->pinned_dev, rt);
   for (mpm_run* r : g) {
@@ -909,7 +939,9 @@ mpm_status group_issue(std::vector<mpm_run*>& g, GroupStreams& gs, std::vector<m
   }
   if (!mpm.empty()) {
     mpm_run* M = mpm[0];
-    const RunTab rm = make_tab(mpm);
+    Runs rm;
+    mpm_status et = group_tab(mpm, 1, gs.st, &rm);
+    if (et) return et;
     // the ds_factor fork of the first run's update waits for the group's conductivity
     HIPCHK(M, hipEventRecord(M->ev_eps, gs.st));
     mpm_status e = mpm_update_body(M, false, rm);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "plan.hpp"
 
 namespace mpm {
@@ -13,26 +15,17 @@ struct Geo {
   int nx, ny, mx, my, Sx, Sy, nsub;
   int nc, band, xfast, nb, ne_x, ne_y, n_vert, ndmax;
   double hx, hy, alpha;
-  double mu_w, mu_o;
   int bc_pack;          // MPM_BC_* of side s in bits 2s..2s+1 (sides W, E, S, N)
   double bc_v0, bc_v1, bc_v2, bc_v3;
   double s_inj;
 };
 
-// Runs of one batch that share their decomposition and parameters step through one launch per
-// phase: blockIdx.z selects the run, whose workspace (and pinned host block) sits at a byte
-// offset from the first run's; the launch carries the first run's pointers. n = 0: one run,
-// no offsets. Passed by value (kernel argument) and indexed only in kernel bodies.
-constexpr int MPM_GROUP_MAX = 128;
-struct RunTab {
-  int32_t n;
-  int64_t ws[MPM_GROUP_MAX];
-  int64_t host[MPM_GROUP_MAX];
-};
-
+// p moved by o bytes (pointer arithmetic on bytes, so that the compiler keeps the address
+// space of p: an integer round trip would turn global loads into flat ones).
 template <class T>
 __host__ __device__ __forceinline__ T* at_off(T* p, int64_t o) {
-  return reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + uintptr_t(o));
+  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return reinterpret_cast<T*>(reinterpret_cast<B*>(p) + o);
 }
 
 // Physical boundary data of a side without a run-time index into the struct (which would
@@ -159,9 +152,10 @@ __device__ __forceinline__ void set_error(int32_t* err, int32_t bits) { atomicOr
 // Transport sub-step from the maximum outflow rate and the boundary inflow, reduced in a fixed
 // order from per-subdomain partials (run by one workgroup of 256 threads; each thread issues
 // its loads in batches of 16 before adding them).
-__device__ __forceinline__ void reduce_dt(int nsub, const double* red_rate, const double* red_qin, double cfl,
-                                          double fmax_deriv, double* scal, double* sm, double* ss) {
+__device__ __forceinline__ void reduce_dt(int nsub, const double* red_rate, const double* red_qin, double* scal,
+                                          double* sm, double* ss) {
   constexpr int B = 16;
+  const double cfl = scal[SC_CFL], fmax_deriv = scal[SC_FMAX];   // requested first
   double m = 0.0, s = 0.0;
   for (int base = 0; base < nsub; base += 256 * B) {
     double vr[B], vq[B];

@@ -7,15 +7,19 @@
 
 namespace mpm {
 
-// The table of a launch for one run (no offsets), and the runs a table covers (grid z).
-inline const RunTab& one_run() {
-  static const RunTab t{};
-  return t;
-}
-inline unsigned runs_of(const RunTab& rt) { return rt.n > 0 ? unsigned(rt.n) : 1u; }
+// The runs of a launch: n runs (grid z) with the table of their offsets in device memory, or
+// one run and no table.
+struct Runs {
+  const RunTab* tab;
+  unsigned n;
+};
+inline Runs one_run() { return Runs{nullptr, 1u}; }
+inline unsigned runs_of(const Runs& rs) { return rs.n; }
 
-// Byte offset of the workspace of the run of this workgroup (grid z) from the first run's.
-__device__ __forceinline__ int64_t ws_off(const RunTab& rt) { return rt.n ? rt.ws[blockIdx.z] : 0; }
+// Byte offsets of the workspace and of the pinned block of the run of this workgroup (grid z)
+// from the first run's.
+__device__ __forceinline__ int64_t ws_off(const RunTab* rt) { return rt ? rt->ws[blockIdx.z] : 0; }
+__device__ __forceinline__ int64_t host_off(const RunTab* rt) { return rt ? rt->host[blockIdx.z] : 0; }
 
 // Destination of a subdomain's interface right-hand side B^T h: the slot of its parent in the
 // nested-dissection tree (entry map_pool[up.map_off + a] for local unknown a).
@@ -32,15 +36,16 @@ __device__ __forceinline__ void leaf_out(const LeafOut& lo, int sub, int a, doub
   if (u.slot_off >= 0) lo.slots[u.slot_off + lo.map_pool[u.map_off + a]] = v;
 }
 
-// Every launcher that takes a RunTab runs the kernel for rt.n runs at once (grid z), with the
+// Every launcher that takes Runs runs the kernel for rt.n runs at once (grid z), with the
 // pointers of the first run; by default for one run.
 
 // local.hip
 void launch_kappa(hipStream_t st, const Geo& g, const double* s, const double* K, double* kn, const double* km,
                   double* red, double* scal, int32_t* flag, int32_t* list, int32_t* count, int32_t* seq,
-                  double* host, const RunTab& rt = one_run());
-void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double cfl,
-               double fmax_deriv, double* scal, int32_t* count, const RunTab& rt = one_run());
+                  double* host, Runs rt = one_run());
+// the sub-step bound uses the run's cfl and fractional-flow derivative bound from scal
+void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double* scal,
+               int32_t* count, Runs rt = one_run());
 
 // basis.hip: returns whether the kappa^m line-block inverses were written as well
 bool launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
@@ -50,30 +55,30 @@ void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double*
 size_t line_factor_doubles(int nsub, int nc, int band);
 void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                       const double* uym, const double* q, const double* fac, double* h, double* vbnd,
-                      LeafOut lo, const RunTab& rt = one_run());
+                      LeafOut lo, Runs rt = one_run());
 void launch_flux(hipStream_t st, const Geo& g, const double* km, const double* S, const double* h,
                  const double* vbnd, const double* y, const int32_t* sub_dofs, double* ubnd, int with_v,
-                 const RunTab& rt = one_run());
+                 Runs rt = one_run());
 // Neumann inverse blocks of kappa^n for the subdomains whose conductivity tile differs from
 // kappa^m (into Escr, flag[sub] = 1), flag[sub] = 0 elsewhere.
 void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, double* Escr, const int32_t* list,
-                      const int32_t* count, int32_t* err, const RunTab& rt = one_run());
+                      const int32_t* count, int32_t* err, Runs rt = one_run());
 // store = 1: kap_s is kappa^m, its inverse blocks are formed here and kept (Ekeep).
 // store = 0: the blocks come from Escr where flag[sub] is set, else from Ekeep.
 // precision form: FP32 inverse blocks, FP64 refinement (MPM-2P steps), and the conversion of
 // FP64 blocks kept by an MRCM update
 void launch_ds_factor_f32(hipStream_t st, const Geo& g, const double* kap_n, float* Escr, const int32_t* list,
-                          const int32_t* count, int32_t* err, const RunTab& rt = one_run());
+                          const int32_t* count, int32_t* err, Runs rt = one_run());
 void launch_mpm_local_f32(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                           const double* uym, const double* q, const float* fac, double* h, double* vbnd,
-                          LeafOut lo, const RunTab& rt = one_run());
+                          LeafOut lo, Runs rt = one_run());
 void launch_downscale_f32(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
                           double* ux, double* uy, double* red_rate, double* red_qin, float* Escr, float* Ekeep,
-                          const int32_t* flag, int32_t* err, const RunTab& rt = one_run());
+                          const int32_t* flag, int32_t* err, Runs rt = one_run());
 void launch_to_f32(hipStream_t st, size_t n, const double* src, float* dst);
 void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
                       double* ux, double* uy, double* red_rate, double* red_qin, double* Escr, double* Ekeep,
-                      const int32_t* flag, int store, int32_t* err, const RunTab& rt = one_run());
+                      const int32_t* flag, int store, int32_t* err, Runs rt = one_run());
 
 // nd.hip: nested-dissection factorisation and solve of the interface system
 struct NdArgs {
@@ -113,14 +118,15 @@ __device__ __forceinline__ NdArgs nd_at(const NdArgs& a, int64_t o) {
 }
 void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nmax, int nImax);
 void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nImax, int nBmax,
-                         const RunTab& rt = one_run());
+                         Runs rt = one_run());
 void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nImax, int nmax, int root,
-                         const RunTab& rt = one_run());
+                         Runs rt = one_run());
 
 // transport.hip
+// (the viscosity ratio M is the run's, from scal)
 void launch_sat_step(hipStream_t st, const Geo& g, const double* s, double* s2, const double* ux,
-                     const double* uy, double* scal, double M, double area, const RunTab& rt = one_run());
+                     const double* uy, double* scal, double area, Runs rt = one_run());
 void launch_water_cut(hipStream_t st, const Geo& g, const double* s, const double* ux, const double* uy,
-                      double* scal, double M, const RunTab& rt = one_run());
+                      double* scal, Runs rt = one_run());
 
 }  // namespace mpm

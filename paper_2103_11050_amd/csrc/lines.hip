@@ -437,7 +437,7 @@ __global__ void __launch_bounds__(64)
 k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict__ kap_m,
                const double* __restrict__ uxm, const double* __restrict__ uym, const double* __restrict__ q,
                const T* __restrict__ fac, double* __restrict__ hg, double* __restrict__ vbnd, LeafOut lo,
-               RunTab rt) {
+               const RunTab* __restrict__ rt) {
   constexpr bool F32 = sizeof(T) == 4;
   {
     const int64_t wo = ws_off(rt);
@@ -540,7 +540,7 @@ __global__ void __launch_bounds__(64)
 k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict__ q,
                const double* __restrict__ ubnd, double* __restrict__ ux, double* __restrict__ uy,
                double* __restrict__ red_rate, double* __restrict__ red_qin, T* __restrict__ Escr,
-               T* __restrict__ Ekeep, const int32_t* __restrict__ flag, int store, int32_t* err, RunTab rt) {
+               T* __restrict__ Ekeep, const int32_t* __restrict__ flag, int store, int32_t* err, const RunTab* __restrict__ rt) {
   constexpr bool F32 = sizeof(T) == 4;
   {
     const int64_t wo = ws_off(rt);
@@ -672,7 +672,7 @@ k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict
 template <int MF, typename T>
 __global__ void __launch_bounds__(64)
 k_ds_factor(Geo g, const double* __restrict__ kap_n, T* __restrict__ Escr, const int32_t* __restrict__ list,
-            const int32_t* __restrict__ count, int32_t* err, RunTab rt) {
+            const int32_t* __restrict__ count, int32_t* err, const RunTab* __restrict__ rt) {
   __shared__ double kl[256], tE[256], tN[256], dg[256];
   {
     const int64_t wo = ws_off(rt);
@@ -732,39 +732,39 @@ void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double*
 
 void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                       const double* uym, const double* q, const double* fac, double* h, double* vbnd,
-                      LeafOut lo, const RunTab& rt) {
-  MPM_LB_DISPATCH(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, lo, rt);
+                      LeafOut lo, Runs rt) {
+  MPM_LB_DISPATCH(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, lo, rt.tab);
 }
 
 template <typename T>
 static void ds_factor_any(hipStream_t st, const Geo& g, const double* kap_n, T* Escr, const int32_t* list,
-                          const int32_t* count, int32_t* err, const RunTab& rt) {
+                          const int32_t* count, int32_t* err, Runs rt) {
   const dim3 grid(std::min(g.nsub, 1024), 1, runs_of(rt));
   if (line_mf(g) == 8)
-    hipLaunchKernelGGL((k_ds_factor<8, T>), grid, dim3(64), 0, st, g, kap_n, Escr, list, count, err, rt);
-  else hipLaunchKernelGGL((k_ds_factor<16, T>), grid, dim3(64), 0, st, g, kap_n, Escr, list, count, err, rt);
+    hipLaunchKernelGGL((k_ds_factor<8, T>), grid, dim3(64), 0, st, g, kap_n, Escr, list, count, err, rt.tab);
+  else hipLaunchKernelGGL((k_ds_factor<16, T>), grid, dim3(64), 0, st, g, kap_n, Escr, list, count, err, rt.tab);
 }
 
 void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, double* Escr, const int32_t* list,
-                      const int32_t* count, int32_t* err, const RunTab& rt) {
+                      const int32_t* count, int32_t* err, Runs rt) {
   ds_factor_any<double>(st, g, kap_n, Escr, list, count, err, rt);
 }
 
 void launch_ds_factor_f32(hipStream_t st, const Geo& g, const double* kap_n, float* Escr, const int32_t* list,
-                          const int32_t* count, int32_t* err, const RunTab& rt) {
+                          const int32_t* count, int32_t* err, Runs rt) {
   ds_factor_any<float>(st, g, kap_n, Escr, list, count, err, rt);
 }
 
 void launch_mpm_local_f32(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                           const double* uym, const double* q, const float* fac, double* h, double* vbnd,
-                          LeafOut lo, const RunTab& rt) {
-  MPM_LB_DISPATCH_F32(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, lo, rt);
+                          LeafOut lo, Runs rt) {
+  MPM_LB_DISPATCH_F32(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, lo, rt.tab);
 }
 
 void launch_downscale_f32(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
                           double* ux, double* uy, double* red_rate, double* red_qin, float* Escr, float* Ekeep,
-                          const int32_t* flag, int32_t* err, const RunTab& rt) {
-  MPM_LB_DISPATCH_F32(k_downscale_lb, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, Escr, Ekeep, flag, 0, err, rt);
+                          const int32_t* flag, int32_t* err, Runs rt) {
+  MPM_LB_DISPATCH_F32(k_downscale_lb, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, Escr, Ekeep, flag, 0, err, rt.tab);
 }
 
 __global__ void __launch_bounds__(256) k_to_f32(size_t n, const double* __restrict__ src, float* __restrict__ dst) {
@@ -779,8 +779,8 @@ void launch_to_f32(hipStream_t st, size_t n, const double* src, float* dst) {
 
 void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
                       double* ux, double* uy, double* red_rate, double* red_qin, double* Escr, double* Ekeep,
-                      const int32_t* flag, int store, int32_t* err, const RunTab& rt) {
-  MPM_LB_DISPATCH(k_downscale_lb, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, Escr, Ekeep, flag, store, err, rt);
+                      const int32_t* flag, int store, int32_t* err, Runs rt) {
+  MPM_LB_DISPATCH(k_downscale_lb, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, Escr, Ekeep, flag, store, err, rt.tab);
 }
 
 size_t line_factor_doubles(int nsub, int nc, int band) {

@@ -15,7 +15,7 @@ namespace mpm {
 __global__ void __launch_bounds__(256)
 k_kappa(Geo g, const double* __restrict__ s, const double* __restrict__ K, double* __restrict__ kap_n,
         const double* __restrict__ kap_m, double* __restrict__ red, int32_t* __restrict__ flag,
-        int32_t* __restrict__ list, int32_t* __restrict__ count, RunTab rt) {
+        int32_t* __restrict__ list, int32_t* __restrict__ count, const double* __restrict__ scal, const RunTab* __restrict__ rt) {
   __shared__ double sa[256], sb[256];
   const int64_t wo = ws_off(rt);
   s = at_off(s, wo);
@@ -26,6 +26,8 @@ k_kappa(Geo g, const double* __restrict__ s, const double* __restrict__ K, doubl
   flag = at_off(flag, wo);
   list = at_off(list, wo);
   count = at_off(count, wo);
+  scal = at_off(scal, wo);
+  const double mu_w = scal[SC_MUW], mu_o = scal[SC_MUO];
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int c = threadIdx.x;
@@ -34,7 +36,7 @@ k_kappa(Geo g, const double* __restrict__ s, const double* __restrict__ K, doubl
   if (c < g.nc) {
     const int gc = (J * g.my + c / g.mx) * g.nx + I * g.mx + c % g.mx;
     const double sv = s[gc];
-    const double lam = sv * sv / g.mu_w + (1.0 - sv) * (1.0 - sv) / g.mu_o;
+    const double lam = sv * sv / mu_w + (1.0 - sv) * (1.0 - sv) / mu_o;
     const double kn = lam * K[gc];
     kap_n[gc] = kn;
     const double km = kap_m[gc];
@@ -69,14 +71,14 @@ k_kappa(Geo g, const double* __restrict__ s, const double* __restrict__ K, doubl
 // number, for the switch decision and breakthrough checks.
 __global__ void __launch_bounds__(256) k_reduce_eps(int nblocks, const double* __restrict__ red,
                                                     double* __restrict__ scal, int32_t* __restrict__ seq,
-                                                    double* __restrict__ host, RunTab rt) {
+                                                    double* __restrict__ host, const RunTab* __restrict__ rt) {
   constexpr int B = 16;
   __shared__ double sa[256], sb[256];
   const int64_t wo = ws_off(rt);
   red = at_off(red, wo);
   scal = at_off(scal, wo);
   seq = at_off(seq, wo);
-  host = at_off(host, rt.n ? rt.host[blockIdx.z] : 0);
+  host = at_off(host, host_off(rt));
   double a = 0.0, b = 0.0;
   for (int base = 0; base < nblocks; base += 256 * B) {
     double va[B], vb[B];
@@ -120,15 +122,15 @@ __global__ void __launch_bounds__(256) k_reduce_eps(int nblocks, const double* _
 // Transport sub-step from the maximum outflow rate and the boundary inflow (fixed order).
 // Also empties the list of changed subdomains for the next velocity update.
 __global__ void __launch_bounds__(256) k_dt(int nsub, const double* __restrict__ red_rate,
-                                            const double* __restrict__ red_qin, double cfl, double fmax_deriv,
-                                            double* __restrict__ scal, int32_t* __restrict__ count, RunTab rt) {
+                                            const double* __restrict__ red_qin,
+                                            double* __restrict__ scal, int32_t* __restrict__ count, const RunTab* __restrict__ rt) {
   __shared__ double sm[256], ss[256];
   const int64_t wo = ws_off(rt);
   red_rate = at_off(red_rate, wo);
   red_qin = at_off(red_qin, wo);
   scal = at_off(scal, wo);
   count = at_off(count, wo);
-  reduce_dt(nsub, red_rate, red_qin, cfl, fmax_deriv, scal, sm, ss);
+  reduce_dt(nsub, red_rate, red_qin, scal, sm, ss);
   if (threadIdx.x == 0) *count = 0;
 }
 
@@ -140,7 +142,7 @@ __global__ void __launch_bounds__(256) k_dt(int nsub, const double* __restrict__
 __global__ void __launch_bounds__(64)
 k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, const double* __restrict__ hg,
        const double* __restrict__ vbnd, const double* __restrict__ y, const int32_t* __restrict__ sub_dofs,
-       double* __restrict__ ubnd, int with_v, RunTab rt) {
+       double* __restrict__ ubnd, int with_v, const RunTab* __restrict__ rt) {
   __shared__ double r[64];
   const int64_t wo = ws_off(rt);
   kap_m = at_off(kap_m, wo);
@@ -189,23 +191,23 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
 
 void launch_kappa(hipStream_t st, const Geo& g, const double* s, const double* K, double* kn, const double* km,
                   double* red, double* scal, int32_t* flag, int32_t* list, int32_t* count, int32_t* seq,
-                  double* host, const RunTab& rt) {
+                  double* host, Runs rt) {
   const unsigned nr = runs_of(rt);
-  hipLaunchKernelGGL(k_kappa, dim3(g.nsub, 1, nr), dim3(256), 0, st, g, s, K, kn, km, red, flag, list, count, rt);
-  hipLaunchKernelGGL(k_reduce_eps, dim3(1, 1, nr), dim3(256), 0, st, g.nsub, red, scal, seq, host, rt);
+  hipLaunchKernelGGL(k_kappa, dim3(g.nsub, 1, nr), dim3(256), 0, st, g, s, K, kn, km, red, flag, list, count, scal,
+                     rt.tab);
+  hipLaunchKernelGGL(k_reduce_eps, dim3(1, 1, nr), dim3(256), 0, st, g.nsub, red, scal, seq, host, rt.tab);
 }
 
-void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double cfl,
-               double fmax_deriv, double* scal, int32_t* count, const RunTab& rt) {
-  hipLaunchKernelGGL(k_dt, dim3(1, 1, runs_of(rt)), dim3(256), 0, st, nsub, red_rate, red_qin, cfl, fmax_deriv, scal,
-                     count, rt);
+void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double* scal,
+               int32_t* count, Runs rt) {
+  hipLaunchKernelGGL(k_dt, dim3(1, 1, runs_of(rt)), dim3(256), 0, st, nsub, red_rate, red_qin, scal, count, rt.tab);
 }
 
 void launch_flux(hipStream_t st, const Geo& g, const double* km, const double* S, const double* h,
                  const double* vbnd, const double* y, const int32_t* sub_dofs, double* ubnd, int with_v,
-                 const RunTab& rt) {
+                 Runs rt) {
   hipLaunchKernelGGL(k_flux, dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, g, km, S, h, vbnd, y, sub_dofs, ubnd,
-                     with_v, rt);
+                     with_v, rt.tab);
 }
 
 }  // namespace mpm

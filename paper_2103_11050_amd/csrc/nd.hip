@@ -228,7 +228,7 @@ __device__ __forceinline__ double ld32(const double* base, uint32_t elem) {
 // workgroup 0 of the node also stores f_I for the backward sweep. The root is not launched.
 // Rows longer than G*U (only with CH) are taken in chunks.
 template <int G, int U, int RP, bool CH>
-__global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a0, int loff, RunTab rt) {
+__global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a0, int loff, const RunTab* __restrict__ rt) {
   const NdArgs a = nd_at(a0, ws_off(rt));
   constexpr int RPP = 256 / G, RPB = RP * RPP;
   const NodeDev nd = a.lnodes[loff + blockIdx.y];
@@ -393,17 +393,17 @@ static RbShape rb_shape(int len) {
   } while (0)
 
 void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nBmax,
-                         const RunTab& rt) {
+                         Runs rt) {
   const RbShape sh = rb_shape(nImax);
-  ND_RB_LAUNCH(k_nd_fwd_rb, sh, nBmax, nnodes, runs_of(rt), st, a, loff, rt);
+  ND_RB_LAUNCH(k_nd_fwd_rb, sh, nBmax, nnodes, runs_of(rt), st, a, loff, rt.tab);
 }
 
 template <int G, int U, int RP, bool CH>
-__global__ void __launch_bounds__(256) k_nd_bwd_inner(NdArgs a, int loff, RunTab rt) {
+__global__ void __launch_bounds__(256) k_nd_bwd_inner(NdArgs a, int loff, const RunTab* __restrict__ rt) {
   k_nd_bwd_body<G, U, RP, CH, false>(nd_at(a, ws_off(rt)), loff);
 }
 template <int G, int U, int RP, bool CH>
-__global__ void __launch_bounds__(256) k_nd_bwd_root(NdArgs a, int loff, RunTab rt) {
+__global__ void __launch_bounds__(256) k_nd_bwd_root(NdArgs a, int loff, const RunTab* __restrict__ rt) {
   k_nd_bwd_body<G, U, RP, CH, true>(nd_at(a, ws_off(rt)), loff);
 }
 
@@ -416,10 +416,10 @@ static RbShape rb_shape_bwd(int len) {
 }
 
 void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nmax, int root,
-                         const RunTab& rt) {
+                         Runs rt) {
   const RbShape sh = rb_shape_bwd(nmax);
-  if (root) ND_RB_LAUNCH(k_nd_bwd_root, sh, nImax, nnodes, runs_of(rt), st, a, loff, rt);
-  else ND_RB_LAUNCH(k_nd_bwd_inner, sh, nImax, nnodes, runs_of(rt), st, a, loff, rt);
+  if (root) ND_RB_LAUNCH(k_nd_bwd_root, sh, nImax, nnodes, runs_of(rt), st, a, loff, rt.tab);
+  else ND_RB_LAUNCH(k_nd_bwd_inner, sh, nImax, nnodes, runs_of(rt), st, a, loff, rt.tab);
 }
 
 }  // namespace mpm

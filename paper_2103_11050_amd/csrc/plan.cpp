@@ -268,6 +268,7 @@ void build_plan(const mpm_desc& d, Plan* p) {
   P.n_red = 4 * blocks;
   P.off_red = take(P.n_red * 8);
   P.off_scal = take(SC_COUNT * 8 + 64);
+  P.off_rtab = take(2 * sizeof(RunTab));
   P.total_bytes = off;
 }
 

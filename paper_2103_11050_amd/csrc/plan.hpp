@@ -45,6 +45,16 @@ struct LeafUp {
   int32_t pad;
 };
 
+// Runs of one batch that share their decomposition step through one launch per phase:
+// blockIdx.z selects the run, whose workspace (and pinned host block) sits at a byte offset
+// from the first run's; the launch carries the first run's pointers and this table, which
+// lives in the first run's workspace.
+constexpr int MPM_GROUP_MAX = 128;
+struct RunTab {
+  int64_t ws[MPM_GROUP_MAX];
+  int64_t host[MPM_GROUP_MAX];
+};
+
 struct Plan {
   mpm_desc d;
   int nx, ny, mx, my, Sx, Sy, nsub;
@@ -85,6 +95,7 @@ struct Plan {
   size_t off_dsflag = 0;              // per subdomain: conductivity changed since the last update
   size_t off_dslist = 0;              // the changed subdomains (count in the integer word after the error word)
   size_t off_red, off_scal;
+  size_t off_rtab = 0;                // two run tables (batch groups led by this run)
   size_t n_red;               // doubles in the reduction scratch
   size_t total_bytes;
   int64_t front_doubles = 0, panel_doubles = 0, fI_doubles = 0, slot_doubles = 0;
@@ -105,6 +116,13 @@ enum Scalar : int {
   SC_PVI,
   SC_WCUT,
   SC_MAXRATE,
+  // per-run physics read by the kernels (set by mpm_start), so that runs of one batch group
+  // may differ in them
+  SC_MUW,           // water viscosity
+  SC_MUO,           // oil viscosity
+  SC_MRATIO,        // M = mu_o / mu_w
+  SC_CFL,           // fraction of the monotone time-step bound
+  SC_FMAX,          // max over [0, 1] of the fractional-flow derivative
   SC_COUNT = 16
 };
 

@@ -21,7 +21,7 @@ __device__ __forceinline__ double fracflow(double s, double M) {
 // s2 = s - dt/|c| sum_f |f| u_f f(s_upwind); the injected saturation on inflow boundary faces.
 __global__ void __launch_bounds__(256)
 k_sat_step(Geo g, const double* __restrict__ s, double* __restrict__ s2, const double* __restrict__ ux,
-           const double* __restrict__ uy, double* __restrict__ scal, double M, double area, RunTab rt) {
+           const double* __restrict__ uy, double* __restrict__ scal, double area, const RunTab* __restrict__ rt) {
   {
     const int64_t wo = ws_off(rt);
     s = at_off(s, wo);
@@ -33,6 +33,7 @@ k_sat_step(Geo g, const double* __restrict__ s, double* __restrict__ s2, const d
   const int gi = blockIdx.x * 64 + (threadIdx.x & 63);
   const int gj = blockIdx.y * 4 + (threadIdx.x >> 6);
   const double dt = scal[SC_DT];
+  const double M = scal[SC_MRATIO];
   if (gi < g.nx && gj < g.ny) {
     const int c = gj * g.nx + gi;
     const double sc = s[c];
@@ -60,7 +61,7 @@ k_sat_step(Geo g, const double* __restrict__ s, double* __restrict__ s2, const d
 // issued in batches of 16 per thread).
 __global__ void __launch_bounds__(256)
 k_water_cut(Geo g, const double* __restrict__ s, const double* __restrict__ ux, const double* __restrict__ uy,
-            double* __restrict__ scal, double M, RunTab rt) {
+            double* __restrict__ scal, const RunTab* __restrict__ rt) {
   {
     const int64_t wo = ws_off(rt);
     s = at_off(s, wo);
@@ -68,6 +69,7 @@ k_water_cut(Geo g, const double* __restrict__ s, const double* __restrict__ ux, 
     uy = at_off(uy, wo);
     scal = at_off(scal, wo);
   }
+  const double M = scal[SC_MRATIO];
   constexpr int B = 16;
   __shared__ double sq[256], sw[256];
   double q = 0.0, w = 0.0;
@@ -114,14 +116,14 @@ k_water_cut(Geo g, const double* __restrict__ s, const double* __restrict__ ux, 
 }
 
 void launch_sat_step(hipStream_t st, const Geo& g, const double* s, double* s2, const double* ux,
-                     const double* uy, double* scal, double M, double area, const RunTab& rt) {
+                     const double* uy, double* scal, double area, Runs rt) {
   dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, runs_of(rt));
-  hipLaunchKernelGGL(k_sat_step, grid, dim3(256), 0, st, g, s, s2, ux, uy, scal, M, area, rt);
+  hipLaunchKernelGGL(k_sat_step, grid, dim3(256), 0, st, g, s, s2, ux, uy, scal, area, rt.tab);
 }
 
 void launch_water_cut(hipStream_t st, const Geo& g, const double* s, const double* ux, const double* uy,
-                      double* scal, double M, const RunTab& rt) {
-  hipLaunchKernelGGL(k_water_cut, dim3(1, 1, runs_of(rt)), dim3(256), 0, st, g, s, ux, uy, scal, M, rt);
+                      double* scal, Runs rt) {
+  hipLaunchKernelGGL(k_water_cut, dim3(1, 1, runs_of(rt)), dim3(256), 0, st, g, s, ux, uy, scal, rt.tab);
 }
 
 }  // namespace mpm

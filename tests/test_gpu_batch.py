@@ -183,14 +183,15 @@ def test_served_equals_alone(binding):
         r.close()
 
 
-# Runs with equal descriptors (only the permeability differs) step as one group: one launch per
-# phase for all of them. Group A mixes MRCM and MPM-2P updates in the same step (small eta),
+# Runs with equal decompositions step as one group: one launch per phase for all of them; the
+# permeability, viscosities, cfl, eta and the epsilon norm may differ inside a group. Group A
+# mixes MRCM and MPM-2P updates in the same step (small eta) and differs in those parameters,
 # group B uses the text switch rule, group C the precision form; one run steps alone.
 GROUPED = [
     # (seed, nx, ny, sub, ne, overrides, precision)
     (201, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=20.0, eta=0.01), 0),
-    (202, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=20.0, eta=0.01), 0),
-    (203, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=20.0, eta=0.01), 0),
+    (202, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=35.0, eta=0.02, eps_norm="abs"), 0),
+    (203, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=20.0, eta=0.01, cfl=0.4), 0),
     (204, 64, 48, 16, 4, dict(sigma2=3.0, corr_len=0.1, mu_o=50.0, eta=0.05, switch_rule="text"), 0),
     (205, 64, 48, 16, 4, dict(sigma2=3.0, corr_len=0.1, mu_o=50.0, eta=0.05, switch_rule="text"), 0),
     (206, 48, 32, 16, 4, dict(sigma2=2.0, corr_len=0.2, mu_o=30.0, eta=0.03), 1),
