@@ -74,12 +74,6 @@ __device__ __forceinline__ int gcell3(const Geo& g, int I, int J, int i, int j) 
   return (J * g.my + j) * g.nx + I * g.mx + i;
 }
 
-// Restriction B^T of boundary-face quantities to local interface unknowns:
-// U unknown: -sgn beta_f on the element's faces; P unknown: 1.
-__device__ __forceinline__ double bweight(const Geo& g, const BFace& f, bool is_p, double kc) {
-  return is_p ? 1.0 : -f.sgn * robin_beta(g, f, kc);
-}
-
 // One wavefront per subdomain. Writes S (nb x nb, row-major per subdomain), h, the interface
 // block K_i = B^T S B - D_i with its right-hand side B^T h (eq:mrc2 with the Robin rows
 // negated; the right-hand side goes into the parent's slot of the interface solve), and, with
@@ -110,18 +104,7 @@ k_basis_mfma(Geo g, const double* __restrict__ kap, const double* __restrict__ q
   for (int c = lane; c < g.nc; c += 64) {
     int i, j;
     loc_ij(g, c, &i, &j);
-    const double kc = kl[c];
-    double r = g.hx * g.hy * q[gcell3(g, I, J, i, j)];
-    for (int t = 0; t < 4; ++t) {
-      const bool on = (t == 0 && i == 0) || (t == 1 && i == g.mx - 1) || (t == 2 && j == 0) ||
-                      (t == 3 && j == g.my - 1);
-      if (!on) continue;
-      const int fi = t == 0 ? j : t == 1 ? g.my + j : t == 2 ? 2 * g.my + i : 2 * g.my + g.mx + i;
-      const BFace f = bface(g, I, J, fi);
-      if (f.kind == FACE_DIR) r += f.flen * bface_trans(g, f, kc) * f.value;
-      if (f.kind == FACE_NEU) r -= f.flen * f.value;
-    }
-    rhs0[c] = r;
+    rhs0[c] = basis_rhs0(g, I, J, c, kl, q[gcell3(g, I, J, i, j)]);
   }
   if (lane < nb) {
     const BFace f = bface(g, I, J, lane);
@@ -247,45 +230,7 @@ k_basis_mfma(Geo g, const double* __restrict__ kap, const double* __restrict__ q
   __syncthreads();
 
   // interface block K_i = B^T S B - D_i and right-hand side B^T h (Gamma faces only)
-  const int nd = sub_ndof(g, I, J);
-  double* Ks = leafK + size_t(sub) * g.ndmax * g.ndmax;
-  for (int p = lane; p < nd * nd; p += 64) {
-    const int a = p / nd, c2 = p % nd;
-    int fa, na, fb, nbb;
-    dof_faces(g, I, J, a, &fa, &na);
-    dof_faces(g, I, J, c2, &fb, &nbb);
-    const bool pa = a & 1, pb = c2 & 1;
-    double v = 0.0;
-    for (int x = fa; x < fa + na; ++x) {
-      const BFace ff = bface(g, I, J, x);
-      const double wa = bweight(g, ff, pa, kl[loc_index(g, ff.i, ff.j)]);
-      double sacc = 0.0;
-      for (int y = fb; y < fb + nbb; ++y) {
-        const BFace fgb = bface(g, I, J, y);
-        sacc += Ss[x * nb + y] * bweight(g, fgb, pb, kl[loc_index(g, fgb.i, fgb.j)]);
-      }
-      v += wa * sacc;
-    }
-    if (a == c2 && !pa) {
-      double dsum = 0.0;
-      for (int x = fa; x < fa + na; ++x) {
-        const BFace ff = bface(g, I, J, x);
-        dsum += ff.flen * robin_beta(g, ff, kl[loc_index(g, ff.i, ff.j)]);
-      }
-      v -= dsum;
-    }
-    Ks[a * nd + c2] = v;
-  }
-  for (int a = lane; a < nd; a += 64) {
-    int fa, na;
-    dof_faces(g, I, J, a, &fa, &na);
-    double v = 0.0;
-    for (int x = fa; x < fa + na; ++x) {
-      const BFace ff = bface(g, I, J, x);
-      v += bweight(g, ff, a & 1, kl[loc_index(g, ff.i, ff.j)]) * hsh[x];
-    }
-    leaf_out(lo, sub, a, v);
-  }
+  basis_iface_block(g, I, J, sub, kl, Ss, hsh, leafK, lo);
 }
 
 }  // namespace
@@ -293,6 +238,10 @@ k_basis_mfma(Geo g, const double* __restrict__ kap, const double* __restrict__ q
 // Returns whether the kappa^m line-block inverses were written (lines of 9..16 cells).
 bool launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
                   double* leafK, LeafOut lo, double* fac, int32_t* err) {
+  if (g.nc / g.band > 16) {   // more lines than the matrix-core column blocks take
+    launch_basis_lines(st, g, kap, q, S, h, leafK, lo, fac, err);
+    return true;
+  }
   const int store = g.band > 8 ? 1 : 0;
   hipLaunchKernelGGL(k_basis_mfma, dim3(g.nsub), dim3(64), 0, st, g, kap, q, S, h, leafK, lo, fac, store, err);
   return store != 0;

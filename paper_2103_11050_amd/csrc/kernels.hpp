@@ -51,6 +51,10 @@ void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* r
 bool launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
                   double* leafK, LeafOut lo, double* fac, int32_t* err);
 // lines.hip
+// The same basis for subdomains of more than 16 lines, by one line-block solve per boundary
+// face; always writes the inverse blocks.
+void launch_basis_lines(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
+                        double* leafK, LeafOut lo, double* fac, int32_t* err);
 void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double* fac, int32_t* err);
 size_t line_factor_doubles(int nsub, int nc, int band);
 void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,

@@ -53,15 +53,17 @@ __device__ __forceinline__ void lb_factor(const Geo& g, const LineW& W, const LB
   }
 }
 
-// x (LDS, local order) holds the right-hand side on entry and the solution on exit; w is LDS
-// scratch of nl*MF doubles; Es holds the block inverses as written by lb_factor.
+// x (LDS, local order) holds the right-hand side on entry and the solution on exit (the forward
+// result w_ln overwrites line ln of the right-hand side, which the row's lanes read before they
+// write it); Es holds the block inverses as written by lb_factor. Any line count.
 template <int MF>
-__device__ __forceinline__ void lb_solve(const Geo& g, const LineW& W, const LB<MF>& L, const double* Es, double* x,
-                                         double* w) {
+__device__ __forceinline__ void lb_solve(const Geo& g, const LineW& W, const LB<MF>& L, const double* Es, double* x) {
   constexpr int EPL = LB<MF>::EPL;
   const int nl = g.nc / g.band;
   const int len = g.band;
   const bool rin = L.row < len;
+  const bool wr = rin && L.cg == 0;
+  const int xr = rin ? L.row : 0;
   // the next line's block is loaded while the current one is applied
   double e[EPL], en[EPL];
 #pragma unroll
@@ -72,15 +74,14 @@ __device__ __forceinline__ void lb_solve(const Geo& g, const LineW& W, const LB<
     const int lnn = ln + 1 < nl ? ln + 1 : ln;
 #pragma unroll
     for (int t = 0; t < EPL; ++t) en[t] = Es[(size_t(lnn) * EPL + t) * 64 + L.lane];
-    double z = rin ? x[ln * len + L.row] : 0.0;
-    if (ln > 0 && rin) z += W.y(ln - 1, L.row) * wprev;
+    double z = rin ? x[ln * len + xr] : 0.0;
+    if (ln > 0 && rin) z += W.y(ln - 1, xr) * wprev;
     wprev = lb_matvec<MF>(L, e, z);
-    if (L.cg == 0) w[ln * MF + L.row] = wprev;
+    if (wr) x[ln * len + xr] = wprev;
 #pragma unroll
     for (int t = 0; t < EPL; ++t) e[t] = en[t];
   }
-  double xnext = wprev;
-  if (rin && L.cg == 0) x[(nl - 1) * len + L.row] = xnext;
+  double xnext = wprev;   // line nl - 1 holds its solution already
   if (nl >= 2) {
 #pragma unroll
     for (int t = 0; t < EPL; ++t) e[t] = Es[(size_t(nl - 2) * EPL + t) * 64 + L.lane];
@@ -90,9 +91,9 @@ __device__ __forceinline__ void lb_solve(const Geo& g, const LineW& W, const LB<
     const int lnn = ln > 0 ? ln - 1 : 0;
 #pragma unroll
     for (int t = 0; t < EPL; ++t) en[t] = Es[(size_t(lnn) * EPL + t) * 64 + L.lane];
-    const double v = rin ? W.y(ln, L.row) * xnext : 0.0;
-    xnext = w[ln * MF + L.row] + lb_matvec<MF>(L, e, v);
-    if (rin && L.cg == 0) x[ln * len + L.row] = xnext;
+    const double v = rin ? W.y(ln, xr) * xnext : 0.0;
+    xnext = (rin ? x[ln * len + xr] : 0.0) + lb_matvec<MF>(L, e, v);
+    if (wr) x[ln * len + xr] = xnext;
 #pragma unroll
     for (int t = 0; t < EPL; ++t) e[t] = en[t];
   }
@@ -133,38 +134,6 @@ __device__ __forceinline__ void lb_solve_regs(const LineW& W, const LB<MF>& L, c
     if (rin && L.cg == 0) x[ln * len + L.row] = xnext;
   }
   __syncthreads();
-}
-
-template <int MF, int NL>
-__device__ __forceinline__ void lb_solve_reg(const LineW& W, const LB<MF>& L, const double* Es, double* x) {
-  constexpr int EPL = LB<MF>::EPL;
-  const int len = W.band;
-  const bool rin = L.row < len;
-  double E[NL][EPL];
-  lb_load_reg<MF, NL>(L, Es, E);
-  double w[NL];
-#pragma unroll
-  for (int ln = 0; ln < NL; ++ln) {
-    double z = rin ? x[ln * len + L.row] : 0.0;
-    if (ln > 0 && rin) z += W.y(ln - 1, L.row) * w[ln - 1];
-    w[ln] = lb_matvec<MF>(L, E[ln], z);
-  }
-  double xnext = w[NL - 1];
-  if (rin && L.cg == 0) x[(NL - 1) * len + L.row] = xnext;
-#pragma unroll
-  for (int ln = NL - 2; ln >= 0; --ln) {
-    const double v = rin ? W.y(ln, L.row) * xnext : 0.0;
-    xnext = w[ln] + lb_matvec<MF>(L, E[ln], v);
-    if (rin && L.cg == 0) x[ln * len + L.row] = xnext;
-  }
-  __syncthreads();
-}
-
-template <int MF, int NL>
-__device__ __forceinline__ void lb_solve_any(const Geo& g, const LineW& W, const LB<MF>& L, const double* Es,
-                                             double* x, double* w) {
-  if constexpr (NL > 0) lb_solve_reg<MF, NL>(W, L, Es, x);
-  else lb_solve<MF>(g, W, L, Es, x, w);
 }
 
 // ------------------------------------------------------------------ FP32 blocks, FP64 refinement
@@ -297,6 +266,69 @@ __global__ void __launch_bounds__(64) k_line_factor(Geo g, const double* __restr
   bool ok = true;
   lb_factor<MF>(g, W, L, fac + efac_off<MF>(g, sub, 0, 0), ok);
   if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
+}
+
+// ---------------------------------------------------------------------------------------------
+// MRCM basis (eq:mrc_homogeneous, eq:mrc_non_homogeneous) of a subdomain with more lines than
+// the matrix-core kernel takes: the line-block inverses of the local Robin matrix A of
+// kappa^m (kept for MPM-2P), then A^-1 applied to the unit vector of each boundary face's
+// cell, which gives column f of the Robin-to-flux map S = W T - W T (E^T A^-1 E) W T, and to the
+// non-homogeneous right-hand side r0, which gives the boundary fluxes h = W T (E^T A^-1 r0 - r_D);
+// then the interface block and its right-hand side. One wavefront per subdomain.
+template <int MF>
+__global__ void __launch_bounds__(64) k_basis_lines(Geo g, const double* __restrict__ kap,
+                                                    const double* __restrict__ q, double* __restrict__ Sg,
+                                                    double* __restrict__ hg, double* __restrict__ leafK, LeafOut lo,
+                                                    double* __restrict__ fac, int32_t* err) {
+  __shared__ double kl[256], tE[256], tN[256], dg[256], x[256], wsh[64], hsh[64];
+  const int sub = blockIdx.x;
+  const int I = sub % g.Sx, J = sub / g.Sx;
+  const int n = g.nc, nb = g.nb;
+  load_tile2(g, I, J, kap, kl);
+  __syncthreads();
+  fill_trans(g, I, J, kl, 0, tE, tN, dg);
+  const LineW W{tE, tN, dg, g.xfast, g.band, 0};
+  LB<MF> L;
+  double* Es = fac + efac_off<MF>(g, sub, 0, 0);
+  bool ok = true;
+  lb_factor<MF>(g, W, L, Es, ok);   // each lane reads back only the entries it wrote
+  if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
+  if (threadIdx.x < nb) {
+    const BFace f = bface(g, I, J, threadIdx.x);
+    wsh[threadIdx.x] = f.flen * bface_trans(g, f, kl[loc_index(g, f.i, f.j)]);
+  }
+  for (int c = threadIdx.x; c < n; c += 64) {
+    int i, j;
+    loc_ij(g, c, &i, &j);
+    x[c] = basis_rhs0(g, I, J, c, kl, q[gcell2(g, I, J, i, j)]);
+  }
+  __syncthreads();
+  lb_solve<MF>(g, W, L, Es, x);
+  if (threadIdx.x < nb) {
+    const int f = threadIdx.x;
+    const BFace bf = bface(g, I, J, f);
+    const double rD = bf.kind == FACE_DIR ? bf.value : 0.0;
+    const double h = bf.kind == FACE_NEU ? 0.0 : wsh[f] * (x[loc_index(g, bf.i, bf.j)] - rD);
+    hsh[f] = h;
+    hg[size_t(sub) * nb + f] = h;
+  }
+  double* Ss = Sg + size_t(sub) * nb * nb;
+#pragma unroll 1
+  for (int f = 0; f < nb; ++f) {
+    __syncthreads();
+    const BFace bf = bface(g, I, J, f);
+    const int cf = loc_index(g, bf.i, bf.j);
+    for (int c = threadIdx.x; c < n; c += 64) x[c] = c == cf ? 1.0 : 0.0;
+    __syncthreads();
+    lb_solve<MF>(g, W, L, Es, x);
+    if (threadIdx.x < nb) {
+      const int fr = threadIdx.x;
+      const BFace br = bface(g, I, J, fr);
+      Ss[fr * nb + f] = (fr == f ? wsh[f] : 0.0) - wsh[fr] * x[loc_index(g, br.i, br.j)] * wsh[f];
+    }
+  }
+  __syncthreads();
+  basis_iface_block(g, I, J, sub, kl, Ss, hsh, leafK, lo);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -502,7 +534,7 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
   } else {
     const LineW W{ty, ty, nullptr, g.xfast, g.band, 0};
     if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
-    else lb_solve<MF>(g, W, L, Es, x, uys);
+    else lb_solve<MF>(g, W, L, Es, x);
   }
   double* hsh = uys;
   for (int f = threadIdx.x; f < nb; f += 64) {
@@ -558,7 +590,7 @@ k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict
   }
   // the conductivity tile is dead once the weights are built and then holds the solution
   __shared__ double kl[256], w[64], tE[256], tN[256], dg[256];
-  __shared__ double wsh[F32 ? 768 : (NL > 0 ? 1 : 256)];
+  __shared__ double wsh[F32 ? 768 : 1];
   double* x = kl;
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
@@ -622,7 +654,7 @@ k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict
       if constexpr (NL > 0) lb_load_reg<MF, NL>(L, Es, E);
     }
     if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
-    else lb_solve<MF>(g, W, L, Es, x, wsh);
+    else lb_solve<MF>(g, W, L, Es, x);
   }
   double rate = 0.0;
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
@@ -703,6 +735,13 @@ k_ds_factor(Geo g, const double* __restrict__ kap_n, T* __restrict__ Escr, const
 // ---------------------------------------------------------------------------------------------
 
 static int line_mf(const Geo& g) { return g.band <= 8 ? 8 : 16; }
+
+void launch_basis_lines(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
+                        double* leafK, LeafOut lo, double* fac, int32_t* err) {
+  if (line_mf(g) == 8)
+    hipLaunchKernelGGL(k_basis_lines<8>, dim3(g.nsub), dim3(64), 0, st, g, kap, q, S, h, leafK, lo, fac, err);
+  else hipLaunchKernelGGL(k_basis_lines<16>, dim3(g.nsub), dim3(64), 0, st, g, kap, q, S, h, leafK, lo, fac, err);
+}
 
 void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double* fac, int32_t* err) {
   if (line_mf(g) == 8) hipLaunchKernelGGL(k_line_factor<8>, dim3(g.nsub), dim3(64), 0, st, g, kap, fac, err);

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
+#include "kernels.hpp"
 
 namespace mpm {
 
@@ -238,6 +239,80 @@ __device__ __forceinline__ void lb_block(const LineW& W, int ln, const LB<MF, IL
     if (!rin || c >= len) v = (c == r) ? 1.0 : 0.0;
     a[t] = v;
   }
+}
+
+// Restriction B^T of boundary-face quantities to local interface unknowns:
+// U unknown: -sgn beta_f on the element's faces; P unknown: 1.
+__device__ __forceinline__ double bweight(const Geo& g, const BFace& f, bool is_p, double kc) {
+  return is_p ? 1.0 : -f.sgn * robin_beta(g, f, kc);
+}
+
+// From the Robin-to-flux map S (nb x nb, global) and the boundary fluxes h (LDS) of a
+// subdomain: its interface block K_i = B^T S B - D_i (eq:mrc2 with the Robin rows negated)
+// and the right-hand side B^T h, written into the parent's slot. kl: kappa in local order.
+// One wavefront; S must be visible to all lanes (barrier before the call).
+__device__ __forceinline__ void basis_iface_block(const Geo& g, int I, int J, int sub, const double* kl,
+                                                  const double* Ss, const double* hsh, double* leafK,
+                                                  const LeafOut& lo) {
+  const int nb = g.nb;
+  const int nd = sub_ndof(g, I, J);
+  double* Ks = leafK + size_t(sub) * g.ndmax * g.ndmax;
+  for (int p = threadIdx.x; p < nd * nd; p += 64) {
+    const int a = p / nd, c2 = p % nd;
+    int fa, na, fb, nbb;
+    dof_faces(g, I, J, a, &fa, &na);
+    dof_faces(g, I, J, c2, &fb, &nbb);
+    const bool pa = a & 1, pb = c2 & 1;
+    double v = 0.0;
+    for (int x = fa; x < fa + na; ++x) {
+      const BFace ff = bface(g, I, J, x);
+      const double wa = bweight(g, ff, pa, kl[loc_index(g, ff.i, ff.j)]);
+      double sacc = 0.0;
+      for (int y = fb; y < fb + nbb; ++y) {
+        const BFace fgb = bface(g, I, J, y);
+        sacc += Ss[x * nb + y] * bweight(g, fgb, pb, kl[loc_index(g, fgb.i, fgb.j)]);
+      }
+      v += wa * sacc;
+    }
+    if (a == c2 && !pa) {
+      double dsum = 0.0;
+      for (int x = fa; x < fa + na; ++x) {
+        const BFace ff = bface(g, I, J, x);
+        dsum += ff.flen * robin_beta(g, ff, kl[loc_index(g, ff.i, ff.j)]);
+      }
+      v -= dsum;
+    }
+    Ks[a * nd + c2] = v;
+  }
+  for (int a = threadIdx.x; a < nd; a += 64) {
+    int fa, na;
+    dof_faces(g, I, J, a, &fa, &na);
+    double v = 0.0;
+    for (int x = fa; x < fa + na; ++x) {
+      const BFace ff = bface(g, I, J, x);
+      v += bweight(g, ff, a & 1, kl[loc_index(g, ff.i, ff.j)]) * hsh[x];
+    }
+    leaf_out(lo, sub, a, v);
+  }
+}
+
+// Right-hand side of the non-homogeneous local problem (eq:mrc_non_homogeneous, Robin datum 0)
+// at local cell c: |c| q + sum_DIR |f| t g - sum_NEU |f| z.
+__device__ __forceinline__ double basis_rhs0(const Geo& g, int I, int J, int c, const double* kl, double qc) {
+  int i, j;
+  loc_ij(g, c, &i, &j);
+  const double kc = kl[c];
+  double r = g.hx * g.hy * qc;
+  for (int t = 0; t < 4; ++t) {
+    const bool on = (t == 0 && i == 0) || (t == 1 && i == g.mx - 1) || (t == 2 && j == 0) ||
+                    (t == 3 && j == g.my - 1);
+    if (!on) continue;
+    const int fi = t == 0 ? j : t == 1 ? g.my + j : t == 2 ? 2 * g.my + i : 2 * g.my + g.mx + i;
+    const BFace f = bface(g, I, J, fi);
+    if (f.kind == FACE_DIR) r += f.flen * bface_trans(g, f, kc) * f.value;
+    if (f.kind == FACE_NEU) r -= f.flen * f.value;
+  }
+  return r;
 }
 
 }  // namespace mpm

@@ -52,7 +52,15 @@ mpm_status validate(const mpm_desc& d, std::string* why) {
   const int band = std::min(d.sub_x, d.sub_y);
   const long nc = long(d.sub_x) * d.sub_y;
   if (nc * (band + 1) * 8 > 64 * 1024) return bad("subdomain too large for the local factorisation (band storage > 64 KiB)");
-  if (d.sub_x > 16 || d.sub_y > 16) return bad("subdomain sides longer than 16 cells are not supported");
+  // local kernels: lines of at most 16 cells, at most 256 cells, 64 boundary faces and 272
+  // faces of each direction per subdomain (one wavefront, fixed LDS tiles)
+  if (band > 16) return bad("subdomains whose shorter side exceeds 16 cells are not supported");
+  if (nc > 256) return bad("more than 256 cells per subdomain");
+  if (d.sub_x + d.sub_y > 32) return bad("more than 64 boundary faces per subdomain");
+  if (long(d.sub_y) * (d.sub_x + 1) > 272 || long(d.sub_y + 1) * d.sub_x > 272)
+    return bad("more than 272 faces of one direction per subdomain");
+  if (d.precision == MPM_PREC_FP32_REFINE && nc / band > 16)
+    return bad("the precision form takes at most 16 lines per subdomain");
   if (2 * (2 * d.ne_x + 2 * d.ne_y) > 128) return bad("more than 128 interface unknowns per subdomain");
   return MPM_OK;
 }

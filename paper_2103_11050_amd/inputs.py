@@ -92,7 +92,10 @@ def self_similar_field(nx: int, ny: int, lx: float, ly: float, seed: int, beta: 
 def permeability(cfg: dict) -> np.ndarray:
     """Permeability of a workload, shape (ny, nx): log-normal K = exp(sqrt(sigma2) xi) with
     Gaussian covariance, or (field = "self_similar") K = k0 exp(delta xi) with xi the
-    self-similar field scaled to the range ln(contrast) / delta."""
+    self-similar field scaled to the range ln(contrast) / delta, or (field = "homogeneous")
+    K = k0."""
+    if cfg.get("field") == "homogeneous":
+        return np.full((cfg["ny"], cfg["nx"]), float(cfg["k0"]))
     if cfg.get("field") == "self_similar":
         xi = self_similar_field(cfg["nx"], cfg["ny"], cfg["lx"], cfg["ly"], cfg["seed"])
         return cfg["k0"] * np.exp(np.log(cfg["contrast"]) * xi)
@@ -113,9 +116,35 @@ def x1_config(contrast: float = 1e3, ne: int = 1, cn: int = 1, eta: float = 1e-2
     return cfg
 
 
+def x4_config(eta: float = 1e-2, cn: int = 1, steps: int = 2000) -> dict:
+    """Water-oil finger growth in a homogeneous medium (the last experiment of Section 5):
+    [0,3] x [0,1/2] with 300 x 50 cells in 15 x 5 subdomains of 20 x 10, K = 1, M = 4, p = 0 on
+    the left and -1e4 on the right, no flow on the bottom and top, no sources, water (s-bar =
+    1) entering on the left; MRCM with H-bar = h (one fine face per interface element: 20 and
+    10 elements per side) for the basis updates, eta = 1e-2, C_n = 1, T_e = 2000. The initial
+    water-oil front with a small perturbation at the channel centre is a reading (the paper
+    shows it only in a figure): s0 = 1 on the cells with centre x < 0.1, and x < 0.15 for
+    |y - 1/4| < 0.05; s0 = 0 elsewhere."""
+    cfg = dict(_BASE, lx=3.0, ly=0.5, nx=300, ny=50, sub_x=20, sub_y=10, ne_x=20, ne_y=10, mu_w=1.0, mu_o=4.0,
+               eta=eta, cn=cn, field="homogeneous", k0=1.0, seed=0, steps=steps,
+               s0="perturbed_front", front_x=0.1, bump_x=0.05, bump_half_width=0.05)
+    cfg["bc_kind"] = [PRESSURE, PRESSURE, NOFLOW, NOFLOW]
+    cfg["bc_value"] = [0.0, -1.0e4, 0.0, 0.0]
+    return cfg
+
+
 def initial_saturation(cfg: dict) -> np.ndarray:
-    """Reservoir initially filled with oil: s0 = 0 everywhere."""
-    return np.zeros((cfg["ny"], cfg["nx"]))
+    """Reservoir initially filled with oil (s0 = 0 everywhere), or (s0 = "perturbed_front") water
+    on the cells whose centre lies left of front_x, and left of front_x + bump_x within
+    bump_half_width of the channel's mid-line."""
+    s = np.zeros((cfg["ny"], cfg["nx"]))
+    if cfg.get("s0") == "perturbed_front":
+        xc = (np.arange(cfg["nx"]) + 0.5) * cfg["lx"] / cfg["nx"]
+        yc = (np.arange(cfg["ny"]) + 0.5) * cfg["ly"] / cfg["ny"]
+        bump = np.abs(yc - 0.5 * cfg["ly"]) < cfg["bump_half_width"]
+        reach = cfg["front_x"] + np.where(bump, cfg["bump_x"], 0.0)
+        s[xc[None, :] < reach[:, None]] = 1.0
+    return s
 
 
 def source(cfg: dict) -> np.ndarray:

@@ -66,10 +66,29 @@ def test_no_pressure_boundary_rejected(lib):
     assert st == binding.MPM_EINVAL
 
 
-def test_oversized_subdomain_rejected(lib):
-    cfg = inputs.config("c1", nx=40, ny=40, sub_x=20, sub_y=10, ne_x=4, ne_y=2)
+@pytest.mark.parametrize("shape", [
+    (34, 34, 17, 17, 1, 1),     # lines longer than 16 cells
+    (48, 20, 24, 10, 4, 2),     # 240 cells but sides summing past 32 (boundary faces > 64)
+    (64, 32, 32, 8, 4, 2),      # x-faces of a tile past 272
+    (40, 40, 20, 20, 4, 4),     # shorter side 20
+])
+def test_oversized_subdomain_rejected(lib, shape):
+    nx, ny, mx, my, nex, ney = shape
+    cfg = inputs.config("c1", nx=nx, ny=ny, sub_x=mx, sub_y=my, ne_x=nex, ne_y=ney)
     st, _ = _size(cfg)
     assert st == binding.MPM_EINVAL
+
+
+@pytest.mark.parametrize("shape", [(40, 20, 20, 10, 20, 10), (48, 16, 24, 8, 4, 2), (20, 40, 10, 20, 5, 4)])
+def test_many_line_subdomains_accepted(lib, shape):
+    """Subdomains with more than 16 lines (the longer side up to 32 cells, at most 256 cells)
+    are taken in FP64; the precision form keeps at most 16 lines."""
+    nx, ny, mx, my, nex, ney = shape
+    cfg = inputs.config("c1", nx=nx, ny=ny, sub_x=mx, sub_y=my, ne_x=nex, ne_y=ney)
+    st, size = _size(cfg)
+    assert st == 0 and size > 0
+    st32, _ = _size(cfg, precision=binding.PREC_FP32_REFINE)
+    assert st32 == binding.MPM_EINVAL
 
 
 def test_eta_infinity_accepted(lib):

@@ -47,6 +47,10 @@ SHAPES = [
     (12, 12, 4, 4, 4, 4),       # one fine face per interface element
     (30, 20, 10, 10, 5, 2),     # 3 x 2 subdomains, ragged tree
     (40, 24, 8, 8, 2, 2),       # 5 x 3 subdomains
+    (40, 20, 20, 10, 20, 10),   # 20 lines of 10 cells, one fine face per element (H-bar = h)
+    (60, 30, 20, 10, 4, 2),     # 20 lines, 3 x 3 subdomains
+    (48, 16, 24, 8, 4, 2),      # 24 lines of 8 cells
+    (20, 40, 10, 20, 5, 4),     # lines along x, 20 of them
 ]
 
 
@@ -133,6 +137,22 @@ def test_mpm_and_mrcm_mixed(binding):
     orun = _compare_runs(binding, cfg, K, 25, "mixed")
     branches = [h["branch"] for h in orun.history]
     assert "mpm" in branches[1:] and "mrcm" in branches[1:]
+
+
+def test_many_line_subdomains_mixed(binding):
+    """Subdomains of 20 x 10 cells (more lines than the matrix-core basis takes): MRCM updates
+    and MPM-2P steps against the oracle."""
+    cfg, K = inputs.random_problem(13, 60, 30, 20, 10, 4, 2, sigma2=3.0, corr_len=0.15, eta=0.002, mu_o=40.0)
+    orun = _compare_runs(binding, cfg, K, 16, "many-line mixed")
+    branches = [h["branch"] for h in orun.history]
+    assert "mpm" in branches[1:] and "mrcm" in branches[1:]
+
+
+def test_x4_finger_growth_config(binding):
+    """The finger-growth workload (15 x 5 subdomains of 20 x 10, one fine face per element,
+    perturbed initial front) against the oracle for the first elliptic steps."""
+    cfg = inputs.x4_config(steps=6)
+    _compare_runs(binding, cfg, inputs.permeability(cfg), cfg["steps"], "x4")
 
 
 def test_text_switch_rule_and_abs_norm(binding):

@@ -42,3 +42,19 @@ def test_batch_and_serve_workloads():
     assert {c["nx"] for c in r} <= {128, 256, 512}
     assert all(10.0 <= c["mu_o"] <= 100.0 and 1.0 <= c["sigma2"] <= 4.0 for c in r)
     assert r[0] == inputs.serve_requests(64)[0]
+
+
+def test_x4_finger_growth_workload():
+    """300 x 50 cells on [0,3] x [0,1/2] in 20 x 10 subdomains with one fine face per element,
+    M = 4, homogeneous K, p = 0 / -1e4, and a water front advanced at the channel centre."""
+    cfg = inputs.x4_config()
+    assert (cfg["nx"], cfg["ny"], cfg["sub_x"], cfg["sub_y"]) == (300, 50, 20, 10)
+    assert (cfg["ne_x"], cfg["ne_y"]) == (20, 10) and cfg["mu_o"] / cfg["mu_w"] == 4.0
+    assert cfg["bc_value"][:2] == [0.0, -1.0e4]
+    K = inputs.permeability(cfg)
+    assert K.shape == (50, 300) and np.all(K == 1.0)
+    s = inputs.initial_saturation(cfg)
+    assert set(np.unique(s)) == {0.0, 1.0}
+    front = s.sum(axis=1)                 # saturated cells per row
+    assert front[0] == front[-1] == 10 and front[25] == 15
+    assert front.max() == 15 and np.all(front[np.abs(np.arange(50) + 0.5 - 25) >= 5] == 10)

@@ -102,6 +102,30 @@ def test_T3_mrcm_one_face_elements_equals_fine(alpha, shape):
     assert np.abs(d["ux_bar"] - ux).max() / scale < 1e-11
 
 
+def test_T3_T11_finger_growth_workload():
+    """The finger-growth workload (300 x 50 cells in 15 x 5 subdomains of 20 x 10 with one fine
+    face per element, p = 0 / -1e4 on the left / right): MRCM equals the undecomposed fine solve,
+    and MPM-2P from that basis equals the Richardson step closed form."""
+    cfg = inputs.x4_config(steps=1)
+    K = inputs.permeability(cfg)
+    s_m = inputs.initial_saturation(cfg)
+    kap_m = physics.conductivity(s_m, K, cfg["mu_w"], cfg["mu_o"])
+    _, ux, uy = fine.fine_solve(cfg, kap_m)
+    u1, v1, st, _ = mpm.mrcm_velocity(cfg, kap_m)
+    scale = np.abs(ux).max()
+    assert np.abs(u1 - ux).max() / scale < 1e-11
+    assert np.abs(v1 - uy).max() / scale < 1e-11
+    rng = np.random.default_rng(4)
+    s_n = np.clip(s_m + rng.uniform(-0.3, 0.3, K.shape) * (np.abs(np.gradient(s_m, axis=1)) > 0), 0, 1)
+    s_n[:, 12:20] = 0.5    # the front moved
+    kap_n = physics.conductivity(s_n, K, cfg["mu_w"], cfg["mu_o"])
+    u2, v2, _ = mpm.mpm_velocity(cfg, st, kap_n)
+    rx, ry = _richardson_reference(cfg, kap_m, kap_n)
+    scale = np.abs(rx).max()
+    assert np.abs(u2 - rx).max() / scale < 1e-11
+    assert np.abs(v2 - ry).max() / scale < 1e-11
+
+
 def test_T4_single_subdomain_equals_fine():
     cfg, K = _problem(3, 8, 8, 8, 8, 1, 1)
     kap = physics.conductivity(np.zeros_like(K), K, 1.0, 10.0)
