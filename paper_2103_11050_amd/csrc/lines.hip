@@ -387,71 +387,102 @@ __device__ __forceinline__ void load_halo_tiles(const Geo& g, int I, int J, cons
   __syncthreads();
 }
 
-// Right-hand side of the trivial-Robin problem at local cell (i, j): |c| q minus the outflow
-// of v = (t^n / t^m) u~^m through the cell's faces, z on Neumann faces (halo tiles as above).
-__device__ __forceinline__ double mpm_rhs_cell(const Geo& g, int I, int J, int i, int j, double qv,
-                                               const double* knt, const double* kmt, const double* uxs,
-                                               const double* uys) {
+// v = (t^n / t^m) u~^m on every face of the tile, in place of u~^m (halo tiles as above): the
+// harmonic-transmissibility ratio with the neighbour cell (across Gamma too), kappa^n / kappa^m
+// of the cell on the physical boundary. One ratio per face. No barrier.
+__device__ __forceinline__ void mpm_face_v(const Geo& g, int I, int J, const double* knt, const double* kmt,
+                                           double* uxs, double* uys) {
   const int TW = g.mx + 2;
+  const int nfx = g.my * (g.mx + 1), nfy = (g.my + 1) * g.mx;
+  for (int e = threadIdx.x; e < nfx; e += 64) {
+    const int j = e / (g.mx + 1), i = e - j * (g.mx + 1);   // face between local cells i-1 and i
+    const int gi = I * g.mx + i;
+    const int cl = (j + 1) * TW + i, cr = cl + 1;          // halo indices of the two cells
+    double ratio;
+    if (gi > 0 && gi < g.nx) ratio = harm_ratio(knt[cr], knt[cl], kmt[cr], kmt[cl]);
+    else if (gi == 0) ratio = knt[cr] / kmt[cr];
+    else ratio = knt[cl] / kmt[cl];
+    uxs[e] = ratio * uxs[e];
+  }
+  for (int e = threadIdx.x; e < nfy; e += 64) {
+    const int j = e / g.mx, i = e - j * g.mx;                 // face between local cells j-1 and j
+    const int gj = J * g.my + j;
+    const int cb = j * TW + i + 1, ct = cb + TW;
+    double ratio;
+    if (gj > 0 && gj < g.ny) ratio = harm_ratio(knt[ct], knt[cb], kmt[ct], kmt[cb]);
+    else if (gj == 0) ratio = knt[ct] / kmt[ct];
+    else ratio = knt[cb] / kmt[cb];
+    uys[e] = ratio * uys[e];
+  }
+}
+
+// Right-hand side of the trivial-Robin problem at local cell (i, j): |c| q minus the outflow
+// of v through the cell's faces (v on the face tiles), z on Neumann faces.
+__device__ __forceinline__ double mpm_rhs_cell(const Geo& g, int I, int J, int i, int j, double qv,
+                                               const double* vx, const double* vy) {
   const int gi = I * g.mx + i, gj = J * g.my + j;
-  const int e = (j + 1) * TW + i + 1;
-  const double kn = knt[e], km = kmt[e];
   double r = g.hx * g.hy * qv;
   {
-    const double u = uxs[j * (g.mx + 1) + i];
+    const double v = vx[j * (g.mx + 1) + i];
     if (gi > 0) {
-      r -= g.hy * (-harm_ratio(kn, knt[e - 1], km, kmt[e - 1]) * u);
+      r -= g.hy * (-v);
     } else {
       BFace f = bface(g, I, J, j);
-      r -= f.kind == FACE_NEU ? f.flen * f.value : g.hy * (-(kn / km) * u);
+      r -= f.kind == FACE_NEU ? f.flen * f.value : g.hy * (-v);
     }
   }
   {
-    const double u = uxs[j * (g.mx + 1) + i + 1];
+    const double v = vx[j * (g.mx + 1) + i + 1];
     if (gi < g.nx - 1) {
-      r -= g.hy * (harm_ratio(kn, knt[e + 1], km, kmt[e + 1]) * u);
+      r -= g.hy * v;
     } else {
       BFace f = bface(g, I, J, g.my + j);
-      r -= f.kind == FACE_NEU ? f.flen * f.value : g.hy * ((kn / km) * u);
+      r -= f.kind == FACE_NEU ? f.flen * f.value : g.hy * v;
     }
   }
   {
-    const double u = uys[j * g.mx + i];
+    const double v = vy[j * g.mx + i];
     if (gj > 0) {
-      r -= g.hx * (-harm_ratio(kn, knt[e - TW], km, kmt[e - TW]) * u);
+      r -= g.hx * (-v);
     } else {
       BFace f = bface(g, I, J, 2 * g.my + i);
-      r -= f.kind == FACE_NEU ? f.flen * f.value : g.hx * (-(kn / km) * u);
+      r -= f.kind == FACE_NEU ? f.flen * f.value : g.hx * (-v);
     }
   }
   {
-    const double u = uys[(j + 1) * g.mx + i];
+    const double v = vy[(j + 1) * g.mx + i];
     if (gj < g.ny - 1) {
-      r -= g.hx * (harm_ratio(kn, knt[e + TW], km, kmt[e + TW]) * u);
+      r -= g.hx * v;
     } else {
       BFace f = bface(g, I, J, 2 * g.my + g.mx + i);
-      r -= f.kind == FACE_NEU ? f.flen * f.value : g.hx * ((kn / km) * u);
+      r -= f.kind == FACE_NEU ? f.flen * f.value : g.hx * v;
     }
   }
   return r;
 }
 
-// Outward v = (t^n / t^m) u~^m on boundary face bf of the subdomain (0 on Neumann faces).
-__device__ __forceinline__ double mpm_vbnd_face(const Geo& g, int I, int J, const BFace& bf, const double* knt,
-                                                const double* kmt, const double* uxs, const double* uys) {
+// Outward v on boundary face bf of the subdomain (0 on Neumann faces).
+__device__ __forceinline__ double mpm_vbnd_face(const Geo& g, const BFace& bf, const double* vx, const double* vy) {
   if (bf.kind == FACE_NEU) return 0.0;
-  const int TW = g.mx + 2;
-  const int gi = I * g.mx + bf.i, gj = J * g.my + bf.j;
-  const int e = (bf.j + 1) * TW + bf.i + 1;
-  const double km = kmt[e], kn = knt[e];
-  double u;
-  int nbr;
-  if (bf.side == 0) { u = -uxs[bf.j * (g.mx + 1) + bf.i]; nbr = gi > 0 ? e - 1 : -1; }
-  else if (bf.side == 1) { u = uxs[bf.j * (g.mx + 1) + bf.i + 1]; nbr = gi < g.nx - 1 ? e + 1 : -1; }
-  else if (bf.side == 2) { u = -uys[bf.j * g.mx + bf.i]; nbr = gj > 0 ? e - TW : -1; }
-  else { u = uys[(bf.j + 1) * g.mx + bf.i]; nbr = gj < g.ny - 1 ? e + TW : -1; }
-  const double ratio = nbr >= 0 ? harm_ratio(kn, knt[nbr], km, kmt[nbr]) : kn / km;
-  return ratio * u;
+  if (bf.side == 0) return -vx[bf.j * (g.mx + 1) + bf.i];
+  if (bf.side == 1) return vx[bf.j * (g.mx + 1) + bf.i + 1];
+  if (bf.side == 2) return -vy[bf.j * g.mx + bf.i];
+  return vy[(bf.j + 1) * g.mx + bf.i];
+}
+
+// The geometry with the subdomain shape as compile-time constants for FX x FX subdomains (FX =
+// 0: as given), so that the index arithmetic of the local kernels folds.
+template <int FX>
+__device__ __forceinline__ Geo fix_geo(Geo g) {
+  if constexpr (FX > 0) {
+    g.mx = FX;
+    g.my = FX;
+    g.nc = FX * FX;
+    g.band = FX;
+    g.xfast = 1;
+    g.nb = 4 * FX;
+  }
+  return g;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -464,13 +495,14 @@ __device__ __forceinline__ double mpm_vbnd_face(const Geo& g, int I, int J, cons
 // y-faces -> h), about 9.5 KB per subdomain: registers, not LDS, bound the subdomains per CU.
 // With T = float the kept blocks are FP32 (all lines in registers, up to 16) and the solve is
 // refined in FP64 against the full line form of the matrix.
-template <int MF, int NL, typename T>
+template <int MF, int NL, typename T, int FX>
 __global__ void __launch_bounds__(64)
-k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict__ kap_m,
+k_mpm_local_lb(Geo g0, const double* __restrict__ kap_n, const double* __restrict__ kap_m,
                const double* __restrict__ uxm, const double* __restrict__ uym, const double* __restrict__ q,
                const T* __restrict__ fac, double* __restrict__ hg, double* __restrict__ vbnd, LeafOut lo,
                const RunTab* __restrict__ rt) {
   constexpr bool F32 = sizeof(T) == 4;
+  const Geo g = fix_geo<FX>(g0);
   {
     const int64_t wo = ws_off(rt);
     kap_n = at_off(kap_n, wo);
@@ -498,6 +530,8 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
   else if constexpr (NL > 0) lb_load_reg<MF, NL>(L, Es, E);
   double qc[4];
   load_halo_tiles(g, I, J, kap_n, kap_m, uxm, uym, q, knt, kmt, uxs, uys, qc);
+  mpm_face_v(g, I, J, knt, kmt, uxs, uys);
+  __syncthreads();
   double rhs[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
@@ -506,11 +540,11 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
     if (c < n) {
       int i, j;
       loc_ij(g, c, &i, &j);
-      rhs[s] = mpm_rhs_cell(g, I, J, i, j, qc[s], knt, kmt, uxs, uys);
+      rhs[s] = mpm_rhs_cell(g, I, J, i, j, qc[s], uxs, uys);
     }
   }
   for (int f = threadIdx.x; f < nb; f += 64)
-    vbnd[size_t(sub) * nb + f] = mpm_vbnd_face(g, I, J, bface(g, I, J, f), knt, kmt, uxs, uys);
+    vbnd[size_t(sub) * nb + f] = mpm_vbnd_face(g, bface(g, I, J, f), uxs, uys);
   __syncthreads();   // the kappa^n halo and the face tiles are dead from here on
   double* x = uxs;
   double* ty = knt;
@@ -567,13 +601,15 @@ k_mpm_local_lb(Geo g, const double* __restrict__ kap_n, const double* __restrict
 // rate per cell volume and the inflow through the physical boundary.
 // With T = float (MPM-2P steps of the precision form; store = 0) the blocks are FP32 and the
 // solve is refined in FP64. The blocks are requested at entry.
-template <int MF, int NL, typename T>
+template <int MF, int NL, typename T, int FX>
 __global__ void __launch_bounds__(64)
-k_downscale_lb(Geo g, const double* __restrict__ kap_s, const double* __restrict__ q,
+k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restrict__ q,
                const double* __restrict__ ubnd, double* __restrict__ ux, double* __restrict__ uy,
                double* __restrict__ red_rate, double* __restrict__ red_qin, T* __restrict__ Escr,
                T* __restrict__ Ekeep, const int32_t* __restrict__ flag, int store, int32_t* err, const RunTab* __restrict__ rt) {
   constexpr bool F32 = sizeof(T) == 4;
+  const Geo g = fix_geo<FX>(g0);
+  if constexpr (FX > 0) store = 0;   // fixed-shape instances serve the MPM-2P steps only
   {
     const int64_t wo = ws_off(rt);
     kap_s = at_off(kap_s, wo);
@@ -749,30 +785,35 @@ void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double*
 }
 
 // line length padded to MF in {8, 16}; the solve keeps the blocks in registers for the
-// common line counts 8 and 16
-#define MPM_LB_DISPATCH(KERNEL, ...)                                                                     \
-  do {                                                                                                   \
-    const int nl_ = g.nc / g.band;                                                                       \
-    if (line_mf(g) == 8) {                                                                               \
-      if (nl_ == 8) hipLaunchKernelGGL((KERNEL<8, 8, double>), dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, __VA_ARGS__);  \
-      else hipLaunchKernelGGL((KERNEL<8, 0, double>), dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, __VA_ARGS__);           \
-    } else {                                                                                             \
-      if (nl_ == 16) hipLaunchKernelGGL((KERNEL<16, 16, double>), dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, __VA_ARGS__); \
-      else hipLaunchKernelGGL((KERNEL<16, 0, double>), dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, __VA_ARGS__);          \
-    }                                                                                                    \
+// common line counts 8 and 16, and square 8^2 / 16^2 subdomains get compile-time shapes
+#define MPM_LB_LAUNCH(KERNEL, ...) \
+  hipLaunchKernelGGL((KERNEL), dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, __VA_ARGS__)
+#define MPM_LB_DISPATCH(KERNEL, FIXOK, ...)                                                        \
+  do {                                                                                             \
+    const int nl_ = g.nc / g.band;                                                                 \
+    const bool sq8_ = (FIXOK) && g.mx == 8 && g.my == 8, sq16_ = (FIXOK) && g.mx == 16 && g.my == 16; \
+    if (line_mf(g) == 8) {                                                                         \
+      if (sq8_) MPM_LB_LAUNCH((KERNEL<8, 8, double, 8>), __VA_ARGS__);                             \
+      else if (nl_ == 8) MPM_LB_LAUNCH((KERNEL<8, 8, double, 0>), __VA_ARGS__);                    \
+      else MPM_LB_LAUNCH((KERNEL<8, 0, double, 0>), __VA_ARGS__);                                  \
+    } else {                                                                                       \
+      if (sq16_) MPM_LB_LAUNCH((KERNEL<16, 16, double, 16>), __VA_ARGS__);                         \
+      else if (nl_ == 16) MPM_LB_LAUNCH((KERNEL<16, 16, double, 0>), __VA_ARGS__);                 \
+      else MPM_LB_LAUNCH((KERNEL<16, 0, double, 0>), __VA_ARGS__);                                 \
+    }                                                                                              \
   } while (0)
 
 // precision form: FP32 blocks, any line count up to 16
-#define MPM_LB_DISPATCH_F32(KERNEL, ...)                                                                 \
-  do {                                                                                                   \
-    if (line_mf(g) == 8) hipLaunchKernelGGL((KERNEL<8, 16, float>), dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, __VA_ARGS__); \
-    else hipLaunchKernelGGL((KERNEL<16, 16, float>), dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, __VA_ARGS__);        \
+#define MPM_LB_DISPATCH_F32(KERNEL, ...)                                                           \
+  do {                                                                                             \
+    if (line_mf(g) == 8) MPM_LB_LAUNCH((KERNEL<8, 16, float, 0>), __VA_ARGS__);                    \
+    else MPM_LB_LAUNCH((KERNEL<16, 16, float, 0>), __VA_ARGS__);                                   \
   } while (0)
 
 void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                       const double* uym, const double* q, const double* fac, double* h, double* vbnd,
                       LeafOut lo, Runs rt) {
-  MPM_LB_DISPATCH(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, lo, rt.tab);
+  MPM_LB_DISPATCH(k_mpm_local_lb, true, g, kn, km, uxm, uym, q, fac, h, vbnd, lo, rt.tab);
 }
 
 template <typename T>
@@ -819,7 +860,8 @@ void launch_to_f32(hipStream_t st, size_t n, const double* src, float* dst) {
 void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
                       double* ux, double* uy, double* red_rate, double* red_qin, double* Escr, double* Ekeep,
                       const int32_t* flag, int store, int32_t* err, Runs rt) {
-  MPM_LB_DISPATCH(k_downscale_lb, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, Escr, Ekeep, flag, store, err, rt.tab);
+  MPM_LB_DISPATCH(k_downscale_lb, !store, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, Escr, Ekeep, flag, store, err,
+                  rt.tab);
 }
 
 size_t line_factor_doubles(int nsub, int nc, int band) {
