@@ -16,7 +16,8 @@ It shares no code with the HIP path. It follows the paper's steps in the paper's
 * ``downscale``  -- the local all-Neumann problems that produce a conservative velocity
                     (Section 4.1, the downscaling problems after eq:soma_u).
 * ``mpm``        -- the zeroth-order perturbation problem solved with reused basis
-                    functions (Section 4.1, eq:mpm_tf_3).
+                    functions (Section 4.1, eq:mpm_tf_3), optionally with the first-order
+                    term (eq:mpm_tf_4, l = 1).
 * ``transport``  -- explicit Euler + first-order upwind saturation step (Section 4).
 * ``splitting``  -- the modified operator splitting (Section 4.2, Algorithm 1).
 * ``cost``       -- basis-function counts and the Relative Cost Reduction (Section 4.3).
@@ -26,7 +27,9 @@ repository (fine element, orientation, epsilon norm, switch timing, downscaling 
 discrete form of kappa^n grad p^m, transport time step, breakthrough).
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test except the MRCM
-solution with interface elements longer than one fine face and the MPM-2P solution with a
-nonzero perturbation on such decompositions, which the paper defines only through the
-algorithm itself (parity unpinned beyond the invariants listed in the tests).
+solution with interface elements longer than one fine face and the MPM-2P solution (zeroth
+or first order) with a nonzero perturbation on such decompositions, which the paper defines
+only through the algorithm itself (parity unpinned beyond the invariants listed in the
+tests). The first-order term is pinned where MRCM is exact (second Richardson step, error
+cubic in the perturbation) and by vanishing without perturbation.
 """

@@ -13,6 +13,17 @@ non-homogeneous local solve per subdomain and one interface solve:
 * Dirichlet datum g - p^m = 0 (the data do not depend on time);
 * u-bar = u^m + delta u^n = u-hat_0 + v on every subdomain's faces, then the mean of both
   sides on Gamma, then downscaling with kappa^n (eq. mpm_upd).
+
+With order = 1 the first-order term of the expansion (eq:mpm_tf_4 with l = 1) is added before
+the downscaling. With eps kappa_eps = kappa^n - kappa^m, the problem for u-hat_1 = -kappa^m
+grad delta p_1 has source div((kappa^n - kappa^m) grad delta p_0) and zero data, and the
+velocity correction is u-hat_1 - (kappa^n - kappa^m) grad delta p_0. Discretely (reading): the
+flux w = (t^n / t^m - 1) u-hat_0 on every face (t^n / t^m the same ratio as for v; u-hat_0 the
+local fluxes of the zeroth-order MRCM solution, the mean of both sides on Gamma; w = 0 on
+Neumann faces, which carry no flux unknown), the first-order problem with source -div w,
+Dirichlet and Neumann data 0 solved by MRCM with the same basis, and u-bar gains u-hat_1 + w.
+With one fine face per interface element this is the second step of the Richardson iteration
+delta p = A_m^-1 (b_n - A_n p^m), delta p_1 = -A_m^-1 (A_n - A_m) delta p_0.
 """
 from __future__ import annotations
 
@@ -73,8 +84,15 @@ def perturbation_flux(cfg, kappa_n, kappa_m, ux_m, uy_m):
     return rx * ux_m, ry * uy_m
 
 
-def mpm_velocity(cfg, state: VelocityState, kappa_n, q=None):
-    """One MPM-2P velocity update reusing ``state``'s basis functions.
+def flux_ratio(cfg, kappa_n, kappa_m):
+    """t^n / t^m on every face (kappa^n / kappa^m of the adjacent cell on boundary faces)."""
+    return perturbation_flux(cfg, kappa_n, kappa_m, np.ones((kappa_n.shape[0], kappa_n.shape[1] + 1)),
+                             np.ones((kappa_n.shape[0] + 1, kappa_n.shape[1])))
+
+
+def mpm_velocity(cfg, state: VelocityState, kappa_n, q=None, order=0):
+    """One MPM-2P velocity update reusing ``state``'s basis functions; ``order`` 1 adds the
+    first-order perturbation term.
 
     Returns (ux, uy, diagnostics)."""
     if q is None:
@@ -103,6 +121,27 @@ def mpm_velocity(cfg, state: VelocityState, kappa_n, q=None):
         j0, j1, i0, i1 = dec.cells(I, J)
         uxs.append(sol.ux[k] + vx[j0:j1, i0:i1 + 1])
         uys.append(sol.uy[k] + vy[j0:j1 + 1, i0:i1])
+    if order >= 1:
+        # w = (t^n / t^m - 1) u-hat_0, 0 on Neumann faces
+        u0x, u0y = average_on_skeleton(dec, sol.ux, sol.uy)
+        rx, ry = flux_ratio(cfg, kappa_n, state.kappa_m)
+        wx, wy = (rx - 1.0) * u0x, (ry - 1.0) * u0y
+        sides = physical_sides(cfg, 0, dec.ny, 0, dec.nx)
+        wx[:, 0] = np.where(sides[W].kind == NEU, 0.0, wx[:, 0])
+        wx[:, -1] = np.where(sides[E].kind == NEU, 0.0, wx[:, -1])
+        wy[0, :] = np.where(sides[S].kind == NEU, 0.0, wy[0, :])
+        wy[-1, :] = np.where(sides[N].kind == NEU, 0.0, wy[-1, :])
+        src1 = -(dec.hy * (wx[:, 1:] - wx[:, :-1]) + dec.hx * (wy[1:, :] - wy[:-1, :])) / (dec.hx * dec.hy)
+
+        def phys_of1(I, J):
+            ph = physical_sides(cfg, *dec.cells(I, J))
+            return [Side(s.kind, s.beta, np.zeros_like(s.datum)) for s in ph]
+
+        sol1 = solve_with_basis(basis, phys_of1, _q_of(dec, src1))
+        for k, (I, J) in enumerate(dec.subdomains()):
+            j0, j1, i0, i1 = dec.cells(I, J)
+            uxs[k] = uxs[k] + sol1.ux[k] + wx[j0:j1, i0:i1 + 1]
+            uys[k] = uys[k] + sol1.uy[k] + wy[j0:j1 + 1, i0:i1]
     uxb, uyb = average_on_skeleton(dec, uxs, uys)
     ux, uy, defects = downscale(cfg, kappa_n, uxb, uyb, q)
     return ux, uy, dict(solution=sol, ux_bar=uxb, uy_bar=uyb, defects=defects, vx=vx, vy=vy)

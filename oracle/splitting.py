@@ -98,7 +98,7 @@ def step(run: Run, force=None):
         run.ell += 1
         run.ux, run.uy, run.state, _ = mrcm_velocity(cfg, kappa_n, run.q)
     else:
-        run.ux, run.uy, _ = mpm_velocity(cfg, run.state, kappa_n, run.q)
+        run.ux, run.uy, _ = mpm_velocity(cfg, run.state, kappa_n, run.q, order=cfg.get("mpm_order", 0))
     run.eps = eps_norm(cfg, kappa_n, run.state.kappa_m)
     run.dt = time_step(cfg, run.ux, run.uy)
     run.history.append(dict(n=run.n, branch=branch, eps=run.eps, decide=decide))

@@ -286,10 +286,12 @@ def test_T10_mpm_without_perturbation_equals_mrcm():
     assert _rel(u2, ux) < 1e-12 and np.abs(v2 - uy).max() < 1e-12 * np.abs(ux).max()
 
 
-def _richardson_reference(cfg, kap_m, kap_n):
+def _richardson_reference(cfg, kap_m, kap_n, order=0):
     """Closed form of MPM-2P when MRCM is exact (one fine face per element, or N = 1):
     p^m = A_m^-1 b_m; delta p = A_m^-1 (b_n - A_n p^m); u-bar = -kappa^m grad delta p
-    - kappa^n grad p^m on the fine grid; then the kappa^n downscaling."""
+    - kappa^n grad p^m on the fine grid; then the kappa^n downscaling. With order 1 the
+    second Richardson step delta p_1 = -A_m^-1 (A_n - A_m) delta p_0 is added, and u-bar gains
+    -kappa^m grad delta p_1 - (kappa^n - kappa^m) grad delta p_0."""
     ny, nx = kap_m.shape
     hx, hy = cfg["lx"] / nx, cfg["ly"] / ny
     sides = fine.physical_sides(cfg, 0, ny, 0, nx)
@@ -303,6 +305,11 @@ def _richardson_reference(cfg, kap_m, kap_n):
     # -kappa^m grad(dp) with homogeneous data on Dirichlet faces, flux 0 on Neumann faces
     hom = [Side(s.kind, s.beta, np.zeros_like(s.datum)) for s in sides]
     ux1, uy1, _ = fine.block_fluxes(kap_m, hx, hy, hom, dp)
+    if order >= 1:
+        dp1 = spla.spsolve(Am, -(An - Am) @ dp)
+        a, b, _ = fine.block_fluxes(kap_m, hx, hy, hom, dp1)
+        c, d, _ = fine.block_fluxes(kap_n, hx, hy, hom, dp)
+        ux1, uy1 = ux1 + a + (c - ux1), uy1 + b + (d - uy1)
     # -kappa^n grad p^m with the true data on Dirichlet faces; Neumann faces keep z
     ux2, uy2, _ = fine.block_fluxes(kap_n, hx, hy, sides, pm)
     uxb, uyb = ux1 + ux2, uy1 + uy2
@@ -314,6 +321,65 @@ def _richardson_reference(cfg, kap_m, kap_n):
         if sides[sd].kind[0] == NEU:
             uyb[sl] = uy2[sl]
     return downscale(cfg, kap_n, uxb, uyb)[:2]
+
+
+@pytest.mark.parametrize("case", ["one_face", "single", "one_face_flux_bc"])
+def test_T11_T12_first_order_term_equals_second_richardson_step(case):
+    """With MRCM exact (one fine face per element, or one subdomain) the first-order term of
+    eq:mpm_tf_4 makes MPM-2P the second Richardson step, closed form on the fine grid."""
+    if case == "single":
+        cfg, K = _problem(18, 10, 8, 10, 8, 1, 1, sigma2=2.0)
+    else:
+        cfg, K = _problem(18, 12, 12, 4, 4, 4, 4, sigma2=2.0)
+    if case == "one_face_flux_bc":
+        cfg["bc_kind"] = [2, 1, 2, 0]
+        cfg["bc_value"] = [-1.0, 0.0, 0.5, 0.0]
+    rng = np.random.default_rng(2)
+    s_m = rng.uniform(0.0, 1.0, K.shape)
+    s_n = np.clip(s_m + rng.uniform(-0.2, 0.2, K.shape), 0, 1)
+    kap_m = physics.conductivity(s_m, K, 1.0, 10.0)
+    kap_n = physics.conductivity(s_n, K, 1.0, 10.0)
+    _, _, st, _ = mpm.mrcm_velocity(cfg, kap_m)
+    ux, uy, _ = mpm.mpm_velocity(cfg, st, kap_n, order=1)
+    rx, ry = _richardson_reference(cfg, kap_m, kap_n, order=1)
+    scale = np.abs(rx).max()
+    assert np.abs(ux - rx).max() / scale < 1e-11
+    assert np.abs(uy - ry).max() / scale < 1e-11
+    # and it differs from the zeroth order by a term of the size of the perturbation
+    u0, v0, _ = mpm.mpm_velocity(cfg, st, kap_n)
+    assert np.abs(ux - u0).max() / scale > 1e-4
+
+
+def test_first_order_term_vanishes_without_perturbation():
+    """kappa^n = kappa^m: w = 0, so the first-order term adds nothing (any decomposition)."""
+    cfg, K, kap = _mrcm_case()
+    ux, uy, st, _ = mpm.mrcm_velocity(cfg, kap)
+    u1, v1, _ = mpm.mpm_velocity(cfg, st, kap, order=1)
+    assert _rel(u1, ux) < 1e-12 and np.abs(v1 - uy).max() < 1e-12 * np.abs(ux).max()
+
+
+def test_first_order_term_error_is_second_order_in_the_perturbation():
+    """Against the exact kappa^n solution (one fine face per element, so MRCM is exact), with a
+    conductivity perturbation of size eps the pressure p^m is off by O(eps), the zeroth-order
+    MPM-2P step (one Richardson step) by O(eps^2) and the first-order one by O(eps^3)."""
+    cfg, K = _problem(19, 12, 12, 4, 4, 4, 4, sigma2=1.0)
+    rng = np.random.default_rng(3)
+    s_m = rng.uniform(0.2, 0.8, K.shape)
+    ds = rng.uniform(-1.0, 1.0, K.shape)
+    kap_m = physics.conductivity(s_m, K, 1.0, 4.0)
+    _, _, st, _ = mpm.mrcm_velocity(cfg, kap_m)
+    errs = {0: [], 1: []}
+    for amp in (0.04, 0.02):
+        kap_n = physics.conductivity(s_m + amp * ds, K, 1.0, 4.0)
+        ex, ey, _, _ = mpm.mrcm_velocity(cfg, kap_n)
+        for order in (0, 1):
+            ux, uy, _ = mpm.mpm_velocity(cfg, st, kap_n, order=order)
+            errs[order].append(max(np.abs(ux - ex).max(), np.abs(uy - ey).max()))
+    r0 = errs[0][0] / errs[0][1]
+    r1 = errs[1][0] / errs[1][1]
+    assert 3.4 < r0 < 4.6, errs
+    assert 6.5 < r1 < 9.5, errs
+    assert errs[1][1] < 0.2 * errs[0][1]
 
 
 @pytest.mark.parametrize("case", ["one_face", "single"])
