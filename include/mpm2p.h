@@ -71,7 +71,7 @@ enum { MPM_PREC_FP64 = 0, MPM_PREC_FP32_REFINE = 1 };
 /* Branch of a velocity update. */
 enum { MPM_AUTO = -1, MPM_FORCE_MPM = 0, MPM_FORCE_MRCM = 1 };
 
-#define MPM_ABI_VERSION 1
+#define MPM_ABI_VERSION 2
 
 typedef struct mpm_desc {
   int32_t abi_version;        /* MPM_ABI_VERSION */
@@ -92,6 +92,11 @@ typedef struct mpm_desc {
   double s_inj;               /* injected saturation s-bar on inflow boundary faces */
   double cfl;                 /* fraction of the monotone upwind time-step bound, (0, 1] */
   double breakthrough_cut;    /* water cut at the outflow boundary that marks breakthrough */
+  int32_t mpm_order;          /* MPM-2P perturbation terms kept: 0 (eq:mpm_tf_3 only, as in the
+                                 paper's runs) or 1 (also eq:mpm_tf_4 with l = 1: one more local
+                                 solve per subdomain, interface solve and reconstruction per
+                                 step; FP64 only) */
+  int32_t reserved;           /* 0 */
 } mpm_desc;
 
 typedef struct mpm_stats {

@@ -18,7 +18,7 @@ EPS_REL, EPS_ABS = 0, 1
 SWITCH_ALG1, SWITCH_TEXT = 0, 1
 PREC_FP64, PREC_FP32_REFINE = 0, 1
 AUTO, FORCE_MPM, FORCE_MRCM = -1, 0, 1
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 
 class Desc(ctypes.Structure):
@@ -35,6 +35,7 @@ class Desc(ctypes.Structure):
         ("bc_kind", ctypes.c_int32 * 4), ("bc_value", ctypes.c_double * 4),
         ("s_inj", ctypes.c_double), ("cfl", ctypes.c_double),
         ("breakthrough_cut", ctypes.c_double),
+        ("mpm_order", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -135,6 +136,7 @@ def make_desc(cfg: dict, precision: int = PREC_FP64) -> Desc:
     d.s_inj = cfg["s_inj"]
     d.cfl = cfg["cfl"]
     d.breakthrough_cut = cfg["breakthrough_cut"]
+    d.mpm_order = int(cfg.get("mpm_order", 0))
     return d
 
 

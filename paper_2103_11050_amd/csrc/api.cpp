@@ -76,6 +76,7 @@ struct mpm_run {
   char* ws = nullptr;
   double *K, *q, *s, *s2, *kn, *km, *ux, *uy, *uxm, *uym, *fac, *S, *h, *vbnd, *ubnd, *leafK;
   double *front, *fI, *slots, *panel, *y, *red, *scal, *dsE, *nfac;
+  double* wbnd = nullptr;              // first-order term only
   int32_t* err;
   float *fac32 = nullptr, *nfac32 = nullptr, *dsE32 = nullptr;   // precision form
   bool f32 = false;
@@ -301,6 +302,17 @@ void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store, Run
   {
     Scope sc(r, "flux");
     launch_flux(r->st, r->g, r->km, r->S, r->h, r->vbnd, r->y, r->subdofs_d, r->ubnd, with_v, rt);
+  }
+  if (with_v && r->P.d.mpm_order == 1) {
+    // first-order term (eq:mpm_tf_4): local problems, a second interface solve, u-hat_1 + w
+    {
+      Scope sc(r, "first_order");
+      launch_mpm_first(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac, r->y, r->subdofs_d, r->ubnd,
+                       r->vbnd, r->h, r->wbnd, leaf_dest(r), rt);
+    }
+    nd_solve(r, rt);
+    Scope sc(r, "flux");
+    launch_flux(r->st, r->g, r->km, r->S, r->h, r->wbnd, r->y, r->subdofs_d, r->ubnd, 2, rt);
   }
   {
     Scope sc(r, "downscale");
@@ -559,6 +571,7 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   r->front = D(P.off_front); r->fI = D(P.off_fI); r->slots = D(P.off_slot);
   r->panel = D(P.off_panel); r->y = D(P.off_y); r->red = D(P.off_red); r->scal = D(P.off_scal);
   r->dsE = D(P.off_dsE); r->nfac = D(P.off_nfac);
+  if (P.d.mpm_order == 1) r->wbnd = D(P.off_wbnd);
   r->f32 = P.d.precision == MPM_PREC_FP32_REFINE;
   if (r->f32) {
     r->fac32 = reinterpret_cast<float*>(r->ws + P.off_fac32);
@@ -630,7 +643,8 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
                     in(r->leafup, ns * sizeof(LeafUp)) &&
                     (!r->f32 || (in(r->fac32, P.n_blocks * 4) && in(r->nfac32, P.n_blocks * 4) &&
                                  in(r->dsE32, P.n_blocks * 4))) &&
-                    in(r->nd.lnodes, std::max<size_t>(P.lnodes.size(), 1) * sizeof(NodeDev));
+                    in(r->nd.lnodes, std::max<size_t>(P.lnodes.size(), 1) * sizeof(NodeDev)) &&
+                    (P.d.mpm_order != 1 || in(r->wbnd, ns * P.nb * 8));
     if (!ok) return fail(MPM_EINVAL);
   }
   CREATE_CHK(hipHostMalloc(reinterpret_cast<void**>(&r->pinned), 64, hipHostMallocDefault));
@@ -807,7 +821,7 @@ std::string group_key(const mpm_run* r) {
   put(&d.abi_version, 4); put(&d.nx, 4); put(&d.ny, 4); put(&d.lx, 8); put(&d.ly, 8);
   put(&d.sub_x, 4); put(&d.sub_y, 4); put(&d.ne_x, 4); put(&d.ne_y, 4); put(&d.alpha, 8);
   put(&d.switch_rule, 4); put(&d.precision, 4); put(&d.cn, 4); put(d.bc_kind, 16); put(d.bc_value, 32);
-  put(&d.s_inj, 8);
+  put(&d.s_inj, 8); put(&d.mpm_order, 4);
   k.push_back(r->s == r->s_base ? 0 : 1);
   return k;
 }

@@ -60,9 +60,16 @@ size_t line_factor_doubles(int nsub, int nc, int band);
 void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                       const double* uym, const double* q, const double* fac, double* h, double* vbnd,
                       LeafOut lo, Runs rt = one_run());
+// with_v: 0 u-hat only, 1 u-hat + v, 2 ubnd += u-hat + v (first-order term)
 void launch_flux(hipStream_t st, const Geo& g, const double* km, const double* S, const double* h,
                  const double* vbnd, const double* y, const int32_t* sub_dofs, double* ubnd, int with_v,
                  Runs rt = one_run());
+// first-order term of MPM-2P after the zeroth-order interface solve and reconstruction: boundary
+// fluxes h and interface right-hand side of its trivial-Robin problem, w on the boundary faces
+void launch_mpm_first(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
+                      const double* uym, const double* q, const double* fac, const double* y,
+                      const int32_t* sub_dofs, const double* ubnd, const double* vbnd, double* h, double* wbnd,
+                      LeafOut lo, Runs rt = one_run());
 // Neumann inverse blocks of kappa^n for the subdomains whose conductivity tile differs from
 // kappa^m (into Escr, flag[sub] = 1), flag[sub] = 0 elsewhere.
 void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, double* Escr, const int32_t* list,

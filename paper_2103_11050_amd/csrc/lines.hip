@@ -389,9 +389,10 @@ __device__ __forceinline__ void load_halo_tiles(const Geo& g, int I, int J, cons
 
 // v = (t^n / t^m) u~^m on every face of the tile, in place of u~^m (halo tiles as above): the
 // harmonic-transmissibility ratio with the neighbour cell (across Gamma too), kappa^n / kappa^m
-// of the cell on the physical boundary. One ratio per face. No barrier.
+// of the cell on the physical boundary. One ratio per face, kept in rx, ry when given. No
+// barrier.
 __device__ __forceinline__ void mpm_face_v(const Geo& g, int I, int J, const double* knt, const double* kmt,
-                                           double* uxs, double* uys) {
+                                           double* uxs, double* uys, double* rx = nullptr, double* ry = nullptr) {
   const int TW = g.mx + 2;
   const int nfx = g.my * (g.mx + 1), nfy = (g.my + 1) * g.mx;
   for (int e = threadIdx.x; e < nfx; e += 64) {
@@ -403,6 +404,7 @@ __device__ __forceinline__ void mpm_face_v(const Geo& g, int I, int J, const dou
     else if (gi == 0) ratio = knt[cr] / kmt[cr];
     else ratio = knt[cl] / kmt[cl];
     uxs[e] = ratio * uxs[e];
+    if (rx) rx[e] = ratio;
   }
   for (int e = threadIdx.x; e < nfy; e += 64) {
     const int j = e / g.mx, i = e - j * g.mx;                 // face between local cells j-1 and j
@@ -413,6 +415,7 @@ __device__ __forceinline__ void mpm_face_v(const Geo& g, int I, int J, const dou
     else if (gj == 0) ratio = knt[ct] / kmt[ct];
     else ratio = knt[cb] / kmt[cb];
     uys[e] = ratio * uys[e];
+    if (ry) ry[e] = ratio;
   }
 }
 
@@ -588,6 +591,174 @@ k_mpm_local_lb(Geo g0, const double* __restrict__ kap_n, const double* __restric
     for (int xx = f0; xx < f0 + cnt; ++xx) {
       BFace ff = bface(g, I, J, xx);
       const double wgt = (a & 1) ? 1.0 : -ff.sgn * robin_beta(g, ff, kmt[(ff.j + 1) * TW + ff.i + 1]);
+      v += wgt * hsh[xx];
+    }
+    leaf_out(lo, sub, a, v);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// First-order term of MPM-2P (eq:mpm_tf_4 with l = 1), after the zeroth-order interface solve
+// y and its reconstruction (ubnd = u-hat_0 + v and vbnd = v on the subdomain's boundary
+// faces). Per subdomain: delta p_0 from the kept kappa^m blocks with the zeroth-order right-hand
+// side and the Robin data r_f = -sgn beta_f U + P of y; the flux u-hat_0 on every face (the mean
+// of both sides' reconstructions on Gamma); w = (t^n / t^m - 1) u-hat_0 (0 on Neumann faces);
+// then the trivial-Robin problem with source -div w and zero data, whose boundary fluxes h and
+// interface right-hand side B^T h go out as for the zeroth order, and w on the boundary faces.
+// The reconstruction of the second interface solve adds u-hat_1 + w to ubnd.
+template <int MF, int NL, typename T, int FX>   // T: double (the term is FP64 only)
+__global__ void __launch_bounds__(64)
+k_mpm_first(Geo g0, const double* __restrict__ kap_n, const double* __restrict__ kap_m,
+            const double* __restrict__ uxm, const double* __restrict__ uym, const double* __restrict__ q,
+            const double* __restrict__ fac, const double* __restrict__ y, const int32_t* __restrict__ sub_dofs,
+            const double* __restrict__ ubnd, const double* __restrict__ vbnd, double* __restrict__ hg,
+            double* __restrict__ wbnd, LeafOut lo, const RunTab* __restrict__ rt) {
+  static_assert(sizeof(T) == 8, "FP64 only");
+  const Geo g = fix_geo<FX>(g0);
+  {
+    const int64_t wo = ws_off(rt);
+    kap_n = at_off(kap_n, wo);
+    kap_m = at_off(kap_m, wo);
+    uxm = at_off(uxm, wo);
+    uym = at_off(uym, wo);
+    q = at_off(q, wo);
+    fac = at_off(fac, wo);
+    y = at_off(y, wo);
+    sub_dofs = at_off(sub_dofs, wo);
+    ubnd = at_off(ubnd, wo);
+    vbnd = at_off(vbnd, wo);
+    hg = at_off(hg, wo);
+    wbnd = at_off(wbnd, wo);
+    lo = leaf_at(lo, wo);
+  }
+  __shared__ double knt[18 * 18], kmt[18 * 18], uxs[16 * 17], uys[17 * 16], rx[16 * 17], ry[17 * 16];
+  __shared__ double wx[16 * 17], wy[17 * 16], x[256], ty[256], rr[64], hsh[64];
+  const int sub = blockIdx.x;
+  const int I = sub % g.Sx, J = sub / g.Sx;
+  const int n = g.nc, nb = g.nb, TW = g.mx + 2;
+  LB<MF> L;
+  constexpr int NLR = NL > 0 ? NL : 1;
+  double E[NLR][LB<MF>::EPL];
+  const double* Es = fac + efac_off<MF>(g, sub, 0, 0);
+  if constexpr (NL > 0) lb_load_reg<MF, NL>(L, Es, E);
+  double qc[4];
+  load_halo_tiles(g, I, J, kap_n, kap_m, uxm, uym, q, knt, kmt, uxs, uys, qc);
+  mpm_face_v(g, I, J, knt, kmt, uxs, uys, rx, ry);
+  auto kmf = [&](int i, int j) { return kmt[(j + 1) * TW + i + 1]; };
+  fill_ycoup_k(g, kmf, ty);
+  // Robin data of the zeroth-order interface solution on Gamma faces
+  for (int f = threadIdx.x; f < nb; f += 64) {
+    const BFace bf = bface(g, I, J, f);
+    double r = 0.0;
+    if (bf.kind == FACE_ROB) {
+      const int a = bface_dof(g, I, J, bf);
+      const int32_t* dofs = sub_dofs + size_t(sub) * g.ndmax;
+      r = -bf.sgn * robin_beta(g, bf, kmf(bf.i, bf.j)) * y[dofs[a]] + y[dofs[a + 1]];
+    }
+    rr[f] = r;
+  }
+  __syncthreads();
+  const LineW W{ty, ty, nullptr, g.xfast, g.band, 0};
+  // delta p_0: the zeroth-order right-hand side plus |f| t_f r_f on the Robin faces
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int c = threadIdx.x + 64 * s;
+    if (c >= n) continue;
+    int i, j;
+    loc_ij(g, c, &i, &j);
+    double rhs = mpm_rhs_cell(g, I, J, i, j, qc[s], uxs, uys);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const bool on = (t == 0 && i == 0) || (t == 1 && i == g.mx - 1) || (t == 2 && j == 0) ||
+                      (t == 3 && j == g.my - 1);
+      if (!on) continue;
+      const int f = t == 0 ? j : t == 1 ? g.my + j : t == 2 ? 2 * g.my + i : 2 * g.my + g.mx + i;
+      const BFace bf = bface(g, I, J, f);
+      if (bf.kind == FACE_ROB) rhs += bf.flen * bface_trans(g, bf, kmf(i, j)) * rr[f];
+    }
+    x[c] = rhs;
+  }
+  __syncthreads();
+  if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
+  else lb_solve<MF>(g, W, L, Es, x);
+  // u-hat_0 on every face of the tile and w = (ratio - 1) u-hat_0 (+x / +y orientation)
+  auto u0_bnd = [&](int f) -> double {   // outward u-hat_0 on boundary face f (mean on Gamma)
+    const BFace bf = bface(g, I, J, f);
+    const double own = ubnd[size_t(sub) * nb + f] - vbnd[size_t(sub) * nb + f];
+    if (bf.kind != FACE_ROB) return own;
+    int ns, nf;
+    if (bf.side == 0) { ns = sub - 1; nf = g.my + bf.k; }
+    else if (bf.side == 1) { ns = sub + 1; nf = bf.k; }
+    else if (bf.side == 2) { ns = sub - g.Sx; nf = 2 * g.my + g.mx + bf.k; }
+    else { ns = sub + g.Sx; nf = 2 * g.my + bf.k; }
+    const double other = ubnd[size_t(ns) * nb + nf] - vbnd[size_t(ns) * nb + nf];
+    return 0.5 * (own - other);
+  };
+  const int nfx = g.my * (g.mx + 1), nfy = (g.my + 1) * g.mx;
+  for (int e = threadIdx.x; e < nfx; e += 64) {
+    const int j = e / (g.mx + 1), i = e - j * (g.mx + 1);
+    double w;
+    if (i > 0 && i < g.mx) {
+      const int cl = loc_index(g, i - 1, j), cr = loc_index(g, i, j);
+      const double u0 = harm_trans(kmf(i - 1, j), kmf(i, j), g.hx) * (x[cl] - x[cr]);
+      w = (rx[e] - 1.0) * u0;
+    } else {
+      const int f = i == 0 ? j : g.my + j;
+      const BFace bf = bface(g, I, J, f);
+      const double u0 = i == 0 ? -u0_bnd(f) : u0_bnd(f);
+      w = bf.kind == FACE_NEU ? 0.0 : (rx[e] - 1.0) * u0;
+    }
+    wx[e] = w;
+  }
+  for (int e = threadIdx.x; e < nfy; e += 64) {
+    const int j = e / g.mx, i = e - j * g.mx;
+    double w;
+    if (j > 0 && j < g.my) {
+      const int cb = loc_index(g, i, j - 1), ct = loc_index(g, i, j);
+      const double u0 = harm_trans(kmf(i, j - 1), kmf(i, j), g.hy) * (x[cb] - x[ct]);
+      w = (ry[e] - 1.0) * u0;
+    } else {
+      const int f = j == 0 ? 2 * g.my + i : 2 * g.my + g.mx + i;
+      const BFace bf = bface(g, I, J, f);
+      const double u0 = j == 0 ? -u0_bnd(f) : u0_bnd(f);
+      w = bf.kind == FACE_NEU ? 0.0 : (ry[e] - 1.0) * u0;
+    }
+    wy[e] = w;
+  }
+  __syncthreads();
+  // first-order problem: source -div w, zero data
+  for (int c = threadIdx.x; c < n; c += 64) {
+    int i, j;
+    loc_ij(g, c, &i, &j);
+    const double out = g.hy * (wx[j * (g.mx + 1) + i + 1] - wx[j * (g.mx + 1) + i]) +
+                       g.hx * (wy[(j + 1) * g.mx + i] - wy[j * g.mx + i]);
+    x[c] = -out;
+  }
+  __syncthreads();
+  if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
+  else lb_solve<MF>(g, W, L, Es, x);
+  for (int f = threadIdx.x; f < nb; f += 64) {
+    const BFace bf = bface(g, I, J, f);
+    const double h = bf.kind == FACE_NEU ? 0.0 : bf.flen * bface_trans(g, bf, kmf(bf.i, bf.j)) *
+                                                     x[loc_index(g, bf.i, bf.j)];
+    hsh[f] = h;
+    hg[size_t(sub) * nb + f] = h;
+    double wo;
+    if (bf.side == 0) wo = -wx[bf.j * (g.mx + 1) + bf.i];
+    else if (bf.side == 1) wo = wx[bf.j * (g.mx + 1) + bf.i + 1];
+    else if (bf.side == 2) wo = -wy[bf.j * g.mx + bf.i];
+    else wo = wy[(bf.j + 1) * g.mx + bf.i];
+    wbnd[size_t(sub) * nb + f] = wo;
+  }
+  __syncthreads();
+  const int nd = sub_ndof(g, I, J);
+  for (int a = threadIdx.x; a < nd; a += 64) {
+    int f0, cnt;
+    dof_faces(g, I, J, a, &f0, &cnt);
+    double v = 0.0;
+    for (int xx = f0; xx < f0 + cnt; ++xx) {
+      const BFace ff = bface(g, I, J, xx);
+      const double wgt = (a & 1) ? 1.0 : -ff.sgn * robin_beta(g, ff, kmf(ff.i, ff.j));
       v += wgt * hsh[xx];
     }
     leaf_out(lo, sub, a, v);
@@ -814,6 +985,13 @@ void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const doub
                       const double* uym, const double* q, const double* fac, double* h, double* vbnd,
                       LeafOut lo, Runs rt) {
   MPM_LB_DISPATCH(k_mpm_local_lb, true, g, kn, km, uxm, uym, q, fac, h, vbnd, lo, rt.tab);
+}
+
+void launch_mpm_first(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
+                      const double* uym, const double* q, const double* fac, const double* y,
+                      const int32_t* sub_dofs, const double* ubnd, const double* vbnd, double* h, double* wbnd,
+                      LeafOut lo, Runs rt) {
+  MPM_LB_DISPATCH(k_mpm_first, true, g, kn, km, uxm, uym, q, fac, y, sub_dofs, ubnd, vbnd, h, wbnd, lo, rt.tab);
 }
 
 template <typename T>

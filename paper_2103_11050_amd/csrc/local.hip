@@ -138,7 +138,8 @@ __global__ void __launch_bounds__(256) k_dt(int nsub, const double* __restrict__
 // Reconstruction on every boundary face of every subdomain from the interface solution:
 // W u = h - S r with the Robin data r_f = -sgn beta_f U_l + P_l on Gamma faces (zero on
 // Dirichlet faces, whose data are in h); Neumann faces keep z. With with_v the MPM-2P flux
-// u-bar = u-hat_0 + v is returned.
+// u-bar = u-hat_0 + v is returned; with with_v = 2 the first-order u-hat_1 + w is added to ubnd
+// (Neumann faces unchanged).
 __global__ void __launch_bounds__(64)
 k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, const double* __restrict__ hg,
        const double* __restrict__ vbnd, const double* __restrict__ y, const int32_t* __restrict__ sub_dofs,
@@ -183,7 +184,11 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
       u = acc / bf.flen;
       if (with_v) u += vbnd[size_t(sub) * nb + f];
     }
-    ubnd[size_t(sub) * nb + f] = u;
+    if (with_v == 2) {
+      if (bf.kind != FACE_NEU) ubnd[size_t(sub) * nb + f] += u;
+    } else {
+      ubnd[size_t(sub) * nb + f] = u;
+    }
   }
 }
 

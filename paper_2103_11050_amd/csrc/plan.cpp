@@ -59,6 +59,9 @@ mpm_status validate(const mpm_desc& d, std::string* why) {
   if (d.sub_x + d.sub_y > 32) return bad("more than 64 boundary faces per subdomain");
   if (long(d.sub_y) * (d.sub_x + 1) > 272 || long(d.sub_y + 1) * d.sub_x > 272)
     return bad("more than 272 faces of one direction per subdomain");
+  if (d.mpm_order != 0 && d.mpm_order != 1) return bad("mpm_order must be 0 or 1");
+  if (d.mpm_order == 1 && d.precision != MPM_PREC_FP64) return bad("the first-order term is FP64 only");
+  if (d.reserved != 0) return bad("reserved must be 0");
   if (d.precision == MPM_PREC_FP32_REFINE && nc / band > 16)
     return bad("the precision form takes at most 16 lines per subdomain");
   if (2 * (2 * d.ne_x + 2 * d.ne_y) > 128) return bad("more than 128 interface unknowns per subdomain");
@@ -277,6 +280,7 @@ void build_plan(const mpm_desc& d, Plan* p) {
   P.off_red = take(P.n_red * 8);
   P.off_scal = take(SC_COUNT * 8 + 64);
   P.off_rtab = take(2 * sizeof(RunTab));
+  if (d.mpm_order == 1) P.off_wbnd = take(size_t(P.nsub) * P.nb * 8);
   P.total_bytes = off;
 }
 

@@ -96,6 +96,7 @@ struct Plan {
   size_t off_dslist = 0;              // the changed subdomains (count in the integer word after the error word)
   size_t off_red, off_scal;
   size_t off_rtab = 0;                // two run tables (batch groups led by this run)
+  size_t off_wbnd = 0;                // first-order term: w on the subdomains' boundary faces
   size_t n_red;               // doubles in the reduction scratch
   size_t total_bytes;
   int64_t front_doubles = 0, panel_doubles = 0, fI_doubles = 0, slot_doubles = 0;

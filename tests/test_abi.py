@@ -51,7 +51,7 @@ def test_workspace_size_valid(lib):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("abi_version", 2), ("nx", 0), ("sub_x", 5), ("ne_x", 3), ("alpha", 0.0), ("alpha", float("nan")),
+    ("abi_version", 1), ("mpm_order", 2), ("reserved", 1), ("nx", 0), ("sub_x", 5), ("ne_x", 3), ("alpha", 0.0), ("alpha", float("nan")),
     ("eta", float("nan")), ("cn", 0), ("mu_w", -1.0), ("cfl", 1.5), ("s_inj", 2.0), ("eps_norm", 7),
     ("switch_rule", 3), ("precision", 9), ("breakthrough_cut", 0.0), ("lx", -1.0),
 ])
@@ -87,6 +87,16 @@ def test_many_line_subdomains_accepted(lib, shape):
     cfg = inputs.config("c1", nx=nx, ny=ny, sub_x=mx, sub_y=my, ne_x=nex, ne_y=ney)
     st, size = _size(cfg)
     assert st == 0 and size > 0
+    st32, _ = _size(cfg, precision=binding.PREC_FP32_REFINE)
+    assert st32 == binding.MPM_EINVAL
+
+
+def test_first_order_term_is_fp64_only(lib):
+    cfg = inputs.config("c1", mpm_order=1)
+    st, n1 = _size(cfg)
+    assert st == 0
+    st0, n0 = _size(inputs.config("c1"))
+    assert st0 == 0 and n1 > n0            # room for w on the boundary faces
     st32, _ = _size(cfg, precision=binding.PREC_FP32_REFINE)
     assert st32 == binding.MPM_EINVAL
 

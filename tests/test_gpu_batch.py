@@ -186,7 +186,8 @@ def test_served_equals_alone(binding):
 # Runs with equal decompositions step as one group: one launch per phase for all of them; the
 # permeability, viscosities, cfl, eta and the epsilon norm may differ inside a group. Group A
 # mixes MRCM and MPM-2P updates in the same step (small eta) and differs in those parameters,
-# group B uses the text switch rule, group C the precision form; one run steps alone.
+# group B uses the text switch rule, group C the precision form, group D the first-order term;
+# one run steps alone.
 GROUPED = [
     # (seed, nx, ny, sub, ne, overrides, precision)
     (201, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=20.0, eta=0.01), 0),
@@ -197,6 +198,8 @@ GROUPED = [
     (206, 48, 32, 16, 4, dict(sigma2=2.0, corr_len=0.2, mu_o=30.0, eta=0.03), 1),
     (207, 48, 32, 16, 4, dict(sigma2=2.0, corr_len=0.2, mu_o=30.0, eta=0.03), 1),
     (208, 64, 64, 16, 8, dict(sigma2=4.0, corr_len=0.1, mu_o=100.0, eta=0.1), 0),
+    (209, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=20.0, eta=0.01, mpm_order=1), 0),
+    (210, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=25.0, eta=0.01, mpm_order=1), 0),
 ]
 
 

@@ -148,6 +148,18 @@ def test_many_line_subdomains_mixed(binding):
     assert "mpm" in branches[1:] and "mrcm" in branches[1:]
 
 
+@pytest.mark.parametrize("shape", [(32, 24, 8, 8, 2, 4), (12, 12, 4, 4, 4, 4), (60, 30, 20, 10, 4, 2),
+                                   (16, 10, 16, 10, 1, 1)])
+def test_first_order_term_matches_oracle(binding, shape):
+    """MPM-2P with the first-order term of eq:mpm_tf_4 (mpm_order = 1) against the oracle, with
+    MRCM updates mixed in (small eta), on square, one-face, many-line and single subdomains."""
+    nx, ny, mx, my, nex, ney = shape
+    cfg, K = inputs.random_problem(71 + nx, nx, ny, mx, my, nex, ney, sigma2=3.0, corr_len=0.15, eta=0.003,
+                                   mu_o=30.0, mpm_order=1)
+    orun = _compare_runs(binding, cfg, K, 14, f"first-order {shape}")
+    assert "mpm" in [h["branch"] for h in orun.history[1:]]
+
+
 def test_x4_finger_growth_config(binding):
     """The finger-growth workload (15 x 5 subdomains of 20 x 10, one fine face per element,
     perturbed initial front) against the oracle for the first elliptic steps."""
