@@ -219,6 +219,40 @@ def precision_form(binding, cfg, Kt, st, steps: int, warmup: int) -> dict:
             "note": "FP32 blocks applied in FP32, FP64 iterative refinement of every local solve"}
 
 
+def first_order_form(binding, cfg, Kt, st, steps: int, warmup: int) -> dict:
+    """MPM-2P with the first-order term of eq:mpm_tf_4 (mpm_order = 1) beside the zeroth-order
+    path on the same workload: its rate over `steps` steps and the relative difference of the two
+    velocities after them (the size of the term the paper neglects)."""
+    import torch
+
+    runs = {}
+    for order in (0, 1):
+        r = binding.Run(dict(cfg, mpm_order=order), Kt, st)
+        r.start()
+        for _ in range(warmup):
+            r.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r.step()
+        torch.cuda.synchronize()
+        runs[order] = (r, steps / (time.perf_counter() - t0))
+    (r0, v0), (r1, v1) = runs[0], runs[1]
+    ux0, uy0 = (t.cpu().numpy() for t in r0.velocity())
+    ux1, uy1 = (t.cpu().numpy() for t in r1.velocity())
+
+    def rt0(ux, uy):
+        return np.sum(ux[:, :-1] ** 2) + np.sum(ux[:, 1:] ** 2) + np.sum(uy[:-1, :] ** 2) + np.sum(uy[1:, :] ** 2)
+
+    diff = float(np.sqrt(rt0(ux1 - ux0, uy1 - uy0) / rt0(ux0, uy0)))
+    same = r0.stats()["tm"] == r1.stats()["tm"]
+    r0.close()
+    r1.close()
+    return {"value": round(v1, 2), "zeroth_order_value_same_window": round(v0, 2), "steps": steps,
+            "vel_rel_l2_first_minus_zeroth": diff, "same_basis_count": bool(same),
+            "note": "one more local solve per subdomain, interface solve and reconstruction per step"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,7 +262,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32-refine"], default="fp64",
                     help="local solves with FP64 blocks, or FP32 blocks with FP64 refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-precision-form", action="store_true",
+    ap.add_argument("--no-precision-form", action="store_true",  # also skips the first-order form
                     help="skip the side-by-side run of the FP32-block precision form")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--make-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -347,6 +381,8 @@ def main():
     run.close()
     if args.precision == "fp64" and not args.no_precision_form:
         out["precision_form"] = precision_form(binding, cfg, Kt, st, min(args.steps, 100), args.warmup)
+    if args.precision == "fp64" and not args.no_precision_form:
+        out["first_order_form"] = first_order_form(binding, cfg, Kt, st, min(args.steps, 100), args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, K)
     print(json.dumps(out))

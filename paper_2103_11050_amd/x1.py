@@ -7,7 +7,8 @@ available). For each contrast and each C_n the runs are:
 * the fine reference: MRCM with one fine face per interface element (H-bar = h), which is the
   undecomposed fine solution, recomputed at every elliptic step;
 * MRCM with H-bar = H and H / 2, basis recomputed at every elliptic step;
-* MPM-2P with H-bar = H and H / 2 (Algorithm 1, eta = 1e-2).
+* MPM-2P with H-bar = H and H / 2 (Algorithm 1, eta = 1e-2), and with --first-order also with
+  the first-order term of eq:mpm_tf_4.
 
 All runs take the same number of elliptic steps, each with its own CFL sub-step; after every
 step the relative L2(Omega) flux error and the relative L1(Omega) saturation error against the
@@ -48,7 +49,8 @@ def _norms(cfg, ux, uy):
                          np.sum(uy[1:, :] ** 2))
 
 
-def run_experiment(contrast: float, cn: int, max_steps: int = 20000, seed: int = 11, curves: bool = False) -> dict:
+def run_experiment(contrast: float, cn: int, max_steps: int = 20000, seed: int = 11, curves: bool = False,
+                   first_order: bool = False) -> dict:
     import torch
     dev = torch.device("cuda:0")
     base = inputs.x1_config(contrast, ne=1, cn=cn, seed=seed)
@@ -62,6 +64,9 @@ def run_experiment(contrast: float, cn: int, max_steps: int = 20000, seed: int =
         "MPM-2P H": (dict(ne_x=1, ne_y=1, eta=1e-2), binding.AUTO),
         "MPM-2P H/2": (dict(ne_x=2, ne_y=2, eta=1e-2), binding.AUTO),
     }
+    if first_order:   # with the first-order term of eq:mpm_tf_4, which the paper neglects
+        cases["MPM-2P H, l=1"] = (dict(ne_x=1, ne_y=1, eta=1e-2, mpm_order=1), binding.AUTO)
+        cases["MPM-2P H/2, l=1"] = (dict(ne_x=2, ne_y=2, eta=1e-2, mpm_order=1), binding.AUTO)
     runs = {}
     for name, (over, force) in cases.items():
         cfg = dict(base, **over)
@@ -116,11 +121,12 @@ def main(argv=None):
     ap.add_argument("--contrast", type=float, nargs="+", default=[1e3, 1e6])
     ap.add_argument("--cn", type=int, nargs="+", default=[1, 20])
     ap.add_argument("--max-steps", type=int, default=20000)
+    ap.add_argument("--first-order", action="store_true", help="also MPM-2P with the first-order term")
     args = ap.parse_args(argv)
     binding.load()
     for c in args.contrast:
         for cn in args.cn:
-            print(json.dumps(run_experiment(c, cn, args.max_steps)), flush=True)
+            print(json.dumps(run_experiment(c, cn, args.max_steps, first_order=args.first_order)), flush=True)
 
 
 if __name__ == "__main__":
