@@ -159,7 +159,7 @@ def host_cpu():
         return platform.processor()
 
 
-def cpu_baseline(cfg: dict, K: np.ndarray, steps: int = 20) -> dict:
+def cpu_baseline(cfg: dict, K: np.ndarray, steps: int = 40) -> dict:
     """The FP64 oracle, as it stands, on a bounded sample of the workload: the 256^2 corner
     window of the same permeability with the same subdomain size and interface elements,
     one initial MRCM update then `steps` MPM-2P steps timed; the rate is scaled by the cell
