@@ -18,7 +18,12 @@ Steps, in the paper's order:
 
 Interface spaces (Section 3.1, and the intermediate length H-bar of Section 5.1): each side
 of each subdomain that lies on Gamma is split into n_e equal elements, and U_H, P_H are
-piecewise constant on those elements (k_U = k_P = 1 per element). The global orientation of
+piecewise constant on those elements (k_U = k_P = 1 per element), or, with iface_degree = 1,
+piecewise linear (k_U = k_P = 2: the -POL spaces of Section 5.2), with the basis 1 and xi on
+each element, xi in [-1, 1] along the global direction of the interface, projected onto the
+fine faces by their midpoint values (the face average of a linear function). Per element the
+unknowns are U_0 .. U_{k-1} then P_0 .. P_{k-1}; the flux equations are tested with each
+pressure function and the Robin equations with each flux function (eq:mrc2). The global orientation of
 the skeleton is n-check = +x on vertical interfaces and +y on horizontal ones, so n-check .
 n-check^i = +1 for the subdomain on the left or below and -1 for the other one.
 Physical-boundary sides carry their physical condition and no interface unknown.
@@ -52,6 +57,10 @@ class Decomposition:
         self.n_vert = (self.Sx - 1) * self.Sy * self.ne_y
         self.n_horiz = self.Sx * (self.Sy - 1) * self.ne_x
         self.n_elem = self.n_vert + self.n_horiz
+        self.npol = cfg.get("iface_degree", 0) + 1        # k_U = k_P
+        assert self.npol == 1 or (self.mx // self.ne_x >= 2 and self.my // self.ne_y >= 2), \
+            "a linear interface function needs at least two faces per element"
+        self.n_dof = 2 * self.npol * self.n_elem
 
     def vert_elem(self, I, J, k):
         """Element k of the vertical interface between subdomains (I, J) and (I+1, J)."""
@@ -65,20 +74,33 @@ class Decomposition:
         return J * self.my, (J + 1) * self.my, I * self.mx, (I + 1) * self.mx
 
     def interface_sides(self, I, J):
-        """Per side: None on the physical boundary, else (element of each face, n.n^i, H)."""
+        """Per side: None on the physical boundary, else (element of each face, n.n^i, H,
+        values of the element's basis functions at each face, shape (npol, faces))."""
         res = [None, None, None, None]
-        fy = np.arange(self.my) // (self.my // self.ne_y)
-        fx = np.arange(self.mx) // (self.mx // self.ne_x)
+        py, px = self.my // self.ne_y, self.mx // self.ne_x
+        fy, fx = np.arange(self.my) // py, np.arange(self.mx) // px
+        xiy = (2 * (np.arange(self.my) % py) + 1) / py - 1.0
+        xix = (2 * (np.arange(self.mx) % px) + 1) / px - 1.0
+        phy = np.stack([np.ones(self.my), xiy][:self.npol])
+        phx = np.stack([np.ones(self.mx), xix][:self.npol])
         Hx, Hy = self.mx * self.hx, self.my * self.hy
         if I > 0:
-            res[W] = (self.vert_elem(I - 1, J, fy), -1.0, Hx)
+            res[W] = (self.vert_elem(I - 1, J, fy), -1.0, Hx, phy)
         if I < self.Sx - 1:
-            res[E] = (self.vert_elem(I, J, fy), +1.0, Hx)
+            res[E] = (self.vert_elem(I, J, fy), +1.0, Hx, phy)
         if J > 0:
-            res[S] = (self.horiz_elem(I, J - 1, fx), -1.0, Hy)
+            res[S] = (self.horiz_elem(I, J - 1, fx), -1.0, Hy, phx)
         if J < self.Sy - 1:
-            res[N] = (self.horiz_elem(I, J, fx), +1.0, Hy)
+            res[N] = (self.horiz_elem(I, J, fx), +1.0, Hy, phx)
         return res
+
+    def u_dof(self, l, k):
+        """Global index of the k-th flux unknown of element l (row of its Robin equation)."""
+        return 2 * self.npol * l + k
+
+    def p_dof(self, l, k):
+        """Global index of the k-th pressure unknown of element l (row of its flux equation)."""
+        return 2 * self.npol * l + self.npol + k
 
     def subdomains(self):
         for J in range(self.Sy):
@@ -121,28 +143,30 @@ def robin_sides(dec: Decomposition, I, J, kap, phys: list, alpha: float):
 
 
 def local_dofs(dec: Decomposition, iface):
-    """Global interface unknowns touching a subdomain: per element, U then P."""
+    """Global interface unknowns touching a subdomain: per element, the U then the P ones."""
     dofs = []
     for sd in (W, E, S, N):
         if iface[sd] is None:
             continue
         for l in np.unique(iface[sd][0]):
-            dofs += [2 * l, 2 * l + 1]
+            dofs += [dec.u_dof(l, k) for k in range(dec.npol)] + [dec.p_dof(l, k) for k in range(dec.npol)]
     return np.array(dofs, dtype=np.int64)
 
 
-def homogeneous_data(sides, iface, dof: int):
+def homogeneous_data(sides, iface, dof: int, npol: int = 1):
     """Robin data of the homogeneous basis function of one interface unknown
-    (eq:mrc_homogeneous with unit coefficient): r = -beta n.n^i on the faces of element l
-    for U_l, r = 1 for P_l, zero elsewhere; zero physical data."""
-    l, is_p = dof // 2, dof % 2
+    (eq:mrc_homogeneous with unit coefficient): r = -beta n.n^i phi_k on the faces of element l
+    for U_{l,k}, r = psi_k for P_{l,k}, zero elsewhere; zero physical data."""
+    l, j = dof // (2 * npol), dof % (2 * npol)
+    is_p, k = j >= npol, j % npol
     out = []
     for sd in (W, E, S, N):
         s = sides[sd]
         datum = np.zeros_like(s.datum)
         if iface[sd] is not None:
             on = iface[sd][0] == l
-            datum = np.where(on, 1.0 if is_p else -s.beta * iface[sd][1], 0.0)
+            ph = iface[sd][3][k]
+            datum = np.where(on, ph if is_p else -s.beta * iface[sd][1] * ph, 0.0)
         out.append(Side(s.kind, s.beta, datum))
     return out
 
@@ -158,7 +182,7 @@ def build_local_basis(dec: Decomposition, I, J, kap_global, alpha: float) -> Loc
     dofs = local_dofs(dec, iface)
     zero_q = np.zeros_like(kap)
     if len(dofs):
-        B = np.stack([block_rhs(kap, dec.hx, dec.hy, homogeneous_data(sides, iface, d), zero_q)
+        B = np.stack([block_rhs(kap, dec.hx, dec.hy, homogeneous_data(sides, iface, d, dec.npol), zero_q)
                       for d in dofs], axis=1)
         P = lu.solve(B).T
     else:
@@ -167,7 +191,7 @@ def build_local_basis(dec: Decomposition, I, J, kap_global, alpha: float) -> Loc
     uy = np.zeros((len(dofs), dec.my + 1, dec.mx))
     outs = [np.zeros((len(dofs), dec.my if sd in (W, E) else dec.mx)) for sd in (W, E, S, N)]
     for k, d in enumerate(dofs):
-        hs = homogeneous_data(sides, iface, d)
+        hs = homogeneous_data(sides, iface, d, dec.npol)
         ux[k], uy[k], o = block_fluxes(kap, dec.hx, dec.hy, hs, P[k])
         for sd in (W, E, S, N):
             outs[sd][k] = o[sd]
@@ -195,43 +219,47 @@ def nonhomogeneous_solve(dec: Decomposition, lb: LocalBasis, phys: list, q_loc):
 def interface_rows(dec: Decomposition, lb: LocalBasis, out_sides, dim_cols):
     """Contributions of one subdomain's traces to the interface equations (eq:mrc2).
 
-    For every element l on the subdomain's interface sides:
-      flux equation   F_l += sum_{f in l} |f| u_f
-      Robin equation  G_l += (n.n^i) sum_{f in l} |f| beta_f u_f
-    ``out_sides[sd]`` has shape (ncols, faces). Rows 2l hold G_l, rows 2l+1 hold F_l.
-    Returns a list of (row, col, value) arrays.
+    For every element l on the subdomain's interface sides and every basis function k:
+      flux equation   F_{l,k} += sum_{f in l} |f| u_f psi_k(f)
+      Robin equation  G_{l,k} += (n.n^i) sum_{f in l} |f| beta_f u_f phi_k(f)
+    ``out_sides[sd]`` has shape (ncols, faces). Row u_dof(l, k) holds G_{l,k}, row p_dof(l, k)
+    holds F_{l,k}. Returns a list of (row, col, value) arrays.
     """
     rows, cols, vals = [], [], []
     for sd in (W, E, S, N):
         if lb.iface[sd] is None:
             continue
-        elem, s, _ = lb.iface[sd]
+        elem, s, _, ph = lb.iface[sd]
         _, flen = side_geometry(dec.hx, dec.hy, sd)
         u = out_sides[sd]                           # (ncols, faces)
         ncols = u.shape[0]
         for l in np.unique(elem):
             on = elem == l
-            F = flen * u[:, on].sum(axis=1)
-            G = s * flen * (u[:, on] * lb.betas[sd][on]).sum(axis=1)
-            rows += [np.full(ncols, 2 * l + 1), np.full(ncols, 2 * l)]
-            cols += [dim_cols, dim_cols]
-            vals += [F, G]
+            for k in range(dec.npol):
+                F = flen * (u[:, on] * ph[k][on]).sum(axis=1)
+                G = s * flen * (u[:, on] * lb.betas[sd][on] * ph[k][on]).sum(axis=1)
+                rows += [np.full(ncols, dec.p_dof(l, k)), np.full(ncols, dec.u_dof(l, k))]
+                cols += [dim_cols, dim_cols]
+                vals += [F, G]
     return rows, cols, vals
 
 
 def robin_diagonal(dec: Decomposition, lb: LocalBasis):
-    """The -sum_{f in l} |f| beta_f U_l term of G_l contributed by one side (eq:mrc2)."""
+    """The -sum_{f in l} |f| beta_f U_H(f) phi_k(f) term of G_{l,k} contributed by one side
+    (eq:mrc2): coefficient -sum_f |f| beta_f phi_k phi_k' of U_{l,k'}."""
     rows, cols, vals = [], [], []
     for sd in (W, E, S, N):
         if lb.iface[sd] is None:
             continue
-        elem, s, _ = lb.iface[sd]
+        elem, s, _, ph = lb.iface[sd]
         _, flen = side_geometry(dec.hx, dec.hy, sd)
         for l in np.unique(elem):
             on = elem == l
-            rows.append(np.array([2 * l]))
-            cols.append(np.array([2 * l]))
-            vals.append(np.array([-flen * lb.betas[sd][on].sum()]))
+            for k in range(dec.npol):
+                for k2 in range(dec.npol):
+                    rows.append(np.array([dec.u_dof(l, k)]))
+                    cols.append(np.array([dec.u_dof(l, k2)]))
+                    vals.append(np.array([-flen * (lb.betas[sd][on] * ph[k][on] * ph[k2][on]).sum()]))
     return rows, cols, vals
 
 
@@ -242,7 +270,7 @@ class MRCMBasis:
     dec: Decomposition
     kappa: np.ndarray
     locals: list
-    M: sp.csc_matrix           # interface matrix, rows 2l = G_l, 2l+1 = F_l
+    M: sp.csc_matrix           # interface matrix, rows u_dof = G, p_dof = F
     lu: object
 
 
@@ -250,7 +278,7 @@ def build_basis(cfg, kappa) -> MRCMBasis:
     dec = Decomposition(cfg)
     alpha = cfg["alpha"]
     locs = [build_local_basis(dec, I, J, kappa, alpha) for I, J in dec.subdomains()]
-    nd = 2 * dec.n_elem
+    nd = dec.n_dof
     rows, cols, vals = [], [], []
     for lb in locs:
         r, c, v = interface_rows(dec, lb, lb.out, lb.dofs)
@@ -283,7 +311,7 @@ def solve_with_basis(basis: MRCMBasis, phys_of, q_of) -> MRCMSolution:
     ``phys_of(I, J)`` gives the physical side data of a subdomain; ``q_of(I, J)`` its source.
     """
     dec = basis.dec
-    nd = 2 * dec.n_elem
+    nd = dec.n_dof
     nh = []
     c = np.zeros(nd)
     for lb in basis.locals:

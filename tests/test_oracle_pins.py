@@ -160,6 +160,69 @@ def test_T5_horizontal_interfaces_not_exact_for_long_elements():
 
 # ---------------------------------------------------------------- T6: local Robin map
 
+def test_POL_homogeneous_flow_along_interfaces_exact():
+    """Linear interface spaces (-POL) carry the linear pressure trace along horizontal
+    interfaces in a homogeneous medium with flow along them, so MRCM-POL reproduces the fine
+    solution with whole-side elements, where constant spaces cannot."""
+    cfg, _ = _problem(3, 16, 12, 4, 4, 1, 1, alpha=1.0)
+    cfg["bc_kind"] = [1, 1, 0, 0]; cfg["bc_value"] = [1.0, 0.0, 0.0, 0.0]
+    kap = np.full((12, 16), 2.0)
+    _, ux, uy = fine.fine_solve(cfg, kap)
+    u1, v1, _, d = mpm.mrcm_velocity(dict(cfg, iface_degree=1), kap)
+    assert np.abs(d["ux_bar"] - ux).max() < 1e-12 * np.abs(ux).max()
+    assert np.abs(d["uy_bar"]).max() < 1e-12 * np.abs(ux).max()
+    _, _, _, d0 = mpm.mrcm_velocity(cfg, kap)
+    assert np.abs(d0["ux_bar"] - ux).max() > 1e-6 * np.abs(ux).max()
+
+
+def test_POL_interface_system_and_weak_continuity():
+    """-POL: the interface matrix with the Robin rows negated is symmetric with a positive
+    definite flux block and a negative definite pressure block, and both compatibility
+    conditions (eq:compatibility) hold against the constant and the linear function of every
+    element."""
+    cfg, K, kap = _mrcm_case()
+    cfg = dict(cfg, iface_degree=1)
+    b = mrcm.build_basis(cfg, kap)
+    dec = b.dec
+    M = b.M.toarray()
+    isu = np.array([(j % (2 * dec.npol)) < dec.npol for j in range(M.shape[0])])
+    sgn = np.where(isu, -1.0, 1.0)
+    Ms = sgn[:, None] * M
+    assert np.abs(Ms - Ms.T).max() <= 1e-13 * np.abs(Ms).max()
+    assert np.linalg.eigvalsh(Ms[np.ix_(isu, isu)]).min() > 0
+    assert np.linalg.eigvalsh(Ms[np.ix_(~isu, ~isu)]).max() < 0
+    sol = mrcm.solve_with_basis(b, mrcm.physical_data(cfg), lambda I, J: np.zeros((4, 4)))
+    flux = np.zeros((dec.n_elem, 2))
+    pint = np.zeros((dec.n_elem, 2))
+    scale_u = scale_p = 0.0
+    for k, lb in enumerate(b.locals):
+        for sd in (W, E, S, N):
+            if lb.iface[sd] is None:
+                continue
+            elem, s, _, ph = lb.iface[sd]
+            _, flen = fine.side_geometry(dec.hx, dec.hy, sd)
+            u = sol.out[k][sd]
+            UH = sum(sol.y[dec.u_dof(elem, q)] * ph[q] for q in range(2))
+            PH = sum(sol.y[dec.p_dof(elem, q)] * ph[q] for q in range(2))
+            pf = -lb.betas[sd] * s * UH + PH + lb.betas[sd] * u
+            for q in range(2):
+                np.add.at(flux[:, q], elem, flen * u * ph[q])
+                np.add.at(pint[:, q], elem, s * flen * pf * ph[q])
+            scale_u = max(scale_u, np.abs(flen * u).max())
+            scale_p = max(scale_p, np.abs(flen * pf).max())
+    assert np.abs(flux).max() < 1e-12 * scale_u
+    assert np.abs(pint).max() < 1e-12 * scale_p
+
+
+def test_POL_basis_count():
+    """-POL doubles the homogeneous basis functions: 4 (k_U + k_P) per interface side."""
+    cfg, K, kap = _mrcm_case()
+    b0 = mrcm.build_basis(cfg, kap)
+    b1 = mrcm.build_basis(dict(cfg, iface_degree=1), kap)
+    assert sum(len(lb.dofs) for lb in b1.locals) == 2 * sum(len(lb.dofs) for lb in b0.locals)
+    assert b1.M.shape[0] == 2 * b0.M.shape[0]
+
+
 def test_T6_robin_to_flux_map_symmetric_psd_and_superposition():
     cfg, K = _problem(11, 12, 12, 6, 6, 3, 2)
     kap = physics.conductivity(np.full_like(K, 0.5), K, 1.0, 10.0)
@@ -173,7 +236,7 @@ def test_T6_robin_to_flux_map_symmetric_psd_and_superposition():
         for sd in (W, E, S, N):
             if lb.iface[sd] is None:
                 continue
-            elem, s, _ = lb.iface[sd]
+            elem, s, _, _ = lb.iface[sd]
             _, flen = fine.side_geometry(dec.hx, dec.hy, sd)
             for a, da in enumerate(lb.dofs):
                 for b, db in enumerate(lb.dofs):
@@ -199,7 +262,7 @@ def test_T6_robin_to_flux_map_symmetric_psd_and_superposition():
             if lb.iface[sd] is None:
                 sides.append(phys[sd])
             else:
-                elem, s, _ = lb.iface[sd]
+                elem, s, _, _ = lb.iface[sd]
                 r = -lb.betas[sd] * s * sol.y[2 * elem] + sol.y[2 * elem + 1]
                 sides.append(Side(np.full(len(r), ROB), lb.betas[sd], r))
         A = fine.block_matrix(lb.kap, dec.hx, dec.hy, sides)
@@ -264,7 +327,7 @@ def test_T9_weak_continuity():
         for sd in (W, E, S, N):
             if lb.iface[sd] is None:
                 continue
-            elem, s, _ = lb.iface[sd]
+            elem, s, _, _ = lb.iface[sd]
             _, flen = fine.side_geometry(dec.hx, dec.hy, sd)
             u = sol.out[k][sd]
             r = -lb.betas[sd] * s * sol.y[2 * elem] + sol.y[2 * elem + 1]
@@ -519,12 +582,16 @@ def test_T18_oracle_bf_count_matches_formula():
 
 def _monolithic_mrcm(cfg, kap):
     """All cell pressures and all interface unknowns in one sparse system, written face by
-    face: local two-point fluxes with Robin faces on Gamma, and the two interface equations
-    of eq:mrc2 per element. Independent of the basis-function machinery."""
+    face: local two-point fluxes with Robin faces on Gamma, and the interface equations
+    of eq:mrc2 per element and basis function (constants, or with iface_degree = 1 also the
+    linear function of the face midpoint). Independent of the basis-function machinery."""
     dec = mrcm.Decomposition(cfg)
     nx, ny, hx, hy = dec.nx, dec.ny, dec.hx, dec.hy
     nc = nx * ny
-    nu = 2 * dec.n_elem
+    npl = cfg.get("iface_degree", 0) + 1
+    nu = 2 * npl * dec.n_elem
+    Ui = lambda l, k: nc + 2 * npl * l + k          # flux unknown k of element l (row: Robin equation)
+    Pi = lambda l, k: nc + 2 * npl * l + npl + k    # pressure unknown k (row: flux equation)
     A = sp.lil_matrix((nc + nu, nc + nu))
     b = np.zeros(nc + nu)
     alpha = cfg["alpha"]
@@ -546,19 +613,28 @@ def _monolithic_mrcm(cfg, kap):
             if di:
                 side_s = 1.0 if di > 0 else -1.0
                 Iv = I if di > 0 else I - 1
-                k = (j % dec.my) // (dec.my // dec.ne_y)
+                per = dec.my // dec.ne_y
+                k = (j % dec.my) // per
+                pos = (j % dec.my) % per
                 l = dec.vert_elem(Iv, J, k)
                 H = dec.mx * hx
             else:
                 side_s = 1.0 if dj > 0 else -1.0
                 Jh = J if dj > 0 else J - 1
-                k = (i % dec.mx) // (dec.mx // dec.ne_x)
+                per = dec.mx // dec.ne_x
+                k = (i % dec.mx) // per
+                pos = (i % dec.mx) % per
                 l = dec.horiz_elem(I, Jh, k)
                 H = dec.my * hy
+            phi = [1.0, (pos + 0.5) / per * 2.0 - 1.0][:npl]    # 1 and xi at the face midpoint
             beta = alpha * H / kc
             t = 1.0 / (d / (2 * kc) + beta)
-            # u = t (p_c - r), r = -beta s U + P
-            return {c: t, nc + 2 * l: t * beta * side_s, nc + 2 * l + 1: -t}, 0.0, (l, side_s, beta)
+            # u = t (p_c - r), r = sum_k (-beta s U_k + P_k) phi_k
+            co = {c: t}
+            for q in range(npl):
+                co[Ui(l, q)] = t * beta * side_s * phi[q]
+                co[Pi(l, q)] = -t * phi[q]
+            return co, 0.0, (l, side_s, beta, phi)
         sd = W if di < 0 else E if di > 0 else S if dj < 0 else N
         kind, val = cfg["bc_kind"][sd], cfg["bc_value"][sd]
         if kind == 1:
@@ -576,20 +652,26 @@ def _monolithic_mrcm(cfg, kap):
                     A[c, k] += flen * v
                 b[c] -= flen * const
                 if rob is not None:
-                    l, s, beta = rob
-                    for k, v in coefs.items():
-                        A[nc + 2 * l + 1, k] += flen * v              # F_l
-                        A[nc + 2 * l, k] += s * flen * beta * v       # G_l
-                    A[nc + 2 * l, nc + 2 * l] += -flen * beta          # -|f| beta U_l
+                    l, s, beta, phi = rob
+                    for q in range(npl):
+                        for k, v in coefs.items():
+                            A[Pi(l, q), k] += flen * v * phi[q]               # F_{l,q}
+                            A[Ui(l, q), k] += s * flen * beta * v * phi[q]    # G_{l,q}
+                        for q2 in range(npl):                                 # -|f| beta U_H phi_q
+                            A[Ui(l, q), Ui(l, q2)] += -flen * beta * phi[q] * phi[q2]
     x = spla.spsolve(A.tocsc(), b)
     return x[:nc].reshape(ny, nx), x[nc:]
 
 
+@pytest.mark.parametrize("degree", [0, 1])
 @pytest.mark.parametrize("shape", [(4, 4, 2, 2, 1, 1), (6, 4, 2, 2, 2, 1), (6, 6, 3, 3, 3, 1),
-                                   (6, 6, 2, 3, 1, 3), (4, 6, 2, 3, 2, 3), (6, 6, 6, 6, 1, 1)])
-def test_T19_brute_force_monolithic(shape):
+                                   (6, 6, 2, 3, 1, 3), (4, 6, 2, 3, 2, 3), (6, 6, 6, 6, 1, 1),
+                                   (12, 8, 4, 4, 1, 2), (9, 6, 3, 3, 1, 1)])
+def test_T19_brute_force_monolithic(shape, degree):
     nx, ny, mx, my, nex, ney = shape
-    cfg, K = _problem(23 + nx + 10 * my, nx, ny, mx, my, nex, ney, sigma2=3.0, alpha=0.7)
+    if degree == 1 and (mx // nex < 2 or my // ney < 2):
+        pytest.skip("a linear function needs at least two faces per element")
+    cfg, K = _problem(23 + nx + 10 * my, nx, ny, mx, my, nex, ney, sigma2=3.0, alpha=0.7, iface_degree=degree)
     cfg["bc_kind"] = [2, 1, 0, 1]; cfg["bc_value"] = [-1.0, 0.0, 0.0, 0.3]
     kap = physics.conductivity(np.full_like(K, 0.4), K, 1.0, 10.0)
     p_ref, y_ref = _monolithic_mrcm(cfg, kap)
@@ -653,7 +735,7 @@ def test_planted_mistakes_are_caught(monkeypatch):
     def same_sign(self, I, J):
         # forgetting n.n^i: both sides of an interface take +1
         res = orig_sides(self, I, J)
-        return [None if r is None else (r[0], 1.0, r[2]) for r in res]
+        return [None if r is None else (r[0], 1.0, r[2], r[3]) for r in res]
     monkeypatch.setattr(mrcm.Decomposition, "interface_sides", same_sign)
     # the sign enters the basis data and the test functions alike, so the interface matrix
     # stays symmetric; the exactness pin is what catches it
