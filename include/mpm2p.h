@@ -96,7 +96,11 @@ typedef struct mpm_desc {
                                  paper's runs) or 1 (also eq:mpm_tf_4 with l = 1: one more local
                                  solve per subdomain, interface solve and reconstruction per
                                  step; FP64 only) */
-  int32_t reserved;           /* 0 */
+  int32_t iface_degree;       /* interface spaces (Section 3.1; -POL of Section 5.2): 0 piecewise
+                                 constant U_H, P_H per element (k_U = k_P = 1), 1 piecewise linear
+                                 (k_U = k_P = 2: the functions 1 and xi, xi in [-1, 1] along the
+                                 element in the global direction, taken at the fine face
+                                 midpoints; needs at least two fine faces per element) */
 } mpm_desc;
 
 typedef struct mpm_stats {

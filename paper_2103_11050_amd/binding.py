@@ -35,7 +35,7 @@ class Desc(ctypes.Structure):
         ("bc_kind", ctypes.c_int32 * 4), ("bc_value", ctypes.c_double * 4),
         ("s_inj", ctypes.c_double), ("cfl", ctypes.c_double),
         ("breakthrough_cut", ctypes.c_double),
-        ("mpm_order", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("mpm_order", ctypes.c_int32), ("iface_degree", ctypes.c_int32),
     ]
 
 
@@ -137,6 +137,7 @@ def make_desc(cfg: dict, precision: int = PREC_FP64) -> Desc:
     d.cfl = cfg["cfl"]
     d.breakthrough_cut = cfg["breakthrough_cut"]
     d.mpm_order = int(cfg.get("mpm_order", 0))
+    d.iface_degree = int(cfg.get("iface_degree", 0))
     return d
 
 

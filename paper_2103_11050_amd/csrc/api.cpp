@@ -166,7 +166,7 @@ Geo make_geo(const Plan& P) {
   Geo g{};
   g.nx = P.nx; g.ny = P.ny; g.mx = P.mx; g.my = P.my; g.Sx = P.Sx; g.Sy = P.Sy; g.nsub = P.nsub;
   g.nc = P.nc; g.band = P.band; g.xfast = P.xfast; g.nb = P.nb; g.ne_x = P.ne_x; g.ne_y = P.ne_y;
-  g.n_vert = P.n_vert; g.ndmax = P.ndmax;
+  g.n_vert = P.n_vert; g.ndmax = P.ndmax; g.npol = P.npol;
   g.hx = P.hx; g.hy = P.hy; g.alpha = P.d.alpha;
   g.bc_pack = 0;
   for (int k = 0; k < 4; ++k) g.bc_pack |= (P.d.bc_kind[k] & 3) << (2 * k);
@@ -821,7 +821,7 @@ std::string group_key(const mpm_run* r) {
   put(&d.abi_version, 4); put(&d.nx, 4); put(&d.ny, 4); put(&d.lx, 8); put(&d.ly, 8);
   put(&d.sub_x, 4); put(&d.sub_y, 4); put(&d.ne_x, 4); put(&d.ne_y, 4); put(&d.alpha, 8);
   put(&d.switch_rule, 4); put(&d.precision, 4); put(&d.cn, 4); put(d.bc_kind, 16); put(d.bc_value, 32);
-  put(&d.s_inj, 8); put(&d.mpm_order, 4);
+  put(&d.s_inj, 8); put(&d.mpm_order, 4); put(&d.iface_degree, 4);
   k.push_back(r->s == r->s_base ? 0 : 1);
   return k;
 }

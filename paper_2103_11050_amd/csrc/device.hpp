@@ -14,6 +14,7 @@ namespace mpm {
 struct Geo {
   int nx, ny, mx, my, Sx, Sy, nsub;
   int nc, band, xfast, nb, ne_x, ne_y, n_vert, ndmax;
+  int npol;             // interface functions per element and field: 1 constant, 2 linear
   double hx, hy, alpha;
   int bc_pack;          // MPM_BC_* of side s in bits 2s..2s+1 (sides W, E, S, N)
   double bc_v0, bc_v1, bc_v2, bc_v3;
@@ -94,38 +95,65 @@ __host__ __device__ __forceinline__ BFace bface(const Geo& g, int I, int J, int 
   return b;
 }
 
-// Local position of the U unknown of the element of a Gamma face (P is the next one).
-__host__ __device__ __forceinline__ int bface_dof(const Geo& g, int I, int J, const BFace& b) {
-  const bool hasW = I > 0, hasE = I < g.Sx - 1, hasS = J > 0;
-  const int offW = 0;
-  const int offE = offW + (hasW ? 2 * g.ne_y : 0);
-  const int offS = offE + (hasE ? 2 * g.ne_y : 0);
-  const int offN = offS + (hasS ? 2 * g.ne_x : 0);
-  const int off = b.side == 0 ? offW : b.side == 1 ? offE : b.side == 2 ? offS : offN;
-  const int per = b.side < 2 ? g.my / g.ne_y : g.mx / g.ne_x;
-  return off + 2 * (b.k / per);
+// Local interface unknowns of a subdomain: sides W, E, S, N present on Gamma, the elements
+// along each side in order, per element U_0 .. U_{npol-1} then P_0 .. P_{npol-1}.
+__host__ __device__ __forceinline__ int faces_per_elem(const Geo& g, int side) {
+  return side < 2 ? g.my / g.ne_y : g.mx / g.ne_x;
 }
 
-// First boundary face and face count of the element carrying local interface unknown a
-// (local order: sides W, E, S, N present on Gamma, elements along each side, U then P).
+// Local position of the U_0 unknown of the element of a Gamma face (U_k at +k, P_k at +npol+k).
+__host__ __device__ __forceinline__ int bface_dof(const Geo& g, int I, int J, const BFace& b) {
+  const bool hasW = I > 0, hasE = I < g.Sx - 1, hasS = J > 0;
+  const int pe = 2 * g.npol;
+  const int offW = 0;
+  const int offE = offW + (hasW ? pe * g.ne_y : 0);
+  const int offS = offE + (hasE ? pe * g.ne_y : 0);
+  const int offN = offS + (hasS ? pe * g.ne_x : 0);
+  const int off = b.side == 0 ? offW : b.side == 1 ? offE : b.side == 2 ? offS : offN;
+  return off + pe * (b.k / faces_per_elem(g, b.side));
+}
+
+// First boundary face and face count of the element carrying local interface unknown a.
 __host__ __device__ __forceinline__ void dof_faces(const Geo& g, int I, int J, int a, int* f0, int* cnt) {
   const bool hasW = I > 0, hasE = I < g.Sx - 1, hasS = J > 0, hasN = J < g.Sy - 1;
-  const int nW = hasW ? 2 * g.ne_y : 0, nE = hasE ? 2 * g.ne_y : 0, nS = hasS ? 2 * g.ne_x : 0;
-  const int nN = hasN ? 2 * g.ne_x : 0;
+  const int pe = 2 * g.npol;
+  const int nW = hasW ? pe * g.ne_y : 0, nE = hasE ? pe * g.ne_y : 0, nS = hasS ? pe * g.ne_x : 0;
+  const int nN = hasN ? pe * g.ne_x : 0;
   const int perY = g.my / g.ne_y, perX = g.mx / g.ne_x;
-  if (a < nW) { *f0 = (a / 2) * perY; *cnt = perY; return; }
+  if (a < nW) { *f0 = (a / pe) * perY; *cnt = perY; return; }
   a -= nW;
-  if (a < nE) { *f0 = g.my + (a / 2) * perY; *cnt = perY; return; }
+  if (a < nE) { *f0 = g.my + (a / pe) * perY; *cnt = perY; return; }
   a -= nE;
-  if (a < nS) { *f0 = 2 * g.my + (a / 2) * perX; *cnt = perX; return; }
+  if (a < nS) { *f0 = 2 * g.my + (a / pe) * perX; *cnt = perX; return; }
   a -= nS;
-  if (a < nN) { *f0 = 2 * g.my + g.mx + (a / 2) * perX; *cnt = perX; return; }
+  if (a < nN) { *f0 = 2 * g.my + g.mx + (a / pe) * perX; *cnt = perX; return; }
   *f0 = 0;
   *cnt = 0;
 }
 
+// Field (P or U) and function index k of local interface unknown a.
+__host__ __device__ __forceinline__ void dof_kind(const Geo& g, int a, bool* is_p, int* k) {
+  if (g.npol == 1) {
+    *is_p = a & 1;
+    *k = 0;
+    return;
+  }
+  const int r = a % (2 * g.npol);
+  *is_p = r >= g.npol;
+  *k = r >= g.npol ? r - g.npol : r;
+}
+
+// Interface function k of a Gamma face's element at the face: 1 for k = 0; for k = 1 the
+// midpoint xi in [-1, 1] of the face along the element (the face mean of the linear function;
+// the global direction of the interface, so both subdomains see the same value).
+__host__ __device__ __forceinline__ double iface_phi(const Geo& g, const BFace& b, int k) {
+  if (k == 0) return 1.0;
+  const int per = faces_per_elem(g, b.side);
+  return double(2 * (b.k % per) + 1) / per - 1.0;
+}
+
 __host__ __device__ __forceinline__ int sub_ndof(const Geo& g, int I, int J) {
-  return 2 * ((I > 0) + (I < g.Sx - 1)) * g.ne_y + 2 * ((J > 0) + (J < g.Sy - 1)) * g.ne_x;
+  return 2 * g.npol * (((I > 0) + (I < g.Sx - 1)) * g.ne_y + ((J > 0) + (J < g.Sy - 1)) * g.ne_x);
 }
 
 // Transmissibility per unit length of a boundary face for conductivity kc of its cell.
@@ -136,6 +164,29 @@ __host__ __device__ __forceinline__ double bface_trans(const Geo& g, const BFace
 }
 __host__ __device__ __forceinline__ double robin_beta(const Geo& g, const BFace& b, double kc) {
   return g.alpha * b.H / kc;
+}
+// Restriction B^T of boundary-face quantities to local interface unknown a (eq:mrc2, Robin
+// rows negated), which is also the Robin datum of a's homogeneous basis function: the U_k
+// unknown -sgn beta_f phi_k(f), the P_k unknown phi_k(f), on the faces of its element.
+__host__ __device__ __forceinline__ double bweight(const Geo& g, const BFace& f, int a, double kc) {
+  bool is_p;
+  int k;
+  dof_kind(g, a, &is_p, &k);
+  const double w = is_p ? 1.0 : -f.sgn * robin_beta(g, f, kc);
+  return k ? w * iface_phi(g, f, k) : w;
+}
+// Robin datum -sgn beta_f U_H(f) + P_H(f) of a Gamma face from the interface solution y
+// (dofs: the subdomain's global unknown ids in local order).
+__device__ __forceinline__ double robin_datum(const Geo& g, int I, int J, const BFace& bf, double kc,
+                                              const int32_t* dofs, const double* y) {
+  const int a = bface_dof(g, I, J, bf);
+  double U = y[dofs[a]], Pv = y[dofs[a + g.npol]];
+  if (g.npol == 2) {
+    const double xi = iface_phi(g, bf, 1);
+    U += xi * y[dofs[a + 1]];
+    Pv += xi * y[dofs[a + 3]];
+  }
+  return -bf.sgn * robin_beta(g, bf, kc) * U + Pv;
 }
 // Harmonic transmissibility per unit length between two cells at distance d:
 // (d/(2 kc) + d/(2 kd))^-1 = 2 kc kd / (d (kc + kd)), one division.

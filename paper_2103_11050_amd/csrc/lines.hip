@@ -582,7 +582,7 @@ k_mpm_local_lb(Geo g0, const double* __restrict__ kap_n, const double* __restric
     hg[size_t(sub) * nb + f] = h;
   }
   __syncthreads();
-  // interface right-hand side B^T h: U unknown -sgn beta_f, P unknown 1 on the element's faces
+  // interface right-hand side B^T h
   const int nd = sub_ndof(g, I, J);
   for (int a = threadIdx.x; a < nd; a += 64) {
     int f0, cnt;
@@ -590,8 +590,7 @@ k_mpm_local_lb(Geo g0, const double* __restrict__ kap_n, const double* __restric
     double v = 0.0;
     for (int xx = f0; xx < f0 + cnt; ++xx) {
       BFace ff = bface(g, I, J, xx);
-      const double wgt = (a & 1) ? 1.0 : -ff.sgn * robin_beta(g, ff, kmt[(ff.j + 1) * TW + ff.i + 1]);
-      v += wgt * hsh[xx];
+      v += bweight(g, ff, a, kmt[(ff.j + 1) * TW + ff.i + 1]) * hsh[xx];
     }
     leaf_out(lo, sub, a, v);
   }
@@ -650,11 +649,7 @@ k_mpm_first(Geo g0, const double* __restrict__ kap_n, const double* __restrict__
   for (int f = threadIdx.x; f < nb; f += 64) {
     const BFace bf = bface(g, I, J, f);
     double r = 0.0;
-    if (bf.kind == FACE_ROB) {
-      const int a = bface_dof(g, I, J, bf);
-      const int32_t* dofs = sub_dofs + size_t(sub) * g.ndmax;
-      r = -bf.sgn * robin_beta(g, bf, kmf(bf.i, bf.j)) * y[dofs[a]] + y[dofs[a + 1]];
-    }
+    if (bf.kind == FACE_ROB) r = robin_datum(g, I, J, bf, kmf(bf.i, bf.j), sub_dofs + size_t(sub) * g.ndmax, y);
     rr[f] = r;
   }
   __syncthreads();
@@ -758,8 +753,7 @@ k_mpm_first(Geo g0, const double* __restrict__ kap_n, const double* __restrict__
     double v = 0.0;
     for (int xx = f0; xx < f0 + cnt; ++xx) {
       const BFace ff = bface(g, I, J, xx);
-      const double wgt = (a & 1) ? 1.0 : -ff.sgn * robin_beta(g, ff, kmf(ff.i, ff.j));
-      v += wgt * hsh[xx];
+      v += bweight(g, ff, a, kmf(ff.i, ff.j)) * hsh[xx];
     }
     leaf_out(lo, sub, a, v);
   }

@@ -241,15 +241,10 @@ __device__ __forceinline__ void lb_block(const LineW& W, int ln, const LB<MF, IL
   }
 }
 
-// Restriction B^T of boundary-face quantities to local interface unknowns:
-// U unknown: -sgn beta_f on the element's faces; P unknown: 1.
-__device__ __forceinline__ double bweight(const Geo& g, const BFace& f, bool is_p, double kc) {
-  return is_p ? 1.0 : -f.sgn * robin_beta(g, f, kc);
-}
-
 // From the Robin-to-flux map S (nb x nb, global) and the boundary fluxes h (LDS) of a
-// subdomain: its interface block K_i = B^T S B - D_i (eq:mrc2 with the Robin rows negated)
-// and the right-hand side B^T h, written into the parent's slot. kl: kappa in local order.
+// subdomain: its interface block K_i = B^T S B - D_i (eq:mrc2 with the Robin rows negated;
+// D_i couples the U unknowns of one element: sum_f |f| beta_f phi_k phi_k') and the right-hand
+// side B^T h, written into the parent's slot. kl: kappa in local order.
 // One wavefront; S must be visible to all lanes (barrier before the call).
 __device__ __forceinline__ void basis_iface_block(const Geo& g, int I, int J, int sub, const double* kl,
                                                   const double* Ss, const double* hsh, double* leafK,
@@ -262,23 +257,27 @@ __device__ __forceinline__ void basis_iface_block(const Geo& g, int I, int J, in
     int fa, na, fb, nbb;
     dof_faces(g, I, J, a, &fa, &na);
     dof_faces(g, I, J, c2, &fb, &nbb);
-    const bool pa = a & 1, pb = c2 & 1;
     double v = 0.0;
     for (int x = fa; x < fa + na; ++x) {
       const BFace ff = bface(g, I, J, x);
-      const double wa = bweight(g, ff, pa, kl[loc_index(g, ff.i, ff.j)]);
+      const double wa = bweight(g, ff, a, kl[loc_index(g, ff.i, ff.j)]);
       double sacc = 0.0;
       for (int y = fb; y < fb + nbb; ++y) {
         const BFace fgb = bface(g, I, J, y);
-        sacc += Ss[x * nb + y] * bweight(g, fgb, pb, kl[loc_index(g, fgb.i, fgb.j)]);
+        sacc += Ss[x * nb + y] * bweight(g, fgb, c2, kl[loc_index(g, fgb.i, fgb.j)]);
       }
       v += wa * sacc;
     }
-    if (a == c2 && !pa) {
+    bool pa, pb;
+    int ka, kb;
+    dof_kind(g, a, &pa, &ka);
+    dof_kind(g, c2, &pb, &kb);
+    if (fa == fb && !pa && !pb) {   // U unknowns of the same element
       double dsum = 0.0;
       for (int x = fa; x < fa + na; ++x) {
         const BFace ff = bface(g, I, J, x);
-        dsum += ff.flen * robin_beta(g, ff, kl[loc_index(g, ff.i, ff.j)]);
+        dsum += ff.flen * robin_beta(g, ff, kl[loc_index(g, ff.i, ff.j)]) * iface_phi(g, ff, ka) *
+                iface_phi(g, ff, kb);
       }
       v -= dsum;
     }
@@ -290,7 +289,7 @@ __device__ __forceinline__ void basis_iface_block(const Geo& g, int I, int J, in
     double v = 0.0;
     for (int x = fa; x < fa + na; ++x) {
       const BFace ff = bface(g, I, J, x);
-      v += bweight(g, ff, a & 1, kl[loc_index(g, ff.i, ff.j)]) * hsh[x];
+      v += bweight(g, ff, a, kl[loc_index(g, ff.i, ff.j)]) * hsh[x];
     }
     leaf_out(lo, sub, a, v);
   }

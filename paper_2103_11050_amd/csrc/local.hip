@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(256) k_dt(int nsub, const double* __restrict__
 
 // ====================================================================== A7: boundary fluxes
 // Reconstruction on every boundary face of every subdomain from the interface solution:
-// W u = h - S r with the Robin data r_f = -sgn beta_f U_l + P_l on Gamma faces (zero on
+// W u = h - S r with the Robin data r_f = -sgn beta_f U_H(f) + P_H(f) on Gamma faces (zero on
 // Dirichlet faces, whose data are in h); Neumann faces keep z. With with_v the MPM-2P flux
 // u-bar = u-hat_0 + v is returned; with with_v = 2 the first-order u-hat_1 + w is added to ubnd
 // (Neumann faces unchanged).
@@ -162,11 +162,8 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
     bf = bface(g, I, J, f);
     double rv = 0.0;
     if (bf.kind == FACE_ROB) {
-      const int a = bface_dof(g, I, J, bf);
-      const int32_t* dofs = sub_dofs + size_t(sub) * g.ndmax;
-      const double U = y[dofs[a]], Pv = y[dofs[a + 1]];
       const int gc = (J * g.my + bf.j) * g.nx + I * g.mx + bf.i;
-      rv = -bf.sgn * robin_beta(g, bf, kap_m[gc]) * U + Pv;
+      rv = robin_datum(g, I, J, bf, kap_m[gc], sub_dofs + size_t(sub) * g.ndmax, y);
     }
     r[f] = rv;
   }

@@ -61,10 +61,13 @@ mpm_status validate(const mpm_desc& d, std::string* why) {
     return bad("more than 272 faces of one direction per subdomain");
   if (d.mpm_order != 0 && d.mpm_order != 1) return bad("mpm_order must be 0 or 1");
   if (d.mpm_order == 1 && d.precision != MPM_PREC_FP64) return bad("the first-order term is FP64 only");
-  if (d.reserved != 0) return bad("reserved must be 0");
+  if (d.iface_degree != 0 && d.iface_degree != 1) return bad("iface_degree must be 0 or 1");
+  if (d.iface_degree == 1 && (d.sub_x / d.ne_x < 2 || d.sub_y / d.ne_y < 2))
+    return bad("linear interface spaces need at least two fine faces per interface element");
   if (d.precision == MPM_PREC_FP32_REFINE && nc / band > 16)
     return bad("the precision form takes at most 16 lines per subdomain");
-  if (2 * (2 * d.ne_x + 2 * d.ne_y) > 128) return bad("more than 128 interface unknowns per subdomain");
+  if (2 * (d.iface_degree + 1) * (2 * d.ne_x + 2 * d.ne_y) > 128)
+    return bad("more than 128 interface unknowns per subdomain");
   return MPM_OK;
 }
 
@@ -78,16 +81,21 @@ void build_plan(const mpm_desc& d, Plan* p) {
   P.n_vert = (P.Sx - 1) * P.Sy * P.ne_y;
   P.n_horiz = P.Sx * (P.Sy - 1) * P.ne_x;
   P.n_elem = P.n_vert + P.n_horiz;
-  P.n_iface = 2 * P.n_elem;
+  P.npol = d.iface_degree + 1;
+  P.n_iface = 2 * P.npol * P.n_elem;
   P.nc = P.mx * P.my;
   P.band = std::min(P.mx, P.my);
   P.xfast = P.mx <= P.my ? 1 : 0;
   P.nb = 2 * (P.mx + P.my);
-  P.ndmax = 4 * (P.ne_x + P.ne_y);
+  P.ndmax = 4 * P.npol * (P.ne_x + P.ne_y);
 
   auto vert = [&](int I, int J, int k) { return (J * (P.Sx - 1) + I) * P.ne_y + k; };
   auto horiz = [&](int I, int J, int k) { return P.n_vert + (J * P.Sx + I) * P.ne_x + k; };
-  auto push_e = [](std::vector<int32_t>& v, int e) { v.push_back(2 * e); v.push_back(2 * e + 1); };
+  // unknowns of element e: U_0 .. U_{npol-1}, P_0 .. P_{npol-1}
+  const int pe = 2 * P.npol;
+  auto push_e = [pe](std::vector<int32_t>& v, int e) {
+    for (int t = 0; t < pe; ++t) v.push_back(pe * e + t);
+  };
 
   // boundary unknowns of a rectangle of subdomains, order: left, right, bottom, top
   auto rect_boundary = [&](const Rect& r) {

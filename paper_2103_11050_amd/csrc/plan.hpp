@@ -61,6 +61,7 @@ struct Plan {
   double hx, hy;
   int ne_x, ne_y;
   int n_vert, n_horiz, n_elem, n_iface;
+  int npol;                   // interface functions per element and field (iface_degree + 1)
   int nc;                     // cells per subdomain
   int band;                   // half bandwidth of the local matrices = min(mx, my)
   int xfast;                  // 1: local cell order has x fastest (band = mx)

@@ -51,7 +51,7 @@ def test_workspace_size_valid(lib):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("abi_version", 1), ("mpm_order", 2), ("reserved", 1), ("nx", 0), ("sub_x", 5), ("ne_x", 3), ("alpha", 0.0), ("alpha", float("nan")),
+    ("abi_version", 1), ("mpm_order", 2), ("iface_degree", 2), ("nx", 0), ("sub_x", 5), ("ne_x", 3), ("alpha", 0.0), ("alpha", float("nan")),
     ("eta", float("nan")), ("cn", 0), ("mu_w", -1.0), ("cfl", 1.5), ("s_inj", 2.0), ("eps_norm", 7),
     ("switch_rule", 3), ("precision", 9), ("breakthrough_cut", 0.0), ("lx", -1.0),
 ])
@@ -99,6 +99,23 @@ def test_first_order_term_is_fp64_only(lib):
     assert st0 == 0 and n1 > n0            # room for w on the boundary faces
     st32, _ = _size(cfg, precision=binding.PREC_FP32_REFINE)
     assert st32 == binding.MPM_EINVAL
+
+
+def test_linear_interface_spaces(lib):
+    """-POL spaces: twice the interface unknowns; at least two fine faces per element and at
+    most 128 unknowns per subdomain."""
+    st0, n0 = _size(inputs.config("c1"))
+    st1, n1 = _size(inputs.config("c1", iface_degree=1))
+    assert st0 == 0 and st1 == 0 and n1 > n0
+    st3, _ = _size(inputs.config("c3", iface_degree=1))          # 8 elements per side: 128 unknowns
+    assert st3 == 0
+    one_face = inputs.config("c1", ne_x=8, ne_y=2, iface_degree=1)
+    assert _size(one_face)[0] == binding.MPM_EINVAL
+    assert _size(inputs.config("c1", ne_x=8, ne_y=2))[0] == 0
+    # two faces per element on both sides of the largest subdomain: 4 (32 + 32) / 2 = 128
+    # unknowns, the bound, which the other limits keep linear spaces within
+    many = inputs.config("c1", nx=48, ny=16, sub_x=24, sub_y=8, ne_x=12, ne_y=4, iface_degree=1)
+    assert _size(many)[0] == 0
 
 
 def test_eta_infinity_accepted(lib):

@@ -200,6 +200,8 @@ GROUPED = [
     (208, 64, 64, 16, 8, dict(sigma2=4.0, corr_len=0.1, mu_o=100.0, eta=0.1), 0),
     (209, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=20.0, eta=0.01, mpm_order=1), 0),
     (210, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=25.0, eta=0.01, mpm_order=1), 0),
+    (211, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=20.0, eta=0.01, iface_degree=1), 0),
+    (212, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=30.0, eta=0.01, iface_degree=1), 0),
 ]
 
 

@@ -160,6 +160,50 @@ def test_first_order_term_matches_oracle(binding, shape):
     assert "mpm" in [h["branch"] for h in orun.history[1:]]
 
 
+LINEAR_SHAPES = [
+    # nx, ny, sub_x, sub_y, ne_x, ne_y: at least two fine faces per element
+    (32, 32, 8, 8, 2, 2),
+    (24, 16, 8, 4, 4, 2),       # two faces per element on both sides
+    (30, 20, 10, 10, 1, 5),     # 3 x 2 subdomains, ragged tree, one element on x sides
+    (48, 8, 8, 8, 1, 4),        # one row of subdomains
+    (60, 30, 20, 10, 4, 2),     # 20 lines, 3 x 3 subdomains
+    (20, 40, 10, 20, 5, 4),     # lines along x, 20 of them
+]
+
+
+@pytest.mark.parametrize("shape", LINEAR_SHAPES)
+def test_linear_interface_mrcm_matches_oracle(binding, shape):
+    """MRCM with the -POL spaces (iface_degree = 1: U_H, P_H linear per element) against the
+    oracle."""
+    nx, ny, mx, my, nex, ney = shape
+    print(f"[gpu] linear-space mrcm shape={shape}", flush=True)
+    cfg, K = inputs.random_problem(41 + nx + ny, nx, ny, mx, my, nex, ney, sigma2=2.0, corr_len=0.2,
+                                   iface_degree=1)
+    s0 = np.random.default_rng(5).uniform(0, 1, K.shape)
+    kap = physics.conductivity(s0, K, cfg["mu_w"], cfg["mu_o"])
+    rx, ry, _, _ = ompm.mrcm_velocity(cfg, kap)
+    r = _gpu_run(binding, cfg, K, s0)
+    r.start()
+    ux, uy = r.velocity()
+    assert r.stats()["error_word"] == 0
+    err = vel_rel_err(cfg, to_np(ux), to_np(uy), rx, ry)
+    print(f"    rel L2 velocity error {err:.3e}", flush=True)
+    assert err <= FP64_VEL_TOL
+    r.close()
+
+
+@pytest.mark.parametrize("shape,order", [((32, 24, 8, 8, 2, 4), 0), ((60, 30, 20, 10, 4, 2), 0),
+                                         ((32, 24, 8, 8, 2, 4), 1), ((24, 16, 8, 4, 4, 2), 1)])
+def test_linear_interface_mixed_run(binding, shape, order):
+    """-POL spaces through MRCM updates and MPM-2P steps (with the first-order term for
+    order 1) against the oracle, step by step."""
+    nx, ny, mx, my, nex, ney = shape
+    cfg, K = inputs.random_problem(19 + nx, nx, ny, mx, my, nex, ney, sigma2=3.0, corr_len=0.15, eta=0.003,
+                                   mu_o=30.0, iface_degree=1, mpm_order=order)
+    orun = _compare_runs(binding, cfg, K, 14, f"linear spaces {shape} order {order}")
+    assert "mpm" in [h["branch"] for h in orun.history[1:]]
+
+
 def test_x4_finger_growth_config(binding):
     """The finger-growth workload (15 x 5 subdomains of 20 x 10, one fine face per element,
     perturbed initial front) against the oracle for the first elliptic steps."""
@@ -241,6 +285,14 @@ def test_precision_form_mpm_steps(binding, shape):
     cfg, K = inputs.random_problem(61 + nx, nx, ny, mx, my, nex, ney, sigma2=3.0, corr_len=0.2, mu_o=40.0)
     _compare_runs(binding, cfg, K, 6, f"mixed-{shape}", forced=[None] + ["mpm"] * 6, vel_tol=MIXED_VEL_TOL,
                   sat_tol=MIXED_SAT_TOL, precision=binding.PREC_FP32_REFINE)
+
+
+def test_precision_form_linear_interface(binding):
+    """The precision form with the -POL spaces: MPM-2P and MRCM steps within the mixed bar."""
+    cfg, K = inputs.random_problem(23, 32, 24, 8, 8, 2, 4, sigma2=3.0, corr_len=0.15, eta=0.003, mu_o=30.0,
+                                   iface_degree=1)
+    _compare_runs(binding, cfg, K, 10, "precision linear spaces", vel_tol=MIXED_VEL_TOL, sat_tol=MIXED_SAT_TOL,
+                  precision=1)
 
 
 def test_precision_form_c2_window(binding):
