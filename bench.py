@@ -219,15 +219,14 @@ def precision_form(binding, cfg, Kt, st, steps: int, warmup: int) -> dict:
             "note": "FP32 blocks applied in FP32, FP64 iterative refinement of every local solve"}
 
 
-def first_order_form(binding, cfg, Kt, st, steps: int, warmup: int) -> dict:
-    """MPM-2P with the first-order term of eq:mpm_tf_4 (mpm_order = 1) beside the zeroth-order
-    path on the same workload: its rate over `steps` steps and the relative difference of the two
-    velocities after them (the size of the term the paper neglects)."""
+def _side_by_side(binding, cfg, Kt, st, steps: int, warmup: int, over: dict):
+    """Rates of the workload as given and with the descriptor fields `over` changed, over the
+    same window, and the relative RT0 difference of the two velocities after it."""
     import torch
 
-    runs = {}
-    for order in (0, 1):
-        r = binding.Run(dict(cfg, mpm_order=order), Kt, st)
+    runs = []
+    for c in (cfg, dict(cfg, **over)):
+        r = binding.Run(c, Kt, st)
         r.start()
         for _ in range(warmup):
             r.step()
@@ -236,8 +235,8 @@ def first_order_form(binding, cfg, Kt, st, steps: int, warmup: int) -> dict:
         for _ in range(steps):
             r.step()
         torch.cuda.synchronize()
-        runs[order] = (r, steps / (time.perf_counter() - t0))
-    (r0, v0), (r1, v1) = runs[0], runs[1]
+        runs.append((r, steps / (time.perf_counter() - t0)))
+    (r0, v0), (r1, v1) = runs
     ux0, uy0 = (t.cpu().numpy() for t in r0.velocity())
     ux1, uy1 = (t.cpu().numpy() for t in r1.velocity())
 
@@ -245,12 +244,41 @@ def first_order_form(binding, cfg, Kt, st, steps: int, warmup: int) -> dict:
         return np.sum(ux[:, :-1] ** 2) + np.sum(ux[:, 1:] ** 2) + np.sum(uy[:-1, :] ** 2) + np.sum(uy[1:, :] ** 2)
 
     diff = float(np.sqrt(rt0(ux1 - ux0, uy1 - uy0) / rt0(ux0, uy0)))
-    same = r0.stats()["tm"] == r1.stats()["tm"]
+    s0, s1 = r0.stats(), r1.stats()
+    upd = []
+    for r in (r0, r1):   # median time of a forced MRCM update (basis, interface factorisation)
+        t = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r.step(binding.FORCE_MRCM)
+            torch.cuda.synchronize()
+            t.append(1e3 * (time.perf_counter() - t0))
+        upd.append(round(float(np.median(t)), 3))
     r0.close()
     r1.close()
+    return v0, v1, diff, s0, s1, upd
+
+
+def first_order_form(binding, cfg, Kt, st, steps: int, warmup: int) -> dict:
+    """MPM-2P with the first-order term of eq:mpm_tf_4 (mpm_order = 1) beside the zeroth-order
+    path on the same workload: its rate over `steps` steps and the relative difference of the two
+    velocities after them (the size of the term the paper neglects)."""
+    v0, v1, diff, s0, s1, _ = _side_by_side(binding, cfg, Kt, st, steps, warmup, {"mpm_order": 1})
     return {"value": round(v1, 2), "zeroth_order_value_same_window": round(v0, 2), "steps": steps,
-            "vel_rel_l2_first_minus_zeroth": diff, "same_basis_count": bool(same),
+            "vel_rel_l2_first_minus_zeroth": diff, "same_basis_count": s0["tm"] == s1["tm"],
             "note": "one more local solve per subdomain, interface solve and reconstruction per step"}
+
+
+def linear_space_form(binding, cfg, Kt, st, steps: int, warmup: int) -> dict:
+    """The same workload with the -POL interface spaces of Section 5.2 (iface_degree = 1: U_H,
+    P_H linear per element, twice the interface unknowns): its rate and the relative difference
+    of its velocity from the piecewise-constant one after the window."""
+    v0, v1, diff, s0, s1, upd = _side_by_side(binding, cfg, Kt, st, steps, warmup, {"iface_degree": 1})
+    return {"value": round(v1, 2), "constant_space_value_same_window": round(v0, 2), "steps": steps,
+            "vel_rel_l2_linear_minus_constant": diff, "basis_updates": [s0["tm"], s1["tm"]],
+            "mrcm_update_ms_constant_linear": upd,
+            "note": "k_U = k_P = 2 per interface element; the interface system has twice the unknowns"}
 
 
 def main():
@@ -262,7 +290,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32-refine"], default="fp64",
                     help="local solves with FP64 blocks, or FP32 blocks with FP64 refinement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-precision-form", action="store_true",  # also skips the first-order form
+    ap.add_argument("--no-precision-form", action="store_true",  # also skips the other side forms
                     help="skip the side-by-side run of the FP32-block precision form")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--make-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -383,6 +411,7 @@ def main():
         out["precision_form"] = precision_form(binding, cfg, Kt, st, min(args.steps, 100), args.warmup)
     if args.precision == "fp64" and not args.no_precision_form:
         out["first_order_form"] = first_order_form(binding, cfg, Kt, st, min(args.steps, 100), args.warmup)
+        out["linear_space_form"] = linear_space_form(binding, cfg, Kt, st, min(args.steps, 100), args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, K)
     print(json.dumps(out))

@@ -8,7 +8,9 @@ available). For each contrast and each C_n the runs are:
   undecomposed fine solution, recomputed at every elliptic step;
 * MRCM with H-bar = H and H / 2, basis recomputed at every elliptic step;
 * MPM-2P with H-bar = H and H / 2 (Algorithm 1, eta = 1e-2), and with --first-order also with
-  the first-order term of eq:mpm_tf_4.
+  the first-order term of eq:mpm_tf_4;
+* with --linear, MRCM and MPM-2P with the -POL spaces of Section 5.2 (U_H, P_H linear per
+  element) at H-bar = H and H / 2.
 
 All runs take the same number of elliptic steps, each with its own CFL sub-step; after every
 step the relative L2(Omega) flux error and the relative L1(Omega) saturation error against the
@@ -35,12 +37,13 @@ def rcr(te: int, tm: int, n_sub: int, n_hat: int) -> float:
 
 
 def homogeneous_bf_count(cfg: dict) -> int:
-    """N-hat: homogeneous basis functions over all subdomains, two per interface element side
-    of every subdomain (flux and pressure), physical-boundary sides excluded."""
+    """N-hat: homogeneous basis functions over all subdomains, k_U + k_P per interface element
+    side of every subdomain (flux and pressure functions), physical-boundary sides excluded."""
     sx, sy = cfg["nx"] // cfg["sub_x"], cfg["ny"] // cfg["sub_y"]
     vert = (sx - 1) * sy * cfg["ne_y"]        # elements on vertical interfaces
     horiz = sx * (sy - 1) * cfg["ne_x"]
-    return 2 * 2 * (vert + horiz)             # two sides, two unknowns per element
+    npol = cfg.get("iface_degree", 0) + 1
+    return 2 * 2 * npol * (vert + horiz)      # two sides, 2 npol unknowns per element
 
 
 def _norms(cfg, ux, uy):
@@ -50,7 +53,7 @@ def _norms(cfg, ux, uy):
 
 
 def run_experiment(contrast: float, cn: int, max_steps: int = 20000, seed: int = 11, curves: bool = False,
-                   first_order: bool = False) -> dict:
+                   first_order: bool = False, linear: bool = False) -> dict:
     import torch
     dev = torch.device("cuda:0")
     base = inputs.x1_config(contrast, ne=1, cn=cn, seed=seed)
@@ -67,6 +70,11 @@ def run_experiment(contrast: float, cn: int, max_steps: int = 20000, seed: int =
     if first_order:   # with the first-order term of eq:mpm_tf_4, which the paper neglects
         cases["MPM-2P H, l=1"] = (dict(ne_x=1, ne_y=1, eta=1e-2, mpm_order=1), binding.AUTO)
         cases["MPM-2P H/2, l=1"] = (dict(ne_x=2, ne_y=2, eta=1e-2, mpm_order=1), binding.AUTO)
+    if linear:        # the -POL spaces of Section 5.2
+        cases["MRCM-POL H"] = (dict(ne_x=1, ne_y=1, eta=0.0, iface_degree=1), binding.FORCE_MRCM)
+        cases["MRCM-POL H/2"] = (dict(ne_x=2, ne_y=2, eta=0.0, iface_degree=1), binding.FORCE_MRCM)
+        cases["MPM-2P-POL H"] = (dict(ne_x=1, ne_y=1, eta=1e-2, iface_degree=1), binding.AUTO)
+        cases["MPM-2P-POL H/2"] = (dict(ne_x=2, ne_y=2, eta=1e-2, iface_degree=1), binding.AUTO)
     runs = {}
     for name, (over, force) in cases.items():
         cfg = dict(base, **over)
@@ -122,11 +130,13 @@ def main(argv=None):
     ap.add_argument("--cn", type=int, nargs="+", default=[1, 20])
     ap.add_argument("--max-steps", type=int, default=20000)
     ap.add_argument("--first-order", action="store_true", help="also MPM-2P with the first-order term")
+    ap.add_argument("--linear", action="store_true", help="also MRCM and MPM-2P with linear interface spaces")
     args = ap.parse_args(argv)
     binding.load()
     for c in args.contrast:
         for cn in args.cn:
-            print(json.dumps(run_experiment(c, cn, args.max_steps, first_order=args.first_order)), flush=True)
+            print(json.dumps(run_experiment(c, cn, args.max_steps, first_order=args.first_order,
+                                            linear=args.linear)), flush=True)
 
 
 if __name__ == "__main__":

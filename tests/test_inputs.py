@@ -58,3 +58,15 @@ def test_x4_finger_growth_workload():
     front = s.sum(axis=1)                 # saturated cells per row
     assert front[0] == front[-1] == 10 and front[25] == 15
     assert front.max() == 15 and np.all(front[np.abs(np.arange(50) + 0.5 - 25) >= 5] == 10)
+
+
+def test_x1_basis_count_matches_cost_model():
+    """The experiment's N-hat (RCR of Section 4.3) agrees with the cost model for constant and
+    linear interface spaces."""
+    from oracle import cost
+    from paper_2103_11050_amd import x1
+    for ne in (1, 2):
+        for deg in (0, 1):
+            cfg = dict(inputs.x1_config(1e3, ne=ne, cn=1), iface_degree=deg)
+            sx, sy = cfg["nx"] // cfg["sub_x"], cfg["ny"] // cfg["sub_y"]
+            assert x1.homogeneous_bf_count(cfg) == cost.homogeneous_bf_count(sx, sy, ne, ne, kU=deg + 1, kP=deg + 1)

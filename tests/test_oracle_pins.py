@@ -576,6 +576,9 @@ def test_T18_oracle_bf_count_matches_formula():
     cfg, K = _problem(1, 16, 16, 4, 4, 2, 2)
     b = mrcm.build_basis(cfg, K)
     assert sum(len(lb.dofs) for lb in b.locals) == cost.homogeneous_bf_count(4, 4, 2, 2)
+    # -POL spaces: k_U = k_P = 2
+    b1 = mrcm.build_basis(dict(cfg, iface_degree=1), K)
+    assert sum(len(lb.dofs) for lb in b1.locals) == cost.homogeneous_bf_count(4, 4, 2, 2, kU=2, kP=2) == 384
 
 
 # ---------------------------------------------------------------- T19: brute force
