@@ -222,13 +222,16 @@ __device__ __forceinline__ double ld32(const double* base, uint32_t elem) {
 // one node, G lanes per row, U columns per lane (longer rows in chunks of G*U), and issues
 // every load of its block and of the vector it multiplies before the first use: one memory
 // round trip per level. Loads are unconditional at clamped (valid) addresses and masked
-// afterwards so that the compiler keeps them all in flight; no LDS and no barriers.
+// afterwards so that the compiler keeps them all in flight. The vector is loaded once per
+// workgroup (a few entries per thread) and shared through LDS, so that the loads of the waves
+// are those of their rows; rows longer than G*U (CH) load it per wave, chunk by chunk.
 
 // c_B = f_B - BI f_I with f = slot0 + slot1, written into the parent's slot for this node;
 // workgroup 0 of the node also stores f_I for the backward sweep. The root is not launched.
 // Rows longer than G*U (only with CH) are taken in chunks.
 template <int G, int U, int RP, bool CH>
 __global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a0, int loff, const RunTab* __restrict__ rt) {
+  static_assert(RP <= G, "lane p of a row group holds row p's operands");
   const NdArgs a = nd_at(a0, ws_off(rt));
   constexpr int RPP = 256 / G, RPB = RP * RPP;
   const NodeDev nd = a.lnodes[loff + blockIdx.y];
@@ -239,18 +242,46 @@ __global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a0, int loff, const Ru
   const double* __restrict__ s0 = a.slots + nd.slot_off;
   const int32_t* __restrict__ up = a.map_pool + nd.up_map_off;
   const int n = nd.n, nI = nd.nI, nI1 = nd.nI - 1, nB1 = nd.nB - 1;
+  // the per-row operands f_B and the target slot of row p are loaded by lane p of the group only
+  const int jm = min(r0 + min(gl, RP - 1) * RPP + grp, nB1);
+  const double fbm = s0[nI + jm] + s0[n + nI + jm];
+  const int32_t tom = up[jm];
   uint32_t rowoff[RP];
-  double fb[RP], acc[RP];
-  int32_t to[RP];
+  double acc[RP];
 #pragma unroll
   for (int p = 0; p < RP; ++p) {
     const int j = min(r0 + p * RPP + grp, nB1);
     rowoff[p] = uint32_t(nI + j) * uint32_t(n);
-    fb[p] = s0[nI + j] + s0[n + nI + j];
-    to[p] = up[j];
     acc[p] = 0.0;
   }
-  for (int k0 = 0; k0 < (CH ? nI : 1); k0 += G * U) {
+  if constexpr (!CH) {
+    constexpr int VPT = (G * U + 255) / 256;
+    __shared__ double fsh[G * U];
+    double m[RP][U], fv[VPT];
+#pragma unroll
+    for (int p = 0; p < RP; ++p)
+#pragma unroll
+      for (int u = 0; u < U; ++u) m[p][u] = ld32(F, rowoff[p] + uint32_t(min(gl + u * G, nI1)));
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int k = min(int(threadIdx.x) + 256 * i, nI1);
+      fv[i] = ld32(s0, k) + ld32(s0, n + k);
+    }
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int k = threadIdx.x + 256 * i;
+      if (k < nI) {
+        fsh[k] = fv[i];
+        if (blockIdx.x == 0) a.fI[nd.fI_off + k] = fv[i];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < RP; ++p)
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[p] += (gl + u * G < nI) ? m[p][u] * fsh[gl + u * G] : 0.0;
+  }
+  for (int k0 = 0; k0 < (CH ? nI : 0); k0 += G * U) {
     double m[RP][U], fk[U];
 #pragma unroll
     for (int p = 0; p < RP; ++p)
@@ -273,14 +304,16 @@ __global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a0, int loff, const Ru
 #pragma unroll
       for (int u = 0; u < U; ++u) acc[p] += (k0 + gl + u * G < nI) ? m[p][u] * fk[u] : 0.0;
   }
+  double mine = 0.0;
 #pragma unroll
   for (int p = 0; p < RP; ++p) {
     double v = acc[p];
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    const int j = r0 + p * RPP + grp;
-    if (gl == 0 && j < nd.nB) a.slots[nd.up_slot_off + to[p]] = fb[p] - v;
+    mine = gl == p ? v : mine;
   }
+  const int j = r0 + gl * RPP + grp;
+  if (gl < RP && j < nd.nB) a.slots[nd.up_slot_off + tom] = fbm - mine;
 }
 
 // x_I = -II f_I - IB x_B, with f_I stored by the forward sweep (at the root: the sum of its two
@@ -288,6 +321,7 @@ __global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a0, int loff, const Ru
 // first, the block loads behind them); x_I goes to the solution vector.
 template <int G, int U, int RP, bool CH, bool ROOT>
 __device__ __forceinline__ void k_nd_bwd_body(const NdArgs& a, int loff) {
+  static_assert(RP <= G, "lane p of a row group holds row p's unknown id");
   constexpr int RPP = 256 / G, RPB = RP * RPP;
   const NodeDev nd = a.lnodes[loff + blockIdx.y];
   const int r0 = blockIdx.x * RPB;
@@ -298,17 +332,54 @@ __device__ __forceinline__ void k_nd_bwd_body(const NdArgs& a, int loff) {
   const double* __restrict__ fI = a.fI + nd.fI_off;
   const int32_t* __restrict__ dofs = a.dof_pool + nd.dof_off;
   const int n = nd.n, nI = nd.nI, n1 = nd.n - 1, nI1 = nd.nI - 1;
+  // the unknown id of row p is loaded by lane p of the group only
+  const int32_t drm = dofs[min(r0 + min(gl, RP - 1) * RPP + grp, nI1)];
   uint32_t rowoff[RP];
-  int32_t dr[RP];
   double acc[RP];
 #pragma unroll
   for (int p = 0; p < RP; ++p) {
     const int r = min(r0 + p * RPP + grp, nI1);
     rowoff[p] = uint32_t(r) * uint32_t(n);
-    dr[p] = dofs[r];
     acc[p] = 0.0;
   }
-  for (int k0 = 0; k0 < (CH ? n : 1); k0 += G * U) {
+  if constexpr (!CH) {
+    constexpr int VPT = (G * U + 255) / 256;
+    __shared__ double vsh[G * U];
+    double m[RP][U], vv[VPT];
+#pragma unroll
+    for (int p = 0; p < RP; ++p)
+#pragma unroll
+      for (int u = 0; u < U; ++u) m[p][u] = ld32(F, rowoff[p] + uint32_t(min(gl + u * G, n1)));
+    if constexpr (ROOT) {
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int k = min(int(threadIdx.x) + 256 * i, n1);
+        vv[i] = ld32(s0, k) + ld32(s0, n + k);
+      }
+    } else {
+      int32_t dk[VPT];
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) dk[i] = dofs[min(max(int(threadIdx.x) + 256 * i, nI), n1)];
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        const int k = threadIdx.x + 256 * i;
+        const double xi = ld32(fI, min(k, nI1));
+        const double xb = a.y[dk[i]];
+        vv[i] = k < nI ? xi : xb;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int k = threadIdx.x + 256 * i;
+      if (k < n) vsh[k] = vv[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < RP; ++p)
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[p] += (gl + u * G < n) ? m[p][u] * vsh[gl + u * G] : 0.0;
+  }
+  for (int k0 = 0; k0 < (CH ? n : 0); k0 += G * U) {
     int32_t dk[U];
     if constexpr (!ROOT) {
 #pragma unroll
@@ -336,14 +407,16 @@ __device__ __forceinline__ void k_nd_bwd_body(const NdArgs& a, int loff) {
 #pragma unroll
       for (int u = 0; u < U; ++u) acc[p] += m[p][u] * v[u];
   }
+  double mine = 0.0;
 #pragma unroll
   for (int p = 0; p < RP; ++p) {
     double x = acc[p];
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    const int r = r0 + p * RPP + grp;
-    if (gl == 0 && r < nI) a.y[dr[p]] = -x;
+    mine = gl == p ? x : mine;
   }
+  const int r = r0 + gl * RPP + grp;
+  if (gl < RP && r < nI) a.y[drm] = -mine;
 }
 
 void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nmax, int nImax) {
