@@ -346,10 +346,20 @@ __device__ __forceinline__ void k_nd_bwd_body(const NdArgs& a, int loff) {
     constexpr int VPT = (G * U + 255) / 256;
     __shared__ double vsh[G * U];
     double m[RP][U], vv[VPT];
+    // unknown ids of x_B first, so that their gather waits for them only, not for the block
+    uint32_t dk[VPT];   // unsigned: no sign extension next to the load, before the block loads
+    if constexpr (!ROOT) {
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) dk[i] = uint32_t(dofs[min(max(int(threadIdx.x) + 256 * i, nI), n1)]);
+    }
+    // the block loads go out before the gather waits for the ids (the scheduler would hoist the
+    // gather above them and start the block stream one round trip late)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int p = 0; p < RP; ++p)
 #pragma unroll
       for (int u = 0; u < U; ++u) m[p][u] = ld32(F, rowoff[p] + uint32_t(min(gl + u * G, n1)));
+    __builtin_amdgcn_sched_barrier(0);
     if constexpr (ROOT) {
 #pragma unroll
       for (int i = 0; i < VPT; ++i) {
@@ -357,14 +367,11 @@ __device__ __forceinline__ void k_nd_bwd_body(const NdArgs& a, int loff) {
         vv[i] = ld32(s0, k) + ld32(s0, n + k);
       }
     } else {
-      int32_t dk[VPT];
-#pragma unroll
-      for (int i = 0; i < VPT; ++i) dk[i] = dofs[min(max(int(threadIdx.x) + 256 * i, nI), n1)];
 #pragma unroll
       for (int i = 0; i < VPT; ++i) {
         const int k = threadIdx.x + 256 * i;
         const double xi = ld32(fI, min(k, nI1));
-        const double xb = a.y[dk[i]];
+        const double xb = ld32(a.y, dk[i]);
         vv[i] = k < nI ? xi : xb;
       }
     }
