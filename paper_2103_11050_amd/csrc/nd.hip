@@ -454,27 +454,59 @@ static RbShape rb_shape(int len) {
   return {64, 0, 1};   // longer rows: chunks of 1024
 }
 
+// Rows per lane group available for each row shape (template instances below).
+static int rb_rp_options(int G, int U, int* opt) {
+  if (G == 16) { opt[0] = 4; opt[1] = 6; opt[2] = 8; return 3; }
+  if (G == 32 || U == 1) { opt[0] = 4; opt[1] = 8; return 2; }
+  if (U == 2) { opt[0] = 2; opt[1] = 4; opt[2] = 8; return 3; }
+  if (U == 4) { opt[0] = 1; opt[1] = 2; opt[2] = 4; return 3; }
+  if (U == 8) { opt[0] = 1; opt[1] = 2; return 2; }
+  opt[0] = 1;
+  return 1;
+}
+
+// Where the shape's block holds more rows than a node has, the smallest block that still takes
+// all of them (no idle lane groups on small fronts).
+static RbShape rb_fit_rows(RbShape sh, int rows) {
+  int opt[3];
+  const int no = rb_rp_options(sh.G, sh.U, opt);
+  const int rpp = 256 / sh.G;
+  if (sh.RP * rpp <= rows) return sh;
+  for (int i = 0; i < no; ++i)
+    if (opt[i] <= sh.RP && opt[i] * rpp >= rows) {
+      sh.RP = opt[i];
+      break;
+    }
+  return sh;
+}
+
+#define ND_RB_CASE(KER, g, u, rp, ch, ...)                                                           \
+  if ((sh).G == g && (sh).U == u && (sh).RP == rp) {                                                \
+    hipLaunchKernelGGL((KER<g, u, rp, ch>), grid_, dim3(256), 0, st, __VA_ARGS__);                  \
+    break;                                                                                          \
+  }
 #define ND_RB_LAUNCH(KER, sh, rows, nnodes, nruns, st, ...)                                           \
   do {                                                                                              \
     const int rpb_ = (sh).RP * (256 / (sh).G);                                                      \
     const dim3 grid_(std::max(1, ((rows) + rpb_ - 1) / rpb_), (nnodes), (nruns));                 \
-    if ((sh).G == 16) hipLaunchKernelGGL((KER<16, 1, 8, false>), grid_, dim3(256), 0, st, __VA_ARGS__);        \
-    else if ((sh).G == 32) hipLaunchKernelGGL((KER<32, 1, 8, false>), grid_, dim3(256), 0, st, __VA_ARGS__);   \
-    else if ((sh).U == 1) hipLaunchKernelGGL((KER<64, 1, 8, false>), grid_, dim3(256), 0, st, __VA_ARGS__);    \
-    else if ((sh).U == 2 && (sh).RP == 8) hipLaunchKernelGGL((KER<64, 2, 8, false>), grid_, dim3(256), 0, st, __VA_ARGS__); \
-    else if ((sh).U == 4 && (sh).RP == 4) hipLaunchKernelGGL((KER<64, 4, 4, false>), grid_, dim3(256), 0, st, __VA_ARGS__); \
-    else if ((sh).U == 8 && (sh).RP == 2) hipLaunchKernelGGL((KER<64, 8, 2, false>), grid_, dim3(256), 0, st, __VA_ARGS__); \
-    else if ((sh).U == 2) hipLaunchKernelGGL((KER<64, 2, 4, false>), grid_, dim3(256), 0, st, __VA_ARGS__);    \
-    else if ((sh).U == 4) hipLaunchKernelGGL((KER<64, 4, 2, false>), grid_, dim3(256), 0, st, __VA_ARGS__);    \
-    else if ((sh).U == 8) hipLaunchKernelGGL((KER<64, 8, 1, false>), grid_, dim3(256), 0, st, __VA_ARGS__);    \
-    else if ((sh).U == 16) hipLaunchKernelGGL((KER<64, 16, 1, false>), grid_, dim3(256), 0, st, __VA_ARGS__);  \
-    else if ((sh).U == 24) hipLaunchKernelGGL((KER<64, 24, 1, false>), grid_, dim3(256), 0, st, __VA_ARGS__);  \
-    else hipLaunchKernelGGL((KER<64, 16, 1, true>), grid_, dim3(256), 0, st, __VA_ARGS__);                     \
+    if ((sh).U == 0) {                                                                              \
+      hipLaunchKernelGGL((KER<64, 16, 1, true>), grid_, dim3(256), 0, st, __VA_ARGS__);             \
+      break;                                                                                        \
+    }                                                                                               \
+    ND_RB_CASE(KER, 16, 1, 8, false, __VA_ARGS__) ND_RB_CASE(KER, 16, 1, 6, false, __VA_ARGS__)     \
+    ND_RB_CASE(KER, 16, 1, 4, false, __VA_ARGS__) ND_RB_CASE(KER, 32, 1, 8, false, __VA_ARGS__)     \
+    ND_RB_CASE(KER, 32, 1, 4, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 1, 8, false, __VA_ARGS__)     \
+    ND_RB_CASE(KER, 64, 1, 4, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 2, 8, false, __VA_ARGS__)     \
+    ND_RB_CASE(KER, 64, 2, 4, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 2, 2, false, __VA_ARGS__)     \
+    ND_RB_CASE(KER, 64, 4, 4, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 4, 2, false, __VA_ARGS__)     \
+    ND_RB_CASE(KER, 64, 4, 1, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 8, 2, false, __VA_ARGS__)     \
+    ND_RB_CASE(KER, 64, 8, 1, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 16, 1, false, __VA_ARGS__)    \
+    ND_RB_CASE(KER, 64, 24, 1, false, __VA_ARGS__)                                                  \
   } while (0)
 
 void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nBmax,
                          Runs rt) {
-  const RbShape sh = rb_shape(nImax);
+  const RbShape sh = rb_fit_rows(rb_shape(nImax), nBmax);
   ND_RB_LAUNCH(k_nd_fwd_rb, sh, nBmax, nnodes, runs_of(rt), st, a, loff, rt.tab);
 }
 
@@ -497,7 +529,7 @@ static RbShape rb_shape_bwd(int len) {
 
 void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nmax, int root,
                          Runs rt) {
-  const RbShape sh = rb_shape_bwd(nmax);
+  const RbShape sh = rb_fit_rows(rb_shape_bwd(nmax), nImax);
   if (root) ND_RB_LAUNCH(k_nd_bwd_root, sh, nImax, nnodes, runs_of(rt), st, a, loff, rt.tab);
   else ND_RB_LAUNCH(k_nd_bwd_inner, sh, nImax, nnodes, runs_of(rt), st, a, loff, rt.tab);
 }
