@@ -78,6 +78,7 @@ struct mpm_run {
   double *front, *fI, *slots, *panel, *y, *red, *scal, *dsE, *nfac;
   double* wbnd = nullptr;              // first-order term only
   int32_t* err;
+  int32_t* wc_ticket;          // completion counter of the water-cut workgroups (zero between launches)
   float *fac32 = nullptr, *nfac32 = nullptr, *dsE32 = nullptr;   // precision form
   bool f32 = false;
   const LeafUp* leafup = nullptr;
@@ -468,7 +469,7 @@ mpm_status transport_body(mpm_run* r, int32_t nsteps) {
   }
   {
     Scope sc(r, "water_cut");
-    launch_water_cut(r->st, r->g, r->s, r->ux, r->uy, r->scal);
+    launch_water_cut(r->st, r->g, r->s, r->ux, r->uy, r->scal, r->red + 2 * r->P.nsub, r->wc_ticket);
   }
   return MPM_OK;
 }
@@ -582,6 +583,7 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   r->dsflag = reinterpret_cast<int32_t*>(r->ws + P.off_dsflag);
   r->dslist = reinterpret_cast<int32_t*>(r->ws + P.off_dslist);
   r->err = reinterpret_cast<int32_t*>(r->scal + SC_COUNT);
+  r->wc_ticket = r->err + 8;   // in the zeroed tail of the scalar block
   r->dscount = r->err + 1;
   r->subdofs_d = reinterpret_cast<const int32_t*>(r->ws + P.off_subdofs);
   r->nd.nodes = reinterpret_cast<const NodeDev*>(r->ws + P.off_nodes);
@@ -931,7 +933,7 @@ mpm_status group_issue(std::vector<mpm_run*>& g, GroupStreams& gs, std::vector<m
     launch_sat_step(gs.st, L->g, L->s, L->s2, L->ux, L->uy, L->scal, L->area, rt);
     for (mpm_run* r : g) std::swap(r->s, r->s2);
   }
-  launch_water_cut(gs.st, L->g, L->s, L->ux, L->uy, L->scal, rt);
+  launch_water_cut(gs.st, L->g, L->s, L->ux, L->uy, L->scal, L->red + 2 * L->P.nsub, L->wc_ticket, rt);
   launch_kappa(gs.st, L->g, L->s, L->K, L->kn, L->km, L->red, L->scal, L->dsflag, L->dslist, L->dscount,
                L->dscount + 1, L->pinned_dev, rt);
   for (mpm_run* r : g) {

@@ -137,7 +137,8 @@ void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int level_off, int nno
 // (the viscosity ratio M is the run's, from scal)
 void launch_sat_step(hipStream_t st, const Geo& g, const double* s, double* s2, const double* ux,
                      const double* uy, double* scal, double area, Runs rt = one_run());
+// part: 2 x 64 doubles of scratch; ticket: a zeroed counter (left at zero)
 void launch_water_cut(hipStream_t st, const Geo& g, const double* s, const double* ux, const double* uy,
-                      double* scal, Runs rt = one_run());
+                      double* scal, double* part, int32_t* ticket, Runs rt = one_run());
 
 }  // namespace mpm
