@@ -295,7 +295,7 @@ void nd_factor(mpm_run* r) {
   for (int l = 1; l <= L; ++l) {
     const int nn = int(P.level_nodes[l].size());
     if (!nn) continue;
-    launch_nd_level_factor(r->st, r->nd, P.level_off[l], nn, P.level_nmax[l], P.level_nImax[l]);
+    launch_nd_level_factor(r->st, r->nd, P.level_off[l], nn, P.level_nmax[l], P.level_nImax[l], P.level_nBmax[l]);
   }
 }
 

@@ -127,7 +127,8 @@ __device__ __forceinline__ NdArgs nd_at(const NdArgs& a, int64_t o) {
   b.err = at_off(a.err, o);
   return b;
 }
-void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nmax, int nImax);
+void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nmax, int nImax,
+                            int nBmax);
 void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nImax, int nBmax,
                          Runs rt = one_run());
 void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nImax, int nmax, int root,

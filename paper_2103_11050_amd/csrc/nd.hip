@@ -7,8 +7,10 @@
 //
 // Recursive bisection of the subdomain grid gives a tree; a node's front holds the unknowns
 // of its separator (I) and of its outer boundary (B). Factorisation, level by level from the
-// leaves: assemble the front from the children's Schur complements, then sweep the I
-// unknowns in blocks of piv_b. After the sweep the front holds
+// leaves: assemble the front from the children's Schur complements; sweep the I unknowns of
+// the II block in blocks of piv_b (Gauss-Jordan, II := -F_II^-1); then on the matrix cores
+// T = F_II^-1 F_IB and BB := F_BB - F_BI T, and IB := T, BI := T^T (F is symmetric). The front
+// then holds
 //   II = -F_II^-1,  IB = F_II^-1 F_IB,  BI = F_BI F_II^-1,  BB = F_BB - F_BI F_II^-1 F_IB.
 // Solve: forward (leaves to root) c_B = f_B - BI f_I; backward (root to leaves)
 //   x_I = -II f_I - IB x_B.
@@ -118,8 +120,8 @@ __global__ void __launch_bounds__(256) k_nd_pivot(NdArgs a, int loff, int kb) {
   }
 }
 
-// Row panel of pivot block kb: C = old rows A_K* (copied, the update overwrites them) and
-// R = Pinv C, 64 columns per workgroup.
+// Row panel of pivot block kb over the II block: C = old rows A_K* (copied, the update
+// overwrites them) and R = Pinv C, 64 columns per workgroup.
 __global__ void __launch_bounds__(256) k_nd_rpanel(NdArgs a, int loff, int kb) {
   __shared__ double Pi[32][33];
   __shared__ double Cs[32][65];
@@ -128,9 +130,9 @@ __global__ void __launch_bounds__(256) k_nd_rpanel(NdArgs a, int loff, int kb) {
   const int K0 = kb * pb;
   if (K0 >= nd.nI) return;
   const int bs = min(pb, nd.nI - K0);
-  const int n = nd.n;
+  const int n = nd.n, ext = nd.nI;
   const int j0 = blockIdx.x * 64;
-  if (j0 >= n) return;
+  if (j0 >= ext) return;
   const double* F = a.front + nd.front_off;
   const double* Pinv = a.panel + nd.panel_off;
   double* C = a.panel + nd.panel_off + pb * pb;
@@ -140,7 +142,7 @@ __global__ void __launch_bounds__(256) k_nd_rpanel(NdArgs a, int loff, int kb) {
     const int k = e / 64, t = e % 64;
     const int j = j0 + t;
     double v = 0.0;
-    if (j < n) {
+    if (j < ext) {
       v = F[int64_t(K0 + k) * n + j];
       C[int64_t(k) * n + j] = v;
     }
@@ -150,14 +152,14 @@ __global__ void __launch_bounds__(256) k_nd_rpanel(NdArgs a, int loff, int kb) {
   for (int e = threadIdx.x; e < bs * 64; e += blockDim.x) {
     const int k = e / 64, t = e % 64;
     const int j = j0 + t;
-    if (j >= n) continue;
+    if (j >= ext) continue;
     double v = 0.0;
     for (int u = 0; u < bs; ++u) v += Pi[k][u] * Cs[u][t];
     R[int64_t(k) * n + j] = v;
   }
 }
 
-// Block sweep update of every front entry (64x64 tiles):
+// Block sweep update of every entry of the II block (64x64 tiles):
 //   i,j not in K : A_ij -= sum_k C_ki R_kj
 //   i not in K, j in K : A_ij = R_(j-K0) i
 //   i in K, j not in K : A_ij = R_(i-K0) j
@@ -170,8 +172,8 @@ __global__ void __launch_bounds__(256) k_nd_update(NdArgs a, int loff, int kb) {
   const int K0 = kb * pb;
   if (K0 >= nd.nI) return;
   const int bs = min(pb, nd.nI - K0);
-  const int n = nd.n;
-  const int tpd = (n + TILE - 1) / TILE;
+  const int n = nd.n, ext = nd.nI;
+  const int tpd = (ext + TILE - 1) / TILE;
   const int ti = blockIdx.x / tpd, tj = blockIdx.x % tpd;
   if (ti >= tpd) return;
   const double* Pinv = a.panel + nd.panel_off;
@@ -181,20 +183,20 @@ __global__ void __launch_bounds__(256) k_nd_update(NdArgs a, int loff, int kb) {
   const int i0 = ti * TILE, j0 = tj * TILE;
   for (int e = threadIdx.x; e < bs * TILE; e += blockDim.x) {
     const int k = e / TILE, t = e % TILE;
-    Cs[k][t] = (i0 + t < n) ? C[int64_t(k) * n + i0 + t] : 0.0;
-    Rs[k][t] = (j0 + t < n) ? R[int64_t(k) * n + j0 + t] : 0.0;
+    Cs[k][t] = (i0 + t < ext) ? C[int64_t(k) * n + i0 + t] : 0.0;
+    Rs[k][t] = (j0 + t < ext) ? R[int64_t(k) * n + j0 + t] : 0.0;
   }
   __syncthreads();
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   for (int ii = 0; ii < 4; ++ii) {
     const int li = ty + 16 * ii;
     const int i = i0 + li;
-    if (i >= n) continue;
+    if (i >= ext) continue;
     const bool inKi = i >= K0 && i < K0 + bs;
     for (int jj = 0; jj < 4; ++jj) {
       const int lj = tx + 16 * jj;
       const int j = j0 + lj;
-      if (j >= n) continue;
+      if (j >= ext) continue;
       const bool inKj = j >= K0 && j < K0 + bs;
       double* dst = F + int64_t(i) * n + j;
       if (!inKi && !inKj) {
@@ -209,6 +211,116 @@ __global__ void __launch_bounds__(256) k_nd_update(NdArgs a, int loff, int kb) {
         *dst = -Pinv[(i - K0) * pb + (j - K0)];
       }
     }
+  }
+}
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Off the II block, on the FP64 matrix cores, 64 x 64 output tiles of every node of a level:
+//   mode 0: T = -II F_IB = F_II^-1 F_IB  (nI x nB, into the node's panel, row stride nB)
+//   mode 1: F_BB -= F_BI T               (nB x nB, in place)
+// K (= nI) in chunks of 32 staged in LDS, the next chunk's loads issued before the current
+// chunk's products. Four wavefronts, each a 32 x 32 quarter as 2 x 2 blocks of 16 x 16;
+// v_mfma_f64_16x16x4 takes A[i][k] from lane 16 k + i and B[k][j] from lane 16 k + j and
+// returns C[k' + 4 v][j] in lane 16 k' + j, register v.
+constexpr int GK = 32;
+__global__ void __launch_bounds__(256) k_nd_gemm(NdArgs a, int loff, int mode, int tiles_n) {
+  const NodeDev nd = a.lnodes[loff + blockIdx.y];
+  const int n = nd.n, nI = nd.nI, nB = nd.nB;
+  const int M = mode ? nB : nI, N = nB, K = nI;
+  const int i0 = int(blockIdx.x / tiles_n) * 64, j0 = int(blockIdx.x % tiles_n) * 64;
+  if (i0 >= M || j0 >= N || K <= 0) return;
+  double* F = a.front + nd.front_off;
+  double* T = a.panel + nd.panel_off;
+  const double* A = mode ? F + int64_t(nI) * n : F;
+  const double* B = mode ? T : F + nI;
+  double* C = mode ? F + int64_t(nI) * n + nI : T;
+  const int lda = n, ldb = mode ? nB : n, ldc = mode ? n : nB;
+  __shared__ double As[64][GK + 1];
+  __shared__ double Bs[GK][64 + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  // this thread's share of a chunk: A rows ra + 8 q at k column ca, B k rows rb + 4 q at column cb
+  const int ra = tid / GK, ca = tid % GK;
+  const int rb = tid / 64, cb = tid % 64;
+  double pa[8], pb[8];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int gi = i0 + ra + 8 * q, gk = k0 + ca;
+      pa[q] = (gi < M && gk < K) ? A[int64_t(gi) * lda + gk] : 0.0;
+      const int gk2 = k0 + rb + 4 * q, gj = j0 + cb;
+      pb[q] = (gk2 < K && gj < N) ? B[int64_t(gk2) * ldb + gj] : 0.0;
+    }
+  };
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += GK) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      As[ra + 8 * q][ca] = pa[q];
+      Bs[rb + 4 * q][cb] = pb[q];
+    }
+    __syncthreads();
+    if (k0 + GK < K) fetch(k0 + GK);
+#pragma unroll
+    for (int ks = 0; ks < GK / 4; ++ks) {
+      double ao[2], bo[2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) ao[bi] = As[wr + 16 * bi + li][4 * ks + lk];
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) bo[bj] = Bs[4 * ks + lk][wc + 16 * bj + li];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ao[bi], bo[bj], acc[bi][bj], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = i0 + wr + 16 * bi + lk + 4 * v, gj = j0 + wc + 16 * bj + li;
+        if (gi < M && gj < N) {
+          double* p = C + int64_t(gi) * ldc + gj;
+          *p = mode ? *p - acc[bi][bj][v] : -acc[bi][bj][v];
+        }
+      }
+}
+
+// IB := T and BI := T^T, 32 x 32 tiles through LDS (both writes coalesced).
+__global__ void __launch_bounds__(256) k_nd_tcopy(NdArgs a, int loff, int tiles_n) {
+  const NodeDev nd = a.lnodes[loff + blockIdx.y];
+  const int n = nd.n, nI = nd.nI, nB = nd.nB;
+  const int r0 = int(blockIdx.x / tiles_n) * 32, c0 = int(blockIdx.x % tiles_n) * 32;
+  if (r0 >= nI || c0 >= nB) return;
+  double* F = a.front + nd.front_off;
+  const double* T = a.panel + nd.panel_off;
+  __shared__ double t[32][33];
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + ty + 8 * q, c = c0 + tx;
+    if (r < nI && c < nB) {
+      const double v = T[int64_t(r) * nB + c];
+      t[ty + 8 * q][tx] = v;
+      F[int64_t(r) * n + nI + c] = v;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = c0 + ty + 8 * q, r = r0 + tx;
+    if (r < nI && c < nB) F[int64_t(nI + c) * n + r] = t[tx][ty + 8 * q];
   }
 }
 
@@ -426,15 +538,22 @@ __device__ __forceinline__ void k_nd_bwd_body(const NdArgs& a, int loff) {
   if (gl < RP && r < nI) a.y[drm] = -mine;
 }
 
-void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nmax, int nImax) {
+void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nmax, int nImax,
+                            int nBmax) {
   hipLaunchKernelGGL(k_nd_assemble, dim3((nmax + ASM_ROWS - 1) / ASM_ROWS, nnodes), dim3(256), 0, st, a, loff);
   const int nblk = (nImax + a.piv_b - 1) / a.piv_b;
-  const int tpd = (nmax + TILE - 1) / TILE;
+  const int tpd = (nImax + TILE - 1) / TILE;
   for (int kb = 0; kb < nblk; ++kb) {
     hipLaunchKernelGGL(k_nd_pivot, dim3(nnodes), dim3(256), 0, st, a, loff, kb);
     hipLaunchKernelGGL(k_nd_rpanel, dim3(tpd, nnodes), dim3(256), 0, st, a, loff, kb);
     hipLaunchKernelGGL(k_nd_update, dim3(tpd * tpd, nnodes), dim3(256), 0, st, a, loff, kb);
   }
+  if (nBmax <= 0) return;
+  const int tI = (nImax + 63) / 64, tB = (nBmax + 63) / 64;
+  hipLaunchKernelGGL(k_nd_gemm, dim3(tI * tB, nnodes), dim3(256), 0, st, a, loff, 0, tB);
+  hipLaunchKernelGGL(k_nd_gemm, dim3(tB * tB, nnodes), dim3(256), 0, st, a, loff, 1, tB);
+  const int cI = (nImax + 31) / 32, cB = (nBmax + 31) / 32;
+  hipLaunchKernelGGL(k_nd_tcopy, dim3(cI * cB, nnodes), dim3(256), 0, st, a, loff, cB);
 }
 
 // Shape for a row length: lanes per row, columns per lane, rows per lane group (about eight

@@ -201,7 +201,9 @@ void build_plan(const mpm_desc& d, Plan* p) {
   for (auto& n : P.nodes) {
     n.front_off = fo; fo += int64_t(n.n) * n.n;
     n.fI_off = io; io += n.nI;
-    n.panel_off = po; po += int64_t(P.piv_b) * P.piv_b + 2 * int64_t(P.piv_b) * n.n;
+    // the sweep's pivot block and row panels, later T = F_II^-1 F_IB (nI x nB)
+    n.panel_off = po;
+    po += std::max(int64_t(P.piv_b) * P.piv_b + 2 * int64_t(P.piv_b) * n.n, int64_t(n.nI) * n.nB);
     n.slot_off = so; so += 2 * int64_t(n.n);
     n.up_slot_off = -1;
     n.up_map_off = -1;

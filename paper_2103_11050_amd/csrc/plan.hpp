@@ -32,7 +32,8 @@ struct NodeDev {
   int32_t pad;
   int64_t front_off;          // offset (doubles) of the n x n front
   int64_t fI_off;             // offset (doubles) of the eliminated part of the condensed rhs
-  int64_t panel_off;          // offset (doubles) of the pivot-block scratch (b*b + 2*b*n)
+  int64_t panel_off;          // offset (doubles) of the pivot-block scratch (b*b + 2*b*n), then
+                              // of T = F_II^-1 F_IB (nI*nB)
   int64_t slot_off;           // offset (doubles) of the node's two child slots (2 x n)
   int64_t up_slot_off;        // offset of the parent's slot this node writes into (-1: root)
 };
