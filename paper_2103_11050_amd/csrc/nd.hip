@@ -73,50 +73,53 @@ __global__ void __launch_bounds__(256) k_nd_assemble(NdArgs a, int loff) {
   }
 }
 
-// Pivot block kb of every node of the level: P = A_KK, Pinv = P^-1 (Gauss-Jordan sweep in LDS,
-// no pivoting). One workgroup per node.
-__global__ void __launch_bounds__(256) k_nd_pivot(NdArgs a, int loff, int kb) {
-  __shared__ double P[32 * 33];
-  __shared__ double colk[32], rowk[32];
+// Pivot block kb of every node of the level: Pinv = A_KK^-1 by the sweep operator on the block
+// held in registers (blocks of 32; one wavefront per node, lane l holds column l % 32 of rows
+// 16 (l / 32) .. 16 (l / 32) + 15; a block smaller than 32 is padded with the identity, which
+// the sweep leaves decoupled). No pivoting (the front is quasi-definite).
+constexpr int PIV = 32;
+__global__ void __launch_bounds__(64) k_nd_pivot(NdArgs a, int loff, int kb) {
   const NodeDev nd = a.nodes[a.levels[loff + blockIdx.x]];
-  const int pb = a.piv_b;
-  const int K0 = kb * pb;
+  const int K0 = kb * PIV;
   if (K0 >= nd.nI) return;
-  const int bs = min(pb, nd.nI - K0);
+  const int bs = min(PIV, nd.nI - K0);
   const int n = nd.n;
   const double* F = a.front + nd.front_off;
   double* Pinv = a.panel + nd.panel_off;
-  for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
-    const int i = e / bs, j = e % bs;
-    P[i * 33 + j] = F[int64_t(K0 + i) * n + K0 + j];
+  const int lane = threadIdx.x, j = lane & 31, h = lane >> 5;
+  double p[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = 16 * h + r;
+    p[r] = (i < bs && j < bs) ? F[int64_t(K0 + i) * n + K0 + j] : (i == j ? 1.0 : 0.0);
   }
-  __syncthreads();
-  // sweep operator on every index of P: afterwards P = -P_orig^-1
   bool ok = true;
-  for (int k = 0; k < bs; ++k) {
-    const double d = P[k * 33 + k];
-    if (!(d != 0.0) || !isfinite(d)) ok = false;
+#pragma unroll
+  for (int k = 0; k < PIV; ++k) {
+    const double rowk = __shfl(p[k % 16], j + 32 * (k / 16));    // P[k][j]
+    const double d = __shfl(p[k % 16], k + 32 * (k / 16));       // P[k][k]
+    double colk[16];                                             // P[16 h + r][k]
+#pragma unroll
+    for (int r = 0; r < 16; ++r) colk[r] = __shfl(p[r], k + 32 * h);
+    ok = ok && d != 0.0 && isfinite(d);
     const double rd = 1.0 / d;
-    if (threadIdx.x < bs) {
-      colk[threadIdx.x] = P[threadIdx.x * 33 + k];
-      rowk[threadIdx.x] = P[k * 33 + threadIdx.x];
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
-      const int i = e / bs, j = e % bs;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 16 * h + r;
       double v;
       if (i == k && j == k) v = -rd;
-      else if (i == k) v = rowk[j] * rd;
-      else if (j == k) v = colk[i] * rd;
-      else v = P[i * 33 + j] - colk[i] * rowk[j] * rd;
-      P[i * 33 + j] = v;
+      else if (i == k) v = rowk * rd;
+      else if (j == k) v = colk[r] * rd;
+      else v = p[r] - colk[r] * rowk * rd;
+      p[r] = v;
     }
-    __syncthreads();
   }
-  if (!ok && threadIdx.x == 0) set_error(a.err, ERR_SINGULAR);
-  for (int e = threadIdx.x; e < bs * bs; e += blockDim.x) {
-    const int i = e / bs, j = e % bs;
-    Pinv[i * pb + j] = -P[i * 33 + j];
+  // afterwards p = -P^-1
+  if (!ok && lane == 0) set_error(a.err, ERR_SINGULAR);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = 16 * h + r;
+    if (i < bs && j < bs) Pinv[i * PIV + j] = -p[r];
   }
 }
 
@@ -538,13 +541,21 @@ __device__ __forceinline__ void k_nd_bwd_body(const NdArgs& a, int loff) {
   if (gl < RP && r < nI) a.y[drm] = -mine;
 }
 
+__global__ void k_nd_flag(int32_t* err, int32_t bits) {
+  if (threadIdx.x == 0) set_error(err, bits);
+}
+
 void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nmax, int nImax,
                             int nBmax) {
+  if (a.piv_b != PIV) {   // the pivot kernel holds blocks of PIV in registers
+    hipLaunchKernelGGL(k_nd_flag, dim3(1), dim3(64), 0, st, a.err, int32_t(ERR_SINGULAR));
+    return;
+  }
   hipLaunchKernelGGL(k_nd_assemble, dim3((nmax + ASM_ROWS - 1) / ASM_ROWS, nnodes), dim3(256), 0, st, a, loff);
   const int nblk = (nImax + a.piv_b - 1) / a.piv_b;
   const int tpd = (nImax + TILE - 1) / TILE;
   for (int kb = 0; kb < nblk; ++kb) {
-    hipLaunchKernelGGL(k_nd_pivot, dim3(nnodes), dim3(256), 0, st, a, loff, kb);
+    hipLaunchKernelGGL(k_nd_pivot, dim3(nnodes), dim3(64), 0, st, a, loff, kb);
     hipLaunchKernelGGL(k_nd_rpanel, dim3(tpd, nnodes), dim3(256), 0, st, a, loff, kb);
     hipLaunchKernelGGL(k_nd_update, dim3(tpd * tpd, nnodes), dim3(256), 0, st, a, loff, kb);
   }
