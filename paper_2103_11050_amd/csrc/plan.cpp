@@ -196,18 +196,22 @@ void build_plan(const mpm_desc& d, Plan* p) {
     P.level_nImax[n.level] = std::max(P.level_nImax[n.level], n.nI);
     P.level_nBmax[n.level] = std::max(P.level_nBmax[n.level], n.nB);
   }
-  // per-node storage and the forward-solve slots
+  // per-node storage and the forward-solve slots, level by level, so that the fronts a level
+  // kernel reads lie in one contiguous range
   int64_t fo = 0, io = 0, po = 0, so = 0;
-  for (auto& n : P.nodes) {
-    n.front_off = fo; fo += int64_t(n.n) * n.n;
-    n.fI_off = io; io += n.nI;
-    // the sweep's pivot block and row panels, later T = F_II^-1 F_IB (nI x nB)
-    n.panel_off = po;
-    po += std::max(int64_t(P.piv_b) * P.piv_b + 2 * int64_t(P.piv_b) * n.n, int64_t(n.nI) * n.nB);
-    n.slot_off = so; so += 2 * int64_t(n.n);
-    n.up_slot_off = -1;
-    n.up_map_off = -1;
-    n.pad = 0;
+  for (const auto& lv : P.level_nodes) {
+    for (int32_t id : lv) {
+      NodeDev& n = P.nodes[id];
+      n.front_off = fo; fo += int64_t(n.n) * n.n;
+      n.fI_off = io; io += n.nI;
+      // the sweep's pivot block and row panels, later T = F_II^-1 F_IB (nI x nB)
+      n.panel_off = po;
+      po += std::max(int64_t(P.piv_b) * P.piv_b + 2 * int64_t(P.piv_b) * n.n, int64_t(n.nI) * n.nB);
+      n.slot_off = so; so += 2 * int64_t(n.n);
+      n.up_slot_off = -1;
+      n.up_map_off = -1;
+      n.pad = 0;
+    }
   }
   P.leafup.assign(P.nsub, LeafUp{-1, -1, 0});
   for (auto& n : P.nodes) {
