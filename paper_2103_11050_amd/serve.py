@@ -105,6 +105,9 @@ class Server:
                     del active[slot]
                     free.append(slot)
                     used -= need
+                    done = sum(1 for r in recs.values() if "finish" in r)
+                    if done % 32 == 0:
+                        print(f"served {done}/{len(requests)} at {rec['finish']:.1f} s", file=sys.stderr, flush=True)
         makespan = time.perf_counter() - t0
         lat = np.array([r["latency"] for r in recs.values()])
         te = sum(r["te"] for r in recs.values())
