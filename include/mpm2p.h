@@ -170,13 +170,21 @@ mpm_status mpm_last_error(const mpm_run* run, char* buf, size_t len);
  * Host-side object; one host thread at a time. */
 typedef struct mpm_batch mpm_batch;
 mpm_status mpm_batch_create(int32_t capacity, mpm_batch** out);
-/* MPM_ESTATE if the slot is taken, the run is already in a batch, not started or poisoned;
- * MPM_EINVAL on a bad slot or NULL. */
+/* MPM_ESTATE if the slot is taken, the run is already in a batch, has no fields set or is
+ * poisoned; MPM_EINVAL on a bad slot or NULL. A run attached before mpm_start is started by
+ * mpm_batch_start. */
 mpm_status mpm_batch_attach(mpm_batch* batch, int32_t slot, mpm_run* run);
+/* Algorithm 1, lines 1-4 (conductivity, the first MRCM basis, interface factorisation and
+ * velocity; Sections 3 and 4.2), for every attached run not yet started, the runs with equal
+ * descriptors together: one launch per phase over a group (at most 128 runs), as in
+ * mpm_batch_step. Each run ends as after mpm_start. Returns the first error met; the runs of a
+ * group that failed are poisoned. */
+mpm_status mpm_batch_start(mpm_batch* batch);
 mpm_status mpm_batch_detach(mpm_batch* batch, int32_t slot);
 /* One pass of Algorithm 1's while loop (automatic switch) for every filled slot with
- * active[slot] != 0 (active NULL: all filled slots). Every run's work is issued before any
- * wait. breakthrough (host, capacity entries, may be NULL) receives 1 for the stepped runs
+ * active[slot] != 0 (active NULL: all filled slots); MPM_ESTATE if one of them is not started.
+ * Every run's work is issued before any wait; the runs of a group that take the MRCM branch in
+ * the same pass share its launches. breakthrough (host, capacity entries, may be NULL) receives 1 for the stepped runs
  * whose water cut reached breakthrough_cut. Returns the first error met; a run that failed is
  * poisoned, the others are stepped. */
 mpm_status mpm_batch_step(mpm_batch* batch, const uint8_t* active, uint8_t* breakthrough);

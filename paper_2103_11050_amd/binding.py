@@ -72,6 +72,7 @@ _SIGS = {
     "mpm_batch_attach": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "mpm_batch_detach": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "mpm_batch_step": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "mpm_batch_start": (ctypes.c_int32, [ctypes.c_void_p]),
     "mpm_batch_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
     "mpm_profile": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
@@ -281,8 +282,9 @@ def header_symbols(header_path: str) -> list[str]:
 
 
 class Batch:
-    """Slots of started runs stepped together (thin wrapper of mpm_batch). Give each run its own
-    stream so that their work overlaps on the device."""
+    """Slots of runs stepped together (thin wrapper of mpm_batch); runs attached before their
+    start are started by `start()`. Give each run its own stream so that their work overlaps on
+    the device."""
 
     def __init__(self, capacity: int):
         h = ctypes.c_void_p()
@@ -298,6 +300,10 @@ class Batch:
     def detach(self, slot: int):
         _check(load().mpm_batch_detach(self.h, slot), "mpm_batch_detach")
         self.runs[slot] = None
+
+    def start(self):
+        """Starts the attached runs that are not started, those with equal descriptors together."""
+        _check(load().mpm_batch_start(self.h), "mpm_batch_start")
 
     def step(self, active=None):
         """One pass for every filled (and active) slot; returns the per-slot breakthrough flags."""

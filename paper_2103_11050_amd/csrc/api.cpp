@@ -288,14 +288,15 @@ void nd_solve(mpm_run* r, Runs rt = one_run()) {
   }
 }
 
-void nd_factor(mpm_run* r) {
+void nd_factor(mpm_run* r, Runs rt = one_run()) {
   const Plan& P = r->P;
   const int L = int(P.level_nodes.size()) - 1;
   Scope sc(r, "iface_factor");
   for (int l = 1; l <= L; ++l) {
     const int nn = int(P.level_nodes[l].size());
     if (!nn) continue;
-    launch_nd_level_factor(r->st, r->nd, P.level_off[l], nn, P.level_nmax[l], P.level_nImax[l], P.level_nBmax[l]);
+    launch_nd_level_factor(r->st, r->nd, P.level_off[l], nn, P.level_nmax[l], P.level_nImax[l], P.level_nBmax[l],
+                           rt);
   }
 }
 
@@ -326,7 +327,7 @@ void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store, Run
   }
   if (r->f32 && store) {
     Scope sc(r, "to_f32");
-    launch_to_f32(r->st, r->P.n_blocks, r->nfac, r->nfac32);
+    launch_to_f32(r->st, r->P.n_blocks, r->nfac, r->nfac32, rt);
   }
   {
     Scope sc(r, "dt");
@@ -357,6 +358,28 @@ mpm_status mrcm_update(mpm_run* r) {
   HIPCHK(r, hipMemcpyAsync(r->uxm, r->ux, fx, hipMemcpyDeviceToDevice, r->st));
   HIPCHK(r, hipMemcpyAsync(r->uym, r->uy, fy, hipMemcpyDeviceToDevice, r->st));
   r->tm += 1;
+  return MPM_OK;
+}
+
+// The same update for the runs g (equal descriptors, led by g[0], run table rt): one launch per
+// phase over all of them, on the leader's stream.
+mpm_status mrcm_update_group(const std::vector<mpm_run*>& g, Runs rt) {
+  mpm_run* r = g[0];
+  const size_t nc = size_t(r->P.nx) * r->P.ny * 8;
+  for (mpm_run* x : g) HIPCHK(r, hipMemcpyAsync(x->km, x->kn, nc, hipMemcpyDeviceToDevice, r->st));
+  const bool have_fac = launch_basis(r->st, r->g, r->km, r->q, r->S, r->h, r->leafK, leaf_dest(r), r->fac, r->err, rt);
+  if (!have_fac) launch_line_factor(r->st, r->g, r->km, r->fac, r->err, rt);
+  if (r->f32) launch_to_f32(r->st, r->P.n_blocks, r->fac, r->fac32, rt);
+  nd_factor(r, rt);
+  nd_solve(r, rt);
+  finish_velocity(r, r->km, 0, 1, rt);
+  const size_t fx = size_t(r->P.ny) * (r->P.nx + 1) * 8, fy = size_t(r->P.ny + 1) * r->P.nx * 8;
+  for (mpm_run* x : g) {
+    HIPCHK(r, hipMemcpyAsync(x->uxm, x->ux, fx, hipMemcpyDeviceToDevice, r->st));
+    HIPCHK(r, hipMemcpyAsync(x->uym, x->uy, fy, hipMemcpyDeviceToDevice, r->st));
+    x->tm += 1;
+  }
+  HIPCHK(r, hipGetLastError());
   return MPM_OK;
 }
 
@@ -969,9 +992,17 @@ mpm_status group_issue(std::vector<mpm_run*>& g, GroupStreams& gs, std::vector<m
       r->te += 1;
     }
   }
-  for (mpm_run* r : mrcm) {
-    mpm_status e = mrcm_update(r);
+  if (mrcm.size() > 1) {
+    // the leader's second table: its own run is not in the MPM-2P subset
+    Runs rr;
+    mpm_status e = group_tab(mrcm, 1, gs.st, &rr);
+    if (!e) e = mrcm_update_group(mrcm, rr);
     if (e) return e;
+  } else if (!mrcm.empty()) {
+    mpm_status e = mrcm_update(mrcm[0]);
+    if (e) return e;
+  }
+  for (mpm_run* r : mrcm) {
     r->eps_prev = 0.0;
     r->eps_pending = false;
     r->last_branch = MPM_FORCE_MRCM;
@@ -1009,7 +1040,7 @@ mpm_status mpm_batch_create(int32_t capacity, mpm_batch** out) {
 mpm_status mpm_batch_attach(mpm_batch* b, int32_t slot, mpm_run* r) {
   if (!b || !r || slot < 0 || slot >= int32_t(b->slot.size())) return MPM_EINVAL;
   if (b->slot[slot] || r->owner) return MPM_ESTATE;
-  if (!r->started || r->poisoned) return MPM_ESTATE;
+  if (!r->fields || r->poisoned) return MPM_ESTATE;
   b->slot[slot] = r;
   r->owner = b;
   r->owner_slot = slot;
@@ -1034,7 +1065,7 @@ mpm_status mpm_batch_step(mpm_batch* b, const uint8_t* active, uint8_t* breakthr
   for (size_t i = 0; i < n; ++i) {
     mpm_run* r = b->slot[i];
     if (!r || (active && !active[i])) continue;
-    if (r->poisoned) return MPM_ESTATE;
+    if (r->poisoned || !r->started) return MPM_ESTATE;
     run.push_back(r);
   }
   mpm_status first = MPM_OK;
@@ -1110,6 +1141,65 @@ mpm_status mpm_batch_step(mpm_batch* b, const uint8_t* active, uint8_t* breakthr
       mpm_run* r = b->slot[i];
       breakthrough[i] = (r && (!active || active[i]) && r->pinned[3] >= r->P.d.breakthrough_cut) ? 1 : 0;
     }
+  return first;
+}
+
+mpm_status mpm_batch_start(mpm_batch* b) {
+  if (!b) return MPM_EINVAL;
+  std::vector<std::string> order;
+  std::map<std::string, std::vector<mpm_run*>> groups;
+  for (mpm_run* r : b->slot) {
+    if (!r || r->started) continue;
+    if (r->poisoned) return MPM_ESTATE;
+    std::string k = group_key(r);
+    auto& v = groups[k];
+    if (v.empty()) order.push_back(k);
+    v.push_back(r);
+  }
+  mpm_status first = MPM_OK;
+  for (const std::string& k : order) {
+    std::vector<mpm_run*>& v = groups[k];
+    int gi = -1;
+    mpm_status st = group_streams(b, k, &gi);
+    for (size_t a = 0; !st && a < v.size(); a += MPM_GROUP_MAX) {
+      std::vector<mpm_run*> g(v.begin() + a, v.begin() + std::min(v.size(), a + MPM_GROUP_MAX));
+      hipStream_t s = b->gs[gi].st;
+      for (mpm_run* r : g)
+        if (!st) st = move_run(r, s);
+      mpm_run* L = g[0];
+      // Algorithm 1, lines 1-4, for every run of the group at once
+      for (mpm_run* r : g) {
+        if (st) break;
+        if (hipMemsetAsync(r->scal, 0, SC_COUNT * 8, s) != hipSuccess ||
+            hipMemcpyAsync(r->scal + SC_MUW, r->params, sizeof(r->params), hipMemcpyHostToDevice, s) != hipSuccess)
+          st = MPM_EHIP;
+      }
+      Runs rt;
+      if (!st) st = group_tab(g, 0, s, &rt);
+      if (!st) {
+        launch_kappa(s, L->g, L->s, L->K, L->kn, L->km, L->red, L->scal, L->dsflag, L->dslist, L->dscount,
+                     L->dscount + 1, L->pinned_dev, rt);
+        for (mpm_run* r : g) {
+          r->eps_seq += 1;
+          r->te = 0; r->tm = 0; r->ntr = 0;
+        }
+        st = g.size() > 1 ? mrcm_update_group(g, rt) : mrcm_update(L);
+      }
+      if (st) break;
+      for (mpm_run* r : g) {
+        r->te = 1;
+        r->eps_prev = r->P.d.eta;
+        r->eps_pending = false;
+        r->last_branch = MPM_FORCE_MRCM;
+        r->started = true;
+      }
+    }
+    if (st) {
+      if (!first) first = st;
+      for (mpm_run* r : v)
+        if (!r->started) r->poisoned = true;
+    }
+  }
   return first;
 }
 

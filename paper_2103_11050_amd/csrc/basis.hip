@@ -82,7 +82,18 @@ __device__ __forceinline__ int gcell3(const Geo& g, int I, int J, int i, int j) 
 __global__ void __launch_bounds__(64)
 k_basis_mfma(Geo g, const double* __restrict__ kap, const double* __restrict__ q, double* __restrict__ Sg,
              double* __restrict__ hg, double* __restrict__ leafK, LeafOut lo, double* __restrict__ fac,
-             int store_fac, int32_t* err) {
+             int store_fac, int32_t* err, const RunTab* __restrict__ rt) {
+  {
+    const int64_t wo = ws_off(rt);
+    kap = at_off(kap, wo);
+    q = at_off(q, wo);
+    Sg = at_off(Sg, wo);
+    hg = at_off(hg, wo);
+    leafK = at_off(leafK, wo);
+    lo = leaf_at(lo, wo);
+    fac = at_off(fac, wo);
+    err = at_off(err, wo);
+  }
   __shared__ double kl[256], tE[256], tN[256], dg[256], rhs0[256], wsh[64], hsh[64];
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
@@ -237,13 +248,14 @@ k_basis_mfma(Geo g, const double* __restrict__ kap, const double* __restrict__ q
 
 // Returns whether the kappa^m line-block inverses were written (lines of 9..16 cells).
 bool launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
-                  double* leafK, LeafOut lo, double* fac, int32_t* err) {
+                  double* leafK, LeafOut lo, double* fac, int32_t* err, Runs rt) {
   if (g.nc / g.band > 16) {   // more lines than the matrix-core column blocks take
-    launch_basis_lines(st, g, kap, q, S, h, leafK, lo, fac, err);
+    launch_basis_lines(st, g, kap, q, S, h, leafK, lo, fac, err, rt);
     return true;
   }
   const int store = g.band > 8 ? 1 : 0;
-  hipLaunchKernelGGL(k_basis_mfma, dim3(g.nsub), dim3(64), 0, st, g, kap, q, S, h, leafK, lo, fac, store, err);
+  hipLaunchKernelGGL(k_basis_mfma, dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, g, kap, q, S, h, leafK, lo, fac,
+                     store, err, rt.tab);
   return store != 0;
 }
 

@@ -49,13 +49,14 @@ void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* r
 
 // basis.hip: returns whether the kappa^m line-block inverses were written as well
 bool launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
-                  double* leafK, LeafOut lo, double* fac, int32_t* err);
+                  double* leafK, LeafOut lo, double* fac, int32_t* err, Runs rt = one_run());
 // lines.hip
 // The same basis for subdomains of more than 16 lines, by one line-block solve per boundary
 // face; always writes the inverse blocks.
 void launch_basis_lines(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
-                        double* leafK, LeafOut lo, double* fac, int32_t* err);
-void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double* fac, int32_t* err);
+                        double* leafK, LeafOut lo, double* fac, int32_t* err, Runs rt = one_run());
+void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double* fac, int32_t* err,
+                        Runs rt = one_run());
 size_t line_factor_doubles(int nsub, int nc, int band);
 void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                       const double* uym, const double* q, const double* fac, double* h, double* vbnd,
@@ -86,7 +87,7 @@ void launch_mpm_local_f32(hipStream_t st, const Geo& g, const double* kn, const 
 void launch_downscale_f32(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
                           double* ux, double* uy, double* red_rate, double* red_qin, float* Escr, float* Ekeep,
                           const int32_t* flag, int32_t* err, Runs rt = one_run());
-void launch_to_f32(hipStream_t st, size_t n, const double* src, float* dst);
+void launch_to_f32(hipStream_t st, size_t n, const double* src, float* dst, Runs rt = one_run());
 void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
                       double* ux, double* uy, double* red_rate, double* red_qin, double* Escr, double* Ekeep,
                       const int32_t* flag, int store, int32_t* err, Runs rt = one_run());
@@ -128,7 +129,7 @@ __device__ __forceinline__ NdArgs nd_at(const NdArgs& a, int64_t o) {
   return b;
 }
 void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nmax, int nImax,
-                            int nBmax);
+                            int nBmax, Runs rt = one_run());
 void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nImax, int nBmax,
                          Runs rt = one_run());
 void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nImax, int nmax, int root,

@@ -254,7 +254,13 @@ __device__ __forceinline__ void lb_solve_refined(const Geo& g, const LineW& W, c
 // Factor of the local Robin matrix of kappa^m (eq:mrc1 with zero data), stored for MPM-2P.
 template <int MF>
 __global__ void __launch_bounds__(64) k_line_factor(Geo g, const double* __restrict__ kap, double* __restrict__ fac,
-                                                    int32_t* err) {
+                                                    int32_t* err, const RunTab* __restrict__ rt) {
+  {
+    const int64_t wo = ws_off(rt);
+    kap = at_off(kap, wo);
+    fac = at_off(fac, wo);
+    err = at_off(err, wo);
+  }
   __shared__ double kl[256], tE[256], tN[256], dg[256];
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
@@ -279,7 +285,19 @@ template <int MF>
 __global__ void __launch_bounds__(64) k_basis_lines(Geo g, const double* __restrict__ kap,
                                                     const double* __restrict__ q, double* __restrict__ Sg,
                                                     double* __restrict__ hg, double* __restrict__ leafK, LeafOut lo,
-                                                    double* __restrict__ fac, int32_t* err) {
+                                                    double* __restrict__ fac, int32_t* err,
+                                                    const RunTab* __restrict__ rt) {
+  {
+    const int64_t wo = ws_off(rt);
+    kap = at_off(kap, wo);
+    q = at_off(q, wo);
+    Sg = at_off(Sg, wo);
+    hg = at_off(hg, wo);
+    leafK = at_off(leafK, wo);
+    lo = leaf_at(lo, wo);
+    fac = at_off(fac, wo);
+    err = at_off(err, wo);
+  }
   __shared__ double kl[256], tE[256], tN[256], dg[256], x[256], wsh[64], hsh[64];
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
@@ -938,15 +956,17 @@ k_ds_factor(Geo g, const double* __restrict__ kap_n, T* __restrict__ Escr, const
 static int line_mf(const Geo& g) { return g.band <= 8 ? 8 : 16; }
 
 void launch_basis_lines(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
-                        double* leafK, LeafOut lo, double* fac, int32_t* err) {
+                        double* leafK, LeafOut lo, double* fac, int32_t* err, Runs rt) {
+  const dim3 grid(g.nsub, 1, runs_of(rt));
   if (line_mf(g) == 8)
-    hipLaunchKernelGGL(k_basis_lines<8>, dim3(g.nsub), dim3(64), 0, st, g, kap, q, S, h, leafK, lo, fac, err);
-  else hipLaunchKernelGGL(k_basis_lines<16>, dim3(g.nsub), dim3(64), 0, st, g, kap, q, S, h, leafK, lo, fac, err);
+    hipLaunchKernelGGL(k_basis_lines<8>, grid, dim3(64), 0, st, g, kap, q, S, h, leafK, lo, fac, err, rt.tab);
+  else hipLaunchKernelGGL(k_basis_lines<16>, grid, dim3(64), 0, st, g, kap, q, S, h, leafK, lo, fac, err, rt.tab);
 }
 
-void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double* fac, int32_t* err) {
-  if (line_mf(g) == 8) hipLaunchKernelGGL(k_line_factor<8>, dim3(g.nsub), dim3(64), 0, st, g, kap, fac, err);
-  else hipLaunchKernelGGL(k_line_factor<16>, dim3(g.nsub), dim3(64), 0, st, g, kap, fac, err);
+void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double* fac, int32_t* err, Runs rt) {
+  const dim3 grid(g.nsub, 1, runs_of(rt));
+  if (line_mf(g) == 8) hipLaunchKernelGGL(k_line_factor<8>, grid, dim3(64), 0, st, g, kap, fac, err, rt.tab);
+  else hipLaunchKernelGGL(k_line_factor<16>, grid, dim3(64), 0, st, g, kap, fac, err, rt.tab);
 }
 
 // line length padded to MF in {8, 16}; the solve keeps the blocks in registers for the
@@ -1019,14 +1039,18 @@ void launch_downscale_f32(hipStream_t st, const Geo& g, const double* kap_s, con
   MPM_LB_DISPATCH_F32(k_downscale_lb, g, kap_s, q, ubnd, ux, uy, red_rate, red_qin, Escr, Ekeep, flag, 0, err, rt.tab);
 }
 
-__global__ void __launch_bounds__(256) k_to_f32(size_t n, const double* __restrict__ src, float* __restrict__ dst) {
+__global__ void __launch_bounds__(256) k_to_f32(size_t n, const double* __restrict__ src, float* __restrict__ dst,
+                                               const RunTab* __restrict__ rt) {
+  src = at_off(src, ws_off(rt));
+  dst = at_off(dst, ws_off(rt));
   const size_t i = size_t(blockIdx.x) * 256 + threadIdx.x;
   if (i < n) dst[i] = float(src[i]);
 }
 
-void launch_to_f32(hipStream_t st, size_t n, const double* src, float* dst) {
+void launch_to_f32(hipStream_t st, size_t n, const double* src, float* dst, Runs rt) {
   if (!n) return;
-  hipLaunchKernelGGL(k_to_f32, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, n, src, dst);
+  hipLaunchKernelGGL(k_to_f32, dim3(unsigned((n + 255) / 256), 1, runs_of(rt)), dim3(256), 0, st, n, src, dst,
+                     rt.tab);
 }
 
 void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,

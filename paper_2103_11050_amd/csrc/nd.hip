@@ -49,7 +49,8 @@ __device__ __forceinline__ const double* child_S(const NdArgs& a, const NodeDev&
 // S0[inv0 k][inv0 l] + S1[inv1 k][inv1 l] with absent terms left out (child 0 first, the same
 // sum as adding the children one after the other into a zeroed front).
 constexpr int ASM_ROWS = 8;
-__global__ void __launch_bounds__(256) k_nd_assemble(NdArgs a, int loff) {
+__global__ void __launch_bounds__(256) k_nd_assemble(NdArgs a0, int loff, const RunTab* __restrict__ rt) {
+  const NdArgs a = nd_at(a0, ws_off(rt));
   const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
   const int n = nd.n;
   const int k0 = blockIdx.x * ASM_ROWS;
@@ -78,7 +79,8 @@ __global__ void __launch_bounds__(256) k_nd_assemble(NdArgs a, int loff) {
 // 16 (l / 32) .. 16 (l / 32) + 15; a block smaller than 32 is padded with the identity, which
 // the sweep leaves decoupled). No pivoting (the front is quasi-definite).
 constexpr int PIV = 32;
-__global__ void __launch_bounds__(64) k_nd_pivot(NdArgs a, int loff, int kb) {
+__global__ void __launch_bounds__(64) k_nd_pivot(NdArgs a0, int loff, int kb, const RunTab* __restrict__ rt) {
+  const NdArgs a = nd_at(a0, ws_off(rt));
   const NodeDev nd = a.nodes[a.levels[loff + blockIdx.x]];
   const int K0 = kb * PIV;
   if (K0 >= nd.nI) return;
@@ -125,7 +127,8 @@ __global__ void __launch_bounds__(64) k_nd_pivot(NdArgs a, int loff, int kb) {
 
 // Row panel of pivot block kb over the II block: C = old rows A_K* (copied, the update
 // overwrites them) and R = Pinv C, 64 columns per workgroup.
-__global__ void __launch_bounds__(256) k_nd_rpanel(NdArgs a, int loff, int kb) {
+__global__ void __launch_bounds__(256) k_nd_rpanel(NdArgs a0, int loff, int kb, const RunTab* __restrict__ rt) {
+  const NdArgs a = nd_at(a0, ws_off(rt));
   __shared__ double Pi[32][33];
   __shared__ double Cs[32][65];
   const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
@@ -167,7 +170,8 @@ __global__ void __launch_bounds__(256) k_nd_rpanel(NdArgs a, int loff, int kb) {
 //   i not in K, j in K : A_ij = R_(j-K0) i
 //   i in K, j not in K : A_ij = R_(i-K0) j
 //   i,j in K : A_ij = -Pinv
-__global__ void __launch_bounds__(256) k_nd_update(NdArgs a, int loff, int kb) {
+__global__ void __launch_bounds__(256) k_nd_update(NdArgs a0, int loff, int kb, const RunTab* __restrict__ rt) {
+  const NdArgs a = nd_at(a0, ws_off(rt));
   __shared__ double Cs[32][TILE + 1];
   __shared__ double Rs[32][TILE + 1];
   const NodeDev nd = a.nodes[a.levels[loff + blockIdx.y]];
@@ -227,7 +231,8 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // v_mfma_f64_16x16x4 takes A[i][k] from lane 16 k + i and B[k][j] from lane 16 k + j and
 // returns C[k' + 4 v][j] in lane 16 k' + j, register v.
 constexpr int GK = 32;
-__global__ void __launch_bounds__(256) k_nd_gemm(NdArgs a, int loff, int mode, int tiles_n) {
+__global__ void __launch_bounds__(256) k_nd_gemm(NdArgs a0, int loff, int mode, int tiles_n, const RunTab* __restrict__ rt) {
+  const NdArgs a = nd_at(a0, ws_off(rt));
   const NodeDev nd = a.lnodes[loff + blockIdx.y];
   const int n = nd.n, nI = nd.nI, nB = nd.nB;
   const int M = mode ? nB : nI, N = nB, K = nI;
@@ -301,7 +306,8 @@ __global__ void __launch_bounds__(256) k_nd_gemm(NdArgs a, int loff, int mode, i
 }
 
 // IB := T and BI := T^T, 32 x 32 tiles through LDS (both writes coalesced).
-__global__ void __launch_bounds__(256) k_nd_tcopy(NdArgs a, int loff, int tiles_n) {
+__global__ void __launch_bounds__(256) k_nd_tcopy(NdArgs a0, int loff, int tiles_n, const RunTab* __restrict__ rt) {
+  const NdArgs a = nd_at(a0, ws_off(rt));
   const NodeDev nd = a.lnodes[loff + blockIdx.y];
   const int n = nd.n, nI = nd.nI, nB = nd.nB;
   const int r0 = int(blockIdx.x / tiles_n) * 32, c0 = int(blockIdx.x % tiles_n) * 32;
@@ -546,25 +552,27 @@ __global__ void k_nd_flag(int32_t* err, int32_t bits) {
 }
 
 void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nmax, int nImax,
-                            int nBmax) {
+                            int nBmax, Runs rt) {
+  const unsigned nr = runs_of(rt);
   if (a.piv_b != PIV) {   // the pivot kernel holds blocks of PIV in registers
     hipLaunchKernelGGL(k_nd_flag, dim3(1), dim3(64), 0, st, a.err, int32_t(ERR_SINGULAR));
     return;
   }
-  hipLaunchKernelGGL(k_nd_assemble, dim3((nmax + ASM_ROWS - 1) / ASM_ROWS, nnodes), dim3(256), 0, st, a, loff);
+  hipLaunchKernelGGL(k_nd_assemble, dim3((nmax + ASM_ROWS - 1) / ASM_ROWS, nnodes, nr), dim3(256), 0, st, a, loff,
+                     rt.tab);
   const int nblk = (nImax + a.piv_b - 1) / a.piv_b;
   const int tpd = (nImax + TILE - 1) / TILE;
   for (int kb = 0; kb < nblk; ++kb) {
-    hipLaunchKernelGGL(k_nd_pivot, dim3(nnodes), dim3(64), 0, st, a, loff, kb);
-    hipLaunchKernelGGL(k_nd_rpanel, dim3(tpd, nnodes), dim3(256), 0, st, a, loff, kb);
-    hipLaunchKernelGGL(k_nd_update, dim3(tpd * tpd, nnodes), dim3(256), 0, st, a, loff, kb);
+    hipLaunchKernelGGL(k_nd_pivot, dim3(nnodes, 1, nr), dim3(64), 0, st, a, loff, kb, rt.tab);
+    hipLaunchKernelGGL(k_nd_rpanel, dim3(tpd, nnodes, nr), dim3(256), 0, st, a, loff, kb, rt.tab);
+    hipLaunchKernelGGL(k_nd_update, dim3(tpd * tpd, nnodes, nr), dim3(256), 0, st, a, loff, kb, rt.tab);
   }
   if (nBmax <= 0) return;
   const int tI = (nImax + 63) / 64, tB = (nBmax + 63) / 64;
-  hipLaunchKernelGGL(k_nd_gemm, dim3(tI * tB, nnodes), dim3(256), 0, st, a, loff, 0, tB);
-  hipLaunchKernelGGL(k_nd_gemm, dim3(tB * tB, nnodes), dim3(256), 0, st, a, loff, 1, tB);
+  hipLaunchKernelGGL(k_nd_gemm, dim3(tI * tB, nnodes, nr), dim3(256), 0, st, a, loff, 0, tB, rt.tab);
+  hipLaunchKernelGGL(k_nd_gemm, dim3(tB * tB, nnodes, nr), dim3(256), 0, st, a, loff, 1, tB, rt.tab);
   const int cI = (nImax + 31) / 32, cB = (nBmax + 31) / 32;
-  hipLaunchKernelGGL(k_nd_tcopy, dim3(cI * cB, nnodes), dim3(256), 0, st, a, loff, cB);
+  hipLaunchKernelGGL(k_nd_tcopy, dim3(cI * cB, nnodes, nr), dim3(256), 0, st, a, loff, cB, rt.tab);
 }
 
 // Shape for a row length: lanes per row, columns per lane, rows per lane group (about eight

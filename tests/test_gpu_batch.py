@@ -205,15 +205,18 @@ GROUPED = [
 ]
 
 
-def _make_g(binding, p, stream=None):
+def _make_g(binding, p, stream=None, start=True):
     seed, nx, ny, sub, ne, kw, prec = p
-    cfg, K = inputs.random_problem(seed, nx, ny, sub, sub, ne, ne, **kw)
+    kw = dict(kw)
+    sub_y, ne_y = kw.pop("sub_y", sub), kw.pop("ne_y", ne)
+    cfg, K = inputs.random_problem(seed, nx, ny, sub, sub_y, ne, ne_y, **kw)
     dev = torch.device("cuda:0")
     Kt = torch.from_numpy(np.ascontiguousarray(K)).to(dev)
     st = torch.from_numpy(np.ascontiguousarray(inputs.initial_saturation(cfg))).to(dev)
     torch.cuda.synchronize()
     r = binding.Run(cfg, Kt, st, precision=prec, stream=stream)
-    r.start()
+    if start:
+        r.start()
     return r
 
 
@@ -284,3 +287,64 @@ def test_grouped_batch_parity_and_refill(binding):
         _same(g, ref)
     for r in runs:
         r.close()
+
+
+# eta = 0: many passes take the MRCM branch, in the same passes for every run of a group, which
+# then share the update's launches
+EVERY_PASS_MRCM = [
+    (221, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.2, mu_o=20.0, eta=0.0), 0),
+    (222, 32, 32, 8, 2, dict(sigma2=2.5, corr_len=0.2, mu_o=30.0, eta=0.0), 0),
+    (223, 32, 32, 8, 2, dict(sigma2=2.0, corr_len=0.15, mu_o=20.0, eta=0.0), 0),
+    (224, 48, 32, 16, 4, dict(sigma2=2.0, corr_len=0.2, mu_o=30.0, eta=0.0), 1),
+    (225, 48, 32, 16, 4, dict(sigma2=2.0, corr_len=0.2, mu_o=40.0, eta=0.0), 1),
+    (226, 60, 30, 20, 4, dict(sigma2=2.0, corr_len=0.2, mu_o=30.0, eta=0.0, sub_y=10, ne_y=2), 0),
+    (227, 60, 30, 20, 4, dict(sigma2=3.0, corr_len=0.2, mu_o=30.0, eta=0.0, sub_y=10, ne_y=2), 0),
+]
+
+
+def test_batch_start_and_grouped_mrcm_equal_solo(binding):
+    """Runs attached before their start, started together (one launch per phase of the first
+    MRCM update for each group of equal descriptors), then stepped: equal, bitwise, to the
+    same runs started and stepped alone. Covers every phase of the MRCM update over a run table:
+    the matrix-core basis and the many-line basis, the FP32 copies of the precision form, the
+    factorisation and both first-order and linear-space groups, and passes in which every run of
+    a group takes the MRCM branch."""
+    ps = GROUPED + EVERY_PASS_MRCM
+    nsteps = 4
+    print("[gpu] batch start of", len(ps), "runs,", nsteps, "steps", flush=True)
+    solo = [_solo(binding, p, nsteps) for p in ps]
+    streams = [torch.cuda.Stream() for _ in ps]
+    runs = [_make_g(binding, p, s, start=False) for p, s in zip(ps, streams)]
+    b = binding.Batch(len(runs))
+    for i, r in enumerate(runs):
+        b.attach(i, r)
+    b.start()
+    for _ in range(nsteps):
+        b.step()
+    for p, r, (ref, hist) in zip(ps, runs, solo):
+        got = _state(r)
+        _same(got, ref)
+        assert got[3]["error_word"] == 0
+    # with the lagged rule and eta = 0 every other pass is an MRCM update, for all runs of a
+    # group in the same passes
+    hists = [hist for _, hist in solo[len(GROUPED):]]
+    for hist in hists:
+        assert sum(h == binding.FORCE_MRCM for h in hist) >= nsteps // 2, hist
+    assert hists[0] == hists[1] == hists[2] and hists[3] == hists[4] and hists[5] == hists[6]
+    b.close()
+    for r in runs:
+        r.close()
+
+
+def test_batch_step_refuses_unstarted_runs(binding):
+    p = GROUPED[0]
+    r = _make_g(binding, p, torch.cuda.Stream(), start=False)
+    b = binding.Batch(2)
+    b.attach(0, r)
+    with pytest.raises(binding.MpmError):
+        b.step()
+    b.start()
+    b.step()
+    assert r.stats()["te"] == 2
+    b.close()
+    r.close()
