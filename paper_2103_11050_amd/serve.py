@@ -2,7 +2,8 @@
 
 Serving: forward-run requests (Algorithm 1 of Section 4.2, each run to water breakthrough)
 arrive over time. A request is admitted into a free slot of one `Batch` when its exact device
-footprint (`mpm_workspace_size`) fits the remaining HBM budget; it then keeps its basis,
+footprint (`mpm_workspace_size`) fits the remaining HBM budget (the requests admitted between
+two passes start together, one launch per phase for equal descriptors); it then keeps its basis,
 interface factorisation and saturation resident in its workspace and steps together with the
 others (runs with equal descriptors as one launch per phase, the rest each on its own stream;
 every run's work issued before any wait). A finished run leaves its slot and frees its
@@ -49,9 +50,7 @@ class Server:
         Kt = torch.from_numpy(K).to(self.dev)
         st = torch.from_numpy(inputs.initial_saturation(cfg)).to(self.dev)
         torch.cuda.synchronize()
-        run = binding.Run(cfg, Kt, st, stream=self.streams[slot])
-        run.start()
-        return run
+        return binding.Run(cfg, Kt, st, stream=self.streams[slot])
 
     def serve(self, requests: list[dict], arrivals: list[float]) -> dict:
         """Runs every request to breakthrough (or max_updates passes); arrivals in seconds from
@@ -67,6 +66,7 @@ class Server:
         batch_steps = 0
         while pending or active:
             now = time.perf_counter() - t0
+            admitted = False
             while pending and free and arrivals[pending[0]] <= now:
                 i = pending[0]
                 need = binding.workspace_size(requests[i])
@@ -80,6 +80,9 @@ class Server:
                 used += need
                 recs[i] = {"id": i, "nx": requests[i]["nx"], "arrival": arrivals[i],
                            "admit": time.perf_counter() - t0}
+                admitted = True
+            if admitted:      # the requests admitted in this round start together
+                self.batch.start()
             if not active:
                 if pending:
                     time.sleep(max(0.0, min(0.01, arrivals[pending[0]] - (time.perf_counter() - t0))))
