@@ -1,0 +1,138 @@
+// Host-side consistency of the plan (the nested-dissection tree of the interface system, the
+// extend-add maps and the workspace layout) for a set of decompositions; built and run by
+// tests/test_plan.py. Prints one line per decomposition: "ok ..." or the first failed check.
+#include <algorithm>
+#include <cstdio>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "plan.hpp"
+
+using namespace mpm;
+
+namespace {
+
+std::string check(const mpm_desc& d) {
+  Plan P;
+  build_plan(d, &P);
+  const int nd = P.n_iface;
+  // every interface unknown is eliminated at exactly one node
+  std::vector<int> elim(nd, 0);
+  for (const NodeDev& n : P.nodes)
+    for (int i = 0; i < n.nI; ++i) {
+      const int id = P.dof_pool[n.dof_off + i];
+      if (id < 0 || id >= nd) return "unknown id out of range";
+      elim[id] += 1;
+    }
+  if (P.nsub > 1)
+    for (int id = 0; id < nd; ++id)
+      if (elim[id] != 1) return "unknown " + std::to_string(id) + " eliminated " + std::to_string(elim[id]) + " times";
+  // children's boundary unknowns sit at the mapped positions of the parent's front, and the
+  // inverse maps point back
+  for (const NodeDev& n : P.nodes) {
+    if (n.n != n.nI + n.nB) return "front size";
+    for (int c = 0; c < 2; ++c) {
+      const int ch = n.child[c];
+      std::vector<int32_t> cb;
+      if (ch < 0) {
+        const int sub = -1 - ch;
+        for (int a = 0; a < P.sub_ndof[sub]; ++a) cb.push_back(P.sub_dofs[size_t(sub) * P.ndmax + a]);
+      } else {
+        const NodeDev& cn = P.nodes[ch];
+        if (cn.level >= n.level) return "child level";
+        for (int i = 0; i < cn.nB; ++i) cb.push_back(P.dof_pool[cn.dof_off + cn.nI + i]);
+        if (cn.up_map_off != n.map_off[c]) return "up map of a child";
+        if (cn.up_slot_off != n.slot_off + int64_t(c) * n.n) return "up slot of a child";
+      }
+      if (int(cb.size()) != n.nB_child[c]) return "child boundary size";
+      for (size_t i = 0; i < cb.size(); ++i) {
+        const int pos = P.map_pool[n.map_off[c] + i];
+        if (pos < 0 || pos >= n.n) return "map out of range";
+        if (P.dof_pool[n.dof_off + pos] != cb[i]) return "map does not match the parent's unknown";
+        if (P.inv_pool[n.inv_off + size_t(c) * n.n + pos] != int(i)) return "inverse map";
+      }
+    }
+  }
+  // the leaves' right-hand sides go to their parent's slot through the same maps
+  for (int s = 0; s < P.nsub && P.nsub > 1; ++s) {
+    const LeafUp& u = P.leafup[s];
+    if (u.slot_off < 0) return "leaf without parent";
+  }
+  // storage: disjoint ranges in bounds, each level's fronts one contiguous range
+  std::vector<std::pair<int64_t, int64_t>> fr, pa, sl, fi;
+  for (const NodeDev& n : P.nodes) {
+    fr.push_back({n.front_off, int64_t(n.n) * n.n});
+    pa.push_back({n.panel_off, std::max<int64_t>(int64_t(P.piv_b) * P.piv_b + 2 * int64_t(P.piv_b) * n.n,
+                                                 int64_t(n.nI) * n.nB)});
+    sl.push_back({n.slot_off, 2 * int64_t(n.n)});
+    fi.push_back({n.fI_off, n.nI});
+  }
+  auto disjoint = [](std::vector<std::pair<int64_t, int64_t>> v, int64_t total) {
+    std::sort(v.begin(), v.end());
+    int64_t end = 0;
+    for (auto& r : v) {
+      if (r.first < end) return false;
+      end = r.first + r.second;
+    }
+    return end <= total;
+  };
+  if (!disjoint(fr, P.front_doubles)) return "fronts overlap";
+  if (!disjoint(pa, P.panel_doubles)) return "panels overlap";
+  if (!disjoint(sl, P.slot_doubles)) return "slots overlap";
+  if (!disjoint(fi, P.fI_doubles)) return "f_I ranges overlap";
+  for (size_t L = 1; L < P.level_nodes.size(); ++L) {
+    int64_t lo = -1, hi = -1, sum = 0;
+    for (int32_t id : P.level_nodes[L]) {
+      const NodeDev& n = P.nodes[id];
+      if (n.level != int(L)) return "level list";
+      lo = lo < 0 ? n.front_off : std::min(lo, n.front_off);
+      hi = std::max(hi, n.front_off + int64_t(n.n) * n.n);
+      sum += int64_t(n.n) * n.n;
+    }
+    if (hi - lo != sum) return "fronts of level " + std::to_string(L) + " not contiguous";
+    for (int k = P.level_off[L]; k < P.level_off[L + 1]; ++k)
+      if (P.lnodes[k].level != int(L) || P.lnodes[k].front_off != P.nodes[P.level_flat[k]].front_off)
+        return "level-ordered copy";
+  }
+  // workspace regions: aligned, in bounds
+  const size_t offs[] = {P.off_K, P.off_q, P.off_s, P.off_s2, P.off_kn, P.off_km, P.off_ux, P.off_uy, P.off_fac,
+                         P.off_S, P.off_h, P.off_ubnd, P.off_leafK, P.off_front, P.off_panel, P.off_y, P.off_red,
+                         P.off_scal, P.off_rtab};
+  for (size_t o : offs)
+    if (o % 256 || o >= P.total_bytes) return "workspace offset";
+  if (P.off_front + size_t(std::max<int64_t>(P.front_doubles, 1)) * 8 > P.off_fI) return "front region size";
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "ok nsub %d unknowns %d nodes %zu levels %zu bytes %zu", P.nsub, P.n_iface,
+                P.nodes.size(), P.level_nodes.size() - 1, P.total_bytes);
+  return buf;
+}
+
+}  // namespace
+
+int main() {
+  // nx, ny, sub_x, sub_y, ne_x, ne_y, iface_degree
+  const int shapes[][7] = {{32, 32, 8, 8, 2, 2, 0},    {32, 32, 8, 8, 2, 2, 1},   {12, 8, 4, 4, 2, 1, 0},
+                           {30, 20, 10, 10, 5, 2, 0},  {30, 20, 10, 10, 1, 5, 1}, {48, 8, 8, 8, 1, 4, 0},
+                           {60, 30, 20, 10, 4, 2, 1},  {16, 10, 16, 10, 1, 1, 0}, {40, 24, 8, 8, 2, 2, 0},
+                           {256, 256, 16, 16, 4, 4, 0}, {1024, 1024, 16, 16, 8, 8, 0}, {300, 50, 20, 10, 20, 10, 0}};
+  int bad = 0;
+  for (const auto& s : shapes) {
+    mpm_desc d{};
+    d.abi_version = MPM_ABI_VERSION;
+    d.nx = s[0]; d.ny = s[1]; d.lx = 1.0; d.ly = 1.0; d.sub_x = s[2]; d.sub_y = s[3]; d.ne_x = s[4]; d.ne_y = s[5];
+    d.iface_degree = s[6];
+    d.alpha = 1.0; d.eta = 0.1; d.cn = 1; d.mu_w = 1.0; d.mu_o = 10.0; d.cfl = 0.5; d.breakthrough_cut = 0.5;
+    d.bc_kind[0] = MPM_BC_FLUX; d.bc_value[0] = -1.0; d.bc_kind[1] = MPM_BC_PRESSURE; d.s_inj = 1.0;
+    std::string why;
+    if (validate(d, &why) != MPM_OK) {
+      std::printf("%dx%d invalid: %s\n", s[0], s[1], why.c_str());
+      bad = 1;
+      continue;
+    }
+    const std::string r = check(d);
+    std::printf("%dx%d sub %dx%d ne %d,%d deg %d: %s\n", s[0], s[1], s[2], s[3], s[4], s[5], s[6], r.c_str());
+    if (r.compare(0, 2, "ok") != 0) bad = 1;
+  }
+  return bad;
+}

@@ -1,0 +1,25 @@
+"""Host logic of the plan (CPU): the nested-dissection tree eliminates every interface unknown
+once, the extend-add maps place each child's boundary unknowns at the parent's matching
+positions (and the inverse maps point back), node storage ranges are disjoint with each level's
+fronts contiguous, and workspace offsets are aligned and in bounds; for constant and linear
+interface spaces, ragged trees, one subdomain, many-line subdomains and the metric workload."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "..", "paper_2103_11050_amd", "csrc")
+INC = os.path.join(HERE, "..", "include")
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="no host C++ compiler")
+def test_plan_consistency(tmp_path):
+    exe = tmp_path / "plan_check"
+    subprocess.run(["g++", "-O1", "-std=c++17", "-I", CSRC, "-I", INC, os.path.join(HERE, "plan_check.cpp"),
+                    os.path.join(CSRC, "plan.cpp"), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    print(out.stdout)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.count(": ok") == 12
