@@ -26,10 +26,11 @@ Where the paper is silent the oracle takes the readings listed in the design not
 repository (fine element, orientation, epsilon norm, switch timing, downscaling of MRCM,
 discrete form of kappa^n grad p^m, transport time step, breakthrough).
 
-Parity status: every function here is pinned by a ``-m "not gpu"`` test except the MRCM
-solution with interface elements longer than one fine face and the MPM-2P solution (zeroth
-or first order) with a nonzero perturbation on such decompositions, which the paper defines
-only through the algorithm itself (parity unpinned beyond the invariants listed in the
-tests). The first-order term is pinned where MRCM is exact (second Richardson step, error
-cubic in the perturbation) and by vanishing without perturbation.
+Parity status: every function here is pinned by a ``-m "not gpu"`` test. The MRCM solution
+with interface elements longer than one fine face (constant and linear spaces) is pinned by a
+monolithic assembly of the whole system written face by face, with no basis functions; the
+MPM-2P velocity (zeroth and first order) on such decompositions by the same assembly applied
+to the perturbation problems, followed by the downscaling. The first-order term is also pinned
+where MRCM is exact (second Richardson step, error cubic in the perturbation) and by vanishing
+without perturbation.
 """

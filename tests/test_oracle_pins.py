@@ -584,10 +584,18 @@ def test_T18_oracle_bf_count_matches_formula():
 # ---------------------------------------------------------------- T19: brute force
 
 def _monolithic_mrcm(cfg, kap):
+    p, y, _, _ = _monolithic(cfg, kap)
+    return p, y
+
+
+def _monolithic(cfg, kap, src=None, bdat=None):
     """All cell pressures and all interface unknowns in one sparse system, written face by
     face: local two-point fluxes with Robin faces on Gamma, and the interface equations
     of eq:mrc2 per element and basis function (constants, or with iface_degree = 1 also the
-    linear function of the face midpoint). Independent of the basis-function machinery."""
+    linear function of the face midpoint). Independent of the basis-function machinery.
+    ``src``: cell source (default 0); ``bdat(side, i, j, kind, value)``: datum of a physical
+    face (default the side's value). Returns (p, y, ux, uy): the face fluxes are the local ones,
+    the mean of both sides' on Gamma."""
     dec = mrcm.Decomposition(cfg)
     nx, ny, hx, hy = dec.nx, dec.ny, dec.hx, dec.hy
     nc = nx * ny
@@ -640,6 +648,8 @@ def _monolithic_mrcm(cfg, kap):
             return co, 0.0, (l, side_s, beta, phi)
         sd = W if di < 0 else E if di > 0 else S if dj < 0 else N
         kind, val = cfg["bc_kind"][sd], cfg["bc_value"][sd]
+        if bdat is not None:
+            val = bdat(sd, i, j, kind, val)
         if kind == 1:
             t = 2 * kc / d
             return {c: t}, -t * val, None
@@ -662,8 +672,27 @@ def _monolithic_mrcm(cfg, kap):
                             A[Ui(l, q), k] += s * flen * beta * v * phi[q]    # G_{l,q}
                         for q2 in range(npl):                                 # -|f| beta U_H phi_q
                             A[Ui(l, q), Ui(l, q2)] += -flen * beta * phi[q] * phi[q2]
+    if src is not None:
+        b[:nc] += hx * hy * src.ravel()
     x = spla.spsolve(A.tocsc(), b)
-    return x[:nc].reshape(ny, nx), x[nc:]
+
+    def out(i, j, di, dj):
+        coefs, const, _ = face_terms(i, j, di, dj)
+        return sum(v * x[k] for k, v in coefs.items()) + const
+
+    ux = np.zeros((ny, nx + 1))
+    uy = np.zeros((ny + 1, nx))
+    for j in range(ny):
+        ux[j, 0] = -out(0, j, -1, 0)
+        ux[j, nx] = out(nx - 1, j, 1, 0)
+        for i in range(1, nx):
+            ux[j, i] = 0.5 * (out(i - 1, j, 1, 0) - out(i, j, -1, 0))
+    for i in range(nx):
+        uy[0, i] = -out(i, 0, 0, -1)
+        uy[ny, i] = out(i, ny - 1, 0, 1)
+        for j in range(1, ny):
+            uy[j, i] = 0.5 * (out(i, j - 1, 0, 1) - out(i, j, 0, -1))
+    return x[:nc].reshape(ny, nx), x[nc:], ux, uy
 
 
 @pytest.mark.parametrize("degree", [0, 1])
@@ -688,6 +717,67 @@ def test_T19_brute_force_monolithic(shape, degree):
     assert _rel(p, p_ref) < 1e-11
     if len(y_ref):
         assert _rel(sol.y, y_ref) < 1e-10
+
+
+def _ratio_flux(cfg, kap_n, kap_m, ux, uy):
+    """(t^n / t^m) u on every face: harmonic transmissibilities inside, the adjacent cell's
+    conductivity ratio on the boundary (the discrete -kappa^n grad p of eq:mpm_tf_3)."""
+    ny, nx = kap_n.shape
+    hx, hy = cfg["lx"] / nx, cfg["ly"] / ny
+    tnx, tny = fine.interior_trans(kap_n, hx, hy)
+    tmx, tmy = fine.interior_trans(kap_m, hx, hy)
+    rx = np.concatenate([(kap_n / kap_m)[:, :1], tnx / tmx, (kap_n / kap_m)[:, -1:]], axis=1)
+    ry = np.concatenate([(kap_n / kap_m)[:1, :], tny / tmy, (kap_n / kap_m)[-1:, :]], axis=0)
+    return rx * ux, ry * uy, rx, ry
+
+
+def _outward(ux, uy, sd, i, j):
+    return (-ux[j, 0], ux[j, -1], -uy[0, i], uy[-1, i])[sd]
+
+
+@pytest.mark.parametrize("degree", [0, 1])
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("shape", [(8, 8, 4, 4, 2, 2), (12, 8, 4, 4, 1, 2), (9, 6, 3, 3, 1, 1),
+                                   (12, 12, 6, 4, 3, 2)])
+def test_T20_mpm_against_monolithic(shape, order, degree):
+    """MPM-2P on decompositions with elements longer than one face, against the perturbation
+    problems assembled monolithically (no basis functions): the zeroth order of eq:mpm_tf_3
+    (source -div v, Neumann data z - v.n, Dirichlet data 0, kappa^m) and, with the first-order
+    term, eq:mpm_tf_4 with l = 1 (source -div w, zero data); u-bar = u-hat_0 + v (+ u-hat_1 + w),
+    then the kappa^n downscaling."""
+    nx, ny, mx, my, nex, ney = shape
+    if degree == 1 and (mx // nex < 2 or my // ney < 2):
+        pytest.skip("a linear function needs at least two faces per element")
+    cfg, K = _problem(41 + nx + 7 * my, nx, ny, mx, my, nex, ney, sigma2=3.0, alpha=0.8, iface_degree=degree)
+    cfg["bc_kind"] = [2, 1, 0, 1]; cfg["bc_value"] = [-1.0, 0.0, 0.0, 0.3]
+    rng = np.random.default_rng(nx * ny + order)
+    s_m = rng.uniform(0.0, 0.6, K.shape)
+    s_n = np.clip(s_m + rng.uniform(0.0, 0.3, K.shape), 0.0, 1.0)
+    kap_m = physics.conductivity(s_m, K, 1.0, 10.0)
+    kap_n = physics.conductivity(s_n, K, 1.0, 10.0)
+    hx, hy = cfg["lx"] / nx, cfg["ly"] / ny
+    um_x, um_y, state, _ = mpm.mrcm_velocity(cfg, kap_m)
+    ux_o, uy_o, _ = mpm.mpm_velocity(cfg, state, kap_n, order=order)
+
+    def div(fx, fy):
+        return (hy * (fx[:, 1:] - fx[:, :-1]) + hx * (fy[1:, :] - fy[:-1, :])) / (hx * hy)
+
+    vx, vy, rx, ry = _ratio_flux(cfg, kap_n, kap_m, um_x, um_y)
+    bd0 = lambda sd, i, j, kind, val: 0.0 if kind == 1 else val - _outward(vx, vy, sd, i, j)
+    _, _, u0x, u0y = _monolithic(cfg, kap_m, src=-div(vx, vy), bdat=bd0)
+    ubx, uby = u0x + vx, u0y + vy
+    if order == 1:
+        wx, wy = (rx - 1.0) * u0x, (ry - 1.0) * u0y
+        for sd, sl in ((W, (slice(None), 0)), (E, (slice(None), -1))):
+            if cfg["bc_kind"][sd] != 1:
+                wx[sl] = 0.0
+        for sd, sl in ((S, (0, slice(None))), (N, (-1, slice(None)))):
+            if cfg["bc_kind"][sd] != 1:
+                wy[sl] = 0.0
+        _, _, u1x, u1y = _monolithic(cfg, kap_m, src=-div(wx, wy), bdat=lambda *a: 0.0)
+        ubx, uby = ubx + u1x + wx, uby + u1y + wy
+    ux_r, uy_r, _ = downscale(cfg, kap_n, ubx, uby)
+    assert _rel(ux_o, ux_r) < 1e-10 and _rel(uy_o, uy_r) < 1e-10
 
 
 # ---------------------------------------------------------------- Algorithm 1 logic
