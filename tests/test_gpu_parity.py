@@ -51,6 +51,7 @@ SHAPES = [
     (60, 30, 20, 10, 4, 2),     # 20 lines, 3 x 3 subdomains
     (48, 16, 24, 8, 4, 2),      # 24 lines of 8 cells
     (20, 40, 10, 20, 5, 4),     # lines along x, 20 of them
+    (64, 64, 16, 16, 16, 16),   # 128 interface unknowns per inner subdomain (the largest)
 ]
 
 
@@ -168,6 +169,7 @@ LINEAR_SHAPES = [
     (48, 8, 8, 8, 1, 4),        # one row of subdomains
     (60, 30, 20, 10, 4, 2),     # 20 lines, 3 x 3 subdomains
     (20, 40, 10, 20, 5, 4),     # lines along x, 20 of them
+    (64, 64, 16, 16, 8, 8),     # 128 interface unknowns per inner subdomain (the largest)
 ]
 
 
