@@ -158,11 +158,13 @@ mpm_status mpm_last_error(const mpm_run* run, char* buf, size_t len);
 
 /* Batch of runs stepped together: the batched and serving forms of the workloads (many
  * independent runs of Algorithm 1, Section 4.2, of any sizes). A batch holds `capacity` slots;
- * a slot takes a started run and can be emptied and refilled at any time (continuous batching).
+ * a slot takes a run (started, or with its fields set and started later by mpm_batch_start)
+ * and can be emptied and refilled at any time (continuous batching).
  * Runs with equal descriptors form groups (at most 128 runs per launch): each phase of a step
  * (transport, conductivity and epsilon, local solves, interface solve, reconstruction,
- * downscaling) is one kernel launch for the whole group, on streams the batch owns; a run in
- * a group whose switch takes the MRCM branch is updated on its own within the step. Other runs
+ * downscaling) is one kernel launch for the whole group, on streams the batch owns; the runs of
+ * a group whose switch takes the MRCM branch in the same step share that update's launches
+ * (one run alone: its own). Other runs
  * step alone on their own streams. The batch owns no device memory; the runs keep their
  * workspaces. While a run is attached, its work is ordered by the batch: work on its stream is
  * ordered before the batch's at attach time and after it at detach time (and around every
@@ -184,8 +186,8 @@ mpm_status mpm_batch_detach(mpm_batch* batch, int32_t slot);
 /* One pass of Algorithm 1's while loop (automatic switch) for every filled slot with
  * active[slot] != 0 (active NULL: all filled slots); MPM_ESTATE if one of them is not started.
  * Every run's work is issued before any wait; the runs of a group that take the MRCM branch in
- * the same pass share its launches. breakthrough (host, capacity entries, may be NULL) receives 1 for the stepped runs
- * whose water cut reached breakthrough_cut. Returns the first error met; a run that failed is
+ * the same pass share its launches. breakthrough (host, capacity entries, may be NULL)
+ * receives 1 for the stepped runs whose water cut reached breakthrough_cut. Returns the first error met; a run that failed is
  * poisoned, the others are stepped. */
 mpm_status mpm_batch_step(mpm_batch* batch, const uint8_t* active, uint8_t* breakthrough);
 /* Detaches every run and frees the batch and its streams (the runs stay the caller's). */
