@@ -48,7 +48,8 @@ def algorithmic_bytes(cfg: dict) -> dict:
     """Bytes each kernel class must move per launch at this workload (FP64 path).
 
     Cell fields are 8 B per cell, face fields 8 B per face. Per subdomain: the kept line-block
-    inverses (lines x 16^2 doubles, lines padded to 8 or 16 cells), the Robin-to-flux map
+    inverses (symmetric, so lines x 16 (16 + 1) / 2 doubles of their upper triangles, lines
+    padded to 8 or 16 cells), the Robin-to-flux map
     nb^2 doubles, boundary vectors nb doubles (nb = 2 (mx + my)).
     """
     nx, ny, mx, my = cfg["nx"], cfg["ny"], cfg["sub_x"], cfg["sub_y"]
@@ -57,7 +58,7 @@ def algorithmic_bytes(cfg: dict) -> dict:
     nsub = (nx // mx) * (ny // my)
     band = min(mx, my)
     mf = 8 if band <= 8 else 16
-    blocks = 8.0 * nsub * (mx * my // band) * mf * mf
+    blocks = 8.0 * nsub * (mx * my // band) * (mf * (mf + 1) // 2)
     nb = 2 * (mx + my)
     ndof = 4 * (cfg["ne_x"] + cfg["ne_y"])
     return {

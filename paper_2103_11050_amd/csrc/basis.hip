@@ -149,10 +149,11 @@ k_basis_mfma(Geo g, const double* __restrict__ kap, const double* __restrict__ q
 #pragma unroll
     for (int t = 0; t < 4; ++t) prev[t] = cur[t];
     if (store_fac) {
-      // entry t of lane (row, cg) is D^-1[row][cg + 4t]: contiguous group t, entry cg
-      double* E = fac + (size_t(sub) * nl + ln) * 4 * 64;
+      // entry t of lane (row, cg) is D^-1[row][cg + 4t]; the upper triangle, packed
+      double* E = fac + (size_t(sub) * nl + ln) * LBP<16>::P;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) E[L.cg * 64 + L.row * 4 + t] = cur[t];
+      for (int t = 0; t < 4; ++t)
+        if (L.row <= L.col(t)) E[lb_pk<16>(L.row, L.col(t))] = cur[t];
     }
     // A operand of D^-1 for chunk kc: D^-1[cc][gq + 4 kc], entry kc of lane (row cc, cg gq)
     double Da[4];

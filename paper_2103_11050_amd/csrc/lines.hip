@@ -24,20 +24,30 @@ __device__ __forceinline__ void load_tile2(const Geo& g, int I, int J, const dou
   }
 }
 
-// factor offsets: E[sub][line][t][lane]
+// factor offsets: E[sub][line][packed upper triangle]
 template <int MF>
-__device__ __forceinline__ size_t efac_off(const Geo& g, int sub, int ln, int t) {
-  constexpr int EPL = LB<MF>::EPL;
+__device__ __forceinline__ size_t efac_off(const Geo& g, int sub) {
   const int nl = g.nc / g.band;
-  return ((size_t(sub) * nl + ln) * EPL + t) * 64;
+  return size_t(sub) * nl * LBP<MF>::P;
 }
 
-// Block elimination over all lines; the inverses D_ln^-1 go to Es[(ln*EPL + t)*64 + lane]
-// (LDS or global).
+// Packed position of entry t of this lane's row (the same for every line).
+template <int MF>
+__device__ __forceinline__ void lb_pk_lane(const LB<MF>& L, int (&pk)[LB<MF>::EPL]) {
+#pragma unroll
+  for (int t = 0; t < LB<MF>::EPL; ++t) pk[t] = lb_pk<MF>(L.row, L.col(t));
+}
+
+// Block elimination over all lines; the upper triangles of the inverses D_ln^-1 go to
+// Es[ln * P + packed position] (global; a reader in the same kernel needs a barrier first, as
+// the entries of a row below the diagonal were written by other lanes).
 template <int MF, typename T>
 __device__ __forceinline__ void lb_factor(const Geo& g, const LineW& W, const LB<MF>& L, T* Es, bool& ok) {
   constexpr int EPL = LB<MF>::EPL;
   const int nl = g.nc / g.band;
+  constexpr int P = LBP<MF>::P;
+  int pk[EPL];
+  lb_pk_lane<MF>(L, pk);
   double prev[EPL], cur[EPL];
 #pragma unroll
   for (int t = 0; t < EPL; ++t) prev[t] = 0.0;
@@ -47,7 +57,7 @@ __device__ __forceinline__ void lb_factor(const Geo& g, const LineW& W, const LB
     lb_inverse<MF>(L, cur, ok);
 #pragma unroll
     for (int t = 0; t < EPL; ++t) {
-      Es[(size_t(ln) * EPL + t) * 64 + L.lane] = T(cur[t]);
+      if (L.row <= L.col(t)) Es[size_t(ln) * P + pk[t]] = T(cur[t]);
       prev[t] = cur[t];
     }
   }
@@ -64,16 +74,19 @@ __device__ __forceinline__ void lb_solve(const Geo& g, const LineW& W, const LB<
   const bool rin = L.row < len;
   const bool wr = rin && L.cg == 0;
   const int xr = rin ? L.row : 0;
+  constexpr int P = LBP<MF>::P;
+  int pk[EPL];
+  lb_pk_lane<MF>(L, pk);
   // the next line's block is loaded while the current one is applied
   double e[EPL], en[EPL];
 #pragma unroll
-  for (int t = 0; t < EPL; ++t) e[t] = Es[size_t(t) * 64 + L.lane];
+  for (int t = 0; t < EPL; ++t) e[t] = Es[pk[t]];
   double wprev = 0.0;
 #pragma unroll 1
   for (int ln = 0; ln < nl; ++ln) {
     const int lnn = ln + 1 < nl ? ln + 1 : ln;
 #pragma unroll
-    for (int t = 0; t < EPL; ++t) en[t] = Es[(size_t(lnn) * EPL + t) * 64 + L.lane];
+    for (int t = 0; t < EPL; ++t) en[t] = Es[size_t(lnn) * P + pk[t]];
     double z = rin ? x[ln * len + xr] : 0.0;
     if (ln > 0 && rin) z += W.y(ln - 1, xr) * wprev;
     wprev = lb_matvec<MF>(L, e, z);
@@ -84,13 +97,13 @@ __device__ __forceinline__ void lb_solve(const Geo& g, const LineW& W, const LB<
   double xnext = wprev;   // line nl - 1 holds its solution already
   if (nl >= 2) {
 #pragma unroll
-    for (int t = 0; t < EPL; ++t) e[t] = Es[(size_t(nl - 2) * EPL + t) * 64 + L.lane];
+    for (int t = 0; t < EPL; ++t) e[t] = Es[size_t(nl - 2) * P + pk[t]];
   }
 #pragma unroll 1
   for (int ln = nl - 2; ln >= 0; --ln) {
     const int lnn = ln > 0 ? ln - 1 : 0;
 #pragma unroll
-    for (int t = 0; t < EPL; ++t) en[t] = Es[(size_t(lnn) * EPL + t) * 64 + L.lane];
+    for (int t = 0; t < EPL; ++t) en[t] = Es[size_t(lnn) * P + pk[t]];
     const double v = rin ? W.y(ln, xr) * xnext : 0.0;
     xnext = (rin ? x[ln * len + xr] : 0.0) + lb_matvec<MF>(L, e, v);
     if (wr) x[ln * len + xr] = xnext;
@@ -105,11 +118,13 @@ __device__ __forceinline__ void lb_solve(const Geo& g, const LineW& W, const LB<
 // once.
 template <int MF, int NL>
 __device__ __forceinline__ void lb_load_reg(const LB<MF>& L, const double* Es, double (&E)[NL][LB<MF>::EPL]) {
-  constexpr int EPL = LB<MF>::EPL;
+  constexpr int EPL = LB<MF>::EPL, P = LBP<MF>::P;
+  int pk[EPL];
+  lb_pk_lane<MF>(L, pk);
 #pragma unroll
   for (int ln = 0; ln < NL; ++ln)
 #pragma unroll
-    for (int t = 0; t < EPL; ++t) E[ln][t] = Es[(size_t(ln) * EPL + t) * 64 + L.lane];
+    for (int t = 0; t < EPL; ++t) E[ln][t] = Es[size_t(ln) * P + pk[t]];
 }
 
 // The two sweeps with the blocks already in registers.
@@ -154,11 +169,13 @@ __device__ __forceinline__ float lb_matvec_f(const LB<MF>& L, const float (&a)[L
 // Up to 16 lines of FP32 blocks into registers (nl lines at run time).
 template <int MF>
 __device__ __forceinline__ void lb_load_f32(const LB<MF>& L, const float* Es, int nl, float (&E)[16][LB<MF>::EPL]) {
-  constexpr int EPL = LB<MF>::EPL;
+  constexpr int EPL = LB<MF>::EPL, P = LBP<MF>::P;
+  int pk[EPL];
+  lb_pk_lane<MF>(L, pk);
 #pragma unroll
   for (int ln = 0; ln < 16; ++ln)
 #pragma unroll
-    for (int t = 0; t < EPL; ++t) E[ln][t] = ln < nl ? Es[(size_t(ln) * EPL + t) * 64 + L.lane] : 0.0f;
+    for (int t = 0; t < EPL; ++t) E[ln][t] = ln < nl ? Es[size_t(ln) * P + pk[t]] : 0.0f;
 }
 
 // d = M^-1 r with the FP32 blocks (both sweeps in FP32); r and d in LDS, local order, FP64.
@@ -270,7 +287,7 @@ __global__ void __launch_bounds__(64) k_line_factor(Geo g, const double* __restr
   fill_trans(g, I, J, kl, 0, tE, tN, dg);
   const LineW W{tE, tN, dg, g.xfast, g.band, 0};
   bool ok = true;
-  lb_factor<MF>(g, W, L, fac + efac_off<MF>(g, sub, 0, 0), ok);
+  lb_factor<MF>(g, W, L, fac + efac_off<MF>(g, sub), ok);
   if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
 }
 
@@ -307,9 +324,9 @@ __global__ void __launch_bounds__(64) k_basis_lines(Geo g, const double* __restr
   fill_trans(g, I, J, kl, 0, tE, tN, dg);
   const LineW W{tE, tN, dg, g.xfast, g.band, 0};
   LB<MF> L;
-  double* Es = fac + efac_off<MF>(g, sub, 0, 0);
+  double* Es = fac + efac_off<MF>(g, sub);
   bool ok = true;
-  lb_factor<MF>(g, W, L, Es, ok);   // each lane reads back only the entries it wrote
+  lb_factor<MF>(g, W, L, Es, ok);   // read back by lb_solve after the barrier below
   if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
   if (threadIdx.x < nb) {
     const BFace f = bface(g, I, J, threadIdx.x);
@@ -546,7 +563,7 @@ k_mpm_local_lb(Geo g0, const double* __restrict__ kap_n, const double* __restric
   constexpr int NLR = NL > 0 ? NL : 1;
   double E[F32 ? 1 : NLR][LB<MF>::EPL];
   float Ef[F32 ? 16 : 1][LB<MF>::EPL];
-  const T* Es = fac + efac_off<MF>(g, sub, 0, 0);
+  const T* Es = fac + efac_off<MF>(g, sub);
   if constexpr (F32) lb_load_f32<MF>(L, Es, g.nc / g.band, Ef);
   else if constexpr (NL > 0) lb_load_reg<MF, NL>(L, Es, E);
   double qc[4];
@@ -656,7 +673,7 @@ k_mpm_first(Geo g0, const double* __restrict__ kap_n, const double* __restrict__
   LB<MF> L;
   constexpr int NLR = NL > 0 ? NL : 1;
   double E[NLR][LB<MF>::EPL];
-  const double* Es = fac + efac_off<MF>(g, sub, 0, 0);
+  const double* Es = fac + efac_off<MF>(g, sub);
   if constexpr (NL > 0) lb_load_reg<MF, NL>(L, Es, E);
   double qc[4];
   load_halo_tiles(g, I, J, kap_n, kap_m, uxm, uym, q, knt, kmt, uxs, uys, qc);
@@ -815,7 +832,7 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int n = g.nc, nb = g.nb;
   LB<MF> L;
-  const size_t eoff = efac_off<MF>(g, sub, 0, 0);
+  const size_t eoff = efac_off<MF>(g, sub);
   T* Es = (!store && flag[sub]) ? Escr + eoff : Ekeep + eoff;
   constexpr int NLR = NL > 0 ? NL : 1;
   double E[F32 ? 1 : NLR][LB<MF>::EPL];
@@ -870,6 +887,7 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
       bool ok = true;
       lb_factor<MF>(g, W, L, Es, ok);
       if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
+      __syncthreads();   // the lower-triangle entries come from other lanes' stores
       if constexpr (NL > 0) lb_load_reg<MF, NL>(L, Es, E);
     }
     if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
@@ -945,7 +963,7 @@ k_ds_factor(Geo g, const double* __restrict__ kap_n, T* __restrict__ Escr, const
     fill_trans(g, I, J, kl, 1, tE, tN, dg);
     const LineW W{tE, tN, dg, g.xfast, g.band, 1};
     bool ok = true;
-    lb_factor<MF>(g, W, L, Escr + efac_off<MF>(g, sub, 0, 0), ok);
+    lb_factor<MF>(g, W, L, Escr + efac_off<MF>(g, sub), ok);
     if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
     __syncthreads();
   }
@@ -1062,7 +1080,7 @@ void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const d
 
 size_t line_factor_doubles(int nsub, int nc, int band) {
   const int mf = band <= 8 ? 8 : 16;
-  return size_t(nsub) * (nc / band) * mf * mf;
+  return size_t(nsub) * (nc / band) * (mf * (mf + 1) / 2);
 }
 
 }  // namespace mpm

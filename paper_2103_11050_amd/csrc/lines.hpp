@@ -37,6 +37,18 @@ struct LB {
   __device__ int col(int t) const { return IL ? cg + LPR * t : cg * EPL + t; }
 };
 
+// Kept line-block inverses are symmetric: each MF x MF block is stored as its upper triangle,
+// row by row (MF (MF + 1) / 2 entries); entry (row, col) of the block sits at lb_pk(min, max).
+template <int MF>
+struct LBP {
+  static constexpr int P = MF * (MF + 1) / 2;
+};
+template <int MF>
+__device__ __forceinline__ int lb_pk(int row, int col) {
+  const int r = row < col ? row : col, c = row < col ? col : row;
+  return r * MF - (r * (r - 1)) / 2 + (c - r);
+}
+
 // In-place inverse of the SPD block held as a[t] = D[row][col(t)]. Clears ok on a
 // non-positive pivot. The pivot loop runs in groups of EPL so that the register holding
 // column k is known at compile time.

@@ -245,7 +245,7 @@ void build_plan(const mpm_desc& d, Plan* p) {
   P.off_uym = take(nfy * 8);
   {
     const int mf = P.band <= 8 ? 8 : 16;
-    P.off_fac = take(size_t(P.nsub) * (P.nc / P.band) * mf * mf * 8);
+    P.off_fac = take(size_t(P.nsub) * (P.nc / P.band) * (mf * (mf + 1) / 2) * 8);
   }
   P.off_dinv = take(size_t(P.nsub) * P.nc * 8);
   P.off_S = take(size_t(P.nsub) * P.nb * P.nb * 8);
@@ -253,10 +253,10 @@ void build_plan(const mpm_desc& d, Plan* p) {
   P.off_vbnd = take(size_t(P.nsub) * P.nb * 8);
   {
     const int mf = P.band <= 8 ? 8 : 16;
-    P.off_dsE = take(size_t(P.nsub) * (P.nc / P.band) * mf * mf * 8);
-    P.off_nfac = take(size_t(P.nsub) * (P.nc / P.band) * mf * mf * 8);
+    P.off_dsE = take(size_t(P.nsub) * (P.nc / P.band) * (mf * (mf + 1) / 2) * 8);
+    P.off_nfac = take(size_t(P.nsub) * (P.nc / P.band) * (mf * (mf + 1) / 2) * 8);
     // precision form: FP32 copies of the three block sets
-    P.n_blocks = size_t(P.nsub) * (P.nc / P.band) * mf * mf;
+    P.n_blocks = size_t(P.nsub) * (P.nc / P.band) * (mf * (mf + 1) / 2);   // packed upper triangles
     const bool f32 = d.precision == MPM_PREC_FP32_REFINE;
     P.off_fac32 = take(f32 ? P.n_blocks * 4 : 0);
     P.off_nfac32 = take(f32 ? P.n_blocks * 4 : 0);
