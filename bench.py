@@ -49,8 +49,8 @@ def algorithmic_bytes(cfg: dict) -> dict:
 
     Cell fields are 8 B per cell, face fields 8 B per face. Per subdomain: the kept line-block
     inverses (symmetric, so lines x 16 (16 + 1) / 2 doubles of their upper triangles, lines
-    padded to 8 or 16 cells), the Robin-to-flux map
-    nb^2 doubles, boundary vectors nb doubles (nb = 2 (mx + my)).
+    padded to 8 or 16 cells), the symmetric Robin-to-flux map ((nb / 2 + 1) nb doubles of its
+    wrapped diagonals), boundary vectors nb doubles (nb = 2 (mx + my)).
     """
     nx, ny, mx, my = cfg["nx"], cfg["ny"], cfg["sub_x"], cfg["sub_y"]
     nc = nx * ny
@@ -68,8 +68,8 @@ def algorithmic_bytes(cfg: dict) -> dict:
         "sat_step": 8.0 * nc + 8.0 * nfaces + 8.0 * nc,
         # kept blocks; kappa^n, kappa^m, q; u~^m; h and v written; interface rhs written
         "mpm_local": blocks + 24.0 * nc + 8.0 * nfaces + 16.0 * nsub * nb + 8.0 * nsub * ndof,
-        # Robin-to-flux map, h, v read; boundary fluxes written
-        "flux": 8.0 * nsub * nb * nb + 24.0 * nsub * nb,
+        # Robin-to-flux map (symmetric: nb / 2 + 1 wrapped diagonals), h, v read; fluxes written
+        "flux": 8.0 * nsub * (nb // 2 + 1) * nb + 24.0 * nsub * nb,
         # kept blocks; kappa, q; boundary fluxes (own + neighbour); velocity written
         "downscale": blocks + 16.0 * nc + 16.0 * nsub * nb + 8.0 * nfaces,
     }

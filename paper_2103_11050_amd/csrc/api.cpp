@@ -659,7 +659,7 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
     const size_t fx = size_t(P.ny) * (P.nx + 1) * 8, fy = size_t(P.ny + 1) * P.nx * 8;
     const bool ok = in(r->K, cb) && in(r->q, cb) && in(r->s, cb) && in(r->s2, cb) && in(r->kn, cb) &&
                     in(r->km, cb) && in(r->ux, fx) && in(r->uy, fy) && in(r->uxm, fx) && in(r->uym, fy) &&
-                    in(r->S, ns * P.nb * P.nb * 8) && in(r->h, ns * P.nb * 8) && in(r->vbnd, ns * P.nb * 8) &&
+                    in(r->S, ns * ((P.nb / 2 + 1) * P.nb) * 8) && in(r->h, ns * P.nb * 8) && in(r->vbnd, ns * P.nb * 8) &&
                     in(r->ubnd, ns * P.nb * 8) && in(r->leafK, ns * P.ndmax * P.ndmax * 8) &&
                     in(r->red, P.n_red * 8) && in(r->scal, SC_COUNT * 8) &&
                     in(r->err, 12) && in(r->dscount, 8) && in(r->dsflag, ns * 4) && in(r->dslist, ns * 4) &&

@@ -206,8 +206,8 @@ k_basis_mfma(Geo g, const double* __restrict__ kap, const double* __restrict__ q
   }
   if (!ok && lane == 0) set_error(err, ERR_NOTSPD);
 
-  // S = W T - W T G W T, both triangles
-  double* Ss = Sg + size_t(sub) * nb * nb;
+  // S = W T - W T G W T, each stored entry once (wrapped diagonals)
+  double* Ss = Sg + size_t(sub) * smap_doubles(nb);
   auto put = [&](const dbl4& t, int a, int b) {
     int lb_, pb_;
     const int fc = block_face(g, b, cc, nl, len, &lb_, &pb_);
@@ -217,8 +217,8 @@ k_basis_mfma(Geo g, const double* __restrict__ kap, const double* __restrict__ q
       const int fr = block_face(g, a, gq + 4 * v, nl, len, &la, &pa);
       if (fr >= 0 && fc >= 0) {
         const double val = (fr == fc ? wsh[fr] : 0.0) - wsh[fr] * t[v] * wsh[fc];
-        Ss[fr * nb + fc] = val;
-        if (a != b) Ss[fc * nb + fr] = val;
+        if (smap_owner(nb, fr, fc)) Ss[smap_at(nb, fr, fc)] = val;
+        if (a != b && smap_owner(nb, fc, fr)) Ss[smap_at(nb, fc, fr)] = val;
       }
     }
   };

@@ -56,6 +56,21 @@ __host__ __device__ __forceinline__ void loc_ij(const Geo& g, int c, int* i, int
   *j = g.xfast ? b : a;
 }
 
+// ---------------------------------------------------------------- Robin-to-flux maps
+// The nb x nb map S_i of a subdomain is symmetric and is kept by wrapped diagonals: entry
+// (i, j) with d = (j - i) mod nb <= nb / 2 sits at [d][i]; every other entry is read from its
+// mirror (j, i). nb / 2 + 1 rows of nb doubles; each row is read coalesced by the lanes.
+__host__ __device__ __forceinline__ int smap_doubles(int nb) { return (nb / 2 + 1) * nb; }
+// Whether (i, j) is the stored orientation (for d = nb / 2 both orientations are stored).
+__device__ __forceinline__ bool smap_owner(int nb, int i, int j) {
+  const int d = j >= i ? j - i : j - i + nb;
+  return 2 * d <= nb;
+}
+__device__ __forceinline__ int smap_at(int nb, int i, int j) {
+  const int d = j >= i ? j - i : j - i + nb;
+  return 2 * d <= nb ? d * nb + i : (nb - d) * nb + j;
+}
+
 // ---------------------------------------------------------------- boundary faces
 // Boundary faces of a subdomain: W faces j=0..my-1, E faces, S faces i=0..mx-1, N faces.
 struct BFace {

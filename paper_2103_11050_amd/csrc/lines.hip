@@ -347,7 +347,7 @@ __global__ void __launch_bounds__(64) k_basis_lines(Geo g, const double* __restr
     hsh[f] = h;
     hg[size_t(sub) * nb + f] = h;
   }
-  double* Ss = Sg + size_t(sub) * nb * nb;
+  double* Ss = Sg + size_t(sub) * smap_doubles(nb);
 #pragma unroll 1
   for (int f = 0; f < nb; ++f) {
     __syncthreads();
@@ -359,7 +359,8 @@ __global__ void __launch_bounds__(64) k_basis_lines(Geo g, const double* __restr
     if (threadIdx.x < nb) {
       const int fr = threadIdx.x;
       const BFace br = bface(g, I, J, fr);
-      Ss[fr * nb + f] = (fr == f ? wsh[f] : 0.0) - wsh[fr] * x[loc_index(g, br.i, br.j)] * wsh[f];
+      if (smap_owner(nb, fr, f))
+        Ss[smap_at(nb, fr, f)] = (fr == f ? wsh[f] : 0.0) - wsh[fr] * x[loc_index(g, br.i, br.j)] * wsh[f];
     }
   }
   __syncthreads();

@@ -276,7 +276,7 @@ __device__ __forceinline__ void basis_iface_block(const Geo& g, int I, int J, in
       double sacc = 0.0;
       for (int y = fb; y < fb + nbb; ++y) {
         const BFace fgb = bface(g, I, J, y);
-        sacc += Ss[x * nb + y] * bweight(g, fgb, c2, kl[loc_index(g, fgb.i, fgb.j)]);
+        sacc += Ss[smap_at(nb, x, y)] * bweight(g, fgb, c2, kl[loc_index(g, fgb.i, fgb.j)]);
       }
       v += wa * sacc;
     }

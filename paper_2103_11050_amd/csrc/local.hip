@@ -157,8 +157,17 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int nb = g.nb;
   const int f = threadIdx.x;
+  // the rows of S do not depend on the interface solution: their loads go out first
+  const bool act = f < nb;
+  const int D = nb / 2;
+  const double* Ss = Sg + size_t(sub) * smap_doubles(nb);
+  double sv[33];
+#pragma unroll
+  for (int d = 0; d < 33; ++d) sv[d] = act && d <= D ? Ss[d * nb + f] : 0.0;
+  double acc = act ? hg[size_t(sub) * nb + f] : 0.0;
+  const double vb = act && with_v ? vbnd[size_t(sub) * nb + f] : 0.0;
   BFace bf;
-  if (f < nb) {
+  if (act) {
     bf = bface(g, I, J, f);
     double rv = 0.0;
     if (bf.kind == FACE_ROB) {
@@ -168,18 +177,32 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
     r[f] = rv;
   }
   __syncthreads();
-  if (f < nb) {
+  // S_i r, row f of S from its wrapped diagonals: S(f, f + d) = D[d][f] for d <= nb / 2, and
+  // S(f, f - e) = D[e][f - e] for the other columns (indices mod nb). Each lane loads its
+  // entry of every diagonal row (coalesced, all loads issued together, above); D[e][f - e]
+  // come from lane f - e through a cross-lane read. Every lane takes part in those reads, so
+  // they are made before the lanes branch on the face kind.
+#pragma unroll
+  for (int d = 0; d < 33; ++d) {
+    if (d <= D) {
+      const int t = f + d < nb ? f + d : f + d - nb;
+      acc -= sv[d] * r[act ? t : 0];
+    }
+  }
+#pragma unroll
+  for (int e = 1; e < 32; ++e) {
+    if (e < nb - D) {
+      const int t = f >= e ? f - e : f - e + nb;
+      const double v = __shfl(sv[e], act ? t : 0);
+      acc -= v * r[act ? t : 0];
+    }
+  }
+  if (act) {
     double u;
     if (bf.kind == FACE_NEU) {
       u = bf.value;
     } else {
-      // S is symmetric: column f is read, coalesced over the lanes
-      const double* Ss = Sg + size_t(sub) * nb * nb + f;
-      double acc = hg[size_t(sub) * nb + f];
-#pragma unroll 16
-      for (int t = 0; t < nb; ++t) acc -= Ss[size_t(t) * nb] * r[t];
-      u = acc / bf.flen;
-      if (with_v) u += vbnd[size_t(sub) * nb + f];
+      u = acc / bf.flen + vb;
     }
     if (with_v == 2) {
       if (bf.kind != FACE_NEU) ubnd[size_t(sub) * nb + f] += u;

@@ -248,7 +248,7 @@ void build_plan(const mpm_desc& d, Plan* p) {
     P.off_fac = take(size_t(P.nsub) * (P.nc / P.band) * (mf * (mf + 1) / 2) * 8);
   }
   P.off_dinv = take(size_t(P.nsub) * P.nc * 8);
-  P.off_S = take(size_t(P.nsub) * P.nb * P.nb * 8);
+  P.off_S = take(size_t(P.nsub) * ((P.nb / 2 + 1) * P.nb) * 8);   // wrapped diagonals of the symmetric maps
   P.off_h = take(size_t(P.nsub) * P.nb * 8);
   P.off_vbnd = take(size_t(P.nsub) * P.nb * 8);
   {
