@@ -194,12 +194,13 @@ double eps_from(const mpm_run* r, double num, double den) {
 }
 
 // kappa^n = lambda(s) K and the sums of epsilon against kappa^m, also written by the reduction
-// kernel into pinned host memory (the caller records ev_eps after it).
-mpm_status kappa_and_eps_nodes(mpm_run* r) {
+// kernel into pinned host memory (the caller records ev_eps after it). With wc the reduction
+// also computes the water cut of s under the current velocity (after a transport).
+mpm_status kappa_and_eps_nodes(mpm_run* r, bool wc = false) {
   {
     Scope sc(r, "kappa_eps");
     launch_kappa(r->st, r->g, r->s, r->K, r->kn, r->km, r->red, r->scal, r->dsflag, r->dslist, r->dscount,
-                 r->dscount + 1, r->pinned_dev);
+                 r->dscount + 1, r->pinned_dev, wc ? r->ux : nullptr, wc ? r->uy : nullptr);
   }
   r->eps_seq += 1;
   return MPM_OK;
@@ -221,8 +222,8 @@ mpm_status wait_eps(mpm_run* r) {
   return MPM_OK;
 }
 
-mpm_status kappa_and_eps(mpm_run* r) {
-  mpm_status st = kappa_and_eps_nodes(r);
+mpm_status kappa_and_eps(mpm_run* r, bool wc = false) {
+  mpm_status st = kappa_and_eps_nodes(r, wc);
   if (st) return st;
   HIPCHK(r, hipEventRecord(r->ev_eps, r->st));
   return MPM_OK;
@@ -484,27 +485,29 @@ mpm_status velocity_update(mpm_run* r, int32_t force, bool kappa_done = false) {
   return vu_finish(r);
 }
 
-mpm_status transport_body(mpm_run* r, int32_t nsteps) {
+// Transport sub-steps; the water cut here unless the conductivity reduction that follows
+// computes it (wc = false).
+mpm_status transport_body(mpm_run* r, int32_t nsteps, bool wc = true) {
   for (int k = 0; k < nsteps; ++k) {
     Scope sc(r, "sat_step");
     launch_sat_step(r->st, r->g, r->s, r->s2, r->ux, r->uy, r->scal, r->area);
     std::swap(r->s, r->s2);
   }
-  {
+  if (wc) {
     Scope sc(r, "water_cut");
     launch_water_cut(r->st, r->g, r->s, r->ux, r->uy, r->scal, r->red + 2 * r->P.nsub, r->wc_ticket);
   }
   return MPM_OK;
 }
 
-mpm_status transport(mpm_run* r, int32_t nsteps) {
-  mpm_status st = transport_body(r, nsteps);
+mpm_status transport(mpm_run* r, int32_t nsteps, bool wc = true) {
+  mpm_status st = transport_body(r, nsteps, wc);
   r->ntr += nsteps;
   return st;
 }
 
-// C_n transport sub-steps and kappa^n with its epsilon sums (event ev_eps recorded after them).
-// With graphs they are one graph per parity of the saturation buffers.
+// C_n transport sub-steps and kappa^n with its epsilon sums and the water cut (event ev_eps
+// recorded after them). With graphs they are one graph per parity of the saturation buffers.
 mpm_status transport_and_kappa(mpm_run* r) {
   const int cn = r->P.d.cn;
   if (r->use_graphs && !r->prof) {
@@ -520,9 +523,9 @@ mpm_status transport_and_kappa(mpm_run* r) {
     double* s0 = r->s;
     double* s1 = r->s2;
     r->g_trans[par] = capture_and_launch(r, [&] {
-      mpm_status st = transport_body(r, cn);
+      mpm_status st = transport_body(r, cn, false);
       if (st) return st;
-      return kappa_and_eps_nodes(r);
+      return kappa_and_eps_nodes(r, true);
     });
     if (r->g_trans[par]) {
       r->ntr += cn;
@@ -534,9 +537,9 @@ mpm_status transport_and_kappa(mpm_run* r) {
     r->s2 = s1;
     r->use_graphs = false;
   }
-  mpm_status st = transport(r, cn);
+  mpm_status st = transport(r, cn, false);
   if (st) return st;
-  return kappa_and_eps(r);
+  return kappa_and_eps(r, true);
 }
 
 // One pass of Algorithm 1's while loop.
@@ -951,14 +954,13 @@ mpm_status group_issue(std::vector<mpm_run*>& g, GroupStreams& gs, std::vector<m
     if (e) return e;
   }
   const int cn = L->P.d.cn;
-  // transport sub-steps, water cut, conductivity and epsilon sums of every run
+  // transport sub-steps, conductivity, epsilon sums and water cut of every run
   for (int k = 0; k < cn; ++k) {
     launch_sat_step(gs.st, L->g, L->s, L->s2, L->ux, L->uy, L->scal, L->area, rt);
     for (mpm_run* r : g) std::swap(r->s, r->s2);
   }
-  launch_water_cut(gs.st, L->g, L->s, L->ux, L->uy, L->scal, L->red + 2 * L->P.nsub, L->wc_ticket, rt);
   launch_kappa(gs.st, L->g, L->s, L->K, L->kn, L->km, L->red, L->scal, L->dsflag, L->dslist, L->dscount,
-               L->dscount + 1, L->pinned_dev, rt);
+               L->dscount + 1, L->pinned_dev, L->ux, L->uy, rt);
   for (mpm_run* r : g) {
     r->eps_seq += 1;
     r->ntr += cn;
@@ -1178,7 +1180,7 @@ mpm_status mpm_batch_start(mpm_batch* b) {
       if (!st) st = group_tab(g, 0, s, &rt);
       if (!st) {
         launch_kappa(s, L->g, L->s, L->K, L->kn, L->km, L->red, L->scal, L->dsflag, L->dslist, L->dscount,
-                     L->dscount + 1, L->pinned_dev, rt);
+                     L->dscount + 1, L->pinned_dev, nullptr, nullptr, rt);
         for (mpm_run* r : g) {
           r->eps_seq += 1;
           r->te = 0; r->tm = 0; r->ntr = 0;

@@ -71,6 +71,31 @@ __device__ __forceinline__ int smap_at(int nb, int i, int j) {
   return 2 * d <= nb ? d * nb + i : (nb - d) * nb + j;
 }
 
+// ---------------------------------------------------------------- fractional flow, water cut
+// Water fractional flow f_w(s) = M s^2 / (M s^2 + (1 - s)^2), M = mu_o / mu_w (eq. BL2D).
+__device__ __forceinline__ double frac_w(double s, double M) {
+  const double a = M * s * s;
+  const double o = 1.0 - s;
+  return a / (a + o * o);
+}
+// Boundary face e of the domain for the water cut, 0 <= e < 2 (nx + ny): W faces j = 0..ny-1,
+// then E faces, S faces i = 0..nx-1, N faces. Its normal velocity index in ux or uy, the cell
+// behind it, whether it is an x-face and whether the outward normal is +x / +y.
+struct DomFace {
+  int ui, si;
+  bool vert, hi;
+};
+__device__ __forceinline__ DomFace dom_face(const Geo& g, int e) {
+  const int nW = g.ny, nS = g.nx;
+  DomFace d;
+  d.vert = e < 2 * nW;
+  const int k = d.vert ? (e < nW ? e : e - nW) : (e < 2 * nW + nS ? e - 2 * nW : e - 2 * nW - nS);
+  d.hi = d.vert ? e >= nW : e >= 2 * nW + nS;
+  d.ui = d.vert ? k * (g.nx + 1) + (d.hi ? g.nx : 0) : (d.hi ? g.ny * g.nx : 0) + k;
+  d.si = d.vert ? k * g.nx + (d.hi ? g.nx - 1 : 0) : (d.hi ? (g.ny - 1) * g.nx : 0) + k;
+  return d;
+}
+
 // ---------------------------------------------------------------- boundary faces
 // Boundary faces of a subdomain: W faces j=0..my-1, E faces, S faces i=0..mx-1, N faces.
 struct BFace {

@@ -12,12 +12,20 @@ namespace mpm {
 // One workgroup per subdomain tile: kappa^n = lambda(s) K, the tile's partial sums of
 // (kappa^n - kappa^m)^2 and (kappa^m)^2, and whether any conductivity of the tile changed
 // since the last MRCM update (flag, and the subdomain appended to the list of changed ones).
+// With ux non-null, also the tile's partial sums of the water cut (outflow |f| u.n and
+// |f| u.n f_w(s) over the domain's boundary faces in the tile) at red[2 nsub + 2 sub].
 __global__ void __launch_bounds__(256)
 k_kappa(Geo g, const double* __restrict__ s, const double* __restrict__ K, double* __restrict__ kap_n,
         const double* __restrict__ kap_m, double* __restrict__ red, int32_t* __restrict__ flag,
-        int32_t* __restrict__ list, int32_t* __restrict__ count, const double* __restrict__ scal, const RunTab* __restrict__ rt) {
-  __shared__ double sa[256], sb[256];
+        int32_t* __restrict__ list, int32_t* __restrict__ count, const double* __restrict__ scal,
+        const double* __restrict__ ux, const double* __restrict__ uy, const RunTab* __restrict__ rt) {
+  __shared__ double sa[256], sb[256], sq[256], sw[256];
   const int64_t wo = ws_off(rt);
+  const bool wc = ux != nullptr;
+  if (wc) {
+    ux = at_off(ux, wo);
+    uy = at_off(uy, wo);
+  }
   s = at_off(s, wo);
   K = at_off(K, wo);
   kap_n = at_off(kap_n, wo);
@@ -33,9 +41,22 @@ k_kappa(Geo g, const double* __restrict__ s, const double* __restrict__ K, doubl
   const int c = threadIdx.x;
   double a = 0.0, bb = 0.0;
   int diff = 0;
+  // block-uniform: the tile touches the domain boundary
+  const bool edge = wc && (I == 0 || J == 0 || I == g.Sx - 1 || J == g.Sy - 1);
+  double wq = 0.0, ww = 0.0;
   if (c < g.nc) {
     const int gc = (J * g.my + c / g.mx) * g.nx + I * g.mx + c % g.mx;
     const double sv = s[gc];
+    if (edge) {
+      const int gi = I * g.mx + c % g.mx, gj = J * g.my + c / g.mx;
+      double out = 0.0;
+      if (gi == 0) out += g.hy * fmax(-ux[size_t(gj) * (g.nx + 1)], 0.0);
+      if (gi == g.nx - 1) out += g.hy * fmax(ux[size_t(gj) * (g.nx + 1) + g.nx], 0.0);
+      if (gj == 0) out += g.hx * fmax(-uy[gi], 0.0);
+      if (gj == g.ny - 1) out += g.hx * fmax(uy[size_t(g.ny) * g.nx + gi], 0.0);
+      wq = out;
+      ww = out * frac_w(sv, scal[SC_MRATIO]);
+    }
     const double lam = sv * sv / mu_w + (1.0 - sv) * (1.0 - sv) / mu_o;
     const double kn = lam * K[gc];
     kap_n[gc] = kn;
@@ -47,17 +68,27 @@ k_kappa(Geo g, const double* __restrict__ s, const double* __restrict__ K, doubl
   }
   sa[threadIdx.x] = a;
   sb[threadIdx.x] = bb;
+  sq[threadIdx.x] = wq;
+  sw[threadIdx.x] = ww;
   const int changed = __syncthreads_or(diff);
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
       sa[threadIdx.x] += sa[threadIdx.x + w];
       sb[threadIdx.x] += sb[threadIdx.x + w];
+      if (edge) {
+        sq[threadIdx.x] += sq[threadIdx.x + w];
+        sw[threadIdx.x] += sw[threadIdx.x + w];
+      }
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     red[2 * sub] = sa[0];
     red[2 * sub + 1] = sb[0];
+    if (wc) {
+      red[2 * size_t(g.nsub) + 2 * sub] = sq[0];
+      red[2 * size_t(g.nsub) + 2 * sub + 1] = sw[0];
+    }
     flag[sub] = changed;
     if (changed) {
       const int at = atomicAdd(count, 1);
@@ -67,18 +98,21 @@ k_kappa(Geo g, const double* __restrict__ s, const double* __restrict__ K, doubl
 }
 
 // Fixed-order reduction of the epsilon partial sums into the scalar block; the two sums (and
-// the water cut of the preceding transport) are also written to host memory, with a sequence
-// number, for the switch decision and breakthrough checks.
-__global__ void __launch_bounds__(256) k_reduce_eps(int nblocks, const double* __restrict__ red,
+// the water cut) are also written to host memory, with a sequence number, for the switch
+// decision and breakthrough checks. With wc the per-tile water-cut partials of k_kappa are
+// reduced as well (fixed order) into the water cut: the transport that precedes the
+// conductivity then needs no launch of its own for it.
+__global__ void __launch_bounds__(256) k_reduce_eps(int nblocks, int wc, const double* __restrict__ red,
                                                     double* __restrict__ scal, int32_t* __restrict__ seq,
                                                     double* __restrict__ host, const RunTab* __restrict__ rt) {
   constexpr int B = 16;
-  __shared__ double sa[256], sb[256];
+  __shared__ double sa[256], sb[256], sq[256], sw[256];
   const int64_t wo = ws_off(rt);
   red = at_off(red, wo);
   scal = at_off(scal, wo);
   seq = at_off(seq, wo);
   host = at_off(host, host_off(rt));
+  double q = 0.0, w = 0.0;
   double a = 0.0, b = 0.0;
   for (int base = 0; base < nblocks; base += 256 * B) {
     double va[B], vb[B];
@@ -96,26 +130,47 @@ __global__ void __launch_bounds__(256) k_reduce_eps(int nblocks, const double* _
         b += vb[u];
       }
     }
+    if (wc) {
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int i = base + threadIdx.x + 256 * u;
+        const int ic = i < nblocks ? i : 0;
+        va[u] = red[2 * nblocks + 2 * ic];
+        vb[u] = red[2 * nblocks + 2 * ic + 1];
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        if (base + int(threadIdx.x) + 256 * u < nblocks) {
+          q += va[u];
+          w += vb[u];
+        }
+      }
+    }
   }
   sa[threadIdx.x] = a;
   sb[threadIdx.x] = b;
+  sq[threadIdx.x] = q;
+  sw[threadIdx.x] = w;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      sa[threadIdx.x] += sa[threadIdx.x + w];
-      sb[threadIdx.x] += sb[threadIdx.x + w];
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      sa[threadIdx.x] += sa[threadIdx.x + o];
+      sb[threadIdx.x] += sb[threadIdx.x + o];
+      sq[threadIdx.x] += sq[threadIdx.x + o];
+      sw[threadIdx.x] += sw[threadIdx.x + o];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     scal[SC_EPS_NUM] = sa[0];
     scal[SC_EPS_DEN] = sb[0];
-    const int32_t q = *seq + 1;
-    *seq = q;
+    if (wc) scal[SC_WCUT] = sq[0] > 0.0 ? sw[0] / sq[0] : 0.0;
+    const int32_t n = *seq + 1;
+    *seq = n;
     host[0] = sa[0];
     host[1] = sb[0];
     host[3] = scal[SC_WCUT];
-    host[2] = double(q);
+    host[2] = double(n);
   }
 }
 
@@ -216,11 +271,12 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
 
 void launch_kappa(hipStream_t st, const Geo& g, const double* s, const double* K, double* kn, const double* km,
                   double* red, double* scal, int32_t* flag, int32_t* list, int32_t* count, int32_t* seq,
-                  double* host, Runs rt) {
+                  double* host, const double* wc_ux, const double* wc_uy, Runs rt) {
   const unsigned nr = runs_of(rt);
   hipLaunchKernelGGL(k_kappa, dim3(g.nsub, 1, nr), dim3(256), 0, st, g, s, K, kn, km, red, flag, list, count, scal,
-                     rt.tab);
-  hipLaunchKernelGGL(k_reduce_eps, dim3(1, 1, nr), dim3(256), 0, st, g.nsub, red, scal, seq, host, rt.tab);
+                     wc_ux, wc_uy, rt.tab);
+  hipLaunchKernelGGL(k_reduce_eps, dim3(1, 1, nr), dim3(256), 0, st, g.nsub, wc_ux != nullptr ? 1 : 0, red, scal,
+                     seq, host, rt.tab);
 }
 
 void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double* scal,

@@ -10,16 +10,6 @@
 
 namespace mpm {
 
-namespace {
-
-__device__ __forceinline__ double fracflow(double s, double M) {
-  const double a = M * s * s;
-  const double o = 1.0 - s;
-  return a / (a + o * o);
-}
-
-}  // namespace
-
 // s2 = s - dt/|c| sum_f |f| u_f f(s_upwind); the injected saturation on inflow boundary faces.
 __global__ void __launch_bounds__(256)
 k_sat_step(Geo g, const double* __restrict__ s, double* __restrict__ s2, const double* __restrict__ ux,
@@ -47,10 +37,10 @@ k_sat_step(Geo g, const double* __restrict__ s, double* __restrict__ s2, const d
     const double sE = gi < g.nx - 1 ? s[c + 1] : g.s_inj;
     const double sS = gj > 0 ? s[c - g.nx] : g.s_inj;
     const double sN = gj < g.ny - 1 ? s[c + g.nx] : g.s_inj;
-    const double FW = g.hy * uW * fracflow(uW > 0.0 ? sW : sc, M);
-    const double FE = g.hy * uE * fracflow(uE > 0.0 ? sc : sE, M);
-    const double FS = g.hx * uS * fracflow(uS > 0.0 ? sS : sc, M);
-    const double FN = g.hx * uN * fracflow(uN > 0.0 ? sc : sN, M);
+    const double FW = g.hy * uW * frac_w(uW > 0.0 ? sW : sc, M);
+    const double FE = g.hy * uE * frac_w(uE > 0.0 ? sc : sE, M);
+    const double FS = g.hx * uS * frac_w(uS > 0.0 ? sS : sc, M);
+    const double FN = g.hx * uN * frac_w(uN > 0.0 ? sc : sN, M);
     s2[c] = sc - dt / (g.hx * g.hy) * ((FE - FW) + (FN - FS));
   }
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
@@ -89,16 +79,10 @@ k_water_cut(Geo g, const double* __restrict__ s, const double* __restrict__ ux, 
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e0 = base + threadIdx.x + 256 * u;
-      const int e = e0 < hi ? e0 : lo;
-      const bool vert = e < 2 * nW;
-      const int k = vert ? (e < nW ? e : e - nW) : (e < 2 * nW + nS ? e - 2 * nW : e - 2 * nW - nS);
-      const bool hiside = vert ? e >= nW : e >= 2 * nW + nS;
-      const double* up = vert ? ux : uy;
-      const int ui = vert ? k * (g.nx + 1) + (hiside ? g.nx : 0) : (hiside ? g.ny * g.nx : 0) + k;
-      const int si = vert ? k * g.nx + (hiside ? g.nx - 1 : 0) : (hiside ? (g.ny - 1) * g.nx : 0) + k;
-      const double uv = up[ui];
-      vu[u] = hiside ? uv : -uv;
-      vs[u] = s[si];
+      const DomFace d = dom_face(g, e0 < hi ? e0 : lo);
+      const double uv = (d.vert ? ux : uy)[d.ui];
+      vu[u] = d.hi ? uv : -uv;
+      vs[u] = s[d.si];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -107,7 +91,7 @@ k_water_cut(Geo g, const double* __restrict__ s, const double* __restrict__ ux, 
         const double fl = e < 2 * nW ? g.hy : g.hx;
         const double out = fl * fmax(vu[u], 0.0);
         q += out;
-        w += out * fracflow(vs[u], M);
+        w += out * frac_w(vs[u], M);
       }
     }
   }
