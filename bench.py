@@ -36,12 +36,12 @@ KERNEL_SOURCES = {
     "mpm_local": ["lines.hip", "lines.hpp", "device.hpp", "kernels.hpp"],
     "downscale": ["lines.hip", "lines.hpp", "device.hpp"],
     "flux": ["local.hip", "device.hpp"],
-    "kappa_eps": ["local.hip"],
+    "sat_kappa": ["local.hip", "device.hpp"],
     "sat_step": ["transport.hip", "device.hpp"],
 }
 # rocprofv3 kernel names -> kernel classes of the library's event profiler
 TRAFFIC_NAMES = {"k_mpm_local_lb": "mpm_local", "k_downscale_lb": "downscale", "k_flux": "flux",
-                 "k_kappa": "kappa_eps", "k_sat_step": "sat_step"}
+                 "k_kappa": "sat_kappa", "k_sat_step": "sat_step"}
 
 
 def algorithmic_bytes(cfg: dict) -> dict:
@@ -62,9 +62,10 @@ def algorithmic_bytes(cfg: dict) -> dict:
     nb = 2 * (mx + my)
     ndof = 4 * (cfg["ne_x"] + cfg["ne_y"])
     return {
-        # s, K, kappa^m read; kappa^n written
-        "kappa_eps": 32.0 * nc,
-        # s read, four face fluxes per cell (each face shared), s written
+        # last transport sub-step with the conductivity: s, four face fluxes per cell (each
+        # face shared), K, kappa^m read; s and kappa^n written
+        "sat_kappa": 8.0 * nc + 8.0 * nfaces + 8.0 * nc + 24.0 * nc,
+        # the other C_n - 1 sub-steps: s and the faces read, s written
         "sat_step": 8.0 * nc + 8.0 * nfaces + 8.0 * nc,
         # kept blocks; kappa^n, kappa^m, q; u~^m; h and v written; interface rhs written
         "mpm_local": blocks + 24.0 * nc + 8.0 * nfaces + 16.0 * nsub * nb + 8.0 * nsub * ndof,
@@ -85,7 +86,7 @@ def phase_rooflines(alg: dict, sb: dict, prof: dict, cfg: dict, ms_step: float) 
             gbs = sb[key] / (prof[name][0] * 1e-3) / 1e9
             out[name] = {"bytes": sb[key], "ms": round(prof[name][0], 5), "achieved": round(gbs, 1),
                          "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    step_bytes = sum(alg[k] * (cfg["cn"] if k == "sat_step" else 1) for k in alg) + sb["fwd"] + sb["bwd"]
+    step_bytes = sum(alg[k] * (cfg["cn"] - 1 if k == "sat_step" else 1) for k in alg) + sb["fwd"] + sb["bwd"]
     gbs = step_bytes / (ms_step * 1e-3) / 1e9
     out["step"] = {"bytes": step_bytes, "ms": round(ms_step, 4), "achieved": round(gbs, 1),
                    "frac": round(gbs / HBM_PEAK_GBS, 4)}

@@ -194,14 +194,17 @@ double eps_from(const mpm_run* r, double num, double den) {
 }
 
 // kappa^n = lambda(s) K and the sums of epsilon against kappa^m, also written by the reduction
-// kernel into pinned host memory (the caller records ev_eps after it). With wc the reduction
-// also computes the water cut of s under the current velocity (after a transport).
-mpm_status kappa_and_eps_nodes(mpm_run* r, bool wc = false) {
+// kernel into pinned host memory (the caller records ev_eps after it). With sat the same
+// kernel first takes the last transport sub-step (s -> s2, then the buffers swap) and the
+// reduction computes the water cut of the new saturation under the current velocity.
+mpm_status kappa_and_eps_nodes(mpm_run* r, bool sat = false) {
   {
-    Scope sc(r, "kappa_eps");
+    Scope sc(r, sat ? "sat_kappa" : "kappa_eps");
     launch_kappa(r->st, r->g, r->s, r->K, r->kn, r->km, r->red, r->scal, r->dsflag, r->dslist, r->dscount,
-                 r->dscount + 1, r->pinned_dev, wc ? r->ux : nullptr, wc ? r->uy : nullptr);
+                 r->dscount + 1, r->pinned_dev, sat ? r->ux : nullptr, sat ? r->uy : nullptr, one_run(),
+                 sat ? r->s2 : nullptr, r->area);
   }
+  if (sat) std::swap(r->s, r->s2);
   r->eps_seq += 1;
   return MPM_OK;
 }
@@ -222,8 +225,8 @@ mpm_status wait_eps(mpm_run* r) {
   return MPM_OK;
 }
 
-mpm_status kappa_and_eps(mpm_run* r, bool wc = false) {
-  mpm_status st = kappa_and_eps_nodes(r, wc);
+mpm_status kappa_and_eps(mpm_run* r, bool sat = false) {
+  mpm_status st = kappa_and_eps_nodes(r, sat);
   if (st) return st;
   HIPCHK(r, hipEventRecord(r->ev_eps, r->st));
   return MPM_OK;
@@ -507,7 +510,8 @@ mpm_status transport(mpm_run* r, int32_t nsteps, bool wc = true) {
 }
 
 // C_n transport sub-steps and kappa^n with its epsilon sums and the water cut (event ev_eps
-// recorded after them). With graphs they are one graph per parity of the saturation buffers.
+// recorded after them); the last sub-step is taken by the conductivity kernel. With graphs
+// they are one graph per parity of the saturation buffers.
 mpm_status transport_and_kappa(mpm_run* r) {
   const int cn = r->P.d.cn;
   if (r->use_graphs && !r->prof) {
@@ -523,7 +527,7 @@ mpm_status transport_and_kappa(mpm_run* r) {
     double* s0 = r->s;
     double* s1 = r->s2;
     r->g_trans[par] = capture_and_launch(r, [&] {
-      mpm_status st = transport_body(r, cn, false);
+      mpm_status st = transport_body(r, cn - 1, false);
       if (st) return st;
       return kappa_and_eps_nodes(r, true);
     });
@@ -537,8 +541,9 @@ mpm_status transport_and_kappa(mpm_run* r) {
     r->s2 = s1;
     r->use_graphs = false;
   }
-  mpm_status st = transport(r, cn, false);
+  mpm_status st = transport(r, cn - 1, false);
   if (st) return st;
+  r->ntr += 1;
   return kappa_and_eps(r, true);
 }
 
@@ -954,13 +959,15 @@ mpm_status group_issue(std::vector<mpm_run*>& g, GroupStreams& gs, std::vector<m
     if (e) return e;
   }
   const int cn = L->P.d.cn;
-  // transport sub-steps, conductivity, epsilon sums and water cut of every run
-  for (int k = 0; k < cn; ++k) {
+  // transport sub-steps, conductivity, epsilon sums and water cut of every run (the last
+  // sub-step taken by the conductivity kernel)
+  for (int k = 0; k + 1 < cn; ++k) {
     launch_sat_step(gs.st, L->g, L->s, L->s2, L->ux, L->uy, L->scal, L->area, rt);
     for (mpm_run* r : g) std::swap(r->s, r->s2);
   }
   launch_kappa(gs.st, L->g, L->s, L->K, L->kn, L->km, L->red, L->scal, L->dsflag, L->dslist, L->dscount,
-               L->dscount + 1, L->pinned_dev, L->ux, L->uy, rt);
+               L->dscount + 1, L->pinned_dev, L->ux, L->uy, rt, L->s2, L->area);
+  for (mpm_run* r : g) std::swap(r->s, r->s2);
   for (mpm_run* r : g) {
     r->eps_seq += 1;
     r->ntr += cn;

@@ -78,6 +78,27 @@ __device__ __forceinline__ double frac_w(double s, double M) {
   const double o = 1.0 - s;
   return a / (a + o * o);
 }
+// Explicit upwind update of cell (gi, gj) over one sub-step dt (eq. BL2D): s - dt/|c| sum_f
+// |f| u_f f_w(s_upwind), the injected saturation behind inflow boundary faces.
+__device__ __forceinline__ double sat_cell(const Geo& g, const double* __restrict__ s,
+                                           const double* __restrict__ ux, const double* __restrict__ uy, int gi,
+                                           int gj, double dt, double M) {
+  const int c = gj * g.nx + gi;
+  const double sc = s[c];
+  const double uW = ux[gj * (g.nx + 1) + gi];
+  const double uE = ux[gj * (g.nx + 1) + gi + 1];
+  const double uS = uy[gj * g.nx + gi];
+  const double uN = uy[(gj + 1) * g.nx + gi];
+  const double sW = gi > 0 ? s[c - 1] : g.s_inj;
+  const double sE = gi < g.nx - 1 ? s[c + 1] : g.s_inj;
+  const double sS = gj > 0 ? s[c - g.nx] : g.s_inj;
+  const double sN = gj < g.ny - 1 ? s[c + g.nx] : g.s_inj;
+  const double FW = g.hy * uW * frac_w(uW > 0.0 ? sW : sc, M);
+  const double FE = g.hy * uE * frac_w(uE > 0.0 ? sc : sE, M);
+  const double FS = g.hx * uS * frac_w(uS > 0.0 ? sS : sc, M);
+  const double FN = g.hx * uN * frac_w(uN > 0.0 ? sc : sN, M);
+  return sc - dt / (g.hx * g.hy) * ((FE - FW) + (FN - FS));
+}
 // Boundary face e of the domain for the water cut, 0 <= e < 2 (nx + ny): W faces j = 0..ny-1,
 // then E faces, S faces i = 0..nx-1, N faces. Its normal velocity index in ux or uy, the cell
 // behind it, whether it is an x-face and whether the outward normal is +x / +y.

@@ -40,10 +40,13 @@ __device__ __forceinline__ void leaf_out(const LeafOut& lo, int sub, int a, doub
 // pointers of the first run; by default for one run.
 
 // local.hip
-// with wc_ux non-null the reduction also computes the water cut of s and (wc_ux, wc_uy)
+// With wc_ux non-null the reduction also computes the water cut under (wc_ux, wc_uy); with
+// s_new non-null (which needs wc_ux) the kernel first takes a transport sub-step from s into
+// s_new under that velocity and works on the new saturation.
 void launch_kappa(hipStream_t st, const Geo& g, const double* s, const double* K, double* kn, const double* km,
                   double* red, double* scal, int32_t* flag, int32_t* list, int32_t* count, int32_t* seq,
-                  double* host, const double* wc_ux, const double* wc_uy, Runs rt = one_run());
+                  double* host, const double* wc_ux, const double* wc_uy, Runs rt = one_run(),
+                  double* s_new = nullptr, double area = 0.0);
 // the sub-step bound uses the run's cfl and fractional-flow derivative bound from scal
 void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double* scal,
                int32_t* count, Runs rt = one_run());

@@ -14,11 +14,16 @@ namespace mpm {
 // since the last MRCM update (flag, and the subdomain appended to the list of changed ones).
 // With ux non-null, also the tile's partial sums of the water cut (outflow |f| u.n and
 // |f| u.n f_w(s) over the domain's boundary faces in the tile) at red[2 nsub + 2 sub].
+// With SAT the kernel first takes the transport sub-step of its cells (the saturation update
+// is local to the tile, reading the neighbours' old values): s is the old saturation, the new
+// one goes to s_new and is the one the conductivity and the water cut use.
+template <bool SAT>
 __global__ void __launch_bounds__(256)
-k_kappa(Geo g, const double* __restrict__ s, const double* __restrict__ K, double* __restrict__ kap_n,
-        const double* __restrict__ kap_m, double* __restrict__ red, int32_t* __restrict__ flag,
-        int32_t* __restrict__ list, int32_t* __restrict__ count, const double* __restrict__ scal,
-        const double* __restrict__ ux, const double* __restrict__ uy, const RunTab* __restrict__ rt) {
+k_kappa(Geo g, const double* __restrict__ s, double* __restrict__ s_new, const double* __restrict__ K,
+        double* __restrict__ kap_n, const double* __restrict__ kap_m, double* __restrict__ red,
+        int32_t* __restrict__ flag, int32_t* __restrict__ list, int32_t* __restrict__ count,
+        double* __restrict__ scal, const double* __restrict__ ux, const double* __restrict__ uy, double area,
+        const RunTab* __restrict__ rt) {
   __shared__ double sa[256], sb[256], sq[256], sw[256];
   const int64_t wo = ws_off(rt);
   const bool wc = ux != nullptr;
@@ -27,6 +32,7 @@ k_kappa(Geo g, const double* __restrict__ s, const double* __restrict__ K, doubl
     uy = at_off(uy, wo);
   }
   s = at_off(s, wo);
+  if constexpr (SAT) s_new = at_off(s_new, wo);
   K = at_off(K, wo);
   kap_n = at_off(kap_n, wo);
   kap_m = at_off(kap_m, wo);
@@ -46,7 +52,13 @@ k_kappa(Geo g, const double* __restrict__ s, const double* __restrict__ K, doubl
   double wq = 0.0, ww = 0.0;
   if (c < g.nc) {
     const int gc = (J * g.my + c / g.mx) * g.nx + I * g.mx + c % g.mx;
-    const double sv = s[gc];
+    double sv;
+    if constexpr (SAT) {
+      sv = sat_cell(g, s, ux, uy, I * g.mx + c % g.mx, J * g.my + c / g.mx, scal[SC_DT], scal[SC_MRATIO]);
+      s_new[gc] = sv;
+    } else {
+      sv = s[gc];
+    }
     if (edge) {
       const int gi = I * g.mx + c % g.mx, gj = J * g.my + c / g.mx;
       double out = 0.0;
@@ -93,6 +105,11 @@ k_kappa(Geo g, const double* __restrict__ s, const double* __restrict__ K, doubl
     if (changed) {
       const int at = atomicAdd(count, 1);
       if (at < g.nsub) list[at] = sub;
+    }
+    if (SAT && sub == 0) {
+      const double dt = scal[SC_DT];
+      scal[SC_T] += dt;
+      scal[SC_PVI] += dt * scal[SC_QIN] / area;
     }
   }
 }
@@ -271,10 +288,14 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
 
 void launch_kappa(hipStream_t st, const Geo& g, const double* s, const double* K, double* kn, const double* km,
                   double* red, double* scal, int32_t* flag, int32_t* list, int32_t* count, int32_t* seq,
-                  double* host, const double* wc_ux, const double* wc_uy, Runs rt) {
+                  double* host, const double* wc_ux, const double* wc_uy, Runs rt, double* s_new, double area) {
   const unsigned nr = runs_of(rt);
-  hipLaunchKernelGGL(k_kappa, dim3(g.nsub, 1, nr), dim3(256), 0, st, g, s, K, kn, km, red, flag, list, count, scal,
-                     wc_ux, wc_uy, rt.tab);
+  if (s_new)
+    hipLaunchKernelGGL(k_kappa<true>, dim3(g.nsub, 1, nr), dim3(256), 0, st, g, s, s_new, K, kn, km, red, flag, list,
+                       count, scal, wc_ux, wc_uy, area, rt.tab);
+  else
+    hipLaunchKernelGGL(k_kappa<false>, dim3(g.nsub, 1, nr), dim3(256), 0, st, g, s, s_new, K, kn, km, red, flag,
+                       list, count, scal, wc_ux, wc_uy, area, rt.tab);
   hipLaunchKernelGGL(k_reduce_eps, dim3(1, 1, nr), dim3(256), 0, st, g.nsub, wc_ux != nullptr ? 1 : 0, red, scal,
                      seq, host, rt.tab);
 }

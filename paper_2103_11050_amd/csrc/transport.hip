@@ -26,23 +26,7 @@ k_sat_step(Geo g, const double* __restrict__ s, double* __restrict__ s2, const d
   const int gj = blockIdx.y * 4 + (threadIdx.x >> 6);
   const double dt = scal[SC_DT];
   const double M = scal[SC_MRATIO];
-  if (gi < g.nx && gj < g.ny) {
-    const int c = gj * g.nx + gi;
-    const double sc = s[c];
-    const double uW = ux[gj * (g.nx + 1) + gi];
-    const double uE = ux[gj * (g.nx + 1) + gi + 1];
-    const double uS = uy[gj * g.nx + gi];
-    const double uN = uy[(gj + 1) * g.nx + gi];
-    const double sW = gi > 0 ? s[c - 1] : g.s_inj;
-    const double sE = gi < g.nx - 1 ? s[c + 1] : g.s_inj;
-    const double sS = gj > 0 ? s[c - g.nx] : g.s_inj;
-    const double sN = gj < g.ny - 1 ? s[c + g.nx] : g.s_inj;
-    const double FW = g.hy * uW * frac_w(uW > 0.0 ? sW : sc, M);
-    const double FE = g.hy * uE * frac_w(uE > 0.0 ? sc : sE, M);
-    const double FS = g.hx * uS * frac_w(uS > 0.0 ? sS : sc, M);
-    const double FN = g.hx * uN * frac_w(uN > 0.0 ? sc : sN, M);
-    s2[c] = sc - dt / (g.hx * g.hy) * ((FE - FW) + (FN - FS));
-  }
+  if (gi < g.nx && gj < g.ny) s2[gj * g.nx + gi] = sat_cell(g, s, ux, uy, gi, gj, dt, M);
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
     scal[SC_T] += dt;
     scal[SC_PVI] += dt * scal[SC_QIN] / area;
