@@ -176,7 +176,7 @@ mpm_status mpm_batch_create(int32_t capacity, mpm_batch** out);
  * poisoned; MPM_EINVAL on a bad slot or NULL. A run attached before mpm_start is started by
  * mpm_batch_start. */
 mpm_status mpm_batch_attach(mpm_batch* batch, int32_t slot, mpm_run* run);
-/* Algorithm 1, lines 1-4 (conductivity, the first MRCM basis, interface factorisation and
+/* Algorithm 1, initialisation (conductivity, the first MRCM basis, interface factorisation and
  * velocity; Sections 3 and 4.2), for every attached run not yet started, the runs with equal
  * descriptors together: one launch per phase over a group (at most 128 runs), as in
  * mpm_batch_step. Each run ends as after mpm_start. Returns the first error met; the runs of a

@@ -197,12 +197,15 @@ double eps_from(const mpm_run* r, double num, double den) {
 // kernel into pinned host memory (the caller records ev_eps after it). With sat the same
 // kernel first takes the last transport sub-step (s -> s2, then the buffers swap) and the
 // reduction computes the water cut of the new saturation under the current velocity.
-mpm_status kappa_and_eps_nodes(mpm_run* r, bool sat = false) {
+// With fork the reduction runs on the second stream, off the path of the velocity update that
+// follows (nothing there needs it until the downscaling rewrites the partials, which joins
+// the second stream first); the caller records ev_eps on that stream.
+mpm_status kappa_and_eps_nodes(mpm_run* r, bool sat = false, bool fork = false) {
   {
     Scope sc(r, sat ? "sat_kappa" : "kappa_eps");
     launch_kappa(r->st, r->g, r->s, r->K, r->kn, r->km, r->red, r->scal, r->dsflag, r->dslist, r->dscount,
                  r->dscount + 1, r->pinned_dev, sat ? r->ux : nullptr, sat ? r->uy : nullptr, one_run(),
-                 sat ? r->s2 : nullptr, r->area);
+                 sat ? r->s2 : nullptr, r->area, fork ? r->st2 : nullptr, r->ev_fork);
   }
   if (sat) std::swap(r->s, r->s2);
   r->eps_seq += 1;
@@ -217,6 +220,7 @@ mpm_status wait_eps(mpm_run* r) {
   volatile double* p = r->pinned;
   if (p[2] != double(r->eps_seq)) {
     HIPCHK(r, hipStreamSynchronize(r->st));
+    HIPCHK(r, hipStreamSynchronize(r->st2));
     if (p[2] != double(r->eps_seq)) {
       r->last_error = "epsilon sums did not reach host memory";
       return MPM_EHIP;
@@ -225,10 +229,13 @@ mpm_status wait_eps(mpm_run* r) {
   return MPM_OK;
 }
 
+// Eager: the reduction forks to the second stream unless graphs are in use (a captured update
+// would not join it).
 mpm_status kappa_and_eps(mpm_run* r, bool sat = false) {
-  mpm_status st = kappa_and_eps_nodes(r, sat);
+  const bool fork = !r->use_graphs;
+  mpm_status st = kappa_and_eps_nodes(r, sat, fork);
   if (st) return st;
-  HIPCHK(r, hipEventRecord(r->ev_eps, r->st));
+  HIPCHK(r, hipEventRecord(r->ev_eps, fork ? r->st2 : r->st));
   return MPM_OK;
 }
 
@@ -341,6 +348,7 @@ void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store, Run
 
 // MRCM with a new basis for kappa^n (stored as kappa^m), downscaled with the same kappa.
 mpm_status mrcm_update(mpm_run* r) {
+  HIPCHK(r, hipStreamWaitEvent(r->st, r->ev_eps, 0));   // the epsilon reduction may be on st2
   HIPCHK(r, hipMemcpyAsync(r->km, r->kn, size_t(r->P.nx) * r->P.ny * 8, hipMemcpyDeviceToDevice, r->st));
   bool have_fac;
   {
@@ -754,7 +762,7 @@ mpm_status mpm_start(mpm_run* r) {
   if (!r->fields || r->poisoned) return MPM_ESTATE;
   mpm_status st = enter(r);
   if (st) return st;
-  // Algorithm 1, lines 1-4
+  // Algorithm 1, initialisation
   auto body = [&]() -> mpm_status {
     HIPCHK(r, hipMemsetAsync(r->scal, 0, SC_COUNT * 8, r->st));
     HIPCHK(r, hipMemcpyAsync(r->scal + SC_MUW, r->params, sizeof(r->params), hipMemcpyHostToDevice, r->st));
@@ -1176,7 +1184,7 @@ mpm_status mpm_batch_start(mpm_batch* b) {
       for (mpm_run* r : g)
         if (!st) st = move_run(r, s);
       mpm_run* L = g[0];
-      // Algorithm 1, lines 1-4, for every run of the group at once
+      // Algorithm 1, initialisation, for every run of the group at once
       for (mpm_run* r : g) {
         if (st) break;
         if (hipMemsetAsync(r->scal, 0, SC_COUNT * 8, s) != hipSuccess ||

@@ -42,11 +42,13 @@ __device__ __forceinline__ void leaf_out(const LeafOut& lo, int sub, int a, doub
 // local.hip
 // With wc_ux non-null the reduction also computes the water cut under (wc_ux, wc_uy); with
 // s_new non-null (which needs wc_ux) the kernel first takes a transport sub-step from s into
-// s_new under that velocity and works on the new saturation.
+// s_new under that velocity and works on the new saturation. With st_red the reduction kernel
+// goes to that stream, ordered after the tile kernel through ev_red.
 void launch_kappa(hipStream_t st, const Geo& g, const double* s, const double* K, double* kn, const double* km,
                   double* red, double* scal, int32_t* flag, int32_t* list, int32_t* count, int32_t* seq,
                   double* host, const double* wc_ux, const double* wc_uy, Runs rt = one_run(),
-                  double* s_new = nullptr, double area = 0.0);
+                  double* s_new = nullptr, double area = 0.0, hipStream_t st_red = nullptr,
+                  hipEvent_t ev_red = nullptr);
 // the sub-step bound uses the run's cfl and fractional-flow derivative bound from scal
 void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double* scal,
                int32_t* count, Runs rt = one_run());

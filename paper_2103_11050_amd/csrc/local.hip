@@ -288,7 +288,8 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
 
 void launch_kappa(hipStream_t st, const Geo& g, const double* s, const double* K, double* kn, const double* km,
                   double* red, double* scal, int32_t* flag, int32_t* list, int32_t* count, int32_t* seq,
-                  double* host, const double* wc_ux, const double* wc_uy, Runs rt, double* s_new, double area) {
+                  double* host, const double* wc_ux, const double* wc_uy, Runs rt, double* s_new, double area,
+                  hipStream_t st_red, hipEvent_t ev_red) {
   const unsigned nr = runs_of(rt);
   if (s_new)
     hipLaunchKernelGGL(k_kappa<true>, dim3(g.nsub, 1, nr), dim3(256), 0, st, g, s, s_new, K, kn, km, red, flag, list,
@@ -296,8 +297,12 @@ void launch_kappa(hipStream_t st, const Geo& g, const double* s, const double* K
   else
     hipLaunchKernelGGL(k_kappa<false>, dim3(g.nsub, 1, nr), dim3(256), 0, st, g, s, s_new, K, kn, km, red, flag,
                        list, count, scal, wc_ux, wc_uy, area, rt.tab);
-  hipLaunchKernelGGL(k_reduce_eps, dim3(1, 1, nr), dim3(256), 0, st, g.nsub, wc_ux != nullptr ? 1 : 0, red, scal,
-                     seq, host, rt.tab);
+  if (st_red) {
+    hipEventRecord(ev_red, st);
+    hipStreamWaitEvent(st_red, ev_red, 0);
+  }
+  hipLaunchKernelGGL(k_reduce_eps, dim3(1, 1, nr), dim3(256), 0, st_red ? st_red : st, g.nsub,
+                     wc_ux != nullptr ? 1 : 0, red, scal, seq, host, rt.tab);
 }
 
 void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* red_qin, double* scal,
