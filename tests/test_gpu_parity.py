@@ -311,3 +311,43 @@ def test_x1_gaussian_experiment_config(binding, ne, contrast, cn, steps):
     cfg = inputs.x1_config(contrast, ne=ne, cn=cn)
     K = inputs.permeability(cfg)
     _compare_runs(binding, cfg, K, steps, f"x1-ne{ne}-c{contrast:g}-cn{cn}")
+
+
+@pytest.mark.parametrize("cn", [1, 3])
+def test_separate_transport_and_update_equal_step(binding, cn):
+    """A pass of Algorithm 1 made of the two separate entry points (mpm_transport: the C_n
+    sub-steps and the water-cut kernel; mpm_velocity_update: conductivity, epsilon and the
+    update) against mpm_step (the last sub-step inside the conductivity kernel, water cut from
+    its tiles, epsilon reduced on the second stream). The sub-step arithmetic is the same
+    device function, so saturations, velocities and decisions agree exactly; the two water cuts
+    sum the same terms in different orders. Both are checked against the oracle's pass."""
+    cfg = dict(inputs.config("c1"), cn=cn)
+    K = inputs.permeability(cfg)
+    print(f"[gpu] separate transport and update, C_n = {cn}", flush=True)
+    a = _gpu_run(binding, cfg, K)
+    b = _gpu_run(binding, cfg, K)
+    a.start()
+    b.start()
+    orun = splitting.start(cfg, K, np.zeros_like(K))
+    for n in range(6):
+        force = [binding.AUTO, binding.FORCE_MRCM, binding.AUTO, binding.AUTO, binding.FORCE_MPM, binding.AUTO][n]
+        a.step(force)
+        b.transport(cn)
+        b.velocity_update(force)
+        sa_, sb_ = a.stats(), b.stats()
+        assert sa_["error_word"] == 0 and sb_["error_word"] == 0
+        for k in ("te", "tm", "last_branch", "eps", "pvi", "dt"):
+            assert sa_[k] == sb_[k], (n, k, sa_[k], sb_[k])
+        assert np.array_equal(to_np(a.saturation()), to_np(b.saturation()))
+        uxa, uya = a.velocity()
+        uxb, uyb = b.velocity()
+        assert np.array_equal(to_np(uxa), to_np(uxb)) and np.array_equal(to_np(uya), to_np(uyb))
+        assert math.isclose(sa_["water_cut"], sb_["water_cut"], rel_tol=1e-13, abs_tol=1e-16)
+        f = {binding.AUTO: None, binding.FORCE_MRCM: "mrcm", binding.FORCE_MPM: "mpm"}[force]
+        branch = splitting.step(orun, f)
+        assert branch == ("mrcm" if sa_["last_branch"] == binding.FORCE_MRCM else "mpm")
+        assert vel_rel_err(cfg, to_np(uxa), to_np(uya), orun.ux, orun.uy) <= FP64_VEL_TOL
+        assert math.isclose(sa_["water_cut"], orun.wcut, rel_tol=1e-8, abs_tol=1e-14)
+        assert math.isclose(sb_["water_cut"], orun.wcut, rel_tol=1e-8, abs_tol=1e-14)
+    a.close()
+    b.close()
