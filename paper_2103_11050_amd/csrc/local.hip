@@ -83,7 +83,7 @@ k_kappa(Geo g, const double* __restrict__ s, double* __restrict__ s_new, const d
   sq[threadIdx.x] = wq;
   sw[threadIdx.x] = ww;
   const int changed = __syncthreads_or(diff);
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = int(blockDim.x) >> 1; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
       sa[threadIdx.x] += sa[threadIdx.x + w];
       sb[threadIdx.x] += sb[threadIdx.x + w];
@@ -291,11 +291,13 @@ void launch_kappa(hipStream_t st, const Geo& g, const double* s, const double* K
                   double* host, const double* wc_ux, const double* wc_uy, Runs rt, double* s_new, double area,
                   hipStream_t st_red, hipEvent_t ev_red) {
   const unsigned nr = runs_of(rt);
+  // one thread per cell of the tile: the power of two from 64 to 256 that covers it
+  const unsigned bs = g.nc <= 64 ? 64 : g.nc <= 128 ? 128 : 256;
   if (s_new)
-    hipLaunchKernelGGL(k_kappa<true>, dim3(g.nsub, 1, nr), dim3(256), 0, st, g, s, s_new, K, kn, km, red, flag, list,
+    hipLaunchKernelGGL(k_kappa<true>, dim3(g.nsub, 1, nr), dim3(bs), 0, st, g, s, s_new, K, kn, km, red, flag, list,
                        count, scal, wc_ux, wc_uy, area, rt.tab);
   else
-    hipLaunchKernelGGL(k_kappa<false>, dim3(g.nsub, 1, nr), dim3(256), 0, st, g, s, s_new, K, kn, km, red, flag,
+    hipLaunchKernelGGL(k_kappa<false>, dim3(g.nsub, 1, nr), dim3(bs), 0, st, g, s, s_new, K, kn, km, red, flag,
                        list, count, scal, wc_ux, wc_uy, area, rt.tab);
   if (st_red) {
     hipEventRecord(ev_red, st);
