@@ -800,6 +800,209 @@ def test_algorithm1_switch_sequences():
     assert never.s.min() >= 0 and never.s.max() <= 1
 
 
+# ---------------------------------------------------------------- scalars of the splitting
+# The mobility and conductivity (Section 2), the switch criterion epsilon (Section 4.1;
+# Algorithm 1), the time step, the boundary inflow behind PVI and the water cut behind
+# breakthrough (Section 5). Each checker takes the function under test, so that the planted
+# mistakes below run through the same checks.
+
+def _check_mobility(mob, cond):
+    """lambda(0) = 1/mu_o and lambda(1) = 1/mu_w (the Corey curves vanish at the other
+    end); the water share of the mobility is the fractional flow, whose Welge shock is pinned
+    in T16; lambda is smallest at s = mu_w/(mu_w+mu_o), where it is 1/(mu_w+mu_o)
+    (d lambda/ds = 2s/mu_w - 2(1-s)/mu_o = 0); kappa = lambda K."""
+    ok = True
+    for mu_w, mu_o in ((1.0, 10.0), (0.5, 40.0), (2.0, 3.0)):
+        ok &= abs(float(mob(0.0, mu_w, mu_o)) - 1.0 / mu_o) <= 1e-15 / mu_o
+        ok &= abs(float(mob(1.0, mu_w, mu_o)) - 1.0 / mu_w) <= 1e-15 / mu_w
+        s = np.linspace(0.0, 1.0, 101)
+        share = (s * s / mu_w) / mob(s, mu_w, mu_o)
+        ok &= bool(np.allclose(share, physics.frac_flow(s, mu_o / mu_w), rtol=0, atol=1e-14))
+        smin = mu_w / (mu_w + mu_o)
+        ok &= abs(float(mob(smin, mu_w, mu_o)) - 1.0 / (mu_w + mu_o)) <= 1e-14 / (mu_w + mu_o)
+        grid = mob(np.linspace(0.0, 1.0, 20001), mu_w, mu_o)
+        ok &= float(grid.min()) >= 1.0 / (mu_w + mu_o) * (1 - 1e-14)
+        K = np.array([[3.0, 0.25], [7.0, 1e-3]])
+        ss = np.array([[0.0, 1.0], [smin, 0.5]])
+        want = K * np.array([[1 / mu_o, 1 / mu_w], [1 / (mu_w + mu_o), 0.25 * (1 / mu_w + 1 / mu_o)]])
+        ok &= bool(np.allclose(cond(ss, K, mu_w, mu_o), want, rtol=1e-14, atol=0))
+    return bool(ok)
+
+
+def test_mobility_and_conductivity_closed_forms():
+    assert _check_mobility(physics.mobility, physics.conductivity)
+
+
+def _check_eps(eps):
+    """kappa^n = (1+c) kappa^m gives epsilon = |c| in the relative norm and |c| ||kappa^m||
+    in L2(Omega); with constant kappa^m = k, ||kappa^m||_{L2(Omega)} = k sqrt(|Omega|). A
+    change of one cell by d gives d sqrt(|cell|) in L2(Omega)."""
+    ok = True
+    rng = np.random.default_rng(11)
+    km = np.exp(rng.standard_normal((6, 9)))
+    for c in (0.5, -0.25, 1e-3):
+        cfg = dict(lx=2.0, ly=0.75)
+        ok &= abs(eps(cfg, (1 + c) * km, km) - abs(c)) <= 1e-14
+        kc = np.full((6, 9), 2.5)
+        got = eps(dict(cfg, eps_norm="abs"), (1 + c) * kc, kc)
+        ok &= abs(got - abs(c) * 2.5 * np.sqrt(2.0 * 0.75)) <= 1e-14 * max(got, 1.0)
+    kn = km.copy()
+    kn[2, 3] += 0.4
+    got = eps(dict(lx=2.0, ly=0.75, eps_norm="abs"), kn, km)
+    ok &= abs(got - 0.4 * np.sqrt(2.0 * 0.75 / 54)) <= 1e-14
+    return bool(ok)
+
+
+def test_eps_norm_closed_forms():
+    assert _check_eps(splitting.eps_norm)
+
+
+def _check_time_step(ts):
+    """The monotone upwind bound: a uniform flow (a, b) gives the outflow rate a/hx + b/hy in
+    every cell, so dt = cfl / (f'_max (a/hx + b/hy)); 1D unit flow gives cfl h / f'_max. With
+    a flux that grows along x, the cell with the largest outflow sets the step (not the
+    largest inflow). f'_max is the root of the cubic f'' = 0 (pinned in T17)."""
+    ok = True
+    for M in (4.0, 100.0):
+        P = np.polynomial.Polynomial
+        s_ = P([0, 1])
+        cubic = (1 - 2 * s_) * (M * s_ ** 2 + (1 - s_) ** 2) - 4 * s_ * (1 - s_) * (M * s_ - (1 - s_))
+        fmax = max(float(physics.frac_flow_deriv(r.real, M)) for r in cubic.roots()
+                   if abs(r.imag) < 1e-12 and 0 < r.real < 1)
+        cfg = dict(lx=2.0, ly=0.5, mu_w=1.0, mu_o=M, cfl=0.5)
+        n = 8
+        got = ts(cfg, np.ones((1, n + 1)), np.zeros((2, n)))
+        ok &= abs(got - 0.5 * (2.0 / n) / fmax) <= 1e-13 * got
+        nx, ny, a, b = 5, 4, 0.3, 2.0
+        hx, hy = 2.0 / nx, 0.5 / ny
+        got = ts(cfg, np.full((ny, nx + 1), a), np.full((ny + 1, nx), b))
+        ok &= abs(got - 0.5 / (fmax * (a / hx + b / hy))) <= 1e-13 * got
+        ux = np.array([[1.0, 2.0, 4.0]])
+        got = ts(dict(cfg, lx=1.0, ly=1.0), ux, np.zeros((2, 2)))
+        ok &= abs(got - 0.5 / (fmax * 4.0 / 0.5)) <= 1e-13 * got
+    return bool(ok)
+
+
+def test_time_step_closed_forms():
+    assert _check_time_step(transport.time_step)
+
+
+def _check_inflow(inflow):
+    """Inflow through the boundary: face length times the inward normal flux, summed.
+    Unit inflow on W over l_y gives l_y. On a hand-made field with inflow and outflow on
+    every side (hx = 1, hy = 0.5): W in 1 + 2, E in 0.5 (u = -0.5 at the first row), S in 3
+    (u_y = +3 at the middle column), N in 4 (u_y = -4 at the last column)."""
+    ok = True
+    ly, lx, ny, nx = 0.75, 2.0, 6, 4
+    ux = np.zeros((ny, nx + 1))
+    ux[:, 0] = 1.0
+    ux[:, -1] = 1.0
+    ok &= abs(inflow(dict(lx=lx, ly=ly), ux, np.zeros((ny + 1, nx))) - ly) <= 1e-15
+    ux = np.array([[1.0, 9.0, 9.0, -0.5], [2.0, 9.0, 9.0, 7.0]])
+    uy = np.array([[-1.0, 3.0, -2.0], [5.0, 5.0, 5.0], [6.0, 0.0, -4.0]])
+    want = 0.5 * (1.0 + 2.0) + 0.5 * 0.5 + 1.0 * 3.0 + 1.0 * 4.0
+    ok &= abs(inflow(dict(lx=3.0, ly=1.0), ux, uy) - want) <= 1e-14
+    return bool(ok)
+
+
+def test_boundary_inflow_closed_forms():
+    assert _check_inflow(transport.boundary_inflow)
+
+
+def test_pvi_and_time_accumulate_with_the_inflow():
+    """PVI after k sub-steps of unit inflow on W is k dt l_y / |Omega| = t / l_x, and the
+    simulated time is k dt (Section 5 reports breakthrough in PVI)."""
+    ny, nx = 3, 5
+    cfg = dict(lx=2.5, ly=0.6, mu_w=1.0, mu_o=4.0, s_inj=1.0, cfl=0.5)
+    run = splitting.Run(cfg, np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx)))
+    run.ux = np.ones((ny, nx + 1))
+    run.uy = np.zeros((ny + 1, nx))
+    run.dt = transport.time_step(cfg, run.ux, run.uy)
+    splitting.transport(run, 7)
+    assert abs(run.t - 7 * run.dt) <= 1e-15 * run.t
+    assert abs(run.pvi - run.t / cfg["lx"]) <= 1e-14 * run.pvi
+
+
+def _check_water_cut(wc):
+    """Water cut = sum over outflow boundary faces of |f| u_f f(s_c) / sum of |f| u_f. A
+    uniform saturation gives f(s) whatever the fluxes; on a hand-made field (hx = 1,
+    hy = 0.5, M = 4, injected s-bar = 1) the outflow is 0.5 at E row 0 (s = 0.2), 1.5 at E
+    row 1 (s = 0.7) and 2 at N column 1 (s = 0.5); inflow faces do not count.
+    f(0.2) = 0.2, f(0.7) = 196/205, f(0.5) = 0.8."""
+    ok = True
+    M = 4.0
+    cfg = dict(lx=3.0, ly=1.0, mu_w=1.0, mu_o=M, s_inj=1.0)
+    ux = np.array([[1.0, 9.0, 9.0, 1.0], [1.0, 9.0, 9.0, 3.0]])
+    uy = np.array([[0.5, 0.0, 0.0], [5.0, 5.0, 5.0], [0.0, 2.0, 0.0]])
+    for sv in (0.0, 0.3, 0.9):
+        s = np.full((2, 3), sv)
+        ok &= abs(wc(cfg, s, ux, uy) - float(physics.frac_flow(sv, M))) <= 1e-15
+    s = np.array([[0.9, 0.9, 0.2], [0.9, 0.5, 0.7]])
+    want = (0.5 * 0.2 + 1.5 * 196.0 / 205.0 + 2.0 * 0.8) / 4.0
+    ok &= abs(wc(cfg, s, ux, uy) - want) <= 1e-15
+    return bool(ok)
+
+
+def test_water_cut_closed_forms():
+    assert _check_water_cut(transport.water_cut)
+
+
+def test_planted_scalar_mistakes_are_caught():
+    """A plausible slip in each scalar of the splitting fails its pin: viscosities swapped
+    in the mobility; epsilon over ||kappa^n|| or without the square root; the time step from
+    the inflow faces, or half the bound; the inflow counted with the outflow; the water cut
+    over the inflow, or with the saturation outside the face."""
+    def mob_swapped(s, mu_w, mu_o):
+        return physics.mobility(s, mu_o, mu_w)
+
+    def cond_swapped(s, K, mu_w, mu_o):
+        return mob_swapped(s, mu_w, mu_o) * np.asarray(K)
+    assert not _check_mobility(mob_swapped, cond_swapped)
+
+    def eps_over_n(cfg, kn, km):
+        d = kn - km
+        if cfg.get("eps_norm", "rel") == "abs":
+            return splitting.eps_norm(cfg, kn, km)
+        return float(np.sqrt(np.sum(d * d)) / np.sqrt(np.sum(kn * kn)))
+    assert not _check_eps(eps_over_n)
+
+    def eps_no_sqrt(cfg, kn, km):
+        return splitting.eps_norm(cfg, kn, km) ** 2
+    assert not _check_eps(eps_no_sqrt)
+
+    def dt_inflow(cfg, ux, uy):
+        ny, nx = ux.shape[0], uy.shape[1]
+        hx, hy = cfg["lx"] / nx, cfg["ly"] / ny
+        inn = (hy * (np.maximum(ux[:, :-1], 0.0) + np.maximum(-ux[:, 1:], 0.0))
+               + hx * (np.maximum(uy[:-1, :], 0.0) + np.maximum(-uy[1:, :], 0.0)))
+        fmax, _ = physics.max_frac_flow_deriv(cfg["mu_o"] / cfg["mu_w"])
+        return cfg["cfl"] / (fmax * float(inn.max()) / (hx * hy))
+    assert not _check_time_step(dt_inflow)
+    assert not _check_time_step(lambda cfg, ux, uy: 0.5 * transport.time_step(cfg, ux, uy))
+
+    def inflow_abs(cfg, ux, uy):
+        ny, nx = ux.shape[0], uy.shape[1]
+        hx, hy = cfg["lx"] / nx, cfg["ly"] / ny
+        return float(hy * (np.abs(ux[:, 0]).sum() + np.abs(ux[:, -1]).sum())
+                     + hx * (np.abs(uy[0, :]).sum() + np.abs(uy[-1, :]).sum()))
+    assert not _check_inflow(inflow_abs)
+
+    def wc_over_inflow(cfg, s, ux, uy):
+        M = cfg["mu_o"] / cfg["mu_w"]
+        ny, nx = s.shape
+        hx, hy = cfg["lx"] / nx, cfg["ly"] / ny
+        qw = (hy * (np.maximum(ux[:, -1], 0) * physics.frac_flow(s[:, -1], M)).sum()
+              + hy * (np.maximum(-ux[:, 0], 0) * physics.frac_flow(s[:, 0], M)).sum()
+              + hx * (np.maximum(uy[-1, :], 0) * physics.frac_flow(s[-1, :], M)).sum()
+              + hx * (np.maximum(-uy[0, :], 0) * physics.frac_flow(s[0, :], M)).sum())
+        return qw / transport.boundary_inflow(cfg, ux, uy)
+    assert not _check_water_cut(wc_over_inflow)
+
+    def wc_outside(cfg, s, ux, uy):
+        return transport.water_cut(cfg, np.full_like(s, cfg["s_inj"]), ux, uy)
+    assert not _check_water_cut(wc_outside)
+
+
 # ---------------------------------------------------------------- planted mistakes
 
 def test_planted_mistakes_are_caught(monkeypatch):
