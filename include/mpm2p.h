@@ -48,7 +48,8 @@ enum {
   MPM_ESINGULAR = -4,  /* the interface system had a zero pivot */
   MPM_ENONFINITE = -5, /* a non-finite value appeared in the state */
   MPM_EHIP = -6,       /* a HIP runtime call failed */
-  MPM_ESTATE = -7      /* call not valid in the run's current state */
+  MPM_ESTATE = -7,     /* call not valid in the run's current state */
+  MPM_ENOCONV = -8     /* an FP64 refinement of the precision form did not reach refine_rtol */
 };
 
 /* Physical boundary kinds, one per side in the order W, E, S, N (eq. Darcy: p = g on the
@@ -71,7 +72,7 @@ enum { MPM_PREC_FP64 = 0, MPM_PREC_FP32_REFINE = 1 };
 /* Branch of a velocity update. */
 enum { MPM_AUTO = -1, MPM_FORCE_MPM = 0, MPM_FORCE_MRCM = 1 };
 
-#define MPM_ABI_VERSION 2
+#define MPM_ABI_VERSION 3
 
 typedef struct mpm_desc {
   int32_t abi_version;        /* MPM_ABI_VERSION */
@@ -101,6 +102,11 @@ typedef struct mpm_desc {
                                  (k_U = k_P = 2: the functions 1 and xi, xi in [-1, 1] along the
                                  element in the global direction, taken at the fine face
                                  midpoints; needs at least two fine faces per element) */
+  double refine_rtol;         /* precision form only: the FP64 iterative refinement of a local
+                                 solve stops once its largest correction is at most refine_rtol
+                                 times the largest entry of the solution, in (0, 1e-2]; a solve
+                                 that needs more than 8 corrections sets MPM_ENOCONV. Ignored
+                                 for MPM_PREC_FP64 */
 } mpm_desc;
 
 typedef struct mpm_stats {

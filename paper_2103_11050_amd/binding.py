@@ -14,11 +14,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpm2p.so")
 
 MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_ENOTSPD, MPM_ESINGULAR, MPM_ENONFINITE, MPM_EHIP, MPM_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+MPM_ENOCONV = -8
 EPS_REL, EPS_ABS = 0, 1
 SWITCH_ALG1, SWITCH_TEXT = 0, 1
 PREC_FP64, PREC_FP32_REFINE = 0, 1
 AUTO, FORCE_MPM, FORCE_MRCM = -1, 0, 1
-ABI_VERSION = 2
+ABI_VERSION = 3
+# refinement target of the precision form when the configuration names none
+REFINE_RTOL_DEFAULT = 1e-10
 
 
 class Desc(ctypes.Structure):
@@ -36,6 +39,7 @@ class Desc(ctypes.Structure):
         ("s_inj", ctypes.c_double), ("cfl", ctypes.c_double),
         ("breakthrough_cut", ctypes.c_double),
         ("mpm_order", ctypes.c_int32), ("iface_degree", ctypes.c_int32),
+        ("refine_rtol", ctypes.c_double),
     ]
 
 
@@ -139,6 +143,7 @@ def make_desc(cfg: dict, precision: int = PREC_FP64) -> Desc:
     d.breakthrough_cut = cfg["breakthrough_cut"]
     d.mpm_order = int(cfg.get("mpm_order", 0))
     d.iface_degree = int(cfg.get("iface_degree", 0))
+    d.refine_rtol = float(cfg.get("refine_rtol", REFINE_RTOL_DEFAULT))
     return d
 
 

@@ -173,6 +173,7 @@ Geo make_geo(const Plan& P) {
   for (int k = 0; k < 4; ++k) g.bc_pack |= (P.d.bc_kind[k] & 3) << (2 * k);
   g.bc_v0 = P.d.bc_value[0]; g.bc_v1 = P.d.bc_value[1]; g.bc_v2 = P.d.bc_value[2]; g.bc_v3 = P.d.bc_value[3];
   g.s_inj = P.d.s_inj;
+  g.refine_rtol = P.d.refine_rtol;
   return g;
 }
 
@@ -187,6 +188,15 @@ mpm_status hip_check(mpm_run* r, hipError_t e, const char* what) {
     mpm_status s_ = hip_check((r), (call), #call);        \
     if (s_ != MPM_OK) return s_;                          \
   } while (0)
+
+// Status of a nonzero device error word. A non-finite value comes first: it is usually the
+// cause of the failed pivots that follow it in the same pass.
+mpm_status err_status(int32_t errw) {
+  if (errw & ERR_NONFINITE) return MPM_ENONFINITE;
+  if (errw & ERR_NOTSPD) return MPM_ENOTSPD;
+  if (errw & ERR_SINGULAR) return MPM_ESINGULAR;
+  return MPM_ENOCONV;
+}
 
 double eps_from(const mpm_run* r, double num, double den) {
   if (r->P.d.eps_norm == MPM_EPS_ABS_L2) return std::sqrt(r->P.hx * r->P.hy * num);
@@ -348,7 +358,7 @@ void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store, Run
 
 // MRCM with a new basis for kappa^n (stored as kappa^m), downscaled with the same kappa.
 mpm_status mrcm_update(mpm_run* r) {
-  HIPCHK(r, hipStreamWaitEvent(r->st, r->ev_eps, 0));   // the epsilon reduction may be on st2
+  if (r->ev_eps) HIPCHK(r, hipStreamWaitEvent(r->st, r->ev_eps, 0));   // the epsilon reduction may be on st2
   HIPCHK(r, hipMemcpyAsync(r->km, r->kn, size_t(r->P.nx) * r->P.ny * 8, hipMemcpyDeviceToDevice, r->st));
   bool have_fac;
   {
@@ -415,9 +425,10 @@ mpm_status mpm_update_body(mpm_run* r, bool capturing, Runs rt = one_run()) {
     Scope sc(r, "mpm_local");
     if (r->f32)
       launch_mpm_local_f32(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac32, r->h, r->vbnd, leaf_dest(r),
-                           rt);
+                           r->err, rt);
     else
-      launch_mpm_local(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac, r->h, r->vbnd, leaf_dest(r), rt);
+      launch_mpm_local(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac, r->h, r->vbnd, leaf_dest(r), r->err,
+                       rt);
   }
   nd_solve(r, rt);
   HIPCHK(r, hipStreamWaitEvent(r->st, r->ev_join, 0));
@@ -562,47 +573,12 @@ mpm_status step(mpm_run* r, int32_t force) {
   return velocity_update(r, force, true);
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* mpm_status_str(mpm_status s) {
-  switch (s) {
-    case MPM_OK: return "ok";
-    case MPM_EINVAL: return "invalid argument";
-    case MPM_ENOMEM: return "workspace too small or host allocation failed";
-    case MPM_ENOTSPD: return "local matrix not positive definite";
-    case MPM_ESINGULAR: return "interface system singular";
-    case MPM_ENONFINITE: return "non-finite value";
-    case MPM_EHIP: return "HIP runtime error";
-    case MPM_ESTATE: return "call not valid in the current state";
-    default: return "unknown status";
-  }
-}
-
-mpm_status mpm_workspace_size(const mpm_desc* desc, size_t* bytes) {
-  if (!desc || !bytes) return MPM_EINVAL;
-  if (validate(*desc, nullptr) != MPM_OK) return MPM_EINVAL;
-  Plan P;
-  build_plan(*desc, &P);
-  *bytes = P.total_bytes;
-  return MPM_OK;
-}
-
-mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, void* hip_stream, mpm_run** out) {
-  if (!desc || !out) return MPM_EINVAL;
-  *out = nullptr;
-  if (validate(*desc, nullptr) != MPM_OK) return MPM_EINVAL;
-  if (!dev_workspace || (reinterpret_cast<uintptr_t>(dev_workspace) & 255)) return MPM_EINVAL;
-  mpm_run* r = new (std::nothrow) mpm_run();
-  if (!r) return MPM_ENOMEM;
-  build_plan(*desc, &r->P);
-  if (bytes < r->P.total_bytes) { delete r; return MPM_ENOMEM; }
+// Points the run's buffers into the workspace ws (the plan's layout) and checks that every
+// device pointer the kernels take lies inside it.
+bool bind_workspace(mpm_run* r, char* ws) {
   const Plan& P = r->P;
   r->g = make_geo(P);
-  r->ust = static_cast<hipStream_t>(hip_stream);
-  hipGetDevice(&r->device);
-  r->ws = static_cast<char*>(dev_workspace);
+  r->ws = ws;
   auto D = [&](size_t off) { return reinterpret_cast<double*>(r->ws + off); };
   r->K = D(P.off_K); r->q = D(P.off_q); r->s = D(P.off_s); r->s2 = D(P.off_s2);
   r->kn = D(P.off_kn); r->km = D(P.off_km); r->ux = D(P.off_ux); r->uy = D(P.off_uy);
@@ -643,6 +619,91 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   r->params[SC_CFL - SC_MUW] = P.d.cfl;
   r->params[SC_FMAX - SC_MUW] = r->fmax_deriv;
   r->area = P.d.lx * P.d.ly;
+  const char* lo = r->ws;
+  const char* hi = r->ws + P.total_bytes;
+  auto in = [&](const void* p, size_t n) {
+    const char* c = static_cast<const char*>(p);
+    return c != nullptr && c >= lo && c + n <= hi;
+  };
+  const size_t cb = size_t(P.nx) * P.ny * 8, ns = size_t(P.nsub);
+  const size_t fx = size_t(P.ny) * (P.nx + 1) * 8, fy = size_t(P.ny + 1) * P.nx * 8;
+  return in(r->K, cb) && in(r->q, cb) && in(r->s, cb) && in(r->s2, cb) && in(r->kn, cb) && in(r->km, cb) &&
+         in(r->ux, fx) && in(r->uy, fy) && in(r->uxm, fx) && in(r->uym, fy) &&
+         in(r->S, ns * ((P.nb / 2 + 1) * P.nb) * 8) && in(r->h, ns * P.nb * 8) && in(r->vbnd, ns * P.nb * 8) &&
+         in(r->ubnd, ns * P.nb * 8) && in(r->leafK, ns * P.ndmax * P.ndmax * 8) && in(r->red, P.n_red * 8) &&
+         in(r->scal, SC_COUNT * 8) && in(r->err, 12) && in(r->dscount, 8) && in(r->dsflag, ns * 4) &&
+         in(r->dslist, ns * 4) && in(r->y, size_t(std::max(P.n_iface, 1)) * 8) &&
+         in(r->subdofs_d, ns * P.ndmax * 4) && in(r->slots, size_t(std::max<int64_t>(P.slot_doubles, 1)) * 8) &&
+         in(r->leafup, ns * sizeof(LeafUp)) &&
+         (!r->f32 || (in(r->fac32, P.n_blocks * 4) && in(r->nfac32, P.n_blocks * 4) && in(r->dsE32, P.n_blocks * 4))) &&
+         in(r->nd.lnodes, std::max<size_t>(P.lnodes.size(), 1) * sizeof(NodeDev)) &&
+         (P.d.mpm_order != 1 || in(r->wbnd, ns * P.nb * 8));
+}
+
+// Uploads the plan's index tables into the workspace and clears what the kernels expect at
+// zero (the forward-solve slots, the scalar block with its integer words, the interface
+// solution), on the run's stream.
+hipError_t upload_plan(mpm_run* r) {
+  const Plan& P = r->P;
+  auto up = [&](size_t off, const void* src, size_t n) {
+    return n ? hipMemcpyAsync(r->ws + off, src, n, hipMemcpyHostToDevice, r->st) : hipSuccess;
+  };
+  hipError_t e = hipSuccess;
+  auto chain = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  chain(up(P.off_nodes, P.nodes.data(), P.nodes.size() * sizeof(NodeDev)));
+  chain(up(P.off_levels, P.level_flat.data(), P.level_flat.size() * 4));
+  chain(up(P.off_lnodes, P.lnodes.data(), P.lnodes.size() * sizeof(NodeDev)));
+  chain(up(P.off_leafup, P.leafup.data(), P.leafup.size() * sizeof(LeafUp)));
+  chain(hipMemsetAsync(r->slots, 0, size_t(std::max<int64_t>(P.slot_doubles, 1)) * 8, r->st));
+  chain(up(P.off_dofpool, P.dof_pool.data(), P.dof_pool.size() * 4));
+  chain(up(P.off_mappool, P.map_pool.data(), P.map_pool.size() * 4));
+  chain(up(P.off_invpool, P.inv_pool.data(), P.inv_pool.size() * 4));
+  chain(up(P.off_subdofs, P.sub_dofs.data(), P.sub_dofs.size() * 4));
+  chain(up(P.off_subndof, P.sub_ndof.data(), P.sub_ndof.size() * 4));
+  chain(hipMemsetAsync(r->scal, 0, SC_COUNT * 8 + 64, r->st));
+  chain(hipMemsetAsync(r->y, 0, size_t(std::max(P.n_iface, 1)) * 8, r->st));
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mpm_status_str(mpm_status s) {
+  switch (s) {
+    case MPM_OK: return "ok";
+    case MPM_EINVAL: return "invalid argument";
+    case MPM_ENOMEM: return "workspace too small or host allocation failed";
+    case MPM_ENOTSPD: return "local matrix not positive definite";
+    case MPM_ESINGULAR: return "interface system singular";
+    case MPM_ENONFINITE: return "non-finite value";
+    case MPM_EHIP: return "HIP runtime error";
+    case MPM_ESTATE: return "call not valid in the current state";
+    case MPM_ENOCONV: return "refinement of a local solve did not converge";
+    default: return "unknown status";
+  }
+}
+
+mpm_status mpm_workspace_size(const mpm_desc* desc, size_t* bytes) {
+  if (!desc || !bytes) return MPM_EINVAL;
+  if (validate(*desc, nullptr) != MPM_OK) return MPM_EINVAL;
+  Plan P;
+  build_plan(*desc, &P);
+  *bytes = P.total_bytes;
+  return MPM_OK;
+}
+
+mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, void* hip_stream, mpm_run** out) {
+  if (!desc || !out) return MPM_EINVAL;
+  *out = nullptr;
+  if (validate(*desc, nullptr) != MPM_OK) return MPM_EINVAL;
+  if (!dev_workspace || (reinterpret_cast<uintptr_t>(dev_workspace) & 255)) return MPM_EINVAL;
+  mpm_run* r = new (std::nothrow) mpm_run();
+  if (!r) return MPM_ENOMEM;
+  build_plan(*desc, &r->P);
+  if (bytes < r->P.total_bytes) { delete r; return MPM_ENOMEM; }
+  r->ust = static_cast<hipStream_t>(hip_stream);
+  hipGetDevice(&r->device);
 #define CREATE_CHK(call)                                                           \
   do {                                                                             \
     const hipError_t e_ = (call);                                                  \
@@ -663,31 +724,7 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
     delete r;
     return s;
   };
-  // every device pointer the kernels take must lie inside the caller's workspace
-  {
-    const char* lo = r->ws;
-    const char* hi = r->ws + P.total_bytes;
-    auto in = [&](const void* p, size_t n) {
-      const char* c = static_cast<const char*>(p);
-      return c != nullptr && c >= lo && c + n <= hi;
-    };
-    const size_t cb = size_t(P.nx) * P.ny * 8, ns = size_t(P.nsub);
-    const size_t fx = size_t(P.ny) * (P.nx + 1) * 8, fy = size_t(P.ny + 1) * P.nx * 8;
-    const bool ok = in(r->K, cb) && in(r->q, cb) && in(r->s, cb) && in(r->s2, cb) && in(r->kn, cb) &&
-                    in(r->km, cb) && in(r->ux, fx) && in(r->uy, fy) && in(r->uxm, fx) && in(r->uym, fy) &&
-                    in(r->S, ns * ((P.nb / 2 + 1) * P.nb) * 8) && in(r->h, ns * P.nb * 8) && in(r->vbnd, ns * P.nb * 8) &&
-                    in(r->ubnd, ns * P.nb * 8) && in(r->leafK, ns * P.ndmax * P.ndmax * 8) &&
-                    in(r->red, P.n_red * 8) && in(r->scal, SC_COUNT * 8) &&
-                    in(r->err, 12) && in(r->dscount, 8) && in(r->dsflag, ns * 4) && in(r->dslist, ns * 4) &&
-                    in(r->y, size_t(std::max(P.n_iface, 1)) * 8) && in(r->subdofs_d, ns * P.ndmax * 4) &&
-                    in(r->slots, size_t(std::max<int64_t>(P.slot_doubles, 1)) * 8) &&
-                    in(r->leafup, ns * sizeof(LeafUp)) &&
-                    (!r->f32 || (in(r->fac32, P.n_blocks * 4) && in(r->nfac32, P.n_blocks * 4) &&
-                                 in(r->dsE32, P.n_blocks * 4))) &&
-                    in(r->nd.lnodes, std::max<size_t>(P.lnodes.size(), 1) * sizeof(NodeDev)) &&
-                    (P.d.mpm_order != 1 || in(r->wbnd, ns * P.nb * 8));
-    if (!ok) return fail(MPM_EINVAL);
-  }
+  if (!bind_workspace(r, static_cast<char*>(dev_workspace))) return fail(MPM_EINVAL);
   CREATE_CHK(hipHostMalloc(reinterpret_cast<void**>(&r->pinned), 64, hipHostMallocDefault));
   CREATE_CHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&r->pinned_dev), r->pinned, 0));
   if (!r->pinned_dev) return fail(MPM_EHIP);
@@ -715,24 +752,7 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   }
   CREATE_CHK(hipStreamCreateWithFlags(&r->st2, hipStreamNonBlocking));
   CREATE_CHK(hipStreamSynchronize(r->ust));
-  // upload the plan's index tables
-  auto up = [&](size_t off, const void* src, size_t n) {
-    return n ? hipMemcpyAsync(r->ws + off, src, n, hipMemcpyHostToDevice, r->st) : hipSuccess;
-  };
-  if (up(P.off_nodes, P.nodes.data(), P.nodes.size() * sizeof(NodeDev)) ||
-      up(P.off_levels, P.level_flat.data(), P.level_flat.size() * 4) ||
-      up(P.off_lnodes, P.lnodes.data(), P.lnodes.size() * sizeof(NodeDev)) ||
-      up(P.off_leafup, P.leafup.data(), P.leafup.size() * sizeof(LeafUp)) ||
-      hipMemsetAsync(r->slots, 0, size_t(std::max<int64_t>(P.slot_doubles, 1)) * 8, r->st) ||
-      up(P.off_dofpool, P.dof_pool.data(), P.dof_pool.size() * 4) ||
-      up(P.off_mappool, P.map_pool.data(), P.map_pool.size() * 4) ||
-      up(P.off_invpool, P.inv_pool.data(), P.inv_pool.size() * 4) ||
-      up(P.off_subdofs, P.sub_dofs.data(), P.sub_dofs.size() * 4) ||
-      up(P.off_subndof, P.sub_ndof.data(), P.sub_ndof.size() * 4) ||
-      hipMemsetAsync(r->scal, 0, SC_COUNT * 8 + 64, r->st) ||
-      hipMemsetAsync(r->y, 0, size_t(std::max(P.n_iface, 1)) * 8, r->st) ||
-      hipStreamSynchronize(r->st))
-    return fail(MPM_EHIP);
+  if (upload_plan(r) != hipSuccess || hipStreamSynchronize(r->st) != hipSuccess) return fail(MPM_EHIP);
   *out = r;
   return MPM_OK;
 }
@@ -815,8 +835,14 @@ mpm_status mpm_advance(mpm_run* r, int32_t max_updates, int32_t stop_at_breakthr
     st = step(r, MPM_AUTO);
     if (st) break;
     ++n;
-    // the water cut reaches host memory with the epsilon sums of the same step
-    if (stop_at_breakthrough && r->pinned[3] >= r->P.d.breakthrough_cut) break;
+    // the water cut reaches host memory with the epsilon sums of the same step; a pass that
+    // took the MRCM branch has not waited for them yet (the wait ends at the conductivity
+    // kernel's reduction, ahead of the basis update)
+    if (stop_at_breakthrough) {
+      st = wait_eps(r);
+      if (st) break;
+      if (r->pinned[3] >= r->P.d.breakthrough_cut) break;
+    }
   }
   if (done) *done = n;
   return leave(r, st);
@@ -1147,11 +1173,15 @@ mpm_status mpm_batch_step(mpm_batch* b, const uint8_t* active, uint8_t* breakthr
   }
   for (Issued& is : issued) {
     mpm_status e = group_finish(is.updated, b->gs[is.gs]);
+    // the water cut of runs that took the MRCM branch: wait for the group's reduction too
+    if (!e && breakthrough && is.updated.size() != is.runs.size()) e = group_wait_eps(is.runs, b->gs[is.gs]);
     if (e) for (mpm_run* r : is.runs) note(r, e);
   }
   for (mpm_run* r : alone) {
     if (r->poisoned) continue;
-    note(r, leave(r, vu_finish(r)));
+    mpm_status e = vu_finish(r);
+    if (!e && breakthrough) e = wait_eps(r);
+    note(r, leave(r, e));
   }
   if (breakthrough)
     for (size_t i = 0; i < n; ++i) {
@@ -1283,9 +1313,7 @@ mpm_status mpm_get_stats(mpm_run* r, mpm_stats* out) {
   out->error_word = errw;
   if (errw) {
     r->poisoned = true;
-    if (errw & ERR_NOTSPD) return MPM_ENOTSPD;
-    if (errw & ERR_SINGULAR) return MPM_ESINGULAR;
-    return MPM_ENONFINITE;
+    return err_status(errw);
   }
   return MPM_OK;
 }
@@ -1310,10 +1338,7 @@ mpm_status mpm_destroy(mpm_run* r) {
   if (r->st && r->st != r->ust) hipStreamDestroy(r->st);
   if (r->pinned) hipHostFree(r->pinned);
   delete r;
-  if (errw & ERR_NOTSPD) return MPM_ENOTSPD;
-  if (errw & ERR_SINGULAR) return MPM_ESINGULAR;
-  if (errw) return MPM_ENONFINITE;
-  return MPM_OK;
+  return errw ? err_status(errw) : MPM_OK;
 }
 
 mpm_status mpm_plan_solve_bytes(const mpm_run* r, int64_t* fwd, int64_t* bwd, int64_t* front) {

@@ -19,6 +19,7 @@ struct Geo {
   int bc_pack;          // MPM_BC_* of side s in bits 2s..2s+1 (sides W, E, S, N)
   double bc_v0, bc_v1, bc_v2, bc_v3;
   double s_inj;
+  double refine_rtol;   // precision form: refinement stops at this correction / solution ratio
 };
 
 // p moved by o bytes (pointer arithmetic on bytes, so that the compiler keeps the address
@@ -38,8 +39,16 @@ __host__ __device__ __forceinline__ double bc_value_of(const Geo& g, int side) {
   return (side & 2) ? b : a;
 }
 
-// Error bits of the device error word.
-enum : int32_t { ERR_NOTSPD = 1, ERR_SINGULAR = 2, ERR_NONFINITE = 4 };
+// Error bits of the device error word. ERR_NOTSPD: a non-positive pivot of a local matrix,
+// or a permeability that is not positive; ERR_NONFINITE: a non-finite value in the state, a
+// saturation outside [0, 1] beyond rounding, or no flow through any cell (the time step of
+// the upwind scheme is then unbounded); ERR_NOCONV: an FP64 refinement of the precision form
+// did not reach its tolerance within its iteration limit.
+enum : int32_t { ERR_NOTSPD = 1, ERR_SINGULAR = 2, ERR_NONFINITE = 4, ERR_NOCONV = 8 };
+
+// Bounds of the saturation checked on the device: [0, 1] up to the rounding of the monotone
+// upwind update.
+constexpr double SAT_TOL = 1e-12;
 
 // ---------------------------------------------------------------- local cell ordering
 // Cells of a subdomain are numbered along the shorter side first so that the 5-point
@@ -260,6 +269,11 @@ __host__ __device__ __forceinline__ double harm_ratio(double knc, double knd, do
 }
 
 __device__ __forceinline__ void set_error(int32_t* err, int32_t bits) { atomicOr(err, bits); }
+// The device error word of a run sits right after its scalar block (the plan lays out the
+// scalars, then the integer words: error, changed-subdomain count, sequence number).
+__device__ __forceinline__ int32_t* err_word(double* scal) { return reinterpret_cast<int32_t*>(scal + SC_COUNT); }
+// Finite (false for NaN and for infinities).
+__device__ __forceinline__ bool finite_d(double v) { return fabs(v) <= 1.7976931348623157e308; }
 
 // Transport sub-step from the maximum outflow rate and the boundary inflow, reduced in a fixed
 // order from per-subdomain partials (run by one workgroup of 256 threads; each thread issues
@@ -269,6 +283,7 @@ __device__ __forceinline__ void reduce_dt(int nsub, const double* red_rate, cons
   constexpr int B = 16;
   const double cfl = scal[SC_CFL], fmax_deriv = scal[SC_FMAX];   // requested first
   double m = 0.0, s = 0.0;
+  int bad = 0;   // a non-finite partial (fmax would drop a NaN)
   for (int base = 0; base < nsub; base += 256 * B) {
     double vr[B], vq[B];
 #pragma unroll
@@ -283,12 +298,13 @@ __device__ __forceinline__ void reduce_dt(int nsub, const double* red_rate, cons
       if (base + int(threadIdx.x) + 256 * u < nsub) {
         m = fmax(m, vr[u]);
         s += vq[u];
+        bad |= !finite_d(vr[u]);
       }
     }
   }
   sm[threadIdx.x] = m;
   ss[threadIdx.x] = s;
-  __syncthreads();
+  bad = __syncthreads_or(bad);
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
       sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
@@ -297,9 +313,13 @@ __device__ __forceinline__ void reduce_dt(int nsub, const double* red_rate, cons
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    // no flow anywhere (rate 0) leaves the step unbounded: flagged, and the step set to 0 so
+    // that the saturation is left as it is rather than turned into NaN
+    const bool ok = !bad && sm[0] > 0.0 && finite_d(ss[0]);
     scal[SC_MAXRATE] = sm[0];
     scal[SC_QIN] = ss[0];
-    scal[SC_DT] = cfl / (fmax_deriv * sm[0]);
+    scal[SC_DT] = ok ? cfl / (fmax_deriv * sm[0]) : 0.0;
+    if (!ok) set_error(err_word(scal), ERR_NONFINITE);
   }
 }
 

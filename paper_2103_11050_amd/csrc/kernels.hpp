@@ -66,7 +66,7 @@ void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double*
 size_t line_factor_doubles(int nsub, int nc, int band);
 void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                       const double* uym, const double* q, const double* fac, double* h, double* vbnd,
-                      LeafOut lo, Runs rt = one_run());
+                      LeafOut lo, int32_t* err, Runs rt = one_run());
 // with_v: 0 u-hat only, 1 u-hat + v, 2 ubnd += u-hat + v (first-order term)
 void launch_flux(hipStream_t st, const Geo& g, const double* km, const double* S, const double* h,
                  const double* vbnd, const double* y, const int32_t* sub_dofs, double* ubnd, int with_v,
@@ -89,7 +89,7 @@ void launch_ds_factor_f32(hipStream_t st, const Geo& g, const double* kap_n, flo
                           const int32_t* count, int32_t* err, Runs rt = one_run());
 void launch_mpm_local_f32(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                           const double* uym, const double* q, const float* fac, double* h, double* vbnd,
-                          LeafOut lo, Runs rt = one_run());
+                          LeafOut lo, int32_t* err, Runs rt = one_run());
 void launch_downscale_f32(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,
                           double* ux, double* uy, double* red_rate, double* red_qin, float* Escr, float* Ekeep,
                           const int32_t* flag, int32_t* err, Runs rt = one_run());

@@ -226,16 +226,15 @@ __device__ __forceinline__ void line_residual(const Geo& g, const LineW& W, int 
   __syncthreads();
 }
 
-// Refinement budget of the precision form: corrections stop once the largest one is below
-// REFINE_RTOL times the largest solution entry (four orders below the 1e-6 bound of the
-// precision form), at most REFINE_MAXIT of them.
-constexpr double REFINE_RTOL = 1e-10;
+// Refinement budget of the precision form: corrections stop once the largest one is at most
+// g.refine_rtol times the largest solution entry, at most REFINE_MAXIT of them.
 constexpr int REFINE_MAXIT = 8;
 
 // x holds the right-hand side on entry and the solution on exit (LDS, local order); ws is LDS
-// scratch of 3 * nc doubles. One wavefront.
+// scratch of 3 * nc doubles. One wavefront. Returns whether the tolerance was reached (the
+// same value in every lane).
 template <int MF>
-__device__ __forceinline__ void lb_solve_refined(const Geo& g, const LineW& W, const LB<MF>& L,
+__device__ __forceinline__ bool lb_solve_refined(const Geo& g, const LineW& W, const LB<MF>& L,
                                                  const float (&E)[16][LB<MF>::EPL], double* x, double* ws) {
   const int nl = g.nc / g.band;
   double* b = ws;
@@ -244,6 +243,7 @@ __device__ __forceinline__ void lb_solve_refined(const Geo& g, const LineW& W, c
   for (int c = threadIdx.x; c < g.nc; c += blockDim.x) b[c] = x[c];
   __syncthreads();
   lb_apply_f32<MF>(W, L, nl, E, b, x);
+  bool conv = false;
 #pragma unroll 1
   for (int it = 0; it < REFINE_MAXIT; ++it) {
     line_residual(g, W, nl, b, x, r);
@@ -261,8 +261,12 @@ __device__ __forceinline__ void lb_solve_refined(const Geo& g, const LineW& W, c
       xm = fmax(xm, __shfl_xor(xm, o));
     }
     __syncthreads();
-    if (dm <= REFINE_RTOL * xm) break;
+    if (dm <= g.refine_rtol * xm) {
+      conv = true;
+      break;
+    }
   }
+  return conv;
 }
 
 }  // namespace
@@ -539,11 +543,12 @@ __global__ void __launch_bounds__(64)
 k_mpm_local_lb(Geo g0, const double* __restrict__ kap_n, const double* __restrict__ kap_m,
                const double* __restrict__ uxm, const double* __restrict__ uym, const double* __restrict__ q,
                const T* __restrict__ fac, double* __restrict__ hg, double* __restrict__ vbnd, LeafOut lo,
-               const RunTab* __restrict__ rt) {
+               int32_t* err, const RunTab* __restrict__ rt) {
   constexpr bool F32 = sizeof(T) == 4;
   const Geo g = fix_geo<FX>(g0);
   {
     const int64_t wo = ws_off(rt);
+    err = at_off(err, wo);
     kap_n = at_off(kap_n, wo);
     kap_m = at_off(kap_m, wo);
     uxm = at_off(uxm, wo);
@@ -603,7 +608,7 @@ k_mpm_local_lb(Geo g0, const double* __restrict__ kap_n, const double* __restric
   }
   if constexpr (F32) {
     const LineW W{tE, tN, dg, g.xfast, g.band, 0};
-    lb_solve_refined<MF>(g, W, L, Ef, x, xtra + 768);
+    if (!lb_solve_refined<MF>(g, W, L, Ef, x, xtra + 768) && L.lane == 0) set_error(err, ERR_NOCONV);
   } else {
     const LineW W{ty, ty, nullptr, g.xfast, g.band, 0};
     if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
@@ -882,7 +887,7 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
   __syncthreads();
   const LineW W{tE, tN, dg, g.xfast, g.band, 1};
   if constexpr (F32) {
-    lb_solve_refined<MF>(g, W, L, Ef, x, wsh);
+    if (!lb_solve_refined<MF>(g, W, L, Ef, x, wsh) && L.lane == 0) set_error(err, ERR_NOCONV);
   } else {
     if (store) {
       bool ok = true;
@@ -915,7 +920,9 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
     if (gi == g.nx - 1) ux[gj * (g.nx + 1) + gi + 1] = uE;
     if (gj == g.ny - 1) uy[(gj + 1) * g.nx + gi] = uN;
     const double out = g.hy * (fmax(uE, 0.0) + fmax(-uW, 0.0)) + g.hx * (fmax(uN, 0.0) + fmax(-uS, 0.0));
-    rate = fmax(rate, out / (g.hx * g.hy));
+    // a non-finite velocity makes the rate infinite (fmax alone would drop a NaN), which the
+    // time-step reduction reports
+    rate = finite_d(uW + uE + uS + uN) ? fmax(rate, out / (g.hx * g.hy)) : __builtin_inf();
   }
   double qin = 0.0;
   for (int f = threadIdx.x; f < nb; f += blockDim.x) {
@@ -1016,8 +1023,8 @@ void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double*
 
 void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                       const double* uym, const double* q, const double* fac, double* h, double* vbnd,
-                      LeafOut lo, Runs rt) {
-  MPM_LB_DISPATCH(k_mpm_local_lb, true, g, kn, km, uxm, uym, q, fac, h, vbnd, lo, rt.tab);
+                      LeafOut lo, int32_t* err, Runs rt) {
+  MPM_LB_DISPATCH(k_mpm_local_lb, true, g, kn, km, uxm, uym, q, fac, h, vbnd, lo, err, rt.tab);
 }
 
 void launch_mpm_first(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
@@ -1048,8 +1055,8 @@ void launch_ds_factor_f32(hipStream_t st, const Geo& g, const double* kap_n, flo
 
 void launch_mpm_local_f32(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
                           const double* uym, const double* q, const float* fac, double* h, double* vbnd,
-                          LeafOut lo, Runs rt) {
-  MPM_LB_DISPATCH_F32(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, lo, rt.tab);
+                          LeafOut lo, int32_t* err, Runs rt) {
+  MPM_LB_DISPATCH_F32(k_mpm_local_lb, g, kn, km, uxm, uym, q, fac, h, vbnd, lo, err, rt.tab);
 }
 
 void launch_downscale_f32(hipStream_t st, const Geo& g, const double* kap_s, const double* q, const double* ubnd,

@@ -69,8 +69,13 @@ k_kappa(Geo g, const double* __restrict__ s, double* __restrict__ s_new, const d
       wq = out;
       ww = out * frac_w(sv, scal[SC_MRATIO]);
     }
+    const double Kc = K[gc];
+    // the state the method needs: s in [0, 1] up to rounding, K finite and positive (NaN
+    // fails every comparison)
+    if (!(sv >= -SAT_TOL && sv <= 1.0 + SAT_TOL) || !finite_d(Kc)) set_error(err_word(scal), ERR_NONFINITE);
+    else if (!(Kc > 0.0)) set_error(err_word(scal), ERR_NOTSPD);
     const double lam = sv * sv / mu_w + (1.0 - sv) * (1.0 - sv) / mu_o;
-    const double kn = lam * K[gc];
+    const double kn = lam * Kc;
     kap_n[gc] = kn;
     const double km = kap_m[gc];
     const double dd = kn - km;
@@ -182,6 +187,8 @@ __global__ void __launch_bounds__(256) k_reduce_eps(int nblocks, int wc, const d
     scal[SC_EPS_NUM] = sa[0];
     scal[SC_EPS_DEN] = sb[0];
     if (wc) scal[SC_WCUT] = sq[0] > 0.0 ? sw[0] / sq[0] : 0.0;
+    if (!finite_d(sa[0]) || !finite_d(sb[0]) || (wc && !(finite_d(sq[0]) && finite_d(sw[0]))))
+      set_error(err_word(scal), ERR_NONFINITE);
     const int32_t n = *seq + 1;
     *seq = n;
     host[0] = sa[0];

@@ -64,6 +64,8 @@ mpm_status validate(const mpm_desc& d, std::string* why) {
   if (d.iface_degree != 0 && d.iface_degree != 1) return bad("iface_degree must be 0 or 1");
   if (d.iface_degree == 1 && (d.sub_x / d.ne_x < 2 || d.sub_y / d.ne_y < 2))
     return bad("linear interface spaces need at least two fine faces per interface element");
+  if (d.precision == MPM_PREC_FP32_REFINE && !(d.refine_rtol > 0 && d.refine_rtol <= 1e-2))
+    return bad("refine_rtol must lie in (0, 1e-2] for the precision form");
   if (d.precision == MPM_PREC_FP32_REFINE && nc / band > 16)
     return bad("the precision form takes at most 16 lines per subdomain");
   if (2 * (d.iface_degree + 1) * (2 * d.ne_x + 2 * d.ne_y) > 128)

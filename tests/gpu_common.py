@@ -6,6 +6,7 @@ from oracle import physics, splitting
 
 FP64_VEL_TOL = 1e-10     # relative L2 velocity error, FP64 path
 FP64_SAT_TOL = 1e-9      # relative L1 saturation error, FP64 path
+FP64_FACE_TOL = 1e-10    # largest face error over the largest face velocity, FP64 path
 
 
 def vel_norm2(cfg, ux, uy):
@@ -17,6 +18,12 @@ def vel_norm2(cfg, ux, uy):
 
 def vel_rel_err(cfg, ux, uy, rx, ry):
     return float(np.sqrt(vel_norm2(cfg, ux - rx, uy - ry) / vel_norm2(cfg, rx, ry)))
+
+
+def vel_face_err(ux, uy, rx, ry):
+    """Face by face: the largest error of a normal flux over the largest normal flux."""
+    scale = max(float(np.abs(rx).max()), float(np.abs(ry).max()), 1e-300)
+    return max(float(np.abs(ux - rx).max()), float(np.abs(uy - ry).max())) / scale
 
 
 def sat_rel_err(s, r):

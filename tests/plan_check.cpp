@@ -2,6 +2,7 @@
 // extend-add maps and the workspace layout) for a set of decompositions; built and run by
 // tests/test_plan.py. Prints one line per decomposition: "ok ..." or the first failed check.
 #include <algorithm>
+#include <cstddef>
 #include <cstdio>
 #include <string>
 #include <utility>
@@ -111,6 +112,9 @@ std::string check(const mpm_desc& d) {
 }  // namespace
 
 int main() {
+  // the descriptor's layout as the C compiler sees it (the Python binding mirrors it)
+  std::printf("desc %zu %zu %zu %zu\n", sizeof(mpm_desc), offsetof(mpm_desc, bc_value), offsetof(mpm_desc, iface_degree),
+              offsetof(mpm_desc, refine_rtol));
   // nx, ny, sub_x, sub_y, ne_x, ne_y, iface_degree
   const int shapes[][7] = {{32, 32, 8, 8, 2, 2, 0},    {32, 32, 8, 8, 2, 2, 1},   {12, 8, 4, 4, 2, 1, 0},
                            {30, 20, 10, 10, 5, 2, 0},  {30, 20, 10, 10, 1, 5, 1}, {48, 8, 8, 8, 1, 4, 0},

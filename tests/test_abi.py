@@ -29,7 +29,7 @@ def test_exports_every_header_symbol(lib):
 
 
 def test_status_strings(lib):
-    for code in range(0, -8, -1):
+    for code in range(0, -9, -1):
         s = lib.mpm_status_str(code).decode()
         assert s and s != "unknown status"
     assert lib.mpm_status_str(-99).decode() == "unknown status"
@@ -116,6 +116,16 @@ def test_linear_interface_spaces(lib):
     # unknowns, the bound, which the other limits keep linear spaces within
     many = inputs.config("c1", nx=48, ny=16, sub_x=24, sub_y=8, ne_x=12, ne_y=4, iface_degree=1)
     assert _size(many)[0] == 0
+
+
+@pytest.mark.parametrize("rtol,ok", [(1e-10, True), (1e-2, True), (0.0, False), (-1e-8, False), (0.5, False),
+                                     (float("nan"), False)])
+def test_refinement_tolerance(lib, rtol, ok):
+    """The precision form takes its refinement target from the descriptor; FP64 runs ignore it."""
+    st, _ = _size(inputs.config("c1"), precision=binding.PREC_FP32_REFINE, refine_rtol=rtol)
+    assert (st == 0) == ok
+    st64, _ = _size(inputs.config("c1"), refine_rtol=rtol)
+    assert st64 == 0
 
 
 def test_eta_infinity_accepted(lib):

@@ -12,7 +12,7 @@ from oracle import downscale as odown
 from oracle import fine, mpm as ompm, mrcm as omrcm, physics, splitting
 from paper_2103_11050_amd import inputs
 
-from .gpu_common import FP64_SAT_TOL, FP64_VEL_TOL, sat_rel_err, to_np, vel_rel_err
+from .gpu_common import FP64_FACE_TOL, FP64_SAT_TOL, FP64_VEL_TOL, sat_rel_err, to_np, vel_face_err, vel_rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -71,6 +71,7 @@ def test_mrcm_velocity_matches_oracle(binding, shape):
     err = vel_rel_err(cfg, to_np(ux), to_np(uy), rx, ry)
     print(f"    rel L2 velocity error {err:.3e}", flush=True)
     assert err <= FP64_VEL_TOL
+    assert vel_face_err(to_np(ux), to_np(uy), rx, ry) <= FP64_FACE_TOL
     r.close()
 
 
@@ -115,6 +116,9 @@ def _compare_runs(binding, cfg, K, nsteps, label, forced=None, vel_tol=FP64_VEL_
         errs.append(e)
         worst_s = max(worst_s, es)
         assert e <= vel_tol, (n, e)
+        # face by face, at the same bound relative to the largest face velocity
+        ef = vel_face_err(to_np(ux), to_np(uy), orun.ux, orun.uy)
+        assert ef <= vel_tol, (n, ef)
         assert es <= sat_tol, (n, es)
         assert math.isclose(st["eps"], orun.eps, rel_tol=1e-8, abs_tol=1e-14), (n, st["eps"], orun.eps)
         assert math.isclose(st["pvi"], orun.pvi, rel_tol=1e-10), (n, st["pvi"], orun.pvi)

@@ -23,3 +23,11 @@ def test_plan_consistency(tmp_path):
     print(out.stdout)
     assert out.returncode == 0, out.stdout + out.stderr
     assert out.stdout.count(": ok") == 12
+    # the ctypes descriptor of the binding has the C layout
+    import ctypes
+
+    from paper_2103_11050_amd import binding
+    line = [l for l in out.stdout.splitlines() if l.startswith("desc ")][0].split()
+    D = binding.Desc
+    assert [int(x) for x in line[1:]] == [ctypes.sizeof(D), D.bc_value.offset, D.iface_degree.offset,
+                                          D.refine_rtol.offset]
