@@ -134,6 +134,26 @@ mpm_status mpm_workspace_size(const mpm_desc* desc, size_t* bytes);
 mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, void* hip_stream,
                       mpm_run** out);
 
+/* Size of the device array behind mpm_create_static (64 MiB: grids up to 256^2 cells with 16^2-cell
+ * subdomains and 4 elements per side). */
+#define MPM_STATIC_WORKSPACE_BYTES (64u << 20)
+
+/* mpm_create for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the run's workspace is a file-scope device
+ * array of MPM_STATIC_WORKSPACE_BYTES held by the library on every device it runs on until the
+ * process ends, instead of a caller buffer. The call allocates nothing: no hipMalloc, hipFree,
+ * hipHostMalloc, stream or event; all of the run's work goes on hip_stream (the epsilon and
+ * water-cut readback is a copy to host memory on that stream). Every later call on the run is as
+ * for mpm_create, except that the run cannot join a batch (mpm_batch_attach returns MPM_ESTATE).
+ * The array keeps the contents of the last run that used it; the library clears what its
+ * kernels expect at zero. One such run per device at a time: while one is alive (until its
+ * mpm_destroy) another mpm_create_static on the same device returns MPM_ESTATE; two threads
+ * using one run race, as for any run.
+ * Errors: MPM_EINVAL for a bad descriptor; MPM_ENOMEM (mpm_last_error(NULL) gives the sizes) if
+ * the run needs more than MPM_STATIC_WORKSPACE_BYTES (mpm_workspace_size plus 256 bytes, rounded
+ * to 256); MPM_EHIP if the array's device address cannot be obtained. */
+mpm_status mpm_create_static(const mpm_desc* desc, void* hip_stream, mpm_run** out);
+
 /* Copies the permeability K (> 0), the source q (may be NULL: q = 0) and the initial
  * saturation s0 (in [0,1]) into the workspace. Device pointers, row-major [ny][nx]. */
 mpm_status mpm_set_fields(mpm_run* run, const double* dev_K, const double* dev_q, const double* dev_s0);

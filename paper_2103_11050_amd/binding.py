@@ -58,6 +58,7 @@ _SIGS = {
     "mpm_workspace_size": (ctypes.c_int32, [ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_size_t)]),
     "mpm_create": (ctypes.c_int32, [ctypes.POINTER(Desc), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                     ctypes.POINTER(ctypes.c_void_p)]),
+    "mpm_create_static": (ctypes.c_int32, [ctypes.POINTER(Desc), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "mpm_set_fields": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "mpm_start": (ctypes.c_int32, [ctypes.c_void_p]),
     "mpm_transport": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
@@ -161,7 +162,9 @@ def _ptr(t) -> int:
 class Run:
     """One MPM-2P run on the current device (thin wrapper of mpm_run)."""
 
-    def __init__(self, cfg: dict, K, s0, q=None, precision: int = PREC_FP64, stream=None):
+    def __init__(self, cfg: dict, K, s0, q=None, precision: int = PREC_FP64, stream=None, static=False):
+        """static: the workspace is the library's own device array (mpm_create_static) instead
+        of a tensor allocated here."""
         import torch
         lib = load()
         self.cfg = cfg
@@ -170,17 +173,21 @@ class Run:
         n = ctypes.c_size_t()
         _check(lib.mpm_workspace_size(ctypes.byref(self.desc), ctypes.byref(n)), "mpm_workspace_size")
         self.ws_bytes = n.value
-        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.ws.data_ptr()
-        aligned = (base + 255) & ~255
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        st = lib.mpm_create(ctypes.byref(self.desc), ctypes.c_void_p(aligned), ctypes.c_size_t(self.ws_bytes),
-                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if static:
+            self.ws = None
+            st = lib.mpm_create_static(ctypes.byref(self.desc), ctypes.c_void_p(self.stream.cuda_stream),
+                                       ctypes.byref(h))
+        else:
+            self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            aligned = (self.ws.data_ptr() + 255) & ~255
+            st = lib.mpm_create(ctypes.byref(self.desc), ctypes.c_void_p(aligned), ctypes.c_size_t(self.ws_bytes),
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if st != MPM_OK:
             buf = ctypes.create_string_buffer(512)
             lib.mpm_last_error(None, buf, 512)
-            _check(st, "mpm_create (" + buf.value.decode() + ")")
+            _check(st, ("mpm_create_static" if static else "mpm_create") + " (" + buf.value.decode() + ")")
         self.h = h
         self._keep = (K, s0, q)
         # the inputs were written on the caller's current stream

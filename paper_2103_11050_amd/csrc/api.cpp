@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -101,6 +102,10 @@ struct mpm_run {
   int last_branch = MPM_FORCE_MRCM;
   double* pinned = nullptr;    // [eps_num, eps_den, sequence, water cut], written by kernels
   double* pinned_dev = nullptr;  // the same memory as the device sees it
+  // a run on the static workspace (mpm_create_static): no stream, event or pinned memory of its
+  // own; the kernels write the block above into the workspace and it is copied to pin_host
+  bool is_static = false;
+  double pin_host[4] = {};
   int64_t eps_seq = 0;           // sequence number of the latest kappa launch
   hipEvent_t ev_eps = nullptr;
   // profiling with HIP events on the run's stream
@@ -226,8 +231,16 @@ mpm_status kappa_and_eps_nodes(mpm_run* r, bool sat = false, bool fork = false) 
 // to pinned host memory with its sequence number; after the event, a number other than the
 // expected one means the data has not reached the host yet: drain the stream and look again.
 mpm_status wait_eps(mpm_run* r) {
-  HIPCHK(r, hipEventSynchronize(r->ev_eps));
   volatile double* p = r->pinned;
+  if (r->is_static) {   // the copy to pageable host memory has returned, or is drained here
+    if (p[2] != double(r->eps_seq)) HIPCHK(r, hipStreamSynchronize(r->st));
+    if (p[2] != double(r->eps_seq)) {
+      r->last_error = "epsilon sums did not reach host memory";
+      return MPM_EHIP;
+    }
+    return MPM_OK;
+  }
+  HIPCHK(r, hipEventSynchronize(r->ev_eps));
   if (p[2] != double(r->eps_seq)) {
     HIPCHK(r, hipStreamSynchronize(r->st));
     HIPCHK(r, hipStreamSynchronize(r->st2));
@@ -242,9 +255,13 @@ mpm_status wait_eps(mpm_run* r) {
 // Eager: the reduction forks to the second stream unless graphs are in use (a captured update
 // would not join it).
 mpm_status kappa_and_eps(mpm_run* r, bool sat = false) {
-  const bool fork = !r->use_graphs;
+  const bool fork = !r->use_graphs && r->st2 != r->st;
   mpm_status st = kappa_and_eps_nodes(r, sat, fork);
   if (st) return st;
+  if (r->is_static) {
+    HIPCHK(r, hipMemcpyAsync(r->pin_host, r->pinned_dev, sizeof(r->pin_host), hipMemcpyDeviceToHost, r->st));
+    return MPM_OK;
+  }
   HIPCHK(r, hipEventRecord(r->ev_eps, fork ? r->st2 : r->st));
   return MPM_OK;
 }
@@ -412,15 +429,17 @@ mpm_status mpm_update_body(mpm_run* r, bool capturing, Runs rt = one_run()) {
   // the local and interface solves. It forks at the epsilon event, recorded right after the
   // conductivity and its changed-subdomain list (one marker on the main stream, not two).
   // (Under graph capture the fork must be recorded inside the capture: a marker of its own.)
-  if (capturing) {
+  // (A run with one stream, the static workspace's, takes them in stream order.)
+  const bool two = r->st2 != r->st;
+  if (two && capturing) {
     HIPCHK(r, hipEventRecord(r->ev_fork, r->st));
     HIPCHK(r, hipStreamWaitEvent(r->st2, r->ev_fork, 0));
-  } else {
+  } else if (two) {
     HIPCHK(r, hipStreamWaitEvent(r->st2, r->ev_eps, 0));
   }
   if (r->f32) launch_ds_factor_f32(r->st2, r->g, r->kn, r->dsE32, r->dslist, r->dscount, r->err, rt);
   else launch_ds_factor(r->st2, r->g, r->kn, r->dsE, r->dslist, r->dscount, r->err, rt);
-  HIPCHK(r, hipEventRecord(r->ev_join, r->st2));
+  if (two) HIPCHK(r, hipEventRecord(r->ev_join, r->st2));
   {
     Scope sc(r, "mpm_local");
     if (r->f32)
@@ -431,7 +450,7 @@ mpm_status mpm_update_body(mpm_run* r, bool capturing, Runs rt = one_run()) {
                        rt);
   }
   nd_solve(r, rt);
-  HIPCHK(r, hipStreamWaitEvent(r->st, r->ev_join, 0));
+  if (two) HIPCHK(r, hipStreamWaitEvent(r->st, r->ev_join, 0));
   finish_velocity(r, r->kn, 1, 0, rt);
   return MPM_OK;
 }
@@ -665,6 +684,26 @@ hipError_t upload_plan(mpm_run* r) {
   return e;
 }
 
+// Workspace of the runs made by mpm_create_static: a file-scope device array, one copy on every
+// device the library runs on, held until the process ends. Its name in host code is a host-side
+// stand-in; the device address comes from hipGetSymbolAddress, once per device, with that
+// device current, and only that address is handed to kernels and copies.
+static __device__ __align__(256) char scratch[MPM_STATIC_WORKSPACE_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+char* g_static_ptr[kMaxDevices] = {};   // device address of scratch on each device
+bool g_static_busy[kMaxDevices] = {};   // a live run holds the device's array
+
+// Bytes a run takes from the static array: the plan's workspace, then 256 bytes for the
+// epsilon and water-cut block that the reduction kernel writes.
+size_t static_bytes(const Plan& P) { return ((P.total_bytes + 255) & ~size_t(255)) + 256; }
+
+void release_static(int device) {
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (device >= 0 && device < kMaxDevices) g_static_busy[device] = false;
+}
+
 }  // namespace
 
 extern "C" {
@@ -753,6 +792,69 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   CREATE_CHK(hipStreamCreateWithFlags(&r->st2, hipStreamNonBlocking));
   CREATE_CHK(hipStreamSynchronize(r->ust));
   if (upload_plan(r) != hipSuccess || hipStreamSynchronize(r->st) != hipSuccess) return fail(MPM_EHIP);
+  *out = r;
+  return MPM_OK;
+}
+
+mpm_status mpm_create_static(const mpm_desc* desc, void* hip_stream, mpm_run** out) {
+  if (!desc || !out) return MPM_EINVAL;
+  *out = nullptr;
+  if (validate(*desc, nullptr) != MPM_OK) return MPM_EINVAL;
+  mpm_run* r = new (std::nothrow) mpm_run();
+  if (!r) return MPM_ENOMEM;
+  build_plan(*desc, &r->P);
+  const size_t need = static_bytes(r->P);
+  if (need > size_t(MPM_STATIC_WORKSPACE_BYTES)) {
+    g_create_error = "the run needs " + std::to_string(need) + " bytes of workspace; the static array holds " +
+                     std::to_string(size_t(MPM_STATIC_WORKSPACE_BYTES));
+    delete r;
+    return MPM_ENOMEM;
+  }
+  if (hipGetDevice(&r->device) != hipSuccess || r->device < 0 || r->device >= kMaxDevices) {
+    g_create_error = "no current device";
+    delete r;
+    return MPM_EHIP;
+  }
+  char* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_busy[r->device]) {
+      g_create_error = "the static workspace of this device is held by another run";
+      delete r;
+      return MPM_ESTATE;
+    }
+    if (!g_static_ptr[r->device]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) {
+        g_create_error = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
+        delete r;
+        return MPM_EHIP;
+      }
+      g_static_ptr[r->device] = static_cast<char*>(p);
+    }
+    ws = g_static_ptr[r->device];
+    g_static_busy[r->device] = true;
+  }
+  const int device = r->device;
+  auto fail = [&](mpm_status s, const char* what, hipError_t e) {
+    g_create_error = std::string(what) + ": " + hipGetErrorString(e);
+    delete r;
+    release_static(device);
+    return s;
+  };
+  r->is_static = true;
+  r->use_graphs = false;
+  r->ust = static_cast<hipStream_t>(hip_stream);
+  r->st = r->st2 = r->ust;   // one stream: the caller's
+  if (!bind_workspace(r, ws)) return fail(MPM_EINVAL, "workspace layout does not fit", hipErrorInvalidValue);
+  r->pinned = r->pin_host;
+  r->pinned_dev = reinterpret_cast<double*>(ws + static_bytes(r->P) - 256);
+  hipError_t e = hipMemsetAsync(r->pinned_dev, 0, 256, r->st);
+  if (e != hipSuccess) return fail(MPM_EHIP, "hipMemsetAsync", e);
+  e = upload_plan(r);
+  if (e == hipSuccess) e = hipStreamSynchronize(r->st);
+  if (e != hipSuccess) return fail(MPM_EHIP, "plan upload", e);
   *out = r;
   return MPM_OK;
 }
@@ -1083,7 +1185,7 @@ mpm_status mpm_batch_create(int32_t capacity, mpm_batch** out) {
 mpm_status mpm_batch_attach(mpm_batch* b, int32_t slot, mpm_run* r) {
   if (!b || !r || slot < 0 || slot >= int32_t(b->slot.size())) return MPM_EINVAL;
   if (b->slot[slot] || r->owner) return MPM_ESTATE;
-  if (!r->fields || r->poisoned) return MPM_ESTATE;
+  if (!r->fields || r->poisoned || r->is_static) return MPM_ESTATE;
   b->slot[slot] = r;
   r->owner = b;
   r->owner_slot = slot;
@@ -1334,10 +1436,13 @@ mpm_status mpm_destroy(mpm_run* r) {
   if (r->ev_eps) hipEventDestroy(r->ev_eps);
   if (r->ev_fork) hipEventDestroy(r->ev_fork);
   if (r->ev_join) hipEventDestroy(r->ev_join);
-  if (r->st2) { hipStreamSynchronize(r->st2); hipStreamDestroy(r->st2); }
+  if (r->st2 && r->st2 != r->ust) { hipStreamSynchronize(r->st2); hipStreamDestroy(r->st2); }
   if (r->st && r->st != r->ust) hipStreamDestroy(r->st);
-  if (r->pinned) hipHostFree(r->pinned);
+  if (r->pinned && !r->is_static) hipHostFree(r->pinned);
+  const bool was_static = r->is_static;
+  const int device = r->device;
   delete r;
+  if (was_static) release_static(device);
   return errw ? err_status(errw) : MPM_OK;
 }
 

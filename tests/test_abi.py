@@ -172,3 +172,19 @@ def test_advance_and_last_error_arguments(lib):
     assert lib.mpm_last_error(None, None, 8) == binding.MPM_EINVAL
     assert lib.mpm_last_error(None, buf, 0) == binding.MPM_EINVAL
     assert lib.mpm_last_error(None, buf, 8) == binding.MPM_OK      # no run: the last create failure
+
+
+def test_static_workspace_size_limit(lib):
+    """mpm_create_static refuses, before any device call, a run that needs more than the static
+    array (a 512^2 grid), and a bad descriptor."""
+    cfg = inputs.config("c2", nx=512, ny=512)
+    d = binding.make_desc(cfg)
+    h = ctypes.c_void_p()
+    assert lib.mpm_create_static(ctypes.byref(d), None, ctypes.byref(h)) == binding.MPM_ENOMEM
+    assert not h.value
+    buf = ctypes.create_string_buffer(256)
+    lib.mpm_last_error(None, buf, 256)
+    assert b"static array" in buf.value
+    d.cn = 0
+    assert lib.mpm_create_static(ctypes.byref(d), None, ctypes.byref(h)) == binding.MPM_EINVAL
+    assert lib.mpm_create_static(None, None, ctypes.byref(h)) == binding.MPM_EINVAL
