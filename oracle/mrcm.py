@@ -304,6 +304,19 @@ class MRCMSolution:
     rhs: np.ndarray            # interface right-hand side
 
 
+def interface_solve(basis: MRCMBasis, rhs):
+    """The solution of the interface system (eq:mrc2) to working precision: the sparse LU solve,
+    then two steps of iterative refinement with the residual of the assembled matrix in FP64,
+    y <- y + LU^-1 (rhs - M y). (With high-contrast conductivity the system is ill-conditioned:
+    on the 129,024 unknowns of the 1024^2 workload the LU solve alone leaves a relative residual
+    of ~2e-11 and errors up to ~2e-9 of the largest unknown; after one step the residual is ~1e-12
+    and the next correction ~3e-13.)"""
+    y = basis.lu.solve(rhs)
+    for _ in range(2):
+        y = y + basis.lu.solve(rhs - basis.M @ y)
+    return y
+
+
 def solve_with_basis(basis: MRCMBasis, phys_of, q_of) -> MRCMSolution:
     """Solve the non-homogeneous local problems, the interface system with the stored
     factorisation, and reconstruct every local solution (Section 3, last paragraph).
@@ -320,7 +333,7 @@ def solve_with_basis(basis: MRCMBasis, phys_of, q_of) -> MRCMSolution:
         r, _, v = interface_rows(dec, lb, [o[None, :] for o in out0], np.zeros(1, dtype=int))
         for rr, vv in zip(r, v):
             np.add.at(c, rr, vv)
-    y = basis.lu.solve(-c) if nd else np.zeros(0)
+    y = interface_solve(basis, -c) if nd else np.zeros(0)
     ps, uxs, uys, outs = [], [], [], []
     for lb, (p0, ux0, uy0, out0) in zip(basis.locals, nh):
         coef = y[lb.dofs]
