@@ -186,16 +186,16 @@ def cpu_baseline(cfg: dict, K: np.ndarray, steps: int = 40) -> dict:
                       f"cell ratio {scale:.4f}; host: {host_cpu()}, {os.cpu_count()} logical CPUs"}
 
 
-def precision_form(binding, cfg, Kt, st, steps: int, warmup: int) -> dict:
+def precision_form(binding, cfg, Kt, st, steps: int, warmup: int, rtols=(1e-6, 1e-10)) -> dict:
     """The precision form (FP32 inverse blocks in the MPM-2P local solves and downscaling, FP64
-    refinement, FP64 interface solve and switch criterion) beside the FP64 path on the same
-    workload: its rate over `steps` steps and its velocity difference from the FP64 path after
-    the same steps from the same start."""
+    refinement to refine_rtol, FP64 interface solve and switch criterion) beside the FP64 path on
+    the same workload: its rate over `steps` steps and its velocity difference from the FP64
+    path after the same steps from the same start, for each refinement target (the first is the
+    headline one)."""
     import torch
 
-    runs = {}
-    for name, prec in (("fp64", binding.PREC_FP64), ("fp32", binding.PREC_FP32_REFINE)):
-        r = binding.Run(cfg, Kt, st, precision=prec)
+    def timed(c, prec):
+        r = binding.Run(c, Kt, st, precision=prec)
         r.start()
         for _ in range(warmup):
             r.step()
@@ -204,21 +204,29 @@ def precision_form(binding, cfg, Kt, st, steps: int, warmup: int) -> dict:
         for _ in range(steps):
             r.step()
         torch.cuda.synchronize()
-        runs[name] = (r, steps / (time.perf_counter() - t0))
-    (r64, v64), (r32, v32) = runs["fp64"], runs["fp32"]
-    ux64, uy64 = (t.cpu().numpy() for t in r64.velocity())
-    ux32, uy32 = (t.cpu().numpy() for t in r32.velocity())
+        return r, steps / (time.perf_counter() - t0)
+
     def rt0(ux, uy):   # velocity norm of the lowest-order mixed space with the trapezoidal rule
         return np.sum(ux[:, :-1] ** 2) + np.sum(ux[:, 1:] ** 2) + np.sum(uy[:-1, :] ** 2) + np.sum(uy[1:, :] ** 2)
 
-    num = rt0(ux32 - ux64, uy32 - uy64)
-    den = rt0(ux64, uy64)
-    b64, b32 = r64.stats()["last_branch"], r32.stats()["last_branch"]
+    r64, v64 = timed(cfg, binding.PREC_FP64)
+    ux64, uy64 = (t.cpu().numpy() for t in r64.velocity())
+    b64 = r64.stats()["last_branch"]
     r64.close()
-    r32.close()
-    return {"value": round(v32, 2), "fp64_value_same_window": round(v64, 2), "steps": steps,
-            "vel_rel_l2_vs_fp64": float(np.sqrt(num / den)), "same_branches": bool(b64 == b32),
-            "note": "FP32 blocks applied in FP32, FP64 iterative refinement of every local solve"}
+    by = {}
+    for rt in rtols:
+        r32, v32 = timed(dict(cfg, refine_rtol=rt), binding.PREC_FP32_REFINE)
+        ux32, uy32 = (t.cpu().numpy() for t in r32.velocity())
+        s32 = r32.stats()
+        r32.close()
+        by[f"{rt:g}"] = {"value": round(v32, 2), "vel_rel_l2_vs_fp64": float(np.sqrt(rt0(ux32 - ux64, uy32 - uy64) /
+                                                                                    rt0(ux64, uy64))),
+                         "same_branches": bool(s32["last_branch"] == b64), "error_word": int(s32["error_word"])}
+    head = by[f"{rtols[0]:g}"]
+    return {"value": head["value"], "refine_rtol": rtols[0], "fp64_value_same_window": round(v64, 2),
+            "steps": steps, "vel_rel_l2_vs_fp64": head["vel_rel_l2_vs_fp64"], "same_branches": head["same_branches"],
+            "by_refine_rtol": by,
+            "note": "FP32 blocks applied in FP32, FP64 iterative refinement of every local solve to refine_rtol"}
 
 
 def _side_by_side(binding, cfg, Kt, st, steps: int, warmup: int, over: dict):
@@ -283,6 +291,38 @@ def linear_space_form(binding, cfg, Kt, st, steps: int, warmup: int) -> dict:
             "note": "k_U = k_P = 2 per interface element; the interface system has twice the unknowns"}
 
 
+def serving_form(binding, inputs, n_requests: int, refine_rtol: float) -> dict:
+    """The serving form on a short request stream: grids drawn from 128^2, 256^2, 512^2 (16^2
+    subdomains, 4 elements per side), log-variance in [1, 4], M in [10, 100], each request run to
+    breakthrough, 16 slots. FP64: the capacity (all requests at t = 0), then Poisson arrivals at
+    70 % of it with p50/p99 latency. The precision form (FP32 blocks refined to refine_rtol) on the
+    same requests, capacity and the same arrival stream; its accuracy is the relative RT0
+    difference of each request's final velocity from the FP64 one (largest over the requests)."""
+    from paper_2103_11050_amd import serve
+
+    reqs = inputs.serve_requests(n_requests, (128, 256, 512))
+    reqs32 = [dict(c, refine_rtol=refine_rtol) for c in reqs]
+    budget = 200 << 30
+    s64, s32 = [], []
+    f64 = serve.serve_measure(reqs, 16, budget, 100000, 0.0, binding.PREC_FP64, states=s64)
+    f32 = serve.serve_measure(reqs32, 16, budget, 100000, f64["rate_per_s"], binding.PREC_FP32_REFINE,
+                              measure_capacity=True, states=s32)
+
+    def rt0(ux, uy):
+        return np.sum(ux[:, :-1] ** 2) + np.sum(ux[:, 1:] ** 2) + np.sum(uy[:-1, :] ** 2) + np.sum(uy[1:, :] ** 2)
+
+    diffs = [float(np.sqrt(rt0(a[0] - b[0], a[1] - b[1]) / rt0(a[0], a[1]))) for a, b in zip(s64, s32)]
+    same = sum(1 for a, b in zip(s64, s32) if a[3] == b[3])
+    keys = ("runs_per_s", "velocity_updates_per_s", "latency_p50_s", "latency_p99_s", "mean_runs_per_batch_step")
+    return {"requests": n_requests, "rate_per_s": f64["rate_per_s"],
+            "fp64": {**{k: f64[k] for k in keys}, "capacity": f64["capacity_measured"]},
+            "precision_form": {**{k: f32[k] for k in keys}, "capacity": f32["capacity_measured"],
+                               "refine_rtol": refine_rtol, "vel_rel_l2_vs_fp64_max": max(diffs),
+                               "requests_same_pass_count": same},
+            "note": "latency from arrival to breakthrough; capacity with every request present at t = 0; "
+                    "requests' fields made before the first arrival"}
+
+
 def long_window(binding, cfg, Kt, st, updates: int) -> dict:
     """Algorithm 1 over a long window from s = 0 (MRCM updates wherever the switch asks for
     them): the whole-job rate with the basis updates inside the timed region."""
@@ -319,6 +359,10 @@ def main():
     ap.add_argument("--no-precision-form", action="store_true",  # also skips the other side forms
                     help="skip the side-by-side run of the FP32-block precision form")
     ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--serve-requests", type=int, default=32,
+                    help="requests of the served-form figures (p50/p99 run latency; 0: skip)")
+    ap.add_argument("--refine-rtol", type=float, default=1e-6,
+                    help="refinement target of the precision form (its velocity bound is 1e-6)")
     ap.add_argument("--long-window", type=int, default=6000,
                     help="velocity updates of the long-window figure (0: skip)")
     ap.add_argument("--make-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -436,12 +480,17 @@ def main():
     }
     run.close()
     if args.precision == "fp64" and not args.no_precision_form:
-        out["precision_form"] = precision_form(binding, cfg, Kt, st, min(args.steps, 100), args.warmup)
+        out["precision_form"] = precision_form(binding, cfg, Kt, st, min(args.steps, 100), args.warmup,
+                                               (args.refine_rtol, 1e-10))
     if args.precision == "fp64" and not args.no_precision_form:
         out["first_order_form"] = first_order_form(binding, cfg, Kt, st, min(args.steps, 100), args.warmup)
         out["linear_space_form"] = linear_space_form(binding, cfg, Kt, st, min(args.steps, 100), args.warmup)
     if args.long_window > 0 and args.precision == "fp64":
         out["long_window"] = long_window(binding, cfg, Kt, st, args.long_window)
+    if args.serve_requests > 0:
+        out["serving"] = serving_form(binding, inputs, args.serve_requests, args.refine_rtol)
+        out["config"]["run_latency_s_p50"] = out["serving"]["fp64"]["latency_p50_s"]
+        out["config"]["run_latency_s_p99"] = out["serving"]["fp64"]["latency_p99_s"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, K)
     print(json.dumps(out))

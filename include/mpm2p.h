@@ -154,8 +154,12 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
  * to 256); MPM_EHIP if the array's device address cannot be obtained. */
 mpm_status mpm_create_static(const mpm_desc* desc, void* hip_stream, mpm_run** out);
 
-/* Copies the permeability K (> 0), the source q (may be NULL: q = 0) and the initial
- * saturation s0 (in [0,1]) into the workspace. Device pointers, row-major [ny][nx]. */
+/* The data of the problem of Section 2: the absolute permeability K of kappa = lambda(s) K
+ * (eq. Darcy; K > 0), the source q (may be NULL: q = 0) and the initial saturation s^0 of eq.
+ * BL2D (in [0,1]), copied into the workspace on the run's stream. Device pointers, row-major
+ * [ny][nx]; the caller may free them once the copy has run. A non-positive or non-finite K or an
+ * s^0 outside [0,1] is found by the first conductivity kernel (mpm_start): MPM_ENOTSPD or
+ * MPM_ENONFINITE from the next mpm_get_stats. MPM_EINVAL for a NULL K or s0. */
 mpm_status mpm_set_fields(mpm_run* run, const double* dev_K, const double* dev_q, const double* dev_s0);
 
 /* Algorithm 1, first four lines: kappa^0 = lambda(s^0) K, the MRCM velocity, the stored
@@ -219,27 +223,37 @@ mpm_status mpm_batch_step(mpm_batch* batch, const uint8_t* active, uint8_t* brea
 /* Detaches every run and frees the batch and its streams (the runs stay the caller's). */
 mpm_status mpm_batch_destroy(mpm_batch* batch);
 
-/* Copies the current velocity (device pointers ux [ny][nx+1], uy [ny+1][nx]). */
+/* The current fine velocity u: after an MRCM update the downscaled MRCM velocity (Section 3),
+ * after an MPM-2P update the conservative velocity of the downscaling problems (eq. mpm_upd,
+ * Section 4.1). Copied on the run's stream into caller-owned device buffers ux [ny][nx+1] and
+ * uy [ny+1][nx] (normal flux per unit face length along +x / +y). MPM_ESTATE before mpm_start. */
 mpm_status mpm_get_velocity(mpm_run* run, double* dev_ux, double* dev_uy);
 
-/* Copies the current saturation (device pointer, [ny][nx]). */
+/* The current water saturation s of eq. BL2D (after the last transport sub-step), copied on the
+ * run's stream into a caller-owned device buffer [ny][nx]. MPM_ESTATE before mpm_set_fields. */
 mpm_status mpm_get_saturation(mpm_run* run, double* dev_s);
 
-/* Counters and scalars; synchronises with the run's stream. Returns the device error, if any. */
+/* The counters of Algorithm 1 (T_e, T_m as counted in the cost ratio of Section 4.3), the last
+ * switch criterion epsilon (Section 4.1), simulated time, pore volumes injected and the outflow
+ * water cut that decides breakthrough (Section 5), written into a host struct. Synchronises with
+ * the run's stream. Returns the device error word's status, if any bit is set (the run is then
+ * poisoned). */
 mpm_status mpm_get_stats(mpm_run* run, mpm_stats* out);
 
-/* Frees the host-side run. The workspace stays the caller's. */
+/* Waits for the run's work and frees the host-side run (and, for mpm_create_static, releases the
+ * device's static array). The workspace stays the caller's. Returns the device error's status. */
 mpm_status mpm_destroy(mpm_run* run);
 
 /* Static description of a status code. */
 const char* mpm_status_str(mpm_status status);
 
-/* Sizes of the run's plan: subdomains, interface unknowns, nested-dissection nodes and
- * levels (host memory; any pointer may be NULL). */
+/* Sizes of the run's plan: subdomains of the decomposition and interface unknowns of eq:mrc2
+ * (Section 3; the N-hat of Section 4.3 is twice the unknowns per element), nested-dissection
+ * nodes and levels (host memory; any pointer may be NULL). */
 mpm_status mpm_plan_info(const mpm_run* run, int64_t* n_sub, int64_t* n_iface, int64_t* n_nodes,
                          int64_t* n_levels);
 
-/* Bytes of the interface factorisation (Section 5.3, eq:mrc2) that one solve reads: the forward
+/* Bytes of the factorisation of the interface system (eq:mrc2, Section 3) that one solve reads: the forward
  * sweep's BI blocks and the backward sweep's [II IB] rows, summed over the nested-dissection
  * nodes, and the size of all fronts (host memory; any pointer may be NULL). */
 mpm_status mpm_plan_solve_bytes(const mpm_run* run, int64_t* fwd_bytes, int64_t* bwd_bytes,

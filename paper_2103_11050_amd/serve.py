@@ -33,28 +33,42 @@ from . import binding, inputs
 class Server:
     """Slots of one batch, admission by device footprint, one stream per slot."""
 
-    def __init__(self, capacity: int, budget_bytes: int, max_updates: int = 100000, keep_results: bool = False):
+    def __init__(self, capacity: int, budget_bytes: int, max_updates: int = 100000, keep_results: bool = False,
+                 precision: int = binding.PREC_FP64):
         import torch
         self.torch = torch
         self.capacity = capacity
         self.budget = budget_bytes
         self.max_updates = max_updates
         self.keep = keep_results
+        self.precision = precision
         self.batch = binding.Batch(capacity)
         self.streams = [torch.cuda.Stream() for _ in range(capacity)]
         self.dev = torch.device("cuda:0")
 
-    def _open(self, cfg: dict, slot: int):
+    def prepare(self, requests: list[dict]) -> list:
+        """The requests' fields (permeability, initial saturation) in pinned host memory, made
+        before the first arrival (a client sends its data with the request)."""
         torch = self.torch
-        K = inputs.permeability(cfg)
-        Kt = torch.from_numpy(K).to(self.dev)
-        st = torch.from_numpy(inputs.initial_saturation(cfg)).to(self.dev)
-        torch.cuda.synchronize()
-        return binding.Run(cfg, Kt, st, stream=self.streams[slot])
+        return [(torch.from_numpy(inputs.permeability(c)).pin_memory(),
+                 torch.from_numpy(inputs.initial_saturation(c)).pin_memory()) for c in requests]
 
-    def serve(self, requests: list[dict], arrivals: list[float]) -> dict:
+    def _open(self, cfg: dict, slot: int, fields):
+        """Copies the request's fields to the device and creates its run, all on the slot's
+        stream (no wait on the other slots' work)."""
+        torch = self.torch
+        st = self.streams[slot]
+        with torch.cuda.stream(st):
+            Kt = fields[0].to(self.dev, non_blocking=True)
+            s0 = fields[1].to(self.dev, non_blocking=True)
+            return binding.Run(cfg, Kt, s0, stream=st, precision=self.precision)
+
+    def serve(self, requests: list[dict], arrivals: list[float], fields=None) -> dict:
         """Runs every request to breakthrough (or max_updates passes); arrivals in seconds from
-        the start. Returns the summary and the per-request records."""
+        the start; fields from prepare() (made here, before the clock starts, if not given).
+        Returns the summary and the per-request records."""
+        if fields is None:
+            fields = self.prepare(requests)
         order = sorted(range(len(requests)), key=lambda i: arrivals[i])
         pending = collections.deque(order)
         free = list(range(self.capacity))
@@ -74,7 +88,7 @@ class Server:
                     break
                 pending.popleft()
                 slot = free.pop()
-                run = self._open(requests[i], slot)
+                run = self._open(requests[i], slot, fields[i])
                 self.batch.attach(slot, run)
                 active[slot] = [i, run, need, 0]
                 used += need
@@ -99,6 +113,7 @@ class Server:
                     s = run.stats()
                     rec = recs[i]
                     rec.update(finish=time.perf_counter() - t0, te=s["te"], tm=s["tm"], pvi=s["pvi"],
+                               error_word=s["error_word"],
                                breakthrough=bool(s["breakthrough"]), passes=n)
                     rec["latency"] = rec["finish"] - rec["arrival"]
                     if self.keep:
@@ -199,6 +214,7 @@ def main(argv=None):
     s.add_argument("--rate", type=float, default=0.0,
                    help="arrivals per second; 0: 70%% of the capacity measured with all requests at t = 0")
     s.add_argument("--max-updates", type=int, default=100000)
+    s.add_argument("--precision", choices=["fp64", "fp32-refine"], default="fp64")
     b = sub.add_parser("batch")
     b.add_argument("--runs", type=int, default=256)
     b.add_argument("--steps", type=int, default=20)
@@ -209,20 +225,38 @@ def main(argv=None):
         print(json.dumps({"form": "batched", **out}))
         return
     reqs = inputs.serve_requests(args.requests, tuple(args.grids))
-    budget = int(args.budget_gib * (1 << 30))
-    rate = args.rate
-    out = {"form": "serving", "grids": args.grids, "capacity": args.capacity}
-    if rate <= 0:
-        srv = Server(args.capacity, budget, args.max_updates)
-        cal = srv.serve(reqs, [0.0] * len(reqs))["summary"]
+    prec = binding.PREC_FP64 if args.precision == "fp64" else binding.PREC_FP32_REFINE
+    out = {"form": "serving", "grids": args.grids, "capacity": args.capacity, "precision": args.precision}
+    out.update(serve_measure(reqs, args.capacity, int(args.budget_gib * (1 << 30)), args.max_updates, args.rate,
+                             prec))
+    print(json.dumps(out))
+
+
+def serve_measure(reqs: list[dict], capacity: int, budget: int, max_updates: int, rate: float,
+                  precision: int = binding.PREC_FP64, measure_capacity: bool = False, states: list = None) -> dict:
+    """The serving figures. The capacity run (every request present at t = 0) is made when rate
+    <= 0 (the arrival rate is then 70 % of it) or measure_capacity is set; then Poisson arrivals
+    at the rate. Returns the summary of the arrival run (runs/s, velocity updates/s, p50/p99
+    latency from arrival to breakthrough) and, under "capacity_measured", that of the capacity
+    run; `states` (a list) receives the final (ux, uy, s, passes) of each request of the
+    capacity run."""
+    out = {}
+    srv = Server(capacity, budget, max_updates, precision=precision, keep_results=states is not None)
+    fields = srv.prepare(reqs)
+    if rate <= 0 or measure_capacity:
+        res = srv.serve(reqs, [0.0] * len(reqs), fields)
         srv.close()
-        rate = 0.7 * cal["runs_per_s"]
+        if states is not None:
+            states.extend((*r["state"], r["passes"]) for r in res["records"])
+        srv = Server(capacity, budget, max_updates, precision=precision)
+        cal = res["summary"]
+        if rate <= 0:
+            rate = 0.7 * cal["runs_per_s"]
         out["capacity_measured"] = cal
-    srv = Server(args.capacity, budget, args.max_updates)
-    res = srv.serve(reqs, poisson_arrivals(len(reqs), rate))
+    res = srv.serve(reqs, poisson_arrivals(len(reqs), rate), fields)
     srv.close()
     out.update(rate_per_s=round(rate, 4), **res["summary"])
-    print(json.dumps(out))
+    return out
 
 
 if __name__ == "__main__":

@@ -348,3 +348,78 @@ def test_batch_step_refuses_unstarted_runs(binding):
     assert r.stats()["te"] == 2
     b.close()
     r.close()
+
+
+def _oracle_compare(cfg, orun, state, label):
+    from .gpu_common import FP64_SAT_TOL, FP64_VEL_TOL, sat_rel_err, vel_face_err, vel_rel_err
+    ux, uy, s, st = state
+    ev = vel_rel_err(cfg, ux, uy, orun.ux, orun.uy)
+    ef = vel_face_err(ux, uy, orun.ux, orun.uy)
+    es = sat_rel_err(s, orun.s)
+    print(f"    {label}: velocity {ev:.2e} (face {ef:.2e}), saturation {es:.2e}, T_e {st['te']} T_m {st['tm']}",
+          flush=True)
+    assert st["error_word"] == 0
+    assert ev <= FP64_VEL_TOL and ef <= FP64_VEL_TOL and es <= FP64_SAT_TOL, (label, ev, ef, es)
+    assert st["te"] == orun.n and st["tm"] == orun.ell + 1, label
+    assert abs(st["pvi"] - orun.pvi) <= 1e-10 * orun.pvi
+
+
+def test_batch_classes_match_oracle(binding):
+    """One realisation of each class of the batched workload (64^2 in 8^2 subdomains, 128^2 and
+    256^2 in 16^2, 4 elements per side, log-variance 4, M = 100) stepped together in one batch
+    for 30 passes of Algorithm 1 against the FP64 oracle run alone on the same inputs (the 64^2
+    run with eta = 0.02, so that its switch takes basis updates inside the window)."""
+    from oracle import splitting
+    nsteps = 30
+    cfgs = inputs.batch_workload(3)
+    cfgs[0]["eta"] = 0.02
+    dev = torch.device("cuda:0")
+    streams = [torch.cuda.Stream() for _ in cfgs]
+    runs = []
+    for c, stream in zip(cfgs, streams):
+        Kt = torch.from_numpy(inputs.permeability(c)).to(dev)
+        st = torch.from_numpy(inputs.initial_saturation(c)).to(dev)
+        torch.cuda.synchronize()
+        runs.append(binding.Run(c, Kt, st, stream=stream))
+    b = binding.Batch(len(runs))
+    for i, r in enumerate(runs):
+        b.attach(i, r)
+    b.start()
+    for _ in range(nsteps):
+        b.step()
+    b.close()
+    states = [_state(r) for r in runs]
+    for r in runs:
+        r.close()
+    for c, state in zip(cfgs, states):
+        print(f"[gpu] batch class {c['nx']}^2 (subdomains {c['sub_x']}^2) against the oracle", flush=True)
+        orun = splitting.simulate(c, inputs.permeability(c), inputs.initial_saturation(c), nsteps + 1)
+        _oracle_compare(c, orun, state, f"{c['nx']}^2")
+    assert states[0][3]["tm"] > 1, "no basis update in the window"
+
+
+@pytest.mark.timeout(600)
+def test_served_512_request_matches_oracle(binding):
+    """A 512^2 request of the serving workload (32 x 32 subdomains of 16^2, 4 elements per side)
+    served beside a 128^2 and a 256^2 request through the continuous-batching server, stopped
+    after 8 passes, against the FP64 oracle run alone on the same inputs."""
+    from oracle import splitting
+    from paper_2103_11050_amd import serve
+    reqs = inputs.serve_requests(24, (128, 256, 512))
+    pick = {}
+    for c in reqs:
+        pick.setdefault(c["nx"], c)
+    sel = [pick[128], pick[256], pick[512]]
+    npass = 8
+    srv = serve.Server(3, 8 << 30, max_updates=npass, keep_results=True)
+    res = srv.serve(sel, [0.0, 0.0, 0.0])
+    srv.close()
+    rec = res["records"][2]
+    assert rec["nx"] == 512 and rec["passes"] == npass
+    c = sel[2]
+    print(f"[gpu] served 512^2 request (M = {c['mu_o']:.1f}, log-variance {c['sigma2']:.2f}) against the oracle",
+          flush=True)
+    orun = splitting.simulate(c, inputs.permeability(c), inputs.initial_saturation(c), npass + 1)
+    ux, uy, s = rec["state"]
+    st = {"te": rec["te"], "tm": rec["tm"], "pvi": rec["pvi"], "error_word": rec["error_word"]}
+    _oracle_compare(c, orun, (ux, uy, s, st), "512^2 served")

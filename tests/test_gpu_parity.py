@@ -124,6 +124,8 @@ def _compare_runs(binding, cfg, K, nsteps, label, forced=None, vel_tol=FP64_VEL_
         assert math.isclose(st["pvi"], orun.pvi, rel_tol=1e-10), (n, st["pvi"], orun.pvi)
         assert math.isclose(st["water_cut"], orun.wcut, rel_tol=1e-8, abs_tol=1e-14)
         assert st["te"] == orun.n and st["tm"] == orun.ell + 1
+        if nsteps >= 50 and n % 25 == 0:
+            print(f"    pass {n}: velocity error {e:.2e}, saturation error {es:.2e}, T_m {st['tm']}", flush=True)
     print(f"    max rel velocity error {max(errs):.3e}, max rel saturation error {worst_s:.3e}", flush=True)
     r.close()
     return orun
@@ -228,6 +230,20 @@ def test_c2_window(binding):
     cfg = inputs.config("c2")
     K = inputs.permeability(cfg)
     _compare_runs(binding, cfg, K, 4, "c2")
+
+
+@pytest.mark.timeout(600)
+def test_c2_long_window(binding):
+    """Workload 2 over 200 passes of Algorithm 1 with eta = 0.02, so that the switch takes
+    automatic MRCM updates inside the window (with eta = 0.1 epsilon first exceeds the threshold
+    after about 270 passes), compared pass by pass: branch, epsilon, time step, water cut, PVI,
+    and the velocity and saturation fields."""
+    cfg = inputs.config("c2", eta=0.02)
+    K = inputs.permeability(cfg)
+    orun = _compare_runs(binding, cfg, K, 200, "c2 long window")
+    auto = [h["n"] for h in orun.history[1:] if h["branch"] == "mrcm"]
+    print(f"    automatic MRCM updates at passes {auto}", flush=True)
+    assert len(auto) >= 1
 
 
 def test_c2_forced_update(binding):
