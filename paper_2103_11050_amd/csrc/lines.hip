@@ -1014,11 +1014,18 @@ void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double*
     }                                                                                              \
   } while (0)
 
-// precision form: FP32 blocks, any line count up to 16
+// precision form: FP32 blocks, any line count up to 16; square 8^2 / 16^2 subdomains get
+// compile-time shapes
 #define MPM_LB_DISPATCH_F32(KERNEL, ...)                                                           \
   do {                                                                                             \
-    if (line_mf(g) == 8) MPM_LB_LAUNCH((KERNEL<8, 16, float, 0>), __VA_ARGS__);                    \
-    else MPM_LB_LAUNCH((KERNEL<16, 16, float, 0>), __VA_ARGS__);                                   \
+    const bool sq8_ = g.mx == 8 && g.my == 8, sq16_ = g.mx == 16 && g.my == 16;                    \
+    if (line_mf(g) == 8) {                                                                         \
+      if (sq8_) MPM_LB_LAUNCH((KERNEL<8, 16, float, 8>), __VA_ARGS__);                             \
+      else MPM_LB_LAUNCH((KERNEL<8, 16, float, 0>), __VA_ARGS__);                                  \
+    } else {                                                                                       \
+      if (sq16_) MPM_LB_LAUNCH((KERNEL<16, 16, float, 16>), __VA_ARGS__);                          \
+      else MPM_LB_LAUNCH((KERNEL<16, 16, float, 0>), __VA_ARGS__);                                 \
+    }                                                                                              \
   } while (0)
 
 void launch_mpm_local(hipStream_t st, const Geo& g, const double* kn, const double* km, const double* uxm,
