@@ -151,6 +151,65 @@ __device__ __forceinline__ void lb_solve_regs(const LineW& W, const LB<MF>& L, c
   __syncthreads();
 }
 
+// The same two sweeps with the blocks streamed through a ring of D register blocks instead of
+// all NL held at once: the uses run forward over lines 0 .. NL-1, then backward over NL-2 .. 0,
+// and the load for use k + D is issued right after use k, so D blocks are in flight while one is
+// applied. The backward uses re-read blocks that the forward sweep read shortly before (served
+// by the caches). Holding D blocks instead of NL frees the registers that bound the resident
+// wavefronts per SIMD.
+template <int NL>
+__device__ __forceinline__ constexpr int ring_line(int k) { return k < NL ? k : 2 * NL - 2 - k; }
+
+template <int MF, int NL, int D>
+__device__ __forceinline__ void lb_ring_load(const LB<MF>& L, const double* Es, double (&e)[D][LB<MF>::EPL]) {
+  constexpr int EPL = LB<MF>::EPL, P = LBP<MF>::P;
+  int pk[EPL];
+  lb_pk_lane<MF>(L, pk);
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+#pragma unroll
+    for (int t = 0; t < EPL; ++t) e[d][t] = Es[size_t(ring_line<NL>(d)) * P + pk[t]];
+}
+
+template <int MF, int NL, int D>
+__device__ __forceinline__ void lb_solve_ring(const LineW& W, const LB<MF>& L, const double* Es,
+                                              double (&e)[D][LB<MF>::EPL], double* x) {
+  constexpr int EPL = LB<MF>::EPL, P = LBP<MF>::P, NU = 2 * NL - 1;
+  static_assert(D >= 1 && D < NU, "ring depth");
+  int pk[EPL];
+  lb_pk_lane<MF>(L, pk);
+  const int len = W.band;
+  const bool rin = L.row < len;
+  const bool wr = rin && L.cg == 0;
+  const int xr = rin ? L.row : 0;
+  // the forward result w_ln overwrites line ln of the right-hand side in x (read by the row's
+  // lanes before one of them writes it); the backward sweep reads it back
+  double xnext = 0.0;
+#pragma unroll
+  for (int k = 0; k < NU; ++k) {
+    const int ln = ring_line<NL>(k);
+    if (k < NL) {
+      double z = rin ? x[ln * len + xr] : 0.0;
+      if (ln > 0 && rin) z += W.y(ln - 1, xr) * xnext;
+      xnext = lb_matvec<MF>(L, e[k % D], z);
+      if (wr) x[ln * len + xr] = xnext;
+    } else {
+      const double v = rin ? W.y(ln, xr) * xnext : 0.0;
+      const double wl = rin ? x[ln * len + xr] : 0.0;
+      xnext = wl + lb_matvec<MF>(L, e[k % D], v);
+      if (wr) x[ln * len + xr] = xnext;
+    }
+    if (k + D < NU) {
+#pragma unroll
+      for (int t = 0; t < EPL; ++t) e[k % D][t] = Es[size_t(ring_line<NL>(k + D)) * P + pk[t]];
+    }
+    // one step at a time: the scheduler would otherwise hoist later steps' loads and LDS reads
+    // and hold their results in registers, which is what the ring is there to avoid
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------ FP32 blocks, FP64 refinement
 // Precision form: the inverse blocks are stored in FP32 and applied in FP32; each solve is
 // recovered by FP64 iterative refinement against the FP64 line form of the same matrix.
@@ -515,6 +574,12 @@ __device__ __forceinline__ double mpm_vbnd_face(const Geo& g, const BFace& bf, c
 
 // The geometry with the subdomain shape as compile-time constants for FX x FX subdomains (FX =
 // 0: as given), so that the index arithmetic of the local kernels folds.
+// Blocks in flight in the ring solve of the fixed-shape local kernels.
+#ifndef MPM_RING_D
+#define MPM_RING_D 4
+#endif
+constexpr int RING_D = MPM_RING_D;
+
 template <int FX>
 __device__ __forceinline__ Geo fix_geo(Geo g) {
   if constexpr (FX > 0) {
@@ -567,10 +632,13 @@ k_mpm_local_lb(Geo g0, const double* __restrict__ kap_n, const double* __restric
   const int TW = g.mx + 2;
   LB<MF> L;
   constexpr int NLR = NL > 0 ? NL : 1;
-  double E[F32 ? 1 : NLR][LB<MF>::EPL];
+  constexpr bool RING = !F32 && FX > 0 && NL > 0;   // fixed shape: blocks streamed through a ring
+  double E[(F32 || RING) ? 1 : NLR][LB<MF>::EPL];
+  double Er[RING ? RING_D : 1][LB<MF>::EPL];
   float Ef[F32 ? 16 : 1][LB<MF>::EPL];
   const T* Es = fac + efac_off<MF>(g, sub);
   if constexpr (F32) lb_load_f32<MF>(L, Es, g.nc / g.band, Ef);
+  else if constexpr (RING) lb_ring_load<MF, NL, RING_D>(L, Es, Er);
   else if constexpr (NL > 0) lb_load_reg<MF, NL>(L, Es, E);
   double qc[4];
   load_halo_tiles(g, I, J, kap_n, kap_m, uxm, uym, q, knt, kmt, uxs, uys, qc);
@@ -611,7 +679,8 @@ k_mpm_local_lb(Geo g0, const double* __restrict__ kap_n, const double* __restric
     if (!lb_solve_refined<MF>(g, W, L, Ef, x, xtra + 768) && L.lane == 0) set_error(err, ERR_NOCONV);
   } else {
     const LineW W{ty, ty, nullptr, g.xfast, g.band, 0};
-    if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
+    if constexpr (RING) lb_solve_ring<MF, NL, RING_D>(W, L, Es, Er, x);
+    else if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
     else lb_solve<MF>(g, W, L, Es, x);
   }
   double* hsh = uys;
@@ -841,9 +910,12 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
   const size_t eoff = efac_off<MF>(g, sub);
   T* Es = (!store && flag[sub]) ? Escr + eoff : Ekeep + eoff;
   constexpr int NLR = NL > 0 ? NL : 1;
-  double E[F32 ? 1 : NLR][LB<MF>::EPL];
+  constexpr bool RING = !F32 && FX > 0 && NL > 0;   // fixed shape (store = 0): ring of blocks
+  double E[(F32 || RING) ? 1 : NLR][LB<MF>::EPL];
+  double Er[RING ? RING_D : 1][LB<MF>::EPL];
   float Ef[F32 ? 16 : 1][LB<MF>::EPL];
   if constexpr (F32) lb_load_f32<MF>(L, Es, g.nc / g.band, Ef);
+  else if constexpr (RING) lb_ring_load<MF, NL, RING_D>(L, Es, Er);
   else if constexpr (NL > 0) {
     if (!store) lb_load_reg<MF, NL>(L, Es, E);
   }
@@ -889,14 +961,21 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
   if constexpr (F32) {
     if (!lb_solve_refined<MF>(g, W, L, Ef, x, wsh) && L.lane == 0) set_error(err, ERR_NOCONV);
   } else {
-    if (store) {
-      bool ok = true;
-      lb_factor<MF>(g, W, L, Es, ok);
-      if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
-      __syncthreads();   // the lower-triangle entries come from other lanes' stores
-      if constexpr (NL > 0) lb_load_reg<MF, NL>(L, Es, E);
+    if constexpr (!RING) {
+      if (store) {
+        bool ok = true;
+        lb_factor<MF>(g, W, L, Es, ok);
+        if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
+        __syncthreads();   // the lower-triangle entries come from other lanes' stores
+        if constexpr (NL > 0) lb_load_reg<MF, NL>(L, Es, E);
+      }
     }
-    if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
+    if constexpr (RING) {
+      // nothing of the flux phase is computed ahead of the solve (it would stay live across it)
+      __builtin_amdgcn_sched_barrier(0);
+      lb_solve_ring<MF, NL, RING_D>(W, L, Es, Er, x);
+      __builtin_amdgcn_sched_barrier(0);
+    } else if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
     else lb_solve<MF>(g, W, L, Es, x);
   }
   double rate = 0.0;
