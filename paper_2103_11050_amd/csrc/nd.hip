@@ -356,8 +356,10 @@ __global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a0, int loff, const Ru
   const NdArgs a = nd_at(a0, ws_off(rt));
   constexpr int RPP = 256 / G, RPB = RP * RPP;
   const NodeDev nd = a.lnodes[loff + blockIdx.y];
+  // a workgroup past the node's rows (nodes smaller than the level's largest) runs with clamped
+  // rows and stores nothing (j >= nB below): no early exit, so that the node record is read in
+  // one go rather than field by field around a branch
   const int r0 = blockIdx.x * RPB;
-  if (r0 >= nd.nB) return;
   const int gl = threadIdx.x % G, grp = threadIdx.x / G;
   const double* __restrict__ F = a.front + nd.front_off;
   const double* __restrict__ s0 = a.slots + nd.slot_off;
@@ -445,8 +447,7 @@ __device__ __forceinline__ void k_nd_bwd_body(const NdArgs& a, int loff) {
   static_assert(RP <= G, "lane p of a row group holds row p's unknown id");
   constexpr int RPP = 256 / G, RPB = RP * RPP;
   const NodeDev nd = a.lnodes[loff + blockIdx.y];
-  const int r0 = blockIdx.x * RPB;
-  if (r0 >= nd.nI) return;
+  const int r0 = blockIdx.x * RPB;   // rows past the node's stay clamped and unstored (r >= nI)
   const int gl = threadIdx.x % G, grp = threadIdx.x / G;
   const double* __restrict__ F = a.front + nd.front_off;
   const double* __restrict__ s0 = a.slots + nd.slot_off;
