@@ -359,6 +359,8 @@ def main():
     ap.add_argument("--no-precision-form", action="store_true",  # also skips the other side forms
                     help="skip the side-by-side run of the FP32-block precision form")
     ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--tune", type=int, default=1, help="autotune the interface-sweep launch shapes (1) or "
+                    "keep the fixed rule (0)")
     ap.add_argument("--serve-requests", type=int, default=32,
                     help="requests of the served-form figures (p50/p99 run latency; 0: skip)")
     ap.add_argument("--refine-rtol", type=float, default=1e-6,
@@ -401,6 +403,9 @@ def main():
     prec = binding.PREC_FP64 if args.precision == "fp64" else binding.PREC_FP32_REFINE
     run = binding.Run(cfg, Kt, st, precision=prec)
     run.start()
+    # interface-sweep launch shapes: autotuned once per decomposition (also used by every later
+    # run of this decomposition in the process)
+    tuned = run.tune(5) if args.tune else None
     for _ in range(args.warmup):
         run.step()
     torch.cuda.synchronize()
@@ -476,6 +481,11 @@ def main():
         "phases": phase_rooflines(alg, sb, prof, cfg, 1e3 * elapsed / args.steps),
         "kernels_ms": {k: round(v[0], 5) for k, v in sorted(prof.items())},
         "mrcm_update_ms": round(float(np.median(mr)), 4),
+        "sweep_tuning": None if tuned is None else {
+            "solve_ms_rule": round(tuned["ms_rule"], 4), "solve_ms_tuned": round(tuned["ms_tuned"], 4),
+            "shapes": [list(x) for x in tuned["shapes"]],
+            "note": "lanes per row, columns per lane, rows per lane group of each sweep launch "
+                    "(forward levels upwards, then backward levels downwards)"},
         "mrcm_kernels_ms": {k: round(v[0], 5) for k, v in sorted(mprof.items())},
     }
     run.close()

@@ -79,6 +79,9 @@ _SIGS = {
     "mpm_batch_step": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "mpm_batch_start": (ctypes.c_int32, [ctypes.c_void_p]),
     "mpm_batch_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "mpm_tune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]),
     "mpm_profile": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
@@ -259,6 +262,18 @@ class Run:
         v = [ctypes.c_int64() for _ in range(3)]
         _check(load().mpm_plan_solve_bytes(self.h, *[ctypes.byref(x) for x in v]), "mpm_plan_solve_bytes")
         return dict(fwd=v[0].value, bwd=v[1].value, front=v[2].value)
+
+    def tune(self, reps: int = 5) -> dict:
+        """Autotunes the interface-sweep launch shapes of this run (mpm_tune)."""
+        cap = 3 * 128
+        shapes = (ctypes.c_int32 * cap)()
+        n = ctypes.c_int32()
+        t0, t1 = ctypes.c_double(), ctypes.c_double()
+        _check(load().mpm_tune(self.h, reps, cap, shapes, ctypes.byref(n), ctypes.byref(t0), ctypes.byref(t1)),
+               "mpm_tune")
+        k = min(n.value, cap // 3)
+        return {"ms_rule": t0.value, "ms_tuned": t1.value,
+                "shapes": [tuple(shapes[3 * i:3 * i + 3]) for i in range(k)]}
 
     def profile(self, enable: bool = True, reset: bool = True) -> dict:
         cap = 64

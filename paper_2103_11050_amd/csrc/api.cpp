@@ -2,6 +2,7 @@
 // transport sub-steps and the modified operator splitting (Section 4.2, Algorithm 1).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -123,6 +124,8 @@ struct mpm_run {
   // runs of the group, and those of them taking the MPM-2P branch
   RunTab tab_host[2] = {};
   unsigned tab_n[2] = {0, 0};
+  // launch shape of each interface-sweep level (nd_shape_code; 0 = the fixed rule), by level
+  std::vector<int> tune_fwd, tune_bwd;
 
   hipEvent_t take_event() {
     if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
@@ -313,7 +316,8 @@ void nd_solve(mpm_run* r, Runs rt = one_run()) {
     for (int l = 1; l < L; ++l) {
       const int nn = int(P.level_nodes[l].size());
       if (!nn) continue;
-      launch_nd_level_fwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l], P.level_nBmax[l], rt);
+      const int sh = l < int(r->tune_fwd.size()) ? r->tune_fwd[l] : 0;
+      launch_nd_level_fwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l], P.level_nBmax[l], rt, sh);
     }
   }
   {
@@ -321,7 +325,9 @@ void nd_solve(mpm_run* r, Runs rt = one_run()) {
     for (int l = L; l >= 1; --l) {
       const int nn = int(P.level_nodes[l].size());
       if (!nn) continue;
-      launch_nd_level_bwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l], P.level_nmax[l], l == L ? 1 : 0, rt);
+      const int sh = l < int(r->tune_bwd.size()) ? r->tune_bwd[l] : 0;
+      launch_nd_level_bwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l], P.level_nmax[l], l == L ? 1 : 0, rt,
+                          sh);
     }
   }
 }
@@ -699,6 +705,26 @@ bool g_static_busy[kMaxDevices] = {};   // a live run holds the device's array
 // epsilon and water-cut block that the reduction kernel writes.
 size_t static_bytes(const Plan& P) { return ((P.total_bytes + 255) & ~size_t(255)) + 256; }
 
+// Sweep launch shapes found by mpm_tune, by decomposition (the nested-dissection plan depends on
+// the grid, the subdomains, the interface elements and their degree): runs created later with the
+// same decomposition start from them.
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<std::vector<int>, std::vector<int>>> g_tune_cache;
+
+std::string tune_key(const mpm_desc& d) {
+  const int32_t v[7] = {d.nx, d.ny, d.sub_x, d.sub_y, d.ne_x, d.ne_y, d.iface_degree};
+  return std::string(reinterpret_cast<const char*>(v), sizeof(v));
+}
+
+void tune_from_cache(mpm_run* r) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune_cache.find(tune_key(r->P.d));
+  if (it != g_tune_cache.end()) {
+    r->tune_fwd = it->second.first;
+    r->tune_bwd = it->second.second;
+  }
+}
+
 void release_static(int device) {
   std::lock_guard<std::mutex> lk(g_static_mu);
   if (device >= 0 && device < kMaxDevices) g_static_busy[device] = false;
@@ -792,6 +818,7 @@ mpm_status mpm_create(const mpm_desc* desc, void* dev_workspace, size_t bytes, v
   CREATE_CHK(hipStreamCreateWithFlags(&r->st2, hipStreamNonBlocking));
   CREATE_CHK(hipStreamSynchronize(r->ust));
   if (upload_plan(r) != hipSuccess || hipStreamSynchronize(r->st) != hipSuccess) return fail(MPM_EHIP);
+  tune_from_cache(r);
   *out = r;
   return MPM_OK;
 }
@@ -855,6 +882,7 @@ mpm_status mpm_create_static(const mpm_desc* desc, void* hip_stream, mpm_run** o
   e = upload_plan(r);
   if (e == hipSuccess) e = hipStreamSynchronize(r->st);
   if (e != hipSuccess) return fail(MPM_EHIP, "plan upload", e);
+  tune_from_cache(r);
   *out = r;
   return MPM_OK;
 }
@@ -1466,6 +1494,105 @@ mpm_status mpm_plan_info(const mpm_run* r, int64_t* n_sub, int64_t* n_iface, int
   if (n_nodes) *n_nodes = int64_t(r->P.nodes.size());
   if (n_levels) *n_levels = int64_t(r->P.level_nodes.size()) - 1;
   return MPM_OK;
+}
+
+// Autotuner of the interface sweeps: for each level of the forward, then of the backward sweep,
+// every admissible launch shape is timed over complete interface solves (the other levels at
+// their current choice; best of `reps`), and the fastest kept. The solves repeat the last one
+// (idempotent: each level writes what only the levels after it read).
+mpm_status mpm_tune(mpm_run* r, int32_t reps, int32_t cap, int32_t* shapes, int32_t* n, double* ms_rule,
+                    double* ms_tuned) {
+  if (!r || reps < 1 || cap < 0 || (cap > 0 && !shapes)) return MPM_EINVAL;
+  if (!r->started || r->poisoned || r->owner) return MPM_ESTATE;
+  mpm_status st = enter(r);
+  if (st) return st;
+  const Plan& P = r->P;
+  const int L = int(P.level_nodes.size()) - 1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool prof = r->prof;   // the trial solves stay out of the kernel profile
+  r->prof = false;
+  auto body = [&]() -> mpm_status {
+    HIPCHK(r, hipEventCreate(&e0));
+    HIPCHK(r, hipEventCreate(&e1));
+    auto time_solve = [&](double* best) -> mpm_status {
+      *best = 1e300;
+      for (int k = 0; k < reps + 1; ++k) {   // the first solve warms up
+        HIPCHK(r, hipEventRecord(e0, r->st));
+        nd_solve(r);
+        HIPCHK(r, hipEventRecord(e1, r->st));
+        HIPCHK(r, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(r, hipEventElapsedTime(&ms, e0, e1));
+        if (k > 0) *best = std::min(*best, double(ms));
+      }
+      return MPM_OK;
+    };
+    r->tune_fwd.assign(std::max(L + 1, 1), 0);
+    r->tune_bwd.assign(std::max(L + 1, 1), 0);
+    double t_rule = 0.0, t = 0.0;
+    mpm_status s2 = time_solve(&t_rule);
+    if (s2) return s2;
+    double cur = t_rule;
+    for (int dir = 0; dir < 2; ++dir) {
+      std::vector<int>& tab = dir == 0 ? r->tune_fwd : r->tune_bwd;
+      for (int l = 1; l <= L; ++l) {
+        if (P.level_nodes[l].empty() || (dir == 0 && l == L)) continue;   // the root has no forward step
+        const int len = dir == 0 ? P.level_nImax[l] : P.level_nmax[l];
+        const int rows = dir == 0 ? P.level_nBmax[l] : P.level_nImax[l];
+        int codes[32];
+        const int nc = nd_shape_candidates(len, rows, dir == 1, codes, 32);
+        int best = tab[l];
+        for (int c = 1; c < nc; ++c) {   // codes[0] is the rule
+          tab[l] = codes[c];
+          s2 = time_solve(&t);
+          if (s2) return s2;
+          if (t < 0.99 * cur) { cur = t; best = codes[c]; }
+        }
+        tab[l] = best;
+      }
+    }
+    s2 = time_solve(&t);
+    if (s2) return s2;
+    if (t > t_rule) {   // keep the rule if the choice does not hold up
+      std::fill(r->tune_fwd.begin(), r->tune_fwd.end(), 0);
+      std::fill(r->tune_bwd.begin(), r->tune_bwd.end(), 0);
+      t = t_rule;
+    }
+    if (ms_rule) *ms_rule = t_rule;
+    if (ms_tuned) *ms_tuned = t;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune_cache[tune_key(P.d)] = {r->tune_fwd, r->tune_bwd};
+    }
+    // the chosen shape of every launch, forward levels upwards then backward levels downwards
+    int32_t k = 0;
+    auto put = [&](int code, int len, int rows, bool bwd) {
+      int G, U, RP;
+      if (code == 0) {
+        int c0[1];
+        nd_shape_candidates(len, rows, bwd, c0, 1);
+        code = c0[0];
+      }
+      nd_shape_unpack(code, &G, &U, &RP);
+      if (3 * k + 2 < cap) {
+        shapes[3 * k] = G;
+        shapes[3 * k + 1] = U;
+        shapes[3 * k + 2] = RP;
+      }
+      ++k;
+    };
+    for (int l = 1; l < L; ++l)
+      if (!P.level_nodes[l].empty()) put(r->tune_fwd[l], P.level_nImax[l], P.level_nBmax[l], false);
+    for (int l = L; l >= 1; --l)
+      if (!P.level_nodes[l].empty()) put(r->tune_bwd[l], P.level_nmax[l], P.level_nImax[l], true);
+    if (n) *n = k;
+    return MPM_OK;
+  };
+  st = body();
+  r->prof = prof;
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  return leave(r, st);
 }
 
 mpm_status mpm_profile(mpm_run* r, int32_t enable, int32_t reset, int32_t cap, const char** names, double* ms,

@@ -136,10 +136,18 @@ __device__ __forceinline__ NdArgs nd_at(const NdArgs& a, int64_t o) {
 }
 void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nmax, int nImax,
                             int nBmax, Runs rt = one_run());
+// Launch shape of a sweep level: lanes per row G, columns per lane U, rows per lane group RP,
+// packed as G | U << 8 | RP << 16; 0 selects the fixed rule (rows of 1536 or more are taken in
+// chunks whatever the code).
+int nd_shape_code(int G, int U, int RP);
+void nd_shape_unpack(int code, int* G, int* U, int* RP);
+// The shapes a level whose rows hold len entries can be launched with (the rule's first), and
+// the rule's shape; returns how many were written (at most cap).
+int nd_shape_candidates(int len, int rows, bool bwd, int* codes, int cap);
 void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nImax, int nBmax,
-                         Runs rt = one_run());
+                         Runs rt = one_run(), int shape = 0);
 void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nImax, int nmax, int root,
-                         Runs rt = one_run());
+                         Runs rt = one_run(), int shape = 0);
 
 // transport.hip
 // (the viscosity ratio M is the run's, from scal)

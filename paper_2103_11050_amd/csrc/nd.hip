@@ -643,9 +643,43 @@ static RbShape rb_fit_rows(RbShape sh, int rows) {
     ND_RB_CASE(KER, 64, 24, 1, false, __VA_ARGS__)                                                  \
   } while (0)
 
+int nd_shape_code(int G, int U, int RP) { return G | (U << 8) | (RP << 16); }
+void nd_shape_unpack(int code, int* G, int* U, int* RP) {
+  *G = code & 255;
+  *U = (code >> 8) & 255;
+  *RP = (code >> 16) & 255;
+}
+
+// The instantiated shapes (ND_RB_LAUNCH) whose G U columns cover a row of len entries at most
+// four times over, the rule's shape first.
+static RbShape rb_shape_bwd(int len);
+int nd_shape_candidates(int len, int rows, bool bwd, int* codes, int cap) {
+  const RbShape rule = rb_fit_rows(bwd ? rb_shape_bwd(len) : rb_shape(len), rows);
+  int n = 0;
+  if (n < cap) codes[n++] = nd_shape_code(rule.G, rule.U, rule.RP);
+  if (rule.U == 0) return n;   // chunked rows: one shape
+  static const RbShape all[] = {{16, 1, 8}, {16, 1, 6}, {16, 1, 4}, {32, 1, 8}, {32, 1, 4}, {64, 1, 8},
+                                {64, 1, 4}, {64, 2, 8}, {64, 2, 4}, {64, 2, 2}, {64, 4, 4}, {64, 4, 2},
+                                {64, 4, 1}, {64, 8, 2}, {64, 8, 1}, {64, 16, 1}, {64, 24, 1}};
+  for (const RbShape& sh : all) {
+    const int cols = sh.G * sh.U;
+    if (cols < len || cols > 4 * len) continue;
+    if (sh.G == rule.G && sh.U == rule.U && sh.RP == rule.RP) continue;
+    if (n < cap) codes[n++] = nd_shape_code(sh.G, sh.U, sh.RP);
+  }
+  return n;
+}
+
+static RbShape rb_pick(int code, RbShape rule) {
+  if (code == 0 || rule.U == 0) return rule;
+  RbShape sh;
+  nd_shape_unpack(code, &sh.G, &sh.U, &sh.RP);
+  return sh;
+}
+
 void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nBmax,
-                         Runs rt) {
-  const RbShape sh = rb_fit_rows(rb_shape(nImax), nBmax);
+                         Runs rt, int shape) {
+  const RbShape sh = rb_pick(shape, rb_fit_rows(rb_shape(nImax), nBmax));
   ND_RB_LAUNCH(k_nd_fwd_rb, sh, nBmax, nnodes, runs_of(rt), st, a, loff, rt.tab);
 }
 
@@ -667,8 +701,8 @@ static RbShape rb_shape_bwd(int len) {
 }
 
 void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, int nImax, int nmax, int root,
-                         Runs rt) {
-  const RbShape sh = rb_fit_rows(rb_shape_bwd(nmax), nImax);
+                         Runs rt, int shape) {
+  const RbShape sh = rb_pick(shape, rb_fit_rows(rb_shape_bwd(nmax), nImax));
   if (root) ND_RB_LAUNCH(k_nd_bwd_root, sh, nImax, nnodes, runs_of(rt), st, a, loff, rt.tab);
   else ND_RB_LAUNCH(k_nd_bwd_inner, sh, nImax, nnodes, runs_of(rt), st, a, loff, rt.tab);
 }

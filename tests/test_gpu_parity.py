@@ -371,3 +371,41 @@ def test_separate_transport_and_update_equal_step(binding, cn):
         assert math.isclose(sb_["water_cut"], orun.wcut, rel_tol=1e-8, abs_tol=1e-14)
     a.close()
     b.close()
+
+
+def test_tuned_sweeps_match_oracle(binding):
+    """The autotuner of the interface-sweep launch shapes (mpm_tune) on the 256^2 workload: it
+    returns one shape per sweep launch and a tuned solve no slower than the fixed rule; the run's
+    next passes still match the oracle; runs created afterwards with the same decomposition start
+    from the tuned shapes, so two of them agree bitwise."""
+    cfg = inputs.config("c2")
+    K = inputs.permeability(cfg)
+    s0 = inputs.initial_saturation(cfg)
+    print("[gpu] autotuned sweeps at 256^2", flush=True)
+    forced = [None, "mpm", "mpm", "mrcm", "mpm"]
+    orun = splitting.start(cfg, K, s0)
+    r = _gpu_run(binding, cfg, K, s0)
+    r.start()
+    tr = r.tune(3)
+    assert len(tr["shapes"]) >= 1 and tr["ms_tuned"] <= tr["ms_rule"]
+    assert all(g in (16, 32, 64) and u >= 1 and rp >= 1 for g, u, rp in tr["shapes"])
+    print(f"    solve {tr['ms_rule']:.4f} -> {tr['ms_tuned']:.4f} ms, shapes {tr['shapes']}", flush=True)
+    for n in range(1, len(forced)):
+        splitting.step(orun, forced[n])
+        r.step(binding.FORCE_MRCM if forced[n] == "mrcm" else binding.FORCE_MPM)
+        ux, uy = r.velocity()
+        e = vel_rel_err(cfg, to_np(ux), to_np(uy), orun.ux, orun.uy)
+        assert e <= FP64_VEL_TOL and vel_face_err(to_np(ux), to_np(uy), orun.ux, orun.uy) <= FP64_FACE_TOL, (n, e)
+        assert sat_rel_err(to_np(r.saturation()), orun.s) <= FP64_SAT_TOL
+    assert r.stats()["error_word"] == 0
+    r.close()
+    outs = []
+    for _ in range(2):
+        r2 = _gpu_run(binding, cfg, K, s0)
+        r2.start()
+        for n in range(1, len(forced)):
+            r2.step(binding.FORCE_MRCM if forced[n] == "mrcm" else binding.FORCE_MPM)
+        ux, uy = r2.velocity()
+        outs.append((to_np(ux).copy(), to_np(uy).copy(), to_np(r2.saturation()).copy()))
+        r2.close()
+    assert all(np.array_equal(a, b) for a, b in zip(outs[0], outs[1]))
