@@ -57,7 +57,7 @@ def algorithmic_bytes(cfg: dict) -> dict:
     nfaces = ny * (nx + 1) + (ny + 1) * nx
     nsub = (nx // mx) * (ny // my)
     band = min(mx, my)
-    mf = 8 if band <= 8 else 16
+    mf = 8 if band <= 8 else 16 if band <= 16 else 32
     blocks = 8.0 * nsub * (mx * my // band) * (mf * (mf + 1) // 2)
     nb = 2 * (mx + my)
     ndof = 4 * (cfg["ne_x"] + cfg["ne_y"])

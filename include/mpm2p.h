@@ -78,7 +78,9 @@ typedef struct mpm_desc {
   int32_t abi_version;        /* MPM_ABI_VERSION */
   int32_t nx, ny;             /* fine grid (cells) */
   double lx, ly;              /* domain [0,lx] x [0,ly] */
-  int32_t sub_x, sub_y;       /* cells per subdomain; nx % sub_x == 0, ny % sub_y == 0 */
+  int32_t sub_x, sub_y;       /* cells per subdomain; nx % sub_x == 0, ny % sub_y == 0. Shorter
+                                 side up to 16 cells: at most 256 cells and 64 boundary faces;
+                                 17 to 32 cells: at most 1024 cells (FP64, mpm_order 0) */
   int32_t ne_x, ne_y;         /* interface elements per subdomain side along x and along y;
                                  sub_x % ne_x == 0, sub_y % ne_y == 0 (H-bar = H / n_e) */
   double alpha;               /* Robin parameter > 0; beta = alpha H / kappa (eq:beta) */

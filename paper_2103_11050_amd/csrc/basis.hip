@@ -250,7 +250,7 @@ k_basis_mfma(Geo g, const double* __restrict__ kap, const double* __restrict__ q
 // Returns whether the kappa^m line-block inverses were written (lines of 9..16 cells).
 bool launch_basis(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
                   double* leafK, LeafOut lo, double* fac, int32_t* err, Runs rt) {
-  if (g.nc / g.band > 16) {   // more lines than the matrix-core column blocks take
+  if (g.band > 16 || g.nc / g.band > 16) {   // longer lines or more lines than the matrix-core blocks take
     launch_basis_lines(st, g, kap, q, S, h, leafK, lo, fac, err, rt);
     return true;
   }

@@ -341,7 +341,8 @@ __global__ void __launch_bounds__(64) k_line_factor(Geo g, const double* __restr
     fac = at_off(fac, wo);
     err = at_off(err, wo);
   }
-  __shared__ double kl[256], tE[256], tN[256], dg[256];
+  constexpr int NC = Cap<MF>::NC;
+  __shared__ double kl[NC], tE[NC], tN[NC], dg[NC];
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
   LB<MF> L;
@@ -378,7 +379,8 @@ __global__ void __launch_bounds__(64) k_basis_lines(Geo g, const double* __restr
     fac = at_off(fac, wo);
     err = at_off(err, wo);
   }
-  __shared__ double kl[256], tE[256], tN[256], dg[256], x[256], wsh[64], hsh[64];
+  constexpr int NC = Cap<MF>::NC, NB = Cap<MF>::NB;
+  __shared__ double kl[NC], tE[NC], tN[NC], dg[NC], x[NC], wsh[NB], hsh[NB];
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int n = g.nc, nb = g.nb;
@@ -391,9 +393,9 @@ __global__ void __launch_bounds__(64) k_basis_lines(Geo g, const double* __restr
   bool ok = true;
   lb_factor<MF>(g, W, L, Es, ok);   // read back by lb_solve after the barrier below
   if (!ok && L.lane == 0) set_error(err, ERR_NOTSPD);
-  if (threadIdx.x < nb) {
-    const BFace f = bface(g, I, J, threadIdx.x);
-    wsh[threadIdx.x] = f.flen * bface_trans(g, f, kl[loc_index(g, f.i, f.j)]);
+  for (int fi = threadIdx.x; fi < nb; fi += 64) {
+    const BFace f = bface(g, I, J, fi);
+    wsh[fi] = f.flen * bface_trans(g, f, kl[loc_index(g, f.i, f.j)]);
   }
   for (int c = threadIdx.x; c < n; c += 64) {
     int i, j;
@@ -402,8 +404,7 @@ __global__ void __launch_bounds__(64) k_basis_lines(Geo g, const double* __restr
   }
   __syncthreads();
   lb_solve<MF>(g, W, L, Es, x);
-  if (threadIdx.x < nb) {
-    const int f = threadIdx.x;
+  for (int f = threadIdx.x; f < nb; f += 64) {
     const BFace bf = bface(g, I, J, f);
     const double rD = bf.kind == FACE_DIR ? bf.value : 0.0;
     const double h = bf.kind == FACE_NEU ? 0.0 : wsh[f] * (x[loc_index(g, bf.i, bf.j)] - rD);
@@ -419,8 +420,7 @@ __global__ void __launch_bounds__(64) k_basis_lines(Geo g, const double* __restr
     for (int c = threadIdx.x; c < n; c += 64) x[c] = c == cf ? 1.0 : 0.0;
     __syncthreads();
     lb_solve<MF>(g, W, L, Es, x);
-    if (threadIdx.x < nb) {
-      const int fr = threadIdx.x;
+    for (int fr = threadIdx.x; fr < nb; fr += 64) {
       const BFace br = bface(g, I, J, fr);
       if (smap_owner(nb, fr, f))
         Ss[smap_at(nb, fr, f)] = (fr == f ? wsh[f] : 0.0) - wsh[fr] * x[loc_index(g, br.i, br.j)] * wsh[f];
@@ -435,14 +435,41 @@ __global__ void __launch_bounds__(64) k_basis_lines(Geo g, const double* __restr
 // read issued before the first use: conductivities kappa^n and kappa^m at
 // T[(j + 1) * (mx + 2) + i + 1] and the previous velocity on the subdomain's faces go to LDS
 // (ux [my][mx + 1], uy [my + 1][mx]); q stays in registers, qc[s] for local cell
-// threadIdx.x + 64 s.
+// threadIdx.x + 64 s. Tiles of up to 16^2 cells have every read in flight at once; 32^2 tiles
+// (four times the values) are copied through LDS in a plain loop instead, which keeps the
+// values in flight within the register budget.
+template <int MF>
 __device__ __forceinline__ void load_halo_tiles(const Geo& g, int I, int J, const double* __restrict__ kap_n,
                                                 const double* __restrict__ kap_m, const double* __restrict__ uxm,
                                                 const double* __restrict__ uym, const double* __restrict__ q,
-                                                double* kn, double* km, double* ux, double* uy, double (&qc)[4]) {
-  constexpr int NH = (18 * 18 + 63) / 64, NF = (16 * 17 + 63) / 64;
+                                                double* kn, double* km, double* ux, double* uy,
+                                                double (&qc)[Cap<MF>::CPL]) {
+  constexpr int NH = (Cap<MF>::HALO + 63) / 64, NF = (Cap<MF>::NF + 63) / 64, CPL = Cap<MF>::CPL;
   const int TW = g.mx + 2, nh = TW * (g.my + 2);
   const int nfx = g.my * (g.mx + 1), nfy = (g.my + 1) * g.mx;
+  if constexpr (MF == 32) {
+    for (int e = threadIdx.x; e < nh; e += 64) {
+      const int ti = e % TW - 1, tj = e / TW - 1;
+      const int gi = I * g.mx + ti, gj = J * g.my + tj;
+      const bool edge_i = ti < 0 || ti >= g.mx, edge_j = tj < 0 || tj >= g.my;
+      const bool ok = !(edge_i && edge_j) && gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
+      const int gc = ok ? gj * g.nx + gi : 0;
+      kn[e] = kap_n[gc];
+      km[e] = kap_m[gc];
+    }
+    for (int e = threadIdx.x; e < nfx; e += 64)
+      ux[e] = uxm[(J * g.my + e / (g.mx + 1)) * (g.nx + 1) + I * g.mx + e % (g.mx + 1)];
+    for (int e = threadIdx.x; e < nfy; e += 64) uy[e] = uym[(J * g.my + e / g.mx) * g.nx + I * g.mx + e % g.mx];
+#pragma unroll
+    for (int s = 0; s < CPL; ++s) {
+      const int c = threadIdx.x + 64 * s;
+      int i, j;
+      loc_ij(g, c < g.nc ? c : 0, &i, &j);
+      qc[s] = q[(J * g.my + j) * g.nx + I * g.mx + i];
+    }
+    __syncthreads();
+    return;
+  }
   double a[NH], b[NH], fx[NF], fy[NF];
 #pragma unroll
   for (int s = 0; s < NH; ++s) {
@@ -463,7 +490,7 @@ __device__ __forceinline__ void load_halo_tiles(const Geo& g, int I, int J, cons
     fy[s] = uym[(J * g.my + ey / g.mx) * g.nx + I * g.mx + ey % g.mx];
   }
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
+  for (int s = 0; s < CPL; ++s) {
     const int c = threadIdx.x + 64 * s;
     int i, j;
     loc_ij(g, c < g.nc ? c : 0, &i, &j);
@@ -624,7 +651,11 @@ k_mpm_local_lb(Geo g0, const double* __restrict__ kap_n, const double* __restric
     vbnd = at_off(vbnd, wo);
     lo = leaf_at(lo, wo);
   }
-  __shared__ double knt[18 * 18], kmt[18 * 18], uxs[16 * 17], uys[17 * 16];
+  static_assert(!F32 || MF <= 16, "the precision form takes lines of at most 16 cells");
+  constexpr int CPL = Cap<MF>::CPL;
+  // halo tiles of the two conductivities, the x- and y-face tiles (later: line couplings,
+  // solution, boundary fluxes)
+  __shared__ double knt[Cap<MF>::HALO], kmt[Cap<MF>::HALO], uxs[Cap<MF>::NF], uys[Cap<MF>::NF];
   __shared__ double xtra[F32 ? 3 * 256 + 768 : 1];   // precision form: tE, tN, dg, refinement scratch
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
@@ -640,13 +671,13 @@ k_mpm_local_lb(Geo g0, const double* __restrict__ kap_n, const double* __restric
   if constexpr (F32) lb_load_f32<MF>(L, Es, g.nc / g.band, Ef);
   else if constexpr (RING) lb_ring_load<MF, NL, RING_D>(L, Es, Er);
   else if constexpr (NL > 0) lb_load_reg<MF, NL>(L, Es, E);
-  double qc[4];
-  load_halo_tiles(g, I, J, kap_n, kap_m, uxm, uym, q, knt, kmt, uxs, uys, qc);
+  double qc[CPL];
+  load_halo_tiles<MF>(g, I, J, kap_n, kap_m, uxm, uym, q, knt, kmt, uxs, uys, qc);
   mpm_face_v(g, I, J, knt, kmt, uxs, uys);
   __syncthreads();
-  double rhs[4];
+  double rhs[CPL];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
+  for (int s = 0; s < CPL; ++s) {
     const int c = threadIdx.x + 64 * s;
     rhs[s] = 0.0;
     if (c < n) {
@@ -661,7 +692,7 @@ k_mpm_local_lb(Geo g0, const double* __restrict__ kap_n, const double* __restric
   double* x = uxs;
   double* ty = knt;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
+  for (int s = 0; s < CPL; ++s) {
     const int c = threadIdx.x + 64 * s;
     if (c < n) x[c] = rhs[s];
   }
@@ -723,6 +754,7 @@ k_mpm_first(Geo g0, const double* __restrict__ kap_n, const double* __restrict__
             const double* __restrict__ ubnd, const double* __restrict__ vbnd, double* __restrict__ hg,
             double* __restrict__ wbnd, LeafOut lo, const RunTab* __restrict__ rt) {
   static_assert(sizeof(T) == 8, "FP64 only");
+  static_assert(MF <= 16, "lines of at most 16 cells");
   const Geo g = fix_geo<FX>(g0);
   {
     const int64_t wo = ws_off(rt);
@@ -751,7 +783,7 @@ k_mpm_first(Geo g0, const double* __restrict__ kap_n, const double* __restrict__
   const double* Es = fac + efac_off<MF>(g, sub);
   if constexpr (NL > 0) lb_load_reg<MF, NL>(L, Es, E);
   double qc[4];
-  load_halo_tiles(g, I, J, kap_n, kap_m, uxm, uym, q, knt, kmt, uxs, uys, qc);
+  load_halo_tiles<MF>(g, I, J, kap_n, kap_m, uxm, uym, q, knt, kmt, uxs, uys, qc);
   mpm_face_v(g, I, J, knt, kmt, uxs, uys, rx, ry);
   auto kmf = [&](int i, int j) { return kmt[(j + 1) * TW + i + 1]; };
   fill_ycoup_k(g, kmf, ty);
@@ -899,8 +931,10 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
     flag = at_off(flag, wo);
     err = at_off(err, wo);
   }
+  static_assert(!F32 || MF <= 16, "the precision form takes lines of at most 16 cells");
+  constexpr int NC = Cap<MF>::NC, CPL = Cap<MF>::CPL;
   // the conductivity tile is dead once the weights are built and then holds the solution
-  __shared__ double kl[256], w[64], tE[256], tN[256], dg[256];
+  __shared__ double kl[NC], w[Cap<MF>::NB], tE[NC], tN[NC], dg[NC];
   __shared__ double wsh[F32 ? 768 : 1];
   double* x = kl;
   const int sub = blockIdx.x;
@@ -933,9 +967,9 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
     }
     w[f] = u;
   }
-  double qc[4];
+  double qc[CPL];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
+  for (int s = 0; s < CPL; ++s) {
     const int c = threadIdx.x + 64 * s;
     int i, j;
     loc_ij(g, c < n ? c : 0, &i, &j);
@@ -944,7 +978,7 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
   __syncthreads();
   fill_trans(g, I, J, kl, 1, tE, tN, dg);
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
+  for (int s = 0; s < CPL; ++s) {
     const int c = threadIdx.x + 64 * s;
     if (c >= n) continue;
     int i, j;
@@ -1029,7 +1063,8 @@ template <int MF, typename T>
 __global__ void __launch_bounds__(64)
 k_ds_factor(Geo g, const double* __restrict__ kap_n, T* __restrict__ Escr, const int32_t* __restrict__ list,
             const int32_t* __restrict__ count, int32_t* err, const RunTab* __restrict__ rt) {
-  __shared__ double kl[256], tE[256], tN[256], dg[256];
+  constexpr int NC = Cap<MF>::NC;
+  __shared__ double kl[NC], tE[NC], tN[NC], dg[NC];
   {
     const int64_t wo = ws_off(rt);
     kap_n = at_off(kap_n, wo);
@@ -1058,27 +1093,33 @@ k_ds_factor(Geo g, const double* __restrict__ kap_n, T* __restrict__ Escr, const
 
 // ---------------------------------------------------------------------------------------------
 
-static int line_mf(const Geo& g) { return g.band <= 8 ? 8 : 16; }
+// Lines padded to MF cells: 8 for lines of up to 8, 16 up to 16, 32 up to 32 (the plan refuses
+// longer lines).
+static int line_mf(const Geo& g) { return g.band <= 8 ? 8 : g.band <= 16 ? 16 : 32; }
 
 void launch_basis_lines(hipStream_t st, const Geo& g, const double* kap, const double* q, double* S, double* h,
                         double* leafK, LeafOut lo, double* fac, int32_t* err, Runs rt) {
   const dim3 grid(g.nsub, 1, runs_of(rt));
   if (line_mf(g) == 8)
     hipLaunchKernelGGL(k_basis_lines<8>, grid, dim3(64), 0, st, g, kap, q, S, h, leafK, lo, fac, err, rt.tab);
-  else hipLaunchKernelGGL(k_basis_lines<16>, grid, dim3(64), 0, st, g, kap, q, S, h, leafK, lo, fac, err, rt.tab);
+  else if (line_mf(g) == 16)
+    hipLaunchKernelGGL(k_basis_lines<16>, grid, dim3(64), 0, st, g, kap, q, S, h, leafK, lo, fac, err, rt.tab);
+  else hipLaunchKernelGGL(k_basis_lines<32>, grid, dim3(64), 0, st, g, kap, q, S, h, leafK, lo, fac, err, rt.tab);
 }
 
 void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double* fac, int32_t* err, Runs rt) {
   const dim3 grid(g.nsub, 1, runs_of(rt));
   if (line_mf(g) == 8) hipLaunchKernelGGL(k_line_factor<8>, grid, dim3(64), 0, st, g, kap, fac, err, rt.tab);
-  else hipLaunchKernelGGL(k_line_factor<16>, grid, dim3(64), 0, st, g, kap, fac, err, rt.tab);
+  else if (line_mf(g) == 16) hipLaunchKernelGGL(k_line_factor<16>, grid, dim3(64), 0, st, g, kap, fac, err, rt.tab);
+  else hipLaunchKernelGGL(k_line_factor<32>, grid, dim3(64), 0, st, g, kap, fac, err, rt.tab);
 }
 
-// line length padded to MF in {8, 16}; the solve keeps the blocks in registers for the
-// common line counts 8 and 16, and square 8^2 / 16^2 subdomains get compile-time shapes
+// line length padded to MF in {8, 16, 32}; the solve keeps the blocks in registers for the
+// common line counts 8 and 16, and square 8^2 / 16^2 subdomains get compile-time shapes; lines
+// of 17 to 32 cells (WIDE kernels only) stream their blocks from memory
 #define MPM_LB_LAUNCH(KERNEL, ...) \
   hipLaunchKernelGGL((KERNEL), dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, __VA_ARGS__)
-#define MPM_LB_DISPATCH(KERNEL, FIXOK, ...)                                                        \
+#define MPM_LB_DISPATCH16(KERNEL, FIXOK, ...)                                                      \
   do {                                                                                             \
     const int nl_ = g.nc / g.band;                                                                 \
     const bool sq8_ = (FIXOK) && g.mx == 8 && g.my == 8, sq16_ = (FIXOK) && g.mx == 16 && g.my == 16; \
@@ -1086,22 +1127,27 @@ void launch_line_factor(hipStream_t st, const Geo& g, const double* kap, double*
       if (sq8_) MPM_LB_LAUNCH((KERNEL<8, 8, double, 8>), __VA_ARGS__);                             \
       else if (nl_ == 8) MPM_LB_LAUNCH((KERNEL<8, 8, double, 0>), __VA_ARGS__);                    \
       else MPM_LB_LAUNCH((KERNEL<8, 0, double, 0>), __VA_ARGS__);                                  \
-    } else {                                                                                       \
+    } else if (line_mf(g) == 16) {                                                                 \
       if (sq16_) MPM_LB_LAUNCH((KERNEL<16, 16, double, 16>), __VA_ARGS__);                         \
       else if (nl_ == 16) MPM_LB_LAUNCH((KERNEL<16, 16, double, 0>), __VA_ARGS__);                 \
       else MPM_LB_LAUNCH((KERNEL<16, 0, double, 0>), __VA_ARGS__);                                 \
     }                                                                                              \
   } while (0)
+#define MPM_LB_DISPATCH(KERNEL, FIXOK, ...)                                                        \
+  do {                                                                                             \
+    if (line_mf(g) == 32) MPM_LB_LAUNCH((KERNEL<32, 0, double, 0>), __VA_ARGS__);                  \
+    else MPM_LB_DISPATCH16(KERNEL, FIXOK, __VA_ARGS__);                                            \
+  } while (0)
 
-// precision form: FP32 blocks, any line count up to 16; square 8^2 / 16^2 subdomains get
-// compile-time shapes
+// precision form: FP32 blocks, lines of up to 16 cells and any line count up to 16 (the plan
+// refuses the rest); square 8^2 / 16^2 subdomains get compile-time shapes
 #define MPM_LB_DISPATCH_F32(KERNEL, ...)                                                           \
   do {                                                                                             \
     const bool sq8_ = g.mx == 8 && g.my == 8, sq16_ = g.mx == 16 && g.my == 16;                    \
     if (line_mf(g) == 8) {                                                                         \
       if (sq8_) MPM_LB_LAUNCH((KERNEL<8, 16, float, 8>), __VA_ARGS__);                             \
       else MPM_LB_LAUNCH((KERNEL<8, 16, float, 0>), __VA_ARGS__);                                  \
-    } else {                                                                                       \
+    } else if (line_mf(g) == 16) {                                                                 \
       if (sq16_) MPM_LB_LAUNCH((KERNEL<16, 16, float, 16>), __VA_ARGS__);                          \
       else MPM_LB_LAUNCH((KERNEL<16, 16, float, 0>), __VA_ARGS__);                                 \
     }                                                                                              \
@@ -1117,7 +1163,8 @@ void launch_mpm_first(hipStream_t st, const Geo& g, const double* kn, const doub
                       const double* uym, const double* q, const double* fac, const double* y,
                       const int32_t* sub_dofs, const double* ubnd, const double* vbnd, double* h, double* wbnd,
                       LeafOut lo, Runs rt) {
-  MPM_LB_DISPATCH(k_mpm_first, true, g, kn, km, uxm, uym, q, fac, y, sub_dofs, ubnd, vbnd, h, wbnd, lo, rt.tab);
+  // lines of at most 16 cells (the plan refuses the first-order term for longer ones)
+  MPM_LB_DISPATCH16(k_mpm_first, true, g, kn, km, uxm, uym, q, fac, y, sub_dofs, ubnd, vbnd, h, wbnd, lo, rt.tab);
 }
 
 template <typename T>
@@ -1126,7 +1173,10 @@ static void ds_factor_any(hipStream_t st, const Geo& g, const double* kap_n, T* 
   const dim3 grid(std::min(g.nsub, 1024), 1, runs_of(rt));
   if (line_mf(g) == 8)
     hipLaunchKernelGGL((k_ds_factor<8, T>), grid, dim3(64), 0, st, g, kap_n, Escr, list, count, err, rt.tab);
-  else hipLaunchKernelGGL((k_ds_factor<16, T>), grid, dim3(64), 0, st, g, kap_n, Escr, list, count, err, rt.tab);
+  else if (line_mf(g) == 16)
+    hipLaunchKernelGGL((k_ds_factor<16, T>), grid, dim3(64), 0, st, g, kap_n, Escr, list, count, err, rt.tab);
+  else if constexpr (sizeof(T) == 8)   // FP32 blocks: lines of at most 16 cells
+    hipLaunchKernelGGL((k_ds_factor<32, T>), grid, dim3(64), 0, st, g, kap_n, Escr, list, count, err, rt.tab);
 }
 
 void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, double* Escr, const int32_t* list,
@@ -1173,7 +1223,7 @@ void launch_downscale(hipStream_t st, const Geo& g, const double* kap_s, const d
 }
 
 size_t line_factor_doubles(int nsub, int nc, int band) {
-  const int mf = band <= 8 ? 8 : 16;
+  const int mf = band <= 8 ? 8 : band <= 16 ? 16 : 32;
   return size_t(nsub) * (nc / band) * (mf * (mf + 1) / 2);
 }
 

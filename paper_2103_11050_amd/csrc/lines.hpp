@@ -37,6 +37,20 @@ struct LB {
   __device__ int col(int t) const { return IL ? cg + LPR * t : cg * EPL + t; }
 };
 
+// Capacity of the per-subdomain LDS tiles and per-lane cell arrays of a kernel whose lines are
+// padded to MF cells: subdomains of at most S x S cells (16 for MF <= 16, 32 for MF = 32), one
+// wavefront of 64 lanes, CPL cells per lane, NB boundary faces, NF faces of one direction and a
+// one-cell halo tile of HALO cells.
+template <int MF>
+struct Cap {
+  static constexpr int S = MF == 32 ? 32 : 16;
+  static constexpr int NC = S * S;
+  static constexpr int CPL = NC / 64;
+  static constexpr int NB = 4 * S;
+  static constexpr int NF = S * (S + 1);
+  static constexpr int HALO = (S + 2) * (S + 2);
+};
+
 // Kept line-block inverses are symmetric: each MF x MF block is stored as its upper triangle,
 // row by row (MF (MF + 1) / 2 entries); entry (row, col) of the block sits at lb_pk(min, max).
 template <int MF>

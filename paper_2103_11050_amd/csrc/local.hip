@@ -44,13 +44,13 @@ k_kappa(Geo g, const double* __restrict__ s, double* __restrict__ s_new, const d
   const double mu_w = scal[SC_MUW], mu_o = scal[SC_MUO];
   const int sub = blockIdx.x;
   const int I = sub % g.Sx, J = sub / g.Sx;
-  const int c = threadIdx.x;
   double a = 0.0, bb = 0.0;
   int diff = 0;
   // block-uniform: the tile touches the domain boundary
   const bool edge = wc && (I == 0 || J == 0 || I == g.Sx - 1 || J == g.Sy - 1);
   double wq = 0.0, ww = 0.0;
-  if (c < g.nc) {
+  // one cell per thread up to 256 cells per tile; larger tiles take several per thread
+  for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
     const int gc = (J * g.my + c / g.mx) * g.nx + I * g.mx + c % g.mx;
     double sv;
     if constexpr (SAT) {
@@ -66,8 +66,8 @@ k_kappa(Geo g, const double* __restrict__ s, double* __restrict__ s_new, const d
       if (gi == g.nx - 1) out += g.hy * fmax(ux[size_t(gj) * (g.nx + 1) + g.nx], 0.0);
       if (gj == 0) out += g.hx * fmax(-uy[gi], 0.0);
       if (gj == g.ny - 1) out += g.hx * fmax(uy[size_t(g.ny) * g.nx + gi], 0.0);
-      wq = out;
-      ww = out * frac_w(sv, scal[SC_MRATIO]);
+      wq += out;
+      ww += out * frac_w(sv, scal[SC_MRATIO]);
     }
     const double Kc = K[gc];
     // the state the method needs: s in [0, 1] up to rounding, K finite and positive (NaN
@@ -79,9 +79,9 @@ k_kappa(Geo g, const double* __restrict__ s, double* __restrict__ s_new, const d
     kap_n[gc] = kn;
     const double km = kap_m[gc];
     const double dd = kn - km;
-    a = dd * dd;
-    bb = km * km;
-    diff = kn != km;
+    a += dd * dd;
+    bb += km * km;
+    diff |= kn != km;
   }
   sa[threadIdx.x] = a;
   sb[threadIdx.x] = bb;
@@ -291,6 +291,62 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
   }
 }
 
+// The same reconstruction for subdomains with 65 to 128 boundary faces: one thread per face
+// over two wavefronts; the mirrored entries S(f, f - e) are read from memory, not from another
+// lane.
+__global__ void __launch_bounds__(128)
+k_flux_wide(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, const double* __restrict__ hg,
+            const double* __restrict__ vbnd, const double* __restrict__ y, const int32_t* __restrict__ sub_dofs,
+            double* __restrict__ ubnd, int with_v, const RunTab* __restrict__ rt) {
+  __shared__ double r[128];
+  const int64_t wo = ws_off(rt);
+  kap_m = at_off(kap_m, wo);
+  Sg = at_off(Sg, wo);
+  hg = at_off(hg, wo);
+  vbnd = at_off(vbnd, wo);
+  y = at_off(y, wo);
+  sub_dofs = at_off(sub_dofs, wo);
+  ubnd = at_off(ubnd, wo);
+  const int sub = blockIdx.x;
+  const int I = sub % g.Sx, J = sub / g.Sx;
+  const int nb = g.nb;
+  const int f = threadIdx.x;
+  const bool act = f < nb;
+  const double* Ss = Sg + size_t(sub) * smap_doubles(nb);
+  BFace bf;
+  if (act) {
+    bf = bface(g, I, J, f);
+    double rv = 0.0;
+    if (bf.kind == FACE_ROB) {
+      const int gc = (J * g.my + bf.j) * g.nx + I * g.mx + bf.i;
+      rv = robin_datum(g, I, J, bf, kap_m[gc], sub_dofs + size_t(sub) * g.ndmax, y);
+    }
+    r[f] = rv;
+  }
+  __syncthreads();
+  if (!act) return;
+  // S_i r over the wrapped diagonals in the order of k_flux: S(f, f + d) for d <= nb / 2, then
+  // S(f, f - e) for the other columns
+  const int D = nb / 2;
+  double acc = hg[size_t(sub) * nb + f];
+  for (int d = 0; d <= D; ++d) {
+    const int t = f + d < nb ? f + d : f + d - nb;
+    acc -= Ss[d * nb + f] * r[t];
+  }
+  for (int e = 1; e < nb - D; ++e) {
+    const int t = f >= e ? f - e : f - e + nb;
+    acc -= Ss[e * nb + t] * r[t];
+  }
+  double u;
+  if (bf.kind == FACE_NEU) u = bf.value;
+  else u = acc / bf.flen + (with_v ? vbnd[size_t(sub) * nb + f] : 0.0);
+  if (with_v == 2) {
+    if (bf.kind != FACE_NEU) ubnd[size_t(sub) * nb + f] += u;
+  } else {
+    ubnd[size_t(sub) * nb + f] = u;
+  }
+}
+
 // ---------------------------------------------------------------------- launchers
 
 void launch_kappa(hipStream_t st, const Geo& g, const double* s, const double* K, double* kn, const double* km,
@@ -298,7 +354,8 @@ void launch_kappa(hipStream_t st, const Geo& g, const double* s, const double* K
                   double* host, const double* wc_ux, const double* wc_uy, Runs rt, double* s_new, double area,
                   hipStream_t st_red, hipEvent_t ev_red) {
   const unsigned nr = runs_of(rt);
-  // one thread per cell of the tile: the power of two from 64 to 256 that covers it
+  // one thread per cell of the tile: the power of two from 64 to 256 that covers it (256 for
+  // larger tiles)
   const unsigned bs = g.nc <= 64 ? 64 : g.nc <= 128 ? 128 : 256;
   if (s_new)
     hipLaunchKernelGGL(k_kappa<true>, dim3(g.nsub, 1, nr), dim3(bs), 0, st, g, s, s_new, K, kn, km, red, flag, list,
@@ -322,8 +379,12 @@ void launch_dt(hipStream_t st, int nsub, const double* red_rate, const double* r
 void launch_flux(hipStream_t st, const Geo& g, const double* km, const double* S, const double* h,
                  const double* vbnd, const double* y, const int32_t* sub_dofs, double* ubnd, int with_v,
                  Runs rt) {
-  hipLaunchKernelGGL(k_flux, dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, g, km, S, h, vbnd, y, sub_dofs, ubnd,
-                     with_v, rt.tab);
+  if (g.nb > 64)
+    hipLaunchKernelGGL(k_flux_wide, dim3(g.nsub, 1, runs_of(rt)), dim3(128), 0, st, g, km, S, h, vbnd, y, sub_dofs,
+                       ubnd, with_v, rt.tab);
+  else
+    hipLaunchKernelGGL(k_flux, dim3(g.nsub, 1, runs_of(rt)), dim3(64), 0, st, g, km, S, h, vbnd, y, sub_dofs, ubnd,
+                       with_v, rt.tab);
 }
 
 }  // namespace mpm

@@ -51,16 +51,22 @@ mpm_status validate(const mpm_desc& d, std::string* why) {
   if (!(d.breakthrough_cut > 0 && d.breakthrough_cut <= 1)) return bad("breakthrough_cut must lie in (0,1]");
   const int band = std::min(d.sub_x, d.sub_y);
   const long nc = long(d.sub_x) * d.sub_y;
-  if (nc * (band + 1) * 8 > 64 * 1024) return bad("subdomain too large for the local factorisation (band storage > 64 KiB)");
-  // local kernels: lines of at most 16 cells, at most 256 cells, 64 boundary faces and 272
-  // faces of each direction per subdomain (one wavefront, fixed LDS tiles)
-  if (band > 16) return bad("subdomains whose shorter side exceeds 16 cells are not supported");
-  if (nc > 256) return bad("more than 256 cells per subdomain");
-  if (d.sub_x + d.sub_y > 32) return bad("more than 64 boundary faces per subdomain");
-  if (long(d.sub_y) * (d.sub_x + 1) > 272 || long(d.sub_y + 1) * d.sub_x > 272)
-    return bad("more than 272 faces of one direction per subdomain");
+  // local kernels (one wavefront per subdomain, fixed LDS tiles): lines of at most 16 cells
+  // with at most 256 cells, 64 boundary faces and 272 faces of each direction per subdomain,
+  // or lines of 17 to 32 cells with at most 1024 cells, 128 boundary faces and 1056 faces of
+  // each direction
+  if (band > 32) return bad("subdomains whose shorter side exceeds 32 cells are not supported");
+  const bool wide = band > 16;
+  const long cap_nc = wide ? 1024 : 256, cap_nb = wide ? 128 : 64, cap_nf = wide ? 1056 : 272;
+  if (nc > cap_nc) return bad(wide ? "more than 1024 cells per subdomain" : "more than 256 cells per subdomain with lines of at most 16 cells");
+  if (2 * (long(d.sub_x) + d.sub_y) > cap_nb)
+    return bad(wide ? "more than 128 boundary faces per subdomain" : "more than 64 boundary faces per subdomain");
+  if (long(d.sub_y) * (d.sub_x + 1) > cap_nf || long(d.sub_y + 1) * d.sub_x > cap_nf)
+    return bad("too many faces of one direction per subdomain");
   if (d.mpm_order != 0 && d.mpm_order != 1) return bad("mpm_order must be 0 or 1");
   if (d.mpm_order == 1 && d.precision != MPM_PREC_FP64) return bad("the first-order term is FP64 only");
+  if (d.mpm_order == 1 && wide) return bad("the first-order term takes lines of at most 16 cells");
+  if (d.precision == MPM_PREC_FP32_REFINE && wide) return bad("the precision form takes lines of at most 16 cells");
   if (d.iface_degree != 0 && d.iface_degree != 1) return bad("iface_degree must be 0 or 1");
   if (d.iface_degree == 1 && (d.sub_x / d.ne_x < 2 || d.sub_y / d.ne_y < 2))
     return bad("linear interface spaces need at least two fine faces per interface element");
@@ -246,7 +252,7 @@ void build_plan(const mpm_desc& d, Plan* p) {
   P.off_uxm = take(nfx * 8);
   P.off_uym = take(nfy * 8);
   {
-    const int mf = P.band <= 8 ? 8 : 16;
+    const int mf = P.band <= 8 ? 8 : P.band <= 16 ? 16 : 32;
     P.off_fac = take(size_t(P.nsub) * (P.nc / P.band) * (mf * (mf + 1) / 2) * 8);
   }
   P.off_dinv = take(size_t(P.nsub) * P.nc * 8);
@@ -254,7 +260,7 @@ void build_plan(const mpm_desc& d, Plan* p) {
   P.off_h = take(size_t(P.nsub) * P.nb * 8);
   P.off_vbnd = take(size_t(P.nsub) * P.nb * 8);
   {
-    const int mf = P.band <= 8 ? 8 : 16;
+    const int mf = P.band <= 8 ? 8 : P.band <= 16 ? 16 : 32;
     P.off_dsE = take(size_t(P.nsub) * (P.nc / P.band) * (mf * (mf + 1) / 2) * 8);
     P.off_nfac = take(size_t(P.nsub) * (P.nc / P.band) * (mf * (mf + 1) / 2) * 8);
     // precision form: FP32 copies of the three block sets

@@ -165,12 +165,11 @@ def random_problem(seed: int, nx: int, ny: int, sub_x: int, sub_y: int, ne_x: in
 
 def batch_workload(n: int = 256) -> list[dict]:
     """Batched form: n realisations of uneven sizes, class r mod 3 -> 64^2 cells in 8^2
-    subdomains, 128^2 in 16^2, 256^2 in 16^2 (subdomain sides are limited to 16 cells here);
-    4 interface elements per side, log-variance 4, correlation length 0.05, seed 1000 + r,
-    viscosity ratio 100, eta = 0.1."""
+    subdomains, 128^2 in 16^2, 256^2 in 32^2; 4 interface elements per side, log-variance 4,
+    correlation length 0.05, seed 1000 + r, viscosity ratio 100, eta = 0.1."""
     out = []
     for r in range(n):
-        nx, sub = ((64, 8), (128, 16), (256, 16))[r % 3]
+        nx, sub = ((64, 8), (128, 16), (256, 32))[r % 3]
         cfg = dict(_BASE, nx=nx, ny=nx, sub_x=sub, sub_y=sub, ne_x=4, ne_y=4, mu_o=100.0, eta=0.1,
                    sigma2=4.0, corr_len=0.05, seed=1000 + r, steps=0)
         cfg["bc_kind"] = list(cfg["bc_kind"])

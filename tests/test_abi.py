@@ -67,10 +67,10 @@ def test_no_pressure_boundary_rejected(lib):
 
 
 @pytest.mark.parametrize("shape", [
-    (34, 34, 17, 17, 1, 1),     # lines longer than 16 cells
-    (48, 20, 24, 10, 4, 2),     # 240 cells but sides summing past 32 (boundary faces > 64)
-    (64, 32, 32, 8, 4, 2),      # x-faces of a tile past 272
-    (40, 40, 20, 20, 4, 4),     # shorter side 20
+    (66, 66, 33, 33, 1, 1),     # lines longer than 32 cells
+    (64, 66, 32, 33, 4, 3),     # lines of 32 cells, but 1056 cells (more than 1024)
+    (48, 20, 24, 10, 4, 2),     # lines of 10: 240 cells but sides summing past 32 (boundary faces > 64)
+    (64, 32, 32, 8, 4, 2),      # lines of 8: x-faces of a tile past 272
 ])
 def test_oversized_subdomain_rejected(lib, shape):
     nx, ny, mx, my, nex, ney = shape
@@ -81,14 +81,28 @@ def test_oversized_subdomain_rejected(lib, shape):
 
 @pytest.mark.parametrize("shape", [(40, 20, 20, 10, 20, 10), (48, 16, 24, 8, 4, 2), (20, 40, 10, 20, 5, 4)])
 def test_many_line_subdomains_accepted(lib, shape):
-    """Subdomains with more than 16 lines (the longer side up to 32 cells, at most 256 cells)
-    are taken in FP64; the precision form keeps at most 16 lines."""
+    """Subdomains with lines of at most 16 cells and more than 16 lines (the longer side up to 32
+    cells, at most 256 cells) are taken in FP64; the precision form keeps at most 16 lines."""
     nx, ny, mx, my, nex, ney = shape
     cfg = inputs.config("c1", nx=nx, ny=ny, sub_x=mx, sub_y=my, ne_x=nex, ne_y=ney)
     st, size = _size(cfg)
     assert st == 0 and size > 0
     st32, _ = _size(cfg, precision=binding.PREC_FP32_REFINE)
     assert st32 == binding.MPM_EINVAL
+
+
+@pytest.mark.parametrize("shape", [(34, 34, 17, 17, 1, 1), (40, 40, 20, 20, 4, 4), (64, 64, 32, 32, 4, 4),
+                                   (96, 48, 32, 24, 4, 4)])
+def test_wide_subdomains_accepted(lib, shape):
+    """Subdomains whose shorter side has 17 to 32 cells (at most 1024 cells) are taken in FP64
+    with the zeroth-order MPM-2P term; the precision form and the first-order term keep lines
+    of at most 16 cells."""
+    nx, ny, mx, my, nex, ney = shape
+    cfg = inputs.config("c1", nx=nx, ny=ny, sub_x=mx, sub_y=my, ne_x=nex, ne_y=ney)
+    st, size = _size(cfg)
+    assert st == 0 and size > 0
+    assert _size(cfg, precision=binding.PREC_FP32_REFINE)[0] == binding.MPM_EINVAL
+    assert _size(cfg, mpm_order=1)[0] == binding.MPM_EINVAL
 
 
 def test_first_order_term_is_fp64_only(lib):

@@ -365,8 +365,8 @@ def _oracle_compare(cfg, orun, state, label):
 
 
 def test_batch_classes_match_oracle(binding):
-    """One realisation of each class of the batched workload (64^2 in 8^2 subdomains, 128^2 and
-    256^2 in 16^2, 4 elements per side, log-variance 4, M = 100) stepped together in one batch
+    """One realisation of each class of the batched workload (64^2 in 8^2 subdomains, 128^2 in
+    16^2, 256^2 in 32^2, 4 elements per side, log-variance 4, M = 100) stepped together in one batch
     for 30 passes of Algorithm 1 against the FP64 oracle run alone on the same inputs (the 64^2
     run with eta = 0.02, so that its switch takes basis updates inside the window)."""
     from oracle import splitting

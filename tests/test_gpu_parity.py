@@ -52,6 +52,10 @@ SHAPES = [
     (48, 16, 24, 8, 4, 2),      # 24 lines of 8 cells
     (20, 40, 10, 20, 5, 4),     # lines along x, 20 of them
     (64, 64, 16, 16, 16, 16),   # 128 interface unknowns per inner subdomain (the largest)
+    (64, 64, 32, 32, 4, 4),     # 2 x 2 subdomains of 32^2 (1024 cells, 128 boundary faces)
+    (96, 48, 32, 24, 4, 4),     # lines of 24 along y, 3 x 2 subdomains
+    (34, 34, 17, 17, 1, 1),     # lines of 17 padded to 32
+    (20, 60, 20, 30, 4, 5),     # one column of 20 x 30 subdomains (100 boundary faces)
 ]
 
 
@@ -151,6 +155,15 @@ def test_many_line_subdomains_mixed(binding):
     and MPM-2P steps against the oracle."""
     cfg, K = inputs.random_problem(13, 60, 30, 20, 10, 4, 2, sigma2=3.0, corr_len=0.15, eta=0.002, mu_o=40.0)
     orun = _compare_runs(binding, cfg, K, 16, "many-line mixed")
+    branches = [h["branch"] for h in orun.history]
+    assert "mpm" in branches[1:] and "mrcm" in branches[1:]
+
+
+def test_wide_subdomains_mixed(binding):
+    """Subdomains of 32 x 32 cells (lines of 32, 128 boundary faces): MRCM updates and MPM-2P
+    steps against the oracle."""
+    cfg, K = inputs.random_problem(17, 96, 64, 32, 32, 4, 4, sigma2=3.0, corr_len=0.15, eta=0.002, mu_o=40.0)
+    orun = _compare_runs(binding, cfg, K, 16, "32^2 subdomains mixed")
     branches = [h["branch"] for h in orun.history]
     assert "mpm" in branches[1:] and "mrcm" in branches[1:]
 

@@ -36,7 +36,7 @@ def test_x1_permeability_contrast():
 
 def test_batch_and_serve_workloads():
     b = inputs.batch_workload(9)
-    assert [(c["nx"], c["sub_x"]) for c in b[:3]] == [(64, 8), (128, 16), (256, 16)]
+    assert [(c["nx"], c["sub_x"]) for c in b[:3]] == [(64, 8), (128, 16), (256, 32)]
     assert [c["seed"] for c in b] == list(range(1000, 1009))
     r = inputs.serve_requests(64)
     assert {c["nx"] for c in r} <= {128, 256, 512}
