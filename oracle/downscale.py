@@ -9,6 +9,14 @@ The problem is determined up to a constant; the pressure of the subdomain's firs
 (lowest row, then lowest column) is fixed to zero. Interior faces take the two-point flux of
 the local pressure, boundary faces keep u-bar.
 
+Such a problem has a solution only if the net outflow through dOmega_i equals the source.
+The exact coarse-stage fluxes satisfy this, because each interface element carries the same
+flux integral on both sides. In floating point the data miss it by a rounding-level defect;
+with the first cell's equation dropped, that defect would all leave through the pinned
+cell's faces. Instead, the defect divided by |Omega_i| is added to the source of every cell
+before the pinned solve. The corrected data are compatible, and in exact arithmetic the
+shift is zero.
+
 The same downscaling is used after an MRCM solve (with kappa^m), where the paper cites a
 downscaling method it does not describe.
 """
@@ -28,7 +36,8 @@ def boundary_outflux(dec: Decomposition, ux, uy, I, J):
 
 
 def downscale(cfg, kappa_star, ux_bar, uy_bar, q=None):
-    """Returns (ux, uy, defects); defects[i] = sum |f| w_f - sum |c| q_c on subdomain i."""
+    """Returns (ux, uy, defects); defects[i] = sum |f| w_f - sum |c| q_c on subdomain i (of the
+    data, before the compatibility shift)."""
     dec = Decomposition(cfg)
     if q is None:
         q = np.zeros_like(kappa_star)
@@ -40,12 +49,15 @@ def downscale(cfg, kappa_star, ux_bar, uy_bar, q=None):
         kap = kappa_star[j0:j1, i0:i1]
         w = boundary_outflux(dec, ux_bar, uy_bar, I, J)
         sides = [Side(np.full(len(w[sd]), NEU), np.zeros(len(w[sd])), w[sd]) for sd in (W, E, S, N)]
+        src = q[j0:j1, i0:i1]
+        flux = dec.hy * (w[W].sum() + w[E].sum()) + dec.hx * (w[S].sum() + w[N].sum())
+        defect = flux - dec.hx * dec.hy * src.sum()
+        src = src + defect / (src.size * dec.hx * dec.hy)   # compatible data
         A = block_matrix(kap, dec.hx, dec.hy, sides, pin=(0, 0))
-        b = block_rhs(kap, dec.hx, dec.hy, sides, q[j0:j1, i0:i1], pin=(0, 0))
+        b = block_rhs(kap, dec.hx, dec.hy, sides, src, pin=(0, 0))
         p = spla.spsolve(A, b)
         lux, luy, _ = block_fluxes(kap, dec.hx, dec.hy, sides, p)
         ux[j0:j1, i0 + 1:i1] = lux[:, 1:-1]
         uy[j0 + 1:j1, i0:i1] = luy[1:-1, :]
-        flux = dec.hy * (w[W].sum() + w[E].sum()) + dec.hx * (w[S].sum() + w[N].sum())
-        defects.append(flux - dec.hx * dec.hy * q[j0:j1, i0:i1].sum())
+        defects.append(defect)
     return ux, uy, np.array(defects)

@@ -904,8 +904,11 @@ k_mpm_first(Geo g0, const double* __restrict__ kap_n, const double* __restrict__
 // ---------------------------------------------------------------------------------------------
 // Downscaling (eq. mpm_upd): all-Neumann problem with conductivity kap_s per subdomain, the
 // mean of both sides' boundary fluxes on Gamma, the own flux on the physical boundary, the
-// first cell pinned. Writes the velocity on the faces the subdomain owns, the largest outflow
-// rate per cell volume and the inflow through the physical boundary.
+// first cell pinned. The data are made compatible first: the rounding-level defect (net
+// outflow minus source, zero for the exact fluxes) is spread over the cells' sources, so that it
+// does not leave through the pinned cell's faces alone. Writes the velocity on the faces the
+// subdomain owns, the largest outflow rate per cell volume and the inflow through the physical
+// boundary.
 // With T = float (MPM-2P steps of the precision form; store = 0) the blocks are FP32 and the
 // solve is refined in FP64. The blocks are requested at entry.
 template <int MF, int NL, typename T, int FX>
@@ -954,6 +957,7 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
     if (!store) lb_load_reg<MF, NL>(L, Es, E);
   }
   load_tile2(g, I, J, kap_s, kl);
+  double defect = 0.0;   // net outflow minus source
   for (int f = threadIdx.x; f < nb; f += blockDim.x) {
     BFace bf = bface(g, I, J, f);
     double u = ubnd[size_t(sub) * nb + f];
@@ -966,6 +970,7 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
       u = 0.5 * (u - ubnd[size_t(ns) * nb + nf]);
     }
     w[f] = u;
+    defect += (f < 2 * g.my ? g.hy : g.hx) * u;
   }
   double qc[CPL];
 #pragma unroll
@@ -974,7 +979,11 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
     int i, j;
     loc_ij(g, c < n ? c : 0, &i, &j);
     qc[s] = q[gcell2(g, I, J, i, j)];
+    if (c < n) defect -= g.hx * g.hy * qc[s];
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) defect += __shfl_xor(defect, o);
+  const double shift = defect / n;   // added to every cell's |c| q
   __syncthreads();
   fill_trans(g, I, J, kl, 1, tE, tN, dg);
 #pragma unroll
@@ -983,7 +992,7 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
     if (c >= n) continue;
     int i, j;
     loc_ij(g, c, &i, &j);
-    double r = g.hx * g.hy * qc[s];
+    double r = g.hx * g.hy * qc[s] + shift;
     if (i == 0) r -= g.hy * w[j];
     if (i == g.mx - 1) r -= g.hy * w[g.my + j];
     if (j == 0) r -= g.hx * w[2 * g.my + i];

@@ -19,7 +19,7 @@ from oracle import downscale as odown
 from oracle import fine, physics, splitting, transport as otrans
 from paper_2103_11050_amd import inputs
 
-from .gpu_common import FP64_SAT_TOL, FP64_VEL_TOL, to_np, vel_rel_err
+from .gpu_common import FP64_FACE_TOL, FP64_SAT_TOL, FP64_VEL_TOL, to_np, vel_rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -154,14 +154,6 @@ def test_steps_against_oracle_pieces(binding, workload):
         assert d <= 1e-9 * scale_w, (I, J, d, scale_w)
 
 
-# Face by face at this size: the interface system of eq:mrc2 on 129,024 unknowns with a
-# conductivity contrast of 1.1e6 has diagonal entries spread over 7e6, so two backward-stable FP64
-# solves (the oracle's LU with refinement, the nested-dissection inverses here) agree to about
-# cond * eps of the largest unknown, not to the RT0 bound face by face: observed 6.5e-10 of the
-# largest face velocity (2.6e-11 in the RT0 norm, whose bound is the stated 1e-10).
-FULL_FACE_TOL = 1e-9
-
-
 def test_metric_workload_matches_stored_oracle(binding, workload):
     """The start, two MPM-2P passes and one pass with a new MRCM basis at 1024^2, against the
     FP64 oracle's values stored by tests/golden/c3_reference.py: the scalars of every pass, the
@@ -213,7 +205,7 @@ def test_metric_workload_matches_stored_oracle(binding, workload):
         nv = abs(float(np.linalg.norm(vecs[p])) - float(ref["unorm"][p])) / float(ref["unorm"][p])
         print(f"    pass {p} ({ref['branches'][p]}): tile faces {ef:.2e}, tile cells {es:.2e}, "
               f"velocity error estimate {ev:.2e}, norm {nv:.2e}", flush=True)
-        assert ef <= FULL_FACE_TOL, (p, ef)
+        assert ef <= FP64_FACE_TOL, (p, ef)
         assert es <= 1e-10, (p, es)
         assert ev <= 0.7 * FP64_VEL_TOL, (p, ev)
         assert nv <= FP64_VEL_TOL, (p, nv)
