@@ -95,7 +95,7 @@ k_basis_mfma(Geo g, const double* __restrict__ kap, const double* __restrict__ q
     err = at_off(err, wo);
   }
   __shared__ double kl[256], tE[256], tN[256], dg[256], rhs0[256], wsh[64], hsh[64];
-  const int sub = blockIdx.x;
+  const int sub = xcd_sub(g.nsub);
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int lane = threadIdx.x;
   const int gq = lane >> 4, cc = lane & 15;

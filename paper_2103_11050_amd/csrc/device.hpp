@@ -50,6 +50,19 @@ enum : int32_t { ERR_NOTSPD = 1, ERR_SINGULAR = 2, ERR_NONFINITE = 4, ERR_NOCONV
 // upwind update.
 constexpr double SAT_TOL = 1e-12;
 
+// ---------------------------------------------------------------- subdomain of a workgroup
+// The chip dispatches workgroups to its 8 XCDs in turn (linear workgroup id mod 8), and each
+// XCD has its own L2. A kernel with one workgroup per subdomain (grid x = nsub) takes the
+// subdomain of its workgroup from here: with nsub a multiple of 8, XCD x receives the
+// contiguous range [x nsub / 8, (x + 1) nsub / 8), i.e. whole rows of subdomains, so that the
+// cache lines neighbouring subdomains share (halo cells, the faces between them) are fetched
+// into one L2 instead of two. A bijection of [0, nsub); identity when nsub is not a multiple of 8.
+__device__ __forceinline__ int xcd_sub(int nsub) {
+  const int b = blockIdx.x;
+  if (nsub & 7) return b;
+  return (b & 7) * (nsub >> 3) + (b >> 3);
+}
+
 // ---------------------------------------------------------------- local cell ordering
 // Cells of a subdomain are numbered along the shorter side first so that the 5-point
 // matrix has half bandwidth min(mx, my).

@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(64) k_line_factor(Geo g, const double* __restr
   }
   constexpr int NC = Cap<MF>::NC;
   __shared__ double kl[NC], tE[NC], tN[NC], dg[NC];
-  const int sub = blockIdx.x;
+  const int sub = xcd_sub(g.nsub);
   const int I = sub % g.Sx, J = sub / g.Sx;
   LB<MF> L;
   load_tile2(g, I, J, kap, kl);
@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(64) k_basis_lines(Geo g, const double* __restr
   }
   constexpr int NC = Cap<MF>::NC, NB = Cap<MF>::NB;
   __shared__ double kl[NC], tE[NC], tN[NC], dg[NC], x[NC], wsh[NB], hsh[NB];
-  const int sub = blockIdx.x;
+  const int sub = xcd_sub(g.nsub);
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int n = g.nc, nb = g.nb;
   load_tile2(g, I, J, kap, kl);
@@ -657,7 +657,7 @@ k_mpm_local_lb(Geo g0, const double* __restrict__ kap_n, const double* __restric
   // solution, boundary fluxes)
   __shared__ double knt[Cap<MF>::HALO], kmt[Cap<MF>::HALO], uxs[Cap<MF>::NF], uys[Cap<MF>::NF];
   __shared__ double xtra[F32 ? 3 * 256 + 768 : 1];   // precision form: tE, tN, dg, refinement scratch
-  const int sub = blockIdx.x;
+  const int sub = xcd_sub(g.nsub);
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int n = g.nc, nb = g.nb;
   const int TW = g.mx + 2;
@@ -774,7 +774,7 @@ k_mpm_first(Geo g0, const double* __restrict__ kap_n, const double* __restrict__
   }
   __shared__ double knt[18 * 18], kmt[18 * 18], uxs[16 * 17], uys[17 * 16], rx[16 * 17], ry[17 * 16];
   __shared__ double wx[16 * 17], wy[17 * 16], x[256], ty[256], rr[64], hsh[64];
-  const int sub = blockIdx.x;
+  const int sub = xcd_sub(g.nsub);
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int n = g.nc, nb = g.nb, TW = g.mx + 2;
   LB<MF> L;
@@ -940,7 +940,7 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
   __shared__ double kl[NC], w[Cap<MF>::NB], tE[NC], tN[NC], dg[NC];
   __shared__ double wsh[F32 ? 768 : 1];
   double* x = kl;
-  const int sub = blockIdx.x;
+  const int sub = xcd_sub(g.nsub);
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int n = g.nc, nb = g.nb;
   LB<MF> L;

@@ -42,7 +42,7 @@ k_kappa(Geo g, const double* __restrict__ s, double* __restrict__ s_new, const d
   count = at_off(count, wo);
   scal = at_off(scal, wo);
   const double mu_w = scal[SC_MUW], mu_o = scal[SC_MUO];
-  const int sub = blockIdx.x;
+  const int sub = xcd_sub(g.nsub);
   const int I = sub % g.Sx, J = sub / g.Sx;
   double a = 0.0, bb = 0.0;
   int diff = 0;
@@ -232,7 +232,7 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
   y = at_off(y, wo);
   sub_dofs = at_off(sub_dofs, wo);
   ubnd = at_off(ubnd, wo);
-  const int sub = blockIdx.x;
+  const int sub = xcd_sub(g.nsub);
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int nb = g.nb;
   const int f = threadIdx.x;
@@ -307,7 +307,7 @@ k_flux_wide(Geo g, const double* __restrict__ kap_m, const double* __restrict__ 
   y = at_off(y, wo);
   sub_dofs = at_off(sub_dofs, wo);
   ubnd = at_off(ubnd, wo);
-  const int sub = blockIdx.x;
+  const int sub = xcd_sub(g.nsub);
   const int I = sub % g.Sx, J = sub / g.Sx;
   const int nb = g.nb;
   const int f = threadIdx.x;
