@@ -63,6 +63,55 @@ __device__ __forceinline__ void lb_factor(const Geo& g, const LineW& W, const LB
   }
 }
 
+// Column steps (COLS = true in the ring solve): each lane reads the EPL entries of its own
+// columns of the line's vector from x in LDS, applies its EPL entries of the block to them and
+// the LPR lanes of the row sum their parts; the row's first lane writes the result over x, and
+// the next step reads those entries back from LDS (the lanes of one wavefront see each other's
+// LDS writes in program order). No shuffle per block entry, but three vector reads per lane and
+// step; same arithmetic, in the same order, as the row steps.
+
+// Forward step on line ln: z = r_ln + Y_{ln-1} w_{ln-1} on this lane's columns (x holds r_ln
+// and, in line ln - 1, w_{ln-1}), w_ln = D_ln^-1 z written over r_ln.
+template <int MF>
+__device__ __forceinline__ void lb_fwd_step(const LineW& W, const LB<MF>& L, const double (&a)[LB<MF>::EPL], int ln,
+                                            double* x) {
+  constexpr int EPL = LB<MF>::EPL, LPR = LB<MF>::LPR;
+  const int len = W.band;
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) {
+    const int c = L.col(t);
+    double z = 0.0;
+    if (c < len) {
+      z = x[ln * len + c];
+      if (ln > 0) z = fma(W.y(ln - 1, c), x[(ln - 1) * len + c], z);
+    }
+    acc = fma(a[t], z, acc);
+  }
+  const double w = row_sum<LPR>(acc);
+  if (L.row < len && L.cg == 0) x[ln * len + L.row] = w;
+}
+
+// Backward step on line ln < nl - 1: x_ln = w_ln + D_ln^-1 (Y_ln x_{ln+1}), with x_{ln+1}
+// final in x and w_ln in line ln of x.
+template <int MF>
+__device__ __forceinline__ void lb_bwd_step(const LineW& W, const LB<MF>& L, const double (&a)[LB<MF>::EPL], int ln,
+                                            double* x) {
+  constexpr int EPL = LB<MF>::EPL, LPR = LB<MF>::LPR;
+  const int len = W.band;
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < EPL; ++t) {
+    const int c = L.col(t);
+    const double v = c < len ? W.y(ln, c) * x[(ln + 1) * len + c] : 0.0;
+    acc = fma(a[t], v, acc);
+  }
+  const bool rin = L.row < len;
+  const double wl = rin ? x[ln * len + L.row] : 0.0;
+  const double xn = wl + row_sum<LPR>(acc);
+  if (rin && L.cg == 0) x[ln * len + L.row] = xn;
+}
+
 // x (LDS, local order) holds the right-hand side on entry and the solution on exit (the forward
 // result w_ln overwrites line ln of the right-hand side, which the row's lanes read before they
 // write it); Es holds the block inverses as written by lb_factor. Any line count.
@@ -171,7 +220,7 @@ __device__ __forceinline__ void lb_ring_load(const LB<MF>& L, const double* Es, 
     for (int t = 0; t < EPL; ++t) e[d][t] = Es[size_t(ring_line<NL>(d)) * P + pk[t]];
 }
 
-template <int MF, int NL, int D>
+template <int MF, int NL, int D, bool COLS>
 __device__ __forceinline__ void lb_solve_ring(const LineW& W, const LB<MF>& L, const double* Es,
                                               double (&e)[D][LB<MF>::EPL], double* x) {
   constexpr int EPL = LB<MF>::EPL, P = LBP<MF>::P, NU = 2 * NL - 1;
@@ -182,13 +231,16 @@ __device__ __forceinline__ void lb_solve_ring(const LineW& W, const LB<MF>& L, c
   const bool rin = L.row < len;
   const bool wr = rin && L.cg == 0;
   const int xr = rin ? L.row : 0;
-  // the forward result w_ln overwrites line ln of the right-hand side in x (read by the row's
-  // lanes before one of them writes it); the backward sweep reads it back
+  // row steps: the forward result w_ln overwrites line ln of the right-hand side in x (read by
+  // the row's lanes before one of them writes it); the backward sweep reads it back
   double xnext = 0.0;
 #pragma unroll
   for (int k = 0; k < NU; ++k) {
     const int ln = ring_line<NL>(k);
-    if (k < NL) {
+    if constexpr (COLS) {
+      if (k < NL) lb_fwd_step<MF>(W, L, e[k % D], ln, x);
+      else lb_bwd_step<MF>(W, L, e[k % D], ln, x);
+    } else if (k < NL) {
       double z = rin ? x[ln * len + xr] : 0.0;
       if (ln > 0 && rin) z += W.y(ln - 1, xr) * xnext;
       xnext = lb_matvec<MF>(L, e[k % D], z);
@@ -621,6 +673,11 @@ __device__ __forceinline__ Geo fix_geo(Geo g) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// Wavefronts per SIMD the fixed-shape FP64 local solve of 16^2 subdomains is compiled for: four
+// (at most 128 registers), so that a 1024^2 grid's 4096 subdomains are resident at once.
+template <int MF, typename T, int FX>
+constexpr int LOCAL_WAVES = (MF == 16 && FX == 16 && sizeof(T) == 8) ? 4 : 1;
+
 // MPM-2P trivial-Robin local solve (eq:mpm_tf_3 with the kappa^m basis): right-hand side
 // |c| q - sum_{non-Neumann faces} |f| v_f - sum_{Neumann faces} |f| z with
 // v_f = (t^n_f / t^m_f) u~^m_f; zero Dirichlet and Robin data. Outputs the boundary fluxes
@@ -631,7 +688,7 @@ __device__ __forceinline__ Geo fix_geo(Geo g) {
 // With T = float the kept blocks are FP32 (all lines in registers, up to 16) and the solve is
 // refined in FP64 against the full line form of the matrix.
 template <int MF, int NL, typename T, int FX>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LOCAL_WAVES<MF, T, FX>)))
 k_mpm_local_lb(Geo g0, const double* __restrict__ kap_n, const double* __restrict__ kap_m,
                const double* __restrict__ uxm, const double* __restrict__ uym, const double* __restrict__ q,
                const T* __restrict__ fac, double* __restrict__ hg, double* __restrict__ vbnd, LeafOut lo,
@@ -710,7 +767,7 @@ k_mpm_local_lb(Geo g0, const double* __restrict__ kap_n, const double* __restric
     if (!lb_solve_refined<MF>(g, W, L, Ef, x, xtra + 768) && L.lane == 0) set_error(err, ERR_NOCONV);
   } else {
     const LineW W{ty, ty, nullptr, g.xfast, g.band, 0};
-    if constexpr (RING) lb_solve_ring<MF, NL, RING_D>(W, L, Es, Er, x);
+    if constexpr (RING) lb_solve_ring<MF, NL, RING_D, true>(W, L, Es, Er, x);
     else if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
     else lb_solve<MF>(g, W, L, Es, x);
   }
@@ -1016,7 +1073,7 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
     if constexpr (RING) {
       // nothing of the flux phase is computed ahead of the solve (it would stay live across it)
       __builtin_amdgcn_sched_barrier(0);
-      lb_solve_ring<MF, NL, RING_D>(W, L, Es, Er, x);
+      lb_solve_ring<MF, NL, RING_D, false>(W, L, Es, Er, x);
       __builtin_amdgcn_sched_barrier(0);
     } else if constexpr (NL > 0) lb_solve_regs<MF, NL>(W, L, E, x);
     else lb_solve<MF>(g, W, L, Es, x);

@@ -132,6 +132,28 @@ __device__ __forceinline__ void lb_inverse_il(const LB<MF, true>& L, double (&a)
   for (int t = 0; t < EPL; ++t) a[t] = -a[t];
 }
 
+// A double moved between lanes by a DPP pattern (both halves with the same pattern; every lane
+// of the wavefront active and every pattern used here reads a lane of the wavefront).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp(int(unsigned(b)), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(int(unsigned(b >> 32)), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (unsigned long long)unsigned(lo) | ((unsigned long long)unsigned(hi) << 32));
+}
+
+// Sum over the LPR consecutive lanes of a row, left in every lane of the row: the same
+// additions as a butterfly over lane ^ 1, lane ^ 2 (quad permutations) and, for 8 lanes, the
+// other quad of the row (half-row mirror, whose partner is in the other quad like lane ^ 4).
+template <int LPR>
+__device__ __forceinline__ double row_sum(double v) {
+  static_assert(LPR == 1 || LPR == 2 || LPR == 4 || LPR == 8, "row of 1, 2, 4 or 8 lanes");
+  if constexpr (LPR >= 2) v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  if constexpr (LPR >= 4) v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  if constexpr (LPR >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
+  return v;
+}
+
 // y = D v for vectors replicated over a row's lanes (lane holds v[row]); result replicated.
 template <int MF, bool IL>
 __device__ __forceinline__ double lb_matvec(const LB<MF, IL>& L, const double (&a)[LB<MF>::EPL], double v) {
@@ -139,9 +161,7 @@ __device__ __forceinline__ double lb_matvec(const LB<MF, IL>& L, const double (&
   double acc = 0.0;
 #pragma unroll
   for (int t = 0; t < EPL; ++t) acc += a[t] * __shfl(v, L.col(t) * LPR);
-#pragma unroll
-  for (int o = 1; o < LPR; o <<= 1) acc += __shfl_xor(acc, o);
-  return acc;
+  return row_sum<LPR>(acc);
 }
 
 // Geometry of the line decomposition of a subdomain.
