@@ -484,7 +484,7 @@ def main():
         "sweep_tuning": None if tuned is None else {
             "solve_ms_rule": round(tuned["ms_rule"], 4), "solve_ms_tuned": round(tuned["ms_tuned"], 4),
             "shapes": [list(x) for x in tuned["shapes"]],
-            "note": "lanes per row, columns per lane, rows per lane group of each sweep launch "
+            "note": "lanes per row, 16-byte column pairs per lane, rows per lane group of each sweep launch "
                     "(forward levels upwards, then backward levels downwards)"},
         "mrcm_kernels_ms": {k: round(v[0], 5) for k, v in sorted(mprof.items())},
     }

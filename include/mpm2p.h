@@ -263,14 +263,14 @@ mpm_status mpm_plan_solve_bytes(const mpm_run* run, int64_t* fwd_bytes, int64_t*
 
 /* Autotuner of the launch shapes of the interface solve (the forward and backward sweeps over the
  * nested-dissection levels of eq:mrc2's factorisation): every admissible shape of each level
- * (lanes per row, columns per lane, rows per lane group) is timed over complete solves on the
+ * (lanes per row, column pairs per lane, rows per lane group) is timed over complete solves on the
  * run's stream (best of reps, reps >= 1) and the fastest kept for the run; the result is also
  * cached for the process, so that runs created later with the same decomposition (grid,
  * subdomains, interface elements and degree) start with it (a batch group launches with its
  * first run's shapes). Another shape changes the summation order of the solve: results move at
  * rounding level, so runs compared bitwise must share their shapes. The run must be started and
  * not in a batch (MPM_ESTATE). Host outputs (any may be NULL when cap is 0): shapes[3 k .. 3 k + 2]
- * = (lanes per row, columns per lane, rows per group) of launch k, forward levels upwards then
+ * = (lanes per row, column pairs per lane, rows per group) of launch k, forward levels upwards then
  * backward levels downwards, for the first cap / 3 launches; *n = the number of launches; *ms_rule
  * and *ms_tuned = the solve time with the fixed rule and with the chosen shapes (ms). Synchronises
  * with the run's stream. */

@@ -136,7 +136,7 @@ __device__ __forceinline__ NdArgs nd_at(const NdArgs& a, int64_t o) {
 }
 void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nmax, int nImax,
                             int nBmax, Runs rt = one_run());
-// Launch shape of a sweep level: lanes per row G, columns per lane U, rows per lane group RP,
+// Launch shape of a sweep level: lanes per row G, column pairs per lane U, rows per lane group RP,
 // packed as G | U << 8 | RP << 16; 0 selects the fixed rule (rows of 1536 or more are taken in
 // chunks whatever the code).
 int nd_shape_code(int G, int U, int RP);

@@ -339,22 +339,31 @@ __device__ __forceinline__ double ld32(const double* base, uint32_t elem) {
   return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + (elem << 3));
 }
 
+// Sixteen bytes (two consecutive entries) at an even 32-bit element offset from a 16-byte
+// aligned base that is uniform over the wavefront.
+__device__ __forceinline__ double2 ld32x2(const double* base, uint32_t elem) {
+  return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(base) + (elem << 3));
+}
+
 // Forward and backward sweeps, one launch per level. A workgroup takes RP x (256/G) rows of
-// one node, G lanes per row, U columns per lane (longer rows in chunks of G*U), and issues
-// every load of its block and of the vector it multiplies before the first use: one memory
-// round trip per level. Loads are unconditional at clamped (valid) addresses and masked
-// afterwards so that the compiler keeps them all in flight. The vector is loaded once per
-// workgroup (a few entries per thread) and shared through LDS, so that the loads of the waves
-// are those of their rows; rows longer than G*U (CH) load it per wave, chunk by chunk.
+// one node, G lanes per row, U column pairs per lane (lane gl holds columns 2 (gl + u G) and
+// 2 (gl + u G) + 1: one 16-byte load each; longer rows in chunks of 2 G U), and issues every
+// load of its block and of the vector it multiplies before the first use: one memory round trip
+// per level. Loads are unconditional at clamped (valid) addresses and masked afterwards so that
+// the compiler keeps them all in flight. The vector is loaded once per workgroup (a few entries
+// per thread) and shared through LDS, so that the loads of the waves are those of their rows;
+// rows longer than 2 G U (CH) load it per wave, chunk by chunk. Front rows start at even
+// offsets (every front size n, separator size nI and front offset is even: the unknowns come in
+// (U, P) pairs), so the pairs are 16-byte aligned.
 
 // c_B = f_B - BI f_I with f = slot0 + slot1, written into the parent's slot for this node;
 // workgroup 0 of the node also stores f_I for the backward sweep. The root is not launched.
-// Rows longer than G*U (only with CH) are taken in chunks.
+// Rows longer than 2 G U (only with CH) are taken in chunks.
 template <int G, int U, int RP, bool CH>
 __global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a0, int loff, const RunTab* __restrict__ rt) {
   static_assert(RP <= G, "lane p of a row group holds row p's operands");
   const NdArgs a = nd_at(a0, ws_off(rt));
-  constexpr int RPP = 256 / G, RPB = RP * RPP;
+  constexpr int RPP = 256 / G, RPB = RP * RPP, W = 2 * G * U;
   const NodeDev nd = a.lnodes[loff + blockIdx.y];
   // a workgroup past the node's rows (nodes smaller than the level's largest) runs with clamped
   // rows and stores nothing (j >= nB below): no early exit, so that the node record is read in
@@ -364,7 +373,7 @@ __global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a0, int loff, const Ru
   const double* __restrict__ F = a.front + nd.front_off;
   const double* __restrict__ s0 = a.slots + nd.slot_off;
   const int32_t* __restrict__ up = a.map_pool + nd.up_map_off;
-  const int n = nd.n, nI = nd.nI, nI1 = nd.nI - 1, nB1 = nd.nB - 1;
+  const int n = nd.n, nI = nd.nI, nI1 = nd.nI - 1, nI2 = nd.nI - 2, nB1 = nd.nB - 1;
   // the per-row operands f_B and the target slot of row p are loaded by lane p of the group only
   const int jm = min(r0 + min(gl, RP - 1) * RPP + grp, nB1);
   const double fbm = s0[nI + jm] + s0[n + nI + jm];
@@ -378,13 +387,14 @@ __global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a0, int loff, const Ru
     acc[p] = 0.0;
   }
   if constexpr (!CH) {
-    constexpr int VPT = (G * U + 255) / 256;
-    __shared__ double fsh[G * U];
-    double m[RP][U], fv[VPT];
+    constexpr int VPT = (W + 255) / 256;
+    __shared__ double fsh[W];
+    double2 m[RP][U];
+    double fv[VPT];
 #pragma unroll
     for (int p = 0; p < RP; ++p)
 #pragma unroll
-      for (int u = 0; u < U; ++u) m[p][u] = ld32(F, rowoff[p] + uint32_t(min(gl + u * G, nI1)));
+      for (int u = 0; u < U; ++u) m[p][u] = ld32x2(F, rowoff[p] + uint32_t(min(2 * (gl + u * G), nI2)));
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const int k = min(int(threadIdx.x) + 256 * i, nI1);
@@ -402,30 +412,45 @@ __global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a0, int loff, const Ru
 #pragma unroll
     for (int p = 0; p < RP; ++p)
 #pragma unroll
-      for (int u = 0; u < U; ++u) acc[p] += (gl + u * G < nI) ? m[p][u] * fsh[gl + u * G] : 0.0;
+      for (int u = 0; u < U; ++u) {
+        const int c = 2 * (gl + u * G);
+        if (c < nI) {
+          acc[p] += m[p][u].x * fsh[c];
+          acc[p] += m[p][u].y * fsh[c + 1];
+        }
+      }
   }
-  for (int k0 = 0; k0 < (CH ? nI : 0); k0 += G * U) {
-    double m[RP][U], fk[U];
+  for (int k0 = 0; k0 < (CH ? nI : 0); k0 += W) {
+    double2 m[RP][U], fk[U];
 #pragma unroll
     for (int p = 0; p < RP; ++p)
 #pragma unroll
-      for (int u = 0; u < U; ++u) m[p][u] = ld32(F, rowoff[p] + uint32_t(min(k0 + gl + u * G, nI1)));
+      for (int u = 0; u < U; ++u) m[p][u] = ld32x2(F, rowoff[p] + uint32_t(min(k0 + 2 * (gl + u * G), nI2)));
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int k = min(k0 + gl + u * G, nI1);
-      fk[u] = ld32(s0, k) + ld32(s0, n + k);
+      const int k = min(k0 + 2 * (gl + u * G), nI2);
+      const double2 sa = ld32x2(s0, k), sb = ld32x2(s0, n + k);
+      fk[u] = make_double2(sa.x + sb.x, sa.y + sb.y);
     }
     if (blockIdx.x == 0 && grp == 0) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int k = k0 + gl + u * G;
-        if (k < nI) a.fI[nd.fI_off + k] = fk[u];
+        const int k = k0 + 2 * (gl + u * G);
+        if (k < nI) {
+          a.fI[nd.fI_off + k] = fk[u].x;
+          a.fI[nd.fI_off + k + 1] = fk[u].y;
+        }
       }
     }
 #pragma unroll
     for (int p = 0; p < RP; ++p)
 #pragma unroll
-      for (int u = 0; u < U; ++u) acc[p] += (k0 + gl + u * G < nI) ? m[p][u] * fk[u] : 0.0;
+      for (int u = 0; u < U; ++u) {
+        if (k0 + 2 * (gl + u * G) < nI) {
+          acc[p] += m[p][u].x * fk[u].x;
+          acc[p] += m[p][u].y * fk[u].y;
+        }
+      }
   }
   double mine = 0.0;
 #pragma unroll
@@ -445,7 +470,7 @@ __global__ void __launch_bounds__(256) k_nd_fwd_rb(NdArgs a0, int loff, const Ru
 template <int G, int U, int RP, bool CH, bool ROOT>
 __device__ __forceinline__ void k_nd_bwd_body(const NdArgs& a, int loff) {
   static_assert(RP <= G, "lane p of a row group holds row p's unknown id");
-  constexpr int RPP = 256 / G, RPB = RP * RPP;
+  constexpr int RPP = 256 / G, RPB = RP * RPP, W = 2 * G * U;
   const NodeDev nd = a.lnodes[loff + blockIdx.y];
   const int r0 = blockIdx.x * RPB;   // rows past the node's stay clamped and unstored (r >= nI)
   const int gl = threadIdx.x % G, grp = threadIdx.x / G;
@@ -453,7 +478,7 @@ __device__ __forceinline__ void k_nd_bwd_body(const NdArgs& a, int loff) {
   const double* __restrict__ s0 = a.slots + nd.slot_off;
   const double* __restrict__ fI = a.fI + nd.fI_off;
   const int32_t* __restrict__ dofs = a.dof_pool + nd.dof_off;
-  const int n = nd.n, nI = nd.nI, n1 = nd.n - 1, nI1 = nd.nI - 1;
+  const int n = nd.n, nI = nd.nI, n1 = nd.n - 1, n2 = nd.n - 2, nI1 = nd.nI - 1;
   // the unknown id of row p is loaded by lane p of the group only
   const int32_t drm = dofs[min(r0 + min(gl, RP - 1) * RPP + grp, nI1)];
   uint32_t rowoff[RP];
@@ -465,9 +490,10 @@ __device__ __forceinline__ void k_nd_bwd_body(const NdArgs& a, int loff) {
     acc[p] = 0.0;
   }
   if constexpr (!CH) {
-    constexpr int VPT = (G * U + 255) / 256;
-    __shared__ double vsh[G * U];
-    double m[RP][U], vv[VPT];
+    constexpr int VPT = (W + 255) / 256;
+    __shared__ double vsh[W];
+    double2 m[RP][U];
+    double vv[VPT];
     // unknown ids of x_B first, so that their gather waits for them only, not for the block
     uint32_t dk[VPT];   // unsigned: no sign extension next to the load, before the block loads
     if constexpr (!ROOT) {
@@ -480,7 +506,7 @@ __device__ __forceinline__ void k_nd_bwd_body(const NdArgs& a, int loff) {
 #pragma unroll
     for (int p = 0; p < RP; ++p)
 #pragma unroll
-      for (int u = 0; u < U; ++u) m[p][u] = ld32(F, rowoff[p] + uint32_t(min(gl + u * G, n1)));
+      for (int u = 0; u < U; ++u) m[p][u] = ld32x2(F, rowoff[p] + uint32_t(min(2 * (gl + u * G), n2)));
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (ROOT) {
 #pragma unroll
@@ -506,35 +532,49 @@ __device__ __forceinline__ void k_nd_bwd_body(const NdArgs& a, int loff) {
 #pragma unroll
     for (int p = 0; p < RP; ++p)
 #pragma unroll
-      for (int u = 0; u < U; ++u) acc[p] += (gl + u * G < n) ? m[p][u] * vsh[gl + u * G] : 0.0;
+      for (int u = 0; u < U; ++u) {
+        const int c = 2 * (gl + u * G);
+        if (c < n) {
+          acc[p] += m[p][u].x * vsh[c];
+          acc[p] += m[p][u].y * vsh[c + 1];
+        }
+      }
   }
-  for (int k0 = 0; k0 < (CH ? n : 0); k0 += G * U) {
-    int32_t dk[U];
+  for (int k0 = 0; k0 < (CH ? n : 0); k0 += W) {
+    int32_t dk[2 * U];
     if constexpr (!ROOT) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) dk[u] = dofs[min(max(k0 + gl + u * G, nI), n1)];
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + 2 * (gl + u * G);
+        dk[2 * u] = dofs[min(max(k, nI), n1)];
+        dk[2 * u + 1] = dofs[min(max(k + 1, nI), n1)];
+      }
     }
-    double m[RP][U], v[U];
+    double2 m[RP][U];
+    double v[2 * U];
 #pragma unroll
     for (int p = 0; p < RP; ++p)
 #pragma unroll
-      for (int u = 0; u < U; ++u) m[p][u] = ld32(F, rowoff[p] + uint32_t(min(k0 + gl + u * G, n1)));
+      for (int u = 0; u < U; ++u) m[p][u] = ld32x2(F, rowoff[p] + uint32_t(min(k0 + 2 * (gl + u * G), n2)));
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = k0 + gl + u * G;
+    for (int h = 0; h < 2 * U; ++h) {
+      const int k = k0 + 2 * (gl + (h / 2) * G) + (h & 1);
       const int ki = min(k, nI1);
       if constexpr (ROOT) {
-        v[u] = k < nI ? ld32(s0, ki) + ld32(s0, n + ki) : 0.0;
+        v[h] = k < nI ? ld32(s0, ki) + ld32(s0, n + ki) : 0.0;
       } else {
         const double xi = ld32(fI, ki);
-        const double xb = a.y[dk[u]];
-        v[u] = k < nI ? xi : (k < n ? xb : 0.0);
+        const double xb = a.y[dk[h]];
+        v[h] = k < nI ? xi : (k < n ? xb : 0.0);
       }
     }
 #pragma unroll
     for (int p = 0; p < RP; ++p)
 #pragma unroll
-      for (int u = 0; u < U; ++u) acc[p] += m[p][u] * v[u];
+      for (int u = 0; u < U; ++u) {
+        acc[p] += m[p][u].x * v[2 * u];
+        acc[p] += m[p][u].y * v[2 * u + 1];
+      }
   }
   double mine = 0.0;
 #pragma unroll
@@ -576,30 +616,30 @@ void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int loff, int nnode
   hipLaunchKernelGGL(k_nd_tcopy, dim3(cI * cB, nnodes, nr), dim3(256), 0, st, a, loff, cB, rt.tab);
 }
 
-// Shape for a row length: lanes per row, columns per lane, rows per lane group (about eight
-// loads of the block per lane); rows longer than 1536 are taken in chunks of 1024.
+// Shape for a row length: lanes per row, column pairs per lane, rows per lane group (about
+// 64 bytes of the block per lane); rows longer than 1536 are taken in chunks of 1024.
 struct RbShape {
   int G, U, RP;
 };
 static RbShape rb_shape(int len) {
-  if (len <= 16) return {16, 1, 8};
-  if (len <= 32) return {32, 1, 8};
-  if (len <= 64) return {64, 1, 8};
-  if (len <= 128) return {64, 2, 4};
-  if (len <= 256) return {64, 4, 2};
-  if (len <= 512) return {64, 8, 1};
-  if (len <= 1024) return {64, 16, 1};
-  if (len <= 1536) return {64, 24, 1};
+  if (len <= 16) return {8, 1, 4};
+  if (len <= 32) return {16, 1, 4};
+  if (len <= 64) return {32, 1, 4};
+  if (len <= 128) return {64, 1, 4};
+  if (len <= 256) return {64, 2, 2};
+  if (len <= 512) return {64, 4, 1};
+  if (len <= 1024) return {64, 8, 1};
+  if (len <= 1536) return {64, 12, 1};
   return {64, 0, 1};   // longer rows: chunks of 1024
 }
 
 // Rows per lane group available for each row shape (template instances below).
 static int rb_rp_options(int G, int U, int* opt) {
-  if (G == 16) { opt[0] = 4; opt[1] = 6; opt[2] = 8; return 3; }
-  if (G == 32 || U == 1) { opt[0] = 4; opt[1] = 8; return 2; }
-  if (U == 2) { opt[0] = 2; opt[1] = 4; opt[2] = 8; return 3; }
-  if (U == 4) { opt[0] = 1; opt[1] = 2; opt[2] = 4; return 3; }
-  if (U == 8) { opt[0] = 1; opt[1] = 2; return 2; }
+  if (G == 8) { opt[0] = 2; opt[1] = 3; opt[2] = 4; return 3; }
+  if (G == 16 || G == 32) { opt[0] = 2; opt[1] = 4; return 2; }
+  if (U == 1) { opt[0] = 2; opt[1] = 4; opt[2] = 8; return 3; }
+  if (U == 2) { opt[0] = 1; opt[1] = 2; opt[2] = 4; return 3; }
+  if (U == 4) { opt[0] = 1; opt[1] = 2; return 2; }
   opt[0] = 1;
   return 1;
 }
@@ -629,18 +669,18 @@ static RbShape rb_fit_rows(RbShape sh, int rows) {
     const int rpb_ = (sh).RP * (256 / (sh).G);                                                      \
     const dim3 grid_(std::max(1, ((rows) + rpb_ - 1) / rpb_), (nnodes), (nruns));                 \
     if ((sh).U == 0) {                                                                              \
-      hipLaunchKernelGGL((KER<64, 16, 1, true>), grid_, dim3(256), 0, st, __VA_ARGS__);             \
+      hipLaunchKernelGGL((KER<64, 8, 1, true>), grid_, dim3(256), 0, st, __VA_ARGS__);              \
       break;                                                                                        \
     }                                                                                               \
-    ND_RB_CASE(KER, 16, 1, 8, false, __VA_ARGS__) ND_RB_CASE(KER, 16, 1, 6, false, __VA_ARGS__)     \
-    ND_RB_CASE(KER, 16, 1, 4, false, __VA_ARGS__) ND_RB_CASE(KER, 32, 1, 8, false, __VA_ARGS__)     \
-    ND_RB_CASE(KER, 32, 1, 4, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 1, 8, false, __VA_ARGS__)     \
-    ND_RB_CASE(KER, 64, 1, 4, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 2, 8, false, __VA_ARGS__)     \
+    ND_RB_CASE(KER, 8, 1, 4, false, __VA_ARGS__) ND_RB_CASE(KER, 8, 1, 3, false, __VA_ARGS__)       \
+    ND_RB_CASE(KER, 8, 1, 2, false, __VA_ARGS__) ND_RB_CASE(KER, 16, 1, 4, false, __VA_ARGS__)      \
+    ND_RB_CASE(KER, 16, 1, 2, false, __VA_ARGS__) ND_RB_CASE(KER, 32, 1, 4, false, __VA_ARGS__)     \
+    ND_RB_CASE(KER, 32, 1, 2, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 1, 8, false, __VA_ARGS__)     \
+    ND_RB_CASE(KER, 64, 1, 4, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 1, 2, false, __VA_ARGS__)     \
     ND_RB_CASE(KER, 64, 2, 4, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 2, 2, false, __VA_ARGS__)     \
-    ND_RB_CASE(KER, 64, 4, 4, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 4, 2, false, __VA_ARGS__)     \
-    ND_RB_CASE(KER, 64, 4, 1, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 8, 2, false, __VA_ARGS__)     \
-    ND_RB_CASE(KER, 64, 8, 1, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 16, 1, false, __VA_ARGS__)    \
-    ND_RB_CASE(KER, 64, 24, 1, false, __VA_ARGS__)                                                  \
+    ND_RB_CASE(KER, 64, 2, 1, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 4, 2, false, __VA_ARGS__)     \
+    ND_RB_CASE(KER, 64, 4, 1, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 8, 1, false, __VA_ARGS__)     \
+    ND_RB_CASE(KER, 64, 12, 1, false, __VA_ARGS__)                                                  \
   } while (0)
 
 int nd_shape_code(int G, int U, int RP) { return G | (U << 8) | (RP << 16); }
@@ -650,7 +690,7 @@ void nd_shape_unpack(int code, int* G, int* U, int* RP) {
   *RP = (code >> 16) & 255;
 }
 
-// The instantiated shapes (ND_RB_LAUNCH) whose G U columns cover a row of len entries at most
+// The instantiated shapes (ND_RB_LAUNCH) whose 2 G U columns cover a row of len entries at most
 // four times over, the rule's shape first.
 static RbShape rb_shape_bwd(int len);
 int nd_shape_candidates(int len, int rows, bool bwd, int* codes, int cap) {
@@ -658,11 +698,11 @@ int nd_shape_candidates(int len, int rows, bool bwd, int* codes, int cap) {
   int n = 0;
   if (n < cap) codes[n++] = nd_shape_code(rule.G, rule.U, rule.RP);
   if (rule.U == 0) return n;   // chunked rows: one shape
-  static const RbShape all[] = {{16, 1, 8}, {16, 1, 6}, {16, 1, 4}, {32, 1, 8}, {32, 1, 4}, {64, 1, 8},
-                                {64, 1, 4}, {64, 2, 8}, {64, 2, 4}, {64, 2, 2}, {64, 4, 4}, {64, 4, 2},
-                                {64, 4, 1}, {64, 8, 2}, {64, 8, 1}, {64, 16, 1}, {64, 24, 1}};
+  static const RbShape all[] = {{8, 1, 4},  {8, 1, 3},  {8, 1, 2},  {16, 1, 4}, {16, 1, 2}, {32, 1, 4},
+                                {32, 1, 2}, {64, 1, 8}, {64, 1, 4}, {64, 1, 2}, {64, 2, 4}, {64, 2, 2},
+                                {64, 2, 1}, {64, 4, 2}, {64, 4, 1}, {64, 8, 1}, {64, 12, 1}};
   for (const RbShape& sh : all) {
-    const int cols = sh.G * sh.U;
+    const int cols = 2 * sh.G * sh.U;
     if (cols < len || cols > 4 * len) continue;
     if (sh.G == rule.G && sh.U == rule.U && sh.RP == rule.RP) continue;
     if (n < cap) codes[n++] = nd_shape_code(sh.G, sh.U, sh.RP);
@@ -696,7 +736,7 @@ __global__ void __launch_bounds__(256) k_nd_bwd_root(NdArgs a, int loff, const R
 // longer-lived workgroups per level; measured slightly faster).
 static RbShape rb_shape_bwd(int len) {
   RbShape sh = rb_shape(len);
-  if (sh.G == 64 && sh.U >= 2 && sh.U <= 8) sh.RP *= 2;
+  if (sh.G == 64 && sh.U >= 1 && sh.U <= 4) sh.RP *= 2;
   return sh;
 }
 

@@ -401,7 +401,7 @@ def test_tuned_sweeps_match_oracle(binding):
     r.start()
     tr = r.tune(3)
     assert len(tr["shapes"]) >= 1 and tr["ms_tuned"] <= tr["ms_rule"]
-    assert all(g in (16, 32, 64) and u >= 1 and rp >= 1 for g, u, rp in tr["shapes"])
+    assert all(g in (8, 16, 32, 64) and u >= 1 and rp >= 1 for g, u, rp in tr["shapes"])
     print(f"    solve {tr['ms_rule']:.4f} -> {tr['ms_tuned']:.4f} ms, shapes {tr['shapes']}", flush=True)
     for n in range(1, len(forced)):
         splitting.step(orun, forced[n])
