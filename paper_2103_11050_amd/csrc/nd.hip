@@ -342,7 +342,10 @@ __device__ __forceinline__ double ld32(const double* base, uint32_t elem) {
 // Sixteen bytes (two consecutive entries) at an even 32-bit element offset from a 16-byte
 // aligned base that is uniform over the wavefront.
 __device__ __forceinline__ double2 ld32x2(const double* base, uint32_t elem) {
-  return *reinterpret_cast<const double2*>(reinterpret_cast<const char*>(base) + (elem << 3));
+  typedef double v2d __attribute__((ext_vector_type(2)));
+  const v2d* q = reinterpret_cast<const v2d*>(reinterpret_cast<const char*>(base) + (elem << 3));
+  const v2d v = __builtin_nontemporal_load(q);
+  return make_double2(v.x, v.y);
 }
 
 // Forward and backward sweeps, one launch per level. A workgroup takes RP x (256/G) rows of
