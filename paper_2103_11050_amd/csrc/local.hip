@@ -242,7 +242,7 @@ k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, c
   const double* Ss = Sg + size_t(sub) * smap_doubles(nb);
   double sv[33];
 #pragma unroll
-  for (int d = 0; d < 33; ++d) sv[d] = act && d <= D ? Ss[d * nb + f] : 0.0;
+  for (int d = 0; d < 33; ++d) sv[d] = act && d <= D ? __builtin_nontemporal_load(&Ss[d * nb + f]) : 0.0;
   double acc = act ? hg[size_t(sub) * nb + f] : 0.0;
   const double vb = act && with_v ? vbnd[size_t(sub) * nb + f] : 0.0;
   BFace bf;
