@@ -50,6 +50,30 @@ enum : int32_t { ERR_NOTSPD = 1, ERR_SINGULAR = 2, ERR_NONFINITE = 4, ERR_NOCONV
 // upwind update.
 constexpr double SAT_TOL = 1e-12;
 
+// A double moved between lanes by a DPP pattern (both halves with the same pattern; every lane
+// of the wavefront active and every pattern used here reads a lane of the wavefront).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp(int(unsigned(b)), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(int(unsigned(b >> 32)), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (unsigned long long)unsigned(lo) | ((unsigned long long)unsigned(hi) << 32));
+}
+
+// Sum over the 64 lanes of a wavefront, the same value in every lane: a butterfly whose partner
+// is always in the other half of the group reached so far (quad permutations, half-row and row
+// mirrors by DPP, then lane ^ 16 and lane ^ 32 by shuffles); each step adds two equal-order
+// pairs, so every lane ends with the same bits.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141>(v);   // row_half_mirror: the other quad of the 8
+  v += dpp_f64<0x140>(v);   // row_mirror: the other 8 of the 16
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
 // ---------------------------------------------------------------- subdomain of a workgroup
 // The chip dispatches workgroups to its 8 XCDs in turn (linear workgroup id mod 8), and each
 // XCD has its own L2. A kernel with one workgroup per subdomain (grid x = nsub) takes the

@@ -132,16 +132,6 @@ __device__ __forceinline__ void lb_inverse_il(const LB<MF, true>& L, double (&a)
   for (int t = 0; t < EPL; ++t) a[t] = -a[t];
 }
 
-// A double moved between lanes by a DPP pattern (both halves with the same pattern; every lane
-// of the wavefront active and every pattern used here reads a lane of the wavefront).
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-  const int lo = __builtin_amdgcn_mov_dpp(int(unsigned(b)), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(int(unsigned(b >> 32)), CTRL, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, (unsigned long long)unsigned(lo) | ((unsigned long long)unsigned(hi) << 32));
-}
-
 // Sum over the LPR consecutive lanes of a row, left in every lane of the row: the same
 // additions as a butterfly over lane ^ 1, lane ^ 2 (quad permutations) and, for 8 lanes, the
 // other quad of the row (half-row mirror, whose partner is in the other quad like lane ^ 4).

@@ -24,7 +24,7 @@ k_kappa(Geo g, const double* __restrict__ s, double* __restrict__ s_new, const d
         int32_t* __restrict__ flag, int32_t* __restrict__ list, int32_t* __restrict__ count,
         double* __restrict__ scal, const double* __restrict__ ux, const double* __restrict__ uy, double area,
         const RunTab* __restrict__ rt) {
-  __shared__ double sa[256], sb[256], sq[256], sw[256];
+  __shared__ double sa[4], sb[4], sq[4], sw[4];   // per-wavefront partials
   const int64_t wo = ws_off(rt);
   const bool wc = ux != nullptr;
   if (wc) {
@@ -83,28 +83,35 @@ k_kappa(Geo g, const double* __restrict__ s, double* __restrict__ s_new, const d
     bb += km * km;
     diff |= kn != km;
   }
-  sa[threadIdx.x] = a;
-  sb[threadIdx.x] = bb;
-  sq[threadIdx.x] = wq;
-  sw[threadIdx.x] = ww;
-  const int changed = __syncthreads_or(diff);
-  for (int w = int(blockDim.x) >> 1; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      sa[threadIdx.x] += sa[threadIdx.x + w];
-      sb[threadIdx.x] += sb[threadIdx.x + w];
-      if (edge) {
-        sq[threadIdx.x] += sq[threadIdx.x + w];
-        sw[threadIdx.x] += sw[threadIdx.x + w];
-      }
-    }
-    __syncthreads();
+  // the tile's sums: over each wavefront by cross-lane moves, then the wavefronts' partials in
+  // order
+  a = wave_sum(a);
+  bb = wave_sum(bb);
+  if (edge) {
+    wq = wave_sum(wq);
+    ww = wave_sum(ww);
   }
+  const int wv = threadIdx.x >> 6, nw = int(blockDim.x) >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sa[wv] = a;
+    sb[wv] = bb;
+    sq[wv] = wq;
+    sw[wv] = ww;
+  }
+  const int changed = __syncthreads_or(diff);
   if (threadIdx.x == 0) {
-    red[2 * sub] = sa[0];
-    red[2 * sub + 1] = sb[0];
+    double ta = sa[0], tb = sb[0], tq = sq[0], tw = sw[0];
+    for (int k = 1; k < nw; ++k) {
+      ta += sa[k];
+      tb += sb[k];
+      tq += sq[k];
+      tw += sw[k];
+    }
+    red[2 * sub] = ta;
+    red[2 * sub + 1] = tb;
     if (wc) {
-      red[2 * size_t(g.nsub) + 2 * sub] = sq[0];
-      red[2 * size_t(g.nsub) + 2 * sub + 1] = sw[0];
+      red[2 * size_t(g.nsub) + 2 * sub] = tq;
+      red[2 * size_t(g.nsub) + 2 * sub + 1] = tw;
     }
     flag[sub] = changed;
     if (changed) {
