@@ -74,6 +74,12 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Makes the LDS writes of this wavefront's lanes visible to the LDS reads that follow in other
+// lanes of the same wavefront: a fence at wavefront scope (the lanes of a wavefront perform their
+// LDS accesses in program order; the fence keeps the compiler from reusing values it loaded
+// earlier, or moving those reads above the writes).
+__device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
 // ---------------------------------------------------------------- subdomain of a workgroup
 // The chip dispatches workgroups to its 8 XCDs in turn (linear workgroup id mod 8), and each
 // XCD has its own L2. A kernel with one workgroup per subdomain (grid x = nsub) takes the

@@ -48,13 +48,14 @@ __device__ __forceinline__ void lb_factor(const Geo& g, const LineW& W, const LB
   constexpr int P = LBP<MF>::P;
   int pk[EPL];
   lb_pk_lane<MF>(L, pk);
+  __shared__ double piv[2 * MF];   // pivot row and column of the Gauss-Jordan sweep
   double prev[EPL], cur[EPL];
 #pragma unroll
   for (int t = 0; t < EPL; ++t) prev[t] = 0.0;
 #pragma unroll 1
   for (int ln = 0; ln < nl; ++ln) {
     lb_block<MF>(W, ln, L, prev, cur);
-    lb_inverse<MF>(L, cur, ok);
+    lb_inverse<MF>(L, cur, ok, piv, piv + MF);
 #pragma unroll
     for (int t = 0; t < EPL; ++t) {
       if (L.row <= L.col(t)) Es[size_t(ln) * P + pk[t]] = T(cur[t]);
@@ -77,6 +78,7 @@ __device__ __forceinline__ void lb_fwd_step(const LineW& W, const LB<MF>& L, con
                                             double* x) {
   constexpr int EPL = LB<MF>::EPL, LPR = LB<MF>::LPR;
   const int len = W.band;
+  wave_lds_fence();   // the previous step's results, written by other lanes
   double acc = 0.0;
 #pragma unroll
   for (int t = 0; t < EPL; ++t) {
@@ -99,6 +101,7 @@ __device__ __forceinline__ void lb_bwd_step(const LineW& W, const LB<MF>& L, con
                                             double* x) {
   constexpr int EPL = LB<MF>::EPL, LPR = LB<MF>::LPR;
   const int len = W.band;
+  wave_lds_fence();   // the previous step's results, written by other lanes
   double acc = 0.0;
 #pragma unroll
   for (int t = 0; t < EPL; ++t) {
@@ -153,6 +156,7 @@ __device__ __forceinline__ void lb_solve(const Geo& g, const LineW& W, const LB<
     const int lnn = ln > 0 ? ln - 1 : 0;
 #pragma unroll
     for (int t = 0; t < EPL; ++t) en[t] = Es[size_t(lnn) * P + pk[t]];
+    wave_lds_fence();   // w_ln was written by the row's first lane
     const double v = rin ? W.y(ln, xr) * xnext : 0.0;
     xnext = (rin ? x[ln * len + xr] : 0.0) + lb_matvec<MF>(L, e, v);
     if (wr) x[ln * len + xr] = xnext;
@@ -246,6 +250,7 @@ __device__ __forceinline__ void lb_solve_ring(const LineW& W, const LB<MF>& L, c
       xnext = lb_matvec<MF>(L, e[k % D], z);
       if (wr) x[ln * len + xr] = xnext;
     } else {
+      wave_lds_fence();   // w_ln was written by the row's first lane
       const double v = rin ? W.y(ln, xr) * xnext : 0.0;
       const double wl = rin ? x[ln * len + xr] : 0.0;
       xnext = wl + lb_matvec<MF>(L, e[k % D], v);

@@ -65,20 +65,32 @@ __device__ __forceinline__ int lb_pk(int row, int col) {
 
 // In-place inverse of the SPD block held as a[t] = D[row][col(t)]. Clears ok on a
 // non-positive pivot. The pivot loop runs in groups of EPL so that the register holding
-// column k is known at compile time.
+// column k is known at compile time. At each pivot the lanes of row k write that row, and the
+// lanes holding column k write that column, into LDS (prow, pcol: MF doubles each), from which
+// every lane reads the entries it needs (one wavefront: its lanes see each other's LDS writes
+// in program order); the same values, and the same arithmetic, as fetching them from the
+// owning lanes by shuffles.
 template <int MF>
-__device__ __forceinline__ void lb_inverse(const LB<MF>& L, double (&a)[LB<MF>::EPL], bool& ok) {
-  constexpr int EPL = LB<MF>::EPL, LPR = LB<MF>::LPR;
+__device__ __forceinline__ void lb_inverse(const LB<MF>& L, double (&a)[LB<MF>::EPL], bool& ok, double* prow,
+                                           double* pcol) {
+  constexpr int EPL = LB<MF>::EPL;
 #pragma unroll 1
   for (int k0 = 0; k0 < MF; k0 += EPL) {
 #pragma unroll
     for (int kk = 0; kk < EPL; ++kk) {
       const int k = k0 + kk;
+      wave_lds_fence();   // the reads of the previous pivot stay ahead of these writes
+      if (L.row == k) {
+#pragma unroll
+        for (int t = 0; t < EPL; ++t) prow[L.col(t)] = a[t];
+      }
+      if (L.cg == k0 / EPL) pcol[L.row] = a[kk];
+      wave_lds_fence();
       double rk[EPL];
 #pragma unroll
-      for (int t = 0; t < EPL; ++t) rk[t] = __shfl(a[t], k * LPR + L.cg);
-      const double ck = __shfl(a[kk], L.row * LPR + k0 / EPL);
-      const double d = __shfl(a[kk], k * LPR + k0 / EPL);
+      for (int t = 0; t < EPL; ++t) rk[t] = prow[L.col(t)];
+      const double ck = pcol[L.row];
+      const double d = prow[k];
       ok = ok && (d > 0.0);
       // 1/d: hardware reciprocal refined by two Newton steps (full double precision)
       double rd = __builtin_amdgcn_rcp(d);
