@@ -32,30 +32,30 @@ __device__ __forceinline__ size_t efac_off(const Geo& g, int sub) {
 }
 
 // Packed position of entry t of this lane's row (the same for every line).
-template <int MF>
-__device__ __forceinline__ void lb_pk_lane(const LB<MF>& L, int (&pk)[LB<MF>::EPL]) {
+template <int MF, int NT = 64>
+__device__ __forceinline__ void lb_pk_lane(const LB<MF, false, NT>& L, int (&pk)[LB<MF, false, NT>::EPL]) {
 #pragma unroll
-  for (int t = 0; t < LB<MF>::EPL; ++t) pk[t] = lb_pk<MF>(L.row, L.col(t));
+  for (int t = 0; t < LB<MF, false, NT>::EPL; ++t) pk[t] = lb_pk<MF>(L.row, L.col(t));
 }
 
 // Block elimination over all lines; the upper triangles of the inverses D_ln^-1 go to
 // Es[ln * P + packed position] (global; a reader in the same kernel needs a barrier first, as
 // the entries of a row below the diagonal were written by other lanes).
-template <int MF, typename T>
-__device__ __forceinline__ void lb_factor(const Geo& g, const LineW& W, const LB<MF>& L, T* Es, bool& ok) {
-  constexpr int EPL = LB<MF>::EPL;
+template <int MF, typename T, int NT = 64>
+__device__ __forceinline__ void lb_factor(const Geo& g, const LineW& W, const LB<MF, false, NT>& L, T* Es, bool& ok) {
+  constexpr int EPL = LB<MF, false, NT>::EPL;
   const int nl = g.nc / g.band;
   constexpr int P = LBP<MF>::P;
   int pk[EPL];
-  lb_pk_lane<MF>(L, pk);
-  __shared__ double piv[2 * MF];   // pivot row and column of the Gauss-Jordan sweep
+  lb_pk_lane<MF, NT>(L, pk);
+  __shared__ double piv[4 * MF];   // pivot rows and columns of the Gauss-Jordan sweep
   double prev[EPL], cur[EPL];
 #pragma unroll
   for (int t = 0; t < EPL; ++t) prev[t] = 0.0;
 #pragma unroll 1
   for (int ln = 0; ln < nl; ++ln) {
     lb_block<MF>(W, ln, L, prev, cur);
-    lb_inverse<MF>(L, cur, ok, piv, piv + MF);
+    lb_inverse<MF, NT>(L, cur, ok, piv);
 #pragma unroll
     for (int t = 0; t < EPL; ++t) {
       if (L.row <= L.col(t)) Es[size_t(ln) * P + pk[t]] = T(cur[t]);
@@ -1129,9 +1129,10 @@ k_downscale_lb(Geo g0, const double* __restrict__ kap_s, const double* __restric
 // Neumann inverse blocks of kappa^n for the subdomains whose conductivity tile changed since the
 // last MRCM update (listed by the conductivity kernel; elsewhere the kept kappa^m blocks are
 // exact). A fixed grid walks the list. Runs on a second stream, overlapped with the interface
-// solve.
-template <int MF, typename T>
-__global__ void __launch_bounds__(64)
+// solve. Blocks of lines of 32 cells are spread over the four wavefronts of a workgroup (NT =
+// 256 lanes: four entries each instead of sixteen), the others over one wavefront.
+template <int MF, typename T, int NT>
+__global__ void __launch_bounds__(NT)
 k_ds_factor(Geo g, const double* __restrict__ kap_n, T* __restrict__ Escr, const int32_t* __restrict__ list,
             const int32_t* __restrict__ count, int32_t* err, const RunTab* __restrict__ rt) {
   constexpr int NC = Cap<MF>::NC;
@@ -1144,7 +1145,7 @@ k_ds_factor(Geo g, const double* __restrict__ kap_n, T* __restrict__ Escr, const
     count = at_off(count, wo);
     err = at_off(err, wo);
   }
-  LB<MF> L;
+  LB<MF, false, NT> L;
   const int n = min(*count, g.nsub);
 #pragma unroll 1
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
@@ -1243,11 +1244,11 @@ static void ds_factor_any(hipStream_t st, const Geo& g, const double* kap_n, T* 
                           const int32_t* count, int32_t* err, Runs rt) {
   const dim3 grid(std::min(g.nsub, 1024), 1, runs_of(rt));
   if (line_mf(g) == 8)
-    hipLaunchKernelGGL((k_ds_factor<8, T>), grid, dim3(64), 0, st, g, kap_n, Escr, list, count, err, rt.tab);
+    hipLaunchKernelGGL((k_ds_factor<8, T, 64>), grid, dim3(64), 0, st, g, kap_n, Escr, list, count, err, rt.tab);
   else if (line_mf(g) == 16)
-    hipLaunchKernelGGL((k_ds_factor<16, T>), grid, dim3(64), 0, st, g, kap_n, Escr, list, count, err, rt.tab);
+    hipLaunchKernelGGL((k_ds_factor<16, T, 64>), grid, dim3(64), 0, st, g, kap_n, Escr, list, count, err, rt.tab);
   else if constexpr (sizeof(T) == 8)   // FP32 blocks: lines of at most 16 cells
-    hipLaunchKernelGGL((k_ds_factor<32, T>), grid, dim3(64), 0, st, g, kap_n, Escr, list, count, err, rt.tab);
+    hipLaunchKernelGGL((k_ds_factor<32, T, 256>), grid, dim3(256), 0, st, g, kap_n, Escr, list, count, err, rt.tab);
 }
 
 void launch_ds_factor(hipStream_t st, const Geo& g, const double* kap_n, double* Escr, const int32_t* list,

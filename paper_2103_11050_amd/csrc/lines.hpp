@@ -21,16 +21,18 @@
 
 namespace mpm {
 
+// A block spread over NT lanes (one wavefront, or NT / 64 wavefronts of one workgroup):
 // IL = false: lane (row, cg) holds columns cg*EPL + t (contiguous groups);
 // IL = true : lane (row, cg) holds columns cg + LPR*t (interleaved), the layout whose entry t
 //             is the matrix-core operand of the t-th K-chunk.
-template <int MF, bool IL = false>
+template <int MF, bool IL = false, int NT = 64>
 struct LB {
-  static constexpr int EPL = MF * MF / 64;   // entries per lane
+  static constexpr int EPL = MF * MF / NT;   // entries per lane
   static constexpr int LPR = MF / EPL;       // lanes per row
+  static_assert(EPL >= 1 && LPR * EPL == MF, "block layout");
   int lane, row, cg;
   __device__ LB() {
-    lane = threadIdx.x & 63;
+    lane = threadIdx.x & (NT - 1);
     row = lane / LPR;
     cg = lane % LPR;
   }
@@ -66,26 +68,29 @@ __device__ __forceinline__ int lb_pk(int row, int col) {
 // In-place inverse of the SPD block held as a[t] = D[row][col(t)]. Clears ok on a
 // non-positive pivot. The pivot loop runs in groups of EPL so that the register holding
 // column k is known at compile time. At each pivot the lanes of row k write that row, and the
-// lanes holding column k write that column, into LDS (prow, pcol: MF doubles each), from which
-// every lane reads the entries it needs (one wavefront: its lanes see each other's LDS writes
-// in program order); the same values, and the same arithmetic, as fetching them from the
-// owning lanes by shuffles.
-template <int MF>
-__device__ __forceinline__ void lb_inverse(const LB<MF>& L, double (&a)[LB<MF>::EPL], bool& ok, double* prow,
-                                           double* pcol) {
-  constexpr int EPL = LB<MF>::EPL;
+// lanes holding column k write that column, into LDS, from which every lane reads the entries
+// it needs; the same values, and the same arithmetic, as fetching them from the owning lanes by
+// shuffles. piv holds 4 MF doubles: row and column of even pivots, then of odd pivots (two
+// buffers, so one synchronisation per pivot: a wavefront-scope fence for one wavefront, whose
+// lanes see each other's LDS writes in program order, a workgroup barrier for several).
+template <int MF, int NT = 64>
+__device__ __forceinline__ void lb_inverse(const LB<MF, false, NT>& L, double (&a)[LB<MF, false, NT>::EPL], bool& ok,
+                                           double* piv) {
+  constexpr int EPL = LB<MF, false, NT>::EPL;
 #pragma unroll 1
   for (int k0 = 0; k0 < MF; k0 += EPL) {
 #pragma unroll
     for (int kk = 0; kk < EPL; ++kk) {
       const int k = k0 + kk;
-      wave_lds_fence();   // the reads of the previous pivot stay ahead of these writes
+      double* prow = piv + 2 * MF * (k & 1);
+      double* pcol = prow + MF;
       if (L.row == k) {
 #pragma unroll
         for (int t = 0; t < EPL; ++t) prow[L.col(t)] = a[t];
       }
       if (L.cg == k0 / EPL) pcol[L.row] = a[kk];
-      wave_lds_fence();
+      if constexpr (NT == 64) wave_lds_fence();
+      else __syncthreads();
       double rk[EPL];
 #pragma unroll
       for (int t = 0; t < EPL; ++t) rk[t] = prow[L.col(t)];
@@ -264,10 +269,11 @@ struct LineW {
 };
 
 // Builds D_ln for line ln in registers: T_ln - Y_{ln-1} Eprev Y_{ln-1}.
-template <int MF, bool IL>
-__device__ __forceinline__ void lb_block(const LineW& W, int ln, const LB<MF, IL>& L,
-                                         const double (&Eprev)[LB<MF>::EPL], double (&a)[LB<MF>::EPL]) {
-  constexpr int EPL = LB<MF>::EPL;
+template <int MF, bool IL, int NT>
+__device__ __forceinline__ void lb_block(const LineW& W, int ln, const LB<MF, IL, NT>& L,
+                                         const double (&Eprev)[LB<MF, IL, NT>::EPL],
+                                         double (&a)[LB<MF, IL, NT>::EPL]) {
+  constexpr int EPL = LB<MF, IL, NT>::EPL;
   const int len = W.band;
   const int r = L.row;
   const bool rin = r < len;
