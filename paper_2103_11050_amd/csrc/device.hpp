@@ -73,6 +73,16 @@ __device__ __forceinline__ double wave_sum(double v) {
   v += __shfl_xor(v, 32);
   return v;
 }
+// The largest value over the 64 lanes, in every lane (same pattern; fmax is exact).
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0x141>(v));
+  v = fmax(v, dpp_f64<0x140>(v));
+  v = fmax(v, __shfl_xor(v, 16));
+  v = fmax(v, __shfl_xor(v, 32));
+  return v;
+}
 
 // Makes the LDS writes of this wavefront's lanes visible to the LDS reads that follow in other
 // lanes of the same wavefront: a fence at wavefront scope (the lanes of a wavefront perform their
@@ -319,8 +329,9 @@ __device__ __forceinline__ int32_t* err_word(double* scal) { return reinterpret_
 __device__ __forceinline__ bool finite_d(double v) { return fabs(v) <= 1.7976931348623157e308; }
 
 // Transport sub-step from the maximum outflow rate and the boundary inflow, reduced in a fixed
-// order from per-subdomain partials (run by one workgroup of 256 threads; each thread issues
-// its loads in batches of 16 before adding them).
+// order from per-subdomain partials (run by one workgroup of 256 threads, sm and ss LDS arrays of
+// 4 doubles; each thread issues its loads in batches of 16 before adding them, then each
+// wavefront reduces its lanes and thread 0 its wavefronts).
 __device__ __forceinline__ void reduce_dt(int nsub, const double* red_rate, const double* red_qin, double* scal,
                                           double* sm, double* ss) {
   constexpr int B = 16;
@@ -345,15 +356,18 @@ __device__ __forceinline__ void reduce_dt(int nsub, const double* red_rate, cons
       }
     }
   }
-  sm[threadIdx.x] = m;
-  ss[threadIdx.x] = s;
+  m = wave_max(m);
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) {
+    sm[threadIdx.x >> 6] = m;
+    ss[threadIdx.x >> 6] = s;
+  }
   bad = __syncthreads_or(bad);
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
-      ss[threadIdx.x] += ss[threadIdx.x + w];
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < 4; ++k) {
+      sm[0] = fmax(sm[0], sm[k]);
+      ss[0] += ss[k];
     }
-    __syncthreads();
   }
   if (threadIdx.x == 0) {
     // no flow anywhere (rate 0) leaves the step unbounded: flagged, and the step set to 0 so

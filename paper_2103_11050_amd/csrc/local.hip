@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(256) k_reduce_eps(int nblocks, int wc, const d
                                                     double* __restrict__ scal, int32_t* __restrict__ seq,
                                                     double* __restrict__ host, const RunTab* __restrict__ rt) {
   constexpr int B = 16;
-  __shared__ double sa[256], sb[256], sq[256], sw[256];
+  __shared__ double sa[4], sb[4], sq[4], sw[4];   // per-wavefront sums
   const int64_t wo = ws_off(rt);
   red = at_off(red, wo);
   scal = at_off(scal, wo);
@@ -176,21 +176,25 @@ __global__ void __launch_bounds__(256) k_reduce_eps(int nblocks, int wc, const d
       }
     }
   }
-  sa[threadIdx.x] = a;
-  sb[threadIdx.x] = b;
-  sq[threadIdx.x] = q;
-  sw[threadIdx.x] = w;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      sa[threadIdx.x] += sa[threadIdx.x + o];
-      sb[threadIdx.x] += sb[threadIdx.x + o];
-      sq[threadIdx.x] += sq[threadIdx.x + o];
-      sw[threadIdx.x] += sw[threadIdx.x + o];
-    }
-    __syncthreads();
+  a = wave_sum(a);
+  b = wave_sum(b);
+  q = wave_sum(q);
+  w = wave_sum(w);
+  if ((threadIdx.x & 63) == 0) {
+    const int wv = threadIdx.x >> 6;
+    sa[wv] = a;
+    sb[wv] = b;
+    sq[wv] = q;
+    sw[wv] = w;
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    for (int k = 1; k < 4; ++k) {
+      sa[0] += sa[k];
+      sb[0] += sb[k];
+      sq[0] += sq[k];
+      sw[0] += sw[k];
+    }
     scal[SC_EPS_NUM] = sa[0];
     scal[SC_EPS_DEN] = sb[0];
     if (wc) scal[SC_WCUT] = sq[0] > 0.0 ? sw[0] / sq[0] : 0.0;
@@ -210,7 +214,7 @@ __global__ void __launch_bounds__(256) k_reduce_eps(int nblocks, int wc, const d
 __global__ void __launch_bounds__(256) k_dt(int nsub, const double* __restrict__ red_rate,
                                             const double* __restrict__ red_qin,
                                             double* __restrict__ scal, int32_t* __restrict__ count, const RunTab* __restrict__ rt) {
-  __shared__ double sm[256], ss[256];
+  __shared__ double sm[4], ss[4];
   const int64_t wo = ws_off(rt);
   red_rate = at_off(red_rate, wo);
   red_qin = at_off(red_qin, wo);
