@@ -524,48 +524,47 @@ __device__ __forceinline__ void load_halo_tiles(const Geo& g, int I, int J, cons
       loc_ij(g, c < g.nc ? c : 0, &i, &j);
       qc[s] = q[(J * g.my + j) * g.nx + I * g.mx + i];
     }
-    __syncthreads();
-    return;
-  }
-  double a[NH], b[NH], fx[NF], fy[NF];
+  } else {
+    double a[NH], b[NH], fx[NF], fy[NF];
 #pragma unroll
-  for (int s = 0; s < NH; ++s) {
-    const int e = threadIdx.x + 64 * s;
-    const int ti = e % TW - 1, tj = e / TW - 1;
-    const int gi = I * g.mx + ti, gj = J * g.my + tj;
-    const bool edge_i = ti < 0 || ti >= g.mx, edge_j = tj < 0 || tj >= g.my;
-    const bool ok = e < nh && !(edge_i && edge_j) && gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
-    const int gc = ok ? gj * g.nx + gi : 0;
-    a[s] = kap_n[gc];
-    b[s] = kap_m[gc];
-  }
-#pragma unroll
-  for (int s = 0; s < NF; ++s) {
-    const int e = threadIdx.x + 64 * s;
-    const int ex = e < nfx ? e : 0, ey = e < nfy ? e : 0;
-    fx[s] = uxm[(J * g.my + ex / (g.mx + 1)) * (g.nx + 1) + I * g.mx + ex % (g.mx + 1)];
-    fy[s] = uym[(J * g.my + ey / g.mx) * g.nx + I * g.mx + ey % g.mx];
-  }
-#pragma unroll
-  for (int s = 0; s < CPL; ++s) {
-    const int c = threadIdx.x + 64 * s;
-    int i, j;
-    loc_ij(g, c < g.nc ? c : 0, &i, &j);
-    qc[s] = q[(J * g.my + j) * g.nx + I * g.mx + i];
-  }
-#pragma unroll
-  for (int s = 0; s < NH; ++s) {
-    const int e = threadIdx.x + 64 * s;
-    if (e < nh) {
-      kn[e] = a[s];
-      km[e] = b[s];
+    for (int s = 0; s < NH; ++s) {
+      const int e = threadIdx.x + 64 * s;
+      const int ti = e % TW - 1, tj = e / TW - 1;
+      const int gi = I * g.mx + ti, gj = J * g.my + tj;
+      const bool edge_i = ti < 0 || ti >= g.mx, edge_j = tj < 0 || tj >= g.my;
+      const bool ok = e < nh && !(edge_i && edge_j) && gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
+      const int gc = ok ? gj * g.nx + gi : 0;
+      a[s] = kap_n[gc];
+      b[s] = kap_m[gc];
     }
-  }
 #pragma unroll
-  for (int s = 0; s < NF; ++s) {
-    const int e = threadIdx.x + 64 * s;
-    if (e < nfx) ux[e] = fx[s];
-    if (e < nfy) uy[e] = fy[s];
+    for (int s = 0; s < NF; ++s) {
+      const int e = threadIdx.x + 64 * s;
+      const int ex = e < nfx ? e : 0, ey = e < nfy ? e : 0;
+      fx[s] = uxm[(J * g.my + ex / (g.mx + 1)) * (g.nx + 1) + I * g.mx + ex % (g.mx + 1)];
+      fy[s] = uym[(J * g.my + ey / g.mx) * g.nx + I * g.mx + ey % g.mx];
+    }
+#pragma unroll
+    for (int s = 0; s < CPL; ++s) {
+      const int c = threadIdx.x + 64 * s;
+      int i, j;
+      loc_ij(g, c < g.nc ? c : 0, &i, &j);
+      qc[s] = q[(J * g.my + j) * g.nx + I * g.mx + i];
+    }
+#pragma unroll
+    for (int s = 0; s < NH; ++s) {
+      const int e = threadIdx.x + 64 * s;
+      if (e < nh) {
+        kn[e] = a[s];
+        km[e] = b[s];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NF; ++s) {
+      const int e = threadIdx.x + 64 * s;
+      if (e < nfx) ux[e] = fx[s];
+      if (e < nfy) uy[e] = fy[s];
+    }
   }
   __syncthreads();
 }
