@@ -16,11 +16,25 @@ namespace {
 
 __device__ __forceinline__ int gcell2(const Geo& g, int I, int J, int i, int j) { return (J * g.my + j) * g.nx + I * g.mx + i; }
 
+// A subdomain's tile of a cell field into LDS (local order), four cells per thread in flight at a
+// time (their loads issued before the first store; addresses past the tile clamped to its first
+// cell, and not stored).
 __device__ __forceinline__ void load_tile2(const Geo& g, int I, int J, const double* src, double* dst) {
-  for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
-    int i, j;
-    loc_ij(g, c, &i, &j);
-    dst[c] = src[gcell2(g, I, J, i, j)];
+  constexpr int U = 4;
+  for (int c0 = threadIdx.x; c0 < g.nc; c0 += U * blockDim.x) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * blockDim.x;
+      int i, j;
+      loc_ij(g, c < g.nc ? c : 0, &i, &j);
+      v[u] = src[gcell2(g, I, J, i, j)];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * blockDim.x;
+      if (c < g.nc) dst[c] = v[u];
+    }
   }
 }
 
@@ -505,18 +519,45 @@ __device__ __forceinline__ void load_halo_tiles(const Geo& g, int I, int J, cons
   const int TW = g.mx + 2, nh = TW * (g.my + 2);
   const int nfx = g.my * (g.mx + 1), nfy = (g.my + 1) * g.mx;
   if constexpr (MF == 32) {
-    for (int e = threadIdx.x; e < nh; e += 64) {
-      const int ti = e % TW - 1, tj = e / TW - 1;
-      const int gi = I * g.mx + ti, gj = J * g.my + tj;
-      const bool edge_i = ti < 0 || ti >= g.mx, edge_j = tj < 0 || tj >= g.my;
-      const bool ok = !(edge_i && edge_j) && gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
-      const int gc = ok ? gj * g.nx + gi : 0;
-      kn[e] = kap_n[gc];
-      km[e] = kap_m[gc];
+    constexpr int U = 4;   // entries per thread in flight at a time
+    for (int e0 = threadIdx.x; e0 < nh; e0 += 64 * U) {
+      double a[U], b[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 64 * u;
+        const int ti = e % TW - 1, tj = e / TW - 1;
+        const int gi = I * g.mx + ti, gj = J * g.my + tj;
+        const bool edge_i = ti < 0 || ti >= g.mx, edge_j = tj < 0 || tj >= g.my;
+        const bool ok = e < nh && !(edge_i && edge_j) && gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny;
+        const int gc = ok ? gj * g.nx + gi : 0;
+        a[u] = kap_n[gc];
+        b[u] = kap_m[gc];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 64 * u;
+        if (e < nh) {
+          kn[e] = a[u];
+          km[e] = b[u];
+        }
+      }
     }
-    for (int e = threadIdx.x; e < nfx; e += 64)
-      ux[e] = uxm[(J * g.my + e / (g.mx + 1)) * (g.nx + 1) + I * g.mx + e % (g.mx + 1)];
-    for (int e = threadIdx.x; e < nfy; e += 64) uy[e] = uym[(J * g.my + e / g.mx) * g.nx + I * g.mx + e % g.mx];
+    for (int e0 = threadIdx.x; e0 < nfx || e0 < nfy; e0 += 64 * U) {
+      double fx[U], fy[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 64 * u;
+        const int ex = e < nfx ? e : 0, ey = e < nfy ? e : 0;
+        fx[u] = uxm[(J * g.my + ex / (g.mx + 1)) * (g.nx + 1) + I * g.mx + ex % (g.mx + 1)];
+        fy[u] = uym[(J * g.my + ey / g.mx) * g.nx + I * g.mx + ey % g.mx];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 64 * u;
+        if (e < nfx) ux[e] = fx[u];
+        if (e < nfy) uy[e] = fy[u];
+      }
+    }
 #pragma unroll
     for (int s = 0; s < CPL; ++s) {
       const int c = threadIdx.x + 64 * s;
