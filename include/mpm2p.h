@@ -269,9 +269,12 @@ mpm_status mpm_plan_solve_bytes(const mpm_run* run, int64_t* fwd_bytes, int64_t*
  * subdomains, interface elements and degree) start with it (a batch group launches with its
  * first run's shapes). Another shape changes the summation order of the solve: results move at
  * rounding level, so runs compared bitwise must share their shapes. The run must be started and
- * not in a batch (MPM_ESTATE). Host outputs (any may be NULL when cap is 0): shapes[3 k .. 3 k + 2]
- * = (lanes per row, column pairs per lane, rows per group) of launch k, forward levels upwards then
- * backward levels downwards, for the first cap / 3 launches; *n = the number of launches; *ms_rule
+ * not in a batch (MPM_ESTATE). The bottom levels of the tree can also be swept by one launch per
+ * direction (one workgroup per subtree, the default where the fronts fit it); the tuner times that
+ * against one launch per level first. Host outputs (any may be NULL when cap is 0): shapes[3 k ..
+ * 3 k + 2] = (lanes per row, column pairs per lane, rows per group) of launch k, or (0, number of
+ * levels, 0) for the fused bottom levels, forward launches upwards then backward launches
+ * downwards, for the first cap / 3 launches; *n = the number of launches; *ms_rule
  * and *ms_tuned = the solve time with the fixed rule and with the chosen shapes (ms). Synchronises
  * with the run's stream. */
 mpm_status mpm_tune(mpm_run* run, int32_t reps, int32_t cap, int32_t* shapes, int32_t* n, double* ms_rule,

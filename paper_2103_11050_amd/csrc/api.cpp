@@ -126,6 +126,8 @@ struct mpm_run {
   unsigned tab_n[2] = {0, 0};
   // launch shape of each interface-sweep level (nd_shape_code; 0 = the fixed rule), by level
   std::vector<int> tune_fwd, tune_bwd;
+  // the plan's bottom levels (P.fuse_h of them) swept by one launch per direction
+  bool fuse = false;
 
   hipEvent_t take_event() {
     if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
@@ -306,14 +308,23 @@ hipGraphExec_t capture_and_launch(mpm_run* r, F&& body) {
   return exec;
 }
 
+// The fused bottom levels of the interface sweeps are on by default; MPM2P_FUSE=0 keeps one
+// launch per level (for measurements against them).
+bool fuse_default() {
+  const char* e = std::getenv("MPM2P_FUSE");
+  return !(e && e[0] == '0');
+}
+
 LeafOut leaf_dest(const mpm_run* r) { return LeafOut{r->slots, r->leafup, r->nd.map_pool}; }
 
 void nd_solve(mpm_run* r, Runs rt = one_run()) {
   const Plan& P = r->P;
   const int L = int(P.level_nodes.size()) - 1;
+  const int H = r->fuse ? P.fuse_h : 0;   // levels 1..H: one launch per direction
   {
     Scope sc(r, "iface_fwd");
-    for (int l = 1; l < L; ++l) {
+    if (H) launch_nd_sub_fwd(r->st, r->nd, P.fuse_roots, rt);
+    for (int l = H + 1; l < L; ++l) {
       const int nn = int(P.level_nodes[l].size());
       if (!nn) continue;
       const int sh = l < int(r->tune_fwd.size()) ? r->tune_fwd[l] : 0;
@@ -322,13 +333,14 @@ void nd_solve(mpm_run* r, Runs rt = one_run()) {
   }
   {
     Scope sc(r, "iface_bwd");
-    for (int l = L; l >= 1; --l) {
+    for (int l = L; l > H; --l) {
       const int nn = int(P.level_nodes[l].size());
       if (!nn) continue;
       const int sh = l < int(r->tune_bwd.size()) ? r->tune_bwd[l] : 0;
       launch_nd_level_bwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l], P.level_nmax[l], l == L ? 1 : 0, rt,
                           sh);
     }
+    if (H) launch_nd_sub_bwd(r->st, r->nd, P.fuse_roots, rt);
   }
 }
 
@@ -635,6 +647,11 @@ bool bind_workspace(mpm_run* r, char* ws) {
   r->nd.leafK = r->leafK; r->nd.y = r->y; r->nd.ndmax = P.ndmax;
   r->nd.piv_b = P.piv_b; r->nd.err = r->err;
   r->nd.lnodes = reinterpret_cast<const NodeDev*>(r->ws + P.off_lnodes);
+  r->nd.fnodes = reinterpret_cast<const FuseNode*>(r->ws + P.off_fnodes);
+  r->nd.flevels = reinterpret_cast<const FuseLevel*>(r->ws + P.off_flevels);
+  r->nd.fxsrc = reinterpret_cast<const int32_t*>(r->ws + P.off_fxsrc);
+  r->nd.fuse_h = P.fuse_h;
+  r->fuse = P.fuse_h > 0 && fuse_default();
   r->leafup = reinterpret_cast<const LeafUp*>(r->ws + P.off_leafup);
   r->M = P.d.mu_o / P.d.mu_w;
   r->fmax_deriv = max_fprime(r->M);
@@ -662,6 +679,9 @@ bool bind_workspace(mpm_run* r, char* ws) {
          in(r->leafup, ns * sizeof(LeafUp)) &&
          (!r->f32 || (in(r->fac32, P.n_blocks * 4) && in(r->nfac32, P.n_blocks * 4) && in(r->dsE32, P.n_blocks * 4))) &&
          in(r->nd.lnodes, std::max<size_t>(P.lnodes.size(), 1) * sizeof(NodeDev)) &&
+         in(r->nd.fnodes, std::max<size_t>(P.fnodes.size(), 1) * sizeof(FuseNode)) &&
+         in(r->nd.flevels, std::max<size_t>(P.flevels.size(), 1) * sizeof(FuseLevel)) &&
+         in(r->nd.fxsrc, std::max<size_t>(P.fxsrc.size(), 1) * 4) &&
          (P.d.mpm_order != 1 || in(r->wbnd, ns * P.nb * 8));
 }
 
@@ -678,6 +698,9 @@ hipError_t upload_plan(mpm_run* r) {
   chain(up(P.off_nodes, P.nodes.data(), P.nodes.size() * sizeof(NodeDev)));
   chain(up(P.off_levels, P.level_flat.data(), P.level_flat.size() * 4));
   chain(up(P.off_lnodes, P.lnodes.data(), P.lnodes.size() * sizeof(NodeDev)));
+  chain(up(P.off_fnodes, P.fnodes.data(), P.fnodes.size() * sizeof(FuseNode)));
+  chain(up(P.off_flevels, P.flevels.data(), P.flevels.size() * sizeof(FuseLevel)));
+  chain(up(P.off_fxsrc, P.fxsrc.data(), P.fxsrc.size() * 4));
   chain(up(P.off_leafup, P.leafup.data(), P.leafup.size() * sizeof(LeafUp)));
   chain(hipMemsetAsync(r->slots, 0, size_t(std::max<int64_t>(P.slot_doubles, 1)) * 8, r->st));
   chain(up(P.off_dofpool, P.dof_pool.data(), P.dof_pool.size() * 4));
@@ -709,7 +732,11 @@ size_t static_bytes(const Plan& P) { return ((P.total_bytes + 255) & ~size_t(255
 // the grid, the subdomains, the interface elements and their degree): runs created later with the
 // same decomposition start from them.
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<std::vector<int>, std::vector<int>>> g_tune_cache;
+struct TuneChoice {
+  std::vector<int> fwd, bwd;
+  bool fuse;
+};
+std::map<std::string, TuneChoice> g_tune_cache;
 
 std::string tune_key(const mpm_desc& d) {
   const int32_t v[7] = {d.nx, d.ny, d.sub_x, d.sub_y, d.ne_x, d.ne_y, d.iface_degree};
@@ -720,8 +747,9 @@ void tune_from_cache(mpm_run* r) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune_cache.find(tune_key(r->P.d));
   if (it != g_tune_cache.end()) {
-    r->tune_fwd = it->second.first;
-    r->tune_bwd = it->second.second;
+    r->tune_fwd = it->second.fwd;
+    r->tune_bwd = it->second.bwd;
+    r->fuse = it->second.fuse && r->P.fuse_h > 0;
   }
 }
 
@@ -1529,13 +1557,23 @@ mpm_status mpm_tune(mpm_run* r, int32_t reps, int32_t cap, int32_t* shapes, int3
     };
     r->tune_fwd.assign(std::max(L + 1, 1), 0);
     r->tune_bwd.assign(std::max(L + 1, 1), 0);
+    const bool fuse_rule = P.fuse_h > 0 && fuse_default();
+    r->fuse = fuse_rule;
     double t_rule = 0.0, t = 0.0;
     mpm_status s2 = time_solve(&t_rule);
     if (s2) return s2;
     double cur = t_rule;
+    if (P.fuse_h > 0) {   // the fused bottom levels against one launch per level
+      r->fuse = !fuse_rule;
+      s2 = time_solve(&t);
+      if (s2) return s2;
+      if (t < 0.99 * cur) cur = t;
+      else r->fuse = fuse_rule;
+    }
+    const int H = r->fuse ? P.fuse_h : 0;
     for (int dir = 0; dir < 2; ++dir) {
       std::vector<int>& tab = dir == 0 ? r->tune_fwd : r->tune_bwd;
-      for (int l = 1; l <= L; ++l) {
+      for (int l = H + 1; l <= L; ++l) {
         if (P.level_nodes[l].empty() || (dir == 0 && l == L)) continue;   // the root has no forward step
         const int len = dir == 0 ? P.level_nImax[l] : P.level_nmax[l];
         const int rows = dir == 0 ? P.level_nBmax[l] : P.level_nImax[l];
@@ -1556,13 +1594,14 @@ mpm_status mpm_tune(mpm_run* r, int32_t reps, int32_t cap, int32_t* shapes, int3
     if (t > t_rule) {   // keep the rule if the choice does not hold up
       std::fill(r->tune_fwd.begin(), r->tune_fwd.end(), 0);
       std::fill(r->tune_bwd.begin(), r->tune_bwd.end(), 0);
+      r->fuse = fuse_rule;
       t = t_rule;
     }
     if (ms_rule) *ms_rule = t_rule;
     if (ms_tuned) *ms_tuned = t;
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
-      g_tune_cache[tune_key(P.d)] = {r->tune_fwd, r->tune_bwd};
+      g_tune_cache[tune_key(P.d)] = TuneChoice{r->tune_fwd, r->tune_bwd, r->fuse};
     }
     // the chosen shape of every launch, forward levels upwards then backward levels downwards
     int32_t k = 0;
@@ -1581,10 +1620,21 @@ mpm_status mpm_tune(mpm_run* r, int32_t reps, int32_t cap, int32_t* shapes, int3
       }
       ++k;
     };
-    for (int l = 1; l < L; ++l)
+    auto put_fused = [&]() {   // the fused bottom levels: (0, their number, 0)
+      if (3 * k + 2 < cap) {
+        shapes[3 * k] = 0;
+        shapes[3 * k + 1] = P.fuse_h;
+        shapes[3 * k + 2] = 0;
+      }
+      ++k;
+    };
+    const int Hf = r->fuse ? P.fuse_h : 0;
+    if (Hf) put_fused();
+    for (int l = Hf + 1; l < L; ++l)
       if (!P.level_nodes[l].empty()) put(r->tune_fwd[l], P.level_nImax[l], P.level_nBmax[l], false);
-    for (int l = L; l >= 1; --l)
+    for (int l = L; l > Hf; --l)
       if (!P.level_nodes[l].empty()) put(r->tune_bwd[l], P.level_nmax[l], P.level_nImax[l], true);
+    if (Hf) put_fused();
     if (n) *n = k;
     return MPM_OK;
   };

@@ -115,6 +115,10 @@ struct NdArgs {
   int ndmax;
   int piv_b;
   int32_t* err;
+  const FuseNode* fnodes;     // fused bottom levels: the nodes subtree by subtree, level by level
+  const FuseLevel* flevels;   // subtree t, level h (1..H): flevels[t H + h - 1]
+  const int32_t* fxsrc;       // where the backward sweep finds each fused node's x_B entries
+  int fuse_h;                 // H (0: no fused levels)
 };
 // The same arguments for a workspace at byte offset o.
 __device__ __forceinline__ NdArgs nd_at(const NdArgs& a, int64_t o) {
@@ -132,6 +136,9 @@ __device__ __forceinline__ NdArgs nd_at(const NdArgs& a, int64_t o) {
   b.leafK = at_off(a.leafK, o);
   b.y = at_off(a.y, o);
   b.err = at_off(a.err, o);
+  b.fnodes = at_off(a.fnodes, o);
+  b.flevels = at_off(a.flevels, o);
+  b.fxsrc = at_off(a.fxsrc, o);
   return b;
 }
 void launch_nd_level_factor(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nmax, int nImax,
@@ -148,6 +155,10 @@ void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int level_off, int nno
                          Runs rt = one_run(), int shape = 0);
 void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nImax, int nmax, int root,
                          Runs rt = one_run(), int shape = 0);
+// The fused bottom levels (a.fuse_h of them) of the forward and of the backward sweep: one
+// workgroup per subtree.
+void launch_nd_sub_fwd(hipStream_t st, const NdArgs& a, int nsubtrees, Runs rt = one_run());
+void launch_nd_sub_bwd(hipStream_t st, const NdArgs& a, int nsubtrees, Runs rt = one_run());
 
 // transport.hip
 // (the viscosity ratio M is the run's, from scal)

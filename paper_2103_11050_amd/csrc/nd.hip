@@ -750,4 +750,381 @@ void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, 
   else ND_RB_LAUNCH(k_nd_bwd_inner, sh, nImax, nnodes, runs_of(rt), st, a, loff, rt.tab);
 }
 
+// ---------------------------------------------------------------------------------------------
+// The bottom levels of both sweeps in one launch per direction. One workgroup takes one subtree
+// (a node of level <= H whose parent lies above H, and its descendants) and its levels in order,
+// upwards in the forward sweep and downwards in the backward one, with a barrier between levels.
+// What passes between the subtree's levels stays in LDS: forward, the front vectors of all its
+// nodes (the leaves' slots loaded at the start, each row's result added into its parent's vector,
+// two terms per entry at most, so that the order of the additions does not change the sum);
+// backward, its separator unknowns (x_B entries from outside the subtree gathered at the start).
+// Only the subtree root's forward results, f_I and x_I go out to global memory. The rows of all a
+// level's nodes are dealt to lane groups; a level costs one round trip for its block rows. The
+// products of a row are those of the level kernels above, summed over the lane group by halving
+// exchanges.
+namespace {
+
+constexpr int SUB_NT = 512;
+
+// A level's prefix sums (one of the FuseNode counts) in registers, a bound past every entry
+// beyond the level's nodes, and the node of entry i with its first entry by selection: no branch
+// or memory access between the loads of a batch. cnt >= 1.
+struct SubSel {
+  int c[FUSE_MAXN];
+  __device__ __forceinline__ SubSel(const FuseNode* f, int cnt, int which) {
+#pragma unroll
+    for (int q = 0; q < FUSE_MAXN; ++q) {
+      const FuseNode& x = f[q < cnt ? q : 0];
+      const int v = which == 0 ? x.fr : which == 1 ? x.fv : which == 2 ? x.br : which == 3 ? x.bv : x.fc;
+      c[q] = q < cnt ? v : 0x7fffffff;
+    }
+  }
+  __device__ __forceinline__ int node(int i, int* start) const {
+    int k = 0, s0 = 0;
+#pragma unroll
+    for (int q = 1; q < FUSE_MAXN; ++q)
+      if (i >= c[q]) {
+        k = q;
+        s0 = c[q];
+      }
+    *start = s0;
+    return k;
+  }
+};
+
+// Sums of RQ rows over a group of G lanes, every lane holding partials of all RQ rows: each
+// halving exchange (lane bit S) keeps the rows whose bit S matches the lane's and sends the
+// others, so that after log2 RQ of them a lane holds row (lane mod RQ) only; the remaining lane
+// bits are summed. Lane p < RQ returns row p's sum.
+template <int K, int S>
+__device__ __forceinline__ void bfly_halve(double* w, int gl) {
+  if constexpr (K > 1) {
+    const bool bit = (gl >> S) & 1;
+#pragma unroll
+    for (int j = 0; j < K / 2; ++j) {
+      const double lo = w[2 * j], hi = w[2 * j + 1];
+      const double keep = bit ? hi : lo, send = bit ? lo : hi;
+      w[j] = keep + __shfl_xor(send, 1 << S);
+    }
+    bfly_halve<K / 2, S + 1>(w, gl);
+  }
+}
+template <int G, int RQ>
+__device__ __forceinline__ double bfly_sum(double* w, int gl) {
+  bfly_halve<RQ, 0>(w, gl);
+  double v = w[0];
+#pragma unroll
+  for (int o = RQ; o < G; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// One forward level: c_B = f_B - BI f_I = f_B - IB^T f_I (IB is stored as the exact transpose
+// of BI), read as IB's rows, which lie in memory one after the other (BI's rows are short pieces
+// of the front's long rows). The node's front vector f (I then B part) is in LDS at sv + vb + bv.
+// A work item is a column pair of IB over a chunk of eight of its rows; the chunk sums go through
+// LDS (part) and are added in chunk order per column, so that the sum does not depend on the
+// scheduling. A column's result goes into its parent's vector (LDS) or, at the subtree root, to
+// the parent's slot (res, dst; dst -1 for the other rows).
+__device__ __forceinline__ void sub_fwd_level(const NdArgs& a, const FuseNode* f, const FuseLevel& lv, double* sv,
+                                              double2* part, double* res, int32_t* dst) {
+  constexpr int RC = 8;
+  const int cnt = lv.e - lv.b;
+  const SubSel cs(f, cnt, 4), ps(f, cnt, 0);
+  const double* cur = sv + lv.vb;
+  const int npair = lv.fR / 2;
+  // the targets of this thread's first column pair (fetched with the block loads)
+  int32_t t0 = 0, t1 = 0;
+  {
+    int st;
+    const int P = min(int(threadIdx.x), npair - 1);
+    const int k = ps.node(2 * P, &st);
+    const int j = 2 * P - st;
+    const int32_t* mp = a.map_pool + f[k].nd.up_map_off + j;
+    t0 = mp[0];
+    t1 = mp[1];
+  }
+  for (int it0 = 0; it0 < lv.fC; it0 += SUB_NT) {
+    int st;
+    const int it = min(it0 + int(threadIdx.x), lv.fC - 1);
+    const int k = cs.node(it, &st);
+    const int n = f[k].nd.n, nI = f[k].nd.nI, pairs = f[k].nd.nB / 2;
+    const int loc = it - st, q = loc / pairs, p = loc - q * pairs;
+    const double* F = a.front + f[k].nd.front_off;
+    double2 m[RC];
+#pragma unroll
+    for (int u = 0; u < RC; ++u)
+      m[u] = ld32x2(F, uint32_t(min(RC * q + u, nI - 1)) * uint32_t(n) + uint32_t(nI + 2 * p));
+    const double* fI = cur + f[k].bv;
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int u = 0; u < RC; ++u)
+      if (RC * q + u < nI) {
+        sx += m[u].x * fI[RC * q + u];
+        sy += m[u].y * fI[RC * q + u];
+      }
+    if (it0 + int(threadIdx.x) < lv.fC) part[it0 + threadIdx.x] = make_double2(sx, sy);
+  }
+  __syncthreads();
+  for (int P = threadIdx.x; P < npair; P += SUB_NT) {
+    int st;
+    const int k = ps.node(2 * P, &st);
+    const int j = 2 * P - st;   // even column of the node's B part
+    const int nI = f[k].nd.nI, pairs = f[k].nd.nB / 2, nch = (nI + RC - 1) / RC;
+    const double2* pp = part + f[k].fc + j / 2;
+    double2 s = pp[0];
+    for (int q = 1; q < nch; ++q) {
+      s.x += pp[q * pairs].x;
+      s.y += pp[q * pairs].y;
+    }
+    if (P >= int(SUB_NT)) {   // beyond the first pair of this thread: targets fetched here
+      const int32_t* mp = a.map_pool + f[k].nd.up_map_off + j;
+      t0 = mp[0];
+      t1 = mp[1];
+    }
+    const double v0 = cur[f[k].bv + nI + j] - s.x, v1 = cur[f[k].bv + nI + j + 1] - s.y;
+    const int r = 2 * P;   // the level's row index of column j
+    if (f[k].pv >= 0) {
+      atomicAdd(sv + f[k].pv + t0, v0);
+      atomicAdd(sv + f[k].pv + t1, v1);
+      dst[r] = -1;
+      dst[r + 1] = -1;
+    } else {
+      res[r] = v0;
+      res[r + 1] = v1;
+      dst[r] = int32_t(f[k].nd.up_slot_off) + t0;
+      dst[r + 1] = int32_t(f[k].nd.up_slot_off) + t1;
+    }
+  }
+}
+
+// One backward level: x_I = -II f_I - IB x_B, f_I from the forward sweep, x_B from the subtree's
+// separator unknowns (xres) or the gathered outside values (xb), by source (xsrc). G = 32 lanes
+// per row, CH chunks of 64 columns, 8 / CH rows per lane group and batch; results to xres, their
+// unknown ids to xid.
+template <int CH>
+__device__ __forceinline__ void sub_bwd_level(const NdArgs& a, const FuseNode* f, const FuseLevel& lv,
+                                              const int32_t* xsrc, const double* xb, double* xres, int32_t* xid,
+                                              double* vsh) {
+  constexpr int G = 32, RQ = 8 / CH, NG = SUB_NT / G, STEP = NG * RQ, VPT = FUSE_VEC / SUB_NT;
+  const int cnt = lv.e - lv.b, R = lv.bR, V = lv.bV;
+  const int gl = threadIdx.x % G, grp = threadIdx.x / G;
+  const SubSel rs(f, cnt, 2), vs(f, cnt, 3);
+  double xi[VPT];
+#pragma unroll
+  for (int q = 0; q < VPT; ++q) {
+    int st;
+    const int i = min(int(threadIdx.x) + SUB_NT * q, V - 1);
+    const int k = vs.node(i, &st);
+    xi[q] = a.fI[f[k].nd.fI_off + min(i - st, f[k].nd.nI - 1)];
+  }
+  double2 m[RQ][CH];
+  int kq[RQ];
+  int32_t drm = 0;
+  auto load = [&](int base) {
+    const int r0 = base + grp * RQ;
+#pragma unroll
+    for (int p = 0; p < RQ; ++p) {
+      int st;
+      const int k = rs.node(min(r0 + p, R - 1), &st);
+      const int i = min(r0 + p, R - 1) - st;
+      kq[p] = k;
+      const int n = f[k].nd.n;
+      const double* F = a.front + f[k].nd.front_off;
+      const uint32_t ro = uint32_t(i) * uint32_t(n);
+#pragma unroll
+      for (int c = 0; c < CH; ++c) m[p][c] = ld32x2(F, ro + uint32_t(min(64 * c + 2 * gl, n - 2)));
+    }
+    int st;
+    const int rm = min(r0 + min(gl, RQ - 1), R - 1);
+    const int km = rs.node(rm, &st);
+    drm = a.dof_pool[f[km].nd.dof_off + rm - st];
+  };
+  load(0);
+#pragma unroll
+  for (int q = 0; q < VPT; ++q) {
+    const int i = threadIdx.x + SUB_NT * q;
+    if (i < V) {
+      int st;
+      const int k = vs.node(i, &st);
+      const int c = i - st, nI = f[k].nd.nI;
+      double v = xi[q];
+      if (c >= nI) {
+        const int e = lv.xo + f[k].fr + c - nI;
+        const int32_t src = xsrc[e];
+        v = src >= 0 ? xres[src] : xb[e];
+      }
+      vsh[i] = v;
+    }
+  }
+  __syncthreads();
+  for (int base = 0;;) {
+    const int r0 = base + grp * RQ;
+    double w[RQ];
+#pragma unroll
+    for (int p = 0; p < RQ; ++p) {
+      const int n = f[kq[p]].nd.n;
+      const double* fv = vsh + f[kq[p]].bv;
+      double v = 0.0;
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int col = 64 * c + 2 * gl;
+        if (col < n) {
+          const double2 x = *reinterpret_cast<const double2*>(fv + col);
+          v += m[p][c].x * x.x;
+          v += m[p][c].y * x.y;
+        }
+      }
+      w[p] = v;
+    }
+    const double s = bfly_sum<G, RQ>(w, gl);
+    if (gl < RQ && r0 + gl < R) {
+      xres[lv.xr + r0 + gl] = -s;
+      xid[lv.xr + r0 + gl] = drm;
+    }
+    base += STEP;
+    if (base >= R) break;
+    load(base);
+  }
+  __syncthreads();   // the levels below read these x_I; vsh is reused
+}
+
+// The subtree's node records into LDS; returns the index of its first node.
+__device__ __forceinline__ int sub_nodes(const NdArgs& a, int t, int H, FuseNode* fn) {
+  const FuseLevel* L = a.flevels + size_t(t) * H;
+  const int n0 = L[0].b, ntot = L[H - 1].e - n0;
+  for (int i = threadIdx.x; i < ntot; i += SUB_NT) fn[i] = a.fnodes[n0 + i];
+  return n0;
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(SUB_NT) __attribute__((amdgpu_waves_per_eu(4)))
+k_nd_sub_fwd(NdArgs a0, const RunTab* __restrict__ rt) {
+  const NdArgs a = nd_at(a0, ws_off(rt));
+  __shared__ FuseNode fn[FUSE_HMAX * FUSE_MAXN];
+  __shared__ __align__(16) double sv[FUSE_SUBVEC];   // front vectors of the subtree's nodes
+  __shared__ double2 part[FUSE_ITEMS];                // chunk sums of the level's column pairs
+  __shared__ double res[FUSE_ROWS];
+  __shared__ int32_t dst[FUSE_ROWS];
+  const int H = a.fuse_h, t = blockIdx.x;
+  const int n0 = sub_nodes(a, t, H, fn);
+  __syncthreads();
+  // the front vectors from the slots the leaf children wrote (both leaves: slot 0 + slot 1, as
+  // the level kernels add them), zero where the children are nodes of the subtree
+  constexpr int VPT = FUSE_VEC / SUB_NT;
+#pragma unroll
+  for (int h = 0; h < FUSE_HMAX; ++h) {
+    const FuseLevel lv = a.flevels[size_t(t) * H + min(h, H - 1)];
+    const int cnt = lv.e - lv.b;
+    if (h < H && cnt > 0) {   // uniform
+      const FuseNode* f = fn + (lv.b - n0);
+      const SubSel vs(f, cnt, 3);
+      double u0[VPT], u1[VPT];
+#pragma unroll
+      for (int q = 0; q < VPT; ++q) {
+        int st;
+        const int i = min(int(threadIdx.x) + SUB_NT * q, lv.bV - 1);
+        const int k = vs.node(i, &st);
+        const double* s0 = a.slots + f[k].nd.slot_off;
+        u0[q] = s0[i - st];
+        u1[q] = s0[f[k].nd.n + i - st];
+      }
+#pragma unroll
+      for (int q = 0; q < VPT; ++q) {
+        const int i = threadIdx.x + SUB_NT * q;
+        if (i < lv.bV) {
+          int st;
+          const int k = vs.node(i, &st);
+          const bool l0 = f[k].nd.child[0] < 0, l1 = f[k].nd.child[1] < 0;
+          sv[lv.vb + i] = l0 && l1 ? u0[q] + u1[q] : l0 ? u0[q] : l1 ? u1[q] : 0.0;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int h = 0; h < H; ++h) {
+    const FuseLevel lv = a.flevels[size_t(t) * H + h];
+    if (lv.e == lv.b) continue;   // uniform over the workgroup
+    const FuseNode* f = fn + (lv.b - n0);
+    // f_I of the level's nodes, complete now, kept for the backward sweep
+    {
+      const SubSel vs(f, lv.e - lv.b, 1);
+      for (int i = threadIdx.x; i < lv.fV; i += SUB_NT) {
+        int st;
+        const int k = vs.node(i, &st);
+        a.fI[f[k].nd.fI_off + i - st] = sv[lv.vb + f[k].bv + i - st];
+      }
+    }
+    if (lv.fR > 0) sub_fwd_level(a, f, lv, sv, part, res, dst);
+    __syncthreads();   // the levels above read the vectors completed here
+    for (int r = threadIdx.x; r < lv.fR; r += SUB_NT)
+      if (dst[r] >= 0) a.slots[dst[r]] = res[r];
+    __syncthreads();   // res and dst are reused
+  }
+}
+
+__global__ void __launch_bounds__(SUB_NT) __attribute__((amdgpu_waves_per_eu(4)))
+k_nd_sub_bwd(NdArgs a0, const RunTab* __restrict__ rt) {
+  const NdArgs a = nd_at(a0, ws_off(rt));
+  __shared__ FuseNode fn[FUSE_HMAX * FUSE_MAXN];
+  __shared__ int32_t xsrc[FUSE_XB];   // x_B sources of the subtree's nodes, level by level
+  __shared__ double xb[FUSE_XB];      // x_B values from outside the subtree
+  __shared__ double xres[FUSE_XRES];  // the subtree's separator unknowns
+  __shared__ int32_t xid[FUSE_XRES];  // and their ids
+  __shared__ __align__(16) double vsh[FUSE_VEC];
+  const int H = a.fuse_h, t = blockIdx.x;
+  const int n0 = sub_nodes(a, t, H, fn);
+  // the x_B sources of every level, and the values from outside the subtree
+  constexpr int XPT = FUSE_ROWS / SUB_NT;
+  int32_t sc[FUSE_HMAX][XPT];
+  double sx[FUSE_HMAX][XPT];
+#pragma unroll
+  for (int h = 0; h < FUSE_HMAX; ++h) {
+    const FuseLevel lv = a.flevels[size_t(t) * H + min(h, H - 1)];
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int i = min(int(threadIdx.x) + SUB_NT * q, max(lv.fR - 1, 0));
+      sc[h][q] = h < H && lv.fR > 0 ? a.fxsrc[lv.xc + i] : 0;
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < FUSE_HMAX; ++h)
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) sx[h][q] = a.y[sc[h][q] < 0 ? -1 - sc[h][q] : 0];
+#pragma unroll
+  for (int h = 0; h < FUSE_HMAX; ++h) {
+    const FuseLevel lv = a.flevels[size_t(t) * H + min(h, H - 1)];
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int i = threadIdx.x + SUB_NT * q;
+      if (h < H && i < lv.fR) {
+        xsrc[lv.xo + i] = sc[h][q];
+        xb[lv.xo + i] = sx[h][q];
+      }
+    }
+  }
+  __syncthreads();
+  for (int h = H - 1; h >= 0; --h) {
+    const FuseLevel lv = a.flevels[size_t(t) * H + h];
+    if (lv.e == lv.b) continue;
+    const FuseNode* f = fn + (lv.b - n0);
+    if (lv.bch <= 1) sub_bwd_level<1>(a, f, lv, xsrc, xb, xres, xid, vsh);
+    else if (lv.bch == 2) sub_bwd_level<2>(a, f, lv, xsrc, xb, xres, xid, vsh);
+    else if (lv.bch == 3) sub_bwd_level<3>(a, f, lv, xsrc, xb, xres, xid, vsh);
+    else sub_bwd_level<4>(a, f, lv, xsrc, xb, xres, xid, vsh);
+  }
+  const FuseLevel top = a.flevels[size_t(t) * H + H - 1];
+  for (int r = threadIdx.x; r < top.xr + top.bR; r += SUB_NT) a.y[xid[r]] = xres[r];
+}
+
+void launch_nd_sub_fwd(hipStream_t st, const NdArgs& a, int nsubtrees, Runs rt) {
+  if (a.fuse_h <= 0 || nsubtrees <= 0) return;
+  hipLaunchKernelGGL(k_nd_sub_fwd, dim3(nsubtrees, 1, runs_of(rt)), dim3(SUB_NT), 0, st, a, rt.tab);
+}
+
+void launch_nd_sub_bwd(hipStream_t st, const NdArgs& a, int nsubtrees, Runs rt) {
+  if (a.fuse_h <= 0 || nsubtrees <= 0) return;
+  hipLaunchKernelGGL(k_nd_sub_bwd, dim3(nsubtrees, 1, runs_of(rt)), dim3(SUB_NT), 0, st, a, rt.tab);
+}
+
 }  // namespace mpm

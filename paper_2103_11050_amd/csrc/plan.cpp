@@ -297,6 +297,105 @@ void build_plan(const mpm_desc& d, Plan* p) {
   for (int32_t id : P.level_flat) P.lnodes.push_back(P.nodes[id]);
   P.off_lnodes = take(std::max<size_t>(P.lnodes.size(), 1) * sizeof(NodeDev));
   P.off_leafup = take(std::max<size_t>(P.leafup.size(), 1) * sizeof(LeafUp));
+  // subtrees of the fused bottom levels: the deepest H <= FUSE_HMAX below the root level whose
+  // subtrees all fit the limits of the fused kernels
+  P.fuse_h = 0;
+  P.fuse_roots = 0;
+  P.flevels.clear();
+  P.fnodes.clear();
+  P.fxsrc.clear();
+  {
+    const int top = int(P.level_nodes.size()) - 1;
+    std::vector<int32_t> parent(P.nodes.size(), -1);
+    for (size_t i = 0; i < P.nodes.size(); ++i)
+      for (int c = 0; c < 2; ++c)
+        if (P.nodes[i].child[c] >= 0) parent[P.nodes[i].child[c]] = int32_t(i);
+    // (the fused kernels keep slot indices in 32 bits)
+    const int hmax = P.slot_doubles < (int64_t(1) << 31) ? std::min(FUSE_HMAX, top - 1) : 0;
+    for (int H = hmax; H >= 2 && !P.fuse_h; --H) {
+      std::vector<FuseLevel> lv;
+      std::vector<FuseNode> fn;
+      std::vector<int32_t> xs;
+      bool ok = true;
+      for (int32_t v : P.level_flat) {
+        const NodeDev& nv = P.nodes[v];
+        if (nv.level > H || (parent[v] >= 0 && P.nodes[parent[v]].level <= H)) continue;
+        std::vector<std::vector<int32_t>> byl(H + 1);
+        std::vector<int32_t> stack{v};
+        while (!stack.empty()) {
+          const int32_t u = stack.back();
+          stack.pop_back();
+          byl[P.nodes[u].level].push_back(u);
+          for (int c = 0; c < 2; ++c)
+            if (P.nodes[u].child[c] >= 0) stack.push_back(P.nodes[u].child[c]);
+        }
+        // places within the subtree: each node's front vector in its level (bv), each level's
+        // separator unknowns (xr) and boundary entries (xo)
+        std::unordered_map<int32_t, int32_t> bv_of, br_of;
+        std::vector<int32_t> xr(H + 2, 0), xo(H + 2, 0), vb(H + 2, 0);
+        for (int l = 1; l <= H; ++l) {
+          int32_t sv = 0, sr = 0, sb = 0;
+          for (int32_t u : byl[l]) {
+            bv_of[u] = vb[l] + sv;
+            br_of[u] = sr;
+            sv += P.nodes[u].n;
+            sr += P.nodes[u].nI;
+            sb += P.nodes[u].nB;
+          }
+          xr[l + 1] = xr[l] + sr;
+          xo[l + 1] = xo[l] + sb;
+          vb[l + 1] = vb[l] + sv;
+        }
+        ok = ok && xr[H + 1] <= FUSE_XRES && xo[H + 1] <= FUSE_XB && vb[H + 1] <= FUSE_SUBVEC;
+        for (int l = 1; l <= H; ++l) {
+          FuseLevel L{int32_t(fn.size()), 0, 0, 0, 0, 0, 0, 0, int32_t(xs.size()), xo[l], xr[l], vb[l]};
+          int nImax = 0, nmax = 0;
+          for (int32_t u : byl[l]) {
+            const NodeDev& x = P.nodes[u];
+            const int32_t p = parent[u];
+            const bool inside = p >= 0 && P.nodes[p].level <= H;
+            fn.push_back(FuseNode{x, L.fR, L.fV, L.bR, L.bV, inside ? bv_of[p] : -1, L.fC});
+            // x_B sources: a separator unknown of an ancestor inside the subtree, else the id
+            for (int c = 0; c < x.nB; ++c) {
+              const int32_t d = P.dof_pool[x.dof_off + x.nI + c];
+              int32_t src = -1 - d;
+              for (int32_t an = p; an >= 0 && P.nodes[an].level <= H && src < 0; an = parent[an]) {
+                const NodeDev& A = P.nodes[an];
+                for (int i = 0; i < A.nI; ++i)
+                  if (P.dof_pool[A.dof_off + i] == d) {
+                    src = xr[A.level] + br_of[an] + i;
+                    break;
+                  }
+              }
+              xs.push_back(src);
+            }
+            L.fR += x.nB;
+            L.fV += x.nI;
+            L.bR += x.nI;
+            L.bV += x.n;
+            L.fC += (x.nB / 2) * ((x.nI + 7) / 8);
+            ok = ok && x.nB % 2 == 0;
+            nImax = std::max(nImax, int(x.nI));
+            nmax = std::max(nmax, int(x.n));
+          }
+          L.e = int32_t(fn.size());
+          L.bch = (nmax + 63) / 64;
+          ok = ok && int(byl[l].size()) <= FUSE_MAXN && nImax <= FUSE_FWD_NI && nmax <= FUSE_BWD_N &&
+               L.bV <= FUSE_VEC && L.fR <= FUSE_ROWS && L.bR <= FUSE_ROWS && L.fC <= FUSE_ITEMS;
+          lv.push_back(L);
+        }
+      }
+      if (!ok) continue;
+      P.fuse_h = H;
+      P.fuse_roots = int(lv.size()) / H;
+      P.flevels = std::move(lv);
+      P.fnodes = std::move(fn);
+      P.fxsrc = std::move(xs);
+    }
+  }
+  P.off_fnodes = take(std::max<size_t>(P.fnodes.size(), 1) * sizeof(FuseNode));
+  P.off_flevels = take(std::max<size_t>(P.flevels.size(), 1) * sizeof(FuseLevel));
+  P.off_fxsrc = take(std::max<size_t>(P.fxsrc.size(), 1) * 4);
   const size_t blocks = (ncell + 255) / 256 + size_t(P.nsub) + 64;
   P.n_red = 4 * blocks;
   P.off_red = take(P.n_red * 8);

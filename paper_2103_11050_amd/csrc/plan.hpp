@@ -46,6 +46,39 @@ struct LeafUp {
   int32_t pad;
 };
 
+// The bottom levels of both sweeps can run as one launch per direction, one workgroup per
+// subtree (a node of level <= H whose parent lies above H, with its descendants), the vectors
+// that pass between the subtree's levels kept in LDS. Per subtree and level at most FUSE_MAXN
+// nodes, forward rows (nI entries) at most FUSE_FWD_NI long, backward rows (n entries) at most
+// FUSE_BWD_N long, the front vectors of a level at most FUSE_VEC entries together, its rows at
+// most FUSE_ROWS in either direction and its forward work items (a column pair of IB over eight
+// of its rows) at most FUSE_ITEMS; over the subtree's levels at most FUSE_SUBVEC front vector
+// entries, FUSE_XB boundary entries and FUSE_XRES separator unknowns.
+constexpr int FUSE_HMAX = 3, FUSE_MAXN = 8;
+constexpr int FUSE_FWD_NI = 64, FUSE_BWD_N = 256, FUSE_VEC = 1024, FUSE_ROWS = 1024;
+constexpr int FUSE_XB = 2048, FUSE_XRES = 1024, FUSE_SUBVEC = 2048, FUSE_ITEMS = 1024;
+
+// A node of a fused subtree with its place in its level's lists: the rows and vector entries of
+// the level's nodes before it, forward (nB rows, nI entries) and backward (nI rows, n entries:
+// also its place among the level's front vectors); pv = the place of its parent's front vector in
+// the subtree's list of them (-1: the parent lies outside the subtree); fc = the forward work
+// items of the level's nodes before it (nB / 2 column pairs times ceil(nI / 8) row chunks each).
+struct FuseNode {
+  NodeDev nd;
+  int32_t fr, fv, br, bv, pv, fc;
+};
+// One level of a fused subtree: nodes fnodes[b .. e), their totals (fC: forward work items), the
+// column chunks of the longest backward row (chunks of 64 entries); xc = offset of the level's x_B
+// sources in fxsrc, xo = their place in the subtree's list, xr = the place of the level's
+// separator unknowns in the subtree's list of them, vb = the place of the level's front vectors
+// in the subtree's list of them.
+struct FuseLevel {
+  int32_t b, e;
+  int32_t fR, fV, bR, bV;
+  int32_t fC, bch;
+  int32_t xc, xo, xr, vb;
+};
+
 // Runs of one batch that share their decomposition step through one launch per phase:
 // blockIdx.z selects the run, whose workspace (and pinned host block) sits at a byte offset
 // from the first run's; the launch carries the first run's pointers and this table, which
@@ -90,6 +123,15 @@ struct Plan {
   std::vector<int32_t> level_flat;
   std::vector<NodeDev> lnodes;        // the nodes again, level by level (level_flat order)
   std::vector<LeafUp> leafup;         // per subdomain
+  // fused bottom levels (fuse_h = 0: none): level h (1..fuse_h) of subtree t is
+  // flevels[t fuse_h + h - 1]; a subtree's nodes are contiguous in fnodes, level by level
+  int fuse_h = 0, fuse_roots = 0;
+  std::vector<FuseLevel> flevels;
+  std::vector<FuseNode> fnodes;
+  // per fused node and boundary entry, in row order: where the backward sweep finds x_B: >= 0,
+  // the subtree's separator unknown of that place; < 0, -1 - its unknown id (outside the subtree)
+  std::vector<int32_t> fxsrc;
+  size_t off_fnodes = 0, off_flevels = 0, off_fxsrc = 0;
   size_t off_lnodes = 0, off_leafup = 0, off_slot = 0;
   size_t off_dsE = 0, off_nfac = 0;   // downscale inverse blocks: scratch and the kept kappa^m ones
   size_t n_blocks = 0;                // entries of one block set (kept kappa^m Robin, Neumann, scratch)

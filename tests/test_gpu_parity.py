@@ -297,6 +297,40 @@ def test_graph_replays_match_eager(binding, monkeypatch):
         assert a[3] == b[3] and a[4] == b[4], n
 
 
+def test_fused_bottom_levels_match_level_launches(binding, monkeypatch):
+    """The bottom levels of the interface sweeps taken by one launch per direction (one
+    workgroup per subtree of the nested-dissection tree) against one launch per level: the same
+    velocity and saturation up to the summation order of the row products, on a regular tree
+    (256^2 in 16 x 16 subdomains, three fused levels) and on ragged ones (9 x 13 and 5 x 3
+    subdomains). Every other parity test runs with the fused levels, the default."""
+    problems = [
+        (inputs.config("c2"), None),
+        inputs.random_problem(5, 144, 208, 16, 16, 4, 4, sigma2=2.0, corr_len=0.1),
+        inputs.random_problem(9, 40, 24, 8, 8, 2, 2, sigma2=3.0, corr_len=0.15),
+    ]
+    forces = [binding.AUTO, binding.FORCE_MPM, binding.FORCE_MRCM, binding.FORCE_MPM]
+    for cfg, K in problems:
+        K = inputs.permeability(cfg) if K is None else K
+        s0 = inputs.initial_saturation(cfg)
+        print(f"[gpu] fused against level launches {cfg['nx']}x{cfg['ny']}", flush=True)
+        outs = []
+        for fuse in ("0", "1"):
+            monkeypatch.setenv("MPM2P_FUSE", fuse)
+            r = _gpu_run(binding, cfg, K, s0)
+            r.start()
+            for f in forces:
+                r.step(f)
+            assert r.stats()["error_word"] == 0
+            ux, uy = r.velocity()
+            outs.append((to_np(ux).copy(), to_np(uy).copy(), to_np(r.saturation()).copy()))
+            r.close()
+        a, b = outs
+        scale = max(np.abs(a[0]).max(), np.abs(a[1]).max())
+        assert np.abs(a[0] - b[0]).max() <= 1e-11 * scale and np.abs(a[1] - b[1]).max() <= 1e-11 * scale
+        assert np.abs(a[2] - b[2]).max() <= 1e-11
+    monkeypatch.delenv("MPM2P_FUSE", raising=False)
+
+
 # ---------------------------------------------------------------- precision form
 # FP32 inverse blocks in the MPM-2P local solves and downscaling, FP64 iterative refinement,
 # FP64 interface solve and switch criterion. Bound of the mixed path: relative L2 velocity
@@ -388,7 +422,7 @@ def test_separate_transport_and_update_equal_step(binding, cn):
 
 def test_tuned_sweeps_match_oracle(binding):
     """The autotuner of the interface-sweep launch shapes (mpm_tune) on the 256^2 workload: it
-    returns one shape per sweep launch and a tuned solve no slower than the fixed rule; the run's
+    returns one shape per sweep launch (the fused bottom levels as one entry each way) and a tuned solve no slower than the fixed rule; the run's
     next passes still match the oracle; runs created afterwards with the same decomposition start
     from the tuned shapes, so two of them agree bitwise."""
     cfg = inputs.config("c2")
@@ -401,7 +435,10 @@ def test_tuned_sweeps_match_oracle(binding):
     r.start()
     tr = r.tune(3)
     assert len(tr["shapes"]) >= 1 and tr["ms_tuned"] <= tr["ms_rule"]
-    assert all(g in (8, 16, 32, 64) and u >= 1 and rp >= 1 for g, u, rp in tr["shapes"])
+    # a level launch (lanes per row, column pairs per lane, rows per group), or the fused bottom
+    # levels (0, their number, 0)
+    assert all((g in (8, 16, 32, 64) and u >= 1 and rp >= 1) or (g == 0 and u >= 2 and rp == 0)
+               for g, u, rp in tr["shapes"])
     print(f"    solve {tr['ms_rule']:.4f} -> {tr['ms_tuned']:.4f} ms, shapes {tr['shapes']}", flush=True)
     for n in range(1, len(forced)):
         splitting.step(orun, forced[n])
