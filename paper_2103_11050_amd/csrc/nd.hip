@@ -764,7 +764,7 @@ void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, 
 // exchanges.
 namespace {
 
-constexpr int SUB_NT = 512;
+constexpr int SUB_NT = 1024;
 
 // A level's prefix sums (one of the FuseNode counts) in registers, a bound past every entry
 // beyond the level's nodes, and the node of entry i with its first entry by selection: no branch
@@ -1111,7 +1111,9 @@ k_nd_sub_bwd(NdArgs a0, const RunTab* __restrict__ rt) {
     if (lv.bch <= 1) sub_bwd_level<1>(a, f, lv, xsrc, xb, xres, xid, vsh);
     else if (lv.bch == 2) sub_bwd_level<2>(a, f, lv, xsrc, xb, xres, xid, vsh);
     else if (lv.bch == 3) sub_bwd_level<3>(a, f, lv, xsrc, xb, xres, xid, vsh);
-    else sub_bwd_level<4>(a, f, lv, xsrc, xb, xres, xid, vsh);
+    else if (lv.bch == 4) sub_bwd_level<4>(a, f, lv, xsrc, xb, xres, xid, vsh);
+    else if (lv.bch <= 6) sub_bwd_level<6>(a, f, lv, xsrc, xb, xres, xid, vsh);
+    else sub_bwd_level<8>(a, f, lv, xsrc, xb, xres, xid, vsh);
   }
   const FuseLevel top = a.flevels[size_t(t) * H + H - 1];
   for (int r = threadIdx.x; r < top.xr + top.bR; r += SUB_NT) a.y[xid[r]] = xres[r];

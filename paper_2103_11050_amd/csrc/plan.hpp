@@ -54,9 +54,9 @@ struct LeafUp {
 // most FUSE_ROWS in either direction and its forward work items (a column pair of IB over eight
 // of its rows) at most FUSE_ITEMS; over the subtree's levels at most FUSE_SUBVEC front vector
 // entries, FUSE_XB boundary entries and FUSE_XRES separator unknowns.
-constexpr int FUSE_HMAX = 3, FUSE_MAXN = 8;
-constexpr int FUSE_FWD_NI = 64, FUSE_BWD_N = 256, FUSE_VEC = 1024, FUSE_ROWS = 1024;
-constexpr int FUSE_XB = 2048, FUSE_XRES = 1024, FUSE_SUBVEC = 2048, FUSE_ITEMS = 1024;
+constexpr int FUSE_HMAX = 4, FUSE_MAXN = 8;
+constexpr int FUSE_FWD_NI = 64, FUSE_BWD_N = 512, FUSE_VEC = 1024, FUSE_ROWS = 1024;
+constexpr int FUSE_XB = 2048, FUSE_XRES = 1024, FUSE_SUBVEC = 4096, FUSE_ITEMS = 1024;
 
 // A node of a fused subtree with its place in its level's lists: the rows and vector entries of
 // the level's nodes before it, forward (nB rows, nI entries) and backward (nI rows, n entries:

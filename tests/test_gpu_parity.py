@@ -301,7 +301,7 @@ def test_fused_bottom_levels_match_level_launches(binding, monkeypatch):
     """The bottom levels of the interface sweeps taken by one launch per direction (one
     workgroup per subtree of the nested-dissection tree) against one launch per level: the same
     velocity and saturation up to the summation order of the row products, on a regular tree
-    (256^2 in 16 x 16 subdomains, three fused levels) and on ragged ones (9 x 13 and 5 x 3
+    (256^2 in 16 x 16 subdomains, four fused levels) and on ragged ones (9 x 13 and 5 x 3
     subdomains). Every other parity test runs with the fused levels, the default."""
     problems = [
         (inputs.config("c2"), None),
