@@ -16,7 +16,8 @@
 //   x_I = -II f_I - IB x_B.
 // In the forward sweep vectors travel between levels through slots (see NodeDev): a node's f
 // is the sum of its two child slots, so every load of a forward level kernel is independent of
-// the others. The backward sweep gathers x_B from the solution vector.
+// the others. The backward sweep gathers x_B from the solution vector. The bottom levels of both
+// sweeps can instead run as one launch per direction, one workgroup per subtree (end of file).
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -348,8 +349,9 @@ __device__ __forceinline__ double2 ld32x2(const double* base, uint32_t elem) {
   return make_double2(v.x, v.y);
 }
 
-// Forward and backward sweeps, one launch per level. A workgroup takes RP x (256/G) rows of
-// one node, G lanes per row, U column pairs per lane (lane gl holds columns 2 (gl + u G) and
+// Forward and backward sweeps, one launch per level (above the fused bottom levels, or all of
+// them). A workgroup takes RP x (256/G) rows of one node, G lanes per row, U column pairs per
+// lane (lane gl holds columns 2 (gl + u G) and
 // 2 (gl + u G) + 1: one 16-byte load each; longer rows in chunks of 2 G U), and issues every
 // load of its block and of the vector it multiplies before the first use: one memory round trip
 // per level. Loads are unconditional at clamped (valid) addresses and masked afterwards so that
