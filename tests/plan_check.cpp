@@ -1,5 +1,6 @@
 // Host-side consistency of the plan (the nested-dissection tree of the interface system, the
-// extend-add maps and the workspace layout) for a set of decompositions; built and run by
+// extend-add maps, the records of the fused bottom levels and the workspace layout) for a set of
+// decompositions; built and run by
 // tests/test_plan.py. Prints one line per decomposition: "ok ..." or the first failed check.
 #include <algorithm>
 #include <cstddef>
@@ -13,6 +14,99 @@
 using namespace mpm;
 
 namespace {
+
+// The fused bottom levels: every node of level <= H in exactly one subtree, its records' places
+// (prefix sums over the level's nodes, the parent's place in the subtree's vector list), the
+// level totals within the kernels' limits, and each x_B source naming the right unknown.
+std::string check_fused(const Plan& P) {
+  const int H = P.fuse_h, top = int(P.level_nodes.size()) - 1;
+  if (H == 0) return P.fnodes.empty() && P.flevels.empty() ? "" : "records without fused levels";
+  if (H < 2 || H > FUSE_HMAX || H >= top) return "fused depth";
+  if (int(P.flevels.size()) != P.fuse_roots * H) return "level records";
+  std::vector<int> seen(P.nodes.size(), 0);
+  std::vector<int> parent(P.nodes.size(), -1);
+  for (size_t i = 0; i < P.nodes.size(); ++i)
+    for (int c = 0; c < 2; ++c)
+      if (P.nodes[i].child[c] >= 0) parent[P.nodes[i].child[c]] = int(i);
+  auto id_of = [&](const NodeDev& x) {
+    for (size_t i = 0; i < P.nodes.size(); ++i)
+      if (P.nodes[i].front_off == x.front_off) return int(i);
+    return -1;
+  };
+  int next = 0;
+  for (int t = 0; t < P.fuse_roots; ++t) {
+    const FuseLevel* L = &P.flevels[size_t(t) * H];
+    std::vector<int> ids;   // the subtree's nodes, fnodes order
+    int vb = 0, xr = 0, xo = 0;
+    for (int h = 1; h <= H; ++h) {
+      const FuseLevel& l = L[h - 1];
+      if (l.b != next || l.e < l.b || l.e - l.b > FUSE_MAXN) return "node range";
+      if (l.vb != vb || l.xr != xr || l.xo != xo) return "level places";
+      int fr = 0, fv = 0, br = 0, bv = 0, fc = 0, nmax = 0;
+      for (int i = l.b; i < l.e; ++i) {
+        const FuseNode& x = P.fnodes[i];
+        const int id = id_of(x.nd);
+        if (id < 0 || x.nd.level != h) return "fused node";
+        ++seen[id];
+        ids.push_back(id);
+        if (x.fr != fr || x.fv != fv || x.br != br || x.bv != bv || x.fc != fc) return "places in the level";
+        fr += x.nd.nB;
+        fv += x.nd.nI;
+        br += x.nd.nI;
+        bv += x.nd.n;
+        fc += (x.nd.nB / 2) * ((x.nd.nI + 7) / 8);
+        nmax = std::max(nmax, int(x.nd.n));
+        if (x.nd.nI > FUSE_FWD_NI || x.nd.n > FUSE_BWD_N || x.nd.nB % 2) return "row limits";
+      }
+      if (l.fR != fr || l.fV != fv || l.bR != br || l.bV != bv || l.fC != fc || l.bch != (nmax + 63) / 64)
+        return "level totals";
+      if (bv > FUSE_VEC || fr > FUSE_ROWS || br > FUSE_ROWS || fc > FUSE_ITEMS) return "level limits";
+      next = l.e;
+      vb += bv;
+      xr += br;
+      xo += fr;
+    }
+    if (vb > FUSE_SUBVEC || xr > FUSE_XRES || xo > FUSE_XB) return "subtree limits";
+    // parents and x_B sources
+    for (int h = 1; h <= H; ++h) {
+      const FuseLevel& l = L[h - 1];
+      for (int i = l.b; i < l.e; ++i) {
+        const FuseNode& x = P.fnodes[i];
+        const int id = id_of(x.nd), p = parent[id];
+        int pv = -1;
+        for (int h2 = h + 1; h2 <= H; ++h2)
+          for (int i2 = L[h2 - 1].b; i2 < L[h2 - 1].e; ++i2)
+            if (id_of(P.fnodes[i2].nd) == p) pv = L[h2 - 1].vb + P.fnodes[i2].bv;
+        if (x.pv != pv) return "parent place";
+        if (pv < 0 && (p < 0 || P.nodes[p].level <= H || x.nd.up_slot_off < 0)) return "subtree root";
+        for (int c = 0; c < x.nd.nB; ++c) {
+          const int d = P.dof_pool[x.nd.dof_off + x.nd.nI + c];
+          const int src = P.fxsrc[l.xc + x.fr + c];
+          if (src < 0) {
+            if (-1 - src != d) return "outside x_B id";
+            // no ancestor inside the subtree holds it
+            for (int a = p; a >= 0 && P.nodes[a].level <= H; a = parent[a])
+              for (int k = 0; k < P.nodes[a].nI; ++k)
+                if (P.dof_pool[P.nodes[a].dof_off + k] == d) return "x_B from outside held inside";
+            continue;
+          }
+          bool found = false;
+          for (int h2 = h + 1; h2 <= H && !found; ++h2)
+            for (int i2 = L[h2 - 1].b; i2 < L[h2 - 1].e; ++i2) {
+              const FuseNode& y = P.fnodes[i2];
+              const int k = src - L[h2 - 1].xr - y.br;
+              if (k >= 0 && k < y.nd.nI && P.dof_pool[y.nd.dof_off + k] == d) found = true;
+            }
+          if (!found) return "x_B source";
+        }
+      }
+    }
+  }
+  if (next != int(P.fnodes.size())) return "node records";
+  for (size_t i = 0; i < P.nodes.size(); ++i)
+    if (seen[i] != (P.nodes[i].level <= H ? 1 : 0)) return "node not in exactly one subtree";
+  return "";
+}
 
 std::string check(const mpm_desc& d) {
   Plan P;
@@ -103,9 +197,13 @@ std::string check(const mpm_desc& d) {
   for (size_t o : offs)
     if (o % 256 || o >= P.total_bytes) return "workspace offset";
   if (P.off_front + size_t(std::max<int64_t>(P.front_doubles, 1)) * 8 > P.off_fI) return "front region size";
-  char buf[160];
-  std::snprintf(buf, sizeof(buf), "ok nsub %d unknowns %d nodes %zu levels %zu bytes %zu", P.nsub, P.n_iface,
-                P.nodes.size(), P.level_nodes.size() - 1, P.total_bytes);
+  for (size_t o : {P.off_fnodes, P.off_flevels, P.off_fxsrc})
+    if (o % 256 || o >= P.total_bytes) return "workspace offset";
+  const std::string fe = check_fused(P);
+  if (!fe.empty()) return "fused levels: " + fe;
+  char buf[200];
+  std::snprintf(buf, sizeof(buf), "ok nsub %d unknowns %d nodes %zu levels %zu fused %d subtrees %d bytes %zu", P.nsub,
+                P.n_iface, P.nodes.size(), P.level_nodes.size() - 1, P.fuse_h, P.fuse_roots, P.total_bytes);
   return buf;
 }
 
@@ -119,7 +217,9 @@ int main() {
   const int shapes[][7] = {{32, 32, 8, 8, 2, 2, 0},    {32, 32, 8, 8, 2, 2, 1},   {12, 8, 4, 4, 2, 1, 0},
                            {30, 20, 10, 10, 5, 2, 0},  {30, 20, 10, 10, 1, 5, 1}, {48, 8, 8, 8, 1, 4, 0},
                            {60, 30, 20, 10, 4, 2, 1},  {16, 10, 16, 10, 1, 1, 0}, {40, 24, 8, 8, 2, 2, 0},
-                           {256, 256, 16, 16, 4, 4, 0}, {1024, 1024, 16, 16, 8, 8, 0}, {300, 50, 20, 10, 20, 10, 0}};
+                           {256, 256, 16, 16, 4, 4, 0}, {1024, 1024, 16, 16, 8, 8, 0}, {300, 50, 20, 10, 20, 10, 0},
+                           {144, 208, 16, 16, 4, 4, 0}, {200, 120, 8, 8, 2, 2, 1}, {1024, 1024, 16, 16, 8, 8, 1},
+                           {512, 128, 32, 32, 8, 8, 1}};
   int bad = 0;
   for (const auto& s : shapes) {
     mpm_desc d{};

@@ -1,8 +1,10 @@
 """Host logic of the plan (CPU): the nested-dissection tree eliminates every interface unknown
 once, the extend-add maps place each child's boundary unknowns at the parent's matching
 positions (and the inverse maps point back), node storage ranges are disjoint with each level's
-fronts contiguous, and workspace offsets are aligned and in bounds; for constant and linear
-interface spaces, ragged trees, one subdomain, many-line subdomains and the metric workload."""
+fronts contiguous, the fused bottom levels cover every node of their levels once with consistent
+places, parents and x_B sources, and workspace offsets are aligned and in bounds; for constant
+and linear interface spaces, ragged trees, one subdomain, many-line subdomains and the metric
+workload."""
 import os
 import shutil
 import subprocess
@@ -22,7 +24,12 @@ def test_plan_consistency(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     print(out.stdout)
     assert out.returncode == 0, out.stdout + out.stderr
-    assert out.stdout.count(": ok") == 12
+    assert out.stdout.count(": ok") == 16
+    # the metric workload fuses four levels in 256 subtrees; ragged trees and the linear spaces
+    # fuse too
+    assert "1024x1024 sub 16x16 ne 8,8 deg 0: ok" in out.stdout and "fused 4 subtrees 256" in out.stdout
+    fused = [l for l in out.stdout.splitlines() if ": ok" in l and " fused 0 " not in l]
+    assert len(fused) >= 10
     # the ctypes descriptor of the binding has the C layout
     import ctypes
 
