@@ -128,6 +128,7 @@ struct mpm_run {
   std::vector<int> tune_fwd, tune_bwd;
   // the plan's bottom levels (P.fuse_h of them) swept by one launch per direction
   bool fuse = false;
+  const int32_t* fleaves = nullptr;   // per subtree, its subdomains (device)
 
   hipEvent_t take_event() {
     if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
@@ -317,10 +318,13 @@ bool fuse_default() {
 
 LeafOut leaf_dest(const mpm_run* r) { return LeafOut{r->slots, r->leafup, r->nd.map_pool}; }
 
-void nd_solve(mpm_run* r, Runs rt = one_run()) {
+// With with_v >= 0 the fused backward sweep also reconstructs the boundary fluxes (flux_sub with
+// that with_v) where the plan allows it; returns whether it did.
+bool nd_solve(mpm_run* r, Runs rt = one_run(), int with_v = -1) {
   const Plan& P = r->P;
   const int L = int(P.level_nodes.size()) - 1;
   const int H = r->fuse ? P.fuse_h : 0;   // levels 1..H: one launch per direction
+  const bool flux = H && with_v >= 0 && P.fuse_flux;
   {
     Scope sc(r, "iface_fwd");
     if (H) launch_nd_sub_fwd(r->st, r->nd, P.fuse_roots, rt);
@@ -340,8 +344,14 @@ void nd_solve(mpm_run* r, Runs rt = one_run()) {
       launch_nd_level_bwd(r->st, r->nd, P.level_off[l], nn, P.level_nImax[l], P.level_nmax[l], l == L ? 1 : 0, rt,
                           sh);
     }
-    if (H) launch_nd_sub_bwd(r->st, r->nd, P.fuse_roots, rt);
+    if (H && flux) {
+      const FluxArgs fa{r->g, r->km, r->S, r->h, r->vbnd, r->subdofs_d, r->ubnd, r->fleaves, with_v};
+      launch_nd_sub_bwd(r->st, r->nd, P.fuse_roots, rt, &fa);
+    } else if (H) {
+      launch_nd_sub_bwd(r->st, r->nd, P.fuse_roots, rt);
+    }
   }
+  return flux;
 }
 
 void nd_factor(mpm_run* r, Runs rt = one_run()) {
@@ -356,8 +366,11 @@ void nd_factor(mpm_run* r, Runs rt = one_run()) {
   }
 }
 
-void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store, Runs rt = one_run()) {
-  {
+// flux_done: the interface solve reconstructed the fluxes already; join (if any): waited for
+// before the downscaling, the first step that needs the work on the second stream.
+mpm_status finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store, Runs rt = one_run(),
+                           bool flux_done = false, hipEvent_t join = nullptr) {
+  if (!flux_done) {
     Scope sc(r, "flux");
     launch_flux(r->st, r->g, r->km, r->S, r->h, r->vbnd, r->y, r->subdofs_d, r->ubnd, with_v, rt);
   }
@@ -372,6 +385,7 @@ void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store, Run
     Scope sc(r, "flux");
     launch_flux(r->st, r->g, r->km, r->S, r->h, r->wbnd, r->y, r->subdofs_d, r->ubnd, 2, rt);
   }
+  if (join) HIPCHK(r, hipStreamWaitEvent(r->st, join, 0));
   {
     Scope sc(r, "downscale");
     if (r->f32 && !store)
@@ -389,6 +403,7 @@ void finish_velocity(mpm_run* r, const double* kap_s, int with_v, int store, Run
     Scope sc(r, "dt");
     launch_dt(r->st, r->P.nsub, r->red, r->red + r->P.nsub, r->scal, r->dscount, rt);
   }
+  return MPM_OK;
 }
 
 // MRCM with a new basis for kappa^n (stored as kappa^m), downscaled with the same kappa.
@@ -409,8 +424,9 @@ mpm_status mrcm_update(mpm_run* r) {
     launch_to_f32(r->st, r->P.n_blocks, r->fac, r->fac32);
   }
   nd_factor(r);
-  nd_solve(r);
-  finish_velocity(r, r->km, 0, 1);
+  const bool fd = nd_solve(r, one_run(), 0);
+  mpm_status fs = finish_velocity(r, r->km, 0, 1, one_run(), fd);
+  if (fs) return fs;
   const size_t fx = size_t(r->P.ny) * (r->P.nx + 1) * 8, fy = size_t(r->P.ny + 1) * r->P.nx * 8;
   HIPCHK(r, hipMemcpyAsync(r->uxm, r->ux, fx, hipMemcpyDeviceToDevice, r->st));
   HIPCHK(r, hipMemcpyAsync(r->uym, r->uy, fy, hipMemcpyDeviceToDevice, r->st));
@@ -428,8 +444,9 @@ mpm_status mrcm_update_group(const std::vector<mpm_run*>& g, Runs rt) {
   if (!have_fac) launch_line_factor(r->st, r->g, r->km, r->fac, r->err, rt);
   if (r->f32) launch_to_f32(r->st, r->P.n_blocks, r->fac, r->fac32, rt);
   nd_factor(r, rt);
-  nd_solve(r, rt);
-  finish_velocity(r, r->km, 0, 1, rt);
+  const bool fd = nd_solve(r, rt, 0);
+  mpm_status fs = finish_velocity(r, r->km, 0, 1, rt, fd);
+  if (fs) return fs;
   const size_t fx = size_t(r->P.ny) * (r->P.nx + 1) * 8, fy = size_t(r->P.ny + 1) * r->P.nx * 8;
   for (mpm_run* x : g) {
     HIPCHK(r, hipMemcpyAsync(x->uxm, x->ux, fx, hipMemcpyDeviceToDevice, r->st));
@@ -467,10 +484,8 @@ mpm_status mpm_update_body(mpm_run* r, bool capturing, Runs rt = one_run()) {
       launch_mpm_local(r->st, r->g, r->kn, r->km, r->uxm, r->uym, r->q, r->fac, r->h, r->vbnd, leaf_dest(r), r->err,
                        rt);
   }
-  nd_solve(r, rt);
-  if (two) HIPCHK(r, hipStreamWaitEvent(r->st, r->ev_join, 0));
-  finish_velocity(r, r->kn, 1, 0, rt);
-  return MPM_OK;
+  const bool fd = nd_solve(r, rt, 1);
+  return finish_velocity(r, r->kn, 1, 0, rt, fd, two ? r->ev_join : nullptr);
 }
 
 mpm_status mpm_update(mpm_run* r) {
@@ -650,6 +665,7 @@ bool bind_workspace(mpm_run* r, char* ws) {
   r->nd.fnodes = reinterpret_cast<const FuseNode*>(r->ws + P.off_fnodes);
   r->nd.flevels = reinterpret_cast<const FuseLevel*>(r->ws + P.off_flevels);
   r->nd.fxsrc = reinterpret_cast<const int32_t*>(r->ws + P.off_fxsrc);
+  r->fleaves = reinterpret_cast<const int32_t*>(r->ws + P.off_fleaves);
   r->nd.fuse_h = P.fuse_h;
   r->fuse = P.fuse_h > 0 && fuse_default();
   r->leafup = reinterpret_cast<const LeafUp*>(r->ws + P.off_leafup);
@@ -682,6 +698,7 @@ bool bind_workspace(mpm_run* r, char* ws) {
          in(r->nd.fnodes, std::max<size_t>(P.fnodes.size(), 1) * sizeof(FuseNode)) &&
          in(r->nd.flevels, std::max<size_t>(P.flevels.size(), 1) * sizeof(FuseLevel)) &&
          in(r->nd.fxsrc, std::max<size_t>(P.fxsrc.size(), 1) * 4) &&
+         in(r->fleaves, std::max<size_t>(P.fleaves.size(), 1) * 4) &&
          (P.d.mpm_order != 1 || in(r->wbnd, ns * P.nb * 8));
 }
 
@@ -701,6 +718,7 @@ hipError_t upload_plan(mpm_run* r) {
   chain(up(P.off_fnodes, P.fnodes.data(), P.fnodes.size() * sizeof(FuseNode)));
   chain(up(P.off_flevels, P.flevels.data(), P.flevels.size() * sizeof(FuseLevel)));
   chain(up(P.off_fxsrc, P.fxsrc.data(), P.fxsrc.size() * 4));
+  chain(up(P.off_fleaves, P.fleaves.data(), P.fleaves.size() * 4));
   chain(up(P.off_leafup, P.leafup.data(), P.leafup.size() * sizeof(LeafUp)));
   chain(hipMemsetAsync(r->slots, 0, size_t(std::max<int64_t>(P.slot_doubles, 1)) * 8, r->st));
   chain(up(P.off_dofpool, P.dof_pool.data(), P.dof_pool.size() * 4));

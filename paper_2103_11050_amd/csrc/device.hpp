@@ -311,6 +311,74 @@ __device__ __forceinline__ double robin_datum(const Geo& g, int I, int J, const 
   }
   return -bf.sgn * robin_beta(g, bf, kc) * U + Pv;
 }
+// Reconstruction on the boundary faces of subdomain sub (at most 64) by one wavefront, lane f
+// taking face f (A7): W u = h - S r with the Robin data r_f = -sgn beta_f U_H(f) + P_H(f) on
+// Gamma faces (zero on Dirichlet faces, whose data are in h); Neumann faces keep z. With
+// with_v the MPM-2P flux u-bar = u-hat_0 + v is returned; with with_v = 2 the first-order
+// u-hat_1 + w is added to ubnd (Neumann faces unchanged). r: 64 doubles of LDS for this
+// wavefront.
+__device__ __forceinline__ void flux_sub(const Geo& g, int sub, const double* __restrict__ kap_m,
+                                         const double* __restrict__ Sg, const double* __restrict__ hg,
+                                         const double* __restrict__ vbnd, const double* __restrict__ y,
+                                         const int32_t* __restrict__ sub_dofs, double* __restrict__ ubnd, int with_v,
+                                         int f, double* r) {
+  const int I = sub % g.Sx, J = sub / g.Sx;
+  const int nb = g.nb;
+  // the rows of S do not depend on the interface solution: their loads go out first
+  const bool act = f < nb;
+  const int D = nb / 2;
+  const double* Ss = Sg + size_t(sub) * smap_doubles(nb);
+  double sv[33];
+#pragma unroll
+  for (int d = 0; d < 33; ++d) sv[d] = act && d <= D ? __builtin_nontemporal_load(&Ss[d * nb + f]) : 0.0;
+  double acc = act ? hg[size_t(sub) * nb + f] : 0.0;
+  const double vb = act && with_v ? vbnd[size_t(sub) * nb + f] : 0.0;
+  BFace bf;
+  if (act) {
+    bf = bface(g, I, J, f);
+    double rv = 0.0;
+    if (bf.kind == FACE_ROB) {
+      const int gc = (J * g.my + bf.j) * g.nx + I * g.mx + bf.i;
+      rv = robin_datum(g, I, J, bf, kap_m[gc], sub_dofs + size_t(sub) * g.ndmax, y);
+    }
+    r[f] = rv;
+  }
+  wave_lds_fence();   // the lanes read each other's Robin data
+  // S_i r, row f of S from its wrapped diagonals: S(f, f + d) = D[d][f] for d <= nb / 2, and
+  // S(f, f - e) = D[e][f - e] for the other columns (indices mod nb). Each lane loads its
+  // entry of every diagonal row (coalesced, all loads issued together, above); D[e][f - e]
+  // come from lane f - e through a cross-lane read. Every lane takes part in those reads, so
+  // they are made before the lanes branch on the face kind.
+#pragma unroll
+  for (int d = 0; d < 33; ++d) {
+    if (d <= D) {
+      const int t = f + d < nb ? f + d : f + d - nb;
+      acc -= sv[d] * r[act ? t : 0];
+    }
+  }
+#pragma unroll
+  for (int e = 1; e < 32; ++e) {
+    if (e < nb - D) {
+      const int t = f >= e ? f - e : f - e + nb;
+      const double v = __shfl(sv[e], act ? t : 0);
+      acc -= v * r[act ? t : 0];
+    }
+  }
+  if (act) {
+    double u;
+    if (bf.kind == FACE_NEU) {
+      u = bf.value;
+    } else {
+      u = acc / bf.flen + vb;
+    }
+    if (with_v == 2) {
+      if (bf.kind != FACE_NEU) ubnd[size_t(sub) * nb + f] += u;
+    } else {
+      ubnd[size_t(sub) * nb + f] = u;
+    }
+  }
+}
+
 // Harmonic transmissibility per unit length between two cells at distance d:
 // (d/(2 kc) + d/(2 kd))^-1 = 2 kc kd / (d (kc + kd)), one division.
 __host__ __device__ __forceinline__ double harm_trans(double kc, double kd, double d) {

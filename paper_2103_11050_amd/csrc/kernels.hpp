@@ -155,10 +155,24 @@ void launch_nd_level_fwd(hipStream_t st, const NdArgs& a, int level_off, int nno
                          Runs rt = one_run(), int shape = 0);
 void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int level_off, int nnodes, int nImax, int nmax, int root,
                          Runs rt = one_run(), int shape = 0);
+// The reconstruction (flux_sub) done by the fused backward sweep for its subtrees' subdomains,
+// leaves[t FUSE_LEAVES + w] for wavefront w of subtree t (-1: none).
+struct FluxArgs {
+  Geo g;
+  const double* km;
+  const double* S;
+  const double* h;
+  const double* vbnd;
+  const int32_t* sub_dofs;
+  double* ubnd;
+  const int32_t* leaves;
+  int with_v;
+};
 // The fused bottom levels (a.fuse_h of them) of the forward and of the backward sweep: one
-// workgroup per subtree.
+// workgroup per subtree; with fa, the backward sweep then reconstructs the fluxes.
 void launch_nd_sub_fwd(hipStream_t st, const NdArgs& a, int nsubtrees, Runs rt = one_run());
-void launch_nd_sub_bwd(hipStream_t st, const NdArgs& a, int nsubtrees, Runs rt = one_run());
+void launch_nd_sub_bwd(hipStream_t st, const NdArgs& a, int nsubtrees, Runs rt = one_run(),
+                       const FluxArgs* fa = nullptr);
 
 // transport.hip
 // (the viscosity ratio M is the run's, from scal)

@@ -225,81 +225,16 @@ __global__ void __launch_bounds__(256) k_dt(int nsub, const double* __restrict__
 }
 
 // ====================================================================== A7: boundary fluxes
-// Reconstruction on every boundary face of every subdomain from the interface solution:
-// W u = h - S r with the Robin data r_f = -sgn beta_f U_H(f) + P_H(f) on Gamma faces (zero on
-// Dirichlet faces, whose data are in h); Neumann faces keep z. With with_v the MPM-2P flux
-// u-bar = u-hat_0 + v is returned; with with_v = 2 the first-order u-hat_1 + w is added to ubnd
-// (Neumann faces unchanged).
+// Reconstruction on every boundary face of every subdomain from the interface solution
+// (flux_sub), one wavefront per subdomain.
 __global__ void __launch_bounds__(64)
 k_flux(Geo g, const double* __restrict__ kap_m, const double* __restrict__ Sg, const double* __restrict__ hg,
        const double* __restrict__ vbnd, const double* __restrict__ y, const int32_t* __restrict__ sub_dofs,
        double* __restrict__ ubnd, int with_v, const RunTab* __restrict__ rt) {
   __shared__ double r[64];
   const int64_t wo = ws_off(rt);
-  kap_m = at_off(kap_m, wo);
-  Sg = at_off(Sg, wo);
-  hg = at_off(hg, wo);
-  vbnd = at_off(vbnd, wo);
-  y = at_off(y, wo);
-  sub_dofs = at_off(sub_dofs, wo);
-  ubnd = at_off(ubnd, wo);
-  const int sub = xcd_sub(g.nsub);
-  const int I = sub % g.Sx, J = sub / g.Sx;
-  const int nb = g.nb;
-  const int f = threadIdx.x;
-  // the rows of S do not depend on the interface solution: their loads go out first
-  const bool act = f < nb;
-  const int D = nb / 2;
-  const double* Ss = Sg + size_t(sub) * smap_doubles(nb);
-  double sv[33];
-#pragma unroll
-  for (int d = 0; d < 33; ++d) sv[d] = act && d <= D ? __builtin_nontemporal_load(&Ss[d * nb + f]) : 0.0;
-  double acc = act ? hg[size_t(sub) * nb + f] : 0.0;
-  const double vb = act && with_v ? vbnd[size_t(sub) * nb + f] : 0.0;
-  BFace bf;
-  if (act) {
-    bf = bface(g, I, J, f);
-    double rv = 0.0;
-    if (bf.kind == FACE_ROB) {
-      const int gc = (J * g.my + bf.j) * g.nx + I * g.mx + bf.i;
-      rv = robin_datum(g, I, J, bf, kap_m[gc], sub_dofs + size_t(sub) * g.ndmax, y);
-    }
-    r[f] = rv;
-  }
-  __syncthreads();
-  // S_i r, row f of S from its wrapped diagonals: S(f, f + d) = D[d][f] for d <= nb / 2, and
-  // S(f, f - e) = D[e][f - e] for the other columns (indices mod nb). Each lane loads its
-  // entry of every diagonal row (coalesced, all loads issued together, above); D[e][f - e]
-  // come from lane f - e through a cross-lane read. Every lane takes part in those reads, so
-  // they are made before the lanes branch on the face kind.
-#pragma unroll
-  for (int d = 0; d < 33; ++d) {
-    if (d <= D) {
-      const int t = f + d < nb ? f + d : f + d - nb;
-      acc -= sv[d] * r[act ? t : 0];
-    }
-  }
-#pragma unroll
-  for (int e = 1; e < 32; ++e) {
-    if (e < nb - D) {
-      const int t = f >= e ? f - e : f - e + nb;
-      const double v = __shfl(sv[e], act ? t : 0);
-      acc -= v * r[act ? t : 0];
-    }
-  }
-  if (act) {
-    double u;
-    if (bf.kind == FACE_NEU) {
-      u = bf.value;
-    } else {
-      u = acc / bf.flen + vb;
-    }
-    if (with_v == 2) {
-      if (bf.kind != FACE_NEU) ubnd[size_t(sub) * nb + f] += u;
-    } else {
-      ubnd[size_t(sub) * nb + f] = u;
-    }
-  }
+  flux_sub(g, xcd_sub(g.nsub), at_off(kap_m, wo), at_off(Sg, wo), at_off(hg, wo), at_off(vbnd, wo), at_off(y, wo),
+           at_off(sub_dofs, wo), at_off(ubnd, wo), with_v, threadIdx.x, r);
 }
 
 // The same reconstruction for subdomains with 65 to 128 boundary faces: one thread per face

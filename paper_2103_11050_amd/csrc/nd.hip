@@ -1065,8 +1065,12 @@ k_nd_sub_fwd(NdArgs a0, const RunTab* __restrict__ rt) {
   }
 }
 
+static_assert(SUB_NT / 64 == FUSE_LEAVES && FUSE_VEC >= 64 * FUSE_LEAVES,
+              "one wavefront per subdomain of a subtree, its Robin data in the vector buffer");
+
+template <bool FLUX>
 __global__ void __launch_bounds__(SUB_NT) __attribute__((amdgpu_waves_per_eu(4)))
-k_nd_sub_bwd(NdArgs a0, const RunTab* __restrict__ rt) {
+k_nd_sub_bwd(NdArgs a0, FluxArgs fa, const RunTab* __restrict__ rt) {
   const NdArgs a = nd_at(a0, ws_off(rt));
   __shared__ FuseNode fn[FUSE_HMAX * FUSE_MAXN];
   __shared__ int32_t xsrc[FUSE_XB];   // x_B sources of the subtree's nodes, level by level
@@ -1119,6 +1123,17 @@ k_nd_sub_bwd(NdArgs a0, const RunTab* __restrict__ rt) {
   }
   const FuseLevel top = a.flevels[size_t(t) * H + H - 1];
   for (int r = threadIdx.x; r < top.xr + top.bR; r += SUB_NT) a.y[xid[r]] = xres[r];
+  if constexpr (FLUX) {
+    // every unknown of the subtree's subdomains is final now (this workgroup's x_I above, the
+    // others from the launches before): one wavefront per subdomain
+    __syncthreads();
+    const int64_t wo = ws_off(rt);
+    const int w = threadIdx.x >> 6;
+    const int sub = at_off(fa.leaves, wo)[size_t(t) * FUSE_LEAVES + w];
+    if (sub >= 0)   // uniform over the wavefront
+      flux_sub(fa.g, sub, at_off(fa.km, wo), at_off(fa.S, wo), at_off(fa.h, wo), at_off(fa.vbnd, wo), a.y,
+               at_off(fa.sub_dofs, wo), at_off(fa.ubnd, wo), fa.with_v, threadIdx.x & 63, vsh + 64 * w);
+  }
 }
 
 void launch_nd_sub_fwd(hipStream_t st, const NdArgs& a, int nsubtrees, Runs rt) {
@@ -1126,9 +1141,13 @@ void launch_nd_sub_fwd(hipStream_t st, const NdArgs& a, int nsubtrees, Runs rt) 
   hipLaunchKernelGGL(k_nd_sub_fwd, dim3(nsubtrees, 1, runs_of(rt)), dim3(SUB_NT), 0, st, a, rt.tab);
 }
 
-void launch_nd_sub_bwd(hipStream_t st, const NdArgs& a, int nsubtrees, Runs rt) {
+void launch_nd_sub_bwd(hipStream_t st, const NdArgs& a, int nsubtrees, Runs rt, const FluxArgs* fa) {
   if (a.fuse_h <= 0 || nsubtrees <= 0) return;
-  hipLaunchKernelGGL(k_nd_sub_bwd, dim3(nsubtrees, 1, runs_of(rt)), dim3(SUB_NT), 0, st, a, rt.tab);
+  if (fa)
+    hipLaunchKernelGGL(k_nd_sub_bwd<true>, dim3(nsubtrees, 1, runs_of(rt)), dim3(SUB_NT), 0, st, a, *fa, rt.tab);
+  else
+    hipLaunchKernelGGL(k_nd_sub_bwd<false>, dim3(nsubtrees, 1, runs_of(rt)), dim3(SUB_NT), 0, st, a, FluxArgs{},
+                       rt.tab);
 }
 
 }  // namespace mpm

@@ -393,9 +393,37 @@ void build_plan(const mpm_desc& d, Plan* p) {
       P.fxsrc = std::move(xs);
     }
   }
+  // the subdomains of each subtree, for the reconstruction in the fused backward sweep
+  P.fuse_flux = false;
+  P.fleaves.clear();
+  if (P.fuse_h > 0 && P.nb <= 64) {
+    std::vector<int32_t> leaves(size_t(P.fuse_roots) * FUSE_LEAVES, -1);
+    std::vector<int> cover(P.nsub, 0);
+    bool ok = true;
+    for (int t = 0; t < P.fuse_roots && ok; ++t) {
+      int cnt = 0;
+      for (int i = P.flevels[size_t(t) * P.fuse_h].b; i < P.flevels[size_t(t) * P.fuse_h + P.fuse_h - 1].e; ++i)
+        for (int c = 0; c < 2; ++c) {
+          const int ch = P.fnodes[i].nd.child[c];
+          if (ch >= 0) continue;
+          if (cnt == FUSE_LEAVES) {
+            ok = false;
+            break;
+          }
+          leaves[size_t(t) * FUSE_LEAVES + cnt++] = -1 - ch;
+          cover[-1 - ch] += 1;
+        }
+    }
+    for (int s = 0; s < P.nsub && ok; ++s) ok = cover[s] == 1;
+    if (ok) {
+      P.fuse_flux = true;
+      P.fleaves = std::move(leaves);
+    }
+  }
   P.off_fnodes = take(std::max<size_t>(P.fnodes.size(), 1) * sizeof(FuseNode));
   P.off_flevels = take(std::max<size_t>(P.flevels.size(), 1) * sizeof(FuseLevel));
   P.off_fxsrc = take(std::max<size_t>(P.fxsrc.size(), 1) * 4);
+  P.off_fleaves = take(std::max<size_t>(P.fleaves.size(), 1) * 4);
   const size_t blocks = (ncell + 255) / 256 + size_t(P.nsub) + 64;
   P.n_red = 4 * blocks;
   P.off_red = take(P.n_red * 8);

@@ -57,6 +57,10 @@ struct LeafUp {
 constexpr int FUSE_HMAX = 4, FUSE_MAXN = 8;
 constexpr int FUSE_FWD_NI = 64, FUSE_BWD_N = 512, FUSE_VEC = 1024, FUSE_ROWS = 1024;
 constexpr int FUSE_XB = 2048, FUSE_XRES = 1024, FUSE_SUBVEC = 4096, FUSE_ITEMS = 1024;
+// The fused backward sweep also reconstructs the boundary fluxes of its subtree's subdomains,
+// one wavefront each, where every subdomain is a leaf of a fused subtree (at most FUSE_LEAVES per
+// subtree) and has at most 64 boundary faces.
+constexpr int FUSE_LEAVES = 16;
 
 // A node of a fused subtree with its place in its level's lists: the rows and vector entries of
 // the level's nodes before it, forward (nB rows, nI entries) and backward (nI rows, n entries:
@@ -131,7 +135,9 @@ struct Plan {
   // per fused node and boundary entry, in row order: where the backward sweep finds x_B: >= 0,
   // the subtree's separator unknown of that place; < 0, -1 - its unknown id (outside the subtree)
   std::vector<int32_t> fxsrc;
-  size_t off_fnodes = 0, off_flevels = 0, off_fxsrc = 0;
+  bool fuse_flux = false;             // the fused backward sweep reconstructs the fluxes too
+  std::vector<int32_t> fleaves;       // per subtree FUSE_LEAVES subdomain ids (-1 past its leaves)
+  size_t off_fnodes = 0, off_flevels = 0, off_fxsrc = 0, off_fleaves = 0;
   size_t off_lnodes = 0, off_leafup = 0, off_slot = 0;
   size_t off_dsE = 0, off_nfac = 0;   // downscale inverse blocks: scratch and the kept kappa^m ones
   size_t n_blocks = 0;                // entries of one block set (kept kappa^m Robin, Neumann, scratch)

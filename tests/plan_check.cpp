@@ -105,6 +105,27 @@ std::string check_fused(const Plan& P) {
   if (next != int(P.fnodes.size())) return "node records";
   for (size_t i = 0; i < P.nodes.size(); ++i)
     if (seen[i] != (P.nodes[i].level <= H ? 1 : 0)) return "node not in exactly one subtree";
+  // the subdomains of each subtree, for the reconstruction in the fused backward sweep: each
+  // one a leaf of its subtree, every subdomain in exactly one list
+  if (P.fuse_flux) {
+    if (P.nb > 64 || int(P.fleaves.size()) != P.fuse_roots * FUSE_LEAVES) return "leaf lists";
+    std::vector<int> cov(P.nsub, 0);
+    for (int t = 0; t < P.fuse_roots; ++t)
+      for (int w = 0; w < FUSE_LEAVES; ++w) {
+        const int s = P.fleaves[size_t(t) * FUSE_LEAVES + w];
+        if (s < 0) continue;
+        if (s >= P.nsub) return "leaf id";
+        ++cov[s];
+        bool child = false;
+        for (int i = P.flevels[size_t(t) * H].b; i < P.flevels[size_t(t) * H + H - 1].e; ++i)
+          child = child || P.fnodes[i].nd.child[0] == -1 - s || P.fnodes[i].nd.child[1] == -1 - s;
+        if (!child) return "leaf outside its subtree";
+      }
+    for (int s = 0; s < P.nsub; ++s)
+      if (cov[s] != 1) return "subdomain not in exactly one leaf list";
+  } else if (!P.fleaves.empty()) {
+    return "leaf lists without the fused reconstruction";
+  }
   return "";
 }
 
@@ -197,13 +218,14 @@ std::string check(const mpm_desc& d) {
   for (size_t o : offs)
     if (o % 256 || o >= P.total_bytes) return "workspace offset";
   if (P.off_front + size_t(std::max<int64_t>(P.front_doubles, 1)) * 8 > P.off_fI) return "front region size";
-  for (size_t o : {P.off_fnodes, P.off_flevels, P.off_fxsrc})
+  for (size_t o : {P.off_fnodes, P.off_flevels, P.off_fxsrc, P.off_fleaves})
     if (o % 256 || o >= P.total_bytes) return "workspace offset";
   const std::string fe = check_fused(P);
   if (!fe.empty()) return "fused levels: " + fe;
   char buf[200];
-  std::snprintf(buf, sizeof(buf), "ok nsub %d unknowns %d nodes %zu levels %zu fused %d subtrees %d bytes %zu", P.nsub,
-                P.n_iface, P.nodes.size(), P.level_nodes.size() - 1, P.fuse_h, P.fuse_roots, P.total_bytes);
+  std::snprintf(buf, sizeof(buf), "ok nsub %d unknowns %d nodes %zu levels %zu fused %d subtrees %d%s bytes %zu",
+                P.nsub, P.n_iface, P.nodes.size(), P.level_nodes.size() - 1, P.fuse_h, P.fuse_roots,
+                P.fuse_flux ? " +flux" : "", P.total_bytes);
   return buf;
 }
 

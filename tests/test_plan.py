@@ -27,7 +27,7 @@ def test_plan_consistency(tmp_path):
     assert out.stdout.count(": ok") == 16
     # the metric workload fuses four levels in 256 subtrees; ragged trees and the linear spaces
     # fuse too
-    assert "1024x1024 sub 16x16 ne 8,8 deg 0: ok" in out.stdout and "fused 4 subtrees 256" in out.stdout
+    assert "1024x1024 sub 16x16 ne 8,8 deg 0: ok" in out.stdout and "fused 4 subtrees 256 +flux" in out.stdout
     fused = [l for l in out.stdout.splitlines() if ": ok" in l and " fused 0 " not in l]
     assert len(fused) >= 10
     # the ctypes descriptor of the binding has the C layout
