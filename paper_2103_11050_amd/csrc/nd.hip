@@ -760,13 +760,15 @@ void launch_nd_level_bwd(hipStream_t st, const NdArgs& a, int loff, int nnodes, 
 // nodes (the leaves' slots loaded at the start, each row's result added into its parent's vector,
 // two terms per entry at most, so that the order of the additions does not change the sum);
 // backward, its separator unknowns (x_B entries from outside the subtree gathered at the start).
-// Only the subtree root's forward results, f_I and x_I go out to global memory. The rows of all a
-// level's nodes are dealt to lane groups; a level costs one round trip for its block rows. The
-// products of a row are those of the level kernels above, summed over the lane group by halving
-// exchanges.
+// Only the subtree root's forward results, f_I and x_I go out to global memory. The work of all a
+// level's nodes is dealt to the workgroup at once, so that a level costs one round trip for its
+// block: forward, column pairs of IB over row chunks (sub_fwd_level); backward, the rows of
+// [II IB], the products of a row summed over its lane group by halving exchanges. After its
+// levels the backward workgroup can also reconstruct the boundary fluxes of the subtree's
+// subdomains (flux_sub), one wavefront each.
 namespace {
 
-constexpr int SUB_NT = 1024;
+constexpr int SUB_NT = 1024;   // 16 wavefronts: one per subdomain of a four-level subtree
 
 // A level's prefix sums (one of the FuseNode counts) in registers, a bound past every entry
 // beyond the level's nodes, and the node of entry i with its first entry by selection: no branch
