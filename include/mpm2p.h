@@ -261,6 +261,13 @@ mpm_status mpm_plan_info(const mpm_run* run, int64_t* n_sub, int64_t* n_iface, i
 mpm_status mpm_plan_solve_bytes(const mpm_run* run, int64_t* fwd_bytes, int64_t* bwd_bytes,
                                 int64_t* front_bytes);
 
+/* The part of those bytes (eq:mrc2, Section 3) that belongs to the bottom levels of the
+ * nested-dissection tree swept by one launch per direction (one workgroup per subtree): *levels =
+ * how many (0: the plan has none), *fwd_bytes and *bwd_bytes = the forward sweep's IB (the
+ * transpose of BI) and the backward sweep's [II IB] rows of their nodes (host memory; any pointer
+ * may be NULL). */
+mpm_status mpm_plan_fused_bytes(const mpm_run* run, int32_t* levels, int64_t* fwd_bytes, int64_t* bwd_bytes);
+
 /* Autotuner of the launch shapes of the interface solve (the forward and backward sweeps over the
  * nested-dissection levels of eq:mrc2's factorisation): every admissible shape of each level
  * (lanes per row, column pairs per lane, rows per lane group) is timed over complete solves on the

@@ -71,6 +71,8 @@ _SIGS = {
     "mpm_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
     "mpm_plan_info": (ctypes.c_int32, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 4),
     "mpm_plan_solve_bytes": (ctypes.c_int32, [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 3),
+    "mpm_plan_fused_bytes": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]
+                             + [ctypes.POINTER(ctypes.c_int64)] * 2),
     "mpm_advance": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "mpm_last_error": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t]),
     "mpm_batch_create": (ctypes.c_int32, [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
@@ -262,6 +264,14 @@ class Run:
         v = [ctypes.c_int64() for _ in range(3)]
         _check(load().mpm_plan_solve_bytes(self.h, *[ctypes.byref(x) for x in v]), "mpm_plan_solve_bytes")
         return dict(fwd=v[0].value, bwd=v[1].value, front=v[2].value)
+
+    def fused_bytes(self) -> dict:
+        """Bytes of the bottom tree levels swept by one launch per direction (mpm_plan_fused_bytes)."""
+        lv = ctypes.c_int32()
+        v = [ctypes.c_int64() for _ in range(2)]
+        _check(load().mpm_plan_fused_bytes(self.h, ctypes.byref(lv), *[ctypes.byref(x) for x in v]),
+               "mpm_plan_fused_bytes")
+        return dict(levels=lv.value, fwd=v[0].value, bwd=v[1].value)
 
     def tune(self, reps: int = 5) -> dict:
         """Autotunes the interface-sweep launch shapes of this run (mpm_tune)."""

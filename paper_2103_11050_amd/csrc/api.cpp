@@ -327,7 +327,10 @@ bool nd_solve(mpm_run* r, Runs rt = one_run(), int with_v = -1) {
   const bool flux = H && with_v >= 0 && P.fuse_flux;
   {
     Scope sc(r, "iface_fwd");
-    if (H) launch_nd_sub_fwd(r->st, r->nd, P.fuse_roots, rt);
+    if (H) {
+      Scope sf(r, "iface_sub_fwd");
+      launch_nd_sub_fwd(r->st, r->nd, P.fuse_roots, rt);
+    }
     for (int l = H + 1; l < L; ++l) {
       const int nn = int(P.level_nodes[l].size());
       if (!nn) continue;
@@ -345,9 +348,11 @@ bool nd_solve(mpm_run* r, Runs rt = one_run(), int with_v = -1) {
                           sh);
     }
     if (H && flux) {
+      Scope sb(r, "iface_sub_bwd_flux");
       const FluxArgs fa{r->g, r->km, r->S, r->h, r->vbnd, r->subdofs_d, r->ubnd, r->fleaves, with_v};
       launch_nd_sub_bwd(r->st, r->nd, P.fuse_roots, rt, &fa);
     } else if (H) {
+      Scope sb(r, "iface_sub_bwd");
       launch_nd_sub_bwd(r->st, r->nd, P.fuse_roots, rt);
     }
   }
@@ -1530,6 +1535,19 @@ mpm_status mpm_plan_solve_bytes(const mpm_run* r, int64_t* fwd, int64_t* bwd, in
   if (fwd) *fwd = f;
   if (bwd) *bwd = b;
   if (front) *front = r->P.front_doubles * 8;
+  return MPM_OK;
+}
+
+mpm_status mpm_plan_fused_bytes(const mpm_run* r, int32_t* levels, int64_t* fwd, int64_t* bwd) {
+  if (!r) return MPM_EINVAL;
+  int64_t f = 0, b = 0;
+  for (const FuseNode& x : r->P.fnodes) {
+    f += int64_t(x.nd.nB) * x.nd.nI * 8;
+    b += int64_t(x.nd.nI) * x.nd.n * 8;
+  }
+  if (levels) *levels = r->P.fuse_h;
+  if (fwd) *fwd = f;
+  if (bwd) *bwd = b;
   return MPM_OK;
 }
 
