@@ -448,6 +448,15 @@ def main():
     for _ in range(args.profile_steps):
         run.step()
     prof = run.profile(enable=False, reset=True)
+    # the fused sweep launches timed in a window of their own (their events would add to the
+    # phases above)
+    run.profile(enable=2, reset=True)
+    for _ in range(args.profile_steps):
+        run.step()
+    fine = run.profile(enable=False, reset=True)
+    for k in ("iface_sub_fwd", "iface_sub_bwd_flux", "iface_sub_bwd"):
+        if k in fine:
+            prof[k] = fine[k]
     # latency of a basis update (MRCM), forced after the timed window
     torch.cuda.synchronize()
     mr = []

@@ -288,8 +288,10 @@ mpm_status mpm_tune(mpm_run* run, int32_t reps, int32_t cap, int32_t* shapes, in
                     double* ms_tuned);
 
 /* Average duration in milliseconds of each kernel class over the calls since the last reset,
- * measured with HIP events on the run's stream when profiling is enabled. names/ms/count are
- * host arrays of length cap; returns the number of classes written in *n. */
+ * measured with HIP events on the run's stream when profiling is enabled (enable = 1; enable = 2
+ * also times the launches of the fused bottom sweep levels, inside their phases, whose times
+ * then include those events). names/ms/count are host arrays of length cap; returns the number
+ * of classes written in *n. */
 mpm_status mpm_profile(mpm_run* run, int32_t enable, int32_t reset, int32_t cap, const char** names,
                        double* ms, int64_t* count, int32_t* n);
 

@@ -285,7 +285,9 @@ class Run:
         return {"ms_rule": t0.value, "ms_tuned": t1.value,
                 "shapes": [tuple(shapes[3 * i:3 * i + 3]) for i in range(k)]}
 
-    def profile(self, enable: bool = True, reset: bool = True) -> dict:
+    def profile(self, enable: int = 1, reset: bool = True) -> dict:
+        """Kernel-class timings (mpm_profile): enable 1 times the phases, 2 also the fused sweep
+        launches, 0 stops; returns what was collected since the last reset."""
         cap = 64
         names = (ctypes.c_char_p * cap)()
         ms = (ctypes.c_double * cap)()

@@ -111,6 +111,7 @@ struct mpm_run {
   hipEvent_t ev_eps = nullptr;
   // profiling with HIP events on the run's stream
   bool prof = false;
+  bool prof_fine = false;   // also the fused sweep launches, inside their phases
   std::vector<std::pair<const char*, std::pair<hipEvent_t, hipEvent_t>>> pending;
   std::vector<hipEvent_t> pool;
   std::map<std::string, ProfEntry> prof_acc;
@@ -170,8 +171,13 @@ struct Scope {
   mpm_run* r;
   const char* name;
   hipEvent_t b = nullptr;
-  Scope(mpm_run* r_, const char* n) : r(r_), name(n) { r->prof_begin(n, &b); }
-  ~Scope() { r->prof_end(name, b); }
+  bool on;
+  Scope(mpm_run* r_, const char* n, bool fine = false) : r(r_), name(n), on(!fine || r_->prof_fine) {
+    if (on) r->prof_begin(n, &b);
+  }
+  ~Scope() {
+    if (on) r->prof_end(name, b);
+  }
 };
 
 Geo make_geo(const Plan& P) {
@@ -328,7 +334,7 @@ bool nd_solve(mpm_run* r, Runs rt = one_run(), int with_v = -1) {
   {
     Scope sc(r, "iface_fwd");
     if (H) {
-      Scope sf(r, "iface_sub_fwd");
+      Scope sf(r, "iface_sub_fwd", true);
       launch_nd_sub_fwd(r->st, r->nd, P.fuse_roots, rt);
     }
     for (int l = H + 1; l < L; ++l) {
@@ -348,11 +354,11 @@ bool nd_solve(mpm_run* r, Runs rt = one_run(), int with_v = -1) {
                           sh);
     }
     if (H && flux) {
-      Scope sb(r, "iface_sub_bwd_flux");
+      Scope sb(r, "iface_sub_bwd_flux", true);
       const FluxArgs fa{r->g, r->km, r->S, r->h, r->vbnd, r->subdofs_d, r->ubnd, r->fleaves, with_v};
       launch_nd_sub_bwd(r->st, r->nd, P.fuse_roots, rt, &fa);
     } else if (H) {
-      Scope sb(r, "iface_sub_bwd");
+      Scope sb(r, "iface_sub_bwd", true);
       launch_nd_sub_bwd(r->st, r->nd, P.fuse_roots, rt);
     }
   }
@@ -1726,6 +1732,7 @@ mpm_status mpm_profile(mpm_run* r, int32_t enable, int32_t reset, int32_t cap, c
   if (n) *n = k;
   if (reset) r->prof_acc.clear();
   r->prof = enable != 0;
+  r->prof_fine = enable == 2;
   return MPM_OK;
 }
 
