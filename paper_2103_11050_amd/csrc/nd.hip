@@ -630,7 +630,7 @@ static RbShape rb_shape(int len) {
   if (len <= 16) return {8, 1, 4};
   if (len <= 32) return {16, 1, 4};
   if (len <= 64) return {32, 1, 4};
-  if (len <= 128) return {64, 1, 4};
+  if (len <= 128) return {32, 2, 4};   // half-wave rows (measured ahead of {64, 1, 4})
   if (len <= 256) return {64, 2, 2};
   if (len <= 512) return {64, 4, 1};
   if (len <= 1024) return {64, 8, 1};
@@ -680,7 +680,9 @@ static RbShape rb_fit_rows(RbShape sh, int rows) {
     ND_RB_CASE(KER, 8, 1, 4, false, __VA_ARGS__) ND_RB_CASE(KER, 8, 1, 3, false, __VA_ARGS__)       \
     ND_RB_CASE(KER, 8, 1, 2, false, __VA_ARGS__) ND_RB_CASE(KER, 16, 1, 4, false, __VA_ARGS__)      \
     ND_RB_CASE(KER, 16, 1, 2, false, __VA_ARGS__) ND_RB_CASE(KER, 32, 1, 4, false, __VA_ARGS__)     \
-    ND_RB_CASE(KER, 32, 1, 2, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 1, 8, false, __VA_ARGS__)     \
+    ND_RB_CASE(KER, 32, 1, 2, false, __VA_ARGS__) ND_RB_CASE(KER, 32, 2, 4, false, __VA_ARGS__)     \
+    ND_RB_CASE(KER, 32, 2, 2, false, __VA_ARGS__) ND_RB_CASE(KER, 32, 4, 2, false, __VA_ARGS__)     \
+    ND_RB_CASE(KER, 32, 4, 1, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 1, 8, false, __VA_ARGS__)     \
     ND_RB_CASE(KER, 64, 1, 4, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 1, 2, false, __VA_ARGS__)     \
     ND_RB_CASE(KER, 64, 2, 4, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 2, 2, false, __VA_ARGS__)     \
     ND_RB_CASE(KER, 64, 2, 1, false, __VA_ARGS__) ND_RB_CASE(KER, 64, 4, 2, false, __VA_ARGS__)     \
@@ -704,8 +706,9 @@ int nd_shape_candidates(int len, int rows, bool bwd, int* codes, int cap) {
   if (n < cap) codes[n++] = nd_shape_code(rule.G, rule.U, rule.RP);
   if (rule.U == 0) return n;   // chunked rows: one shape
   static const RbShape all[] = {{8, 1, 4},  {8, 1, 3},  {8, 1, 2},  {16, 1, 4}, {16, 1, 2}, {32, 1, 4},
-                                {32, 1, 2}, {64, 1, 8}, {64, 1, 4}, {64, 1, 2}, {64, 2, 4}, {64, 2, 2},
-                                {64, 2, 1}, {64, 4, 2}, {64, 4, 1}, {64, 8, 1}, {64, 12, 1}};
+                                {32, 1, 2}, {32, 2, 4}, {32, 2, 2}, {32, 4, 2}, {32, 4, 1}, {64, 1, 8},
+                                {64, 1, 4}, {64, 1, 2}, {64, 2, 4}, {64, 2, 2}, {64, 2, 1}, {64, 4, 2},
+                                {64, 4, 1}, {64, 8, 1}, {64, 12, 1}};
   for (const RbShape& sh : all) {
     const int cols = 2 * sh.G * sh.U;
     if (cols < len || cols > 4 * len) continue;
@@ -740,7 +743,8 @@ __global__ void __launch_bounds__(256) k_nd_bwd_root(NdArgs a, int loff, const R
 // The backward sweep takes twice the rows per lane group for rows of 65..512 entries (fewer,
 // longer-lived workgroups per level; measured slightly faster).
 static RbShape rb_shape_bwd(int len) {
-  RbShape sh = rb_shape(len);
+  // (full-wave rows at 65..128 entries here: the half-wave shape was measured on forward rows)
+  RbShape sh = len > 64 && len <= 128 ? RbShape{64, 1, 4} : rb_shape(len);
   if (sh.G == 64 && sh.U >= 1 && sh.U <= 4) sh.RP *= 2;
   return sh;
 }
